@@ -1,0 +1,1004 @@
+/*
+ * CPU ORACLE (test infrastructure, not product code).
+ *
+ * A plain, slow, FP64 reference of the solver's hot path: element matrices of
+ * linear tetrahedra and zero-thickness interface triangles, scalar-CSR
+ * assembly, the Coulomb return map, matrix-free coupling products, point-Jacobi
+ * CG, the partitioned (Prevost) CG on the pressure Schur complement and the
+ * Newton loop of one implicit step.  It shares no code with the HIP library.
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load it.
+ *
+ * Paper: Gallyamov et al., "A Parallelized 3D Geomechanical Solver for
+ * Fluid-induced Fault Slip in Poroelastic Media" (arXiv 2410.17133).
+ * Each routine names the section / equation it follows.
+ *
+ * Readings of points the paper leaves open (all listed in the design notes):
+ *  - element matrices are the 3D analogues of the 2D operators of Appendix A
+ *    (Voigt order xx,yy,zz,yz,xz,xy with engineering shear strains);
+ *  - storage mass is consistent, fracture storage uses S_F = 1/M_F;
+ *  - fracture normals, areas and tangents are frozen at the reference geometry;
+ *  - 3-point interior Gauss rule on interface triangles;
+ *  - the Newton tangent keeps only the symmetric part of the slip tangent;
+ *  - the fracture coupling A^f_pu is the transpose of A^f_up (eq. afdpd), i.e.
+ *    a factor 1/2 on the mean pressure acting on each lip;
+ *  - Dirichlet DOFs are eliminated symmetrically (row and column zero, unit
+ *    diagonal) and the coupling operators are masked on both sides.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    double nu, alpha, biot_M, mu, k_par, k_perp, w0, M_F, k_n, k_s, friction, dt;
+} or_params;
+
+typedef struct {
+    int64_t n, nnz;
+    int64_t *rowptr;
+    int32_t *col;
+    double *val;
+} or_csr;
+
+typedef struct {
+    int64_t N, ne, nf;
+    double *xyz;
+    int32_t *tets, *coh;
+    double *E, *logk;
+    uint8_t *dir_u, *dir_p;
+    or_params p;
+    or_csr Kb, Kt, A22, C;
+    /* reference interface geometry per triangle */
+    double *tri_A, *tri_n, *tri_t1, *tri_t2;
+    /* last tangent's qp states (for the adjoint's non-symmetric correction) */
+    double *qp_trac, *qp_ttr;
+    uint8_t *qp_flag;
+} or_problem;
+
+enum { OR_STICK = 0, OR_SLIP = 1, OR_OPEN = 2 };
+
+/* ------------------------------------------------------------------ */
+/* small dense helpers                                                 */
+/* ------------------------------------------------------------------ */
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static void cross3(const double *a, const double *b, double *c)
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* Linear tetrahedron: volume and gradients of the four shape functions.
+ * With J = [x1-x0, x2-x0, x3-x0] (edge vectors as columns), x = x0 + J xi, the
+ * gradient of N_{c+1} = xi_c is row c of J^{-1} and grad N_0 = -sum (Sec. 3.1,
+ * first-order elements; Appendix A gives the 2D B_p). */
+void or_tet_grad(const double *X /*[4][3]*/, double *V, double *g /*[4][3]*/)
+{
+    double J[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) J[r][c] = X[3 * (c + 1) + r] - X[r];
+    double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                 J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    double inv[3][3];
+    inv[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+    inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+    inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+    inv[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+    inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+    inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+    inv[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+    inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+    inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+    *V = fabs(det) / 6.0;
+    for (int c = 0; c < 3; ++c)
+        for (int r = 0; r < 3; ++r) g[3 * (c + 1) + r] = inv[c][r];
+    for (int r = 0; r < 3; ++r) g[r] = -(g[3 + r] + g[6 + r] + g[9 + r]);
+}
+
+/* Bulk stiffness K_e = V B^T D B (eq. discrete_balance, first term; Appendix A
+ * B_u in 3D).  Ke is 12x12 row-major, DOF order (node a, component i) -> 3a+i. */
+void or_tet_stiffness(const double *X, double E, double nu, double *Ke)
+{
+    double V, g[12];
+    or_tet_grad(X, &V, g);
+    double B[6][12];
+    memset(B, 0, sizeof B);
+    for (int a = 0; a < 4; ++a) {
+        const double *ga = g + 3 * a;
+        B[0][3 * a + 0] = ga[0];
+        B[1][3 * a + 1] = ga[1];
+        B[2][3 * a + 2] = ga[2];
+        B[3][3 * a + 1] = ga[2]; /* gamma_yz */
+        B[3][3 * a + 2] = ga[1];
+        B[4][3 * a + 0] = ga[2]; /* gamma_xz */
+        B[4][3 * a + 2] = ga[0];
+        B[5][3 * a + 0] = ga[1]; /* gamma_xy */
+        B[5][3 * a + 1] = ga[0];
+    }
+    double lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    double G = E / (2.0 * (1.0 + nu));
+    double D[6][6];
+    memset(D, 0, sizeof D);
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) D[i][j] = lam;
+        D[i][i] = lam + 2.0 * G;
+        D[3 + i][3 + i] = G;
+    }
+    double DB[6][12];
+    for (int i = 0; i < 6; ++i)
+        for (int c = 0; c < 12; ++c) {
+            double s = 0;
+            for (int k = 0; k < 6; ++k) s += D[i][k] * B[k][c];
+            DB[i][c] = s;
+        }
+    for (int r = 0; r < 12; ++r)
+        for (int c = 0; c < 12; ++c) {
+            double s = 0;
+            for (int k = 0; k < 6; ++k) s += B[k][r] * DB[k][c];
+            Ke[12 * r + c] = V * s;
+        }
+}
+
+/* Matrix coupling block A^m_pu,e (eq. Apdp): alpha * int B_u^T m N_p with one
+ * integration point; int N_b = V/4 for a linear tetrahedron.  Ae is 12x4. */
+void or_tet_coupling(const double *X, double alpha, double *Ae)
+{
+    double V, g[12];
+    or_tet_grad(X, &V, g);
+    for (int a = 0; a < 4; ++a)
+        for (int i = 0; i < 3; ++i)
+            for (int b = 0; b < 4; ++b) Ae[4 * (3 * a + i) + b] = alpha * 0.25 * V * g[3 * a + i];
+}
+
+/* Matrix flow blocks (eq. discrete_mass): storage S_e = (1/M) int N_a N_b
+ * (consistent mass, V(1+delta_ab)/20) and conductivity C_e = (k/mu) V grad N_a . grad N_b. */
+void or_tet_flow(const double *X, double perm_over_mu, double inv_M, double *Se, double *Ce)
+{
+    double V, g[12];
+    or_tet_grad(X, &V, g);
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+            Se[4 * a + b] = inv_M * V * (a == b ? 2.0 : 1.0) / 20.0;
+            Ce[4 * a + b] = perm_over_mu * V * dot3(g + 3 * a, g + 3 * b);
+        }
+}
+
+/* Interface triangle geometry in the reference configuration (Sec. 3.1.1):
+ * area, unit normal n (from the - lip to the + lip, given the vertex order),
+ * in-plane tangent t1 (projection of +z, else of +x) and t2 = n x t1, and the
+ * in-plane gradients of the three linear shape functions. */
+void or_tri_geom(const double *X /*[3][3]*/, double *A, double *n, double *t1, double *t2, double *gG /*[3][3]*/)
+{
+    double e1[3], e2[3], c[3];
+    for (int r = 0; r < 3; ++r) {
+        e1[r] = X[3 + r] - X[r];
+        e2[r] = X[6 + r] - X[r];
+    }
+    cross3(e1, e2, c);
+    double cn = sqrt(dot3(c, c));
+    *A = 0.5 * cn;
+    for (int r = 0; r < 3; ++r) n[r] = c[r] / cn;
+    double ez[3] = {0, 0, 1}, ex[3] = {1, 0, 0};
+    double v[3];
+    double s = dot3(ez, n);
+    for (int r = 0; r < 3; ++r) v[r] = ez[r] - s * n[r];
+    double vn = sqrt(dot3(v, v));
+    if (vn < 1e-8) {
+        s = dot3(ex, n);
+        for (int r = 0; r < 3; ++r) v[r] = ex[r] - s * n[r];
+        vn = sqrt(dot3(v, v));
+    }
+    for (int r = 0; r < 3; ++r) t1[r] = v[r] / vn;
+    cross3(n, t1, t2);
+    /* grad N_a = n x (x_c - x_b) / (2A) for (a,b,c) cyclic */
+    for (int a = 0; a < 3; ++a) {
+        int b = (a + 1) % 3, cc = (a + 2) % 3;
+        double d[3];
+        for (int r = 0; r < 3; ++r) d[r] = X[3 * cc + r] - X[3 * b + r];
+        cross3(n, d, gG + 3 * a);
+        for (int r = 0; r < 3; ++r) gG[3 * a + r] /= (2.0 * *A);
+    }
+}
+
+/* Fracture flow on one interface element (eq. discrete_mass_fracture with the
+ * double-node operators of eq. operators).  6x6 blocks in the order
+ * [+a,+b,+c,-a,-b,-c]:  storage w0 S_F int <r><p>;  longitudinal
+ * (w0 k_par/mu) int grad<r>.grad<p>;  transverse (k_perp/(mu w0)) int [[r]][[p]]. */
+void or_tri_flow(const double *X, const or_params *p, double *Sf, double *Cf)
+{
+    double A, n[3], t1[3], t2[3], gG[9];
+    or_tri_geom(X, &A, n, t1, t2, gG);
+    double M3[3][3], CG[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            M3[a][b] = A * (a == b ? 2.0 : 1.0) / 12.0;
+            CG[a][b] = A * dot3(gG + 3 * a, gG + 3 * b);
+        }
+    double cs = p->w0 / p->M_F, cl = p->w0 * p->k_par / p->mu, ct = p->k_perp / (p->mu * p->w0);
+    for (int sa = 0; sa < 2; ++sa)
+        for (int sb = 0; sb < 2; ++sb) {
+            double jump = (sa == sb) ? 1.0 : -1.0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    int r = 3 * sa + a, c = 3 * sb + b;
+                    Sf[6 * r + c] = cs * 0.25 * M3[a][b];
+                    Cf[6 * r + c] = cl * 0.25 * CG[a][b] + ct * jump * M3[a][b];
+                }
+        }
+}
+
+/* Elastic predictor / plastic corrector at one interface quadrature point
+ * (Sec. 2.2.1: eq. normal_traction, yield_function, slip_split,
+ * plastic_slip_increment, kuhn-tucker, corrector).
+ *   d[3]    opening (n, t1, t2 components) of the displacement since t = 0
+ *   die_n   inelastic slip at the start of the step
+ *   t0[3]   initial effective traction (t'_n0, t'_s0 along t1, t2)
+ * Out: trac = (t'_n, t_s1, t_s2), die, flag, and the local 3x3 symmetric
+ * tangent Dl (frame n,t1,t2).  Returns the trial-traction norm. */
+double or_return_map(const double *d, const double *die_n, const double *t0, double kn, double ks, double f,
+                     double *trac, double *die, uint8_t *flag, double *Dl)
+{
+    double dn0 = -t0[0] / kn;
+    double ds0[2] = {t0[1] / ks, t0[2] / ks};
+    double dnt = dn0 + d[0];
+    double tn = dnt < 0 ? -kn * dnt : 0.0;
+    double ttr[2] = {ks * (ds0[0] + d[1] - die_n[0]), ks * (ds0[1] + d[2] - die_n[1])};
+    double nt = sqrt(ttr[0] * ttr[0] + ttr[1] * ttr[1]);
+    double F = nt - f * tn;
+    memset(Dl, 0, 9 * sizeof(double));
+    if (F <= 0.0) {
+        trac[1] = ttr[0];
+        trac[2] = ttr[1];
+        die[0] = die_n[0];
+        die[1] = die_n[1];
+        *flag = dnt > 0 ? OR_OPEN : OR_STICK;
+        if (*flag == OR_STICK) {
+            Dl[4] = ks;
+            Dl[8] = ks;
+        }
+    } else {
+        double tau[2] = {1.0, 0.0};
+        if (nt > 0) {
+            tau[0] = ttr[0] / nt;
+            tau[1] = ttr[1] / nt;
+        }
+        double dl = F / ks;
+        die[0] = die_n[0] + dl * tau[0];
+        die[1] = die_n[1] + dl * tau[1];
+        trac[1] = f * tn * tau[0];
+        trac[2] = f * tn * tau[1];
+        *flag = dnt > 0 ? OR_OPEN : OR_SLIP;
+        if (*flag == OR_SLIP) {
+            double c = ks * f * tn / nt;
+            Dl[4] = c * (1.0 - tau[0] * tau[0]);
+            Dl[5] = c * (-tau[0] * tau[1]);
+            Dl[7] = c * (-tau[1] * tau[0]);
+            Dl[8] = c * (1.0 - tau[1] * tau[1]);
+        }
+    }
+    trac[0] = tn;
+    if (dnt <= 0) Dl[0] = kn;
+    return nt;
+}
+
+/* ------------------------------------------------------------------ */
+/* CSR                                                                 */
+/* ------------------------------------------------------------------ */
+static int cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+static int64_t csr_find(const or_csr *A, int64_t row, int32_t col)
+{
+    int64_t lo = A->rowptr[row], hi = A->rowptr[row + 1] - 1;
+    while (lo <= hi) {
+        int64_t mid = (lo + hi) / 2;
+        int32_t c = A->col[mid];
+        if (c == col) return mid;
+        if (c < col) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    abort(); /* entry outside the element graph: a bug in the caller */
+}
+
+static void csr_free(or_csr *A)
+{
+    free(A->rowptr);
+    free(A->col);
+    free(A->val);
+    memset(A, 0, sizeof *A);
+}
+
+/* Node graph: nodes coupled through a tetrahedron or an interface element. */
+static void node_graph(const or_problem *P, int64_t **rp_out, int32_t **adj_out)
+{
+    int64_t N = P->N;
+    int64_t *cnt = calloc(N + 1, sizeof(int64_t));
+    for (int64_t e = 0; e < P->ne; ++e)
+        for (int a = 0; a < 4; ++a) cnt[P->tets[4 * e + a] + 1] += 4;
+    for (int64_t t = 0; t < P->nf; ++t)
+        for (int a = 0; a < 6; ++a) cnt[P->coh[6 * t + a] + 1] += 6;
+    for (int64_t i = 0; i < N; ++i) cnt[i + 1] += cnt[i];
+    int32_t *lst = malloc(cnt[N] * sizeof(int32_t));
+    int64_t *pos = malloc(N * sizeof(int64_t));
+    memcpy(pos, cnt, N * sizeof(int64_t));
+    for (int64_t e = 0; e < P->ne; ++e)
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) lst[pos[P->tets[4 * e + a]]++] = P->tets[4 * e + b];
+    for (int64_t t = 0; t < P->nf; ++t)
+        for (int a = 0; a < 6; ++a)
+            for (int b = 0; b < 6; ++b) lst[pos[P->coh[6 * t + a]]++] = P->coh[6 * t + b];
+    int64_t *rp = calloc(N + 1, sizeof(int64_t));
+    for (int64_t i = 0; i < N; ++i) {
+        int32_t *row = lst + cnt[i];
+        int64_t len = cnt[i + 1] - cnt[i];
+        qsort(row, len, sizeof(int32_t), cmp_i32);
+        int64_t u = 0;
+        for (int64_t k = 0; k < len; ++k)
+            if (u == 0 || row[k] != row[u - 1]) row[u++] = row[k];
+        rp[i + 1] = u;
+    }
+    for (int64_t i = 0; i < N; ++i) rp[i + 1] += rp[i];
+    int32_t *adj = malloc(rp[N] * sizeof(int32_t));
+    for (int64_t i = 0; i < N; ++i) {
+        int64_t len = rp[i + 1] - rp[i];
+        memcpy(adj + rp[i], lst + cnt[i], len * sizeof(int32_t));
+    }
+    free(lst);
+    free(pos);
+    free(cnt);
+    *rp_out = rp;
+    *adj_out = adj;
+}
+
+/* Expand the node graph to a scalar CSR with `d` DOFs per node. */
+static void csr_from_graph(or_csr *A, int64_t N, const int64_t *rp, const int32_t *adj, int d)
+{
+    A->n = N * d;
+    A->nnz = rp[N] * d * d;
+    A->rowptr = malloc((A->n + 1) * sizeof(int64_t));
+    A->col = malloc(A->nnz * sizeof(int32_t));
+    A->val = calloc(A->nnz, sizeof(double));
+    A->rowptr[0] = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        int64_t len = rp[i + 1] - rp[i];
+        for (int c = 0; c < d; ++c) {
+            int64_t r = i * d + c, base = rp[i] * d * d + c * len * d;
+            A->rowptr[r + 1] = base + len * d;
+            for (int64_t k = 0; k < len; ++k)
+                for (int cc = 0; cc < d; ++cc) A->col[base + k * d + cc] = adj[rp[i] + k] * d + cc;
+        }
+    }
+}
+
+static void csr_copy_values(or_csr *dst, const or_csr *src)
+{
+    if (!dst->rowptr) {
+        dst->n = src->n;
+        dst->nnz = src->nnz;
+        dst->rowptr = malloc((src->n + 1) * sizeof(int64_t));
+        dst->col = malloc(src->nnz * sizeof(int32_t));
+        dst->val = malloc(src->nnz * sizeof(double));
+        memcpy(dst->rowptr, src->rowptr, (src->n + 1) * sizeof(int64_t));
+        memcpy(dst->col, src->col, src->nnz * sizeof(int32_t));
+    }
+    memcpy(dst->val, src->val, src->nnz * sizeof(double));
+}
+
+/* Symmetric elimination of masked DOFs: zero row and column, unit diagonal. */
+static void csr_eliminate(or_csr *A, const uint8_t *mask)
+{
+    for (int64_t r = 0; r < A->n; ++r)
+        for (int64_t k = A->rowptr[r]; k < A->rowptr[r + 1]; ++k) {
+            int32_t c = A->col[k];
+            if (mask[r] || mask[c]) A->val[k] = (r == c && mask[r]) ? 1.0 : 0.0;
+        }
+}
+
+void or_csr_spmv(const or_csr *A, const double *x, double *y)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < A->n; ++r) {
+        double s = 0;
+        for (int64_t k = A->rowptr[r]; k < A->rowptr[r + 1]; ++k) s += A->val[k] * x[A->col[k]];
+        y[r] = s;
+    }
+}
+
+static double vdot(int64_t n, const double *a, const double *b)
+{
+    double s = 0;
+#pragma omp parallel for reduction(+ : s) schedule(static)
+    for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
+    return s;
+}
+
+/* ------------------------------------------------------------------ */
+/* problem set-up and assembly                                         */
+/* ------------------------------------------------------------------ */
+static void tet_coords(const or_problem *P, int64_t e, double *X)
+{
+    for (int a = 0; a < 4; ++a)
+        for (int r = 0; r < 3; ++r) X[3 * a + r] = P->xyz[3 * (int64_t)P->tets[4 * e + a] + r];
+}
+
+static void tri_coords(const or_problem *P, int64_t t, double *X)
+{
+    /* reference geometry: the - lip (lips coincide at t = 0) */
+    for (int a = 0; a < 3; ++a)
+        for (int r = 0; r < 3; ++r) X[3 * a + r] = P->xyz[3 * (int64_t)P->coh[6 * t + 3 + a] + r];
+}
+
+/* Assemble K_bulk (Sec. 3.2.1), S and C (Sec. 3.2.2-3.2.3) and A22 = S + dt C
+ * (eq. prevost_system), with Dirichlet elimination. */
+or_problem *or_create(int64_t N, int64_t ne, int64_t nf, const double *xyz, const int32_t *tets,
+                      const int32_t *coh, const double *E, const double *logk, const uint8_t *dir_u,
+                      const uint8_t *dir_p, const double *params)
+{
+    or_problem *P = calloc(1, sizeof *P);
+    P->N = N;
+    P->ne = ne;
+    P->nf = nf;
+    P->xyz = malloc(N * 3 * sizeof(double));
+    memcpy(P->xyz, xyz, N * 3 * sizeof(double));
+    P->tets = malloc(ne * 4 * sizeof(int32_t));
+    memcpy(P->tets, tets, ne * 4 * sizeof(int32_t));
+    P->coh = malloc((nf ? nf : 1) * 6 * sizeof(int32_t));
+    if (nf) memcpy(P->coh, coh, nf * 6 * sizeof(int32_t));
+    P->E = malloc(ne * sizeof(double));
+    memcpy(P->E, E, ne * sizeof(double));
+    P->logk = malloc(ne * sizeof(double));
+    memcpy(P->logk, logk, ne * sizeof(double));
+    P->dir_u = malloc(3 * N);
+    memcpy(P->dir_u, dir_u, 3 * N);
+    P->dir_p = malloc(N);
+    memcpy(P->dir_p, dir_p, N);
+    memcpy(&P->p, params, sizeof(or_params));
+
+    int64_t *rp;
+    int32_t *adj;
+    node_graph(P, &rp, &adj);
+    csr_from_graph(&P->Kb, N, rp, adj, 3);
+    csr_from_graph(&P->A22, N, rp, adj, 1);
+    csr_from_graph(&P->C, N, rp, adj, 1);
+    free(rp);
+    free(adj);
+
+    double *S = calloc(P->A22.nnz, sizeof(double));
+    for (int64_t e = 0; e < ne; ++e) {
+        double X[12], Ke[144], Se[16], Ce[16];
+        tet_coords(P, e, X);
+        or_tet_stiffness(X, P->E[e], P->p.nu, Ke);
+        or_tet_flow(X, exp(P->logk[e]) / P->p.mu, 1.0 / P->p.biot_M, Se, Ce);
+        const int32_t *nd = P->tets + 4 * e;
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) {
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j)
+                        P->Kb.val[csr_find(&P->Kb, 3 * (int64_t)nd[a] + i, 3 * nd[b] + j)] += Ke[12 * (3 * a + i) + 3 * b + j];
+                int64_t k = csr_find(&P->A22, nd[a], nd[b]);
+                S[k] += Se[4 * a + b];
+                P->C.val[k] += Ce[4 * a + b];
+            }
+    }
+    P->tri_A = malloc((nf ? nf : 1) * sizeof(double));
+    P->tri_n = malloc((nf ? nf : 1) * 3 * sizeof(double));
+    P->tri_t1 = malloc((nf ? nf : 1) * 3 * sizeof(double));
+    P->tri_t2 = malloc((nf ? nf : 1) * 3 * sizeof(double));
+    for (int64_t t = 0; t < nf; ++t) {
+        double X[9], Sf[36], Cf[36], gG[9];
+        tri_coords(P, t, X);
+        or_tri_geom(X, P->tri_A + t, P->tri_n + 3 * t, P->tri_t1 + 3 * t, P->tri_t2 + 3 * t, gG);
+        or_tri_flow(X, &P->p, Sf, Cf);
+        const int32_t *nd = P->coh + 6 * t;
+        for (int a = 0; a < 6; ++a)
+            for (int b = 0; b < 6; ++b) {
+                int64_t k = csr_find(&P->A22, nd[a], nd[b]);
+                S[k] += Sf[6 * a + b];
+                P->C.val[k] += Cf[6 * a + b];
+            }
+    }
+    for (int64_t k = 0; k < P->A22.nnz; ++k) P->A22.val[k] = S[k] + P->p.dt * P->C.val[k];
+    free(S);
+    csr_eliminate(&P->Kb, P->dir_u);
+    csr_eliminate(&P->A22, P->dir_p);
+    /* C enters only through the residual; rows of held pressures are dropped there */
+    csr_copy_values(&P->Kt, &P->Kb);
+    int64_t nq = 3 * (nf ? nf : 1);
+    P->qp_trac = calloc(nq * 3, sizeof(double));
+    P->qp_ttr = calloc(nq, sizeof(double));
+    P->qp_flag = calloc(nq, 1);
+    return P;
+}
+
+void or_free(or_problem *P)
+{
+    if (!P) return;
+    csr_free(&P->Kb);
+    csr_free(&P->Kt);
+    csr_free(&P->A22);
+    csr_free(&P->C);
+    free(P->xyz);
+    free(P->tets);
+    free(P->coh);
+    free(P->E);
+    free(P->logk);
+    free(P->dir_u);
+    free(P->dir_p);
+    free(P->tri_A);
+    free(P->tri_n);
+    free(P->tri_t1);
+    free(P->tri_t2);
+    free(P->qp_trac);
+    free(P->qp_ttr);
+    free(P->qp_flag);
+    free(P);
+}
+
+/* which: 0 = K_bulk, 1 = K tangent, 2 = A22, 3 = C */
+static or_csr *pick(or_problem *P, int which)
+{
+    switch (which) {
+    case 0: return &P->Kb;
+    case 1: return &P->Kt;
+    case 2: return &P->A22;
+    default: return &P->C;
+    }
+}
+
+int64_t or_nnz(or_problem *P, int which) { return pick(P, which)->nnz; }
+
+void or_get_csr(or_problem *P, int which, int64_t *rowptr, int32_t *col, double *val)
+{
+    or_csr *A = pick(P, which);
+    memcpy(rowptr, A->rowptr, (A->n + 1) * sizeof(int64_t));
+    memcpy(col, A->col, A->nnz * sizeof(int32_t));
+    memcpy(val, A->val, A->nnz * sizeof(double));
+}
+
+void or_spmv(or_problem *P, int which, const double *x, double *y) { or_csr_spmv(pick(P, which), x, y); }
+
+/* Quadrature on the interface triangle: interior 3-point Gauss rule, weights A/3. */
+static const double QP_N[3][3] = {{2.0 / 3, 1.0 / 6, 1.0 / 6}, {1.0 / 6, 2.0 / 3, 1.0 / 6}, {1.0 / 6, 1.0 / 6, 2.0 / 3}};
+
+/* Interface update (Sec. 2.2.1 and eq. discrete_balance_full, fracture term):
+ * opening at every quadrature point from the displacement U since t = 0,
+ * return map from the start-of-step inelastic slip, the cohesive force
+ * sum_q w N_a (T_q - T_0q) (+ lip) / its negative (- lip), where
+ * T = -t'_n n + t_s1 t1 + t_s2 t2, and the symmetric tangent added to K_bulk. */
+void or_cohesive(or_problem *P, const double *U, const double *die_n, const double *t0, double *trac, double *die,
+                 uint8_t *flag, double *fcoh)
+{
+    int64_t N = P->N;
+    memset(fcoh, 0, 3 * N * sizeof(double));
+    csr_copy_values(&P->Kt, &P->Kb);
+    const double kn = P->p.k_n, ks = P->p.k_s, f = P->p.friction;
+    for (int64_t t = 0; t < P->nf; ++t) {
+        const int32_t *nd = P->coh + 6 * t;
+        const double *n = P->tri_n + 3 * t, *t1 = P->tri_t1 + 3 * t, *t2 = P->tri_t2 + 3 * t;
+        double w = P->tri_A[t] / 3.0;
+        double Kc[18][18];
+        memset(Kc, 0, sizeof Kc);
+        for (int q = 0; q < 3; ++q) {
+            int64_t iq = 3 * t + q;
+            double jump[3] = {0, 0, 0};
+            for (int a = 0; a < 3; ++a)
+                for (int r = 0; r < 3; ++r)
+                    jump[r] += QP_N[q][a] * (U[3 * (int64_t)nd[a] + r] - U[3 * (int64_t)nd[3 + a] + r]);
+            double d[3] = {dot3(n, jump), dot3(t1, jump), dot3(t2, jump)};
+            double Dl[9];
+            double nt = or_return_map(d, die_n + 2 * iq, t0 + 3 * iq, kn, ks, f, trac + 3 * iq, die + 2 * iq, flag + iq, Dl);
+            P->qp_ttr[iq] = nt;
+            P->qp_flag[iq] = flag[iq];
+            memcpy(P->qp_trac + 3 * iq, trac + 3 * iq, 3 * sizeof(double));
+            const double *tr = trac + 3 * iq, *tz = t0 + 3 * iq;
+            double T[3];
+            for (int r = 0; r < 3; ++r)
+                T[r] = -(tr[0] - tz[0]) * n[r] + (tr[1] - tz[1]) * t1[r] + (tr[2] - tz[2]) * t2[r];
+            /* global tangent D = R Dl R^T with R = [n t1 t2] */
+            const double *R[3] = {n, t1, t2};
+            double Dg[3][3];
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) {
+                    double s = 0;
+                    for (int k = 0; k < 3; ++k)
+                        for (int l = 0; l < 3; ++l) s += R[k][r] * Dl[3 * k + l] * R[l][c];
+                    Dg[r][c] = s;
+                }
+            for (int a = 0; a < 3; ++a) {
+                double wa = w * QP_N[q][a];
+                for (int r = 0; r < 3; ++r) {
+                    fcoh[3 * (int64_t)nd[a] + r] += wa * T[r];
+                    fcoh[3 * (int64_t)nd[3 + a] + r] -= wa * T[r];
+                }
+                for (int b = 0; b < 3; ++b) {
+                    double wab = wa * QP_N[q][b];
+                    for (int r = 0; r < 3; ++r)
+                        for (int c = 0; c < 3; ++c) {
+                            double v = wab * Dg[r][c];
+                            Kc[3 * a + r][3 * b + c] += v;
+                            Kc[3 * a + r][9 + 3 * b + c] -= v;
+                            Kc[9 + 3 * a + r][3 * b + c] -= v;
+                            Kc[9 + 3 * a + r][9 + 3 * b + c] += v;
+                        }
+                }
+            }
+        }
+        for (int a = 0; a < 6; ++a)
+            for (int b = 0; b < 6; ++b)
+                for (int r = 0; r < 3; ++r)
+                    for (int c = 0; c < 3; ++c) {
+                        int64_t row = 3 * (int64_t)nd[a] + r, col = 3 * (int64_t)nd[b] + c;
+                        if (P->dir_u[row] || P->dir_u[col]) continue;
+                        P->Kt.val[csr_find(&P->Kt, row, (int32_t)col)] += Kc[3 * a + r][3 * b + c];
+                    }
+    }
+    for (int64_t i = 0; i < 3 * N; ++i)
+        if (P->dir_u[i]) fcoh[i] = 0;
+}
+
+/* A_pu p = (A^m_pu + A^f_pu) p, masked on held displacement rows and held
+ * pressure columns (eq. Apdp and eq. afpdp read as the transpose of eq. afdpd). */
+void or_apply_Apu(or_problem *P, const double *p_in, double *out)
+{
+    int64_t N = P->N;
+    double *p = malloc(N * sizeof(double));
+    for (int64_t i = 0; i < N; ++i) p[i] = P->dir_p[i] ? 0.0 : p_in[i];
+    memset(out, 0, 3 * N * sizeof(double));
+    for (int64_t e = 0; e < P->ne; ++e) {
+        double X[12], Ae[48];
+        tet_coords(P, e, X);
+        or_tet_coupling(X, P->p.alpha, Ae);
+        const int32_t *nd = P->tets + 4 * e;
+        for (int a = 0; a < 4; ++a)
+            for (int i = 0; i < 3; ++i) {
+                double s = 0;
+                for (int b = 0; b < 4; ++b) s += Ae[4 * (3 * a + i) + b] * p[nd[b]];
+                out[3 * (int64_t)nd[a] + i] += s;
+            }
+    }
+    for (int64_t t = 0; t < P->nf; ++t) {
+        const int32_t *nd = P->coh + 6 * t;
+        const double *n = P->tri_n + 3 * t;
+        double A = P->tri_A[t];
+        for (int a = 0; a < 3; ++a) {
+            double s = 0;
+            for (int b = 0; b < 3; ++b) s += 0.5 * A * (a == b ? 2.0 : 1.0) / 12.0 * (p[nd[b]] + p[nd[3 + b]]);
+            for (int r = 0; r < 3; ++r) {
+                out[3 * (int64_t)nd[a] + r] += s * n[r];
+                out[3 * (int64_t)nd[3 + a] + r] -= s * n[r];
+            }
+        }
+    }
+    for (int64_t i = 0; i < 3 * N; ++i)
+        if (P->dir_u[i]) out[i] = 0;
+    free(p);
+}
+
+/* A_up u = (A^m_up + A^f_up) u (eq. Adpd and eq. afdpd), the exact transpose of or_apply_Apu. */
+void or_apply_Aup(or_problem *P, const double *u_in, double *out)
+{
+    int64_t N = P->N;
+    double *u = malloc(3 * N * sizeof(double));
+    for (int64_t i = 0; i < 3 * N; ++i) u[i] = P->dir_u[i] ? 0.0 : u_in[i];
+    memset(out, 0, N * sizeof(double));
+    for (int64_t e = 0; e < P->ne; ++e) {
+        double X[12], Ae[48];
+        tet_coords(P, e, X);
+        or_tet_coupling(X, P->p.alpha, Ae);
+        const int32_t *nd = P->tets + 4 * e;
+        for (int b = 0; b < 4; ++b) {
+            double s = 0;
+            for (int a = 0; a < 4; ++a)
+                for (int i = 0; i < 3; ++i) s += Ae[4 * (3 * a + i) + b] * u[3 * (int64_t)nd[a] + i];
+            out[nd[b]] += s;
+        }
+    }
+    for (int64_t t = 0; t < P->nf; ++t) {
+        const int32_t *nd = P->coh + 6 * t;
+        const double *n = P->tri_n + 3 * t;
+        double A = P->tri_A[t];
+        for (int b = 0; b < 3; ++b) {
+            double s = 0;
+            for (int a = 0; a < 3; ++a) {
+                double dn = 0;
+                for (int r = 0; r < 3; ++r) dn += n[r] * (u[3 * (int64_t)nd[a] + r] - u[3 * (int64_t)nd[3 + a] + r]);
+                s += 0.5 * A * (a == b ? 2.0 : 1.0) / 12.0 * dn;
+            }
+            out[nd[b]] += s;
+            out[nd[3 + b]] += s;
+        }
+    }
+    for (int64_t i = 0; i < N; ++i)
+        if (P->dir_p[i]) out[i] = 0;
+    free(u);
+}
+
+/* ------------------------------------------------------------------ */
+/* solvers                                                             */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int64_t iters;
+    double relres;
+    int status; /* 0 converged, 1 not converged, -3 breakdown */
+} or_cg_info;
+
+/* Point-Jacobi preconditioned CG (Hestenes-Stiefel, cited in Sec. 3.3.2),
+ * x0 = 0, stop on the unpreconditioned ||r||/||b||. */
+static or_cg_info pcg(const or_csr *A, const double *b, double *x, double tol, int64_t maxit)
+{
+    int64_t n = A->n;
+    or_cg_info info = {0, 0.0, 0};
+    double *r = malloc(n * sizeof(double)), *z = malloc(n * sizeof(double));
+    double *p = malloc(n * sizeof(double)), *q = malloc(n * sizeof(double)), *dinv = malloc(n * sizeof(double));
+    for (int64_t i = 0; i < n; ++i) {
+        double d = 0;
+        for (int64_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k)
+            if (A->col[k] == i) d = A->val[k];
+        dinv[i] = 1.0 / d;
+        x[i] = 0;
+        r[i] = b[i];
+        z[i] = dinv[i] * r[i];
+        p[i] = z[i];
+    }
+    double bn = sqrt(vdot(n, b, b));
+    if (bn == 0.0) goto done;
+    double rho = vdot(n, r, z);
+    for (;;) {
+        double rn = sqrt(vdot(n, r, r));
+        info.relres = rn / bn;
+        if (info.relres <= tol) break;
+        if (info.iters >= maxit) {
+            info.status = 1;
+            break;
+        }
+        or_csr_spmv(A, p, q);
+        double pq = vdot(n, p, q);
+        if (!(pq > 0.0)) {
+            info.status = -3;
+            break;
+        }
+        double al = rho / pq;
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            x[i] += al * p[i];
+            r[i] -= al * q[i];
+            z[i] = dinv[i] * r[i];
+        }
+        double rho2 = vdot(n, r, z);
+        double be = rho2 / rho;
+        rho = rho2;
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) p[i] = z[i] + be * p[i];
+        info.iters++;
+    }
+done:
+    free(r);
+    free(z);
+    free(p);
+    free(q);
+    free(dinv);
+    return info;
+}
+
+int or_pcg(or_problem *P, int which, const double *b, double *x, double tol, int64_t maxit, int64_t *iters, double *relres)
+{
+    or_cg_info in = pcg(pick(P, which), b, x, tol, maxit);
+    *iters = in.iters;
+    *relres = in.relres;
+    return in.status;
+}
+
+/* Partitioned CG of Prevost (Sec. 3.3.2, eq. prevost_system and schur_system):
+ * solve [[K, -A],[A^T, A22]] [x1; x2] = [b1; b2] through CG on the Schur
+ * complement A22 + A^T K^{-1} A preconditioned by A22^{-1}, never forming it;
+ * K^{-1} and A22^{-1} are inner Jacobi-PCG solves.  The Polak-Ribiere form of
+ * beta keeps the outer iteration stable under inexact inner solves.
+ * stats: [outer iters, inner K iters, inner A22 iters, outer relres, status] */
+int or_prevost(or_problem *P, const double *b1, const double *b2, double *x1, double *x2, double tol_outer,
+               double tol_inner, int64_t maxit_outer, int64_t maxit_inner, double *stats)
+{
+    int64_t n1 = 3 * P->N, n2 = P->N;
+    or_csr *K = &P->Kt, *A22 = &P->A22;
+    double *y = calloc(n1, sizeof(double)), *w = calloc(n1, sizeof(double)), *t1 = calloc(n1, sizeof(double));
+    double *r = calloc(n2, sizeof(double)), *z = calloc(n2, sizeof(double)), *zn = calloc(n2, sizeof(double));
+    double *d = calloc(n2, sizeof(double)), *Sd = calloc(n2, sizeof(double)), *t2 = calloc(n2, sizeof(double));
+    int64_t itK = 0, itA = 0, outer = 0;
+    int status = 0;
+    or_cg_info ci;
+
+    ci = pcg(K, b1, y, tol_inner, maxit_inner); /* y0 = K^-1 b1 */
+    itK += ci.iters;
+    if (ci.status < 0) status = ci.status;
+    or_apply_Aup(P, y, t2);
+    for (int64_t i = 0; i < n2; ++i) {
+        r[i] = b2[i] - t2[i];
+        x2[i] = 0;
+    }
+    double r0 = sqrt(vdot(n2, r, r));
+    double relres = 0;
+    if (r0 > 0 && status == 0) {
+        ci = pcg(A22, r, z, tol_inner, maxit_inner);
+        itA += ci.iters;
+        memcpy(d, z, n2 * sizeof(double));
+        double rz = vdot(n2, r, z);
+        for (;;) {
+            or_apply_Apu(P, d, t1);
+            ci = pcg(K, t1, w, tol_inner, maxit_inner); /* w = K^-1 A d */
+            itK += ci.iters;
+            if (ci.status < 0) {
+                status = ci.status;
+                break;
+            }
+            or_apply_Aup(P, w, t2);
+            or_csr_spmv(A22, d, Sd);
+            for (int64_t i = 0; i < n2; ++i) Sd[i] += t2[i];
+            double dSd = vdot(n2, d, Sd);
+            if (!(dSd > 0)) {
+                status = -3;
+                break;
+            }
+            double al = rz / dSd;
+            for (int64_t i = 0; i < n2; ++i) {
+                x2[i] += al * d[i];
+                r[i] -= al * Sd[i];
+            }
+            for (int64_t i = 0; i < n1; ++i) y[i] += al * w[i];
+            outer++;
+            relres = sqrt(vdot(n2, r, r)) / r0;
+            if (relres <= tol_outer) break;
+            if (outer >= maxit_outer) {
+                status = 1;
+                break;
+            }
+            ci = pcg(A22, r, zn, tol_inner, maxit_inner);
+            itA += ci.iters;
+            double rzn = vdot(n2, r, zn);
+            double rzo = 0;
+            for (int64_t i = 0; i < n2; ++i) rzo += r[i] * z[i];
+            double be = (rzn - rzo) / rz;
+            for (int64_t i = 0; i < n2; ++i) d[i] = zn[i] + be * d[i];
+            memcpy(z, zn, n2 * sizeof(double));
+            rz = rzn;
+        }
+    }
+    memcpy(x1, y, n1 * sizeof(double));
+    stats[0] = (double)outer;
+    stats[1] = (double)itK;
+    stats[2] = (double)itA;
+    stats[3] = relres;
+    stats[4] = (double)status;
+    free(y);
+    free(w);
+    free(t1);
+    free(r);
+    free(z);
+    free(zn);
+    free(d);
+    free(Sd);
+    free(t2);
+    return status;
+}
+
+static double vnorm(int64_t n, const double *a) { return sqrt(vdot(n, a, a)); }
+
+/* Residuals of eq. nonlinear_system in total form with respect to t = 0:
+ *   R_m = K_bulk U + f_coh(U) - A_pu P - F_u
+ *   R_f = A_up (U - U_n) + A22 (P - P_n) + dt (C P_n - f_p)
+ * rows of held DOFs are zero. */
+void or_residual(or_problem *P, const double *U, const double *P_, const double *Un, const double *Pn,
+                 const double *fcoh, const double *Fu, const double *fp, double *Rm, double *Rf)
+{
+    int64_t N = P->N;
+    double *t1 = malloc(3 * N * sizeof(double)), *du = malloc(3 * N * sizeof(double));
+    double *t2 = malloc(N * sizeof(double)), *dp = malloc(N * sizeof(double));
+    or_csr_spmv(&P->Kb, U, Rm);
+    or_apply_Apu(P, P_, t1);
+    for (int64_t i = 0; i < 3 * N; ++i) Rm[i] = P->dir_u[i] ? 0.0 : Rm[i] + fcoh[i] - t1[i] - Fu[i];
+    for (int64_t i = 0; i < 3 * N; ++i) du[i] = U[i] - Un[i];
+    for (int64_t i = 0; i < N; ++i) dp[i] = P_[i] - Pn[i];
+    or_apply_Aup(P, du, Rf);
+    or_csr_spmv(&P->A22, dp, t2);
+    for (int64_t i = 0; i < N; ++i) Rf[i] += t2[i];
+    or_csr_spmv(&P->C, Pn, t2);
+    for (int64_t i = 0; i < N; ++i) Rf[i] = P->dir_p[i] ? 0.0 : Rf[i] + P->p.dt * (t2[i] - fp[i]);
+    free(t1);
+    free(t2);
+    free(du);
+    free(dp);
+}
+
+/* One implicit step (Sec. 3.3, eq. nonlinear_system and linear_system):
+ * Newton on (U, P) from the state at t_n with an elastic-predictor /
+ * plastic-corrector interface update at every iterate and a Prevost solve of
+ * each Jacobian system.  Convergence: ||R_m|| <= tol s_m and ||R_f|| <= tol s_f
+ * with s_m = max(||R_m^0||, ||A_pu P||, ||F_u||), s_f = max(||R_f^0||, dt ||f_p||).
+ * In/out: U, P (totals since t = 0), die (inelastic slip per qp).
+ * Out: trac, flag per qp.
+ * info: [newton its, outer its, inner K its, inner A22 its, ||Rm||/s_m, ||Rf||/s_f, status] */
+int or_step(or_problem *P, double *U, double *Pp, double *die, double *trac, uint8_t *flag, const double *t0,
+            const double *Fu, const double *fp, double tol_newton, int64_t max_newton, double tol_outer,
+            double tol_inner, int64_t maxit_outer, int64_t maxit_inner, double *info)
+{
+    int64_t N = P->N, nq = 3 * P->nf;
+    double *Un = malloc(3 * N * sizeof(double)), *Pn = malloc(N * sizeof(double));
+    memcpy(Un, U, 3 * N * sizeof(double));
+    memcpy(Pn, Pp, N * sizeof(double));
+    double *die_n = malloc((nq ? nq : 1) * 2 * sizeof(double));
+    memcpy(die_n, die, nq * 2 * sizeof(double));
+    double *fcoh = malloc(3 * N * sizeof(double)), *Rm = malloc(3 * N * sizeof(double)), *Rf = malloc(N * sizeof(double));
+    double *du = malloc(3 * N * sizeof(double)), *dp = malloc(N * sizeof(double));
+    double *t1 = malloc(3 * N * sizeof(double));
+    double sm = 0, sf = 0;
+    int64_t it = 0;
+    int status = 1;
+    double st[5], tot_outer = 0, tot_K = 0, tot_A = 0, em = 0, ef = 0;
+    for (;;) {
+        or_cohesive(P, U, die_n, t0, trac, die, flag, fcoh);
+        or_residual(P, U, Pp, Un, Pn, fcoh, Fu, fp, Rm, Rf);
+        double rm = vnorm(3 * N, Rm), rf = vnorm(N, Rf);
+        if (it == 0) {
+            or_apply_Apu(P, Pp, t1);
+            sm = fmax(rm, fmax(vnorm(3 * N, t1), vnorm(3 * N, Fu)));
+            sf = fmax(rf, P->p.dt * vnorm(N, fp));
+        } else {
+            or_apply_Apu(P, Pp, t1);
+            sm = fmax(sm, vnorm(3 * N, t1));
+        }
+        em = sm > 0 ? rm / sm : rm;
+        ef = sf > 0 ? rf / sf : rf;
+        if (em <= tol_newton && ef <= tol_newton) {
+            status = 0;
+            break;
+        }
+        if (it >= max_newton) {
+            status = 1;
+            break;
+        }
+        for (int64_t i = 0; i < 3 * N; ++i) Rm[i] = -Rm[i];
+        for (int64_t i = 0; i < N; ++i) Rf[i] = -Rf[i];
+        int s = or_prevost(P, Rm, Rf, du, dp, tol_outer, tol_inner, maxit_outer, maxit_inner, st);
+        tot_outer += st[0];
+        tot_K += st[1];
+        tot_A += st[2];
+        if (s < 0) {
+            status = s;
+            break;
+        }
+        for (int64_t i = 0; i < 3 * N; ++i) U[i] += du[i];
+        for (int64_t i = 0; i < N; ++i) Pp[i] += dp[i];
+        it++;
+    }
+    info[0] = (double)it;
+    info[1] = tot_outer;
+    info[2] = tot_K;
+    info[3] = tot_A;
+    info[4] = em;
+    info[5] = ef;
+    info[6] = (double)status;
+    free(Un);
+    free(Pn);
+    free(die_n);
+    free(fcoh);
+    free(Rm);
+    free(Rf);
+    free(du);
+    free(dp);
+    free(t1);
+    return status;
+}
+
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,290 @@
+"""System-level pins of the oracle: mesh counts, patch tests, a free poroelastic
+cube, the monolithic direct solve against the partitioned CG, fluid-volume
+balance, Terzaghi consolidation (textbook series) and fracture flow from a
+point injection (Theis line source with the prefactor printed in Sec. 4.2).
+"""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+import scipy.special
+
+from oracle import oracle as O
+from paper_2410_17133_amd import inputs as I
+
+
+def box_instance(nx, ny, nz, L=(1.0, 1.0, 1.0), fault_i=None, params=None, E=10e9, lnk=math.log(1e-15), dip=90.0):
+    mesh = I.make_mesh(nx, ny, nz, L, fault_i=fault_i, dip_deg=dip)
+    N = mesh.n_nodes
+    ne = mesh.tets.shape[0]
+    prm = params or I.Params()
+    cfg = I.Config("box", nx, fault=fault_i is not None, params=prm)
+    return I.Instance(cfg, mesh, prm, np.full(ne, E), np.full(ne, lnk), np.zeros(3 * N, np.uint8),
+                      np.zeros(N, np.uint8), np.zeros(N), np.zeros(3 * N),
+                      np.zeros((mesh.coh.shape[0] * 3, 3)))
+
+
+# ------------------------------------------------------------ mesh
+@pytest.mark.parametrize("n", [2, 4, 8])
+def test_mesh_counts_and_conformity(n):
+    inst = I.make_instance(I.cube_config(n))
+    m = inst.mesh
+    assert m.tets.shape[0] == 6 * n ** 3
+    assert m.n_nodes == (n + 1) ** 3 + (n + 1) ** 2
+    assert m.coh.shape[0] == 2 * n * n
+    faces = set()
+    for t in m.tets:
+        for drop in range(4):
+            faces.add(tuple(sorted(np.delete(t, drop).tolist())))
+    for c in m.coh:
+        assert tuple(sorted(c[:3].tolist())) in faces
+        assert tuple(sorted(c[3:].tolist())) in faces
+        np.testing.assert_array_equal(m.xyz[c[:3]], m.xyz[c[3:]])
+    P = O.Problem(inst)
+    E = 3 * n * (n + 1) ** 2 + 3 * n * n * (n + 1) + n ** 3
+    Epl = 2 * n * (n + 1) + n * n
+    nnzb = (n + 1) ** 3 + 2 * E + 3 * (n + 1) ** 2 + 6 * Epl
+    assert P.csr(O.A22)[1].size == nnzb
+    assert P.csr(O.K_BULK)[1].size == 9 * nnzb
+
+
+# ------------------------------------------------------------ patch tests
+def _boundary_nodes(mesh):
+    g = mesh.grid
+    return (g[:, 0] == 0) | (g[:, 0] == mesh.nx) | (g[:, 1] == 0) | (g[:, 1] == mesh.ny) | (g[:, 2] == 0) | (g[:, 2] == mesh.nz)
+
+
+def test_displacement_patch_test():
+    inst = box_instance(4, 3, 5, L=(1.0, 0.7, 1.3))
+    m = inst.mesh
+    r = np.random.default_rng(3)
+    m.xyz[:] += 0.03 * r.standard_normal(m.xyz.shape) * (~_boundary_nodes(m))[:, None]  # distorted interior
+    H, c = r.standard_normal((3, 3)), r.standard_normal(3)
+    u_lin = (m.xyz @ H.T + c).reshape(-1)
+    free = O.Problem(inst)
+    Ku = free.spmv(O.K_BULK, u_lin)
+    bnd = np.repeat(_boundary_nodes(m), 3)
+    assert np.abs(Ku[~bnd]).max() <= 1e-12 * np.abs(Ku).max()   # interior rows annihilate a linear field
+    inst.dir_u[bnd] = 1
+    held = O.Problem(inst)
+    b = -free.spmv(O.K_BULK, np.where(bnd, u_lin, 0.0))
+    b[bnd] = u_lin[bnd]
+    x, st, it, rr = held.pcg(O.K_BULK, b, tol=1e-14)
+    assert st == 0
+    np.testing.assert_allclose(x, u_lin, rtol=0, atol=1e-10 * np.abs(u_lin).max())
+
+
+def test_pressure_patch_test_steady():
+    inst = box_instance(3, 4, 3)
+    m = inst.mesh
+    P = O.Problem(inst)
+    gp = np.array([0.3, -1.1, 2.0])
+    p_lin = 5.0 + m.xyz @ gp
+    Cp = P.spmv(O.C_FLOW, p_lin)
+    inner = ~_boundary_nodes(m)
+    assert np.abs(Cp[inner]).max() <= 1e-12 * np.abs(Cp).max()
+    np.testing.assert_allclose(P.spmv(O.C_FLOW, np.ones(P.N)), 0, atol=1e-12 * np.abs(Cp).max())
+
+
+def test_free_cube_uniform_pressure():
+    # sigma = C:eps - alpha p I = 0 with free faces -> eps = alpha p / (3K) I (uniform)
+    prm = I.Params(nu=0.2, alpha=0.7)
+    E = 12e9
+    inst = box_instance(3, 3, 3, params=prm, E=E)
+    m = inst.mesh
+    g = m.grid
+    corner = np.nonzero((g == 0).all(1))[0][0]
+    xnode = np.nonzero((g[:, 0] == m.nx) & (g[:, 1] == 0) & (g[:, 2] == 0))[0][0]
+    ynode = np.nonzero((g[:, 0] == 0) & (g[:, 1] == m.ny) & (g[:, 2] == 0))[0][0]
+    inst.dir_u[3 * corner:3 * corner + 3] = 1
+    inst.dir_u[[3 * xnode + 1, 3 * xnode + 2, 3 * ynode + 0, 3 * ynode + 2]] = 1
+    P = O.Problem(inst)
+    dp = 2.5e6
+    b = P.apply_Apu(np.full(P.N, dp))
+    u, st, it, rr = P.pcg(O.K_BULK, b, tol=1e-14)
+    K = E / (3 * (1 - 2 * prm.nu))
+    e = prm.alpha * dp / (3 * K)
+    np.testing.assert_allclose(u.reshape(-1, 3), e * m.xyz, rtol=0, atol=1e-9 * e)
+
+
+def test_coupling_transpose_and_divergence_identity():
+    inst = I.make_instance(I.cube_config(4, dip_deg=70))
+    inst.dir_u[:] = 0
+    P = O.Problem(inst)
+    r = np.random.default_rng(0)
+    u, p = r.standard_normal(3 * P.N), r.standard_normal(P.N)
+    lhs, rhs = u @ P.apply_Apu(p), P.apply_Aup(u) @ p
+    assert lhs == pytest.approx(rhs, rel=1e-13)
+    # matrix part: u = s (x, 0, 0) continuous across the fault (no opening), p = 1 + x + 2y
+    m = inst.mesh
+    u = np.zeros((P.N, 3))
+    u[:, 0] = 0.3 * m.xyz[:, 0]
+    pl = 1 + m.xyz[:, 0] + 2 * m.xyz[:, 1]
+    assert u.reshape(-1) @ P.apply_Apu(pl) == pytest.approx(1.0 * 0.3 * 2.5, rel=1e-12)
+
+
+def test_fracture_coupling_opening_volume():
+    # A_up of a uniform normal opening w on the whole fault = w * area split evenly on the lips
+    inst = I.make_instance(I.cube_config(4))
+    inst.dir_u[:] = 0
+    P = O.Problem(inst)
+    m = inst.mesh
+    u = np.zeros((P.N, 3))
+    plus = m.pairs[:, 1]
+    right = np.isin(np.arange(P.N), m.tets[(m.xyz[m.tets].mean(1)[:, 0] > 0.5)].reshape(-1))
+    u[right, 0] = 1e-4          # rigid shift of the + block along +x (the fault normal)
+    vol = P.apply_Aup(u.reshape(-1))
+    assert vol.sum() == pytest.approx(1e-4 * 1.0, rel=1e-12)    # fault area 1 m^2
+    assert vol[m.pairs[:, 0]].sum() == pytest.approx(vol[plus].sum(), rel=1e-12)
+
+
+# ------------------------------------------------------------ partitioned CG = monolithic solve
+def _dense_coupling(P):
+    return np.stack([P.apply_Apu(e) for e in np.eye(P.N)], 1)
+
+
+def test_prevost_equals_dense_lu():
+    inst = I.make_instance(I.config(1))
+    P = O.Problem(inst)
+    # a state with stick, slip and contact points
+    r = np.random.default_rng(5)
+    U = r.normal(0, 3e-6, 3 * P.N) * (1 - inst.dir_u)
+    trac, die, flag, fcoh = P.cohesive(U, np.zeros((P.nq, 2)))
+    assert (flag == 1).sum() > 0 and (flag == 0).sum() > 0
+    K = P.scipy(O.K_TANGENT).toarray()
+    A22 = P.scipy(O.A22).toarray()
+    A = _dense_coupling(P)
+    J = np.block([[K, -A], [A.T, A22]])
+    b1 = r.standard_normal(3 * P.N) * 1e6 * (1 - inst.dir_u)
+    b2 = r.standard_normal(P.N) * 1e-6
+    x = np.linalg.solve(J, np.r_[b1, b2])
+    x1, x2, st, stats = P.prevost(b1, b2, tol_outer=1e-13, tol_inner=1e-14)
+    assert st == 0
+    assert np.linalg.norm(x1 - x[:3 * P.N]) <= 1e-8 * np.linalg.norm(x[:3 * P.N])
+    assert np.linalg.norm(x2 - x[3 * P.N:]) <= 1e-8 * np.linalg.norm(x[3 * P.N:])
+    # the Schur complement is SPD
+    Kinv_A = np.linalg.solve(K, A)
+    S = A22 + A.T @ Kinv_A
+    assert np.linalg.eigvalsh(0.5 * (S + S.T)).min() > 0
+
+
+def test_cohesive_force_and_tangent_consistent():
+    """Global cohesive force f_coh(U) and the assembled tangent K_t - K_bulk agree
+    by central differences wherever the tangent is exact (stick and contact)."""
+    inst = I.make_instance(I.config(1))
+    P = O.Problem(inst)
+    r = np.random.default_rng(11)
+    free = 1.0 - inst.dir_u
+    U = r.normal(0, 1e-8, 3 * P.N) * free
+    die = np.zeros((P.nq, 2))
+    _, _, flag, _ = P.cohesive(U, die)
+    assert np.all(flag == 0)
+    Kt = P.scipy(O.K_TANGENT)
+    Kb = P.scipy(O.K_BULK)
+    v = r.standard_normal(3 * P.N) * free
+    h = 1e-12
+    fp = P.cohesive(U + h * v, die)[3]
+    fm = P.cohesive(U - h * v, die)[3]
+    fd = (fp - fm) / (2 * h)
+    np.testing.assert_allclose((Kt - Kb) @ v, fd, rtol=0, atol=1e-6 * np.abs(fd).max())
+
+
+# ------------------------------------------------------------ whole step
+def test_step_volume_balance_and_equilibrium():
+    inst = I.make_instance(I.config(1))
+    P = O.Problem(inst)
+    U, Pp, die = np.zeros(3 * P.N), np.zeros(P.N), np.zeros((P.nq, 2))
+    trac, flag, info, st = P.step(U, Pp, die)
+    assert st == 0
+    dt, Q = inst.params.dt, inst.cfg.Q
+    stored = P.apply_Aup(U).sum() + P.spmv(O.A22, Pp).sum()
+    assert stored == pytest.approx(dt * Q, rel=1e-9)
+    # equilibrium of the converged state (residual of the oracle's own operators)
+    _, _, _, fcoh = P.cohesive(U, np.zeros((P.nq, 2)))
+    Rm, Rf = P.residual(U, Pp, np.zeros_like(U), np.zeros_like(Pp), fcoh)
+    assert np.linalg.norm(Rm) <= 1e-9 * np.linalg.norm(P.apply_Apu(Pp))
+    # the injection drives slip at the centre of the fault
+    assert (flag == 1).sum() > 0
+    assert Pp.max() == pytest.approx(Pp[inst.centre_pair[0]])
+
+
+# ------------------------------------------------------------ Terzaghi consolidation
+def terzaghi(zp, t, H, cv, p0, terms=400):
+    m = np.arange(terms)[:, None]
+    k = (2 * m + 1) * math.pi / (2 * H)
+    return p0 * np.sum(4 / ((2 * m + 1) * math.pi) * np.sin(k * zp) * np.exp(-k * k * cv * t), axis=0)
+
+
+@pytest.mark.slow
+def test_terzaghi_column():
+    nz, H, dt = 64, 1.0, 0.25
+    prm = I.Params(nu=0.25, alpha=1.0, biot_M=22.7e9, mu=0.89e-3, dt=dt)
+    E, k = 10e9, 1e-15
+    inst = box_instance(1, 1, nz, L=(H / nz, H / nz, H), params=prm, E=E, lnk=math.log(k))
+    m = inst.mesh
+    g = m.grid
+    inst.dir_u[0::3] = 1                       # one hex wide: every node is on an x face
+    inst.dir_u[1::3] = 1                       # ... and on a y face
+    inst.dir_u[2::3][g[:, 2] == 0] = 1         # bottom held vertically
+    top = g[:, 2] == nz
+    inst.dir_p[top] = 1                        # drained top
+    sigma0 = 1e6
+    Fu = np.zeros(3 * m.n_nodes)
+    Fu[2::3][top] = -sigma0 * (H / nz) ** 2 / 4
+    P = O.Problem(inst)
+    lam = E * prm.nu / ((1 + prm.nu) * (1 - 2 * prm.nu))
+    G = E / (2 * (1 + prm.nu))
+    Kv = lam + 2 * G
+    p0 = prm.alpha * prm.biot_M * sigma0 / (Kv + prm.alpha ** 2 * prm.biot_M)
+    cv = k / prm.mu / (1 / prm.biot_M + prm.alpha ** 2 / Kv)
+    U, Pp, die = np.zeros(3 * P.N), np.zeros(P.N), np.zeros((0, 2))
+    nsteps = 160
+    for s in range(nsteps):
+        _, _, info, st = P.step(U, Pp, die, Fu=Fu, fp=np.zeros(P.N), tol_outer=1e-12, tol_inner=1e-13)
+        assert st == 0
+    t = nsteps * dt
+    zp = H - m.xyz[:, 2]
+    sel = (zp > 0.05) & (zp < 0.95)
+    ref = terzaghi(zp[sel], t, H, cv, p0)
+    assert 0.1 < cv * t / H ** 2 < 1.0
+    assert np.abs(Pp[sel] - ref).max() <= 0.01 * p0
+
+
+# ------------------------------------------------------------ fracture flow from a point injection
+@pytest.mark.slow
+def test_fracture_point_injection_theis():
+    """Pressure on an isolated fracture fed at constant rate Q: with an
+    impermeable, stiff-storage matrix it is the line-source solution
+    p = dp* E1(r^2 / (4 a_f t)), dp* = Q mu / (4 pi k_par w) (Sec. 4.2),
+    a_f = k_par M_F / mu (conductance w k_par / mu over storage w / M_F)."""
+    n = 32
+    prm = I.Params(mu=0.89e-3, biot_M=1e14, k_par=1e-12, k_perp=1e-12, w0=1e-3, M_F=0.2e6, dt=0.25)
+    inst = box_instance(n, n, n, fault_i=n // 2, params=prm, lnk=math.log(1e-30))
+    m = inst.mesh
+    P = O.Problem(inst)
+    c = n // 2 + (n + 1) * (n // 2)
+    Q = 1e-6
+    fp = np.zeros(P.N)
+    fp[m.pairs[c]] = Q / 2
+    p = np.zeros(P.N)
+    steps = 120
+    for _ in range(steps):
+        rhs = prm.dt * (fp - P.spmv(O.C_FLOW, p))
+        dp, st, it, rr = P.pcg(O.A22, rhs, tol=1e-13)
+        assert st == 0
+        p += dp
+    t = steps * prm.dt
+    af = prm.k_par * prm.M_F / prm.mu
+    dps = Q * prm.mu / (4 * math.pi * prm.k_par * prm.w0)
+    xy = m.xyz[m.pairs[:, 0]][:, 1:] - 0.5
+    r = np.hypot(xy[:, 0], xy[:, 1])
+    h = 1.0 / n
+    num = 0.5 * (p[m.pairs[:, 0]] + p[m.pairs[:, 1]])
+    assert math.sqrt(4 * af * t) < 0.3           # front well inside the plane
+    # the structured triangulation biases diagonal directions; ring means cancel that bias
+    for ring in range(1, 6):
+        sel = (r > (ring - 0.5) * h) & (r <= (ring + 0.5) * h)
+        ref = dps * scipy.special.exp1(r[sel] ** 2 / (4 * af * t))
+        assert abs(num[sel].mean() / ref.mean() - 1) < 0.02
+        np.testing.assert_allclose(num[sel], ref, rtol=0.06)
