@@ -1,0 +1,240 @@
+/*
+ * fg.h -- C-ABI of libfg, an MI355X (gfx950) implementation of the hot path of
+ * the fully implicit flow / geomechanics scheme of Gallyamov et al., "A
+ * Parallelized 3D Geomechanical Solver for Fluid-induced Fault Slip in
+ * Poroelastic Media" (arXiv 2410.17133): the assembled linear-tetrahedron
+ * poroelastic stiffness with zero-thickness cohesive fault elements, the scalar
+ * pressure system with double-node fracture flow, and the preconditioned CG
+ * solves that the partitioned (Prevost) iteration runs in every Newton step.
+ *
+ * Conventions shared by every entry point
+ *  - Ownership.  Pointers named *_h are host memory, all others are device
+ *    memory on the context's GPU.  Every buffer is owned by the caller; libfg
+ *    owns only the opaque fg_ctx / fg_system objects and their workspaces,
+ *    freed by the matching *_destroy call.  No call hands out memory the
+ *    caller must free.
+ *  - Ordering.  Nodes are numbered by the caller; displacement vectors are
+ *    node-major [u0x,u0y,u0z,u1x,...] (length 3N), pressure vectors have length
+ *    N.  libfg permutes internally; inputs and outputs are always in the
+ *    caller's order.  Interface quadrature points are numbered 3*t+q for
+ *    cohesive element t and point q of the interior 3-point Gauss rule
+ *    (barycentric (2/3,1/6,1/6) and its permutations, weights area/3).
+ *  - Mesh.  tets[e*4..e*4+3] are the four vertices of a linear tetrahedron.
+ *    coh[t*6..t*6+5] = [+a,+b,+c,-a,-b,-c] is a zero-thickness interface element
+ *    (Sec. 3.1.1): the same triangle seen from the + lip and the - lip, with
+ *    (x_b-x_a) x (x_c-x_a) pointing from the - lip to the + lip.  That cross
+ *    product defines the element normal n; t1 is the unit projection of +z on
+ *    the plane (of +x if the plane is horizontal) and t2 = n x t1.  Geometry is
+ *    frozen at the reference configuration (small deformation).
+ *  - Unknowns.  U and P are the displacement and pressure changes since t = 0
+ *    (the initial state is in equilibrium, Sec. 2.1); held DOFs (dir_u, dir_p)
+ *    stay zero and are eliminated symmetrically (zero row and column, unit
+ *    diagonal).
+ *  - Streams.  Every call is ordered on `stream` (a hipStream_t; 0 = the null
+ *    stream).  Calls that report scalars (iterations, residuals) synchronise
+ *    that stream before returning.
+ *  - Errors.  Every call returns an fg_status; on error fg_last_error() returns
+ *    a message for the calling thread.  No C++ exception crosses the ABI.
+ *    Outputs are unspecified after an error other than FG_NOT_CONVERGED.
+ */
+#ifndef FG_H
+#define FG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int fg_status;
+#define FG_OK 0
+#define FG_NOT_CONVERGED 1   /* result valid, tolerance not reached within max_iter */
+#define FG_ERR_ARG (-1)      /* bad argument: null pointer, size mismatch, malformed mesh */
+#define FG_ERR_OOM (-2)      /* device or host allocation failed */
+#define FG_ERR_BREAKDOWN (-3) /* CG breakdown: p.Ap <= 0 (matrix not SPD) */
+#define FG_ERR_NAN (-4)      /* NaN or Inf met in a residual or a CG scalar */
+#define FG_ERR_HIP (-5)      /* HIP runtime error (launch, copy) */
+#define FG_ERR_STATE (-6)    /* call out of order (e.g. solve before fg_assemble) */
+
+/* Which operator a solve or product uses. */
+#define FG_K 0      /* tangent stiffness K = K_bulk + interface tangent (3 DOFs per node) */
+#define FG_A22 1    /* pressure operator A22 = S + dt C (eq. prevost_system) */
+#define FG_KBULK 2  /* bulk stiffness only (products and export, not solves) */
+#define FG_C 3      /* conductivity C (products and export) */
+
+/* Arithmetic of a K solve. */
+#define FG_F64 0    /* FP64 storage and arithmetic */
+#define FG_F32 1    /* FP32 matrix and vectors throughout (no refinement) */
+#define FG_MIXED 2  /* FP32 inner PCG, FP64 residual and iterative refinement */
+
+typedef struct fg_ctx fg_ctx;
+typedef struct fg_system fg_system;
+
+/* Material, fluid, fault and time-step scalars (SI units).  nu, alpha: Poisson
+ * ratio and Biot coefficient (eq. stress); biot_M: Biot modulus (eq.
+ * fluid_content); mu: viscosity (eq. darcy_matrix); k_par, k_perp: fault
+ * permeabilities along and across the plane, w0: default hydraulic aperture,
+ * M_F: fracture Biot modulus, S_F = 1/M_F (eq. flux_decompose_operators,
+ * discrete_mass_fracture); k_n, k_s [Pa/m]: normal and shear penalties,
+ * friction: Coulomb coefficient (eq. normal_traction, yield_function); dt:
+ * backward-Euler step (eq. time_disc). */
+typedef struct {
+    double nu, alpha, biot_M, mu, k_par, k_perp, w0, M_F, k_n, k_s, friction, dt;
+} fg_params;
+
+/* Mesh and boundary masks, all host arrays, copied by fg_system_create. */
+typedef struct {
+    int64_t n_nodes, n_tets, n_coh;
+    const double *xyz_h;     /* [n_nodes*3] coordinates */
+    const int32_t *tets_h;   /* [n_tets*4] */
+    const int32_t *coh_h;    /* [n_coh*6], may be NULL when n_coh == 0 */
+    const uint8_t *dir_u_h;  /* [3*n_nodes], 1 = displacement DOF held at zero */
+    const uint8_t *dir_p_h;  /* [n_nodes], 1 = pressure DOF held at zero */
+} fg_mesh;
+
+typedef struct {
+    double tol;          /* stop when ||b - A x||_2 <= tol ||b||_2 (K solves: FP64 residual for FG_MIXED) */
+    int64_t max_iter;    /* CG iterations (inner iterations in total for FG_MIXED) */
+    int precision;       /* FG_F64 / FG_F32 / FG_MIXED (K only; A22 solves are FP64) */
+    int check_every;     /* iterations between convergence polls by the host (0 = default 32) */
+    double inner_tol;    /* FG_MIXED: relative tolerance of each FP32 inner solve (0 = default 1e-4) */
+} fg_pcg_opts;
+
+typedef struct {
+    int64_t iters;       /* CG iterations performed (sum over refinement cycles) */
+    int64_t cycles;      /* refinement cycles (FG_MIXED), else 1 */
+    double relres;       /* final ||b - A x|| / ||b|| as tracked by the solver */
+    int status;          /* same value as returned */
+} fg_pcg_info;
+
+/* Statistics of a partitioned solve or a step. */
+typedef struct {
+    int64_t newton_iters, outer_iters, inner_k_iters, inner_a22_iters;
+    double outer_relres;  /* last Prevost ||r||/||r0|| */
+    double res_m, res_f;  /* scaled Newton residual norms at exit (fg_step) */
+    int status;
+} fg_solve_info;
+
+/* Thread-local message of the last failing call ("" if none). */
+const char *fg_last_error(void);
+
+/* Create / destroy a context bound to HIP device `device`. */
+fg_status fg_ctx_create(fg_ctx **ctx, int device);
+fg_status fg_ctx_destroy(fg_ctx *ctx);
+
+/* Plan a mesh: builds the node graph of the tetrahedra and interface elements,
+ * a locality-preserving row permutation, the sliced block-ELL storage of 3x3
+ * blocks (K) and scalars (A22, C) on that graph, a colouring of the tetrahedra
+ * (no two tetrahedra of a colour share a node) and the interface adjacency of
+ * fault nodes; uploads everything to the device.  Host work, once per mesh.
+ * Errors: FG_ERR_ARG for out-of-range node ids or degenerate interface
+ * triangles, FG_ERR_OOM. */
+fg_status fg_system_create(fg_ctx *ctx, const fg_mesh *mesh, fg_system **sys);
+fg_status fg_system_destroy(fg_system *sys);
+
+/* Assemble (Sec. 3.2): K_bulk = sum_e V B^T D(E_e, nu) B (eq. discrete_balance),
+ * the storage S = (1/M) int N N plus fracture storage (w0/M_F) int <r><p>,
+ * the conductivity C = (k_e/mu) int grad N . grad N plus fracture longitudinal
+ * (w0 k_par/mu) int grad<r>.grad<p> and transverse (k_perp/(mu w0)) int [[r]][[p]]
+ * (eq. discrete_mass, discrete_mass_fracture), A22 = S + dt C, Dirichlet
+ * elimination, and the point-Jacobi diagonals.  K starts as K_bulk plus the
+ * stick tangent of the interface.
+ * E [n_tets] Young modulus per tetrahedron, log_k [n_tets] natural log of the
+ * matrix permeability per tetrahedron (device, caller order).
+ * Errors: FG_ERR_ARG (null pointers, non-positive volume). */
+fg_status fg_assemble(fg_ctx *ctx, fg_system *sys, const fg_params *params, const double *E, const double *log_k,
+                      void *stream);
+
+/* Interface update at every quadrature point (Sec. 2.2.1, eq. normal_traction to
+ * eq. corrector): opening delta = sum_a N_a (U_a+ - U_a-) resolved on (n,t1,t2);
+ * normal traction t'_n = k_n max(-(delta_n - t'_n0/k_n), 0); elastic trial
+ * t_tr = k_s (t'_s0/k_s + delta_s - die_n); Coulomb yield F = |t_tr| - f t'_n;
+ * if F > 0 a single-step projection with dlambda = F/k_s along t_tr.
+ *   U      [3N]   displacement since t = 0
+ *   die_n  [nq*2] inelastic slip at the start of the step (t1, t2 components)
+ *   t0     [nq*3] initial effective traction (t'_n0, t'_s0 along t1, t2)
+ * Out:
+ *   trac   [nq*3] (t'_n, t_s1, t_s2);  die [nq*2];  flag [nq] 0 stick, 1 slip, 2 open
+ *   f_coh  [3N]   interface force sum_q w_q N_a (T_q - T_0q) on + lips and its
+ *                 negative on - lips, T = -t'_n n + t_s1 t1 + t_s2 t2; zero on held DOFs
+ * write_tangent != 0 also rewrites the fault rows of K with K_bulk plus the
+ * symmetric interface tangent: k_n n(x)n in contact, plus k_s (t1(x)t1 + t2(x)t2)
+ * in stick or k_s (f t'_n/|t_tr|)(I_t - tau(x)tau) in slip; zero when open. */
+fg_status fg_cohesive_update(fg_ctx *ctx, fg_system *sys, const double *U, const double *die_n, const double *t0,
+                             double *trac, double *die, uint8_t *flag, double *f_coh, int write_tangent,
+                             void *stream);
+
+/* Point-Jacobi preconditioned CG (Hestenes-Stiefel, Sec. 3.3.2) on `which`
+ * (FG_K or FG_A22) from x0 = 0.  b, x: nrhs column vectors, each of length 3N
+ * (FG_K) or N (FG_A22), stored one after the other.  precision applies to FG_K.
+ * Returns FG_OK, FG_NOT_CONVERGED (x holds the last iterate),
+ * FG_ERR_BREAKDOWN, FG_ERR_NAN.  info (host) receives the worst column. */
+fg_status fg_pcg_solve(fg_ctx *ctx, fg_system *sys, int which, int nrhs, const double *b, double *x,
+                       const fg_pcg_opts *opts, fg_pcg_info *info_h, void *stream);
+
+/* One partitioned solve of the Newton system (eq. linear_system,
+ * eq. prevost_system, eq. schur_system):
+ *   [ K      -A_pu ] [du]   [b_u]
+ *   [ A_up    A22  ] [dp] = [b_p]
+ * by CG on the Schur complement A22 + A_up K^-1 A_pu preconditioned with
+ * A22^-1, with matrix-free coupling products A_pu p and A_up u = A_pu^T u
+ * (Appendix A, Appendix B) and inner Jacobi-PCG solves with K and A22.
+ * b_u [3N], b_p [N] in; du [3N], dp [N] out. */
+fg_status fg_flow_solve(fg_ctx *ctx, fg_system *sys, const double *b_u, const double *b_p, double *du, double *dp,
+                        const fg_pcg_opts *inner_k, const fg_pcg_opts *inner_p, double outer_tol,
+                        int64_t outer_max_iter, fg_solve_info *info_h, void *stream);
+
+/* One implicit step (Sec. 3.3, eq. nonlinear_system): Newton on (U, P) from the
+ * state at t_n, each iterate with an interface update from die_n and a
+ * partitioned solve; residuals in total form
+ *   R_m = K_bulk U + f_coh(U) - A_pu P - F_u
+ *   R_f = A_up (U - U_n) + A22 (P - P_n) + dt (C P_n - f_p).
+ * Stops when ||R_m|| <= tol s_m and ||R_f|| <= tol s_f, with
+ * s_m = max(||R_m^0||, ||A_pu P||, ||F_u||) and s_f = max(||R_f^0||, dt ||f_p||).
+ * In/out: U [3N], P [N], die [nq*2] (start-of-step inelastic slip in, final out).
+ * Out: trac [nq*3], flag [nq].  In: t0 [nq*3], F_u [3N] total external force
+ * change at t_n+1, f_p [N] volumetric sources. */
+fg_status fg_step(fg_ctx *ctx, fg_system *sys, double *U, double *P, double *die, double *trac, uint8_t *flag,
+                  const double *t0, const double *F_u, const double *f_p, double newton_tol,
+                  int64_t newton_max_iter, const fg_pcg_opts *inner_k, const fg_pcg_opts *inner_p,
+                  double outer_tol, int64_t outer_max_iter, fg_solve_info *info_h, void *stream);
+
+/* Products on the assembled system, caller order: y = A x for which in
+ * {FG_K, FG_A22, FG_KBULK, FG_C}. */
+fg_status fg_spmv(fg_ctx *ctx, fg_system *sys, int which, const double *x, double *y, void *stream);
+
+/* Coupling products (Appendix A eq. Apdp / Adpd, Appendix B eq. afdpd and its
+ * transpose): transpose == 0: y[3N] = A_pu x[N]; transpose != 0: y[N] = A_up x[3N],
+ * masked on held DOFs on both sides. */
+fg_status fg_coupling(fg_ctx *ctx, fg_system *sys, int transpose, const double *x, double *y, void *stream);
+
+/* Residuals R_m [3N], R_f [N] of fg_step's definition at (U, P) given the state
+ * at t_n (U_n, P_n), f_coh from fg_cohesive_update, F_u and f_p. */
+fg_status fg_residual(fg_ctx *ctx, fg_system *sys, const double *U, const double *P, const double *U_n,
+                      const double *P_n, const double *f_coh, const double *F_u, const double *f_p, double *R_m,
+                      double *R_f, void *stream);
+
+/* Number of stored (nonzero-pattern) node pairs of the graph, and the
+ * padded block count of the sliced storage. */
+fg_status fg_system_sizes(const fg_system *sys, int64_t *n_pairs_h, int64_t *n_padded_blocks_h,
+                          int64_t *n_slices_h);
+
+/* Export an assembled operator as node-pair blocks in caller order (host
+ * arrays of n_pairs entries): rows_h, cols_h node ids; vals_h 9 (K, KBULK,
+ * row-major 3x3) or 1 (A22, C) values per pair.  Synchronises the stream. */
+fg_status fg_export(fg_ctx *ctx, fg_system *sys, int which, int32_t *rows_h, int32_t *cols_h, double *vals_h,
+                    void *stream);
+
+/* Live timing of the CG product kernel (the hot loop's dominant kernel).
+ * enable != 0: every CG iteration records a HIP event on the solve's stream
+ * before and after its SpMV launch; durations are summed per operator slot:
+ * 0 = K in FP64, 1 = K in FP32, 2 = A22.  fg_profile_read returns the number of
+ * timed launches and their total milliseconds for `slot`, and clears the slot
+ * when reset != 0. */
+fg_status fg_profile(fg_system *sys, int enable);
+fg_status fg_profile_read(fg_system *sys, int slot, int64_t *launches_h, double *milliseconds_h, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FG_H */

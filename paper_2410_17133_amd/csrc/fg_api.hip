@@ -1,0 +1,779 @@
+// C-ABI of libfg: object lifetime, drivers of the partitioned solve and of the
+// Newton step.  The drivers run on the host and keep every vector on the
+// device; only scalars (dot products, CG status) come back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "fg_kernels.h"
+
+namespace fg {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+}  // namespace fg
+
+using namespace fg;
+
+namespace {
+
+struct Guard {
+    explicit Guard(int dev) { hipSetDevice(dev); }
+};
+
+template <class T>
+fg_status dalloc(T **p, int64_t n)
+{
+    *p = nullptr;
+    if (n <= 0) n = 1;
+    if (hipMalloc((void **)p, sizeof(T) * (size_t)n) != hipSuccess) {
+        hipGetLastError();
+        set_error("device allocation of " + std::to_string(sizeof(T) * (size_t)n) + " bytes failed");
+        return FG_ERR_OOM;
+    }
+    return FG_OK;
+}
+
+template <class T>
+fg_status upload(T **p, const std::vector<T> &v)
+{
+    fg_status e = dalloc(p, (int64_t)v.size());
+    if (e) return e;
+    if (!v.empty() && hipMemcpy(*p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        set_error("host to device copy failed");
+        return FG_ERR_HIP;
+    }
+    return FG_OK;
+}
+
+void dfree(void *p)
+{
+    if (p) hipFree(p);
+}
+
+#define TRY(x)                       \
+    do {                             \
+        fg_status _e = (x);          \
+        if (_e < 0) return _e;       \
+    } while (0)
+
+hipStream_t S_(void *s) { return (hipStream_t)s; }
+
+double vnorm(fg_system *S, int64_t n, const double *a, hipStream_t st)
+{
+    const double *A[1] = {a};
+    double r;
+    vdots(S, n, 1, A, A, &r, st);
+    return std::sqrt(r);
+}
+
+double vdot1(fg_system *S, int64_t n, const double *a, const double *b, hipStream_t st)
+{
+    const double *A[1] = {a}, *B[1] = {b};
+    double r;
+    vdots(S, n, 1, A, B, &r, st);
+    return r;
+}
+
+fg_pcg_opts defaults(const fg_pcg_opts *o, double tol)
+{
+    fg_pcg_opts d{};
+    d.tol = tol;
+    d.max_iter = 1000000;
+    d.precision = FG_F64;
+    d.check_every = 32;
+    d.inner_tol = 1e-4;
+    if (o) {
+        d = *o;
+        if (d.check_every <= 0) d.check_every = 32;
+        if (d.inner_tol <= 0) d.inner_tol = 1e-4;
+        if (d.max_iter <= 0) d.max_iter = 1000000;
+    }
+    return d;
+}
+
+// K solve on internal vectors: rhs (3 Npad) -> out (3 Npad).
+fg_status k_solve(fg_system *S, const double *rhs, double *out, const fg_pcg_opts &o, fg_pcg_info *info, hipStream_t st)
+{
+    const int64_t n = 3 * S->Npad;
+    if (o.precision == FG_F64 || o.precision == FG_F32) {
+        int64_t it = 0;
+        double rr = 0;
+        fg_status s;
+        if (o.precision == FG_F64) {
+            hipMemcpyAsync(S->wr, rhs, n * sizeof(double), hipMemcpyDeviceToDevice, st);
+            s = cg_run(S, FG_K, FG_F64, o.tol, o.max_iter, o.check_every, &it, &rr, st);
+            hipMemcpyAsync(out, S->wx, n * sizeof(double), hipMemcpyDeviceToDevice, st);
+        } else {
+            to_f32(n, 1.0, rhs, S->fr, st);
+            s = cg_run(S, FG_K, FG_F32, o.tol, o.max_iter, o.check_every, &it, &rr, st);
+            vfill(out, 0.0, n, st);
+            add_f32(n, 1.0, S->fx, out, st);
+        }
+        if (info) {
+            info->iters = it;
+            info->cycles = 1;
+            info->relres = rr;
+            info->status = s;
+        }
+        return s;
+    }
+    // Mixed precision: FP32 inner CG on the correction equation, FP64 true
+    // residual and accumulation (iterative refinement).
+    if (!S->k32_valid) refresh_k32(S, st);
+    double *x = S->v3, *r = S->v4;
+    const double bn = vnorm(S, n, rhs, st);
+    vfill(x, 0.0, n, st);
+    hipMemcpyAsync(r, rhs, n * sizeof(double), hipMemcpyDeviceToDevice, st);
+    int64_t total = 0, cycles = 0;
+    double rel = bn > 0 ? 1.0 : 0.0;
+    fg_status s = FG_OK;
+    while (bn > 0) {
+        const double rn = vnorm(S, n, r, st);
+        rel = rn / bn;
+        if (!std::isfinite(rel)) {
+            s = FG_ERR_NAN;
+            set_error("fg_pcg_solve: NaN in the mixed-precision residual");
+            break;
+        }
+        if (rel <= o.tol) {
+            s = FG_OK;
+            break;
+        }
+        if (total >= o.max_iter || cycles >= 200) {
+            s = FG_NOT_CONVERGED;
+            break;
+        }
+        to_f32(n, 1.0 / rn, r, S->fr, st);
+        int64_t it = 0;
+        double rr = 0;
+        fg_status si = cg_run(S, FG_K, FG_F32, std::max(o.inner_tol, o.tol * bn / rn), o.max_iter - total,
+                              o.check_every, &it, &rr, st);
+        total += it;
+        cycles++;
+        if (si < 0) {
+            s = si;
+            break;
+        }
+        add_f32(n, rn, S->fx, x, st);
+        spmv(S, FG_K, x, S->wq, st);
+        hipMemcpyAsync(r, rhs, n * sizeof(double), hipMemcpyDeviceToDevice, st);
+        vaxpby(n, -1.0, S->wq, 1.0, r, st);
+    }
+    hipMemcpyAsync(out, x, n * sizeof(double), hipMemcpyDeviceToDevice, st);
+    if (info) {
+        info->iters = total;
+        info->cycles = cycles;
+        info->relres = rel;
+        info->status = s;
+    }
+    return s;
+}
+
+fg_status a_solve(fg_system *S, const double *rhs, double *out, const fg_pcg_opts &o, int64_t *iters, hipStream_t st)
+{
+    const int64_t n = S->Npad;
+    hipMemcpyAsync(S->wr, rhs, n * sizeof(double), hipMemcpyDeviceToDevice, st);
+    int64_t it = 0;
+    double rr = 0;
+    fg_status s = cg_run(S, FG_A22, FG_F64, o.tol, o.max_iter, o.check_every, &it, &rr, st);
+    hipMemcpyAsync(out, S->wx, n * sizeof(double), hipMemcpyDeviceToDevice, st);
+    if (iters) *iters += it;
+    return s;
+}
+
+// Partitioned CG (Sec. 3.3.2) on internal vectors.  b1, x1: 3 Npad; b2, x2: Npad.
+fg_status prevost(fg_system *S, const double *b1, const double *b2, double *x1, double *x2, const fg_pcg_opts &ok,
+                  const fg_pcg_opts &op, double tol, int64_t maxit, fg_solve_info *info, hipStream_t st)
+{
+    const int64_t n1 = 3 * S->Npad, n2 = S->Npad;
+    double *y = S->v1, *w = S->v2, *t1 = S->pv1;
+    double *r = S->s1, *z = S->s2, *zn = S->s3, *d = S->s4, *Sd = S->s5, *t2 = S->s6;
+    fg_pcg_info ki{};
+    fg_status s = k_solve(S, b1, y, ok, &ki, st);  // y0 = K^-1 b1
+    info->inner_k_iters += ki.iters;
+    if (s < 0) return s;
+    apply_Aup(S, y, t2, st);
+    hipMemcpyAsync(r, b2, n2 * sizeof(double), hipMemcpyDeviceToDevice, st);
+    vaxpby(n2, -1.0, t2, 1.0, r, st);
+    vfill(x2, 0.0, n2, st);
+    const double r0 = vnorm(S, n2, r, st);
+    double rel = 0;
+    fg_status st_out = FG_OK;
+    if (r0 > 0) {
+        s = a_solve(S, r, z, op, &info->inner_a22_iters, st);
+        if (s < 0) return s;
+        hipMemcpyAsync(d, z, n2 * sizeof(double), hipMemcpyDeviceToDevice, st);
+        double rz = vdot1(S, n2, r, z, st);
+        int64_t outer = 0;
+        for (;;) {
+            apply_Apu(S, d, t1, st);
+            s = k_solve(S, t1, w, ok, &ki, st);  // w = K^-1 A_pu d
+            info->inner_k_iters += ki.iters;
+            if (s < 0) return s;
+            apply_Aup(S, w, t2, st);
+            spmv(S, FG_A22, d, Sd, st);
+            vaxpby(n2, 1.0, t2, 1.0, Sd, st);
+            const double dSd = vdot1(S, n2, d, Sd, st);
+            if (!std::isfinite(dSd)) {
+                set_error("fg_flow_solve: NaN in the Schur-complement product");
+                return FG_ERR_NAN;
+            }
+            if (!(dSd > 0)) {
+                set_error("fg_flow_solve: Schur complement not positive (d.S d <= 0)");
+                return FG_ERR_BREAKDOWN;
+            }
+            const double al = rz / dSd;
+            vaxpby(n2, al, d, 1.0, x2, st);
+            vaxpby(n2, -al, Sd, 1.0, r, st);
+            vaxpby(n1, al, w, 1.0, y, st);
+            outer++;
+            rel = vnorm(S, n2, r, st) / r0;
+            if (rel <= tol) break;
+            if (outer >= maxit) {
+                st_out = FG_NOT_CONVERGED;
+                break;
+            }
+            s = a_solve(S, r, zn, op, &info->inner_a22_iters, st);
+            if (s < 0) return s;
+            const double *A[2] = {r, r}, *B[2] = {zn, z};
+            double dd[2];
+            vdots(S, n2, 2, A, B, dd, st);
+            const double be = (dd[0] - dd[1]) / rz;  // flexible (Polak-Ribiere) beta
+            vaxpby(n2, 1.0, zn, be, d, st);
+            hipMemcpyAsync(z, zn, n2 * sizeof(double), hipMemcpyDeviceToDevice, st);
+            rz = dd[0];
+        }
+        info->outer_iters += outer;
+    }
+    info->outer_relres = rel;
+    hipMemcpyAsync(x1, y, n1 * sizeof(double), hipMemcpyDeviceToDevice, st);
+    return st_out;
+}
+
+// Residuals of the Newton system (internal order).
+void residual_int(fg_system *S, const double *U, const double *P, const double *Un, const double *Pn,
+                  const double *fcoh, const double *Fu, const double *fp, double *Rm, double *Rf, hipStream_t st)
+{
+    const int64_t n1 = 3 * S->Npad, n2 = S->Npad;
+    double *t1 = S->pv1, *du = S->pv2, *t2 = S->s7, *dp = S->s8;
+    spmv(S, FG_KBULK, U, Rm, st);
+    apply_Apu(S, P, t1, st);
+    vaxpby(n1, 1.0, fcoh, 1.0, Rm, st);
+    vaxpby(n1, -1.0, t1, 1.0, Rm, st);
+    vaxpby(n1, -1.0, Fu, 1.0, Rm, st);
+    vmask(n1, S->dir_u, Rm, st);
+    hipMemcpyAsync(du, U, n1 * sizeof(double), hipMemcpyDeviceToDevice, st);
+    vaxpby(n1, -1.0, Un, 1.0, du, st);
+    hipMemcpyAsync(dp, P, n2 * sizeof(double), hipMemcpyDeviceToDevice, st);
+    vaxpby(n2, -1.0, Pn, 1.0, dp, st);
+    apply_Aup(S, du, Rf, st);
+    spmv(S, FG_A22, dp, t2, st);
+    vaxpby(n2, 1.0, t2, 1.0, Rf, st);
+    spmv(S, FG_C, Pn, t2, st);
+    vaxpby(n2, S->prm.dt, t2, 1.0, Rf, st);
+    vaxpby(n2, -S->prm.dt, fp, 1.0, Rf, st);
+    vmask(n2, S->dir_p, Rf, st);
+}
+
+bool ready(fg_system *S)
+{
+    if (!S || !S->assembled) {
+        set_error("call fg_assemble first");
+        return false;
+    }
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fg_last_error(void) { return fg::g_err.c_str(); }
+
+fg_status fg_ctx_create(fg_ctx **ctx, int device)
+{
+    if (!ctx) {
+        set_error("fg_ctx_create: null output");
+        return FG_ERR_ARG;
+    }
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+        hipGetLastError();
+        set_error("fg_ctx_create: no such HIP device");
+        return FG_ERR_ARG;
+    }
+    Guard g(device);
+    fg_ctx *c = new fg_ctx;
+    c->device = device;
+    hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device);
+    *ctx = c;
+    return FG_OK;
+}
+
+fg_status fg_ctx_destroy(fg_ctx *ctx)
+{
+    delete ctx;
+    return FG_OK;
+}
+
+fg_status fg_system_destroy(fg_system *S)
+{
+    if (!S) return FG_OK;
+    Guard g(S->ctx->device);
+    hipDeviceSynchronize();
+    void *ptrs[] = {S->slice_ptr, S->col, S->rowlen, S->diag_slot, S->perm, S->xyz, S->tets, S->tet_orig, S->coh,
+                    S->frows, S->fadj_ptr, S->fadj, S->dir_u, S->dir_p, S->tri_geo, S->K, S->K32, S->Kfb, S->A22,
+                    S->Cm, S->dinvK, S->dinvK32, S->dinvA, S->qpD, S->qpT, S->wx, S->wr, S->wp, S->wq, S->fx,
+                    S->fr, S->fp, S->fq, S->v1, S->v2, S->v3, S->v4, S->pv1, S->pv2, S->ui, S->ui0, S->fi, S->rm,
+                    S->du, S->fc, S->s1, S->s2, S->s3, S->s4, S->s5, S->s6, S->s7, S->s8, S->pi, S->pi0, S->qi,
+                    S->rf, S->dpv, S->die0, S->partials, S->sc, S->red, S->red_counter};
+    for (void *p : ptrs) dfree(p);
+    for (hipEvent_t ev : S->prof_ev) hipEventDestroy(ev);
+    if (S->sc_host) hipHostFree(S->sc_host);
+    if (S->red_host) hipHostFree(S->red_host);
+    delete S;
+    return FG_OK;
+}
+
+fg_status fg_system_create(fg_ctx *ctx, const fg_mesh *mesh, fg_system **out)
+{
+    if (!ctx || !mesh || !out) {
+        set_error("fg_system_create: null argument");
+        return FG_ERR_ARG;
+    }
+    Guard g(ctx->device);
+    fg_system *S = new fg_system;
+    S->ctx = ctx;
+    std::string err;
+    fg_status e = build_plan(*mesh, S->plan, err);
+    if (e) {
+        set_error(err);
+        delete S;
+        return e;
+    }
+    const Plan &P = S->plan;
+    S->N = P.N;
+    S->Npad = P.Npad;
+    S->nslices = P.nslices;
+    S->nblk = P.nblk_pad;
+    S->ne = P.ne;
+    S->nf = P.nf;
+    S->nq = 3 * P.nf;
+    S->nfr = (int64_t)P.frows.size();
+    S->ncolours = (int)P.colour_ptr.size() - 1;
+    int fw = 0;
+    for (int32_t r : P.frows) fw = std::max(fw, (int)P.rowlen[r]);
+    S->fault_w = fw;
+    const int64_t n1 = 3 * S->Npad, n2 = S->Npad;
+#define CK(x)                       \
+    do {                            \
+        fg_status _e = (x);         \
+        if (_e) {                   \
+            fg_system_destroy(S);   \
+            return _e;              \
+        }                           \
+    } while (0)
+    CK(upload(&S->slice_ptr, P.slice_ptr));
+    CK(upload(&S->col, P.col));
+    CK(upload(&S->rowlen, P.rowlen));
+    CK(upload(&S->diag_slot, P.diag_slot));
+    CK(upload(&S->perm, P.perm));
+    std::vector<double> xyz(3 * S->Npad, 0.0);
+    for (int64_t r = 0; r < S->N; ++r)
+        for (int c = 0; c < 3; ++c) xyz[3 * r + c] = mesh->xyz_h[3 * (int64_t)P.perm[r] + c];
+    CK(upload(&S->xyz, xyz));
+    CK(upload(&S->tets, P.tets));
+    CK(upload(&S->tet_orig, P.tet_orig));
+    CK(upload(&S->coh, P.coh));
+    CK(upload(&S->frows, P.frows));
+    CK(upload(&S->fadj_ptr, P.fadj_ptr));
+    CK(upload(&S->fadj, P.fadj));
+    CK(upload(&S->dir_u, P.dir_u));
+    CK(upload(&S->dir_p, P.dir_p));
+    CK(dalloc(&S->tri_geo, 10 * S->nf));
+    CK(dalloc(&S->K, 9 * S->nblk));
+    CK(dalloc(&S->K32, 9 * S->nblk));
+    CK(dalloc(&S->Kfb, 9 * S->nfr * std::max(fw, 1)));
+    CK(dalloc(&S->A22, S->nblk));
+    CK(dalloc(&S->Cm, S->nblk));
+    CK(dalloc(&S->dinvK, n1));
+    CK(dalloc(&S->dinvK32, n1));
+    CK(dalloc(&S->dinvA, n2));
+    CK(dalloc(&S->qpD, 6 * S->nq));
+    CK(dalloc(&S->qpT, 3 * S->nq));
+    double **d3[] = {&S->wx, &S->wr, &S->wp, &S->wq, &S->v1, &S->v2, &S->v3, &S->v4, &S->pv1, &S->pv2,
+                     &S->ui, &S->ui0, &S->fi, &S->rm, &S->du, &S->fc};
+    for (double **p : d3) CK(dalloc(p, n1));
+    float **f3[] = {&S->fx, &S->fr, &S->fp, &S->fq};
+    for (float **p : f3) CK(dalloc(p, n1));
+    double **d1[] = {&S->s1, &S->s2, &S->s3, &S->s4, &S->s5, &S->s6, &S->s7, &S->s8,
+                     &S->pi, &S->pi0, &S->qi, &S->rf, &S->dpv};
+    for (double **p : d1) CK(dalloc(p, n2));
+    CK(dalloc(&S->die0, 2 * S->nq));
+    S->npartials = 1 << 17;
+    CK(dalloc(&S->partials, 4 * S->npartials));
+    CK(dalloc(&S->sc, 1));
+    CK(dalloc(&S->red, 8));
+    CK(dalloc(&S->red_counter, 4));
+    hipMemset(S->red_counter, 0, 4 * sizeof(uint32_t));
+    hipMemset(S->sc, 0, sizeof(CgScalars));
+    if (hipHostMalloc((void **)&S->sc_host, sizeof(CgScalars)) != hipSuccess ||
+        hipHostMalloc((void **)&S->red_host, 8 * sizeof(double)) != hipSuccess) {
+        set_error("pinned host allocation failed");
+        fg_system_destroy(S);
+        return FG_ERR_OOM;
+    }
+#undef CK
+    if ((S->nslices + 3) / 4 + 8 > S->npartials) {
+        set_error("fg_system_create: mesh too large for the reduction workspace");
+        fg_system_destroy(S);
+        return FG_ERR_ARG;
+    }
+    *out = S;
+    return check_hip("fg_system_create");
+}
+
+fg_status fg_system_sizes(const fg_system *S, int64_t *n_pairs, int64_t *n_blk, int64_t *n_slices)
+{
+    if (!S) return FG_ERR_ARG;
+    if (n_pairs) *n_pairs = S->plan.npairs;
+    if (n_blk) *n_blk = S->nblk;
+    if (n_slices) *n_slices = S->nslices;
+    return FG_OK;
+}
+
+fg_status fg_assemble(fg_ctx *ctx, fg_system *S, const fg_params *prm, const double *E, const double *log_k, void *stream)
+{
+    if (!ctx || !S || !prm || !E || !log_k) {
+        set_error("fg_assemble: null argument");
+        return FG_ERR_ARG;
+    }
+    Guard g(ctx->device);
+    hipStream_t st = S_(stream);
+    S->prm = *prm;
+    S->k32_valid = false;
+    assemble_all(S, E, log_k, st);
+    TRY(check_hip("fg_assemble"));
+    int bad = 0;
+    hipMemcpyAsync(&bad, (int *)S->red_counter + 1, sizeof(int), hipMemcpyDeviceToHost, st);
+    hipStreamSynchronize(st);
+    if (bad) {
+        set_error(bad == 1 ? "fg_assemble: tetrahedron with non-positive volume" : "fg_assemble: graph slot missing");
+        return FG_ERR_ARG;
+    }
+    S->assembled = true;
+    stick_tangent(S, st);  // K = K_bulk + stick-and-contact interface tangent
+    return check_hip("fg_assemble");
+}
+
+fg_status fg_cohesive_update(fg_ctx *ctx, fg_system *S, const double *U, const double *die_n, const double *t0,
+                             double *trac, double *die, uint8_t *flag, double *f_coh, int write_tangent, void *stream)
+{
+    if (!ctx || !S || !U || (S->nq && (!die_n || !t0 || !trac || !die || !flag)) || !f_coh) {
+        set_error("fg_cohesive_update: null argument");
+        return FG_ERR_ARG;
+    }
+    if (!ready(S)) return FG_ERR_STATE;
+    Guard g(ctx->device);
+    hipStream_t st = S_(stream);
+    perm_in(S, 3, U, S->ui, st);
+    cohesive_qp(S, S->ui, die_n, t0, trac, die, flag, st);
+    cohesive_rows(S, S->fc, write_tangent, st);
+    perm_out(S, 3, S->fc, f_coh, st);
+    return check_hip("fg_cohesive_update");
+}
+
+fg_status fg_pcg_solve(fg_ctx *ctx, fg_system *S, int which, int nrhs, const double *b, double *x,
+                       const fg_pcg_opts *opts, fg_pcg_info *info, void *stream)
+{
+    if (!ctx || !S || !b || !x || nrhs < 1 || (which != FG_K && which != FG_A22)) {
+        set_error("fg_pcg_solve: bad argument");
+        return FG_ERR_ARG;
+    }
+    if (!ready(S)) return FG_ERR_STATE;
+    Guard g(ctx->device);
+    hipStream_t st = S_(stream);
+    fg_pcg_opts o = defaults(opts, 1e-10);
+    if (opts && !(opts->tol > 0)) {
+        set_error("fg_pcg_solve: tol must be positive");
+        return FG_ERR_ARG;
+    }
+    const int bs = which == FG_K ? 3 : 1;
+    const int64_t nn = bs * S->N;
+    fg_status worst = FG_OK;
+    fg_pcg_info wi{};
+    for (int c = 0; c < nrhs; ++c) {
+        fg_pcg_info ci{};
+        fg_status s;
+        if (which == FG_K) {
+            perm_in(S, 3, b + c * nn, S->pv1, st);
+            s = k_solve(S, S->pv1, S->pv2, o, &ci, st);
+            perm_out(S, 3, S->pv2, x + c * nn, st);
+        } else {
+            perm_in(S, 1, b + c * nn, S->s7, st);
+            int64_t it = 0;
+            hipMemcpyAsync(S->wr, S->s7, S->Npad * sizeof(double), hipMemcpyDeviceToDevice, st);
+            double rr = 0;
+            s = cg_run(S, FG_A22, FG_F64, o.tol, o.max_iter, o.check_every, &it, &rr, st);
+            perm_out(S, 1, S->wx, x + c * nn, st);
+            ci.iters = it;
+            ci.cycles = 1;
+            ci.relres = rr;
+            ci.status = s;
+        }
+        if (s < 0) {
+            if (info) *info = ci;
+            return s;
+        }
+        if (s > worst || ci.relres > wi.relres || c == 0) wi = ci;
+        if (s > worst) worst = s;
+    }
+    hipStreamSynchronize(st);
+    if (info) {
+        *info = wi;
+        info->status = worst;
+    }
+    fg_status e = check_hip("fg_pcg_solve");
+    return e ? e : worst;
+}
+
+fg_status fg_flow_solve(fg_ctx *ctx, fg_system *S, const double *b_u, const double *b_p, double *du, double *dp,
+                        const fg_pcg_opts *inner_k, const fg_pcg_opts *inner_p, double outer_tol,
+                        int64_t outer_max_iter, fg_solve_info *info, void *stream)
+{
+    if (!ctx || !S || !b_u || !b_p || !du || !dp || !(outer_tol > 0)) {
+        set_error("fg_flow_solve: bad argument");
+        return FG_ERR_ARG;
+    }
+    if (!ready(S)) return FG_ERR_STATE;
+    Guard g(ctx->device);
+    hipStream_t st = S_(stream);
+    fg_pcg_opts ok = defaults(inner_k, 1e-12), op = defaults(inner_p, 1e-12);
+    fg_solve_info si{};
+    perm_in(S, 3, b_u, S->rm, st);
+    perm_in(S, 1, b_p, S->rf, st);
+    fg_status s = prevost(S, S->rm, S->rf, S->du, S->dpv, ok, op, outer_tol, outer_max_iter > 0 ? outer_max_iter : 1000,
+                          &si, st);
+    perm_out(S, 3, S->du, du, st);
+    perm_out(S, 1, S->dpv, dp, st);
+    hipStreamSynchronize(st);
+    si.status = s;
+    if (info) *info = si;
+    fg_status e = check_hip("fg_flow_solve");
+    return e ? e : s;
+}
+
+fg_status fg_residual(fg_ctx *ctx, fg_system *S, const double *U, const double *P, const double *U_n,
+                      const double *P_n, const double *f_coh, const double *F_u, const double *f_p, double *R_m,
+                      double *R_f, void *stream)
+{
+    if (!ctx || !S || !U || !P || !U_n || !P_n || !f_coh || !F_u || !f_p || !R_m || !R_f) {
+        set_error("fg_residual: null argument");
+        return FG_ERR_ARG;
+    }
+    if (!ready(S)) return FG_ERR_STATE;
+    Guard g(ctx->device);
+    hipStream_t st = S_(stream);
+    perm_in(S, 3, U, S->ui, st);
+    perm_in(S, 3, U_n, S->ui0, st);
+    perm_in(S, 1, P, S->pi, st);
+    perm_in(S, 1, P_n, S->pi0, st);
+    perm_in(S, 3, f_coh, S->fc, st);
+    perm_in(S, 3, F_u, S->fi, st);
+    perm_in(S, 1, f_p, S->qi, st);
+    residual_int(S, S->ui, S->pi, S->ui0, S->pi0, S->fc, S->fi, S->qi, S->rm, S->rf, st);
+    perm_out(S, 3, S->rm, R_m, st);
+    perm_out(S, 1, S->rf, R_f, st);
+    return check_hip("fg_residual");
+}
+
+fg_status fg_step(fg_ctx *ctx, fg_system *S, double *U, double *P, double *die, double *trac, uint8_t *flag,
+                  const double *t0, const double *F_u, const double *f_p, double newton_tol, int64_t newton_max_iter,
+                  const fg_pcg_opts *inner_k, const fg_pcg_opts *inner_p, double outer_tol, int64_t outer_max_iter,
+                  fg_solve_info *info, void *stream)
+{
+    if (!ctx || !S || !U || !P || !F_u || !f_p || (S->nq && (!die || !trac || !flag || !t0))) {
+        set_error("fg_step: null argument");
+        return FG_ERR_ARG;
+    }
+    if (!ready(S)) return FG_ERR_STATE;
+    Guard g(ctx->device);
+    hipStream_t st = S_(stream);
+    const int64_t n1 = 3 * S->Npad, n2 = S->Npad;
+    fg_pcg_opts ok = defaults(inner_k, 1e-12), op = defaults(inner_p, 1e-12);
+    fg_solve_info si{};
+    perm_in(S, 3, U, S->ui, st);
+    perm_in(S, 1, P, S->pi, st);
+    hipMemcpyAsync(S->ui0, S->ui, n1 * sizeof(double), hipMemcpyDeviceToDevice, st);
+    hipMemcpyAsync(S->pi0, S->pi, n2 * sizeof(double), hipMemcpyDeviceToDevice, st);
+    perm_in(S, 3, F_u, S->fi, st);
+    perm_in(S, 1, f_p, S->qi, st);
+    if (S->nq) hipMemcpyAsync(S->die0, die, 2 * S->nq * sizeof(double), hipMemcpyDeviceToDevice, st);
+    double sm = 0, sf = 0, em = 0, ef = 0;
+    int64_t it = 0;
+    fg_status status = FG_NOT_CONVERGED;
+    for (;;) {
+        cohesive_qp(S, S->ui, S->die0, t0, trac, die, flag, st);
+        cohesive_rows(S, S->fc, 1, st);
+        residual_int(S, S->ui, S->pi, S->ui0, S->pi0, S->fc, S->fi, S->qi, S->rm, S->rf, st);
+        const double rm = vnorm(S, n1, S->rm, st), rf = vnorm(S, n2, S->rf, st);
+        apply_Apu(S, S->pi, S->pv1, st);
+        const double ap = vnorm(S, n1, S->pv1, st);
+        if (it == 0) {
+            sm = std::max(rm, std::max(ap, vnorm(S, n1, S->fi, st)));
+            sf = std::max(rf, S->prm.dt * vnorm(S, n2, S->qi, st));
+        } else {
+            sm = std::max(sm, ap);
+        }
+        em = sm > 0 ? rm / sm : rm;
+        ef = sf > 0 ? rf / sf : rf;
+        if (!std::isfinite(em) || !std::isfinite(ef)) {
+            set_error("fg_step: NaN in the Newton residual");
+            status = FG_ERR_NAN;
+            break;
+        }
+        if (em <= newton_tol && ef <= newton_tol) {
+            status = FG_OK;
+            break;
+        }
+        if (it >= newton_max_iter) {
+            status = FG_NOT_CONVERGED;
+            break;
+        }
+        vaxpby(n1, 0.0, S->rm, -1.0, S->rm, st);
+        vaxpby(n2, 0.0, S->rf, -1.0, S->rf, st);
+        fg_status s = prevost(S, S->rm, S->rf, S->du, S->dpv, ok, op, outer_tol,
+                              outer_max_iter > 0 ? outer_max_iter : 1000, &si, st);
+        if (s < 0) {
+            status = s;
+            break;
+        }
+        vaxpby(n1, 1.0, S->du, 1.0, S->ui, st);
+        vaxpby(n2, 1.0, S->dpv, 1.0, S->pi, st);
+        it++;
+    }
+    perm_out(S, 3, S->ui, U, st);
+    perm_out(S, 1, S->pi, P, st);
+    hipStreamSynchronize(st);
+    si.newton_iters = it;
+    si.res_m = em;
+    si.res_f = ef;
+    si.status = status;
+    if (info) *info = si;
+    fg_status e = check_hip("fg_step");
+    return e ? e : status;
+}
+
+fg_status fg_spmv(fg_ctx *ctx, fg_system *S, int which, const double *x, double *y, void *stream)
+{
+    if (!ctx || !S || !x || !y || which < 0 || which > 3) {
+        set_error("fg_spmv: bad argument");
+        return FG_ERR_ARG;
+    }
+    if (!ready(S)) return FG_ERR_STATE;
+    Guard g(ctx->device);
+    hipStream_t st = S_(stream);
+    const int bs = (which == FG_K || which == FG_KBULK) ? 3 : 1;
+    double *xi = bs == 3 ? S->pv1 : S->s7, *yi = bs == 3 ? S->pv2 : S->s8;
+    perm_in(S, bs, x, xi, st);
+    spmv(S, which, xi, yi, st);
+    perm_out(S, bs, yi, y, st);
+    return check_hip("fg_spmv");
+}
+
+fg_status fg_coupling(fg_ctx *ctx, fg_system *S, int transpose, const double *x, double *y, void *stream)
+{
+    if (!ctx || !S || !x || !y) {
+        set_error("fg_coupling: null argument");
+        return FG_ERR_ARG;
+    }
+    if (!ready(S)) return FG_ERR_STATE;
+    Guard g(ctx->device);
+    hipStream_t st = S_(stream);
+    if (!transpose) {
+        perm_in(S, 1, x, S->s7, st);
+        apply_Apu(S, S->s7, S->pv1, st);
+        perm_out(S, 3, S->pv1, y, st);
+    } else {
+        perm_in(S, 3, x, S->pv1, st);
+        apply_Aup(S, S->pv1, S->s7, st);
+        perm_out(S, 1, S->s7, y, st);
+    }
+    return check_hip("fg_coupling");
+}
+
+fg_status fg_export(fg_ctx *ctx, fg_system *S, int which, int32_t *rows, int32_t *cols, double *vals, void *stream)
+{
+    if (!ctx || !S || !rows || !cols || !vals || which < 0 || which > 3) {
+        set_error("fg_export: bad argument");
+        return FG_ERR_ARG;
+    }
+    if (!ready(S)) return FG_ERR_STATE;
+    Guard g(ctx->device);
+    hipStream_t st = S_(stream);
+    const Plan &P = S->plan;
+    const int bs = (which == FG_K || which == FG_KBULK) ? 9 : 1;
+    std::vector<double> v((size_t)S->nblk * bs);
+    const double *src = which == FG_K || which == FG_KBULK ? S->K : (which == FG_A22 ? S->A22 : S->Cm);
+    hipMemcpyAsync(v.data(), src, v.size() * sizeof(double), hipMemcpyDeviceToHost, st);
+    std::vector<double> kfb;
+    if (which == FG_KBULK && S->nfr) {
+        kfb.resize((size_t)S->nfr * S->fault_w * 9);
+        hipMemcpyAsync(kfb.data(), S->Kfb, kfb.size() * sizeof(double), hipMemcpyDeviceToHost, st);
+    }
+    hipStreamSynchronize(st);
+    TRY(check_hip("fg_export"));
+    std::vector<int32_t> fidx(S->Npad, -1);
+    for (size_t k = 0; k < P.frows.size(); ++k) fidx[P.frows[k]] = (int32_t)k;
+    int64_t m = 0;
+    for (int64_t r = 0; r < S->N; ++r) {
+        const int64_t s = r / SLICE, l = r % SLICE, base = P.slice_ptr[s];
+        for (int j = 0; j < P.rowlen[r]; ++j) {
+            const int64_t c = P.col[base + (int64_t)j * SLICE + l];
+            rows[m] = P.perm[r];
+            cols[m] = P.perm[c];
+            if (bs == 1) {
+                vals[m] = v[base + (int64_t)j * SLICE + l];
+            } else if (which == FG_KBULK && fidx[r] >= 0) {
+                for (int e = 0; e < 9; ++e) vals[9 * m + e] = kfb[((size_t)fidx[r] * S->fault_w + j) * 9 + e];
+            } else {
+                for (int e = 0; e < 9; ++e) vals[9 * m + e] = v[9 * base + (int64_t)(9 * j + e) * SLICE + l];
+            }
+            ++m;
+        }
+    }
+    return FG_OK;
+}
+
+fg_status fg_profile(fg_system *S, int enable)
+{
+    if (!S) {
+        set_error("fg_profile: null system");
+        return FG_ERR_ARG;
+    }
+    S->prof = enable != 0;
+    return FG_OK;
+}
+
+fg_status fg_profile_read(fg_system *S, int slot, int64_t *launches, double *ms, int reset)
+{
+    if (!S || slot < 0 || slot > 2) {
+        set_error("fg_profile_read: bad argument");
+        return FG_ERR_ARG;
+    }
+    if (launches) *launches = S->prof_count[slot];
+    if (ms) *ms = S->prof_ms[slot];
+    if (reset) {
+        S->prof_count[slot] = 0;
+        S->prof_ms[slot] = 0;
+    }
+    return FG_OK;
+}
+
+}  // extern "C"

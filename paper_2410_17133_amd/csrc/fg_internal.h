@@ -1,0 +1,126 @@
+// Internal declarations shared by the libfg sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fg.h"
+
+namespace fg {
+
+// Rows per slice of the sliced block-ELL storage: one wavefront, one row per lane.
+constexpr int SLICE = 64;
+constexpr int WG = 256;  // threads per workgroup in most kernels
+
+// Result of planning a mesh on the host (see fg_system_create).
+struct Plan {
+    int64_t N = 0, Npad = 0, nslices = 0, nblk_pad = 0, npairs = 0;
+    int64_t ne = 0, nf = 0;
+    std::vector<int32_t> perm;       // internal row -> caller node
+    std::vector<int32_t> iperm;      // caller node -> internal row
+    std::vector<int64_t> slice_ptr;  // [nslices+1] first block of each slice
+    std::vector<int32_t> col;        // [nblk_pad] internal column node, padding = own row
+    std::vector<uint8_t> rowlen;     // [Npad]
+    std::vector<int32_t> diag_slot;  // [Npad] slot of the diagonal block, -1 for padding rows
+    std::vector<int32_t> tets;       // [ne*4] internal node ids, grouped by colour
+    std::vector<int32_t> tet_orig;   // [ne] caller index of each grouped tetrahedron
+    std::vector<int64_t> colour_ptr; // [ncolours+1]
+    std::vector<int32_t> coh;        // [nf*6] internal node ids, caller order
+    std::vector<int32_t> frows;      // internal rows of interface nodes, ascending
+    std::vector<int32_t> fadj_ptr;   // [nfr+1]
+    std::vector<int32_t> fadj;       // 6*t + local vertex (0..5) of each incident interface element
+    std::vector<uint8_t> dir_u;      // [3*Npad] internal order, padding rows 0
+    std::vector<uint8_t> dir_p;      // [Npad]
+    std::vector<uint8_t> is_pad;     // unused
+};
+
+// Builds the plan; returns FG_OK or an error with a message in `err`.
+fg_status build_plan(const fg_mesh &m, Plan &P, std::string &err);
+
+// Per-solve scalars of a CG iteration, kept in device memory so that the
+// iteration never returns to the host.
+struct CgScalars {
+    double rho;    // r.z of the current iterate
+    double pq;     // p.Ap
+    double rr;     // r.r
+    double bb;     // b.b
+    double alpha, beta;
+    double tol2;   // tol^2 * b.b
+    double rz_new;
+    int64_t iter, maxit;
+    int32_t done, status;
+    uint32_t counter;  // blocks finished in the current reduction
+    uint32_t pad;
+};
+
+void set_error(const std::string &msg);
+
+}  // namespace fg
+
+// Opaque objects of the C-ABI.
+struct fg_ctx {
+    int device = 0;
+    int n_cu = 0;
+};
+
+struct fg_system {
+    fg_ctx *ctx = nullptr;
+    fg::Plan plan;  // host copy (sizes, colours, permutation)
+    int64_t N = 0, Npad = 0, nslices = 0, nblk = 0, ne = 0, nf = 0, nq = 0, nfr = 0;
+    int ncolours = 0;
+    bool assembled = false;
+    fg_params prm{};
+    // device graph
+    int64_t *slice_ptr = nullptr;
+    int32_t *col = nullptr;
+    uint8_t *rowlen = nullptr;
+    int32_t *diag_slot = nullptr;
+    int32_t *perm = nullptr;  // internal -> caller
+    // device mesh (internal numbering)
+    double *xyz = nullptr;
+    int32_t *tets = nullptr, *tet_orig = nullptr;
+    int32_t *coh = nullptr;
+    int32_t *frows = nullptr, *fadj_ptr = nullptr, *fadj = nullptr;
+    uint8_t *dir_u = nullptr, *dir_p = nullptr;
+    double *tri_geo = nullptr;  // [nf*10]: area, n[3], t1[3], t2[3]
+    // operators
+    double *K = nullptr;        // [nblk*9] tangent stiffness, sliced block-ELL
+    float *K32 = nullptr;       // [nblk*9] FP32 copy (mixed precision)
+    double *Kfb = nullptr;      // [nfr*maxw*9] bulk blocks of interface rows
+    int fault_w = 0;            // slots saved per interface row
+    double *A22 = nullptr;      // [nblk]
+    double *Cm = nullptr;       // [nblk] conductivity
+    double *dinvK = nullptr;    // [3*Npad]
+    float *dinvK32 = nullptr;   // [3*Npad]
+    double *dinvA = nullptr;    // [Npad]
+    bool k32_valid = false;
+    // interface quadrature-point scratch
+    double *qpD = nullptr;      // [nq*6] symmetric global tangent
+    double *qpT = nullptr;      // [nq*3] T - T0
+    // solver workspaces (internal order)
+    double *wx = nullptr, *wr = nullptr, *wp = nullptr, *wq = nullptr;  // [3*Npad]
+    float *fx = nullptr, *fr = nullptr, *fp = nullptr, *fq = nullptr;   // [3*Npad]
+    double *v1 = nullptr, *v2 = nullptr, *v3 = nullptr, *v4 = nullptr;  // [3*Npad] scratch
+    double *pv1 = nullptr, *pv2 = nullptr;                              // [3*Npad] scratch
+    double *ui = nullptr, *ui0 = nullptr, *fi = nullptr, *rm = nullptr, *du = nullptr, *fc = nullptr;  // [3*Npad]
+    double *s1 = nullptr, *s2 = nullptr, *s3 = nullptr, *s4 = nullptr, *s5 = nullptr, *s6 = nullptr;  // [Npad]
+    double *s7 = nullptr, *s8 = nullptr, *pi = nullptr, *pi0 = nullptr, *qi = nullptr, *rf = nullptr, *dpv = nullptr;
+    double *die0 = nullptr;      // [nq*2] start-of-step inelastic slip
+    double *partials = nullptr;  // reduction partials
+    int64_t npartials = 0;
+    fg::CgScalars *sc = nullptr;      // device scalars
+    fg::CgScalars *sc_host = nullptr; // pinned host mirror
+    double *red = nullptr;            // device reduction results [8]
+    double *red_host = nullptr;       // pinned [8]
+    uint32_t *red_counter = nullptr;
+    // live kernel timing (fg_profile)
+    bool prof = false;
+    std::vector<hipEvent_t> prof_ev;  // pairs (start, stop), one per pending launch
+    int prof_pending = 0;
+    int prof_slot = 0;
+    int64_t prof_count[3] = {0, 0, 0};
+    double prof_ms[3] = {0, 0, 0};
+};

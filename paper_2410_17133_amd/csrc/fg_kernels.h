@@ -1,0 +1,54 @@
+// Launchers of the libfg device kernels (implemented in fg_kernels.hip).
+#pragma once
+
+#include "fg_internal.h"
+
+namespace fg {
+
+// caller order <-> internal order
+void perm_in(const fg_system *S, int bs, const double *nat, double *in, hipStream_t st);
+void perm_out(const fg_system *S, int bs, const double *in, double *nat, hipStream_t st);
+void perm_in_u8(const fg_system *S, int bs, const uint8_t *nat, uint8_t *in, hipStream_t st);
+
+// assembly
+void assemble_all(fg_system *S, const double *E, const double *logk, hipStream_t st);
+void refresh_k32(fg_system *S, hipStream_t st);
+void stick_tangent(fg_system *S, hipStream_t st);
+
+// interface
+void cohesive_qp(fg_system *S, const double *U_int, const double *die_n, const double *t0, double *trac,
+                 double *die, uint8_t *flag, hipStream_t st);
+void cohesive_rows(fg_system *S, double *fcoh_int, int write_tangent, hipStream_t st);
+
+// coupling products, internal order, masked on both sides
+void apply_Apu(fg_system *S, const double *p, double *out, hipStream_t st);
+void apply_Aup(fg_system *S, const double *u, double *out, hipStream_t st);
+
+// products: which in {FG_K, FG_A22, FG_KBULK, FG_C}
+void spmv(fg_system *S, int which, const double *x, double *y, hipStream_t st);
+void spmv_k32(fg_system *S, const float *x, float *y, hipStream_t st);
+
+// vector helpers (internal order, n elements)
+void vfill(double *y, double v, int64_t n, hipStream_t st);
+// y = a*x + b*y
+void vaxpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t st);
+// y[i] = mask[i] ? 0 : y[i]
+void vmask(int64_t n, const uint8_t *mask, double *y, hipStream_t st);
+// red[slot+k] = dot(a_k, b_k) for k < nd; synchronous result in host[0..nd)
+void vdots(fg_system *S, int64_t n, int nd, const double *const *a, const double *const *b, double *host,
+           hipStream_t st);
+
+// CG on internal-order vectors.  bs = 3 (K) or 1 (A22).  The right-hand side
+// must already be in S->wr (FP64) or S->fr (FP32); the solution is left in
+// S->wx / S->fx.  Returns the final status and fills iters/relres.
+fg_status cg_run(fg_system *S, int which, int precision, double tol, int64_t maxit, int check_every,
+                 int64_t *iters, double *relres, hipStream_t st);
+
+// float <-> double conversions with a scale: y = (T)(s * x)
+void to_f32(int64_t n, double s, const double *x, float *y, hipStream_t st);
+// y += s * (double)x
+void add_f32(int64_t n, double s, const float *x, double *y, hipStream_t st);
+
+fg_status check_hip(const char *where);
+
+}  // namespace fg

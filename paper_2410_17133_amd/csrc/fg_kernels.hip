@@ -1,0 +1,1106 @@
+// Device kernels of libfg (gfx950).
+//
+// Storage: the stiffness K is a sliced block-ELL matrix of 3x3 blocks.  Rows
+// (nodes, in the planner's internal order) come in slices of 64, one per
+// wavefront, one row per lane.  For slice s with width w (blocks per row) the
+// column of slot j of lane l is col[slice_ptr[s] + 64 j + l] and entry (r,c)
+// of that block is val[9 slice_ptr[s] + 64 (9 j + 3 r + c) + l]: every load
+// of a wavefront reads 64 consecutive values.  Scalar operators (A22, C) use
+// the same slots with one value each.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+
+#include "fg_kernels.h"
+
+namespace fg {
+
+namespace {
+
+constexpr int STICK = 0, SLIP = 1, OPEN = 2;
+
+__device__ __forceinline__ double wave_sum(double x)
+{
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    return x;
+}
+
+// Deterministic grid-wide sum of NV values: per-block partial sums, then the
+// last block to finish adds the partials in a fixed order.  Returns true in
+// every thread of that last block, with the totals in tot.
+template <int NV>
+__device__ bool grid_reduce(const double (&v)[NV], double *partials, int64_t stride, uint32_t *counter,
+                            double (&tot)[NV])
+{
+    __shared__ double sh[NV][WG / 64];
+    __shared__ int last;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int k = 0; k < NV; ++k) {
+        double s = wave_sum(v[k]);
+        if (lane == 0) sh[k][w] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < NV; ++k) {
+            double s = 0;
+            for (int i = 0; i < nw; ++i) s += sh[k][i];
+            partials[k * stride + blockIdx.x] = s;
+        }
+        __threadfence();
+        unsigned prev = atomicAdd(counter, 1u);
+        last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+    const volatile double *vp = partials;
+    for (int k = 0; k < NV; ++k) {
+        double s = 0;
+        for (int64_t i = threadIdx.x; i < gridDim.x; i += blockDim.x) s += vp[k * stride + i];
+        s = wave_sum(s);
+        if (lane == 0) sh[k][w] = s;
+    }
+    __syncthreads();
+    for (int k = 0; k < NV; ++k) {
+        double s = 0;
+        for (int i = 0; i < nw; ++i) s += sh[k][i];
+        tot[k] = s;
+    }
+    if (threadIdx.x == 0) *counter = 0;
+    return true;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; hand each XCD a
+// contiguous range of work so that its L2 sees neighbouring slices.  The grid
+// is a multiple of 8.
+__device__ __forceinline__ int64_t xcd_block()
+{
+    const int64_t per = gridDim.x / 8;
+    return (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+}
+
+inline int64_t grid_xcd(int64_t nblocks) { return ((nblocks + 7) / 8) * 8; }
+
+inline int64_t grid_elems(int64_t n)
+{
+    int64_t g = (n + WG - 1) / WG;
+    return g < 2048 ? (g < 1 ? 1 : g) : 2048;
+}
+
+// ----------------------------------------------------------------- permutation
+__global__ void k_perm_in(int64_t N, int64_t Npad, int bs, const int32_t *__restrict__ perm,
+                          const double *__restrict__ nat, double *__restrict__ in)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < Npad * bs; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = i / bs;
+        int c = (int)(i - r * bs);
+        in[i] = r < N ? nat[(int64_t)perm[r] * bs + c] : 0.0;
+    }
+}
+
+__global__ void k_perm_out(int64_t N, int bs, const int32_t *__restrict__ perm, const double *__restrict__ in,
+                           double *__restrict__ nat)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N * bs; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = i / bs;
+        int c = (int)(i - r * bs);
+        nat[(int64_t)perm[r] * bs + c] = in[i];
+    }
+}
+
+__global__ void k_perm_in_u8(int64_t N, int64_t Npad, int bs, const int32_t *__restrict__ perm,
+                             const uint8_t *__restrict__ nat, uint8_t *__restrict__ in)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < Npad * bs; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = i / bs;
+        int c = (int)(i - r * bs);
+        in[i] = r < N ? nat[(int64_t)perm[r] * bs + c] : 0;
+    }
+}
+
+// ----------------------------------------------------------------- geometry
+struct V3 {
+    double x, y, z;
+};
+__device__ __forceinline__ V3 sub(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ V3 crs(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+__device__ __forceinline__ double dt3(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ V3 scl(V3 a, double s) { return {a.x * s, a.y * s, a.z * s}; }
+__device__ __forceinline__ V3 ld3(const double *p) { return {p[0], p[1], p[2]}; }
+__device__ __forceinline__ double cmp(V3 a, int i) { return i == 0 ? a.x : (i == 1 ? a.y : a.z); }
+
+// Linear tetrahedron: gradients of the barycentric shape functions from the
+// face normals, grad N_1 = (e2 x e3)/det etc., grad N_0 = -sum, V = |det|/6.
+__device__ __forceinline__ double tet_grads(const double *xyz, const int32_t *nd, V3 g[4])
+{
+    V3 x0 = ld3(xyz + 3 * (int64_t)nd[0]);
+    V3 e1 = sub(ld3(xyz + 3 * (int64_t)nd[1]), x0);
+    V3 e2 = sub(ld3(xyz + 3 * (int64_t)nd[2]), x0);
+    V3 e3 = sub(ld3(xyz + 3 * (int64_t)nd[3]), x0);
+    V3 c23 = crs(e2, e3), c31 = crs(e3, e1), c12 = crs(e1, e2);
+    double det = dt3(e1, c23);
+    double inv = 1.0 / det;
+    g[1] = scl(c23, inv);
+    g[2] = scl(c31, inv);
+    g[3] = scl(c12, inv);
+    g[0] = {-(g[1].x + g[2].x + g[3].x), -(g[1].y + g[2].y + g[3].y), -(g[1].z + g[2].z + g[3].z)};
+    return fabs(det) / 6.0;
+}
+
+__device__ __forceinline__ int find_slot(const int32_t *colrow, int len, int32_t c)
+{
+    for (int j = 0; j < len; ++j)
+        if (colrow[(int64_t)j * SLICE] == c) return j;
+    return -1;
+}
+
+// Shape function a of the interface triangle at quadrature point q.
+__device__ __forceinline__ double qpN(int q, int a) { return q == a ? 2.0 / 3.0 : 1.0 / 6.0; }
+
+// ----------------------------------------------------------------- assembly
+// One colour of tetrahedra: element stiffness V [lam g_a g_b^T + G (g_b g_a^T + (g_a.g_b) I)],
+// storage (V/(20 M))(1 + delta_ab) and conductivity (k/mu) V g_a.g_b, added to the
+// rows of the element's own nodes (no two elements of a colour share a node).
+__global__ void k_assemble_tets(int64_t t0, int64_t t1, const int32_t *__restrict__ tets,
+                                const int32_t *__restrict__ orig, const double *__restrict__ xyz,
+                                const double *__restrict__ E, const double *__restrict__ logk, fg_params prm,
+                                const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ col,
+                                const uint8_t *__restrict__ rowlen, double *K, double *A22, double *Cm, int *bad)
+{
+    int64_t t = t0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= t1) return;
+    const int32_t *nd = tets + 4 * t;
+    V3 g[4];
+    double V = tet_grads(xyz, nd, g);
+    if (!(V > 0)) {
+        *bad = 1;
+        return;
+    }
+    const int64_t e = orig[t];
+    const double Ee = E[e], nu = prm.nu;
+    const double lam = Ee * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    const double G = Ee / (2.0 * (1.0 + nu));
+    const double kmu = exp(logk[e]) / prm.mu;
+    const double sm = V / (20.0 * prm.biot_M);
+    for (int a = 0; a < 4; ++a) {
+        const int64_t row = nd[a];
+        const int64_t s = row / SLICE, l = row % SLICE;
+        const int64_t base = slice_ptr[s];
+        const int len = rowlen[row];
+        for (int b = 0; b < 4; ++b) {
+            int j = find_slot(col + base + l, len, nd[b]);
+            if (j < 0) {
+                *bad = 2;
+                return;
+            }
+            const double gg = dt3(g[a], g[b]);
+            double *kb = K + 9 * base + (int64_t)9 * j * SLICE + l;
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) {
+                    double v = lam * cmp(g[a], r) * cmp(g[b], c) + G * (cmp(g[a], c) * cmp(g[b], r) + (r == c ? gg : 0.0));
+                    kb[(int64_t)(3 * r + c) * SLICE] += V * v;
+                }
+            const double cab = kmu * V * gg;
+            const double sab = sm * (a == b ? 2.0 : 1.0);
+            const int64_t k = base + (int64_t)j * SLICE + l;
+            A22[k] += sab + prm.dt * cab;
+            Cm[k] += cab;
+        }
+    }
+}
+
+// Reference geometry of each interface element: area, normal, t1, t2.
+__global__ void k_tri_geo(int64_t nf, const int32_t *__restrict__ coh, const double *__restrict__ xyz, double *geo)
+{
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= nf) return;
+    const int32_t *c = coh + 6 * t;
+    V3 x0 = ld3(xyz + 3 * (int64_t)c[3]);
+    V3 cr = crs(sub(ld3(xyz + 3 * (int64_t)c[4]), x0), sub(ld3(xyz + 3 * (int64_t)c[5]), x0));
+    double twoA = sqrt(dt3(cr, cr));
+    V3 n = scl(cr, 1.0 / twoA);
+    V3 v = {-n.z * n.x, -n.z * n.y, 1.0 - n.z * n.z};  // e_z minus its normal part
+    double vn = sqrt(dt3(v, v));
+    if (vn < 1e-8) {
+        v = {1.0 - n.x * n.x, -n.x * n.y, -n.x * n.z};
+        vn = sqrt(dt3(v, v));
+    }
+    V3 t1 = scl(v, 1.0 / vn);
+    V3 t2 = crs(n, t1);
+    double *o = geo + 10 * t;
+    o[0] = 0.5 * twoA;
+    o[1] = n.x, o[2] = n.y, o[3] = n.z;
+    o[4] = t1.x, o[5] = t1.y, o[6] = t1.z;
+    o[7] = t2.x, o[8] = t2.y, o[9] = t2.z;
+}
+
+// Fracture flow (double-node operators) gathered per interface row and slot:
+// storage (w0/M_F) int <r><p>, longitudinal (w0 k_par/mu) int grad<r>.grad<p>
+// and transverse (k_perp/(mu w0)) int [[r]][[p]] with int N_a N_b = A(1+d_ab)/12.
+__global__ void k_fault_flow(int64_t nfr, int fw, const int32_t *__restrict__ frows, const int32_t *__restrict__ fadj_ptr,
+                             const int32_t *__restrict__ fadj, const int32_t *__restrict__ coh,
+                             const double *__restrict__ geo, const double *__restrict__ xyz, fg_params prm,
+                             const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ col,
+                             const uint8_t *__restrict__ rowlen, double *A22, double *Cm)
+{
+    int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (id >= nfr * fw) return;
+    const int64_t k = id / fw;
+    const int j = (int)(id - k * fw);
+    const int64_t row = frows[k];
+    const int64_t s = row / SLICE, l = row % SLICE, base = slice_ptr[s];
+    if (j >= rowlen[row]) return;
+    const int32_t cj = col[base + (int64_t)j * SLICE + l];
+    const double cs = prm.w0 / prm.M_F, cl = prm.w0 * prm.k_par / prm.mu, ct = prm.k_perp / (prm.mu * prm.w0);
+    double sacc = 0, cacc = 0;
+    for (int m = fadj_ptr[k]; m < fadj_ptr[k + 1]; ++m) {
+        const int64_t t = fadj[m] / 6;
+        const int la = fadj[m] % 6, sa = la / 3, va = la % 3;
+        const int32_t *c = coh + 6 * t;
+        for (int lb = 0; lb < 6; ++lb) {
+            if (c[lb] != cj) continue;
+            const int sb = lb / 3, vb = lb % 3;
+            const double A = geo[10 * t];
+            const V3 n = ld3(geo + 10 * t + 1);
+            // in-plane gradients from the - lip vertices: grad N_a = n x (x_c - x_b) / (2A)
+            V3 X[3] = {ld3(xyz + 3 * (int64_t)c[3]), ld3(xyz + 3 * (int64_t)c[4]), ld3(xyz + 3 * (int64_t)c[5])};
+            V3 ga = scl(crs(n, sub(X[(va + 2) % 3], X[(va + 1) % 3])), 0.5 / A);
+            V3 gb = scl(crs(n, sub(X[(vb + 2) % 3], X[(vb + 1) % 3])), 0.5 / A);
+            const double m3 = A * (va == vb ? 2.0 : 1.0) / 12.0;
+            const double cg = A * dt3(ga, gb);
+            sacc += 0.25 * cs * m3;
+            cacc += 0.25 * cl * cg + (sa == sb ? 1.0 : -1.0) * ct * m3;
+        }
+    }
+    const int64_t kk = base + (int64_t)j * SLICE + l;
+    A22[kk] += sacc + prm.dt * cacc;
+    Cm[kk] += cacc;
+}
+
+// Symmetric elimination of held DOFs (zero row and column, unit diagonal),
+// then point-Jacobi inverse diagonals.
+__global__ void k_dirichlet(int64_t Npad, const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ col,
+                            const uint8_t *__restrict__ rowlen, const uint8_t *__restrict__ dir_u,
+                            const uint8_t *__restrict__ dir_p, double *K, double *A22, double *dinvK, double *dinvA)
+{
+    int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (row >= Npad) return;
+    const int64_t s = row / SLICE, l = row % SLICE, base = slice_ptr[s];
+    const int len = rowlen[row];
+    double dK[3] = {0, 0, 0}, dA = 0;
+    for (int j = 0; j < len; ++j) {
+        const int64_t c = col[base + (int64_t)j * SLICE + l];
+        double *kb = K + 9 * base + (int64_t)9 * j * SLICE + l;
+        for (int r = 0; r < 3; ++r)
+            for (int cc = 0; cc < 3; ++cc) {
+                const bool hr = dir_u[3 * row + r], hc = dir_u[3 * c + cc];
+                if (hr || hc) kb[(int64_t)(3 * r + cc) * SLICE] = (c == row && r == cc) ? 1.0 : 0.0;
+            }
+        double *ab = A22 + base + (int64_t)j * SLICE + l;
+        if (dir_p[row] || dir_p[c]) *ab = (c == row) ? 1.0 : 0.0;
+        if (c == row) {
+            for (int r = 0; r < 3; ++r) dK[r] = kb[(int64_t)(4 * r) * SLICE];
+            dA = *ab;
+        }
+    }
+    for (int r = 0; r < 3; ++r) dinvK[3 * row + r] = len ? 1.0 / dK[r] : 0.0;
+    dinvA[row] = len ? 1.0 / dA : 0.0;
+}
+
+__global__ void k_save_fault_bulk(int64_t nfr, int fw, const int32_t *__restrict__ frows,
+                                  const int64_t *__restrict__ slice_ptr, const uint8_t *__restrict__ rowlen,
+                                  const double *__restrict__ K, double *Kfb)
+{
+    int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (id >= nfr * fw) return;
+    const int64_t k = id / fw;
+    const int j = (int)(id - k * fw);
+    const int64_t row = frows[k];
+    const int64_t s = row / SLICE, l = row % SLICE, base = slice_ptr[s];
+    for (int e = 0; e < 9; ++e)
+        Kfb[id * 9 + e] = j < rowlen[row] ? K[9 * base + (int64_t)(9 * j + e) * SLICE + l] : 0.0;
+}
+
+__global__ void k_to_f32(int64_t n, double s, const double *__restrict__ x, float *__restrict__ y)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (float)(s * x[i]);
+}
+
+__global__ void k_add_f32(int64_t n, double s, const float *__restrict__ x, double *__restrict__ y)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] += s * (double)x[i];
+}
+
+// ----------------------------------------------------------------- interface
+// Elastic predictor / plastic corrector (Sec. 2.2.1) at one quadrature point.
+// Inputs: opening (dn, ds1, ds2) of the displacement since t = 0, inelastic slip
+// die at the start of the step, initial tractions (tn0, ts01, ts02).  Outputs
+// the tractions, new inelastic slip, state and the local symmetric tangent
+// (Dn on n(x)n, S on the tangent plane).
+struct QpOut {
+    double tn, ts1, ts2, die1, die2, Dn, S11, S12, S22;
+    int flag;
+};
+
+__device__ QpOut return_map(double dn, double ds1, double ds2, double die1, double die2, double tn0, double ts01,
+                            double ts02, double kn, double ks, double f)
+{
+    QpOut o;
+    const double gap = dn - tn0 / kn;  // normal opening including the initial penetration
+    o.tn = gap < 0.0 ? -kn * gap : 0.0;
+    const double tr1 = ts01 + ks * (ds1 - die1);
+    const double tr2 = ts02 + ks * (ds2 - die2);
+    const double trn = sqrt(tr1 * tr1 + tr2 * tr2);
+    const double F = trn - f * o.tn;
+    o.Dn = gap <= 0.0 ? kn : 0.0;
+    if (F <= 0.0) {
+        o.ts1 = tr1, o.ts2 = tr2;
+        o.die1 = die1, o.die2 = die2;
+        o.flag = gap > 0.0 ? OPEN : STICK;
+        const double k = o.flag == STICK ? ks : 0.0;
+        o.S11 = k, o.S12 = 0.0, o.S22 = k;
+    } else {
+        const double u1 = tr1 / trn, u2 = tr2 / trn;
+        const double dl = F / ks;
+        o.die1 = die1 + dl * u1, o.die2 = die2 + dl * u2;
+        o.ts1 = f * o.tn * u1, o.ts2 = f * o.tn * u2;
+        o.flag = gap > 0.0 ? OPEN : SLIP;
+        const double k = o.flag == SLIP ? ks * f * o.tn / trn : 0.0;
+        o.S11 = k * (1.0 - u1 * u1), o.S12 = -k * u1 * u2, o.S22 = k * (1.0 - u2 * u2);
+    }
+    return o;
+}
+
+__global__ void k_cohesive_qp(int64_t nq, const int32_t *__restrict__ coh, const double *__restrict__ geo,
+                              const double *__restrict__ U, const double *__restrict__ die_n,
+                              const double *__restrict__ t0, double kn, double ks, double f, double *trac,
+                              double *die, uint8_t *flag, double *qpT, double *qpD)
+{
+    int64_t iq = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (iq >= nq) return;
+    const int64_t t = iq / 3;
+    const int q = (int)(iq - 3 * t);
+    const int32_t *c = coh + 6 * t;
+    const double *gp = geo + 10 * t;
+    const V3 n = ld3(gp + 1), e1 = ld3(gp + 4), e2 = ld3(gp + 7);
+    V3 jmp = {0, 0, 0};
+    for (int a = 0; a < 3; ++a) {
+        const double Na = qpN(q, a);
+        V3 d = sub(ld3(U + 3 * (int64_t)c[a]), ld3(U + 3 * (int64_t)c[3 + a]));
+        jmp = {jmp.x + Na * d.x, jmp.y + Na * d.y, jmp.z + Na * d.z};
+    }
+    const double *tz = t0 + 3 * iq;
+    QpOut o = return_map(dt3(n, jmp), dt3(e1, jmp), dt3(e2, jmp), die_n[2 * iq], die_n[2 * iq + 1], tz[0], tz[1],
+                         tz[2], kn, ks, f);
+    trac[3 * iq] = o.tn, trac[3 * iq + 1] = o.ts1, trac[3 * iq + 2] = o.ts2;
+    die[2 * iq] = o.die1, die[2 * iq + 1] = o.die2;
+    flag[iq] = (uint8_t)o.flag;
+    // force conjugate to the opening, relative to the initial state
+    const double fn = -(o.tn - tz[0]), f1 = o.ts1 - tz[1], f2 = o.ts2 - tz[2];
+    qpT[3 * iq] = fn * n.x + f1 * e1.x + f2 * e2.x;
+    qpT[3 * iq + 1] = fn * n.y + f1 * e1.y + f2 * e2.y;
+    qpT[3 * iq + 2] = fn * n.z + f1 * e1.z + f2 * e2.z;
+    // global tangent Dn n n^T + sum S_ab t_a t_b^T, stored xx yy zz yz xz xy
+    const double nn[3] = {n.x, n.y, n.z}, a1[3] = {e1.x, e1.y, e1.z}, a2[3] = {e2.x, e2.y, e2.z};
+    const int I[6] = {0, 1, 2, 1, 0, 0}, J[6] = {0, 1, 2, 2, 2, 1};
+    for (int m = 0; m < 6; ++m) {
+        const int i = I[m], jj = J[m];
+        qpD[6 * iq + m] = o.Dn * nn[i] * nn[jj] + o.S11 * a1[i] * a1[jj] + o.S22 * a2[i] * a2[jj] +
+                          o.S12 * (a1[i] * a2[jj] + a2[i] * a1[jj]);
+    }
+}
+
+// Stick-and-contact tangent k_n n(x)n + k_s (t1(x)t1 + t2(x)t2) at every point.
+__global__ void k_stick_tangent(int64_t nq, const double *__restrict__ geo, double kn, double ks, double *qpD)
+{
+    int64_t iq = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (iq >= nq) return;
+    const double *gp = geo + 10 * (iq / 3);
+    const int I[6] = {0, 1, 2, 1, 0, 0}, J[6] = {0, 1, 2, 2, 2, 1};
+    for (int m = 0; m < 6; ++m)
+        qpD[6 * iq + m] = kn * gp[1 + I[m]] * gp[1 + J[m]] +
+                          ks * (gp[4 + I[m]] * gp[4 + J[m]] + gp[7 + I[m]] * gp[7 + J[m]]);
+}
+
+__device__ __forceinline__ double symD(const double *d, int r, int c)
+{
+    // xx yy zz yz xz xy
+    if (r == c) return d[r];
+    const int s = r + c;  // 1: xy, 2: xz, 3: yz
+    return s == 3 ? d[3] : (s == 2 ? d[4] : d[5]);
+}
+
+// Interface force per fault row: sum over incident elements and quadrature
+// points of +-w N_a (T - T0).
+__global__ void k_cohesive_force(int64_t nfr, const int32_t *__restrict__ frows, const int32_t *__restrict__ fadj_ptr,
+                                 const int32_t *__restrict__ fadj, const double *__restrict__ geo,
+                                 const double *__restrict__ qpT, const uint8_t *__restrict__ dir_u, double *fcoh)
+{
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= nfr) return;
+    const int64_t row = frows[k];
+    double acc[3] = {0, 0, 0};
+    for (int m = fadj_ptr[k]; m < fadj_ptr[k + 1]; ++m) {
+        const int64_t t = fadj[m] / 6;
+        const int la = fadj[m] % 6, va = la % 3;
+        const double sg = la < 3 ? 1.0 : -1.0;
+        const double w = geo[10 * t] / 3.0;
+        for (int q = 0; q < 3; ++q) {
+            const double c = sg * w * qpN(q, va);
+            for (int r = 0; r < 3; ++r) acc[r] += c * qpT[3 * (3 * t + q) + r];
+        }
+    }
+    for (int r = 0; r < 3; ++r) fcoh[3 * row + r] = dir_u[3 * row + r] ? 0.0 : acc[r];
+}
+
+// Fault rows of K = saved bulk blocks + interface tangent, with the held DOFs
+// eliminated again; one thread per (fault row, slot).
+__global__ void k_cohesive_tangent(int64_t nfr, int fw, const int32_t *__restrict__ frows,
+                                   const int32_t *__restrict__ fadj_ptr, const int32_t *__restrict__ fadj,
+                                   const int32_t *__restrict__ coh, const double *__restrict__ geo,
+                                   const double *__restrict__ qpD, const double *__restrict__ Kfb,
+                                   const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ col,
+                                   const uint8_t *__restrict__ rowlen, const uint8_t *__restrict__ dir_u, double *K,
+                                   float *K32, double *dinvK, float *dinvK32)
+{
+    int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (id >= nfr * fw) return;
+    const int64_t k = id / fw;
+    const int j = (int)(id - k * fw);
+    const int64_t row = frows[k];
+    const int64_t s = row / SLICE, l = row % SLICE, base = slice_ptr[s];
+    if (j >= rowlen[row]) return;
+    const int64_t cj = col[base + (int64_t)j * SLICE + l];
+    double acc[9];
+    for (int e = 0; e < 9; ++e) acc[e] = Kfb[id * 9 + e];
+    for (int m = fadj_ptr[k]; m < fadj_ptr[k + 1]; ++m) {
+        const int64_t t = fadj[m] / 6;
+        const int la = fadj[m] % 6, va = la % 3;
+        const int32_t *c = coh + 6 * t;
+        const double w = geo[10 * t] / 3.0;
+        for (int lb = 0; lb < 6; ++lb) {
+            if (c[lb] != cj) continue;
+            const int vb = lb % 3;
+            const double sg = ((la < 3) == (lb < 3)) ? 1.0 : -1.0;
+            for (int q = 0; q < 3; ++q) {
+                const double cq = sg * w * qpN(q, va) * qpN(q, vb);
+                const double *d = qpD + 6 * (3 * t + q);
+                for (int r = 0; r < 3; ++r)
+                    for (int cc = 0; cc < 3; ++cc) acc[3 * r + cc] += cq * symD(d, r, cc);
+            }
+        }
+    }
+    double *kb = K + 9 * base + (int64_t)9 * j * SLICE + l;
+    for (int r = 0; r < 3; ++r)
+        for (int cc = 0; cc < 3; ++cc) {
+            double v = acc[3 * r + cc];
+            if (dir_u[3 * row + r] || dir_u[3 * cj + cc]) v = (cj == row && r == cc) ? 1.0 : 0.0;
+            kb[(int64_t)(3 * r + cc) * SLICE] = v;
+            if (K32) K32[9 * base + (int64_t)(9 * j + 3 * r + cc) * SLICE + l] = (float)v;
+            if (cj == row && r == cc) {
+                dinvK[3 * row + r] = 1.0 / v;
+                if (dinvK32) dinvK32[3 * row + r] = (float)(1.0 / v);
+            }
+        }
+}
+
+// ----------------------------------------------------------------- coupling
+// A^m_pu p: per tetrahedron alpha (V/4) grad N_a sum_b p_b (eq. Apdp), one colour.
+__global__ void k_apu_tets(int64_t t0, int64_t t1, const int32_t *__restrict__ tets, const double *__restrict__ xyz,
+                           double alpha, const double *__restrict__ p, const uint8_t *__restrict__ dir_p, double *out)
+{
+    int64_t t = t0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= t1) return;
+    const int32_t *nd = tets + 4 * t;
+    V3 g[4];
+    const double V = tet_grads(xyz, nd, g);
+    double sp = 0;
+    for (int b = 0; b < 4; ++b) sp += dir_p[nd[b]] ? 0.0 : p[nd[b]];
+    const double c = alpha * 0.25 * V * sp;
+    for (int a = 0; a < 4; ++a) {
+        double *o = out + 3 * (int64_t)nd[a];
+        o[0] += c * g[a].x;
+        o[1] += c * g[a].y;
+        o[2] += c * g[a].z;
+    }
+}
+
+// A^m_up u: per tetrahedron alpha (V/4) div u added to each vertex (eq. Adpd), one colour.
+__global__ void k_aup_tets(int64_t t0, int64_t t1, const int32_t *__restrict__ tets, const double *__restrict__ xyz,
+                           double alpha, const double *__restrict__ u, const uint8_t *__restrict__ dir_u, double *out)
+{
+    int64_t t = t0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= t1) return;
+    const int32_t *nd = tets + 4 * t;
+    V3 g[4];
+    const double V = tet_grads(xyz, nd, g);
+    double dv = 0;
+    for (int a = 0; a < 4; ++a) {
+        const int64_t o = 3 * (int64_t)nd[a];
+        dv += (dir_u[o] ? 0.0 : u[o]) * g[a].x + (dir_u[o + 1] ? 0.0 : u[o + 1]) * g[a].y +
+              (dir_u[o + 2] ? 0.0 : u[o + 2]) * g[a].z;
+    }
+    const double c = alpha * 0.25 * V * dv;
+    for (int b = 0; b < 4; ++b) out[nd[b]] += c;
+}
+
+// A^f_pu p per fault row: +-(1/2) int N_a N_b (p_b+ + p_b-) n (transpose of eq. afdpd).
+__global__ void k_apu_fault(int64_t nfr, const int32_t *__restrict__ frows, const int32_t *__restrict__ fadj_ptr,
+                            const int32_t *__restrict__ fadj, const int32_t *__restrict__ coh,
+                            const double *__restrict__ geo, const double *__restrict__ p,
+                            const uint8_t *__restrict__ dir_p, double *out)
+{
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= nfr) return;
+    const int64_t row = frows[k];
+    double acc[3] = {0, 0, 0};
+    for (int m = fadj_ptr[k]; m < fadj_ptr[k + 1]; ++m) {
+        const int64_t t = fadj[m] / 6;
+        const int la = fadj[m] % 6, va = la % 3;
+        const int32_t *c = coh + 6 * t;
+        const double A = geo[10 * t];
+        double sp = 0;
+        for (int b = 0; b < 3; ++b) {
+            const double pb = (dir_p[c[b]] ? 0.0 : p[c[b]]) + (dir_p[c[3 + b]] ? 0.0 : p[c[3 + b]]);
+            sp += 0.5 * A * (va == b ? 2.0 : 1.0) / 12.0 * pb;
+        }
+        const double sg = la < 3 ? sp : -sp;
+        for (int r = 0; r < 3; ++r) acc[r] += sg * geo[10 * t + 1 + r];
+    }
+    for (int r = 0; r < 3; ++r) out[3 * row + r] += acc[r];
+}
+
+// A^f_up u per fault row (eq. afdpd): (1/2) int N_b n.(u+ - u-) on both lips.
+__global__ void k_aup_fault(int64_t nfr, const int32_t *__restrict__ frows, const int32_t *__restrict__ fadj_ptr,
+                            const int32_t *__restrict__ fadj, const int32_t *__restrict__ coh,
+                            const double *__restrict__ geo, const double *__restrict__ u,
+                            const uint8_t *__restrict__ dir_u, double *out)
+{
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= nfr) return;
+    const int64_t row = frows[k];
+    double acc = 0;
+    for (int m = fadj_ptr[k]; m < fadj_ptr[k + 1]; ++m) {
+        const int64_t t = fadj[m] / 6;
+        const int vb = (fadj[m] % 6) % 3;
+        const int32_t *c = coh + 6 * t;
+        const double A = geo[10 * t];
+        for (int a = 0; a < 3; ++a) {
+            double jn = 0;
+            for (int r = 0; r < 3; ++r) {
+                const int64_t ip = 3 * (int64_t)c[a] + r, im = 3 * (int64_t)c[3 + a] + r;
+                jn += geo[10 * t + 1 + r] * ((dir_u[ip] ? 0.0 : u[ip]) - (dir_u[im] ? 0.0 : u[im]));
+            }
+            acc += 0.5 * A * (vb == a ? 2.0 : 1.0) / 12.0 * jn;
+        }
+    }
+    out[row] += acc;
+}
+
+// ----------------------------------------------------------------- vectors
+__global__ void k_fill(double *y, double v, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) y[i] = v;
+}
+
+__global__ void k_axpby(int64_t n, double a, const double *__restrict__ x, double b, double *__restrict__ y)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = a * x[i] + b * y[i];
+}
+
+__global__ void k_mask(int64_t n, const uint8_t *__restrict__ m, double *y)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if (m[i]) y[i] = 0.0;
+}
+
+struct DotArgs {
+    const double *a[4];
+    const double *b[4];
+};
+
+template <int ND>
+__global__ void k_dots(int64_t n, DotArgs args, double *partials, int64_t stride, uint32_t *counter, double *res)
+{
+    double v[ND];
+    for (int k = 0; k < ND; ++k) v[k] = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        for (int k = 0; k < ND; ++k) v[k] += args.a[k][i] * args.b[k][i];
+    double tot[ND];
+    if (grid_reduce<ND>(v, partials, stride, counter, tot) && threadIdx.x == 0)
+        for (int k = 0; k < ND; ++k) res[k] = tot[k];
+}
+
+// ----------------------------------------------------------------- SpMV
+template <typename T, typename TV>
+__device__ __forceinline__ void row3(int64_t base, int w, int lane, const int32_t *__restrict__ col,
+                                     const TV *__restrict__ val, const T *__restrict__ x, T &y0, T &y1, T &y2)
+{
+    const int32_t *c = col + base + lane;
+    const TV *v = val + 9 * base + lane;
+    T a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll 3
+    for (int j = 0; j < w; ++j) {
+        const int64_t cj = c[(int64_t)j * SLICE];
+        const T *xp = x + 3 * cj;
+        const T x0 = xp[0], x1 = xp[1], x2 = xp[2];
+        const TV *vb = v + (int64_t)9 * j * SLICE;
+        a0 += (T)vb[0] * x0 + (T)vb[SLICE] * x1 + (T)vb[2 * SLICE] * x2;
+        a1 += (T)vb[3 * SLICE] * x0 + (T)vb[4 * SLICE] * x1 + (T)vb[5 * SLICE] * x2;
+        a2 += (T)vb[6 * SLICE] * x0 + (T)vb[7 * SLICE] * x1 + (T)vb[8 * SLICE] * x2;
+    }
+    y0 = a0, y1 = a1, y2 = a2;
+}
+
+template <typename T, typename TV>
+__device__ __forceinline__ T row1(int64_t base, int w, int lane, const int32_t *__restrict__ col,
+                                  const TV *__restrict__ val, const T *__restrict__ x)
+{
+    const int32_t *c = col + base + lane;
+    const TV *v = val + base + lane;
+    T a = 0;
+#pragma unroll 4
+    for (int j = 0; j < w; ++j) a += (T)v[(int64_t)j * SLICE] * x[c[(int64_t)j * SLICE]];
+    return a;
+}
+
+template <typename T, typename TV>
+__global__ __launch_bounds__(WG) void k_spmv3(int64_t nslices, const int64_t *__restrict__ slice_ptr,
+                                              const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                              const T *__restrict__ x, T *__restrict__ y)
+{
+    const int64_t s = xcd_block() * (WG / SLICE) + (threadIdx.x >> 6);
+    if (s >= nslices) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t base = slice_ptr[s];
+    const int w = (int)((slice_ptr[s + 1] - base) / SLICE);
+    T y0, y1, y2;
+    row3<T, TV>(base, w, lane, col, val, x, y0, y1, y2);
+    const int64_t r = s * SLICE + lane;
+    y[3 * r] = y0, y[3 * r + 1] = y1, y[3 * r + 2] = y2;
+}
+
+template <typename T, typename TV>
+__global__ __launch_bounds__(WG) void k_spmv1(int64_t nslices, const int64_t *__restrict__ slice_ptr,
+                                              const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                              const T *__restrict__ x, T *__restrict__ y)
+{
+    const int64_t s = xcd_block() * (WG / SLICE) + (threadIdx.x >> 6);
+    if (s >= nslices) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t base = slice_ptr[s];
+    const int w = (int)((slice_ptr[s + 1] - base) / SLICE);
+    y[s * SLICE + lane] = row1<T, TV>(base, w, lane, col, val, x);
+}
+
+// Fault rows of K_bulk x from the saved bulk blocks (overwrites y on those rows).
+__global__ void k_spmv_fault_bulk(int64_t nfr, int fw, const int32_t *__restrict__ frows,
+                                  const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ col,
+                                  const uint8_t *__restrict__ rowlen, const double *__restrict__ Kfb,
+                                  const double *__restrict__ x, double *y)
+{
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= nfr) return;
+    const int64_t row = frows[k];
+    const int64_t s = row / SLICE, l = row % SLICE, base = slice_ptr[s];
+    double a[3] = {0, 0, 0};
+    for (int j = 0; j < rowlen[row]; ++j) {
+        const int64_t cj = col[base + (int64_t)j * SLICE + l];
+        const double *b = Kfb + (k * fw + j) * 9;
+        for (int r = 0; r < 3; ++r) a[r] += b[3 * r] * x[3 * cj] + b[3 * r + 1] * x[3 * cj + 1] + b[3 * r + 2] * x[3 * cj + 2];
+    }
+    for (int r = 0; r < 3; ++r) y[3 * row + r] = a[r];
+}
+
+// ----------------------------------------------------------------- CG
+// The iteration lives on the device: alpha, beta, rho and the stop flag are in
+// CgScalars; every kernel returns at once when the flag is set, so the host
+// can launch iterations in batches and poll the flag between batches.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_cg_init(int64_t n, const T *__restrict__ dinv, T *__restrict__ x,
+                                                const T *__restrict__ r, T *__restrict__ p, double *partials,
+                                                int64_t stride, CgScalars *sc, double tol)
+{
+    double v[2] = {0, 0};
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const T ri = r[i], zi = dinv[i] * ri;
+        x[i] = 0;
+        p[i] = zi;
+        v[0] += (double)ri * (double)zi;
+        v[1] += (double)ri * (double)ri;
+    }
+    double tot[2];
+    if (grid_reduce<2>(v, partials, stride, &sc->counter, tot) && threadIdx.x == 0) {
+        sc->rho = tot[0];
+        sc->rr = tot[1];
+        sc->bb = tot[1];
+        sc->tol2 = tol * tol * tot[1];
+        sc->iter = 0;
+        sc->status = FG_OK;
+        sc->done = 0;
+        if (!isfinite(tot[0]) || !isfinite(tot[1])) {
+            sc->status = FG_ERR_NAN;
+            sc->done = 1;
+        } else if (tot[1] == 0.0) {
+            sc->done = 1;
+        } else if (sc->maxit <= 0) {
+            sc->status = FG_NOT_CONVERGED;
+            sc->done = 1;
+        }
+    }
+}
+
+template <int BS, typename T, typename TV>
+__global__ __launch_bounds__(WG) void k_cg_spmv(int64_t nslices, const int64_t *__restrict__ slice_ptr,
+                                                const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                                const T *__restrict__ p, T *__restrict__ q, double *partials,
+                                                int64_t stride, CgScalars *sc)
+{
+    if (sc->done) return;
+    const int64_t s = xcd_block() * (WG / SLICE) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    double v[1] = {0};
+    if (s < nslices) {
+        const int64_t base = slice_ptr[s];
+        const int w = (int)((slice_ptr[s + 1] - base) / SLICE);
+        const int64_t r = s * SLICE + lane;
+        if (BS == 3) {
+            T y0, y1, y2;
+            row3<T, TV>(base, w, lane, col, val, p, y0, y1, y2);
+            q[3 * r] = y0, q[3 * r + 1] = y1, q[3 * r + 2] = y2;
+            v[0] = (double)p[3 * r] * (double)y0 + (double)p[3 * r + 1] * (double)y1 + (double)p[3 * r + 2] * (double)y2;
+        } else {
+            const T y0 = row1<T, TV>(base, w, lane, col, val, p);
+            q[r] = y0;
+            v[0] = (double)p[r] * (double)y0;
+        }
+    }
+    double tot[1];
+    if (grid_reduce<1>(v, partials, stride, &sc->counter, tot) && threadIdx.x == 0) {
+        const double pq = tot[0];
+        sc->pq = pq;
+        if (!isfinite(pq)) {
+            sc->status = FG_ERR_NAN;
+            sc->done = 1;
+        } else if (!(pq > 0.0)) {
+            sc->status = FG_ERR_BREAKDOWN;
+            sc->done = 1;
+        } else {
+            sc->alpha = sc->rho / pq;
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(WG) void k_cg_update(int64_t n, const T *__restrict__ dinv, T *__restrict__ x,
+                                                  T *__restrict__ r, const T *__restrict__ p,
+                                                  const T *__restrict__ q, double *partials, int64_t stride,
+                                                  CgScalars *sc)
+{
+    if (sc->done) return;
+    const T al = (T)sc->alpha;
+    double v[2] = {0, 0};
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        x[i] += al * p[i];
+        const T ri = r[i] - al * q[i];
+        r[i] = ri;
+        const T zi = dinv[i] * ri;
+        v[0] += (double)ri * (double)zi;
+        v[1] += (double)ri * (double)ri;
+    }
+    double tot[2];
+    if (grid_reduce<2>(v, partials, stride, &sc->counter, tot) && threadIdx.x == 0) {
+        sc->iter += 1;
+        sc->rr = tot[1];
+        if (!isfinite(tot[0]) || !isfinite(tot[1])) {
+            sc->status = FG_ERR_NAN;
+            sc->done = 1;
+        } else if (tot[1] <= sc->tol2) {
+            sc->status = FG_OK;
+            sc->done = 1;
+        } else if (sc->iter >= sc->maxit) {
+            sc->status = FG_NOT_CONVERGED;
+            sc->done = 1;
+        } else {
+            sc->beta = tot[0] / sc->rho;
+            sc->rho = tot[0];
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(WG) void k_cg_pupdate(int64_t n, const T *__restrict__ dinv, const T *__restrict__ r,
+                                                   T *__restrict__ p, const CgScalars *sc)
+{
+    if (sc->done) return;
+    const T be = (T)sc->beta;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = dinv[i] * r[i] + be * p[i];
+}
+
+}  // namespace
+
+// =================================================================== launchers
+fg_status check_hip(const char *where)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error(std::string(where) + ": " + hipGetErrorString(e));
+        return FG_ERR_HIP;
+    }
+    return FG_OK;
+}
+
+#define LAUNCH(kern, grid, block, st, ...) hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, st, __VA_ARGS__)
+
+void perm_in(const fg_system *S, int bs, const double *nat, double *in, hipStream_t st)
+{
+    LAUNCH(k_perm_in, grid_elems(S->Npad * bs), WG, st, S->N, S->Npad, bs, S->perm, nat, in);
+}
+
+void perm_out(const fg_system *S, int bs, const double *in, double *nat, hipStream_t st)
+{
+    LAUNCH(k_perm_out, grid_elems(S->N * bs), WG, st, S->N, bs, S->perm, in, nat);
+}
+
+void perm_in_u8(const fg_system *S, int bs, const uint8_t *nat, uint8_t *in, hipStream_t st)
+{
+    LAUNCH(k_perm_in_u8, grid_elems(S->Npad * bs), WG, st, S->N, S->Npad, bs, S->perm, nat, in);
+}
+
+void vfill(double *y, double v, int64_t n, hipStream_t st) { LAUNCH(k_fill, grid_elems(n), WG, st, y, v, n); }
+
+void vaxpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t st)
+{
+    LAUNCH(k_axpby, grid_elems(n), WG, st, n, a, x, b, y);
+}
+
+void vmask(int64_t n, const uint8_t *mask, double *y, hipStream_t st) { LAUNCH(k_mask, grid_elems(n), WG, st, n, mask, y); }
+
+void to_f32(int64_t n, double s, const double *x, float *y, hipStream_t st)
+{
+    LAUNCH(k_to_f32, grid_elems(n), WG, st, n, s, x, y);
+}
+
+void add_f32(int64_t n, double s, const float *x, double *y, hipStream_t st)
+{
+    LAUNCH(k_add_f32, grid_elems(n), WG, st, n, s, x, y);
+}
+
+void vdots(fg_system *S, int64_t n, int nd, const double *const *a, const double *const *b, double *host, hipStream_t st)
+{
+    DotArgs args{};
+    for (int k = 0; k < nd; ++k) {
+        args.a[k] = a[k];
+        args.b[k] = b[k];
+    }
+    const int64_t g = grid_elems(n);
+    switch (nd) {
+    case 1: LAUNCH(k_dots<1>, g, WG, st, n, args, S->partials, S->npartials, S->red_counter, S->red); break;
+    case 2: LAUNCH(k_dots<2>, g, WG, st, n, args, S->partials, S->npartials, S->red_counter, S->red); break;
+    case 3: LAUNCH(k_dots<3>, g, WG, st, n, args, S->partials, S->npartials, S->red_counter, S->red); break;
+    default: LAUNCH(k_dots<4>, g, WG, st, n, args, S->partials, S->npartials, S->red_counter, S->red); break;
+    }
+    hipMemcpyAsync(S->red_host, S->red, nd * sizeof(double), hipMemcpyDeviceToHost, st);
+    hipStreamSynchronize(st);
+    for (int k = 0; k < nd; ++k) host[k] = S->red_host[k];
+}
+
+void assemble_all(fg_system *S, const double *E, const double *logk, hipStream_t st)
+{
+    const Plan &P = S->plan;
+    hipMemsetAsync(S->K, 0, S->nblk * 9 * sizeof(double), st);
+    hipMemsetAsync(S->A22, 0, S->nblk * sizeof(double), st);
+    hipMemsetAsync(S->Cm, 0, S->nblk * sizeof(double), st);
+    int *bad = (int *)S->red_counter + 1;
+    hipMemsetAsync(bad, 0, sizeof(int), st);
+    for (size_t c = 0; c + 1 < P.colour_ptr.size(); ++c) {
+        const int64_t a = P.colour_ptr[c], b = P.colour_ptr[c + 1];
+        if (b > a)
+            LAUNCH(k_assemble_tets, (b - a + WG - 1) / WG, WG, st, a, b, S->tets, S->tet_orig, S->xyz, E, logk, S->prm,
+                   S->slice_ptr, S->col, S->rowlen, S->K, S->A22, S->Cm, bad);
+    }
+    if (S->nf > 0) {
+        LAUNCH(k_tri_geo, (S->nf + WG - 1) / WG, WG, st, S->nf, S->coh, S->xyz, S->tri_geo);
+        LAUNCH(k_fault_flow, (S->nfr * S->fault_w + WG - 1) / WG, WG, st, S->nfr, S->fault_w, S->frows, S->fadj_ptr,
+               S->fadj, S->coh, S->tri_geo, S->xyz, S->prm, S->slice_ptr, S->col, S->rowlen, S->A22, S->Cm);
+    }
+    LAUNCH(k_dirichlet, (S->Npad + WG - 1) / WG, WG, st, S->Npad, S->slice_ptr, S->col, S->rowlen, S->dir_u, S->dir_p,
+           S->K, S->A22, S->dinvK, S->dinvA);
+    if (S->nf > 0)
+        LAUNCH(k_save_fault_bulk, (S->nfr * S->fault_w + WG - 1) / WG, WG, st, S->nfr, S->fault_w, S->frows,
+               S->slice_ptr, S->rowlen, S->K, S->Kfb);
+}
+
+void stick_tangent(fg_system *S, hipStream_t st)
+{
+    if (S->nq == 0) return;
+    LAUNCH(k_stick_tangent, (S->nq + WG - 1) / WG, WG, st, S->nq, S->tri_geo, S->prm.k_n, S->prm.k_s, S->qpD);
+    cohesive_rows(S, S->fc, 1, st);
+}
+
+void refresh_k32(fg_system *S, hipStream_t st)
+{
+    to_f32(S->nblk * 9, 1.0, S->K, S->K32, st);
+    to_f32(3 * S->Npad, 1.0, S->dinvK, S->dinvK32, st);
+    S->k32_valid = true;
+}
+
+void cohesive_qp(fg_system *S, const double *U_int, const double *die_n, const double *t0, double *trac, double *die,
+                 uint8_t *flag, hipStream_t st)
+{
+    if (S->nq == 0) return;
+    LAUNCH(k_cohesive_qp, (S->nq + WG - 1) / WG, WG, st, S->nq, S->coh, S->tri_geo, U_int, die_n, t0, S->prm.k_n,
+           S->prm.k_s, S->prm.friction, trac, die, flag, S->qpT, S->qpD);
+}
+
+void cohesive_rows(fg_system *S, double *fcoh_int, int write_tangent, hipStream_t st)
+{
+    vfill(fcoh_int, 0.0, 3 * S->Npad, st);
+    if (S->nq == 0) return;
+    LAUNCH(k_cohesive_force, (S->nfr + WG - 1) / WG, WG, st, S->nfr, S->frows, S->fadj_ptr, S->fadj, S->tri_geo,
+           S->qpT, S->dir_u, fcoh_int);
+    if (write_tangent)
+        LAUNCH(k_cohesive_tangent, (S->nfr * S->fault_w + WG - 1) / WG, WG, st, S->nfr, S->fault_w, S->frows,
+               S->fadj_ptr, S->fadj, S->coh, S->tri_geo, S->qpD, S->Kfb, S->slice_ptr, S->col, S->rowlen, S->dir_u,
+               S->K, S->k32_valid ? S->K32 : nullptr, S->dinvK, S->k32_valid ? S->dinvK32 : nullptr);
+}
+
+void apply_Apu(fg_system *S, const double *p, double *out, hipStream_t st)
+{
+    const Plan &P = S->plan;
+    vfill(out, 0.0, 3 * S->Npad, st);
+    for (size_t c = 0; c + 1 < P.colour_ptr.size(); ++c) {
+        const int64_t a = P.colour_ptr[c], b = P.colour_ptr[c + 1];
+        if (b > a) LAUNCH(k_apu_tets, (b - a + WG - 1) / WG, WG, st, a, b, S->tets, S->xyz, S->prm.alpha, p, S->dir_p, out);
+    }
+    if (S->nf > 0)
+        LAUNCH(k_apu_fault, (S->nfr + WG - 1) / WG, WG, st, S->nfr, S->frows, S->fadj_ptr, S->fadj, S->coh, S->tri_geo,
+               p, S->dir_p, out);
+    vmask(3 * S->Npad, S->dir_u, out, st);
+}
+
+void apply_Aup(fg_system *S, const double *u, double *out, hipStream_t st)
+{
+    const Plan &P = S->plan;
+    vfill(out, 0.0, S->Npad, st);
+    for (size_t c = 0; c + 1 < P.colour_ptr.size(); ++c) {
+        const int64_t a = P.colour_ptr[c], b = P.colour_ptr[c + 1];
+        if (b > a) LAUNCH(k_aup_tets, (b - a + WG - 1) / WG, WG, st, a, b, S->tets, S->xyz, S->prm.alpha, u, S->dir_u, out);
+    }
+    if (S->nf > 0)
+        LAUNCH(k_aup_fault, (S->nfr + WG - 1) / WG, WG, st, S->nfr, S->frows, S->fadj_ptr, S->fadj, S->coh, S->tri_geo,
+               u, S->dir_u, out);
+    vmask(S->Npad, S->dir_p, out, st);
+}
+
+void spmv(fg_system *S, int which, const double *x, double *y, hipStream_t st)
+{
+    const int64_t g = grid_xcd((S->nslices + 3) / 4);
+    if (which == FG_K || which == FG_KBULK) {
+        LAUNCH((k_spmv3<double, double>), g, WG, st, S->nslices, S->slice_ptr, S->col, S->K, x, y);
+        if (which == FG_KBULK && S->nf > 0)
+            LAUNCH(k_spmv_fault_bulk, (S->nfr + WG - 1) / WG, WG, st, S->nfr, S->fault_w, S->frows, S->slice_ptr,
+                   S->col, S->rowlen, S->Kfb, x, y);
+    } else {
+        const double *v = which == FG_A22 ? S->A22 : S->Cm;
+        LAUNCH((k_spmv1<double, double>), g, WG, st, S->nslices, S->slice_ptr, S->col, v, x, y);
+    }
+}
+
+void spmv_k32(fg_system *S, const float *x, float *y, hipStream_t st)
+{
+    const int64_t g = grid_xcd((S->nslices + 3) / 4);
+    LAUNCH((k_spmv3<float, float>), g, WG, st, S->nslices, S->slice_ptr, S->col, S->K32, x, y);
+}
+
+// Sum the durations of the timed launches of the last batch (stream already synchronised).
+static void prof_collect(fg_system *S)
+{
+    for (int i = 0; i < S->prof_pending; ++i) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, S->prof_ev[2 * i], S->prof_ev[2 * i + 1]) == hipSuccess) {
+            S->prof_ms[S->prof_slot] += ms;
+            S->prof_count[S->prof_slot] += 1;
+        }
+    }
+    S->prof_pending = 0;
+}
+
+template <int BS, typename T, typename TV>
+static void cg_batch(fg_system *S, const TV *val, const T *dinv, T *x, T *r, T *p, T *q, int iters, int slot,
+                     hipStream_t st)
+{
+    const int64_t n = BS * S->Npad;
+    const int64_t gs = grid_xcd((S->nslices + 3) / 4), ge = grid_elems(n);
+    if (S->prof) {
+        while ((int)S->prof_ev.size() < 2 * iters) {
+            hipEvent_t e;
+            hipEventCreate(&e);
+            S->prof_ev.push_back(e);
+        }
+        S->prof_slot = slot;
+    }
+    for (int it = 0; it < iters; ++it) {
+        if (S->prof) hipEventRecord(S->prof_ev[2 * it], st);
+        LAUNCH((k_cg_spmv<BS, T, TV>), gs, WG, st, S->nslices, S->slice_ptr, S->col, val, p, q, S->partials,
+               S->npartials, S->sc);
+        if (S->prof) {
+            hipEventRecord(S->prof_ev[2 * it + 1], st);
+            S->prof_pending = it + 1;
+        }
+        LAUNCH((k_cg_update<T>), ge, WG, st, n, dinv, x, r, p, q, S->partials, S->npartials, S->sc);
+        LAUNCH((k_cg_pupdate<T>), ge, WG, st, n, dinv, r, p, S->sc);
+    }
+}
+
+fg_status cg_run(fg_system *S, int which, int precision, double tol, int64_t maxit, int check_every, int64_t *iters,
+                 double *relres, hipStream_t st)
+{
+    const int bs = which == FG_K ? 3 : 1;
+    const int64_t n = bs * S->Npad;
+    CgScalars init{};
+    init.maxit = maxit;
+    hipMemcpyAsync(S->sc, &init, sizeof init, hipMemcpyHostToDevice, st);
+    const bool f32 = (which == FG_K && precision == FG_F32);
+    if (f32) {
+        if (!S->k32_valid) refresh_k32(S, st);
+        LAUNCH((k_cg_init<float>), grid_elems(n), WG, st, n, S->dinvK32, S->fx, S->fr, S->fp, S->partials, S->npartials,
+               S->sc, tol);
+    } else if (which == FG_K) {
+        LAUNCH((k_cg_init<double>), grid_elems(n), WG, st, n, S->dinvK, S->wx, S->wr, S->wp, S->partials, S->npartials,
+               S->sc, tol);
+    } else {
+        LAUNCH((k_cg_init<double>), grid_elems(n), WG, st, n, S->dinvA, S->wx, S->wr, S->wp, S->partials, S->npartials,
+               S->sc, tol);
+    }
+    fg_status e = check_hip("cg init");
+    if (e) return e;
+    const int batch = check_every > 0 ? check_every : 32;
+    for (;;) {
+        hipMemcpyAsync(S->sc_host, S->sc, sizeof(CgScalars), hipMemcpyDeviceToHost, st);
+        hipStreamSynchronize(st);
+        e = check_hip("cg poll");
+        if (e) return e;
+        if (S->prof_pending) prof_collect(S);
+        if (S->sc_host->done) break;
+        if (f32)
+            cg_batch<3, float, float>(S, S->K32, S->dinvK32, S->fx, S->fr, S->fp, S->fq, batch, 1, st);
+        else if (which == FG_K)
+            cg_batch<3, double, double>(S, S->K, S->dinvK, S->wx, S->wr, S->wp, S->wq, batch, 0, st);
+        else
+            cg_batch<1, double, double>(S, S->A22, S->dinvA, S->wx, S->wr, S->wp, S->wq, batch, 2, st);
+    }
+    const CgScalars &h = *S->sc_host;
+    *iters = h.iter;
+    *relres = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
+    if (h.status == FG_ERR_BREAKDOWN) set_error("fg_pcg_solve: CG breakdown (p.Ap <= 0): operator not SPD");
+    if (h.status == FG_ERR_NAN) set_error("fg_pcg_solve: NaN or Inf in the CG iteration");
+    return h.status;
+}
+
+}  // namespace fg

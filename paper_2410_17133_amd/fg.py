@@ -1,0 +1,284 @@
+"""Python binding of libfg (ctypes).  Argument marshalling only: every step of
+the solver runs in libfg's HIP kernels; torch supplies device memory and the
+stream.  Raises when the library or the GPU is missing -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfg.so")
+
+FG_OK, FG_NOT_CONVERGED = 0, 1
+FG_ERR_ARG, FG_ERR_OOM, FG_ERR_BREAKDOWN, FG_ERR_NAN, FG_ERR_HIP, FG_ERR_STATE = -1, -2, -3, -4, -5, -6
+FG_K, FG_A22, FG_KBULK, FG_C = 0, 1, 2, 3
+FG_F64, FG_F32, FG_MIXED = 0, 1, 2
+
+SYMBOLS = ["fg_last_error", "fg_ctx_create", "fg_ctx_destroy", "fg_system_create", "fg_system_destroy",
+           "fg_assemble", "fg_cohesive_update", "fg_pcg_solve", "fg_flow_solve", "fg_step", "fg_spmv",
+           "fg_coupling", "fg_residual", "fg_system_sizes", "fg_export", "fg_profile", "fg_profile_read"]
+
+
+class FgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libfg status {status}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [(n, C.c_double) for n in
+                ("nu", "alpha", "biot_M", "mu", "k_par", "k_perp", "w0", "M_F", "k_n", "k_s", "friction", "dt")]
+
+
+class Mesh(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("n_tets", C.c_int64), ("n_coh", C.c_int64),
+                ("xyz_h", C.c_void_p), ("tets_h", C.c_void_p), ("coh_h", C.c_void_p),
+                ("dir_u_h", C.c_void_p), ("dir_p_h", C.c_void_p)]
+
+
+class PcgOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int64), ("precision", C.c_int),
+                ("check_every", C.c_int), ("inner_tol", C.c_double)]
+
+
+class PcgInfo(C.Structure):
+    _fields_ = [("iters", C.c_int64), ("cycles", C.c_int64), ("relres", C.c_double), ("status", C.c_int)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("newton_iters", C.c_int64), ("outer_iters", C.c_int64), ("inner_k_iters", C.c_int64),
+                ("inner_a22_iters", C.c_int64), ("outer_relres", C.c_double), ("res_m", C.c_double),
+                ("res_f", C.c_double), ("status", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libfg.so (built by __graft_entry__.build / paper_2410_17133_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FgError(FG_ERR_STATE, f"{LIB_PATH} is missing: build it first (python __graft_entry__.py)")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = C.c_void_p, C.c_int, C.c_int64, C.c_double
+        L.fg_last_error.restype = C.c_char_p
+        sig = {
+            "fg_ctx_create": [C.POINTER(vp), i32],
+            "fg_ctx_destroy": [vp],
+            "fg_system_create": [vp, C.POINTER(Mesh), C.POINTER(vp)],
+            "fg_system_destroy": [vp],
+            "fg_assemble": [vp, vp, C.POINTER(Params), vp, vp, vp],
+            "fg_cohesive_update": [vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp],
+            "fg_pcg_solve": [vp, vp, i32, i32, vp, vp, C.POINTER(PcgOpts), C.POINTER(PcgInfo), vp],
+            "fg_flow_solve": [vp, vp, vp, vp, vp, vp, C.POINTER(PcgOpts), C.POINTER(PcgOpts), dbl, i64,
+                              C.POINTER(SolveInfo), vp],
+            "fg_step": [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, dbl, i64, C.POINTER(PcgOpts), C.POINTER(PcgOpts),
+                        dbl, i64, C.POINTER(SolveInfo), vp],
+            "fg_spmv": [vp, vp, i32, vp, vp, vp],
+            "fg_coupling": [vp, vp, i32, vp, vp, vp],
+            "fg_residual": [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
+            "fg_system_sizes": [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)],
+            "fg_export": [vp, vp, i32, vp, vp, vp, vp],
+            "fg_profile": [vp, i32],
+            "fg_profile_read": [vp, i32, C.POINTER(i64), C.POINTER(dbl), i32],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.restype = C.c_int
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status, allow_not_converged=True):
+    if status == FG_OK or (status == FG_NOT_CONVERGED and allow_not_converged):
+        return status
+    raise FgError(status, lib().fg_last_error().decode())
+
+
+def _ptr(t, dtype, n=None, name="tensor"):
+    if t is None:
+        return None
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise FgError(FG_ERR_ARG, f"{name}: expected a contiguous {dtype} CUDA tensor")
+    if n is not None and t.numel() != n:
+        raise FgError(FG_ERR_ARG, f"{name}: expected {n} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def opts(tol=1e-10, max_iter=1000000, precision=FG_F64, check_every=32, inner_tol=1e-4):
+    return PcgOpts(tol, max_iter, precision, check_every, inner_tol)
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        if not torch.cuda.is_available():
+            raise FgError(FG_ERR_STATE, "no HIP device visible")
+        h = C.c_void_p()
+        _check(lib().fg_ctx_create(C.byref(h), device))
+        self._h = h
+        self.device = torch.device("cuda", device)
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.fg_ctx_destroy(self._h)
+            self._h = None
+
+
+class System:
+    """A planned mesh with its assembled operators on the GPU."""
+
+    def __init__(self, ctx: Context, xyz, tets, coh, dir_u, dir_p):
+        self.ctx = ctx
+        self._keep = [np.ascontiguousarray(xyz, np.float64), np.ascontiguousarray(tets, np.int32),
+                      np.ascontiguousarray(coh if len(coh) else np.zeros((0, 6)), np.int32),
+                      np.ascontiguousarray(dir_u, np.uint8), np.ascontiguousarray(dir_p, np.uint8)]
+        x, t, c, du, dp = self._keep
+        self.N, self.ne, self.nf = x.shape[0], t.shape[0], c.shape[0]
+        self.nq = 3 * self.nf
+        m = Mesh(self.N, self.ne, self.nf, x.ctypes.data, t.ctypes.data, c.ctypes.data if self.nf else None,
+                 du.ctypes.data, dp.ctypes.data)
+        h = C.c_void_p()
+        _check(lib().fg_system_create(ctx._h, C.byref(m), C.byref(h)))
+        self._h = h
+        self.dev = ctx.device
+
+    @classmethod
+    def from_instance(cls, ctx, inst):
+        m = inst.mesh
+        return cls(ctx, m.xyz, m.tets, m.coh, inst.dir_u, inst.dir_p)
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.fg_system_destroy(self._h)
+            self._h = None
+
+    def sizes(self):
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().fg_system_sizes(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def _d(self, n, dtype=torch.float64):
+        return torch.zeros(n, dtype=dtype, device=self.dev)
+
+    def assemble(self, params, E, logk):
+        self.params = Params(*params.as_tuple()) if hasattr(params, "as_tuple") else params
+        self.E = E if isinstance(E, torch.Tensor) else torch.as_tensor(np.asarray(E, np.float64), device=self.dev)
+        self.logk = logk if isinstance(logk, torch.Tensor) else torch.as_tensor(np.asarray(logk, np.float64), device=self.dev)
+        _check(lib().fg_assemble(self.ctx._h, self._h, C.byref(self.params), _ptr(self.E, torch.float64, self.ne, "E"),
+                                 _ptr(self.logk, torch.float64, self.ne, "log_k"), _stream()))
+
+    def cohesive_update(self, U, die_n, t0, write_tangent=True):
+        nq = self.nq
+        trac, die = self._d(3 * nq), self._d(2 * nq)
+        flag = self._d(nq, torch.uint8)
+        fcoh = self._d(3 * self.N)
+        _check(lib().fg_cohesive_update(self.ctx._h, self._h, _ptr(U, torch.float64, 3 * self.N, "U"),
+                                        _ptr(die_n, torch.float64, 2 * nq, "die_n"), _ptr(t0, torch.float64, 3 * nq, "t0"),
+                                        _ptr(trac, torch.float64), _ptr(die, torch.float64), _ptr(flag, torch.uint8),
+                                        _ptr(fcoh, torch.float64), int(bool(write_tangent)), _stream()))
+        return trac, die, flag, fcoh
+
+    def pcg_solve(self, which, b, nrhs=1, **kw):
+        n = (3 if which == FG_K else 1) * self.N * nrhs
+        x = self._d(n)
+        info = PcgInfo()
+        st = lib().fg_pcg_solve(self.ctx._h, self._h, which, nrhs, _ptr(b, torch.float64, n, "b"),
+                                _ptr(x, torch.float64), C.byref(opts(**kw)), C.byref(info), _stream())
+        _check(st)
+        return x, info
+
+    def flow_solve(self, b_u, b_p, inner_k=None, inner_p=None, outer_tol=1e-10, outer_max_iter=1000):
+        du, dp = self._d(3 * self.N), self._d(self.N)
+        info = SolveInfo()
+        ik = inner_k or opts(tol=1e-12)
+        ip = inner_p or opts(tol=1e-12)
+        st = lib().fg_flow_solve(self.ctx._h, self._h, _ptr(b_u, torch.float64, 3 * self.N, "b_u"),
+                                 _ptr(b_p, torch.float64, self.N, "b_p"), _ptr(du, torch.float64),
+                                 _ptr(dp, torch.float64), C.byref(ik), C.byref(ip), outer_tol, outer_max_iter,
+                                 C.byref(info), _stream())
+        _check(st)
+        return du, dp, info
+
+    def step(self, U, P, die, t0, F_u, f_p, newton_tol=1e-10, newton_max_iter=30, inner_k=None, inner_p=None,
+             outer_tol=1e-10, outer_max_iter=1000):
+        """One implicit step; U, P, die (CUDA float64) are updated in place."""
+        nq = self.nq
+        trac = self._d(3 * nq)
+        flag = self._d(nq, torch.uint8)
+        info = SolveInfo()
+        ik = inner_k or opts(tol=1e-12)
+        ip = inner_p or opts(tol=1e-12)
+        st = lib().fg_step(self.ctx._h, self._h, _ptr(U, torch.float64, 3 * self.N, "U"),
+                           _ptr(P, torch.float64, self.N, "P"), _ptr(die, torch.float64, 2 * nq, "die"),
+                           _ptr(trac, torch.float64), _ptr(flag, torch.uint8), _ptr(t0, torch.float64, 3 * nq, "t0"),
+                           _ptr(F_u, torch.float64, 3 * self.N, "F_u"), _ptr(f_p, torch.float64, self.N, "f_p"),
+                           newton_tol, newton_max_iter, C.byref(ik), C.byref(ip), outer_tol, outer_max_iter,
+                           C.byref(info), _stream())
+        _check(st)
+        return trac, flag, info
+
+    def spmv(self, which, x):
+        n = (3 if which in (FG_K, FG_KBULK) else 1) * self.N
+        y = self._d(n)
+        _check(lib().fg_spmv(self.ctx._h, self._h, which, _ptr(x, torch.float64, n, "x"), _ptr(y, torch.float64),
+                             _stream()), False)
+        return y
+
+    def coupling(self, x, transpose=False):
+        nin, nout = (3 * self.N, self.N) if transpose else (self.N, 3 * self.N)
+        y = self._d(nout)
+        _check(lib().fg_coupling(self.ctx._h, self._h, int(transpose), _ptr(x, torch.float64, nin, "x"),
+                                 _ptr(y, torch.float64), _stream()), False)
+        return y
+
+    def residual(self, U, P, U_n, P_n, f_coh, F_u, f_p):
+        Rm, Rf = self._d(3 * self.N), self._d(self.N)
+        n3, n1 = 3 * self.N, self.N
+        _check(lib().fg_residual(self.ctx._h, self._h, _ptr(U, torch.float64, n3), _ptr(P, torch.float64, n1),
+                                 _ptr(U_n, torch.float64, n3), _ptr(P_n, torch.float64, n1),
+                                 _ptr(f_coh, torch.float64, n3), _ptr(F_u, torch.float64, n3),
+                                 _ptr(f_p, torch.float64, n1), _ptr(Rm, torch.float64), _ptr(Rf, torch.float64),
+                                 _stream()), False)
+        return Rm, Rf
+
+    def profile(self, enable=True):
+        _check(lib().fg_profile(self._h, int(bool(enable))), False)
+
+    def profile_read(self, slot=0, reset=True):
+        """(launches, milliseconds) of the timed CG product kernel for slot 0 = K FP64, 1 = K FP32, 2 = A22."""
+        n, ms = C.c_int64(), C.c_double()
+        _check(lib().fg_profile_read(self._h, slot, C.byref(n), C.byref(ms), int(bool(reset))), False)
+        return n.value, ms.value
+
+    def export(self, which):
+        """Assembled operator as node-pair blocks (rows, cols, vals), caller order, host numpy."""
+        npairs = self.sizes()[0]
+        bs = 9 if which in (FG_K, FG_KBULK) else 1
+        rows, cols = np.zeros(npairs, np.int32), np.zeros(npairs, np.int32)
+        vals = np.zeros(npairs * bs)
+        _check(lib().fg_export(self.ctx._h, self._h, which, rows.ctypes.data, cols.ctypes.data, vals.ctypes.data,
+                               _stream()), False)
+        return rows, cols, vals.reshape(npairs, 3, 3) if bs == 9 else vals
+
+    def scipy(self, which):
+        """The exported operator as a scalar scipy CSR matrix (caller DOF order)."""
+        import scipy.sparse as sp
+        rows, cols, vals = self.export(which)
+        if which in (FG_K, FG_KBULK):
+            r = (3 * rows[:, None, None] + np.arange(3)[None, :, None]).repeat(3, 2).reshape(-1)
+            c = (3 * cols[:, None, None] + np.arange(3)[None, None, :]).repeat(3, 1).reshape(-1)
+            return sp.csr_matrix((vals.reshape(-1), (r, c)), shape=(3 * self.N, 3 * self.N))
+        return sp.csr_matrix((vals, (rows, cols)), shape=(self.N, self.N))

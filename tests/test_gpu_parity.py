@@ -1,0 +1,281 @@
+"""GPU (libfg through its C-ABI) against the CPU oracle on the same seeded inputs.
+
+Tolerances: assembled operators and products agree to 1e-12 of the largest
+entry (same arithmetic, different rounding order); iterative solves are run
+to tight tolerances on both sides and compared in relative L2 norm.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2410_17133_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _fg():
+    from paper_2410_17133_amd import fg
+    return fg
+
+
+def _oracle():
+    from oracle import oracle as O
+    return O
+
+
+def dev(a, dtype=None):
+    t = torch.as_tensor(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def relerr(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+CASES = {
+    "cube8": lambda: I.make_instance(I.config(1)),
+    "cube12_dip60_hetero": lambda: I.make_instance(I.cube_config(12, dip_deg=60, heterogeneous=True)),
+    "cube16_dip70": lambda: I.make_instance(I.cube_config(16, dip_deg=70)),
+}
+
+_cache = {}
+
+
+def setup(name):
+    if name not in _cache:
+        fg, O = _fg(), _oracle()
+        inst = CASES[name]()
+        ctx = fg.Context(0)
+        S = fg.System.from_instance(ctx, inst)
+        S.assemble(inst.params, inst.E, inst.logk)
+        P = O.Problem(inst)
+        _cache[name] = (inst, ctx, S, P)
+    return _cache[name]
+
+
+def spdiff(A, B):
+    D = (A - B).tocoo()
+    return (np.abs(D.data).max() if D.nnz else 0.0) / np.abs(B.data).max()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_assembled_operators(name):
+    fg, O = _fg(), _oracle()
+    inst, ctx, S, P = setup(name)
+    print(f"[case] assembly {name} N={S.N}", flush=True)
+    assert spdiff(S.scipy(fg.FG_KBULK), P.scipy(O.K_BULK)) < 1e-12
+    assert spdiff(S.scipy(fg.FG_A22), P.scipy(O.A22)) < 1e-12
+    assert spdiff(S.scipy(fg.FG_C), P.scipy(O.C_FLOW)) < 1e-12
+    # initial tangent: bulk plus stick-and-contact interface stiffness
+    P.cohesive(np.zeros(3 * P.N), np.zeros((P.nq, 2)))
+    assert spdiff(S.scipy(fg.FG_K), P.scipy(O.K_TANGENT)) < 1e-12
+    npairs, nblk, nsl = S.sizes()
+    assert npairs == P.csr(O.A22)[1].size
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_products(name):
+    fg, O = _fg(), _oracle()
+    inst, ctx, S, P = setup(name)
+    print(f"[case] products {name}", flush=True)
+    r = np.random.default_rng(1)
+    u, p = r.standard_normal(3 * S.N), r.standard_normal(S.N)
+    P.cohesive(np.zeros(3 * P.N), np.zeros((P.nq, 2)))
+    S.cohesive_update(dev(np.zeros(3 * S.N)), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)))
+    for which, ow, x in ((fg.FG_K, O.K_TANGENT, u), (fg.FG_KBULK, O.K_BULK, u), (fg.FG_A22, O.A22, p), (fg.FG_C, O.C_FLOW, p)):
+        y = host(S.spmv(which, dev(x)))
+        yo = P.spmv(ow, x)
+        assert relerr(y, yo) < 1e-13, which
+    assert relerr(host(S.coupling(dev(p))), P.apply_Apu(p)) < 1e-13
+    assert relerr(host(S.coupling(dev(u), transpose=True)), P.apply_Aup(u)) < 1e-13
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_cohesive_update(name):
+    fg, O = _fg(), _oracle()
+    inst, ctx, S, P = setup(name)
+    print(f"[case] cohesive {name}", flush=True)
+    r = np.random.default_rng(2)
+    U = r.normal(0, 4e-7, 3 * S.N) * (1 - inst.dir_u)
+    die_n = r.normal(0, 2e-7, (S.nq, 2))
+    trac_o, die_o, flag_o, f_o = P.cohesive(U, die_n)
+    assert len(set(flag_o.tolist())) == 3  # stick, slip and open all present
+    trac, die, flag, fcoh = S.cohesive_update(dev(U), dev(die_n.reshape(-1)), dev(inst.t0.reshape(-1)))
+    np.testing.assert_array_equal(host(flag), flag_o)
+    scale = inst.cfg.tn0
+    assert np.abs(host(trac).reshape(-1, 3) - trac_o).max() <= 1e-9 * scale
+    assert np.abs(host(die).reshape(-1, 2) - die_o).max() <= 1e-12 * max(np.abs(die_o).max(), 1e-9)
+    assert relerr(host(fcoh), f_o) < 1e-11
+    assert spdiff(S.scipy(fg.FG_K), P.scipy(O.K_TANGENT)) < 1e-12
+    # bulk part untouched by the tangent update
+    assert spdiff(S.scipy(fg.FG_KBULK), P.scipy(O.K_BULK)) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["cube8", "cube12_dip60_hetero"])
+def test_pcg_k_and_a22(name):
+    fg, O = _fg(), _oracle()
+    inst, ctx, S, P = setup(name)
+    print(f"[case] pcg {name}", flush=True)
+    P.cohesive(np.zeros(3 * P.N), np.zeros((P.nq, 2)))
+    S.cohesive_update(dev(np.zeros(3 * S.N)), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)))
+    r = np.random.default_rng(3)
+    b = r.standard_normal(3 * S.N) * (1 - inst.dir_u)
+    x, info = S.pcg_solve(fg.FG_K, dev(b), tol=1e-13)
+    xo, st, it, rr = P.pcg(O.K_TANGENT, b, tol=1e-13)
+    assert info.status == 0 and st == 0
+    assert relerr(host(x), xo) < 1e-9
+    # true residual of the GPU solution, measured with the oracle's own product, is as
+    # small as that of the oracle's solution (both sit at the FP64 drift floor)
+    true_gpu = np.linalg.norm(b - P.spmv(O.K_TANGENT, host(x))) / np.linalg.norm(b)
+    true_orc = np.linalg.norm(b - P.spmv(O.K_TANGENT, xo)) / np.linalg.norm(b)
+    assert true_gpu <= max(10 * true_orc, 1e-12)
+    assert abs(info.iters - it) <= max(3, 0.02 * it)
+    bp = r.standard_normal(S.N)
+    xp, info = S.pcg_solve(fg.FG_A22, dev(bp), tol=1e-13)
+    xpo, st, it, rr = P.pcg(O.A22, bp, tol=1e-13)
+    assert relerr(host(xp), xpo) < 1e-9
+
+
+def test_pcg_mixed_and_f32():
+    fg, O = _fg(), _oracle()
+    inst, ctx, S, P = setup("cube12_dip60_hetero")
+    P.cohesive(np.zeros(3 * P.N), np.zeros((P.nq, 2)))
+    S.cohesive_update(dev(np.zeros(3 * S.N)), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)))
+    r = np.random.default_rng(4)
+    b = r.standard_normal(3 * S.N) * (1 - inst.dir_u)
+    x, info = S.pcg_solve(fg.FG_K, dev(b), tol=1e-8, precision=fg.FG_MIXED)
+    assert info.status == 0 and info.cycles >= 1
+    assert np.linalg.norm(b - P.spmv(O.K_TANGENT, host(x))) <= 1e-8 * np.linalg.norm(b)
+    xo, st, it, rr = P.pcg(O.K_TANGENT, b, tol=1e-13)
+    print(f"[mixed] cycles {info.cycles} iters {info.iters} err vs fp64 {relerr(host(x), xo):.2e}", flush=True)
+    # FP32 alone: the recursive residual reaches the tolerance, the true residual stops
+    # near kappa * u32 (about 1e4 * 6e-8 here), which is what refinement removes
+    x32, info32 = S.pcg_solve(fg.FG_K, dev(b), tol=1e-5, precision=fg.FG_F32)
+    assert info32.status == 0
+    assert np.linalg.norm(b - P.spmv(O.K_TANGENT, host(x32))) <= 5e-3 * np.linalg.norm(b)
+
+
+def test_flow_solve_parity():
+    fg, O = _fg(), _oracle()
+    inst, ctx, S, P = setup("cube8")
+    print("[case] prevost cube8", flush=True)
+    r = np.random.default_rng(5)
+    U = r.normal(0, 3e-6, 3 * S.N) * (1 - inst.dir_u)
+    P.cohesive(U, np.zeros((P.nq, 2)))
+    S.cohesive_update(dev(U), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)))
+    b1 = r.standard_normal(3 * S.N) * 1e6 * (1 - inst.dir_u)
+    b2 = r.standard_normal(S.N) * 1e-6
+    du, dp, info = S.flow_solve(dev(b1), dev(b2), inner_k=fg.opts(tol=1e-14), inner_p=fg.opts(tol=1e-14), outer_tol=1e-13)
+    x1, x2, st, stats = P.prevost(b1, b2, tol_outer=1e-13, tol_inner=1e-14)
+    assert info.status == 0 and st == 0
+    assert relerr(host(du), x1) < 1e-9
+    assert relerr(host(dp), x2) < 1e-9
+    assert abs(info.outer_iters - stats[0]) <= 2
+
+
+def test_step_parity_config1():
+    fg, O = _fg(), _oracle()
+    inst, ctx, S, P = setup("cube8")
+    print("[case] step cube8", flush=True)
+    N, nq = S.N, S.nq
+    Uo, Po, dieo = np.zeros(3 * N), np.zeros(N), np.zeros((nq, 2))
+    kw = dict(tol_newton=1e-11, max_newton=40, tol_outer=1e-12, tol_inner=1e-13)
+    trac_o, flag_o, info_o, st_o = P.step(Uo, Po, dieo, **kw)
+    U, Pp, die = dev(np.zeros(3 * N)), dev(np.zeros(N)), dev(np.zeros(2 * nq))
+    trac, flag, info = S.step(U, Pp, die, dev(inst.t0.reshape(-1)), dev(inst.load), dev(inst.source),
+                              newton_tol=1e-11, newton_max_iter=40, inner_k=fg.opts(tol=1e-13),
+                              inner_p=fg.opts(tol=1e-13), outer_tol=1e-12)
+    print(f"[step] gpu {info.as_dict()} oracle {info_o}", flush=True)
+    assert info.status == 0 and st_o == 0
+    assert info.newton_iters == info_o[0]
+    np.testing.assert_array_equal(host(flag), flag_o)
+    assert relerr(host(U), Uo) < 1e-9
+    assert relerr(host(Pp), Po) < 1e-9
+    assert np.abs(host(die).reshape(-1, 2) - dieo).max() <= 1e-9 * np.abs(dieo).max()
+    assert np.abs(host(trac).reshape(-1, 3) - trac_o).max() <= 1e-9 * inst.cfg.tn0
+
+
+def test_residual_parity():
+    fg, O = _fg(), _oracle()
+    inst, ctx, S, P = setup("cube12_dip60_hetero")
+    r = np.random.default_rng(6)
+    N = S.N
+    U, Un = r.normal(0, 1e-7, 3 * N), r.normal(0, 1e-7, 3 * N)
+    Pp, Pn = r.normal(0, 1e6, N), r.normal(0, 1e6, N)
+    die_n = np.zeros((S.nq, 2))
+    _, _, _, fo = P.cohesive(U, die_n)
+    Rm_o, Rf_o = P.residual(U, Pp, Un, Pn, fo, inst.load, inst.source)
+    _, _, _, f = S.cohesive_update(dev(U), dev(die_n.reshape(-1)), dev(inst.t0.reshape(-1)))
+    Rm, Rf = S.residual(dev(U), dev(Pp), dev(Un), dev(Pn), f, dev(inst.load), dev(inst.source))
+    assert relerr(host(Rm), Rm_o) < 1e-11
+    assert relerr(host(Rf), Rf_o) < 1e-11
+
+
+# ------------------------------------------------------------------ error paths
+def test_error_paths():
+    fg = _fg()
+    inst, ctx, S, P = setup("cube8")
+    N = S.N
+    z = dev(np.zeros(3 * N))
+    x, info = S.pcg_solve(fg.FG_K, z)                     # b = 0 -> x = 0
+    assert info.status == 0 and info.iters == 0 and float(host(x).__abs__().max()) == 0.0
+    b = np.ones(3 * N) * (1 - inst.dir_u)
+    x, info = S.pcg_solve(fg.FG_K, dev(b), tol=1e-14, max_iter=3)
+    assert info.status == fg.FG_NOT_CONVERGED and info.iters == 3
+    bn = b.copy()
+    bn[5] = np.nan
+    with pytest.raises(fg.FgError) as e:
+        S.pcg_solve(fg.FG_K, dev(bn))
+    assert e.value.status == fg.FG_ERR_NAN
+    with pytest.raises(fg.FgError) as e:
+        S.pcg_solve(fg.FG_K, dev(np.zeros(3 * N + 1)))
+    assert e.value.status == fg.FG_ERR_ARG
+    with pytest.raises(fg.FgError) as e:
+        S.pcg_solve(7, z)
+    assert e.value.status == fg.FG_ERR_ARG
+
+
+def test_breakdown_on_indefinite_operator():
+    fg, O = _fg(), _oracle()
+    inst = I.make_instance(I.cube_config(4))
+    E = inst.E.copy()
+    E[::2] *= -1.0                                          # indefinite stiffness
+    ctx = fg.Context(0)
+    S = fg.System.from_instance(ctx, inst)
+    S.assemble(inst.params, E, inst.logk)
+    b = np.random.default_rng(0).standard_normal(3 * S.N) * (1 - inst.dir_u)
+    with pytest.raises(fg.FgError) as e:
+        S.pcg_solve(fg.FG_K, dev(b), tol=1e-12, max_iter=100000)
+    assert e.value.status == fg.FG_ERR_BREAKDOWN
+
+
+def test_assemble_before_solve_is_an_error():
+    fg = _fg()
+    inst = I.make_instance(I.cube_config(2))
+    ctx = fg.Context(0)
+    S = fg.System.from_instance(ctx, inst)
+    with pytest.raises(fg.FgError) as e:
+        S.pcg_solve(fg.FG_K, dev(np.zeros(3 * S.N)))
+    assert e.value.status == fg.FG_ERR_STATE
+
+
+def test_bad_mesh_is_rejected():
+    fg = _fg()
+    inst = I.make_instance(I.cube_config(2))
+    ctx = fg.Context(0)
+    tets = inst.mesh.tets.copy()
+    tets[3, 1] = inst.n_nodes + 5
+    with pytest.raises(fg.FgError) as e:
+        fg.System(ctx, inst.mesh.xyz, tets, inst.mesh.coh, inst.dir_u, inst.dir_p)
+    assert e.value.status == fg.FG_ERR_ARG
