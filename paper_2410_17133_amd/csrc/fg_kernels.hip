@@ -26,38 +26,37 @@ __device__ __forceinline__ double wave_sum(double x)
     return x;
 }
 
-// Deterministic grid-wide sum of NV values: per-block partial sums, then the
-// last block to finish adds the partials in a fixed order.  Returns true in
-// every thread of that last block, with the totals in tot.
+// Grid-wide sums without device-scope fences: every block stores its partial
+// sums with plain stores and a one-block finalize kernel adds them in a fixed
+// order after the kernel boundary (which makes the stores visible across XCDs).
+// Per-block fences would write back L2 once per block on this multi-XCD part.
 template <int NV>
-__device__ bool grid_reduce(const double (&v)[NV], double *partials, int64_t stride, uint32_t *counter,
-                            double (&tot)[NV])
+__device__ __forceinline__ void block_partials(const double (&v)[NV], double *partials, int64_t stride)
 {
     __shared__ double sh[NV][WG / 64];
-    __shared__ int last;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int k = 0; k < NV; ++k) {
         double s = wave_sum(v[k]);
         if (lane == 0) sh[k][w] = s;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0)
         for (int k = 0; k < NV; ++k) {
             double s = 0;
             for (int i = 0; i < nw; ++i) s += sh[k][i];
             partials[k * stride + blockIdx.x] = s;
         }
-        __threadfence();
-        unsigned prev = atomicAdd(counter, 1u);
-        last = (prev == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
-    const volatile double *vp = partials;
+}
+
+// Sum of nparts partials per value, in a fixed order; result valid in every thread.
+template <int NV>
+__device__ __forceinline__ void finalize_sum(const double *partials, int64_t stride, int64_t nparts, double (&tot)[NV])
+{
+    __shared__ double sh[NV][WG / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int k = 0; k < NV; ++k) {
         double s = 0;
-        for (int64_t i = threadIdx.x; i < gridDim.x; i += blockDim.x) s += vp[k * stride + i];
+        for (int64_t i = threadIdx.x; i < nparts; i += blockDim.x) s += partials[k * stride + i];
         s = wave_sum(s);
         if (lane == 0) sh[k][w] = s;
     }
@@ -67,8 +66,6 @@ __device__ bool grid_reduce(const double (&v)[NV], double *partials, int64_t str
         for (int i = 0; i < nw; ++i) s += sh[k][i];
         tot[k] = s;
     }
-    if (threadIdx.x == 0) *counter = 0;
-    return true;
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs; hand each XCD a
@@ -624,14 +621,21 @@ struct DotArgs {
 };
 
 template <int ND>
-__global__ void k_dots(int64_t n, DotArgs args, double *partials, int64_t stride, uint32_t *counter, double *res)
+__global__ void k_dots(int64_t n, DotArgs args, double *partials, int64_t stride)
 {
     double v[ND];
     for (int k = 0; k < ND; ++k) v[k] = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         for (int k = 0; k < ND; ++k) v[k] += args.a[k][i] * args.b[k][i];
+    block_partials<ND>(v, partials, stride);
+}
+
+template <int ND>
+__global__ void k_dots_fin(const double *partials, int64_t stride, int64_t nparts, double *res)
+{
     double tot[ND];
-    if (grid_reduce<ND>(v, partials, stride, counter, tot) && threadIdx.x == 0)
+    finalize_sum<ND>(partials, stride, nparts, tot);
+    if (threadIdx.x == 0)
         for (int k = 0; k < ND; ++k) res[k] = tot[k];
 }
 
@@ -723,7 +727,7 @@ __global__ void k_spmv_fault_bulk(int64_t nfr, int fw, const int32_t *__restrict
 template <typename T>
 __global__ __launch_bounds__(WG) void k_cg_init(int64_t n, const T *__restrict__ dinv, T *__restrict__ x,
                                                 const T *__restrict__ r, T *__restrict__ p, double *partials,
-                                                int64_t stride, CgScalars *sc, double tol)
+                                                int64_t stride)
 {
     double v[2] = {0, 0};
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -733,32 +737,39 @@ __global__ __launch_bounds__(WG) void k_cg_init(int64_t n, const T *__restrict__
         v[0] += (double)ri * (double)zi;
         v[1] += (double)ri * (double)ri;
     }
+    block_partials<2>(v, partials, stride);
+}
+
+__global__ __launch_bounds__(WG) void k_cg_init_fin(const double *partials, int64_t stride, int64_t nparts,
+                                                    CgScalars *sc, double tol)
+{
     double tot[2];
-    if (grid_reduce<2>(v, partials, stride, &sc->counter, tot) && threadIdx.x == 0) {
-        sc->rho = tot[0];
-        sc->rr = tot[1];
-        sc->bb = tot[1];
-        sc->tol2 = tol * tol * tot[1];
-        sc->iter = 0;
-        sc->status = FG_OK;
-        sc->done = 0;
-        if (!isfinite(tot[0]) || !isfinite(tot[1])) {
-            sc->status = FG_ERR_NAN;
-            sc->done = 1;
-        } else if (tot[1] == 0.0) {
-            sc->done = 1;
-        } else if (sc->maxit <= 0) {
-            sc->status = FG_NOT_CONVERGED;
-            sc->done = 1;
-        }
+    finalize_sum<2>(partials, stride, nparts, tot);
+    if (threadIdx.x != 0) return;
+    sc->rho = tot[0];
+    sc->rr = tot[1];
+    sc->bb = tot[1];
+    sc->tol2 = tol * tol * tot[1];
+    sc->iter = 0;
+    sc->status = FG_OK;
+    sc->done = 0;
+    if (!isfinite(tot[0]) || !isfinite(tot[1])) {
+        sc->status = FG_ERR_NAN;
+        sc->done = 1;
+    } else if (tot[1] == 0.0) {
+        sc->done = 1;
+    } else if (sc->maxit <= 0) {
+        sc->status = FG_NOT_CONVERGED;
+        sc->done = 1;
     }
 }
 
+// q = A p and the per-block partials of p.q.
 template <int BS, typename T, typename TV>
 __global__ __launch_bounds__(WG) void k_cg_spmv(int64_t nslices, const int64_t *__restrict__ slice_ptr,
                                                 const int32_t *__restrict__ col, const TV *__restrict__ val,
                                                 const T *__restrict__ p, T *__restrict__ q, double *partials,
-                                                int64_t stride, CgScalars *sc)
+                                                int64_t stride, const CgScalars *sc)
 {
     if (sc->done) return;
     const int64_t s = xcd_block() * (WG / SLICE) + (threadIdx.x >> 6);
@@ -779,19 +790,25 @@ __global__ __launch_bounds__(WG) void k_cg_spmv(int64_t nslices, const int64_t *
             v[0] = (double)p[r] * (double)y0;
         }
     }
+    block_partials<1>(v, partials, stride);
+}
+
+__global__ __launch_bounds__(WG) void k_cg_alpha(const double *partials, int64_t stride, int64_t nparts, CgScalars *sc)
+{
+    if (sc->done) return;
     double tot[1];
-    if (grid_reduce<1>(v, partials, stride, &sc->counter, tot) && threadIdx.x == 0) {
-        const double pq = tot[0];
-        sc->pq = pq;
-        if (!isfinite(pq)) {
-            sc->status = FG_ERR_NAN;
-            sc->done = 1;
-        } else if (!(pq > 0.0)) {
-            sc->status = FG_ERR_BREAKDOWN;
-            sc->done = 1;
-        } else {
-            sc->alpha = sc->rho / pq;
-        }
+    finalize_sum<1>(partials, stride, nparts, tot);
+    if (threadIdx.x != 0) return;
+    const double pq = tot[0];
+    sc->pq = pq;
+    if (!isfinite(pq)) {
+        sc->status = FG_ERR_NAN;
+        sc->done = 1;
+    } else if (!(pq > 0.0)) {
+        sc->status = FG_ERR_BREAKDOWN;
+        sc->done = 1;
+    } else {
+        sc->alpha = sc->rho / pq;
     }
 }
 
@@ -799,7 +816,7 @@ template <typename T>
 __global__ __launch_bounds__(WG) void k_cg_update(int64_t n, const T *__restrict__ dinv, T *__restrict__ x,
                                                   T *__restrict__ r, const T *__restrict__ p,
                                                   const T *__restrict__ q, double *partials, int64_t stride,
-                                                  CgScalars *sc)
+                                                  const CgScalars *sc)
 {
     if (sc->done) return;
     const T al = (T)sc->alpha;
@@ -812,23 +829,29 @@ __global__ __launch_bounds__(WG) void k_cg_update(int64_t n, const T *__restrict
         v[0] += (double)ri * (double)zi;
         v[1] += (double)ri * (double)ri;
     }
+    block_partials<2>(v, partials, stride);
+}
+
+__global__ __launch_bounds__(WG) void k_cg_beta(const double *partials, int64_t stride, int64_t nparts, CgScalars *sc)
+{
+    if (sc->done) return;
     double tot[2];
-    if (grid_reduce<2>(v, partials, stride, &sc->counter, tot) && threadIdx.x == 0) {
-        sc->iter += 1;
-        sc->rr = tot[1];
-        if (!isfinite(tot[0]) || !isfinite(tot[1])) {
-            sc->status = FG_ERR_NAN;
-            sc->done = 1;
-        } else if (tot[1] <= sc->tol2) {
-            sc->status = FG_OK;
-            sc->done = 1;
-        } else if (sc->iter >= sc->maxit) {
-            sc->status = FG_NOT_CONVERGED;
-            sc->done = 1;
-        } else {
-            sc->beta = tot[0] / sc->rho;
-            sc->rho = tot[0];
-        }
+    finalize_sum<2>(partials, stride, nparts, tot);
+    if (threadIdx.x != 0) return;
+    sc->iter += 1;
+    sc->rr = tot[1];
+    if (!isfinite(tot[0]) || !isfinite(tot[1])) {
+        sc->status = FG_ERR_NAN;
+        sc->done = 1;
+    } else if (tot[1] <= sc->tol2) {
+        sc->status = FG_OK;
+        sc->done = 1;
+    } else if (sc->iter >= sc->maxit) {
+        sc->status = FG_NOT_CONVERGED;
+        sc->done = 1;
+    } else {
+        sc->beta = tot[0] / sc->rho;
+        sc->rho = tot[0];
     }
 }
 
@@ -900,10 +923,22 @@ void vdots(fg_system *S, int64_t n, int nd, const double *const *a, const double
     }
     const int64_t g = grid_elems(n);
     switch (nd) {
-    case 1: LAUNCH(k_dots<1>, g, WG, st, n, args, S->partials, S->npartials, S->red_counter, S->red); break;
-    case 2: LAUNCH(k_dots<2>, g, WG, st, n, args, S->partials, S->npartials, S->red_counter, S->red); break;
-    case 3: LAUNCH(k_dots<3>, g, WG, st, n, args, S->partials, S->npartials, S->red_counter, S->red); break;
-    default: LAUNCH(k_dots<4>, g, WG, st, n, args, S->partials, S->npartials, S->red_counter, S->red); break;
+    case 1:
+        LAUNCH(k_dots<1>, g, WG, st, n, args, S->partials, S->npartials);
+        LAUNCH(k_dots_fin<1>, 1, WG, st, S->partials, S->npartials, g, S->red);
+        break;
+    case 2:
+        LAUNCH(k_dots<2>, g, WG, st, n, args, S->partials, S->npartials);
+        LAUNCH(k_dots_fin<2>, 1, WG, st, S->partials, S->npartials, g, S->red);
+        break;
+    case 3:
+        LAUNCH(k_dots<3>, g, WG, st, n, args, S->partials, S->npartials);
+        LAUNCH(k_dots_fin<3>, 1, WG, st, S->partials, S->npartials, g, S->red);
+        break;
+    default:
+        LAUNCH(k_dots<4>, g, WG, st, n, args, S->partials, S->npartials);
+        LAUNCH(k_dots_fin<4>, 1, WG, st, S->partials, S->npartials, g, S->red);
+        break;
     }
     hipMemcpyAsync(S->red_host, S->red, nd * sizeof(double), hipMemcpyDeviceToHost, st);
     hipStreamSynchronize(st);
@@ -1053,7 +1088,9 @@ static void cg_batch(fg_system *S, const TV *val, const T *dinv, T *x, T *r, T *
             hipEventRecord(S->prof_ev[2 * it + 1], st);
             S->prof_pending = it + 1;
         }
+        LAUNCH(k_cg_alpha, 1, WG, st, S->partials, S->npartials, gs, S->sc);
         LAUNCH((k_cg_update<T>), ge, WG, st, n, dinv, x, r, p, q, S->partials, S->npartials, S->sc);
+        LAUNCH(k_cg_beta, 1, WG, st, S->partials, S->npartials, ge, S->sc);
         LAUNCH((k_cg_pupdate<T>), ge, WG, st, n, dinv, r, p, S->sc);
     }
 }
@@ -1069,15 +1106,13 @@ fg_status cg_run(fg_system *S, int which, int precision, double tol, int64_t max
     const bool f32 = (which == FG_K && precision == FG_F32);
     if (f32) {
         if (!S->k32_valid) refresh_k32(S, st);
-        LAUNCH((k_cg_init<float>), grid_elems(n), WG, st, n, S->dinvK32, S->fx, S->fr, S->fp, S->partials, S->npartials,
-               S->sc, tol);
+        LAUNCH((k_cg_init<float>), grid_elems(n), WG, st, n, S->dinvK32, S->fx, S->fr, S->fp, S->partials, S->npartials);
     } else if (which == FG_K) {
-        LAUNCH((k_cg_init<double>), grid_elems(n), WG, st, n, S->dinvK, S->wx, S->wr, S->wp, S->partials, S->npartials,
-               S->sc, tol);
+        LAUNCH((k_cg_init<double>), grid_elems(n), WG, st, n, S->dinvK, S->wx, S->wr, S->wp, S->partials, S->npartials);
     } else {
-        LAUNCH((k_cg_init<double>), grid_elems(n), WG, st, n, S->dinvA, S->wx, S->wr, S->wp, S->partials, S->npartials,
-               S->sc, tol);
+        LAUNCH((k_cg_init<double>), grid_elems(n), WG, st, n, S->dinvA, S->wx, S->wr, S->wp, S->partials, S->npartials);
     }
+    LAUNCH(k_cg_init_fin, 1, WG, st, S->partials, S->npartials, grid_elems(n), S->sc, tol);
     fg_status e = check_hip("cg init");
     if (e) return e;
     const int batch = check_every > 0 ? check_every : 32;
