@@ -61,7 +61,7 @@ def main():
     t = time.perf_counter()
     ctx = fg.Context(0)
     S = fg.System.from_instance(ctx, inst)
-    npairs, nblk, nslices = S.sizes()
+    npairs, nblk, nslices, nhalo = S.sizes()
     log(f"planned: {npairs} blocks ({nblk} padded), {nslices} slices ({time.perf_counter() - t:.1f}s)")
     t = time.perf_counter()
     S.assemble(inst.params, inst.E, inst.logk)
@@ -98,9 +98,10 @@ def main():
     launches, ms = S.profile_read(0, reset=True)
     S.profile(False)
     value = k_iters / elapsed
-    # algorithmic bytes of one FP64 CG SpMV launch: each stored 3x3 block (72 B) and its
-    # column index (4 B) read once, x read once and q written once (24 B each per node)
-    bytes_launch = 76.0 * npairs + 48.0 * N
+    # algorithmic bytes of one FP64 CG SpMV launch in this storage: each stored 3x3 block
+    # (72 B) and its 16-bit halo-local column once, each halo list entry (4 B) once,
+    # x read once, q written once (24 B each per node) and the diagonal slot (4 B per node)
+    bytes_launch = 74.0 * npairs + 4.0 * nhalo + 52.0 * N
     avg_s = ms / 1e3 / max(launches, 1)
     achieved = bytes_launch / avg_s / 1e9
     out = {

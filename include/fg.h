@@ -130,6 +130,7 @@ fg_status fg_ctx_destroy(fg_ctx *ctx);
  * Errors: FG_ERR_ARG for out-of-range node ids or degenerate interface
  * triangles, FG_ERR_OOM. */
 fg_status fg_system_create(fg_ctx *ctx, const fg_mesh *mesh, fg_system **sys);
+/* Frees the system's device memory; valid even after its context was destroyed. */
 fg_status fg_system_destroy(fg_system *sys);
 
 /* Assemble (Sec. 3.2): K_bulk = sum_e V B^T D(E_e, nu) B (eq. discrete_balance),
@@ -214,16 +215,25 @@ fg_status fg_residual(fg_ctx *ctx, fg_system *sys, const double *U, const double
                       const double *P_n, const double *f_coh, const double *F_u, const double *f_p, double *R_m,
                       double *R_f, void *stream);
 
-/* Number of stored (nonzero-pattern) node pairs of the graph, and the
- * padded block count of the sliced storage. */
+/* Sizes of the planned storage (host outputs, each may be NULL): stored node
+ * pairs of the graph, blocks of the sliced storage including padding, slices
+ * of 64 rows, and the total length of the per-slice halo lists (distinct
+ * columns of each slice, staged in LDS by the products). */
 fg_status fg_system_sizes(const fg_system *sys, int64_t *n_pairs_h, int64_t *n_padded_blocks_h,
-                          int64_t *n_slices_h);
+                          int64_t *n_slices_h, int64_t *n_halo_h);
 
 /* Export an assembled operator as node-pair blocks in caller order (host
  * arrays of n_pairs entries): rows_h, cols_h node ids; vals_h 9 (K, KBULK,
  * row-major 3x3) or 1 (A22, C) values per pair.  Synchronises the stream. */
 fg_status fg_export(fg_ctx *ctx, fg_system *sys, int which, int32_t *rows_h, int32_t *cols_h, double *vals_h,
                     void *stream);
+
+/* Tuning knobs of the products (the autotuner's search space).
+ *   "halo_cap": largest per-slice halo whose x is staged in LDS; slices with a
+ *               larger halo gather x from global memory (0 = never stage).
+ *               Clipped to what 64 KB of LDS per 4-wavefront workgroup holds.
+ * Returns FG_ERR_ARG for an unknown key or a negative value. */
+fg_status fg_tune(fg_system *sys, const char *key, int64_t value);
 
 /* Live timing of the CG product kernel (the hot loop's dominant kernel).
  * enable != 0: every CG iteration records a HIP event on the solve's stream

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
 
@@ -22,8 +23,16 @@ using namespace fg;
 
 namespace {
 
+// Every entry point first discards a HIP error left pending by other code on
+// this thread (torch, the caller), so that check_hip reports only libfg's own
+// failures, then makes the context's device current.
 struct Guard {
-    explicit Guard(int dev) { hipSetDevice(dev); }
+    explicit Guard(int dev)
+    {
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) fprintf(stderr, "libfg: discarding a HIP error raised before this call: %s\n", hipGetErrorString(e));
+        hipSetDevice(dev);
+    }
 };
 
 template <class T>
@@ -325,9 +334,9 @@ fg_status fg_ctx_destroy(fg_ctx *ctx)
 fg_status fg_system_destroy(fg_system *S)
 {
     if (!S) return FG_OK;
-    Guard g(S->ctx->device);
+    Guard g(S->device);
     hipDeviceSynchronize();
-    void *ptrs[] = {S->slice_ptr, S->col, S->rowlen, S->diag_slot, S->perm, S->xyz, S->tets, S->tet_orig, S->coh,
+    void *ptrs[] = {S->halo_ptr, S->halo, S->lcol, S->slice_ptr, S->col, S->rowlen, S->diag_slot, S->perm, S->xyz, S->tets, S->tet_orig, S->coh,
                     S->frows, S->fadj_ptr, S->fadj, S->dir_u, S->dir_p, S->tri_geo, S->K, S->K32, S->Kfb, S->A22,
                     S->Cm, S->dinvK, S->dinvK32, S->dinvA, S->qpD, S->qpT, S->wx, S->wr, S->wp, S->wq, S->fx,
                     S->fr, S->fp, S->fq, S->v1, S->v2, S->v3, S->v4, S->pv1, S->pv2, S->ui, S->ui0, S->fi, S->rm,
@@ -350,6 +359,7 @@ fg_status fg_system_create(fg_ctx *ctx, const fg_mesh *mesh, fg_system **out)
     Guard g(ctx->device);
     fg_system *S = new fg_system;
     S->ctx = ctx;
+    S->device = ctx->device;
     std::string err;
     fg_status e = build_plan(*mesh, S->plan, err);
     if (e) {
@@ -384,6 +394,11 @@ fg_status fg_system_create(fg_ctx *ctx, const fg_mesh *mesh, fg_system **out)
     CK(upload(&S->rowlen, P.rowlen));
     CK(upload(&S->diag_slot, P.diag_slot));
     CK(upload(&S->perm, P.perm));
+    CK(upload(&S->halo_ptr, P.halo_ptr));
+    CK(upload(&S->halo, P.halo));
+    CK(upload(&S->lcol, P.lcol));
+    // LDS window per wavefront: the largest halo, within 64 KB per 4-wave workgroup of FP64 3-vectors
+    S->halo_cap = (int)std::min<int64_t>(P.halo_max, 65536 / (4 * 3 * (int64_t)sizeof(double)));
     std::vector<double> xyz(3 * S->Npad, 0.0);
     for (int64_t r = 0; r < S->N; ++r)
         for (int c = 0; c < 3; ++c) xyz[3 * r + c] = mesh->xyz_h[3 * (int64_t)P.perm[r] + c];
@@ -439,9 +454,10 @@ fg_status fg_system_create(fg_ctx *ctx, const fg_mesh *mesh, fg_system **out)
     return check_hip("fg_system_create");
 }
 
-fg_status fg_system_sizes(const fg_system *S, int64_t *n_pairs, int64_t *n_blk, int64_t *n_slices)
+fg_status fg_system_sizes(const fg_system *S, int64_t *n_pairs, int64_t *n_blk, int64_t *n_slices, int64_t *n_halo)
 {
     if (!S) return FG_ERR_ARG;
+    if (n_halo) *n_halo = S->plan.halo_ptr.empty() ? 0 : S->plan.halo_ptr.back();
     if (n_pairs) *n_pairs = S->plan.npairs;
     if (n_blk) *n_blk = S->nblk;
     if (n_slices) *n_slices = S->nslices;
@@ -749,6 +765,20 @@ fg_status fg_export(fg_ctx *ctx, fg_system *S, int which, int32_t *rows, int32_t
         }
     }
     return FG_OK;
+}
+
+fg_status fg_tune(fg_system *S, const char *key, int64_t value)
+{
+    if (!S || !key || value < 0) {
+        set_error("fg_tune: bad argument");
+        return FG_ERR_ARG;
+    }
+    if (std::strcmp(key, "halo_cap") == 0) {
+        S->halo_cap = (int)std::min<int64_t>(value, 65536 / (4 * 3 * (int64_t)sizeof(double)));
+        return FG_OK;
+    }
+    set_error(std::string("fg_tune: unknown key ") + key);
+    return FG_ERR_ARG;
 }
 
 fg_status fg_profile(fg_system *S, int enable)

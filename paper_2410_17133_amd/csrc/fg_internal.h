@@ -25,6 +25,10 @@ struct Plan {
     std::vector<int32_t> col;        // [nblk_pad] internal column node, padding = own row
     std::vector<uint8_t> rowlen;     // [Npad]
     std::vector<int32_t> diag_slot;  // [Npad] slot of the diagonal block, -1 for padding rows
+    std::vector<int64_t> halo_ptr;   // [nslices+1] first halo entry of each slice
+    std::vector<int32_t> halo;       // sorted distinct columns of each slice
+    std::vector<uint16_t> lcol;      // [nblk_pad] column as an index into the slice's halo
+    int64_t halo_max = 0;
     std::vector<int32_t> tets;       // [ne*4] internal node ids, grouped by colour
     std::vector<int32_t> tet_orig;   // [ne] caller index of each grouped tetrahedron
     std::vector<int64_t> colour_ptr; // [ncolours+1]
@@ -34,7 +38,6 @@ struct Plan {
     std::vector<int32_t> fadj;       // 6*t + local vertex (0..5) of each incident interface element
     std::vector<uint8_t> dir_u;      // [3*Npad] internal order, padding rows 0
     std::vector<uint8_t> dir_p;      // [Npad]
-    std::vector<uint8_t> is_pad;     // unused
 };
 
 // Builds the plan; returns FG_OK or an error with a message in `err`.
@@ -68,6 +71,7 @@ struct fg_ctx {
 
 struct fg_system {
     fg_ctx *ctx = nullptr;
+    int device = 0;  // own copy: the system may outlive its context object
     fg::Plan plan;  // host copy (sizes, colours, permutation)
     int64_t N = 0, Npad = 0, nslices = 0, nblk = 0, ne = 0, nf = 0, nq = 0, nfr = 0;
     int ncolours = 0;
@@ -79,6 +83,10 @@ struct fg_system {
     uint8_t *rowlen = nullptr;
     int32_t *diag_slot = nullptr;
     int32_t *perm = nullptr;  // internal -> caller
+    int64_t *halo_ptr = nullptr;
+    int32_t *halo = nullptr;
+    uint16_t *lcol = nullptr;
+    int halo_cap = 0;         // largest halo staged in LDS; larger slices gather from global memory
     // device mesh (internal numbering)
     double *xyz = nullptr;
     int32_t *tets = nullptr, *tet_orig = nullptr;

@@ -640,65 +640,102 @@ __global__ void k_dots_fin(const double *partials, int64_t stride, int64_t npart
 }
 
 // ----------------------------------------------------------------- SpMV
-template <typename T, typename TV>
-__device__ __forceinline__ void row3(int64_t base, int w, int lane, const int32_t *__restrict__ col,
-                                     const TV *__restrict__ val, const T *__restrict__ x, T &y0, T &y1, T &y2)
+// Each wavefront owns one slice.  It first copies x of the slice's halo (the
+// sorted distinct columns of its 64 rows) into its own LDS window, then walks
+// the slots: the 9 (or 1) values of a slot are 64-wide coalesced loads and the
+// x operands come from LDS through 16-bit local column indices.  A slice whose
+// halo exceeds the LDS window (irregular meshes) gathers x from global memory.
+template <int BS, typename T>
+__device__ __forceinline__ bool stage_halo(int64_t s, int lane, const int64_t *__restrict__ halo_ptr,
+                                           const int32_t *__restrict__ halo, int cap, const T *__restrict__ x, T *xs)
 {
-    const int32_t *c = col + base + lane;
-    const TV *v = val + 9 * base + lane;
-    T a0 = 0, a1 = 0, a2 = 0;
+    const int64_t h0 = halo_ptr[s];
+    const int hn = (int)(halo_ptr[s + 1] - h0);
+    if (hn > cap) return false;
+    for (int i = lane; i < hn; i += SLICE) {
+        const int64_t node = halo[h0 + i];
+#pragma unroll
+        for (int k = 0; k < BS; ++k) xs[BS * i + k] = x[BS * node + k];
+    }
+    return true;
+}
+
+// y = A x for one row (lane) of a slice; IDX is uint16_t (halo-local, xs in LDS)
+// or int32_t (global, xs = x).  dj: slot of the row's diagonal, whose x is
+// returned in d0..d2 (for p.Ap).
+template <int BS, typename T, typename TV, typename IDX>
+__device__ __forceinline__ void slice_row(int64_t base, int w, int lane, int dj, const IDX *__restrict__ idx,
+                                          const TV *__restrict__ val, const T *xs, T (&y)[BS], T (&d)[BS])
+{
+    const IDX *c = idx + base + lane;
+    const TV *v = val + BS * BS * base + lane;
+#pragma unroll
+    for (int r = 0; r < BS; ++r) y[r] = 0, d[r] = 0;
 #pragma unroll 3
     for (int j = 0; j < w; ++j) {
         const int64_t cj = c[(int64_t)j * SLICE];
-        const T *xp = x + 3 * cj;
-        const T x0 = xp[0], x1 = xp[1], x2 = xp[2];
-        const TV *vb = v + (int64_t)9 * j * SLICE;
-        a0 += (T)vb[0] * x0 + (T)vb[SLICE] * x1 + (T)vb[2 * SLICE] * x2;
-        a1 += (T)vb[3 * SLICE] * x0 + (T)vb[4 * SLICE] * x1 + (T)vb[5 * SLICE] * x2;
-        a2 += (T)vb[6 * SLICE] * x0 + (T)vb[7 * SLICE] * x1 + (T)vb[8 * SLICE] * x2;
+        T xv[BS];
+#pragma unroll
+        for (int k = 0; k < BS; ++k) xv[k] = xs[BS * cj + k];
+        const TV *vb = v + (int64_t)BS * BS * j * SLICE;
+#pragma unroll
+        for (int r = 0; r < BS; ++r)
+#pragma unroll
+            for (int k = 0; k < BS; ++k) y[r] += (T)vb[(BS * r + k) * SLICE] * xv[k];
+        if (j == dj)
+#pragma unroll
+            for (int k = 0; k < BS; ++k) d[k] = xv[k];
     }
-    y0 = a0, y1 = a1, y2 = a2;
 }
 
-template <typename T, typename TV>
-__device__ __forceinline__ T row1(int64_t base, int w, int lane, const int32_t *__restrict__ col,
-                                  const TV *__restrict__ val, const T *__restrict__ x)
+// q = A p for the rows of one slice; returns p.q of the lane's row.
+template <int BS, typename T, typename TV>
+__device__ __forceinline__ double slice_spmv(int64_t s, int lane, bool staged, const int64_t *__restrict__ slice_ptr,
+                                             const int32_t *__restrict__ col, const uint16_t *__restrict__ lcol,
+                                             const int32_t *__restrict__ diag_slot, const TV *__restrict__ val,
+                                             const T *__restrict__ x, const T *xs, T *__restrict__ y)
 {
-    const int32_t *c = col + base + lane;
-    const TV *v = val + base + lane;
-    T a = 0;
-#pragma unroll 4
-    for (int j = 0; j < w; ++j) a += (T)v[(int64_t)j * SLICE] * x[c[(int64_t)j * SLICE]];
-    return a;
-}
-
-template <typename T, typename TV>
-__global__ __launch_bounds__(WG) void k_spmv3(int64_t nslices, const int64_t *__restrict__ slice_ptr,
-                                              const int32_t *__restrict__ col, const TV *__restrict__ val,
-                                              const T *__restrict__ x, T *__restrict__ y)
-{
-    const int64_t s = xcd_block() * (WG / SLICE) + (threadIdx.x >> 6);
-    if (s >= nslices) return;
-    const int lane = threadIdx.x & 63;
     const int64_t base = slice_ptr[s];
     const int w = (int)((slice_ptr[s + 1] - base) / SLICE);
-    T y0, y1, y2;
-    row3<T, TV>(base, w, lane, col, val, x, y0, y1, y2);
     const int64_t r = s * SLICE + lane;
-    y[3 * r] = y0, y[3 * r + 1] = y1, y[3 * r + 2] = y2;
+    const int dj = diag_slot[r];
+    T yv[BS], d[BS];
+    if (staged)
+        slice_row<BS, T, TV, uint16_t>(base, w, lane, dj, lcol, val, xs, yv, d);
+    else
+        slice_row<BS, T, TV, int32_t>(base, w, lane, dj, col, val, x, yv, d);
+    double pq = 0;
+#pragma unroll
+    for (int k = 0; k < BS; ++k) {
+        y[BS * r + k] = yv[k];
+        pq += (double)d[k] * (double)yv[k];
+    }
+    return pq;
 }
 
-template <typename T, typename TV>
-__global__ __launch_bounds__(WG) void k_spmv1(int64_t nslices, const int64_t *__restrict__ slice_ptr,
-                                              const int32_t *__restrict__ col, const TV *__restrict__ val,
-                                              const T *__restrict__ x, T *__restrict__ y)
+struct SpmvArgs {
+    int64_t nslices;
+    const int64_t *slice_ptr;
+    const int32_t *col;
+    const uint16_t *lcol;
+    const int32_t *diag_slot;
+    const int64_t *halo_ptr;
+    const int32_t *halo;
+    int cap;
+};
+
+template <int BS, typename T, typename TV>
+__global__ __launch_bounds__(WG) void k_spmv(SpmvArgs a, const TV *__restrict__ val, const T *__restrict__ x,
+                                             T *__restrict__ y)
 {
-    const int64_t s = xcd_block() * (WG / SLICE) + (threadIdx.x >> 6);
-    if (s >= nslices) return;
-    const int lane = threadIdx.x & 63;
-    const int64_t base = slice_ptr[s];
-    const int w = (int)((slice_ptr[s + 1] - base) / SLICE);
-    y[s * SLICE + lane] = row1<T, TV>(base, w, lane, col, val, x);
+    extern __shared__ unsigned char smem[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    T *xs = (T *)smem + (int64_t)wave * a.cap * BS;
+    const int64_t s = xcd_block() * (WG / SLICE) + wave;
+    bool staged = false;
+    if (s < a.nslices) staged = stage_halo<BS, T>(s, lane, a.halo_ptr, a.halo, a.cap, x, xs);
+    __syncthreads();
+    if (s < a.nslices) slice_spmv<BS, T, TV>(s, lane, staged, a.slice_ptr, a.col, a.lcol, a.diag_slot, val, x, xs, y);
 }
 
 // Fault rows of K_bulk x from the saved bulk blocks (overwrites y on those rows).
@@ -766,30 +803,20 @@ __global__ __launch_bounds__(WG) void k_cg_init_fin(const double *partials, int6
 
 // q = A p and the per-block partials of p.q.
 template <int BS, typename T, typename TV>
-__global__ __launch_bounds__(WG) void k_cg_spmv(int64_t nslices, const int64_t *__restrict__ slice_ptr,
-                                                const int32_t *__restrict__ col, const TV *__restrict__ val,
-                                                const T *__restrict__ p, T *__restrict__ q, double *partials,
-                                                int64_t stride, const CgScalars *sc)
+__global__ __launch_bounds__(WG) void k_cg_spmv(SpmvArgs a, const TV *__restrict__ val, const T *__restrict__ p,
+                                                T *__restrict__ q, double *partials, int64_t stride,
+                                                const CgScalars *sc)
 {
     if (sc->done) return;
-    const int64_t s = xcd_block() * (WG / SLICE) + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
+    extern __shared__ unsigned char smem[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    T *xs = (T *)smem + (int64_t)wave * a.cap * BS;
+    const int64_t s = xcd_block() * (WG / SLICE) + wave;
+    bool staged = false;
+    if (s < a.nslices) staged = stage_halo<BS, T>(s, lane, a.halo_ptr, a.halo, a.cap, p, xs);
+    __syncthreads();
     double v[1] = {0};
-    if (s < nslices) {
-        const int64_t base = slice_ptr[s];
-        const int w = (int)((slice_ptr[s + 1] - base) / SLICE);
-        const int64_t r = s * SLICE + lane;
-        if (BS == 3) {
-            T y0, y1, y2;
-            row3<T, TV>(base, w, lane, col, val, p, y0, y1, y2);
-            q[3 * r] = y0, q[3 * r + 1] = y1, q[3 * r + 2] = y2;
-            v[0] = (double)p[3 * r] * (double)y0 + (double)p[3 * r + 1] * (double)y1 + (double)p[3 * r + 2] * (double)y2;
-        } else {
-            const T y0 = row1<T, TV>(base, w, lane, col, val, p);
-            q[r] = y0;
-            v[0] = (double)p[r] * (double)y0;
-        }
-    }
+    if (s < a.nslices) v[0] = slice_spmv<BS, T, TV>(s, lane, staged, a.slice_ptr, a.col, a.lcol, a.diag_slot, val, p, xs, q);
     block_partials<1>(v, partials, stride);
 }
 
@@ -879,6 +906,19 @@ fg_status check_hip(const char *where)
 }
 
 #define LAUNCH(kern, grid, block, st, ...) hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, st, __VA_ARGS__)
+#define LAUNCH_SH(kern, grid, block, sh, st, ...) \
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), sh, st, __VA_ARGS__)
+
+static SpmvArgs spmv_args(const fg_system *S)
+{
+    return SpmvArgs{S->nslices, S->slice_ptr, S->col, S->lcol, S->diag_slot, S->halo_ptr, S->halo, S->halo_cap};
+}
+
+template <int BS, typename T>
+static size_t spmv_lds(const fg_system *S)
+{
+    return (size_t)(WG / SLICE) * S->halo_cap * BS * sizeof(T);
+}
 
 void perm_in(const fg_system *S, int bs, const double *nat, double *in, hipStream_t st)
 {
@@ -1036,21 +1076,22 @@ void apply_Aup(fg_system *S, const double *u, double *out, hipStream_t st)
 void spmv(fg_system *S, int which, const double *x, double *y, hipStream_t st)
 {
     const int64_t g = grid_xcd((S->nslices + 3) / 4);
+    const SpmvArgs a = spmv_args(S);
     if (which == FG_K || which == FG_KBULK) {
-        LAUNCH((k_spmv3<double, double>), g, WG, st, S->nslices, S->slice_ptr, S->col, S->K, x, y);
+        LAUNCH_SH((k_spmv<3, double, double>), g, WG, (spmv_lds<3, double>(S)), st, a, S->K, x, y);
         if (which == FG_KBULK && S->nf > 0)
             LAUNCH(k_spmv_fault_bulk, (S->nfr + WG - 1) / WG, WG, st, S->nfr, S->fault_w, S->frows, S->slice_ptr,
                    S->col, S->rowlen, S->Kfb, x, y);
     } else {
         const double *v = which == FG_A22 ? S->A22 : S->Cm;
-        LAUNCH((k_spmv1<double, double>), g, WG, st, S->nslices, S->slice_ptr, S->col, v, x, y);
+        LAUNCH_SH((k_spmv<1, double, double>), g, WG, (spmv_lds<1, double>(S)), st, a, v, x, y);
     }
 }
 
 void spmv_k32(fg_system *S, const float *x, float *y, hipStream_t st)
 {
     const int64_t g = grid_xcd((S->nslices + 3) / 4);
-    LAUNCH((k_spmv3<float, float>), g, WG, st, S->nslices, S->slice_ptr, S->col, S->K32, x, y);
+    LAUNCH_SH((k_spmv<3, float, float>), g, WG, (spmv_lds<3, float>(S)), st, spmv_args(S), S->K32, x, y);
 }
 
 // Sum the durations of the timed launches of the last batch (stream already synchronised).
@@ -1082,8 +1123,8 @@ static void cg_batch(fg_system *S, const TV *val, const T *dinv, T *x, T *r, T *
     }
     for (int it = 0; it < iters; ++it) {
         if (S->prof) hipEventRecord(S->prof_ev[2 * it], st);
-        LAUNCH((k_cg_spmv<BS, T, TV>), gs, WG, st, S->nslices, S->slice_ptr, S->col, val, p, q, S->partials,
-               S->npartials, S->sc);
+        LAUNCH_SH((k_cg_spmv<BS, T, TV>), gs, WG, (spmv_lds<BS, T>(S)), st, spmv_args(S), val, p, q, S->partials,
+                  S->npartials, S->sc);
         if (S->prof) {
             hipEventRecord(S->prof_ev[2 * it + 1], st);
             S->prof_pending = it + 1;

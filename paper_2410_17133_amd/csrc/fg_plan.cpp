@@ -190,6 +190,31 @@ fg_status build_plan(const fg_mesh &m, Plan &P, std::string &err)
     });
     P.npairs = npairs.load();
 
+    // Per-slice halo: the sorted distinct columns of the slice's rows.  The
+    // products stage x of the halo in LDS and address it with 16-bit local
+    // column indices.
+    P.halo_ptr.assign(P.nslices + 1, 0);
+    std::vector<std::vector<int32_t>> halos(P.nslices);
+    P.lcol.assign(P.nblk_pad, 0);
+    parallel_for(P.nslices, [&](int64_t a, int64_t b) {
+        for (int64_t s = a; s < b; ++s) {
+            const int64_t base = P.slice_ptr[s];
+            const int64_t len = P.slice_ptr[s + 1] - base;
+            std::vector<int32_t> &h = halos[s];
+            h.assign(P.col.begin() + base, P.col.begin() + base + len);
+            std::sort(h.begin(), h.end());
+            h.erase(std::unique(h.begin(), h.end()), h.end());
+            for (int64_t k = 0; k < len; ++k)
+                P.lcol[base + k] = (uint16_t)(std::lower_bound(h.begin(), h.end(), P.col[base + k]) - h.begin());
+        }
+    });
+    for (int64_t s = 0; s < P.nslices; ++s) {
+        P.halo_ptr[s + 1] = P.halo_ptr[s] + (int64_t)halos[s].size();
+        P.halo_max = std::max<int64_t>(P.halo_max, (int64_t)halos[s].size());
+    }
+    P.halo.resize(P.halo_ptr[P.nslices]);
+    for (int64_t s = 0; s < P.nslices; ++s) std::copy(halos[s].begin(), halos[s].end(), P.halo.begin() + P.halo_ptr[s]);
+
     // greedy colouring of tetrahedra: no two tetrahedra of a colour share a node
     const int MAXC = 256;
     std::vector<uint64_t> used((size_t)N * (MAXC / 64), 0);

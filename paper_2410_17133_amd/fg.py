@@ -20,7 +20,7 @@ FG_F64, FG_F32, FG_MIXED = 0, 1, 2
 
 SYMBOLS = ["fg_last_error", "fg_ctx_create", "fg_ctx_destroy", "fg_system_create", "fg_system_destroy",
            "fg_assemble", "fg_cohesive_update", "fg_pcg_solve", "fg_flow_solve", "fg_step", "fg_spmv",
-           "fg_coupling", "fg_residual", "fg_system_sizes", "fg_export", "fg_profile", "fg_profile_read"]
+           "fg_coupling", "fg_residual", "fg_system_sizes", "fg_export", "fg_profile", "fg_profile_read", "fg_tune"]
 
 
 class FgError(RuntimeError):
@@ -85,9 +85,10 @@ def lib():
             "fg_spmv": [vp, vp, i32, vp, vp, vp],
             "fg_coupling": [vp, vp, i32, vp, vp, vp],
             "fg_residual": [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
-            "fg_system_sizes": [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)],
+            "fg_system_sizes": [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)],
             "fg_export": [vp, vp, i32, vp, vp, vp, vp],
             "fg_profile": [vp, i32],
+            "fg_tune": [vp, C.c_char_p, i64],
             "fg_profile_read": [vp, i32, C.POINTER(i64), C.POINTER(dbl), i32],
         }
         for name, args in sig.items():
@@ -166,9 +167,10 @@ class System:
             self._h = None
 
     def sizes(self):
-        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
-        _check(lib().fg_system_sizes(self._h, C.byref(a), C.byref(b), C.byref(c)))
-        return a.value, b.value, c.value
+        """(stored blocks, padded blocks, slices, total halo entries)."""
+        a, b, c, d = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().fg_system_sizes(self._h, C.byref(a), C.byref(b), C.byref(c), C.byref(d)))
+        return a.value, b.value, c.value, d.value
 
     def _d(self, n, dtype=torch.float64):
         return torch.zeros(n, dtype=dtype, device=self.dev)
@@ -253,6 +255,9 @@ class System:
                                  _ptr(f_p, torch.float64, n1), _ptr(Rm, torch.float64), _ptr(Rf, torch.float64),
                                  _stream()), False)
         return Rm, Rf
+
+    def tune(self, key, value):
+        _check(lib().fg_tune(self._h, key.encode(), int(value)), False)
 
     def profile(self, enable=True):
         _check(lib().fg_profile(self._h, int(bool(enable))), False)

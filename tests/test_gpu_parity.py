@@ -80,7 +80,7 @@ def test_assembled_operators(name):
     # initial tangent: bulk plus stick-and-contact interface stiffness
     P.cohesive(np.zeros(3 * P.N), np.zeros((P.nq, 2)))
     assert spdiff(S.scipy(fg.FG_K), P.scipy(O.K_TANGENT)) < 1e-12
-    npairs, nblk, nsl = S.sizes()
+    npairs, nblk, nsl, nhalo = S.sizes()
     assert npairs == P.csr(O.A22)[1].size
 
 
@@ -99,6 +99,17 @@ def test_products(name):
         assert relerr(y, yo) < 1e-13, which
     assert relerr(host(S.coupling(dev(p))), P.apply_Apu(p)) < 1e-13
     assert relerr(host(S.coupling(dev(u), transpose=True)), P.apply_Aup(u)) < 1e-13
+    # the global-gather path (halos not staged in LDS) gives the same products
+    S.tune("halo_cap", 0)
+    try:
+        for which, x in ((fg.FG_K, u), (fg.FG_A22, p)):
+            y0 = host(S.spmv(which, dev(x)))
+            S.tune("halo_cap", 1 << 20)
+            y1 = host(S.spmv(which, dev(x)))
+            S.tune("halo_cap", 0)
+            assert relerr(y0, y1) < 1e-14
+    finally:
+        S.tune("halo_cap", 1 << 20)
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -145,6 +156,21 @@ def test_pcg_k_and_a22(name):
     xp, info = S.pcg_solve(fg.FG_A22, dev(bp), tol=1e-13)
     xpo, st, it, rr = P.pcg(O.A22, bp, tol=1e-13)
     assert relerr(host(xp), xpo) < 1e-9
+
+
+def test_pcg_global_gather_path_matches():
+    fg, O = _fg(), _oracle()
+    inst, ctx, S, P = setup("cube16_dip70")
+    S.cohesive_update(dev(np.zeros(3 * S.N)), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)))
+    b = np.random.default_rng(7).standard_normal(3 * S.N) * (1 - inst.dir_u)
+    x1, i1 = S.pcg_solve(fg.FG_K, dev(b), tol=1e-12)
+    S.tune("halo_cap", 0)
+    try:
+        x0, i0 = S.pcg_solve(fg.FG_K, dev(b), tol=1e-12)
+    finally:
+        S.tune("halo_cap", 1 << 20)
+    assert i0.status == 0 and i1.status == 0
+    assert relerr(host(x0), host(x1)) < 1e-10
 
 
 def test_pcg_mixed_and_f32():
