@@ -232,12 +232,15 @@ fg_status fg_export(fg_ctx *ctx, fg_system *sys, int which, int32_t *rows_h, int
  *   "halo_cap": largest per-slice halo whose x is staged in LDS; slices with a
  *               larger halo gather x from global memory (0 = never stage).
  *               Clipped to what 64 KB of LDS per 4-wavefront workgroup holds.
+ *   "graphs":   1 (default) replays each batch of CG iterations as a captured
+ *               HIP graph, 0 launches the kernels one by one (same results).
  * Returns FG_ERR_ARG for an unknown key or a negative value. */
 fg_status fg_tune(fg_system *sys, const char *key, int64_t value);
 
 /* Live timing of the CG product kernel (the hot loop's dominant kernel).
- * enable != 0: every CG iteration records a HIP event on the solve's stream
- * before and after its SpMV launch; durations are summed per operator slot:
+ * enable != 0: CG iterations launch kernel by kernel (no graph replay) and
+ * record a timing-only HIP event (no system-scope fence) on the solve's stream
+ * before and after each SpMV launch; durations are summed per operator slot:
  * 0 = K in FP64, 1 = K in FP32, 2 = A22.  fg_profile_read returns the number of
  * timed launches and their total milliseconds for `slot`, and clears the slot
  * when reset != 0. */

@@ -343,7 +343,10 @@ fg_status fg_system_destroy(fg_system *S)
                     S->du, S->fc, S->s1, S->s2, S->s3, S->s4, S->s5, S->s6, S->s7, S->s8, S->pi, S->pi0, S->qi,
                     S->rf, S->dpv, S->die0, S->partials, S->sc, S->red, S->red_counter};
     for (void *p : ptrs) dfree(p);
-    for (hipEvent_t ev : S->prof_ev) hipEventDestroy(ev);
+    drop_graphs(S);
+    if (S->cap_stream) hipStreamDestroy(S->cap_stream);
+    for (auto &pool : S->prof_ev)
+        for (hipEvent_t ev : pool) hipEventDestroy(ev);
     if (S->sc_host) hipHostFree(S->sc_host);
     if (S->red_host) hipHostFree(S->red_host);
     delete S;
@@ -438,6 +441,11 @@ fg_status fg_system_create(fg_ctx *ctx, const fg_mesh *mesh, fg_system **out)
     CK(dalloc(&S->red_counter, 4));
     hipMemset(S->red_counter, 0, 4 * sizeof(uint32_t));
     hipMemset(S->sc, 0, sizeof(CgScalars));
+    if (hipStreamCreateWithFlags(&S->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        set_error("stream creation failed");
+        fg_system_destroy(S);
+        return FG_ERR_HIP;
+    }
     if (hipHostMalloc((void **)&S->sc_host, sizeof(CgScalars)) != hipSuccess ||
         hipHostMalloc((void **)&S->red_host, 8 * sizeof(double)) != hipSuccess) {
         set_error("pinned host allocation failed");
@@ -773,8 +781,15 @@ fg_status fg_tune(fg_system *S, const char *key, int64_t value)
         set_error("fg_tune: bad argument");
         return FG_ERR_ARG;
     }
+    Guard g(S->device);
     if (std::strcmp(key, "halo_cap") == 0) {
         S->halo_cap = (int)std::min<int64_t>(value, 65536 / (4 * 3 * (int64_t)sizeof(double)));
+        drop_graphs(S);
+        return FG_OK;
+    }
+    if (std::strcmp(key, "graphs") == 0) {
+        S->use_graphs = value != 0;
+        drop_graphs(S);
         return FG_OK;
     }
     set_error(std::string("fg_tune: unknown key ") + key);

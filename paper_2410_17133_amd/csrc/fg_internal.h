@@ -61,6 +61,11 @@ struct CgScalars {
 
 void set_error(const std::string &msg);
 
+struct GraphCache {
+    hipGraphExec_t exec = nullptr;
+    int iters = 0;
+};
+
 }  // namespace fg
 
 // Opaque objects of the C-ABI.
@@ -124,9 +129,13 @@ struct fg_system {
     double *red = nullptr;            // device reduction results [8]
     double *red_host = nullptr;       // pinned [8]
     uint32_t *red_counter = nullptr;
+    // captured CG batches per operator slot: K FP64, K FP32, A22
+    bool use_graphs = true;
+    hipStream_t cap_stream = nullptr;
+    fg::GraphCache cg_graph[3];
     // live kernel timing (fg_profile)
     bool prof = false;
-    std::vector<hipEvent_t> prof_ev;  // pairs (start, stop), one per pending launch
+    std::vector<hipEvent_t> prof_ev[3];  // per operator slot: pairs (start, stop), one per launch of a batch
     int prof_pending = 0;
     int prof_slot = 0;
     int64_t prof_count[3] = {0, 0, 0};

@@ -51,4 +51,7 @@ void add_f32(int64_t n, double s, const float *x, double *y, hipStream_t st);
 
 fg_status check_hip(const char *where);
 
+// Destroy the captured CG batches (after a change of launch parameters).
+void drop_graphs(fg_system *S);
+
 }  // namespace fg

@@ -9,6 +9,7 @@
 // the same slots with one value each.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 
@@ -49,10 +50,12 @@ __device__ __forceinline__ void block_partials(const double (&v)[NV], double *pa
 }
 
 // Sum of nparts partials per value, in a fixed order; result valid in every thread.
+constexpr int FIN = 1024;  // threads of the one-block finalize kernels
+
 template <int NV>
 __device__ __forceinline__ void finalize_sum(const double *partials, int64_t stride, int64_t nparts, double (&tot)[NV])
 {
-    __shared__ double sh[NV][WG / 64];
+    __shared__ double sh[NV][FIN / 64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int k = 0; k < NV; ++k) {
         double s = 0;
@@ -631,7 +634,7 @@ __global__ void k_dots(int64_t n, DotArgs args, double *partials, int64_t stride
 }
 
 template <int ND>
-__global__ void k_dots_fin(const double *partials, int64_t stride, int64_t nparts, double *res)
+__global__ __launch_bounds__(FIN) void k_dots_fin(const double *partials, int64_t stride, int64_t nparts, double *res)
 {
     double tot[ND];
     finalize_sum<ND>(partials, stride, nparts, tot);
@@ -777,7 +780,7 @@ __global__ __launch_bounds__(WG) void k_cg_init(int64_t n, const T *__restrict__
     block_partials<2>(v, partials, stride);
 }
 
-__global__ __launch_bounds__(WG) void k_cg_init_fin(const double *partials, int64_t stride, int64_t nparts,
+__global__ __launch_bounds__(FIN) void k_cg_init_fin(const double *partials, int64_t stride, int64_t nparts,
                                                     CgScalars *sc, double tol)
 {
     double tot[2];
@@ -820,7 +823,7 @@ __global__ __launch_bounds__(WG) void k_cg_spmv(SpmvArgs a, const TV *__restrict
     block_partials<1>(v, partials, stride);
 }
 
-__global__ __launch_bounds__(WG) void k_cg_alpha(const double *partials, int64_t stride, int64_t nparts, CgScalars *sc)
+__global__ __launch_bounds__(FIN) void k_cg_alpha(const double *partials, int64_t stride, int64_t nparts, CgScalars *sc)
 {
     if (sc->done) return;
     double tot[1];
@@ -859,7 +862,7 @@ __global__ __launch_bounds__(WG) void k_cg_update(int64_t n, const T *__restrict
     block_partials<2>(v, partials, stride);
 }
 
-__global__ __launch_bounds__(WG) void k_cg_beta(const double *partials, int64_t stride, int64_t nparts, CgScalars *sc)
+__global__ __launch_bounds__(FIN) void k_cg_beta(const double *partials, int64_t stride, int64_t nparts, CgScalars *sc)
 {
     if (sc->done) return;
     double tot[2];
@@ -965,19 +968,19 @@ void vdots(fg_system *S, int64_t n, int nd, const double *const *a, const double
     switch (nd) {
     case 1:
         LAUNCH(k_dots<1>, g, WG, st, n, args, S->partials, S->npartials);
-        LAUNCH(k_dots_fin<1>, 1, WG, st, S->partials, S->npartials, g, S->red);
+        LAUNCH(k_dots_fin<1>, 1, FIN, st, S->partials, S->npartials, g, S->red);
         break;
     case 2:
         LAUNCH(k_dots<2>, g, WG, st, n, args, S->partials, S->npartials);
-        LAUNCH(k_dots_fin<2>, 1, WG, st, S->partials, S->npartials, g, S->red);
+        LAUNCH(k_dots_fin<2>, 1, FIN, st, S->partials, S->npartials, g, S->red);
         break;
     case 3:
         LAUNCH(k_dots<3>, g, WG, st, n, args, S->partials, S->npartials);
-        LAUNCH(k_dots_fin<3>, 1, WG, st, S->partials, S->npartials, g, S->red);
+        LAUNCH(k_dots_fin<3>, 1, FIN, st, S->partials, S->npartials, g, S->red);
         break;
     default:
         LAUNCH(k_dots<4>, g, WG, st, n, args, S->partials, S->npartials);
-        LAUNCH(k_dots_fin<4>, 1, WG, st, S->partials, S->npartials, g, S->red);
+        LAUNCH(k_dots_fin<4>, 1, FIN, st, S->partials, S->npartials, g, S->red);
         break;
     }
     hipMemcpyAsync(S->red_host, S->red, nd * sizeof(double), hipMemcpyDeviceToHost, st);
@@ -1094,45 +1097,98 @@ void spmv_k32(fg_system *S, const float *x, float *y, hipStream_t st)
     LAUNCH_SH((k_spmv<3, float, float>), g, WG, (spmv_lds<3, float>(S)), st, spmv_args(S), S->K32, x, y);
 }
 
-// Sum the durations of the timed launches of the last batch (stream already synchronised).
-static void prof_collect(fg_system *S)
+// Sum the durations of the timed launches of the last batch (stream already
+// synchronised); only the first `worked` launches ran a real iteration, the
+// rest returned at once because the solve had stopped.
+static void prof_collect(fg_system *S, int64_t worked)
 {
-    for (int i = 0; i < S->prof_pending; ++i) {
+    const int n = (int)std::min<int64_t>(S->prof_pending, std::max<int64_t>(worked, 0));
+    const std::vector<hipEvent_t> &ev = S->prof_ev[S->prof_slot];
+    for (int i = 0; i < n; ++i) {
         float ms = 0;
-        if (hipEventElapsedTime(&ms, S->prof_ev[2 * i], S->prof_ev[2 * i + 1]) == hipSuccess) {
+        if (hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]) == hipSuccess) {
             S->prof_ms[S->prof_slot] += ms;
             S->prof_count[S->prof_slot] += 1;
+        } else {
+            hipGetLastError();  // an untimed launch is not an error of the solve
         }
     }
     S->prof_pending = 0;
 }
 
 template <int BS, typename T, typename TV>
-static void cg_batch(fg_system *S, const TV *val, const T *dinv, T *x, T *r, T *p, T *q, int iters, int slot,
-                     hipStream_t st)
+static void cg_launch_batch(fg_system *S, const TV *val, const T *dinv, T *x, T *r, T *p, T *q, int iters, int slot,
+                            bool prof, hipStream_t st)
 {
+    const std::vector<hipEvent_t> &ev = S->prof_ev[slot];
     const int64_t n = BS * S->Npad;
     const int64_t gs = grid_xcd((S->nslices + 3) / 4), ge = grid_elems(n);
-    if (S->prof) {
-        while ((int)S->prof_ev.size() < 2 * iters) {
-            hipEvent_t e;
-            hipEventCreate(&e);
-            S->prof_ev.push_back(e);
-        }
-        S->prof_slot = slot;
-    }
     for (int it = 0; it < iters; ++it) {
-        if (S->prof) hipEventRecord(S->prof_ev[2 * it], st);
+        if (prof) hipEventRecord(ev[2 * it], st);
         LAUNCH_SH((k_cg_spmv<BS, T, TV>), gs, WG, (spmv_lds<BS, T>(S)), st, spmv_args(S), val, p, q, S->partials,
                   S->npartials, S->sc);
-        if (S->prof) {
-            hipEventRecord(S->prof_ev[2 * it + 1], st);
-            S->prof_pending = it + 1;
-        }
-        LAUNCH(k_cg_alpha, 1, WG, st, S->partials, S->npartials, gs, S->sc);
+        if (prof) hipEventRecord(ev[2 * it + 1], st);
+        LAUNCH(k_cg_alpha, 1, FIN, st, S->partials, S->npartials, gs, S->sc);
         LAUNCH((k_cg_update<T>), ge, WG, st, n, dinv, x, r, p, q, S->partials, S->npartials, S->sc);
-        LAUNCH(k_cg_beta, 1, WG, st, S->partials, S->npartials, ge, S->sc);
+        LAUNCH(k_cg_beta, 1, FIN, st, S->partials, S->npartials, ge, S->sc);
         LAUNCH((k_cg_pupdate<T>), ge, WG, st, n, dinv, r, p, S->sc);
+    }
+}
+
+// One batch of CG iterations.  With graphs enabled the batch is captured once
+// per (operator slot, batch length) on the system's capture stream and
+// replayed on `st`: every kernel argument is a fixed workspace pointer of the
+// system, so the graph stays valid until fg_tune changes a launch parameter or
+// the system is destroyed.  Timed batches (fg_profile) launch kernel by kernel
+// with fence-free events on `st` around each SpMV: event records captured into
+// a graph are not ordered against the kernels between them.
+template <int BS, typename T, typename TV>
+static fg_status cg_batch(fg_system *S, const TV *val, const T *dinv, T *x, T *r, T *p, T *q, int iters, int slot,
+                          hipStream_t st)
+{
+    if (S->prof) {
+        std::vector<hipEvent_t> &ev = S->prof_ev[slot];
+        while ((int)ev.size() < 2 * iters) {
+            hipEvent_t e;
+            hipEventCreateWithFlags(&e, hipEventDisableSystemFence);  // no cache write-back around the kernel
+            ev.push_back(e);
+        }
+        S->prof_slot = slot;
+        S->prof_pending = iters;
+        cg_launch_batch<BS, T, TV>(S, val, dinv, x, r, p, q, iters, slot, true, st);
+        return check_hip("cg batch");
+    }
+    if (!S->use_graphs) {
+        cg_launch_batch<BS, T, TV>(S, val, dinv, x, r, p, q, iters, slot, false, st);
+        return check_hip("cg batch");
+    }
+    GraphCache &g = S->cg_graph[slot];
+    if (!g.exec || g.iters != iters) {
+        if (g.exec) hipGraphExecDestroy(g.exec);
+        g.exec = nullptr;
+        hipGraph_t graph = nullptr;
+        if (hipStreamBeginCapture(S->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return check_hip("cg graph capture");
+        cg_launch_batch<BS, T, TV>(S, val, dinv, x, r, p, q, iters, slot, false, S->cap_stream);
+        if (hipStreamEndCapture(S->cap_stream, &graph) != hipSuccess) return check_hip("cg graph capture end");
+        hipError_t e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            g.exec = nullptr;
+            return check_hip("cg graph instantiate");
+        }
+        g.iters = iters;
+    }
+    hipGraphLaunch(g.exec, st);
+    return check_hip("cg graph launch");
+}
+
+void drop_graphs(fg_system *S)
+{
+    for (GraphCache &g : S->cg_graph) {
+        if (g.exec) hipGraphExecDestroy(g.exec);
+        g.exec = nullptr;
+        g.iters = 0;
     }
 }
 
@@ -1153,23 +1209,27 @@ fg_status cg_run(fg_system *S, int which, int precision, double tol, int64_t max
     } else {
         LAUNCH((k_cg_init<double>), grid_elems(n), WG, st, n, S->dinvA, S->wx, S->wr, S->wp, S->partials, S->npartials);
     }
-    LAUNCH(k_cg_init_fin, 1, WG, st, S->partials, S->npartials, grid_elems(n), S->sc, tol);
+    LAUNCH(k_cg_init_fin, 1, FIN, st, S->partials, S->npartials, grid_elems(n), S->sc, tol);
     fg_status e = check_hip("cg init");
     if (e) return e;
     const int batch = check_every > 0 ? check_every : 32;
+    int64_t iter0 = 0;
+    S->prof_pending = 0;
     for (;;) {
         hipMemcpyAsync(S->sc_host, S->sc, sizeof(CgScalars), hipMemcpyDeviceToHost, st);
         hipStreamSynchronize(st);
         e = check_hip("cg poll");
         if (e) return e;
-        if (S->prof_pending) prof_collect(S);
+        if (S->prof_pending) prof_collect(S, S->sc_host->iter - iter0);
         if (S->sc_host->done) break;
+        iter0 = S->sc_host->iter;
         if (f32)
-            cg_batch<3, float, float>(S, S->K32, S->dinvK32, S->fx, S->fr, S->fp, S->fq, batch, 1, st);
+            e = cg_batch<3, float, float>(S, S->K32, S->dinvK32, S->fx, S->fr, S->fp, S->fq, batch, 1, st);
         else if (which == FG_K)
-            cg_batch<3, double, double>(S, S->K, S->dinvK, S->wx, S->wr, S->wp, S->wq, batch, 0, st);
+            e = cg_batch<3, double, double>(S, S->K, S->dinvK, S->wx, S->wr, S->wp, S->wq, batch, 0, st);
         else
-            cg_batch<1, double, double>(S, S->A22, S->dinvA, S->wx, S->wr, S->wp, S->wq, batch, 2, st);
+            e = cg_batch<1, double, double>(S, S->A22, S->dinvA, S->wx, S->wr, S->wp, S->wq, batch, 2, st);
+        if (e) return e;
     }
     const CgScalars &h = *S->sc_host;
     *iters = h.iter;

@@ -173,6 +173,27 @@ def test_pcg_global_gather_path_matches():
     assert relerr(host(x0), host(x1)) < 1e-10
 
 
+def test_graph_replay_matches_eager_launches():
+    """CG batches replayed as captured graphs (many replays, host polls and eager
+    kernels in between) give bitwise the same iterates as kernel-by-kernel launches."""
+    fg, O = _fg(), _oracle()
+    inst, ctx, S, P = setup("cube12_dip60_hetero")
+    S.cohesive_update(dev(np.zeros(3 * S.N)), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)))
+    r = np.random.default_rng(8)
+    b = r.standard_normal(3 * S.N) * (1 - inst.dir_u)
+    bp = r.standard_normal(S.N)
+    out = {}
+    for g in (1, 0):
+        S.tune("graphs", g)
+        xk, ik = S.pcg_solve(fg.FG_K, dev(b), tol=1e-12, check_every=7)
+        xa, ia = S.pcg_solve(fg.FG_A22, dev(bp), tol=1e-12, check_every=5)
+        xm, im = S.pcg_solve(fg.FG_K, dev(b), tol=1e-9, precision=fg.FG_MIXED, check_every=9)
+        out[g] = (host(xk), ik.iters, host(xa), ia.iters, host(xm), im.iters)
+    S.tune("graphs", 1)
+    for a, b_ in zip(out[0], out[1]):
+        np.testing.assert_array_equal(a, b_)
+
+
 def test_pcg_mixed_and_f32():
     fg, O = _fg(), _oracle()
     inst, ctx, S, P = setup("cube12_dip60_hetero")
