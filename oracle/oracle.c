@@ -54,8 +54,8 @@ typedef struct {
     or_csr Kb, Kt, A22, C;
     /* reference interface geometry per triangle */
     double *tri_A, *tri_n, *tri_t1, *tri_t2;
-    /* last tangent's qp states (for the adjoint's non-symmetric correction) */
-    double *qp_trac, *qp_ttr;
+    /* last interface update's qp states (for the adjoint's non-symmetric correction) */
+    double *qp_trac, *qp_ttr, *qp_tau;
     uint8_t *qp_flag;
 } or_problem;
 
@@ -513,6 +513,7 @@ or_problem *or_create(int64_t N, int64_t ne, int64_t nf, const double *xyz, cons
     int64_t nq = 3 * (nf ? nf : 1);
     P->qp_trac = calloc(nq * 3, sizeof(double));
     P->qp_ttr = calloc(nq, sizeof(double));
+    P->qp_tau = calloc(nq * 3, sizeof(double));
     P->qp_flag = calloc(nq, 1);
     return P;
 }
@@ -537,6 +538,7 @@ void or_free(or_problem *P)
     free(P->tri_t2);
     free(P->qp_trac);
     free(P->qp_ttr);
+    free(P->qp_tau);
     free(P->qp_flag);
     free(P);
 }
@@ -596,6 +598,17 @@ void or_cohesive(or_problem *P, const double *U, const double *die_n, const doub
             double nt = or_return_map(d, die_n + 2 * iq, t0 + 3 * iq, kn, ks, f, trac + 3 * iq, die + 2 * iq, flag + iq, Dl);
             P->qp_ttr[iq] = nt;
             P->qp_flag[iq] = flag[iq];
+            {
+                /* slip direction in global coordinates (from the trial traction) */
+                double a = 1.0, b = 0.0;
+                if (nt > 0) {
+                    double tt1 = ks * (t0[3 * iq + 1] / ks + d[1] - die_n[2 * iq]);
+                    double tt2 = ks * (t0[3 * iq + 2] / ks + d[2] - die_n[2 * iq + 1]);
+                    a = tt1 / nt;
+                    b = tt2 / nt;
+                }
+                for (int r = 0; r < 3; ++r) P->qp_tau[3 * iq + r] = a * t1[r] + b * t2[r];
+            }
             memcpy(P->qp_trac + 3 * iq, trac + 3 * iq, 3 * sizeof(double));
             const double *tr = trac + 3 * iq, *tz = t0 + 3 * iq;
             double T[3];
@@ -1001,4 +1014,137 @@ int or_num_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* ------------------------------------------------------------------ */
+/* adjoint                                                             */
+/* ------------------------------------------------------------------ */
+/* y = N^T x, N the part of the exact interface tangent that the symmetric
+ * Newton tangent omits: at slip points in contact the shear traction
+ * f t'_n tau changes with the normal opening, d t_s / d delta_n = -f k_n tau,
+ * i.e. D_exact = D_sym + (-f k_n) tau (x) n.  Uses the points' states of the
+ * last or_cohesive call.  Held displacement DOFs are masked on both sides. */
+void or_apply_NT(or_problem *P, const double *x_in, double *y)
+{
+    int64_t N = P->N;
+    memset(y, 0, 3 * N * sizeof(double));
+    const double kn = P->p.k_n, f = P->p.friction;
+    for (int64_t t = 0; t < P->nf; ++t) {
+        const int32_t *nd = P->coh + 6 * t;
+        const double *n = P->tri_n + 3 * t;
+        double w = P->tri_A[t] / 3.0;
+        for (int q = 0; q < 3; ++q) {
+            int64_t iq = 3 * t + q;
+            if (P->qp_flag[iq] != OR_SLIP) continue;
+            const double *tau = P->qp_tau + 3 * iq;
+            /* opening of x at the point, then D_ns^T jump = (-f k_n) n (tau . jump) */
+            double jump[3] = {0, 0, 0};
+            for (int a = 0; a < 3; ++a)
+                for (int r = 0; r < 3; ++r) {
+                    int64_t ip = 3 * (int64_t)nd[a] + r, im = 3 * (int64_t)nd[3 + a] + r;
+                    double xp = P->dir_u[ip] ? 0.0 : x_in[ip], xm = P->dir_u[im] ? 0.0 : x_in[im];
+                    jump[r] += QP_N[q][a] * (xp - xm);
+                }
+            double s = -f * kn * dot3(tau, jump);
+            for (int a = 0; a < 3; ++a)
+                for (int r = 0; r < 3; ++r) {
+                    y[3 * (int64_t)nd[a] + r] += w * QP_N[q][a] * s * n[r];
+                    y[3 * (int64_t)nd[3 + a] + r] -= w * QP_N[q][a] * s * n[r];
+                }
+        }
+    }
+    for (int64_t i = 0; i < 3 * N; ++i)
+        if (P->dir_u[i]) y[i] = 0;
+}
+
+/* Adjoint of one converged step (the transposed Newton system, Sec. 3.3.1):
+ *   [K_exact^T  A_pu ] [lam_u]   [g_u]
+ *   [-A_up      A22  ] [lam_p] = [g_p]
+ * With mu = -lam_u this is [[K_exact^T, -A_pu],[A_up, A22]] [mu; lam_p] = [-g_u; g_p],
+ * the forward block structure; K_exact^T = K_sym + N^T is handled by defect
+ * correction around the partitioned CG: solve with K_sym and the right-hand side
+ * -g_u - N^T mu^k until mu stops changing.  Requires or_cohesive at the converged
+ * state (tangent and point states).  stats: [defect its, outer its, K its, A22 its,
+ * last relative change of mu, status]. */
+int or_adjoint(or_problem *P, const double *g_u, const double *g_p, double *lam_u, double *lam_p, double tol_defect,
+               int64_t max_defect, double tol_outer, double tol_inner, int64_t maxit_outer, int64_t maxit_inner,
+               double *stats)
+{
+    int64_t n1 = 3 * P->N, n2 = P->N;
+    double *mu = calloc(n1, sizeof(double)), *mu_new = calloc(n1, sizeof(double)), *b1 = calloc(n1, sizeof(double));
+    double *b2 = calloc(n2, sizeof(double)), *ntm = calloc(n1, sizeof(double));
+    for (int64_t i = 0; i < n2; ++i) b2[i] = P->dir_p[i] ? 0.0 : g_p[i];
+    int status = 1;
+    double change = 0, st[5], tot[3] = {0, 0, 0};
+    int64_t k = 0;
+    for (; k < max_defect; ++k) {
+        or_apply_NT(P, mu, ntm);
+        for (int64_t i = 0; i < n1; ++i) b1[i] = P->dir_u[i] ? 0.0 : -g_u[i] - ntm[i];
+        int s = or_prevost(P, b1, b2, mu_new, lam_p, tol_outer, tol_inner, maxit_outer, maxit_inner, st);
+        tot[0] += st[0];
+        tot[1] += st[1];
+        tot[2] += st[2];
+        if (s < 0) {
+            status = s;
+            break;
+        }
+        double dn = 0, mn = 0;
+        for (int64_t i = 0; i < n1; ++i) {
+            dn += (mu_new[i] - mu[i]) * (mu_new[i] - mu[i]);
+            mn += mu_new[i] * mu_new[i];
+        }
+        change = mn > 0 ? sqrt(dn / mn) : sqrt(dn);
+        memcpy(mu, mu_new, n1 * sizeof(double));
+        if (change <= tol_defect) {
+            status = 0;
+            k++;
+            break;
+        }
+    }
+    for (int64_t i = 0; i < n1; ++i) lam_u[i] = -mu[i];
+    stats[0] = (double)k;
+    stats[1] = tot[0];
+    stats[2] = tot[1];
+    stats[3] = tot[2];
+    stats[4] = change;
+    stats[5] = (double)status;
+    free(mu);
+    free(mu_new);
+    free(b1);
+    free(b2);
+    free(ntm);
+    return status;
+}
+
+/* Parameter sensitivities dJ/dtheta = -lam^T dR/dtheta at the converged state:
+ *   dR_m/dE_e   = (K_e / E_e) U_e              (bulk stiffness is linear in E)
+ *   dR_f/dlnk_e = dt C_e P_e                   (conductivity is linear in k = e^{ln k})
+ * with held DOFs of lam, U and P taken as zero. */
+void or_sensitivity(or_problem *P, const double *U, const double *Pp, const double *lam_u, const double *lam_p,
+                    double *dJ_dE, double *dJ_dlogk)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < P->ne; ++e) {
+        double X[12], Ke[144], Se[16], Ce[16], ue[12], le[12], pe[4], qe[4];
+        tet_coords(P, e, X);
+        or_tet_stiffness(X, 1.0, P->p.nu, Ke);
+        or_tet_flow(X, exp(P->logk[e]) / P->p.mu, 1.0 / P->p.biot_M, Se, Ce);
+        const int32_t *nd = P->tets + 4 * e;
+        for (int a = 0; a < 4; ++a) {
+            for (int r = 0; r < 3; ++r) {
+                int64_t i = 3 * (int64_t)nd[a] + r;
+                ue[3 * a + r] = P->dir_u[i] ? 0.0 : U[i];
+                le[3 * a + r] = P->dir_u[i] ? 0.0 : lam_u[i];
+            }
+            pe[a] = P->dir_p[nd[a]] ? 0.0 : Pp[nd[a]];
+            qe[a] = P->dir_p[nd[a]] ? 0.0 : lam_p[nd[a]];
+        }
+        double sE = 0, sk = 0;
+        for (int r = 0; r < 12; ++r)
+            for (int c = 0; c < 12; ++c) sE += le[r] * Ke[12 * r + c] * ue[c];
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) sk += qe[a] * Ce[4 * a + b] * pe[b];
+        dJ_dE[e] = -sE;
+        dJ_dlogk[e] = -P->p.dt * sk;
+    }
 }

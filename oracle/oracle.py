@@ -69,6 +69,11 @@ def lib():
         L.or_tri_flow.argtypes = [_f64p, _f64p, _f64p, _f64p]
         L.or_return_map.restype = C.c_double
         L.or_return_map.argtypes = [_f64p, _f64p, _f64p, C.c_double, C.c_double, C.c_double, _f64p, _f64p, _u8p, _f64p]
+        L.or_apply_NT.argtypes = [C.c_void_p, _f64p, _f64p]
+        L.or_adjoint.restype = C.c_int
+        L.or_adjoint.argtypes = [C.c_void_p, _f64p, _f64p, _f64p, _f64p, C.c_double, C.c_int64, C.c_double,
+                                 C.c_double, C.c_int64, C.c_int64, _f64p]
+        L.or_sensitivity.argtypes = [C.c_void_p, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p]
         L.or_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -220,6 +225,36 @@ class Problem:
                           tol_inner, maxit_outer, maxit_inner, info)
         die.reshape(-1)[:] = dieb[: self.nq * 2]
         return trac.reshape(-1, 3)[: self.nq], flag[: self.nq], info, s
+
+
+def _adjoint_methods():
+    def apply_NT(self, x):
+        """N^T x: transpose of the slip-tangent part the symmetric Newton tangent omits (last cohesive call)."""
+        y = np.zeros(3 * self.N)
+        lib().or_apply_NT(self._h, _c(x, np.float64), y)
+        return y
+
+    def adjoint(self, g_u, g_p, tol_defect=1e-12, max_defect=50, tol_outer=1e-12, tol_inner=1e-13,
+                maxit_outer=1000, maxit_inner=500000):
+        """(lam_u, lam_p, status, stats) of the transposed Newton system at the state of the last cohesive call."""
+        lu, lp, st = np.zeros(3 * self.N), np.zeros(self.N), np.zeros(6)
+        s = lib().or_adjoint(self._h, _c(g_u, np.float64), _c(g_p, np.float64), lu, lp, tol_defect, max_defect,
+                             tol_outer, tol_inner, maxit_outer, maxit_inner, st)
+        return lu, lp, s, st
+
+    def sensitivity(self, U, P, lam_u, lam_p):
+        """(dJ/dE, dJ/dlnk) per tetrahedron."""
+        ne = self.inst.mesh.tets.shape[0]
+        dE, dk = np.zeros(ne), np.zeros(ne)
+        lib().or_sensitivity(self._h, *[_c(a, np.float64) for a in (U, P, lam_u, lam_p)], dE, dk)
+        return dE, dk
+
+    Problem.apply_NT = apply_NT
+    Problem.adjoint = adjoint
+    Problem.sensitivity = sensitivity
+
+
+_adjoint_methods()
 
 
 def num_threads() -> int:
