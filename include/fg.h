@@ -109,7 +109,7 @@ typedef struct {
 
 /* Statistics of a partitioned solve or a step. */
 typedef struct {
-    int64_t newton_iters, outer_iters, inner_k_iters, inner_a22_iters;
+    int64_t newton_iters, outer_iters, inner_k_iters, inner_a22_iters;  /* newton_iters: defect iterations for the adjoint */
     double outer_relres;  /* last Prevost ||r||/||r0|| */
     double res_m, res_f;  /* scaled Newton residual norms at exit (fg_step) */
     int status;
@@ -199,6 +199,30 @@ fg_status fg_step(fg_ctx *ctx, fg_system *sys, double *U, double *P, double *die
                   const double *t0, const double *F_u, const double *f_p, double newton_tol,
                   int64_t newton_max_iter, const fg_pcg_opts *inner_k, const fg_pcg_opts *inner_p,
                   double outer_tol, int64_t outer_max_iter, fg_solve_info *info_h, void *stream);
+
+/* Adjoint of one converged implicit step and the gradient of an objective J(U, P)
+ * with respect to the per-tetrahedron Young modulus and log-permeability.  The
+ * step's residual R(U, P; E, ln k) = 0 (fg_step) gives dJ/dtheta = -lambda^T dR/dtheta
+ * with the multipliers of the transposed Newton Jacobian (Sec. 3.3.1):
+ *   [ K_exact^T   A_pu ] [lam_u]   [dJ/dU]
+ *   [ -A_up       A22  ] [lam_p] = [dJ/dP]
+ * solved as the forward partitioned CG (Sec. 3.3.2) on mu = -lam_u, with the slip
+ * part of the exact interface tangent, N = sum w N_a N_b (-f k_n tau (x) n), moved to
+ * the right-hand side and iterated (defect correction) until ||mu_k+1 - mu_k|| <=
+ * defect_tol ||mu_k+1||.  Then dJ/dE_e = -lam_u^T (K_e/E_e) U_e and
+ * dJ/dln k_e = -dt lam_p^T C_e P_e.
+ *   U, P       converged state of fg_step (changes since t = 0), caller order
+ *   die_n, t0  the step's start-of-step inelastic slip and initial tractions
+ *   log_k      [n_tets] the log-permeability given to fg_assemble
+ *   dJdU, dJdP [3N], [N] objective gradient
+ * Out: dJ_dE, dJ_dlogk [n_tets] (caller order); lam_u [3N], lam_p [N] (may be NULL).
+ * Uses the operators of the last fg_assemble (it must be the step's assembly).
+ * Returns FG_NOT_CONVERGED when max_defect_iters is reached. */
+fg_status fg_adjoint_solve(fg_ctx *ctx, fg_system *sys, const double *U, const double *P, const double *die_n,
+                           const double *t0, const double *log_k, const double *dJdU, const double *dJdP,
+                           double *dJ_dE, double *dJ_dlogk, double *lam_u, double *lam_p,
+                           const fg_pcg_opts *inner_k, const fg_pcg_opts *inner_p, double outer_tol,
+                           double defect_tol, int64_t max_defect_iters, fg_solve_info *info_h, void *stream);
 
 /* Products on the assembled system, caller order: y = A x for which in
  * {FG_K, FG_A22, FG_KBULK, FG_C}. */

@@ -338,7 +338,7 @@ fg_status fg_system_destroy(fg_system *S)
     hipDeviceSynchronize();
     void *ptrs[] = {S->halo_ptr, S->halo, S->lcol, S->slice_ptr, S->col, S->rowlen, S->diag_slot, S->perm, S->xyz, S->tets, S->tet_orig, S->coh,
                     S->frows, S->fadj_ptr, S->fadj, S->dir_u, S->dir_p, S->tri_geo, S->K, S->K32, S->Kfb, S->A22,
-                    S->Cm, S->dinvK, S->dinvK32, S->dinvA, S->qpD, S->qpT, S->wx, S->wr, S->wp, S->wq, S->fx,
+                    S->Cm, S->dinvK, S->dinvK32, S->dinvA, S->qpD, S->qpT, S->qpNs, S->qpS, S->adj_trac, S->adj_die, S->adj_flag, S->wx, S->wr, S->wp, S->wq, S->fx,
                     S->fr, S->fp, S->fq, S->v1, S->v2, S->v3, S->v4, S->pv1, S->pv2, S->ui, S->ui0, S->fi, S->rm,
                     S->du, S->fc, S->s1, S->s2, S->s3, S->s4, S->s5, S->s6, S->s7, S->s8, S->pi, S->pi0, S->qi,
                     S->rf, S->dpv, S->die0, S->partials, S->sc, S->red, S->red_counter};
@@ -425,6 +425,11 @@ fg_status fg_system_create(fg_ctx *ctx, const fg_mesh *mesh, fg_system **out)
     CK(dalloc(&S->dinvA, n2));
     CK(dalloc(&S->qpD, 6 * S->nq));
     CK(dalloc(&S->qpT, 3 * S->nq));
+    CK(dalloc(&S->qpNs, 3 * S->nq));
+    CK(dalloc(&S->qpS, S->nq));
+    CK(dalloc(&S->adj_trac, 3 * S->nq));
+    CK(dalloc(&S->adj_die, 2 * S->nq));
+    CK(dalloc(&S->adj_flag, S->nq));
     double **d3[] = {&S->wx, &S->wr, &S->wp, &S->wq, &S->v1, &S->v2, &S->v3, &S->v4, &S->pv1, &S->pv2,
                      &S->ui, &S->ui0, &S->fi, &S->rm, &S->du, &S->fc};
     for (double **p : d3) CK(dalloc(p, n1));
@@ -691,6 +696,75 @@ fg_status fg_step(fg_ctx *ctx, fg_system *S, double *U, double *P, double *die, 
     si.status = status;
     if (info) *info = si;
     fg_status e = check_hip("fg_step");
+    return e ? e : status;
+}
+
+fg_status fg_adjoint_solve(fg_ctx *ctx, fg_system *S, const double *U, const double *P, const double *die_n,
+                           const double *t0, const double *log_k, const double *dJdU, const double *dJdP,
+                           double *dJ_dE, double *dJ_dlogk, double *lam_u, double *lam_p,
+                           const fg_pcg_opts *inner_k, const fg_pcg_opts *inner_p, double outer_tol,
+                           double defect_tol, int64_t max_defect_iters, fg_solve_info *info, void *stream)
+{
+    if (!ctx || !S || !U || !P || !log_k || !dJdU || !dJdP || !dJ_dE || !dJ_dlogk ||
+        (S->nq && (!die_n || !t0)) || !(outer_tol > 0) || !(defect_tol > 0)) {
+        set_error("fg_adjoint_solve: bad argument");
+        return FG_ERR_ARG;
+    }
+    if (!ready(S)) return FG_ERR_STATE;
+    Guard g(ctx->device);
+    hipStream_t st = S_(stream);
+    const int64_t n1 = 3 * S->Npad, n2 = S->Npad;
+    fg_pcg_opts ok = defaults(inner_k, 1e-12), op = defaults(inner_p, 1e-12);
+    fg_solve_info si{};
+    // interface state and symmetric tangent at the converged state
+    perm_in(S, 3, U, S->ui, st);
+    perm_in(S, 1, P, S->pi, st);
+    cohesive_qp(S, S->ui, die_n, t0, S->adj_trac, S->adj_die, S->adj_flag, st);
+    cohesive_rows(S, S->fc, 1, st);
+    // right-hand sides: b1 = -dJ/dU - N^T mu, b2 = dJ/dP (held DOFs zero)
+    perm_in(S, 3, dJdU, S->fi, st);
+    vmask(n1, S->dir_u, S->fi, st);
+    perm_in(S, 1, dJdP, S->qi, st);
+    vmask(n2, S->dir_p, S->qi, st);
+    double *mu = S->ui0, *mu_new = S->du, *b1 = S->rm, *lp = S->dpv, *ntm = S->pv2;
+    vfill(mu, 0.0, n1, st);
+    fg_status status = FG_NOT_CONVERGED;
+    double change = 0;
+    int64_t k = 0;
+    while (k < max_defect_iters) {
+        apply_NT(S, mu, ntm, st);
+        hipMemcpyAsync(b1, S->fi, n1 * sizeof(double), hipMemcpyDeviceToDevice, st);
+        vaxpby(n1, -1.0, ntm, -1.0, b1, st);  // b1 = -dJ/dU - N^T mu
+        fg_status s = prevost(S, b1, S->qi, mu_new, lp, ok, op, outer_tol, 1000, &si, st);
+        if (s < 0) {
+            status = s;
+            break;
+        }
+        ++k;
+        // relative change of mu, from the explicit difference (no cancellation)
+        vaxpby(n1, 1.0, mu_new, -1.0, mu, st);  // mu <- mu_new - mu
+        const double *A[2] = {mu, mu_new};
+        double dd[2];
+        vdots(S, n1, 2, A, A, dd, st);
+        change = dd[1] > 0 ? std::sqrt(dd[0] / dd[1]) : 0.0;
+        hipMemcpyAsync(mu, mu_new, n1 * sizeof(double), hipMemcpyDeviceToDevice, st);
+        if (change <= defect_tol) {
+            status = FG_OK;
+            break;
+        }
+    }
+    if (status >= 0) {
+        vaxpby(n1, 0.0, mu, -1.0, mu, st);  // lam_u = -mu
+        sensitivity(S, S->ui, S->pi, mu, lp, dJ_dE, dJ_dlogk, log_k, st);
+        if (lam_u) perm_out(S, 3, mu, lam_u, st);
+        if (lam_p) perm_out(S, 1, lp, lam_p, st);
+    }
+    hipStreamSynchronize(st);
+    si.newton_iters = k;
+    si.outer_relres = change;
+    si.status = status;
+    if (info) *info = si;
+    fg_status e = check_hip("fg_adjoint_solve");
     return e ? e : status;
 }
 

@@ -113,6 +113,10 @@ struct fg_system {
     // interface quadrature-point scratch
     double *qpD = nullptr;      // [nq*6] symmetric global tangent
     double *qpT = nullptr;      // [nq*3] T - T0
+    double *qpNs = nullptr;     // [nq*3] -f k_n tau at slip points, else 0 (adjoint)
+    double *qpS = nullptr;      // [nq] scratch of the N^T product
+    double *adj_trac = nullptr, *adj_die = nullptr;  // [nq*3], [nq*2] scratch of the adjoint's interface update
+    uint8_t *adj_flag = nullptr;                      // [nq]
     // solver workspaces (internal order)
     double *wx = nullptr, *wr = nullptr, *wp = nullptr, *wq = nullptr;  // [3*Npad]
     float *fx = nullptr, *fr = nullptr, *fp = nullptr, *fq = nullptr;   // [3*Npad]

@@ -20,6 +20,12 @@ void cohesive_qp(fg_system *S, const double *U_int, const double *die_n, const d
                  double *die, uint8_t *flag, hipStream_t st);
 void cohesive_rows(fg_system *S, double *fcoh_int, int write_tangent, hipStream_t st);
 
+// adjoint: y = N^T x (slip part of the exact interface tangent, last interface update)
+void apply_NT(fg_system *S, const double *x, double *y, hipStream_t st);
+// dJ/dE and dJ/dln k per tetrahedron (caller order) from the state and the multipliers
+void sensitivity(fg_system *S, const double *U, const double *P, const double *lu, const double *lp, double *dE,
+                 double *dlogk, const double *logk, hipStream_t st);
+
 // coupling products, internal order, masked on both sides
 void apply_Apu(fg_system *S, const double *p, double *out, hipStream_t st);
 void apply_Aup(fg_system *S, const double *u, double *out, hipStream_t st);

@@ -377,7 +377,7 @@ __device__ QpOut return_map(double dn, double ds1, double ds2, double die1, doub
 __global__ void k_cohesive_qp(int64_t nq, const int32_t *__restrict__ coh, const double *__restrict__ geo,
                               const double *__restrict__ U, const double *__restrict__ die_n,
                               const double *__restrict__ t0, double kn, double ks, double f, double *trac,
-                              double *die, uint8_t *flag, double *qpT, double *qpD)
+                              double *die, uint8_t *flag, double *qpT, double *qpD, double *qpNs)
 {
     int64_t iq = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (iq >= nq) return;
@@ -403,6 +403,17 @@ __global__ void k_cohesive_qp(int64_t nq, const int32_t *__restrict__ coh, const
     qpT[3 * iq] = fn * n.x + f1 * e1.x + f2 * e2.x;
     qpT[3 * iq + 1] = fn * n.y + f1 * e1.y + f2 * e2.y;
     qpT[3 * iq + 2] = fn * n.z + f1 * e1.z + f2 * e2.z;
+    // the part of the exact tangent the symmetric one omits: at slip points
+    // d t_s / d delta_n = -f k_n tau, stored as the vector -f k_n tau (global frame)
+    {
+        const double ttr1 = tz[1] + ks * (dt3(e1, jmp) - die_n[2 * iq]);
+        const double ttr2 = tz[2] + ks * (dt3(e2, jmp) - die_n[2 * iq + 1]);
+        const double tn_ = sqrt(ttr1 * ttr1 + ttr2 * ttr2);
+        const double c = (o.flag == SLIP && tn_ > 0.0) ? -f * kn / tn_ : 0.0;
+        qpNs[3 * iq] = c * (ttr1 * e1.x + ttr2 * e2.x);
+        qpNs[3 * iq + 1] = c * (ttr1 * e1.y + ttr2 * e2.y);
+        qpNs[3 * iq + 2] = c * (ttr1 * e1.z + ttr2 * e2.z);
+    }
     // global tangent Dn n n^T + sum S_ab t_a t_b^T, stored xx yy zz yz xz xy
     const double nn[3] = {n.x, n.y, n.z}, a1[3] = {e1.x, e1.y, e1.z}, a2[3] = {e2.x, e2.y, e2.z};
     const int I[6] = {0, 1, 2, 1, 0, 0}, J[6] = {0, 1, 2, 2, 2, 1};
@@ -505,6 +516,89 @@ __global__ void k_cohesive_tangent(int64_t nfr, int fw, const int32_t *__restric
                 if (dinvK32) dinvK32[3 * row + r] = (float)(1.0 / v);
             }
         }
+}
+
+// ----------------------------------------------------------------- adjoint
+// N^T x, step 1: per point s_q = (-f k_n tau) . [[x]](q) (zero away from slip points).
+__global__ void k_nt_qp(int64_t nq, const int32_t *__restrict__ coh, const double *__restrict__ qpNs,
+                        const double *__restrict__ x, const uint8_t *__restrict__ dir_u, double *qpS)
+{
+    int64_t iq = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (iq >= nq) return;
+    const int64_t t = iq / 3;
+    const int q = (int)(iq - 3 * t);
+    const int32_t *c = coh + 6 * t;
+    double s = 0;
+    for (int a = 0; a < 3; ++a)
+        for (int r = 0; r < 3; ++r) {
+            const int64_t ip = 3 * (int64_t)c[a] + r, im = 3 * (int64_t)c[3 + a] + r;
+            s += qpNs[3 * iq + r] * qpN(q, a) * ((dir_u[ip] ? 0.0 : x[ip]) - (dir_u[im] ? 0.0 : x[im]));
+        }
+    qpS[iq] = s;
+}
+
+// N^T x, step 2: per fault row, +-sum_q w N_a s_q n on the + / - lip.
+__global__ void k_nt_rows(int64_t nfr, const int32_t *__restrict__ frows, const int32_t *__restrict__ fadj_ptr,
+                          const int32_t *__restrict__ fadj, const double *__restrict__ geo,
+                          const double *__restrict__ qpS, const uint8_t *__restrict__ dir_u, double *y)
+{
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= nfr) return;
+    const int64_t row = frows[k];
+    double acc[3] = {0, 0, 0};
+    for (int m = fadj_ptr[k]; m < fadj_ptr[k + 1]; ++m) {
+        const int64_t t = fadj[m] / 6;
+        const int la = fadj[m] % 6, va = la % 3;
+        const double w = (la < 3 ? 1.0 : -1.0) * geo[10 * t] / 3.0;
+        double s = 0;
+        for (int q = 0; q < 3; ++q) s += w * qpN(q, va) * qpS[3 * t + q];
+        for (int r = 0; r < 3; ++r) acc[r] += s * geo[10 * t + 1 + r];
+    }
+    for (int r = 0; r < 3; ++r) y[3 * row + r] = dir_u[3 * row + r] ? 0.0 : acc[r];
+}
+
+// Parameter sensitivities per tetrahedron: dJ/dE_e = -lam_u^T (K_e/E_e) U_e, written as
+// -V [lam1 tr eps(U) tr eps(lam) + 2 G1 eps(U):eps(lam)] with the E = 1 Lame constants, and
+// dJ/dln k_e = -dt lam_p^T C_e P_e = -dt (k_e/mu) V grad(lam_p) . grad(P).
+__global__ void k_sensitivity(int64_t ne, const int32_t *__restrict__ tets, const int32_t *__restrict__ orig,
+                              const double *__restrict__ xyz, const double *__restrict__ logk, fg_params prm,
+                              const double *__restrict__ U, const double *__restrict__ P,
+                              const double *__restrict__ lu, const double *__restrict__ lp,
+                              const uint8_t *__restrict__ dir_u, const uint8_t *__restrict__ dir_p, double *dE,
+                              double *dlogk)
+{
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= ne) return;
+    const int32_t *nd = tets + 4 * t;
+    V3 g[4];
+    const double V = tet_grads(xyz, nd, g);
+    double eu[3][3] = {{0}}, el[3][3] = {{0}};
+    V3 gp = {0, 0, 0}, gl = {0, 0, 0};
+    for (int a = 0; a < 4; ++a) {
+        const int64_t o = 3 * (int64_t)nd[a];
+        double ua[3], la[3];
+        for (int r = 0; r < 3; ++r) {
+            ua[r] = dir_u[o + r] ? 0.0 : U[o + r];
+            la[r] = dir_u[o + r] ? 0.0 : lu[o + r];
+        }
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                eu[i][j] += 0.5 * (ua[i] * cmp(g[a], j) + ua[j] * cmp(g[a], i));
+                el[i][j] += 0.5 * (la[i] * cmp(g[a], j) + la[j] * cmp(g[a], i));
+            }
+        const double pa = dir_p[nd[a]] ? 0.0 : P[nd[a]];
+        const double qa = dir_p[nd[a]] ? 0.0 : lp[nd[a]];
+        gp = {gp.x + pa * g[a].x, gp.y + pa * g[a].y, gp.z + pa * g[a].z};
+        gl = {gl.x + qa * g[a].x, gl.y + qa * g[a].y, gl.z + qa * g[a].z};
+    }
+    const double nu = prm.nu;
+    const double lam1 = nu / ((1.0 + nu) * (1.0 - 2.0 * nu)), G1 = 1.0 / (2.0 * (1.0 + nu));
+    double tru = eu[0][0] + eu[1][1] + eu[2][2], trl = el[0][0] + el[1][1] + el[2][2], dd = 0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) dd += eu[i][j] * el[i][j];
+    const int64_t e = orig[t];
+    dE[e] = -V * (lam1 * tru * trl + 2.0 * G1 * dd);
+    dlogk[e] = -prm.dt * exp(logk[e]) / prm.mu * V * dt3(gl, gp);
 }
 
 // ----------------------------------------------------------------- coupling
@@ -1033,7 +1127,7 @@ void cohesive_qp(fg_system *S, const double *U_int, const double *die_n, const d
 {
     if (S->nq == 0) return;
     LAUNCH(k_cohesive_qp, (S->nq + WG - 1) / WG, WG, st, S->nq, S->coh, S->tri_geo, U_int, die_n, t0, S->prm.k_n,
-           S->prm.k_s, S->prm.friction, trac, die, flag, S->qpT, S->qpD);
+           S->prm.k_s, S->prm.friction, trac, die, flag, S->qpT, S->qpD, S->qpNs);
 }
 
 void cohesive_rows(fg_system *S, double *fcoh_int, int write_tangent, hipStream_t st)
@@ -1046,6 +1140,22 @@ void cohesive_rows(fg_system *S, double *fcoh_int, int write_tangent, hipStream_
         LAUNCH(k_cohesive_tangent, (S->nfr * S->fault_w + WG - 1) / WG, WG, st, S->nfr, S->fault_w, S->frows,
                S->fadj_ptr, S->fadj, S->coh, S->tri_geo, S->qpD, S->Kfb, S->slice_ptr, S->col, S->rowlen, S->dir_u,
                S->K, S->k32_valid ? S->K32 : nullptr, S->dinvK, S->k32_valid ? S->dinvK32 : nullptr);
+}
+
+void apply_NT(fg_system *S, const double *x, double *y, hipStream_t st)
+{
+    vfill(y, 0.0, 3 * S->Npad, st);
+    if (S->nq == 0) return;
+    LAUNCH(k_nt_qp, (S->nq + WG - 1) / WG, WG, st, S->nq, S->coh, S->qpNs, x, S->dir_u, S->qpS);
+    LAUNCH(k_nt_rows, (S->nfr + WG - 1) / WG, WG, st, S->nfr, S->frows, S->fadj_ptr, S->fadj, S->tri_geo, S->qpS,
+           S->dir_u, y);
+}
+
+void sensitivity(fg_system *S, const double *U, const double *P, const double *lu, const double *lp, double *dE,
+                 double *dlogk, const double *logk, hipStream_t st)
+{
+    LAUNCH(k_sensitivity, (S->ne + WG - 1) / WG, WG, st, S->ne, S->tets, S->tet_orig, S->xyz, logk, S->prm, U, P, lu,
+           lp, S->dir_u, S->dir_p, dE, dlogk);
 }
 
 void apply_Apu(fg_system *S, const double *p, double *out, hipStream_t st)

@@ -20,7 +20,7 @@ FG_F64, FG_F32, FG_MIXED = 0, 1, 2
 
 SYMBOLS = ["fg_last_error", "fg_ctx_create", "fg_ctx_destroy", "fg_system_create", "fg_system_destroy",
            "fg_assemble", "fg_cohesive_update", "fg_pcg_solve", "fg_flow_solve", "fg_step", "fg_spmv",
-           "fg_coupling", "fg_residual", "fg_system_sizes", "fg_export", "fg_profile", "fg_profile_read", "fg_tune"]
+           "fg_coupling", "fg_residual", "fg_system_sizes", "fg_export", "fg_profile", "fg_profile_read", "fg_tune", "fg_adjoint_solve"]
 
 
 class FgError(RuntimeError):
@@ -89,6 +89,8 @@ def lib():
             "fg_export": [vp, vp, i32, vp, vp, vp, vp],
             "fg_profile": [vp, i32],
             "fg_tune": [vp, C.c_char_p, i64],
+            "fg_adjoint_solve": [vp, vp] + [vp] * 11 + [C.POINTER(PcgOpts), C.POINTER(PcgOpts), dbl, dbl, i64,
+                                                        C.POINTER(SolveInfo), vp],
             "fg_profile_read": [vp, i32, C.POINTER(i64), C.POINTER(dbl), i32],
         }
         for name, args in sig.items():
@@ -231,6 +233,29 @@ class System:
                            C.byref(info), _stream())
         _check(st)
         return trac, flag, info
+
+    def adjoint(self, U, P, die_n, t0, logk, dJdU, dJdP, inner_k=None, inner_p=None, outer_tol=1e-12,
+                defect_tol=1e-12, max_defect_iters=50, multipliers=False):
+        """Gradient of J w.r.t. (E, ln k) at a converged step state: returns (dJ_dE, dJ_dlogk, info)
+        or, with multipliers=True, (dJ_dE, dJ_dlogk, lam_u, lam_p, info)."""
+        dE, dk = self._d(self.ne), self._d(self.ne)
+        lu = self._d(3 * self.N) if multipliers else None
+        lp = self._d(self.N) if multipliers else None
+        info = SolveInfo()
+        ik = inner_k or opts(tol=1e-13)
+        ip = inner_p or opts(tol=1e-13)
+        nq = self.nq
+        st = lib().fg_adjoint_solve(self.ctx._h, self._h, _ptr(U, torch.float64, 3 * self.N, "U"),
+                                    _ptr(P, torch.float64, self.N, "P"), _ptr(die_n, torch.float64, 2 * nq, "die_n"),
+                                    _ptr(t0, torch.float64, 3 * nq, "t0"), _ptr(logk, torch.float64, self.ne, "log_k"),
+                                    _ptr(dJdU, torch.float64, 3 * self.N, "dJdU"), _ptr(dJdP, torch.float64, self.N, "dJdP"),
+                                    _ptr(dE, torch.float64), _ptr(dk, torch.float64), _ptr(lu, torch.float64),
+                                    _ptr(lp, torch.float64), C.byref(ik), C.byref(ip), outer_tol, defect_tol,
+                                    max_defect_iters, C.byref(info), _stream())
+        _check(st)
+        if multipliers:
+            return dE, dk, lu, lp, info
+        return dE, dk, info
 
     def spmv(self, which, x):
         n = (3 if which in (FG_K, FG_KBULK) else 1) * self.N

@@ -1,0 +1,142 @@
+"""GPU adjoint (fg_adjoint_solve and the autograd.Function) against the oracle
+adjoint at the identical converged state, and against central finite
+differences of the GPU's own forward step."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from paper_2410_17133_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TIGHT = dict(tol_newton=1e-13, max_newton=80, tol_outer=1e-13, tol_inner=1e-14)
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def small_slip_instance():
+    return I.make_instance(dataclasses.replace(I.cube_config(4), Q=4e-3))
+
+
+def fault_normal(inst):
+    m = inst.mesh
+    X = m.xyz[m.coh[0, 3:]]
+    n = np.cross(X[1] - X[0], X[2] - X[0])
+    return n / np.linalg.norm(n)
+
+
+def objective_np(inst, U, uplift):
+    m = inst.mesh
+    n = fault_normal(inst)
+    U3 = U.reshape(-1, 3)
+    jump = U3[m.pairs[:, 1]] - U3[m.pairs[:, 0]]
+    slip = jump - np.outer(jump @ n, n)
+    g = np.zeros_like(U3)
+    np.add.at(g, m.pairs[:, 1], 2 * slip)
+    np.add.at(g, m.pairs[:, 0], -2 * slip)
+    g[uplift, 2] += 2 * U3[uplift, 2]
+    return np.sum(slip * slip) + np.sum(U3[uplift, 2] ** 2), g.reshape(-1)
+
+
+@pytest.mark.parametrize("case", ["small_slip", "config1"])
+def test_adjoint_matches_oracle_at_the_same_state(case):
+    from oracle import oracle as O
+    from paper_2410_17133_amd import fg
+    inst = small_slip_instance() if case == "small_slip" else I.make_instance(I.config(1))
+    print(f"[case] adjoint parity {case}", flush=True)
+    P = O.Problem(inst)
+    U, Pp, die = np.zeros(3 * P.N), np.zeros(P.N), np.zeros((P.nq, 2))
+    trac, flag, info, st = P.step(U, Pp, die, **TIGHT)
+    assert st == 0 and (flag == 1).sum() > 0
+    uplift = I.uplift_nodes(inst, 8)
+    J, gu = objective_np(inst, U, uplift)
+    gp = np.random.default_rng(1).standard_normal(P.N) * 1e-20   # exercise the pressure right-hand side too
+    P.cohesive(U, np.zeros((P.nq, 2)))
+    lu_o, lp_o, st, stats = P.adjoint(gu, gp)
+    assert st == 0
+    dE_o, dk_o = P.sensitivity(U, Pp, lu_o, lp_o)
+    ctx = fg.Context(0)
+    S = fg.System.from_instance(ctx, inst)
+    S.assemble(inst.params, inst.E, inst.logk)
+    dE, dk, lu, lp, ai = S.adjoint(dev(U), dev(Pp), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)), dev(inst.logk),
+                                   dev(gu), dev(gp), multipliers=True)
+    print(f"[adjoint] defect iterations gpu {ai.newton_iters} oracle {stats[0]:.0f}", flush=True)
+    assert ai.status == 0
+    assert rel(host(lu), lu_o) < 1e-9
+    assert rel(host(lp), lp_o) < 1e-9
+    assert rel(host(dE), dE_o) < 1e-9
+    assert rel(host(dk), dk_o) < 1e-9
+
+
+def _gpu_objective(S, inst, logk, E, uplift, solver=None):
+    from paper_2410_17133_amd.autograd import ImplicitStep, fault_slip_uplift_objective
+    U, P = ImplicitStep.apply(logk, E, S, inst.params, dev(inst.t0.reshape(-1)), dev(inst.load), dev(inst.source), solver)
+    m = inst.mesh
+    pairs = torch.as_tensor(m.pairs.astype(np.int64)).cuda()
+    return fault_slip_uplift_objective(U, pairs, dev(fault_normal(inst)), torch.as_tensor(uplift.astype(np.int64)).cuda())
+
+
+def test_autograd_gradient_matches_oracle_and_finite_differences():
+    from oracle import oracle as O
+    from paper_2410_17133_amd import fg
+    inst = small_slip_instance()
+    ctx = fg.Context(0)
+    S = fg.System.from_instance(ctx, inst)
+    uplift = I.uplift_nodes(inst, 8)
+    logk = dev(inst.logk).requires_grad_(True)
+    E = dev(inst.E).requires_grad_(True)
+    J = _gpu_objective(S, inst, logk, E, uplift)
+    J.backward()
+    gk, gE = host(logk.grad), host(E.grad)
+    # oracle gradient at its own converged state
+    P = O.Problem(inst)
+    U, Pp, die = np.zeros(3 * P.N), np.zeros(P.N), np.zeros((P.nq, 2))
+    P.step(U, Pp, die, **TIGHT)
+    Jo, gu = objective_np(inst, U, uplift)
+    P.cohesive(U, np.zeros((P.nq, 2)))
+    lu, lp, st, stats = P.adjoint(gu, np.zeros(P.N))
+    dE_o, dk_o = P.sensitivity(U, Pp, lu, lp)
+    assert abs(J.item() - Jo) <= 1e-9 * Jo
+    assert rel(gk, dk_o) < 1e-7 and rel(gE, dE_o) < 1e-7
+    # central differences of the GPU forward along seeded directions, step 1e-6 on (ln k, ln E)
+    ne = inst.E.size
+    eps = 1e-6
+    for d in I.fd_directions(2 * ne, count=3):
+        dlk, dlE = d[:ne], d[ne:]
+        with torch.no_grad():
+            Jp = _gpu_objective(S, inst, dev(inst.logk + eps * dlk), dev(inst.E * np.exp(eps * dlE)), uplift).item()
+            Jm = _gpu_objective(S, inst, dev(inst.logk - eps * dlk), dev(inst.E * np.exp(-eps * dlE)), uplift).item()
+        fd = (Jp - Jm) / (2 * eps)
+        ad = gk @ dlk + (gE * inst.E) @ dlE
+        print(f"[fd] fd {fd:.10e} adjoint {ad:.10e} rel {abs(fd - ad) / abs(ad):.2e}", flush=True)
+        assert abs(fd - ad) <= 1e-5 * abs(ad)
+
+
+def test_mixed_precision_adjoint_matches_fp64():
+    from paper_2410_17133_amd import fg
+    inst = small_slip_instance()
+    ctx = fg.Context(0)
+    S = fg.System.from_instance(ctx, inst)
+    uplift = I.uplift_nodes(inst, 8)
+    grads = {}
+    for prec in (fg.FG_F64, fg.FG_MIXED):
+        logk = dev(inst.logk).requires_grad_(True)
+        E = dev(inst.E).requires_grad_(True)
+        J = _gpu_objective(S, inst, logk, E, uplift, solver={"precision": prec})
+        J.backward()
+        grads[prec] = (host(logk.grad), host(E.grad))
+    assert rel(grads[fg.FG_MIXED][0], grads[fg.FG_F64][0]) < 1e-7
+    assert rel(grads[fg.FG_MIXED][1], grads[fg.FG_F64][1]) < 1e-7
