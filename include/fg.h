@@ -168,6 +168,11 @@ fg_status fg_cohesive_update(fg_ctx *ctx, fg_system *sys, const double *U, const
 /* Point-Jacobi preconditioned CG (Hestenes-Stiefel, Sec. 3.3.2) on `which`
  * (FG_K or FG_A22) from x0 = 0.  b, x: nrhs column vectors, each of length 3N
  * (FG_K) or N (FG_A22), stored one after the other.  precision applies to FG_K.
+ * With FG_K and nrhs > 1 (a power of two up to 64) the columns are solved
+ * together: independent CG recurrences (own alpha, beta, stop test) advanced in
+ * lockstep so that each iteration streams the matrix once per tile of columns
+ * (block product); converged columns are masked out.  FG_MIXED refines every
+ * column in FP64 around FP32 block iterations.
  * Returns FG_OK, FG_NOT_CONVERGED (x holds the last iterate),
  * FG_ERR_BREAKDOWN, FG_ERR_NAN.  info (host) receives the worst column. */
 fg_status fg_pcg_solve(fg_ctx *ctx, fg_system *sys, int which, int nrhs, const double *b, double *x,
@@ -258,6 +263,8 @@ fg_status fg_export(fg_ctx *ctx, fg_system *sys, int which, int32_t *rows_h, int
  *               Clipped to what 64 KB of LDS per 4-wavefront workgroup holds.
  *   "graphs":   1 (default) replays each batch of CG iterations as a captured
  *               HIP graph, 0 launches the kernels one by one (same results).
+ *   "rhs_tile": columns per pass of the block (many right-hand sides) product:
+ *               1, 2, 4, 8 (default) or 16; the matrix is streamed once per tile.
  * Returns FG_ERR_ARG for an unknown key or a negative value. */
 fg_status fg_tune(fg_system *sys, const char *key, int64_t value);
 

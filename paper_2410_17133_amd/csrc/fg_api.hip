@@ -344,6 +344,12 @@ fg_status fg_system_destroy(fg_system *S)
                     S->rf, S->dpv, S->die0, S->partials, S->sc, S->red, S->red_counter};
     for (void *p : ptrs) dfree(p);
     drop_graphs(S);
+    drop_mr_graphs(S);
+    void *mr_ptrs[] = {S->mx, S->mr, S->mp, S->mq, S->mb, S->mx64, S->mr64, S->mfx, S->mfr, S->mfp, S->mfq,
+                       S->msc, S->mpart, S->mred};
+    for (void *p : mr_ptrs) dfree(p);
+    if (S->msc_host) hipHostFree(S->msc_host);
+    if (S->mred_host) hipHostFree(S->mred_host);
     if (S->cap_stream) hipStreamDestroy(S->cap_stream);
     for (auto &pool : S->prof_ev)
         for (hipEvent_t ev : pool) hipEventDestroy(ev);
@@ -446,6 +452,14 @@ fg_status fg_system_create(fg_ctx *ctx, const fg_mesh *mesh, fg_system **out)
     CK(dalloc(&S->red_counter, 4));
     hipMemset(S->red_counter, 0, 4 * sizeof(uint32_t));
     hipMemset(S->sc, 0, sizeof(CgScalars));
+    S->mpart_stride = std::max<int64_t>(((S->nslices + 3) / 4 + 7) / 8 * 8, 2048) + 8;
+    if (dalloc(&S->mpart, 2 * (int64_t)MR_MAX * S->mpart_stride) || dalloc(&S->msc, 1) || dalloc(&S->mred, MR_MAX) ||
+        hipHostMalloc((void **)&S->msc_host, sizeof(MrScalars)) != hipSuccess ||
+        hipHostMalloc((void **)&S->mred_host, MR_MAX * sizeof(double)) != hipSuccess) {
+        set_error("allocation of the block-solve scalars failed");
+        fg_system_destroy(S);
+        return FG_ERR_OOM;
+    }
     if (hipStreamCreateWithFlags(&S->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         set_error("stream creation failed");
         fg_system_destroy(S);
@@ -535,6 +549,12 @@ fg_status fg_pcg_solve(fg_ctx *ctx, fg_system *S, int which, int nrhs, const dou
     }
     const int bs = which == FG_K ? 3 : 1;
     const int64_t nn = bs * S->N;
+    if (which == FG_K && nrhs > 1) {
+        fg_pcg_info bi{};
+        fg_status s = block_solve(S, nrhs, b, x, o.precision, o.tol, o.max_iter, o.check_every, o.inner_tol, &bi, st);
+        if (info) *info = bi;
+        return s;
+    }
     fg_status worst = FG_OK;
     fg_pcg_info wi{};
     for (int c = 0; c < nrhs; ++c) {
@@ -864,6 +884,16 @@ fg_status fg_tune(fg_system *S, const char *key, int64_t value)
     if (std::strcmp(key, "graphs") == 0) {
         S->use_graphs = value != 0;
         drop_graphs(S);
+        drop_mr_graphs(S);
+        return FG_OK;
+    }
+    if (std::strcmp(key, "rhs_tile") == 0) {
+        if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16) {
+            set_error("fg_tune: rhs_tile must be 1, 2, 4, 8 or 16");
+            return FG_ERR_ARG;
+        }
+        S->mr_tile = (int)value;
+        drop_mr_graphs(S);
         return FG_OK;
     }
     set_error(std::string("fg_tune: unknown key ") + key);

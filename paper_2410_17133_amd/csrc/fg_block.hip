@@ -1,0 +1,603 @@
+// Many right-hand sides on one stiffness: independent point-Jacobi CG per
+// column, advanced together so that every iteration streams the matrix once
+// per tile of columns instead of once per column.
+//
+// Vector layout: column-interleaved, element (dof d, column c) at d*nrhs + c, so
+// the columns of one DOF are contiguous (one wide load per gathered node).
+// Each column has its own alpha, beta, rho and stop flag; a converged column is
+// masked out of the vector updates.  nrhs is a power of two <= MR_MAX.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "fg_device.h"
+#include "fg_kernels.h"
+
+namespace fg {
+
+namespace {
+
+// per-thread column of an element-wise kernel: the grid size is a multiple of nrhs
+__device__ __forceinline__ int elem_col(int nrhs) { return (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) & (nrhs - 1)); }
+
+// Per-column block partials: thread t holds NV sums of column (t mod nrhs); the
+// block adds the threads of each column and stores partials[(k*nrhs + c)*stride + block].
+template <int NV>
+__device__ __forceinline__ void block_partials_cols(const double (&v)[NV], int nrhs, double *partials, int64_t stride)
+{
+    __shared__ double sh[NV][WG];
+    for (int k = 0; k < NV; ++k) sh[k][threadIdx.x] = v[k];
+    __syncthreads();
+    if ((int)threadIdx.x < nrhs)
+        for (int k = 0; k < NV; ++k) {
+            double s = 0;
+            for (int j = threadIdx.x; j < WG; j += nrhs) s += sh[k][j];
+            partials[((int64_t)k * nrhs + threadIdx.x) * stride + blockIdx.x] = s;
+        }
+}
+
+template <int NV>
+__device__ __forceinline__ void column_sum(const double *partials, int nrhs, int c, int64_t stride, int64_t nparts,
+                                           double (&tot)[NV])
+{
+    __shared__ double sh[NV][FIN / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int k = 0; k < NV; ++k) {
+        double s = 0;
+        for (int64_t i = threadIdx.x; i < nparts; i += blockDim.x) s += partials[((int64_t)k * nrhs + c) * stride + i];
+        s = wave_sum(s);
+        if (lane == 0) sh[k][w] = s;
+    }
+    __syncthreads();
+    for (int k = 0; k < NV; ++k) {
+        double s = 0;
+        for (int i = 0; i < nw; ++i) s += sh[k][i];
+        tot[k] = s;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(WG) void k_mr_init(int64_t n, int nrhs, int lg, const T *__restrict__ dinv, T *__restrict__ x,
+                                                const T *__restrict__ r, T *__restrict__ p, double *partials,
+                                                int64_t stride)
+{
+    double v[2] = {0, 0};
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const T ri = r[i], zi = dinv[i >> lg] * ri;
+        x[i] = 0;
+        p[i] = zi;
+        v[0] += (double)ri * (double)zi;
+        v[1] += (double)ri * (double)ri;
+    }
+    block_partials_cols<2>(v, nrhs, partials, stride);
+}
+
+__global__ __launch_bounds__(FIN) void k_mr_init_fin(const double *partials, int nrhs, int64_t stride, int64_t nparts,
+                                                     MrScalars *sc, double tol)
+{
+    const int c = blockIdx.x;
+    double tot[2];
+    column_sum<2>(partials, nrhs, c, stride, nparts, tot);
+    if (threadIdx.x != 0) return;
+    sc->rho[c] = tot[0];
+    sc->rr[c] = tot[1];
+    sc->bb[c] = tot[1];
+    sc->tol2[c] = tol * tol * tot[1];
+    sc->iter[c] = 0;
+    sc->status[c] = FG_OK;
+    sc->done[c] = 0;
+    if (!isfinite(tot[0]) || !isfinite(tot[1])) {
+        sc->status[c] = FG_ERR_NAN;
+        sc->done[c] = 1;
+    } else if (tot[1] == 0.0) {
+        sc->done[c] = 1;
+    } else if (sc->maxit <= 0) {
+        sc->status[c] = FG_NOT_CONVERGED;
+        sc->done[c] = 1;
+    }
+}
+
+// Q = K P for the columns [c0, c0 + CT) of one slice per wavefront, with the
+// per-column block partials of P.Q.  The 9 values of a slot are loaded once
+// and applied to all CT columns; x operands are gathered from global memory.
+template <typename T, typename TV, int CT>
+__global__ __launch_bounds__(WG) void k_mr_spmm(SpmvArgs a, int nrhs, const TV *__restrict__ val,
+                                                const T *__restrict__ p, T *__restrict__ q, double *partials,
+                                                int64_t stride, const MrScalars *sc, int with_dot)
+{
+    const int c0 = blockIdx.y * CT;
+    const int64_t s = xcd_block() * (WG / SLICE) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    double v[CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) v[c] = 0;
+    if (s < a.nslices) {
+        const int64_t base = a.slice_ptr[s];
+        const int w = (int)((a.slice_ptr[s + 1] - base) / SLICE);
+        const int32_t *cl = a.col + base + lane;
+        const TV *vb0 = val + 9 * base + lane;
+        T acc[3][CT];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < CT; ++c) acc[r][c] = 0;
+        for (int j = 0; j < w; ++j) {
+            const int64_t cj = cl[(int64_t)j * SLICE];
+            const TV *vb = vb0 + (int64_t)9 * j * SLICE;
+            T m[9];
+#pragma unroll
+            for (int e = 0; e < 9; ++e) m[e] = (T)vb[e * SLICE];
+            const T *xp = p + 3 * cj * nrhs + c0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int c = 0; c < CT; ++c) {
+                    const T xv = xp[k * nrhs + c];
+                    acc[0][c] += m[k] * xv;
+                    acc[1][c] += m[3 + k] * xv;
+                    acc[2][c] += m[6 + k] * xv;
+                }
+        }
+        const int64_t r0 = s * SLICE + lane;
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                const int64_t i = (3 * r0 + r) * nrhs + c0 + c;
+                q[i] = acc[r][c];
+                if (with_dot) v[c] += (double)p[i] * (double)acc[r][c];
+            }
+    }
+    if (!with_dot) return;
+    // block partials of the CT columns of this tile
+    __shared__ double sh[CT][WG / 64];
+    const int wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+        const double t = wave_sum(v[c]);
+        if (lane == 0) sh[c][wv] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < CT) {
+        double t = 0;
+        for (int i = 0; i < WG / 64; ++i) t += sh[threadIdx.x][i];
+        partials[(int64_t)(c0 + threadIdx.x) * stride + blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(FIN) void k_mr_alpha(const double *partials, int nrhs, int64_t stride, int64_t nparts,
+                                                  MrScalars *sc)
+{
+    const int c = blockIdx.x;
+    if (sc->done[c]) return;
+    double tot[1];
+    column_sum<1>(partials, nrhs, c, stride, nparts, tot);
+    if (threadIdx.x != 0) return;
+    const double pq = tot[0];
+    sc->pq[c] = pq;
+    if (!isfinite(pq)) {
+        sc->status[c] = FG_ERR_NAN;
+        sc->done[c] = 1;
+    } else if (!(pq > 0.0)) {
+        sc->status[c] = FG_ERR_BREAKDOWN;
+        sc->done[c] = 1;
+    } else {
+        sc->alpha[c] = sc->rho[c] / pq;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(WG) void k_mr_update(int64_t n, int nrhs, int lg, const T *__restrict__ dinv, T *__restrict__ x,
+                                                  T *__restrict__ r, const T *__restrict__ p,
+                                                  const T *__restrict__ q, double *partials, int64_t stride,
+                                                  const MrScalars *sc)
+{
+    const int c = elem_col(nrhs);
+    double v[2] = {0, 0};
+    if (!sc->done[c]) {
+        const T al = (T)sc->alpha[c];
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+            x[i] += al * p[i];
+            const T ri = r[i] - al * q[i];
+            r[i] = ri;
+            const T zi = dinv[i >> lg] * ri;
+            v[0] += (double)ri * (double)zi;
+            v[1] += (double)ri * (double)ri;
+        }
+    }
+    block_partials_cols<2>(v, nrhs, partials, stride);
+}
+
+__global__ __launch_bounds__(FIN) void k_mr_beta(const double *partials, int nrhs, int64_t stride, int64_t nparts,
+                                                 MrScalars *sc)
+{
+    const int c = blockIdx.x;
+    if (sc->done[c]) return;
+    double tot[2];
+    column_sum<2>(partials, nrhs, c, stride, nparts, tot);
+    if (threadIdx.x != 0) return;
+    sc->iter[c] += 1;
+    sc->rr[c] = tot[1];
+    if (!isfinite(tot[0]) || !isfinite(tot[1])) {
+        sc->status[c] = FG_ERR_NAN;
+        sc->done[c] = 1;
+    } else if (tot[1] <= sc->tol2[c]) {
+        sc->status[c] = FG_OK;
+        sc->done[c] = 1;
+    } else if (sc->iter[c] >= sc->maxit) {
+        sc->status[c] = FG_NOT_CONVERGED;
+        sc->done[c] = 1;
+    } else {
+        sc->beta[c] = tot[0] / sc->rho[c];
+        sc->rho[c] = tot[0];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(WG) void k_mr_pupdate(int64_t n, int nrhs, int lg, const T *__restrict__ dinv,
+                                                   const T *__restrict__ r, T *__restrict__ p, const MrScalars *sc)
+{
+    const int c = elem_col(nrhs);
+    if (sc->done[c]) return;
+    const T be = (T)sc->beta[c];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = dinv[i >> lg] * r[i] + be * p[i];
+}
+
+// caller layout (column c of length 3N at c*3N, caller node order) <-> interleaved internal layout
+__global__ void k_mr_in(int64_t N, int64_t Npad, int nrhs, const int32_t *__restrict__ perm,
+                        const double *__restrict__ b, double *__restrict__ out)
+{
+    const int64_t n = 3 * Npad * nrhs;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % nrhs);
+        const int64_t d = i / nrhs, r = d / 3;
+        out[i] = r < N ? b[(int64_t)c * 3 * N + 3 * (int64_t)perm[r] + (d - 3 * r)] : 0.0;
+    }
+}
+
+__global__ void k_mr_out(int64_t N, int nrhs, const int32_t *__restrict__ perm, const double *__restrict__ in,
+                         double *__restrict__ x)
+{
+    const int64_t n = 3 * N * nrhs;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % nrhs);
+        const int64_t d = i / nrhs, r = d / 3;
+        x[(int64_t)c * 3 * N + 3 * (int64_t)perm[r] + (d - 3 * r)] = in[i];
+    }
+}
+
+// per-column dot products a_c . b_c (block partials; k_mr_colfin adds them)
+__global__ __launch_bounds__(WG) void k_mr_coldot(int64_t n, int nrhs, const double *__restrict__ a,
+                                                  const double *__restrict__ b, double *partials, int64_t stride)
+{
+    double v[1] = {0};
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        v[0] += a[i] * b[i];
+    block_partials_cols<1>(v, nrhs, partials, stride);
+}
+
+__global__ __launch_bounds__(FIN) void k_mr_colfin(const double *partials, int nrhs, int64_t stride, int64_t nparts,
+                                                   double *res)
+{
+    double tot[1];
+    column_sum<1>(partials, nrhs, blockIdx.x, stride, nparts, tot);
+    if (threadIdx.x == 0) res[blockIdx.x] = tot[0];
+}
+
+// y_c = s_c * x_c (per-column scale, FP64 -> FP32 or FP32 -> FP64 accumulate)
+__global__ void k_mr_scale_to_f32(int64_t n, int nrhs, const double *__restrict__ s, const double *__restrict__ x,
+                                  float *__restrict__ y)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (float)(s[i % nrhs] * x[i]);
+}
+
+__global__ void k_mr_add_f32(int64_t n, int nrhs, const double *__restrict__ s, const float *__restrict__ x,
+                             double *__restrict__ y)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] += s[i % nrhs] * (double)x[i];
+}
+
+// r = b - q, element-wise
+__global__ void k_mr_resid(int64_t n, const double *__restrict__ b, const double *__restrict__ q, double *__restrict__ r)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        r[i] = b[i] - q[i];
+}
+
+// element-wise grid for column-interleaved vectors; blocks of WG threads make the
+// grid a multiple of nrhs, so each thread keeps one column
+inline int64_t grid_cols(int64_t n) { return grid_elems(n); }
+
+inline int log2i(int v)
+{
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+}  // namespace
+
+template <typename T, typename TV>
+static void mr_launch_spmm(fg_system *S, int nrhs, const TV *val, const T *p, T *q, int with_dot, hipStream_t st)
+{
+    const int64_t gx = grid_xcd((S->nslices + 3) / 4);
+    const int ct = std::min(S->mr_tile, nrhs);
+    const SpmvArgs a = spmv_args(S);
+    switch (ct) {
+    case 1:
+        hipLaunchKernelGGL((k_mr_spmm<T, TV, 1>), dim3(gx, nrhs / 1), dim3(WG), 0, st, a, nrhs, val, p, q, S->mpart,
+                           S->mpart_stride, S->msc, with_dot);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_mr_spmm<T, TV, 2>), dim3(gx, nrhs / 2), dim3(WG), 0, st, a, nrhs, val, p, q, S->mpart,
+                           S->mpart_stride, S->msc, with_dot);
+        break;
+    case 4:
+        hipLaunchKernelGGL((k_mr_spmm<T, TV, 4>), dim3(gx, nrhs / 4), dim3(WG), 0, st, a, nrhs, val, p, q, S->mpart,
+                           S->mpart_stride, S->msc, with_dot);
+        break;
+    case 8:
+        hipLaunchKernelGGL((k_mr_spmm<T, TV, 8>), dim3(gx, nrhs / 8), dim3(WG), 0, st, a, nrhs, val, p, q, S->mpart,
+                           S->mpart_stride, S->msc, with_dot);
+        break;
+    default:
+        hipLaunchKernelGGL((k_mr_spmm<T, TV, 16>), dim3(gx, nrhs / 16), dim3(WG), 0, st, a, nrhs, val, p, q, S->mpart,
+                           S->mpart_stride, S->msc, with_dot);
+        break;
+    }
+}
+
+template <typename T, typename TV>
+static void mr_launch_batch(fg_system *S, int nrhs, const TV *val, const T *dinv, T *x, T *r, T *p, T *q, int iters,
+                            hipStream_t st)
+{
+    const int64_t n = 3 * S->Npad * nrhs;
+    const int64_t ge = grid_cols(n), gx = grid_xcd((S->nslices + 3) / 4);
+    for (int it = 0; it < iters; ++it) {
+        mr_launch_spmm<T, TV>(S, nrhs, val, p, q, 1, st);
+        hipLaunchKernelGGL(k_mr_alpha, dim3(nrhs), dim3(FIN), 0, st, S->mpart, nrhs, S->mpart_stride, gx, S->msc);
+        hipLaunchKernelGGL((k_mr_update<T>), dim3(ge), dim3(WG), 0, st, n, nrhs, log2i(nrhs), dinv, x, r, p, q, S->mpart,
+                           S->mpart_stride, S->msc);
+        hipLaunchKernelGGL(k_mr_beta, dim3(nrhs), dim3(FIN), 0, st, S->mpart, nrhs, S->mpart_stride, ge, S->msc);
+        hipLaunchKernelGGL((k_mr_pupdate<T>), dim3(ge), dim3(WG), 0, st, n, nrhs, log2i(nrhs), dinv, r, p, S->msc);
+    }
+}
+
+// Allocate the block workspaces for nrhs columns (grown on demand).
+fg_status mr_reserve(fg_system *S, int nrhs)
+{
+    if (nrhs <= S->mr_cap) return FG_OK;
+    double **d[] = {&S->mx, &S->mr, &S->mp, &S->mq, &S->mb, &S->mx64, &S->mr64};
+    float **f[] = {&S->mfx, &S->mfr, &S->mfp, &S->mfq};
+    for (double **p : d) {
+        if (*p) hipFree(*p);
+        *p = nullptr;
+    }
+    for (float **p : f) {
+        if (*p) hipFree(*p);
+        *p = nullptr;
+    }
+    drop_mr_graphs(S);
+    const size_t n = (size_t)3 * S->Npad * nrhs;
+    for (double **p : d)
+        if (hipMalloc((void **)p, n * sizeof(double)) != hipSuccess) {
+            hipGetLastError();
+            set_error("fg_pcg_solve: device allocation for the block solve failed");
+            return FG_ERR_OOM;
+        }
+    for (float **p : f)
+        if (hipMalloc((void **)p, n * sizeof(float)) != hipSuccess) {
+            hipGetLastError();
+            set_error("fg_pcg_solve: device allocation for the block solve failed");
+            return FG_ERR_OOM;
+        }
+    S->mr_cap = nrhs;
+    return FG_OK;
+}
+
+void drop_mr_graphs(fg_system *S)
+{
+    for (GraphCache &g : S->mr_graph) {
+        if (g.exec) hipGraphExecDestroy(g.exec);
+        g.exec = nullptr;
+        g.iters = 0;
+    }
+}
+
+// Block CG on the interleaved right-hand sides already in S->mr (FP64) or S->mfr
+// (FP32); solutions left in S->mx / S->mfx.  Per-column results in S->msc_host.
+static fg_status mr_cg(fg_system *S, int nrhs, bool f32, double tol, int64_t maxit, int check_every, hipStream_t st)
+{
+    const int64_t n = 3 * S->Npad * nrhs;
+    MrScalars init{};
+    init.maxit = maxit;
+    init.nrhs = nrhs;
+    hipMemcpyAsync(S->msc, &init, sizeof init, hipMemcpyHostToDevice, st);
+    const int64_t ge = grid_cols(n);
+    if (f32) {
+        if (!S->k32_valid) refresh_k32(S, st);
+        hipLaunchKernelGGL((k_mr_init<float>), dim3(ge), dim3(WG), 0, st, n, nrhs, log2i(nrhs), S->dinvK32, S->mfx, S->mfr, S->mfp,
+                           S->mpart, S->mpart_stride);
+    } else {
+        hipLaunchKernelGGL((k_mr_init<double>), dim3(ge), dim3(WG), 0, st, n, nrhs, log2i(nrhs), S->dinvK, S->mx, S->mr, S->mp,
+                           S->mpart, S->mpart_stride);
+    }
+    hipLaunchKernelGGL(k_mr_init_fin, dim3(nrhs), dim3(FIN), 0, st, S->mpart, nrhs, S->mpart_stride, ge, S->msc, tol);
+    fg_status e = check_hip("block cg init");
+    if (e) return e;
+    const int batch = check_every > 0 ? check_every : 32;
+    GraphCache &g = S->mr_graph[f32 ? 1 : 0];
+    for (;;) {
+        hipMemcpyAsync(S->msc_host, S->msc, sizeof(MrScalars), hipMemcpyDeviceToHost, st);
+        hipStreamSynchronize(st);
+        e = check_hip("block cg poll");
+        if (e) return e;
+        bool all = true;
+        for (int c = 0; c < nrhs; ++c) all = all && S->msc_host->done[c];
+        if (all) break;
+        if (!S->use_graphs) {
+            if (f32)
+                mr_launch_batch<float, float>(S, nrhs, S->K32, S->dinvK32, S->mfx, S->mfr, S->mfp, S->mfq, batch, st);
+            else
+                mr_launch_batch<double, double>(S, nrhs, S->K, S->dinvK, S->mx, S->mr, S->mp, S->mq, batch, st);
+        } else {
+            if (!g.exec || g.iters != batch || g.nrhs != nrhs || g.tile != S->mr_tile) {
+                if (g.exec) hipGraphExecDestroy(g.exec);
+                g.exec = nullptr;
+                hipGraph_t graph = nullptr;
+                if (hipStreamBeginCapture(S->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                    return check_hip("block cg capture");
+                if (f32)
+                    mr_launch_batch<float, float>(S, nrhs, S->K32, S->dinvK32, S->mfx, S->mfr, S->mfp, S->mfq, batch,
+                                                  S->cap_stream);
+                else
+                    mr_launch_batch<double, double>(S, nrhs, S->K, S->dinvK, S->mx, S->mr, S->mp, S->mq, batch,
+                                                    S->cap_stream);
+                if (hipStreamEndCapture(S->cap_stream, &graph) != hipSuccess) return check_hip("block cg capture end");
+                hipError_t ie = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+                hipGraphDestroy(graph);
+                if (ie != hipSuccess) {
+                    g.exec = nullptr;
+                    return check_hip("block cg instantiate");
+                }
+                g.iters = batch;
+                g.nrhs = nrhs;
+                g.tile = S->mr_tile;
+            }
+            hipGraphLaunch(g.exec, st);
+        }
+        e = check_hip("block cg batch");
+        if (e) return e;
+    }
+    return FG_OK;
+}
+
+static void mr_colnorms(fg_system *S, int nrhs, const double *a, double *host, hipStream_t st)
+{
+    const int64_t n = 3 * S->Npad * nrhs, ge = grid_cols(n);
+    hipLaunchKernelGGL(k_mr_coldot, dim3(ge), dim3(WG), 0, st, n, nrhs, a, a, S->mpart, S->mpart_stride);
+    hipLaunchKernelGGL(k_mr_colfin, dim3(nrhs), dim3(FIN), 0, st, S->mpart, nrhs, S->mpart_stride, ge, S->mred);
+    hipMemcpyAsync(S->mred_host, S->mred, nrhs * sizeof(double), hipMemcpyDeviceToHost, st);
+    hipStreamSynchronize(st);
+    for (int c = 0; c < nrhs; ++c) host[c] = std::sqrt(S->mred_host[c]);
+}
+
+// Multi-right-hand-side K solve: b, x in the caller layout (column c at c*3N).
+fg_status block_solve(fg_system *S, int nrhs, const double *b, double *x, int precision, double tol, int64_t maxit,
+                      int check_every, double inner_tol, fg_pcg_info *info, hipStream_t st)
+{
+    if (nrhs > MR_MAX || (nrhs & (nrhs - 1))) {
+        set_error("fg_pcg_solve: the block solve takes a power-of-two number of right-hand sides up to 64");
+        return FG_ERR_ARG;
+    }
+    fg_status e = mr_reserve(S, nrhs);
+    if (e) return e;
+    const int64_t n = 3 * S->Npad * nrhs, ge = grid_cols(n);
+    hipLaunchKernelGGL(k_mr_in, dim3(ge), dim3(WG), 0, st, S->N, S->Npad, nrhs, S->perm, b, S->mb);
+    fg_status worst = FG_OK;
+    int64_t max_iters = 0, cycles = 0;
+    double worst_rel = 0;
+    if (precision == FG_F64 || precision == FG_F32) {
+        const bool f32 = precision == FG_F32;
+        if (f32) {
+            std::vector<double> ones(nrhs, 1.0);
+            hipMemcpyAsync(S->mred, ones.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st);
+            hipLaunchKernelGGL(k_mr_scale_to_f32, dim3(ge), dim3(WG), 0, st, n, nrhs, S->mred, S->mb, S->mfr);
+        } else {
+            hipMemcpyAsync(S->mr, S->mb, n * sizeof(double), hipMemcpyDeviceToDevice, st);
+        }
+        e = mr_cg(S, nrhs, f32, tol, maxit, check_every, st);
+        if (e) return e;
+        if (f32) {
+            hipMemsetAsync(S->mx64, 0, n * sizeof(double), st);
+            std::vector<double> ones(nrhs, 1.0);
+            hipMemcpyAsync(S->mred, ones.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st);
+            hipLaunchKernelGGL(k_mr_add_f32, dim3(ge), dim3(WG), 0, st, n, nrhs, S->mred, S->mfx, S->mx64);
+            hipLaunchKernelGGL(k_mr_out, dim3(ge), dim3(WG), 0, st, S->N, nrhs, S->perm, S->mx64, x);
+        } else {
+            hipLaunchKernelGGL(k_mr_out, dim3(ge), dim3(WG), 0, st, S->N, nrhs, S->perm, S->mx, x);
+        }
+        const MrScalars &h = *S->msc_host;
+        for (int c = 0; c < nrhs; ++c) {
+            max_iters = std::max<int64_t>(max_iters, h.iter[c]);
+            worst_rel = std::max(worst_rel, h.bb[c] > 0 ? std::sqrt(h.rr[c] / h.bb[c]) : 0.0);
+            if (h.status[c] < 0) worst = h.status[c] < worst ? h.status[c] : worst;
+            else if (worst >= 0 && h.status[c] > worst) worst = h.status[c];
+        }
+        cycles = 1;
+    } else {
+        // FP32 inner block CG, FP64 residual and refinement per column
+        if (!S->k32_valid) refresh_k32(S, st);
+        std::vector<double> bn(nrhs), rn(nrhs), scale(nrhs);
+        mr_colnorms(S, nrhs, S->mb, bn.data(), st);
+        hipMemsetAsync(S->mx64, 0, n * sizeof(double), st);
+        hipMemcpyAsync(S->mr64, S->mb, n * sizeof(double), hipMemcpyDeviceToDevice, st);
+        int64_t total = 0;
+        for (;;) {
+            mr_colnorms(S, nrhs, S->mr64, rn.data(), st);
+            bool active = false;
+            worst_rel = 0;
+            for (int c = 0; c < nrhs; ++c) {
+                const double rel = bn[c] > 0 ? rn[c] / bn[c] : 0.0;
+                if (!std::isfinite(rel)) {
+                    set_error("fg_pcg_solve: NaN in a block refinement residual");
+                    return FG_ERR_NAN;
+                }
+                worst_rel = std::max(worst_rel, rel);
+                const bool act = rel > tol;
+                active = active || act;
+                scale[c] = act ? 1.0 / rn[c] : 0.0;  // a converged column gets a zero right-hand side
+            }
+            if (!active) {
+                worst = FG_OK;
+                break;
+            }
+            if (total >= maxit || cycles >= 200) {
+                worst = FG_NOT_CONVERGED;
+                break;
+            }
+            hipMemcpyAsync(S->mred, scale.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st);
+            hipLaunchKernelGGL(k_mr_scale_to_f32, dim3(ge), dim3(WG), 0, st, n, nrhs, S->mred, S->mr64, S->mfr);
+            double itol = inner_tol;
+            for (int c = 0; c < nrhs; ++c)
+                if (scale[c] > 0) itol = std::max(itol, std::min(inner_tol, tol * bn[c] / rn[c]));
+            e = mr_cg(S, nrhs, true, std::max(itol, inner_tol), maxit - total, check_every, st);
+            if (e) return e;
+            int64_t it_max = 0;
+            for (int c = 0; c < nrhs; ++c) {
+                it_max = std::max<int64_t>(it_max, S->msc_host->iter[c]);
+                if (S->msc_host->status[c] < 0) {
+                    set_error("fg_pcg_solve: breakdown or NaN in a block inner solve");
+                    return S->msc_host->status[c];
+                }
+            }
+            total += it_max;
+            cycles++;
+            for (int c = 0; c < nrhs; ++c) scale[c] = scale[c] > 0 ? rn[c] : 0.0;
+            hipMemcpyAsync(S->mred, scale.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st);
+            hipLaunchKernelGGL(k_mr_add_f32, dim3(ge), dim3(WG), 0, st, n, nrhs, S->mred, S->mfx, S->mx64);
+            mr_launch_spmm<double, double>(S, nrhs, S->K, S->mx64, S->mq, 0, st);
+            hipLaunchKernelGGL(k_mr_resid, dim3(ge), dim3(WG), 0, st, n, S->mb, S->mq, S->mr64);
+        }
+        max_iters = total;
+        hipLaunchKernelGGL(k_mr_out, dim3(ge), dim3(WG), 0, st, S->N, nrhs, S->perm, S->mx64, x);
+    }
+    hipStreamSynchronize(st);
+    if (info) {
+        info->iters = max_iters;
+        info->cycles = cycles;
+        info->relres = worst_rel;
+        info->status = worst;
+    }
+    if (worst == FG_ERR_BREAKDOWN) set_error("fg_pcg_solve: CG breakdown in a column (p.Ap <= 0)");
+    if (worst == FG_ERR_NAN) set_error("fg_pcg_solve: NaN or Inf in a column");
+    e = check_hip("fg_pcg_solve (block)");
+    return e ? e : worst;
+}
+
+}  // namespace fg

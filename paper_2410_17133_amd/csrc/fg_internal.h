@@ -63,7 +63,17 @@ void set_error(const std::string &msg);
 
 struct GraphCache {
     hipGraphExec_t exec = nullptr;
-    int iters = 0;
+    int iters = 0, nrhs = 0, tile = 0;
+};
+
+// Per-column scalars of the block (many right-hand sides) CG.
+constexpr int MR_MAX = 64;
+struct MrScalars {
+    double rho[MR_MAX], pq[MR_MAX], rr[MR_MAX], bb[MR_MAX], alpha[MR_MAX], beta[MR_MAX], tol2[MR_MAX];
+    int64_t iter[MR_MAX];
+    int32_t done[MR_MAX], status[MR_MAX];
+    int64_t maxit;
+    int32_t nrhs, pad;
 };
 
 }  // namespace fg
@@ -137,6 +147,16 @@ struct fg_system {
     bool use_graphs = true;
     hipStream_t cap_stream = nullptr;
     fg::GraphCache cg_graph[3];
+    // block solves (many right-hand sides), column-interleaved workspaces
+    int mr_cap = 0;   // columns allocated
+    int mr_tile = 8;  // columns per SpMM pass (fg_tune "rhs_tile")
+    double *mx = nullptr, *mr = nullptr, *mp = nullptr, *mq = nullptr, *mb = nullptr, *mx64 = nullptr, *mr64 = nullptr;
+    float *mfx = nullptr, *mfr = nullptr, *mfp = nullptr, *mfq = nullptr;
+    fg::MrScalars *msc = nullptr, *msc_host = nullptr;
+    double *mpart = nullptr;
+    int64_t mpart_stride = 0;
+    double *mred = nullptr, *mred_host = nullptr;
+    fg::GraphCache mr_graph[2];  // FP64, FP32
     // live kernel timing (fg_profile)
     bool prof = false;
     std::vector<hipEvent_t> prof_ev[3];  // per operator slot: pairs (start, stop), one per launch of a batch

@@ -326,3 +326,53 @@ def test_bad_mesh_is_rejected():
     with pytest.raises(fg.FgError) as e:
         fg.System(ctx, inst.mesh.xyz, tets, inst.mesh.coh, inst.dir_u, inst.dir_p)
     assert e.value.status == fg.FG_ERR_ARG
+
+
+# ------------------------------------------------------------------ many right-hand sides
+def test_block_solve_matches_single_column_solves():
+    fg, O = _fg(), _oracle()
+    inst, ctx, S, P = setup("cube12_dip60_hetero")
+    P.cohesive(np.zeros(3 * P.N), np.zeros((P.nq, 2)))
+    S.cohesive_update(dev(np.zeros(3 * S.N)), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)))
+    nrhs = 8
+    r = np.random.default_rng(9)
+    B = r.standard_normal((nrhs, 3 * S.N)) * (1 - inst.dir_u) * np.logspace(-3, 3, nrhs)[:, None]
+    B[5] = 0.0                                     # a zero column is done at once
+    X, info = S.pcg_solve(fg.FG_K, dev(B.reshape(-1)), nrhs=nrhs, tol=1e-12)
+    assert info.status == 0
+    X = host(X).reshape(nrhs, -1)
+    assert np.all(X[5] == 0)
+    for c in (0, 3, 7):
+        x1, i1 = S.pcg_solve(fg.FG_K, dev(B[c]), tol=1e-12)
+        assert relerr(X[c], host(x1)) < 1e-10
+        xo, st, it, rr = P.pcg(O.K_TANGENT, B[c], tol=1e-12)
+        assert relerr(X[c], xo) < 1e-9
+    # the column tile only changes how often the matrix is streamed, not the arithmetic
+    ref = None
+    for tile in (1, 2, 4, 8, 16):
+        S.tune("rhs_tile", tile)
+        Xt, it = S.pcg_solve(fg.FG_K, dev(B.reshape(-1)), nrhs=nrhs, tol=1e-10)
+        Xt = host(Xt)
+        if ref is None:
+            ref = Xt
+        np.testing.assert_array_equal(Xt, ref)
+    S.tune("rhs_tile", 8)
+
+
+def test_block_solve_mixed_precision_and_errors():
+    fg, O = _fg(), _oracle()
+    inst, ctx, S, P = setup("cube12_dip60_hetero")
+    P.cohesive(np.zeros(3 * P.N), np.zeros((P.nq, 2)))
+    S.cohesive_update(dev(np.zeros(3 * S.N)), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)))
+    nrhs = 16
+    B = np.random.default_rng(10).standard_normal((nrhs, 3 * S.N)) * (1 - inst.dir_u)
+    X, info = S.pcg_solve(fg.FG_K, dev(B.reshape(-1)), nrhs=nrhs, tol=1e-8, precision=fg.FG_MIXED)
+    assert info.status == 0 and info.cycles >= 2
+    X = host(X).reshape(nrhs, -1)
+    for c in range(nrhs):
+        assert np.linalg.norm(B[c] - P.spmv(O.K_TANGENT, X[c])) <= 1e-8 * np.linalg.norm(B[c])
+    X32, i32 = S.pcg_solve(fg.FG_K, dev(B.reshape(-1)), nrhs=nrhs, tol=1e-5, precision=fg.FG_F32)
+    assert i32.status == 0
+    with pytest.raises(fg.FgError) as e:
+        S.pcg_solve(fg.FG_K, dev(np.zeros(3 * 3 * S.N)), nrhs=3)
+    assert e.value.status == fg.FG_ERR_ARG
