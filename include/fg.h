@@ -90,6 +90,8 @@ typedef struct {
     const int32_t *coh_h;    /* [n_coh*6], may be NULL when n_coh == 0 */
     const uint8_t *dir_u_h;  /* [3*n_nodes], 1 = displacement DOF held at zero */
     const uint8_t *dir_p_h;  /* [n_nodes], 1 = pressure DOF held at zero */
+    const int32_t *group_h;  /* [n_nodes] or NULL: instance of each node in a batch of independent
+                                problems (0..63); no element may couple two groups */
 } fg_mesh;
 
 typedef struct {
@@ -145,6 +147,17 @@ fg_status fg_system_destroy(fg_system *sys);
  * Errors: FG_ERR_ARG (null pointers, non-positive volume). */
 fg_status fg_assemble(fg_ctx *ctx, fg_system *sys, const fg_params *params, const double *E, const double *log_k,
                       void *stream);
+
+/* fg_assemble for a batch system (fg_mesh.group_h set) whose instances carry
+ * their own parameters: params[g] applies to every element of group g.  The
+ * penalties of Sec. 2.2.1 scale with the element size, so instances of different
+ * resolution need their own k_n and k_s.  n_params is 1 (all groups share
+ * params[0], same as fg_assemble) or the number of groups.  params is host
+ * memory, read before the call returns.
+ * Errors: FG_ERR_ARG for another n_params or for groups with different dt (the
+ * time step enters the host-side flow residual and is shared by the batch). */
+fg_status fg_assemble_groups(fg_ctx *ctx, fg_system *sys, const fg_params *params, int n_params, const double *E,
+                             const double *log_k, void *stream);
 
 /* Interface update at every quadrature point (Sec. 2.2.1, eq. normal_traction to
  * eq. corrector): opening delta = sum_a N_a (U_a+ - U_a-) resolved on (n,t1,t2);
@@ -256,6 +269,12 @@ fg_status fg_system_sizes(const fg_system *sys, int64_t *n_pairs_h, int64_t *n_p
  * row-major 3x3) or 1 (A22, C) values per pair.  Synchronises the stream. */
 fg_status fg_export(fg_ctx *ctx, fg_system *sys, int which, int32_t *rows_h, int32_t *cols_h, double *vals_h,
                     void *stream);
+
+/* Per-group results of the last fg_pcg_solve on a batched system (fg_mesh.group_h):
+ * each group is an independent problem with its own CG scalars and stop test.
+ * Host arrays of n_groups entries (each may be NULL): CG iterations (summed over
+ * refinement cycles), final relative residual, status. */
+fg_status fg_group_stats(const fg_system *sys, int64_t *iters_h, double *relres_h, int *status_h, int *n_groups_h);
 
 /* Tuning knobs of the products (the autotuner's search space).
  *   "halo_cap": largest per-slice halo whose x is staged in LDS; slices with a

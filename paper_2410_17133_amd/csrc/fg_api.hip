@@ -106,6 +106,66 @@ fg_pcg_opts defaults(const fg_pcg_opts *o, double tol)
     return d;
 }
 
+// Mixed-precision K solve of a batched system: every group refines against its
+// own residual norm; groups that meet the tolerance get a zero inner right-hand side.
+fg_status k_solve_mixed_grouped(fg_system *S, const double *rhs, double *out, const fg_pcg_opts &o, fg_pcg_info *info,
+                                hipStream_t st)
+{
+    const int G = S->ngroups;
+    const int64_t n = 3 * S->Npad;
+    double *x = S->v3, *r = S->v4;
+    std::vector<double> bn(G), rn(G), scale(G);
+    group_norms(S, 3, rhs, bn.data(), st);
+    vfill(x, 0.0, n, st);
+    hipMemcpyAsync(r, rhs, n * sizeof(double), hipMemcpyDeviceToDevice, st);
+    int64_t total = 0, cycles = 0;
+    double worst_rel = 0;
+    fg_status s = FG_OK;
+    for (;;) {
+        group_norms(S, 3, r, rn.data(), st);
+        bool active = false;
+        worst_rel = 0;
+        double itol = o.inner_tol;
+        for (int g = 0; g < G; ++g) {
+            const double rel = bn[g] > 0 ? rn[g] / bn[g] : 0.0;
+            if (!std::isfinite(rel)) {
+                set_error("fg_pcg_solve: NaN in a group's refinement residual");
+                return FG_ERR_NAN;
+            }
+            worst_rel = std::max(worst_rel, rel);
+            const bool act = rel > o.tol;
+            active = active || act;
+            scale[g] = act ? 1.0 / rn[g] : 0.0;
+        }
+        if (!active) break;
+        if (total >= o.max_iter || cycles >= 200) {
+            s = FG_NOT_CONVERGED;
+            break;
+        }
+        group_to_f32(S, scale.data(), r, S->fr, st);
+        int64_t it = 0;
+        double rr = 0;
+        fg_status si = cg_run_grouped(S, FG_K, FG_F32, itol, o.max_iter - total, o.check_every, &it, &rr, st);
+        total += it;
+        cycles++;
+        if (si < 0) return si;
+        for (int g = 0; g < G; ++g) scale[g] = scale[g] > 0 ? rn[g] : 0.0;
+        group_add_f32(S, scale.data(), S->fx, x, st);
+        spmv(S, FG_K, x, S->wq, st);
+        hipMemcpyAsync(r, rhs, n * sizeof(double), hipMemcpyDeviceToDevice, st);
+        vaxpby(n, -1.0, S->wq, 1.0, r, st);
+    }
+    for (int g = 0; g < G; ++g) S->grp_relres[g] = bn[g] > 0 ? rn[g] / bn[g] : 0.0;
+    hipMemcpyAsync(out, x, n * sizeof(double), hipMemcpyDeviceToDevice, st);
+    if (info) {
+        info->iters = total;
+        info->cycles = cycles;
+        info->relres = worst_rel;
+        info->status = s;
+    }
+    return s;
+}
+
 // K solve on internal vectors: rhs (3 Npad) -> out (3 Npad).
 fg_status k_solve(fg_system *S, const double *rhs, double *out, const fg_pcg_opts &o, fg_pcg_info *info, hipStream_t st)
 {
@@ -135,6 +195,7 @@ fg_status k_solve(fg_system *S, const double *rhs, double *out, const fg_pcg_opt
     // Mixed precision: FP32 inner CG on the correction equation, FP64 true
     // residual and accumulation (iterative refinement).
     if (!S->k32_valid) refresh_k32(S, st);
+    if (S->ngroups > 1) return k_solve_mixed_grouped(S, rhs, out, o, info, st);
     double *x = S->v3, *r = S->v4;
     const double bn = vnorm(S, n, rhs, st);
     vfill(x, 0.0, n, st);
@@ -336,7 +397,7 @@ fg_status fg_system_destroy(fg_system *S)
     if (!S) return FG_OK;
     Guard g(S->device);
     hipDeviceSynchronize();
-    void *ptrs[] = {S->halo_ptr, S->halo, S->lcol, S->slice_ptr, S->col, S->rowlen, S->diag_slot, S->perm, S->xyz, S->tets, S->tet_orig, S->coh,
+    void *ptrs[] = {S->gprm, S->slice_group, S->group_slice_ptr, S->gsc, S->gpart, S->gred, S->halo_ptr, S->halo, S->lcol, S->slice_ptr, S->col, S->rowlen, S->diag_slot, S->perm, S->xyz, S->tets, S->tet_orig, S->coh,
                     S->frows, S->fadj_ptr, S->fadj, S->dir_u, S->dir_p, S->tri_geo, S->K, S->K32, S->Kfb, S->A22,
                     S->Cm, S->dinvK, S->dinvK32, S->dinvA, S->qpD, S->qpT, S->qpNs, S->qpS, S->adj_trac, S->adj_die, S->adj_flag, S->wx, S->wr, S->wp, S->wq, S->fx,
                     S->fr, S->fp, S->fq, S->v1, S->v2, S->v3, S->v4, S->pv1, S->pv2, S->ui, S->ui0, S->fi, S->rm,
@@ -345,10 +406,13 @@ fg_status fg_system_destroy(fg_system *S)
     for (void *p : ptrs) dfree(p);
     drop_graphs(S);
     drop_mr_graphs(S);
+    drop_group_graphs(S);
     void *mr_ptrs[] = {S->mx, S->mr, S->mp, S->mq, S->mb, S->mx64, S->mr64, S->mfx, S->mfr, S->mfp, S->mfq,
                        S->msc, S->mpart, S->mred};
     for (void *p : mr_ptrs) dfree(p);
     if (S->msc_host) hipHostFree(S->msc_host);
+    if (S->gsc_host) hipHostFree(S->gsc_host);
+    if (S->gred_host) hipHostFree(S->gred_host);
     if (S->mred_host) hipHostFree(S->mred_host);
     if (S->cap_stream) hipStreamDestroy(S->cap_stream);
     for (auto &pool : S->prof_ev)
@@ -409,8 +473,12 @@ fg_status fg_system_create(fg_ctx *ctx, const fg_mesh *mesh, fg_system **out)
     // LDS window per wavefront: the largest halo, within 64 KB per 4-wave workgroup of FP64 3-vectors
     S->halo_cap = (int)std::min<int64_t>(P.halo_max, 65536 / (4 * 3 * (int64_t)sizeof(double)));
     std::vector<double> xyz(3 * S->Npad, 0.0);
-    for (int64_t r = 0; r < S->N; ++r)
-        for (int c = 0; c < 3; ++c) xyz[3 * r + c] = mesh->xyz_h[3 * (int64_t)P.perm[r] + c];
+    for (int64_t r = 0; r < S->Npad; ++r)
+        if (P.perm[r] >= 0)
+            for (int c = 0; c < 3; ++c) xyz[3 * r + c] = mesh->xyz_h[3 * (int64_t)P.perm[r] + c];
+    S->ngroups = P.ngroups;
+    CK(upload(&S->slice_group, P.slice_group));
+    CK(upload(&S->group_slice_ptr, P.group_slice_ptr));
     CK(upload(&S->xyz, xyz));
     CK(upload(&S->tets, P.tets));
     CK(upload(&S->tet_orig, P.tet_orig));
@@ -420,6 +488,7 @@ fg_status fg_system_create(fg_ctx *ctx, const fg_mesh *mesh, fg_system **out)
     CK(upload(&S->fadj, P.fadj));
     CK(upload(&S->dir_u, P.dir_u));
     CK(upload(&S->dir_p, P.dir_p));
+    CK(dalloc(&S->gprm, S->ngroups));
     CK(dalloc(&S->tri_geo, 10 * S->nf));
     CK(dalloc(&S->K, 9 * S->nblk));
     CK(dalloc(&S->K32, 9 * S->nblk));
@@ -452,6 +521,16 @@ fg_status fg_system_create(fg_ctx *ctx, const fg_mesh *mesh, fg_system **out)
     CK(dalloc(&S->red_counter, 4));
     hipMemset(S->red_counter, 0, 4 * sizeof(uint32_t));
     hipMemset(S->sc, 0, sizeof(CgScalars));
+    S->grp_iters.assign(S->ngroups, 0);
+    S->grp_relres.assign(S->ngroups, 0.0);
+    S->grp_status.assign(S->ngroups, 0);
+    if (dalloc(&S->gsc, 1) || dalloc(&S->gpart, 2 * S->nslices) || dalloc(&S->gred, MAX_GROUPS) ||
+        hipHostMalloc((void **)&S->gsc_host, sizeof(MrScalars)) != hipSuccess ||
+        hipHostMalloc((void **)&S->gred_host, MAX_GROUPS * sizeof(double)) != hipSuccess) {
+        set_error("allocation of the batched-solve scalars failed");
+        fg_system_destroy(S);
+        return FG_ERR_OOM;
+    }
     S->mpart_stride = std::max<int64_t>(((S->nslices + 3) / 4 + 7) / 8 * 8, 2048) + 8;
     if (dalloc(&S->mpart, 2 * (int64_t)MR_MAX * S->mpart_stride) || dalloc(&S->msc, 1) || dalloc(&S->mred, MR_MAX) ||
         hipHostMalloc((void **)&S->msc_host, sizeof(MrScalars)) != hipSuccess ||
@@ -493,13 +572,34 @@ fg_status fg_system_sizes(const fg_system *S, int64_t *n_pairs, int64_t *n_blk, 
 
 fg_status fg_assemble(fg_ctx *ctx, fg_system *S, const fg_params *prm, const double *E, const double *log_k, void *stream)
 {
+    return fg_assemble_groups(ctx, S, prm, 1, E, log_k, stream);
+}
+
+fg_status fg_assemble_groups(fg_ctx *ctx, fg_system *S, const fg_params *prm, int n_params, const double *E,
+                             const double *log_k, void *stream)
+{
     if (!ctx || !S || !prm || !E || !log_k) {
         set_error("fg_assemble: null argument");
         return FG_ERR_ARG;
     }
+    if (n_params != 1 && n_params != S->ngroups) {
+        set_error("fg_assemble_groups: n_params must be 1 or the number of groups");
+        return FG_ERR_ARG;
+    }
+    for (int g = 1; g < n_params; ++g)
+        if (prm[g].dt != prm[0].dt) {
+            set_error("fg_assemble_groups: every group must use the same time step dt");
+            return FG_ERR_ARG;
+        }
     Guard g(ctx->device);
     hipStream_t st = S_(stream);
-    S->prm = *prm;
+    std::vector<fg_params> gp(S->ngroups);
+    for (int i = 0; i < S->ngroups; ++i) gp[i] = prm[n_params == 1 ? 0 : i];
+    // synchronous upload: the parameters are host data owned by the caller
+    if (hipStreamSynchronize(st) != hipSuccess ||
+        hipMemcpy(S->gprm, gp.data(), gp.size() * sizeof(fg_params), hipMemcpyHostToDevice) != hipSuccess)
+        return check_hip("fg_assemble parameters");
+    S->prm = prm[0];
     S->k32_valid = false;
     assemble_all(S, E, log_k, st);
     TRY(check_hip("fg_assemble"));
@@ -549,6 +649,7 @@ fg_status fg_pcg_solve(fg_ctx *ctx, fg_system *S, int which, int nrhs, const dou
     }
     const int bs = which == FG_K ? 3 : 1;
     const int64_t nn = bs * S->N;
+    std::fill(S->grp_iters.begin(), S->grp_iters.end(), 0);
     if (which == FG_K && nrhs > 1) {
         fg_pcg_info bi{};
         fg_status s = block_solve(S, nrhs, b, x, o.precision, o.tol, o.max_iter, o.check_every, o.inner_tol, &bi, st);
@@ -850,7 +951,8 @@ fg_status fg_export(fg_ctx *ctx, fg_system *S, int which, int32_t *rows, int32_t
     std::vector<int32_t> fidx(S->Npad, -1);
     for (size_t k = 0; k < P.frows.size(); ++k) fidx[P.frows[k]] = (int32_t)k;
     int64_t m = 0;
-    for (int64_t r = 0; r < S->N; ++r) {
+    for (int64_t r = 0; r < S->Npad; ++r) {
+        if (P.perm[r] < 0) continue;
         const int64_t s = r / SLICE, l = r % SLICE, base = P.slice_ptr[s];
         for (int j = 0; j < P.rowlen[r]; ++j) {
             const int64_t c = P.col[base + (int64_t)j * SLICE + l];
@@ -869,6 +971,21 @@ fg_status fg_export(fg_ctx *ctx, fg_system *S, int which, int32_t *rows, int32_t
     return FG_OK;
 }
 
+fg_status fg_group_stats(const fg_system *S, int64_t *iters, double *relres, int *status, int *n_groups)
+{
+    if (!S) {
+        set_error("fg_group_stats: null system");
+        return FG_ERR_ARG;
+    }
+    for (int g = 0; g < S->ngroups; ++g) {
+        if (iters) iters[g] = S->grp_iters[g];
+        if (relres) relres[g] = S->grp_relres[g];
+        if (status) status[g] = S->grp_status[g];
+    }
+    if (n_groups) *n_groups = S->ngroups;
+    return FG_OK;
+}
+
 fg_status fg_tune(fg_system *S, const char *key, int64_t value)
 {
     if (!S || !key || value < 0) {
@@ -879,12 +996,14 @@ fg_status fg_tune(fg_system *S, const char *key, int64_t value)
     if (std::strcmp(key, "halo_cap") == 0) {
         S->halo_cap = (int)std::min<int64_t>(value, 65536 / (4 * 3 * (int64_t)sizeof(double)));
         drop_graphs(S);
+        drop_group_graphs(S);
         return FG_OK;
     }
     if (std::strcmp(key, "graphs") == 0) {
         S->use_graphs = value != 0;
         drop_graphs(S);
         drop_mr_graphs(S);
+        drop_group_graphs(S);
         return FG_OK;
     }
     if (std::strcmp(key, "rhs_tile") == 0) {

@@ -254,18 +254,20 @@ __global__ void k_mr_in(int64_t N, int64_t Npad, int nrhs, const int32_t *__rest
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int c = (int)(i % nrhs);
         const int64_t d = i / nrhs, r = d / 3;
-        out[i] = r < N ? b[(int64_t)c * 3 * N + 3 * (int64_t)perm[r] + (d - 3 * r)] : 0.0;
+        const int32_t o = perm[r];
+        out[i] = o >= 0 ? b[(int64_t)c * 3 * N + 3 * (int64_t)o + (d - 3 * r)] : 0.0;
     }
 }
 
-__global__ void k_mr_out(int64_t N, int nrhs, const int32_t *__restrict__ perm, const double *__restrict__ in,
-                         double *__restrict__ x)
+__global__ void k_mr_out(int64_t N, int64_t Npad, int nrhs, const int32_t *__restrict__ perm,
+                         const double *__restrict__ in, double *__restrict__ x)
 {
-    const int64_t n = 3 * N * nrhs;
+    const int64_t n = 3 * Npad * nrhs;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int c = (int)(i % nrhs);
         const int64_t d = i / nrhs, r = d / 3;
-        x[(int64_t)c * 3 * N + 3 * (int64_t)perm[r] + (d - 3 * r)] = in[i];
+        const int32_t o = perm[r];
+        if (o >= 0) x[(int64_t)c * 3 * N + 3 * (int64_t)o + (d - 3 * r)] = in[i];
     }
 }
 
@@ -518,9 +520,9 @@ fg_status block_solve(fg_system *S, int nrhs, const double *b, double *x, int pr
             std::vector<double> ones(nrhs, 1.0);
             hipMemcpyAsync(S->mred, ones.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st);
             hipLaunchKernelGGL(k_mr_add_f32, dim3(ge), dim3(WG), 0, st, n, nrhs, S->mred, S->mfx, S->mx64);
-            hipLaunchKernelGGL(k_mr_out, dim3(ge), dim3(WG), 0, st, S->N, nrhs, S->perm, S->mx64, x);
+            hipLaunchKernelGGL(k_mr_out, dim3(ge), dim3(WG), 0, st, S->N, S->Npad, nrhs, S->perm, S->mx64, x);
         } else {
-            hipLaunchKernelGGL(k_mr_out, dim3(ge), dim3(WG), 0, st, S->N, nrhs, S->perm, S->mx, x);
+            hipLaunchKernelGGL(k_mr_out, dim3(ge), dim3(WG), 0, st, S->N, S->Npad, nrhs, S->perm, S->mx, x);
         }
         const MrScalars &h = *S->msc_host;
         for (int c = 0; c < nrhs; ++c) {
@@ -585,7 +587,7 @@ fg_status block_solve(fg_system *S, int nrhs, const double *b, double *x, int pr
             hipLaunchKernelGGL(k_mr_resid, dim3(ge), dim3(WG), 0, st, n, S->mb, S->mq, S->mr64);
         }
         max_iters = total;
-        hipLaunchKernelGGL(k_mr_out, dim3(ge), dim3(WG), 0, st, S->N, nrhs, S->perm, S->mx64, x);
+        hipLaunchKernelGGL(k_mr_out, dim3(ge), dim3(WG), 0, st, S->N, S->Npad, nrhs, S->perm, S->mx64, x);
     }
     hipStreamSynchronize(st);
     if (info) {

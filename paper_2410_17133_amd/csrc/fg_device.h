@@ -89,6 +89,80 @@ struct SpmvArgs {
     int cap;
 };
 
+// Each wavefront owns one slice.  It first copies x of the slice's halo (the
+// sorted distinct columns of its 64 rows) into its own LDS window, then walks
+// the slots: the 9 (or 1) values of a slot are 64-wide coalesced loads and the
+// x operands come from LDS through 16-bit local column indices.  A slice whose
+// halo exceeds the LDS window (irregular meshes) gathers x from global memory.
+template <int BS, typename T>
+__device__ __forceinline__ bool stage_halo(int64_t s, int lane, const int64_t *__restrict__ halo_ptr,
+                                           const int32_t *__restrict__ halo, int cap, const T *__restrict__ x, T *xs)
+{
+    const int64_t h0 = halo_ptr[s];
+    const int hn = (int)(halo_ptr[s + 1] - h0);
+    if (hn > cap) return false;
+    for (int i = lane; i < hn; i += SLICE) {
+        const int64_t node = halo[h0 + i];
+#pragma unroll
+        for (int k = 0; k < BS; ++k) xs[BS * i + k] = x[BS * node + k];
+    }
+    return true;
+}
+
+// y = A x for one row (lane) of a slice; IDX is uint16_t (halo-local, xs in LDS)
+// or int32_t (global, xs = x).  dj: slot of the row's diagonal, whose x is
+// returned in d0..d2 (for p.Ap).
+template <int BS, typename T, typename TV, typename IDX>
+__device__ __forceinline__ void slice_row(int64_t base, int w, int lane, int dj, const IDX *__restrict__ idx,
+                                          const TV *__restrict__ val, const T *xs, T (&y)[BS], T (&d)[BS])
+{
+    const IDX *c = idx + base + lane;
+    const TV *v = val + BS * BS * base + lane;
+#pragma unroll
+    for (int r = 0; r < BS; ++r) y[r] = 0, d[r] = 0;
+#pragma unroll 3
+    for (int j = 0; j < w; ++j) {
+        const int64_t cj = c[(int64_t)j * SLICE];
+        T xv[BS];
+#pragma unroll
+        for (int k = 0; k < BS; ++k) xv[k] = xs[BS * cj + k];
+        const TV *vb = v + (int64_t)BS * BS * j * SLICE;
+#pragma unroll
+        for (int r = 0; r < BS; ++r)
+#pragma unroll
+            for (int k = 0; k < BS; ++k) y[r] += (T)vb[(BS * r + k) * SLICE] * xv[k];
+        if (j == dj)
+#pragma unroll
+            for (int k = 0; k < BS; ++k) d[k] = xv[k];
+    }
+}
+
+// q = A p for the rows of one slice; returns p.q of the lane's row.
+template <int BS, typename T, typename TV>
+__device__ __forceinline__ double slice_spmv(int64_t s, int lane, bool staged, const int64_t *__restrict__ slice_ptr,
+                                             const int32_t *__restrict__ col, const uint16_t *__restrict__ lcol,
+                                             const int32_t *__restrict__ diag_slot, const TV *__restrict__ val,
+                                             const T *__restrict__ x, const T *xs, T *__restrict__ y)
+{
+    const int64_t base = slice_ptr[s];
+    const int w = (int)((slice_ptr[s + 1] - base) / SLICE);
+    const int64_t r = s * SLICE + lane;
+    const int dj = diag_slot[r];
+    T yv[BS], d[BS];
+    if (staged)
+        slice_row<BS, T, TV, uint16_t>(base, w, lane, dj, lcol, val, xs, yv, d);
+    else
+        slice_row<BS, T, TV, int32_t>(base, w, lane, dj, col, val, x, yv, d);
+    double pq = 0;
+#pragma unroll
+    for (int k = 0; k < BS; ++k) {
+        y[BS * r + k] = yv[k];
+        pq += (double)d[k] * (double)yv[k];
+    }
+    return pq;
+}
+
+
 }  // namespace
 
 #define LAUNCH(kern, grid, block, st, ...) hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, st, __VA_ARGS__)

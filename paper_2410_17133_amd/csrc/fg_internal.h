@@ -14,12 +14,13 @@ namespace fg {
 // Rows per slice of the sliced block-ELL storage: one wavefront, one row per lane.
 constexpr int SLICE = 64;
 constexpr int WG = 256;  // threads per workgroup in most kernels
+constexpr int MAX_GROUPS = 64;  // independent instances of one batched system
 
 // Result of planning a mesh on the host (see fg_system_create).
 struct Plan {
     int64_t N = 0, Npad = 0, nslices = 0, nblk_pad = 0, npairs = 0;
     int64_t ne = 0, nf = 0;
-    std::vector<int32_t> perm;       // internal row -> caller node
+    std::vector<int32_t> perm;       // [Npad] internal row -> caller node, -1 for padding rows
     std::vector<int32_t> iperm;      // caller node -> internal row
     std::vector<int64_t> slice_ptr;  // [nslices+1] first block of each slice
     std::vector<int32_t> col;        // [nblk_pad] internal column node, padding = own row
@@ -29,6 +30,9 @@ struct Plan {
     std::vector<int32_t> halo;       // sorted distinct columns of each slice
     std::vector<uint16_t> lcol;      // [nblk_pad] column as an index into the slice's halo
     int64_t halo_max = 0;
+    int ngroups = 1;
+    std::vector<int64_t> group_slice_ptr;  // [ngroups+1] slice range of each group
+    std::vector<int32_t> slice_group;      // [nslices]
     std::vector<int32_t> tets;       // [ne*4] internal node ids, grouped by colour
     std::vector<int32_t> tet_orig;   // [ne] caller index of each grouped tetrahedron
     std::vector<int64_t> colour_ptr; // [ncolours+1]
@@ -91,13 +95,24 @@ struct fg_system {
     int64_t N = 0, Npad = 0, nslices = 0, nblk = 0, ne = 0, nf = 0, nq = 0, nfr = 0;
     int ncolours = 0;
     bool assembled = false;
-    fg_params prm{};
+    fg_params prm{};                   // group 0's parameters (the time step is shared by all groups)
+    fg_params *gprm = nullptr;         // [ngroups] per-group parameters on the device
     // device graph
     int64_t *slice_ptr = nullptr;
     int32_t *col = nullptr;
     uint8_t *rowlen = nullptr;
     int32_t *diag_slot = nullptr;
-    int32_t *perm = nullptr;  // internal -> caller
+    int32_t *perm = nullptr;  // [Npad] internal -> caller, -1 for padding rows
+    int ngroups = 1;
+    int32_t *slice_group = nullptr;  // [nslices]
+    int64_t *group_slice_ptr = nullptr;
+    fg::MrScalars *gsc = nullptr, *gsc_host = nullptr;  // per-group CG scalars
+    double *gpart = nullptr;                             // per-slice partials [2][nslices]
+    double *gred = nullptr, *gred_host = nullptr;        // [MAX_GROUPS]
+    fg::GraphCache g_graph[3];
+    std::vector<int64_t> grp_iters;   // per-group results of the last solve (fg_group_stats)
+    std::vector<double> grp_relres;
+    std::vector<int> grp_status;
     int64_t *halo_ptr = nullptr;
     int32_t *halo = nullptr;
     uint16_t *lcol = nullptr;

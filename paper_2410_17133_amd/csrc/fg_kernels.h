@@ -66,4 +66,13 @@ fg_status block_solve(fg_system *S, int nrhs, const double *b, double *x, int pr
 fg_status mr_reserve(fg_system *S, int nrhs);
 void drop_mr_graphs(fg_system *S);
 
+// Batched systems (fg_group.hip): per-group CG with the right-hand side in
+// S->wr / S->fr and the solution left in S->wx / S->fx, as cg_run.
+fg_status cg_run_grouped(fg_system *S, int which, int precision, double tol, int64_t maxit, int check_every,
+                         int64_t *iters, double *relres, hipStream_t st);
+void group_norms(fg_system *S, int bs, const double *a, double *host, hipStream_t st);
+void group_to_f32(fg_system *S, const double *scale, const double *x, float *y, hipStream_t st);
+void group_add_f32(fg_system *S, const double *scale, const float *x, double *y, hipStream_t st);
+void drop_group_graphs(fg_system *S);
+
 }  // namespace fg

@@ -29,17 +29,19 @@ __global__ void k_perm_in(int64_t N, int64_t Npad, int bs, const int32_t *__rest
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < Npad * bs; i += (int64_t)gridDim.x * blockDim.x) {
         int64_t r = i / bs;
         int c = (int)(i - r * bs);
-        in[i] = r < N ? nat[(int64_t)perm[r] * bs + c] : 0.0;
+        const int32_t o = perm[r];
+        in[i] = o >= 0 ? nat[(int64_t)o * bs + c] : 0.0;
     }
 }
 
-__global__ void k_perm_out(int64_t N, int bs, const int32_t *__restrict__ perm, const double *__restrict__ in,
+__global__ void k_perm_out(int64_t Npad, int bs, const int32_t *__restrict__ perm, const double *__restrict__ in,
                            double *__restrict__ nat)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N * bs; i += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < Npad * bs; i += (int64_t)gridDim.x * blockDim.x) {
         int64_t r = i / bs;
         int c = (int)(i - r * bs);
-        nat[(int64_t)perm[r] * bs + c] = in[i];
+        const int32_t o = perm[r];
+        if (o >= 0) nat[(int64_t)o * bs + c] = in[i];
     }
 }
 
@@ -49,7 +51,8 @@ __global__ void k_perm_in_u8(int64_t N, int64_t Npad, int bs, const int32_t *__r
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < Npad * bs; i += (int64_t)gridDim.x * blockDim.x) {
         int64_t r = i / bs;
         int c = (int)(i - r * bs);
-        in[i] = r < N ? nat[(int64_t)perm[r] * bs + c] : 0;
+        const int32_t o = perm[r];
+        in[i] = o >= 0 ? nat[(int64_t)o * bs + c] : 0;
     }
 }
 
@@ -92,13 +95,20 @@ __device__ __forceinline__ int find_slot(const int32_t *colrow, int len, int32_t
 // Shape function a of the interface triangle at quadrature point q.
 __device__ __forceinline__ double qpN(int q, int a) { return q == a ? 2.0 / 3.0 : 1.0 / 6.0; }
 
+// Parameters of the instance that owns internal row r (slices never mix instances).
+__device__ __forceinline__ const fg_params &group_params(const fg_params *gprm, const int32_t *sgrp, int64_t r)
+{
+    return gprm[sgrp[r / SLICE]];
+}
+
 // ----------------------------------------------------------------- assembly
 // One colour of tetrahedra: element stiffness V [lam g_a g_b^T + G (g_b g_a^T + (g_a.g_b) I)],
 // storage (V/(20 M))(1 + delta_ab) and conductivity (k/mu) V g_a.g_b, added to the
 // rows of the element's own nodes (no two elements of a colour share a node).
 __global__ void k_assemble_tets(int64_t t0, int64_t t1, const int32_t *__restrict__ tets,
                                 const int32_t *__restrict__ orig, const double *__restrict__ xyz,
-                                const double *__restrict__ E, const double *__restrict__ logk, fg_params prm,
+                                const double *__restrict__ E, const double *__restrict__ logk,
+                                const fg_params *__restrict__ gprm, const int32_t *__restrict__ sgrp,
                                 const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ col,
                                 const uint8_t *__restrict__ rowlen, double *K, double *A22, double *Cm, int *bad)
 {
@@ -112,6 +122,7 @@ __global__ void k_assemble_tets(int64_t t0, int64_t t1, const int32_t *__restric
         return;
     }
     const int64_t e = orig[t];
+    const fg_params &prm = group_params(gprm, sgrp, nd[0]);
     const double Ee = E[e], nu = prm.nu;
     const double lam = Ee * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
     const double G = Ee / (2.0 * (1.0 + nu));
@@ -174,7 +185,8 @@ __global__ void k_tri_geo(int64_t nf, const int32_t *__restrict__ coh, const dou
 // and transverse (k_perp/(mu w0)) int [[r]][[p]] with int N_a N_b = A(1+d_ab)/12.
 __global__ void k_fault_flow(int64_t nfr, int fw, const int32_t *__restrict__ frows, const int32_t *__restrict__ fadj_ptr,
                              const int32_t *__restrict__ fadj, const int32_t *__restrict__ coh,
-                             const double *__restrict__ geo, const double *__restrict__ xyz, fg_params prm,
+                             const double *__restrict__ geo, const double *__restrict__ xyz,
+                             const fg_params *__restrict__ gprm, const int32_t *__restrict__ sgrp,
                              const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ col,
                              const uint8_t *__restrict__ rowlen, double *A22, double *Cm)
 {
@@ -186,6 +198,7 @@ __global__ void k_fault_flow(int64_t nfr, int fw, const int32_t *__restrict__ fr
     const int64_t s = row / SLICE, l = row % SLICE, base = slice_ptr[s];
     if (j >= rowlen[row]) return;
     const int32_t cj = col[base + (int64_t)j * SLICE + l];
+    const fg_params &prm = group_params(gprm, sgrp, row);
     const double cs = prm.w0 / prm.M_F, cl = prm.w0 * prm.k_par / prm.mu, ct = prm.k_perp / (prm.mu * prm.w0);
     double sacc = 0, cacc = 0;
     for (int m = fadj_ptr[k]; m < fadj_ptr[k + 1]; ++m) {
@@ -310,7 +323,8 @@ __device__ QpOut return_map(double dn, double ds1, double ds2, double die1, doub
 
 __global__ void k_cohesive_qp(int64_t nq, const int32_t *__restrict__ coh, const double *__restrict__ geo,
                               const double *__restrict__ U, const double *__restrict__ die_n,
-                              const double *__restrict__ t0, double kn, double ks, double f, double *trac,
+                              const double *__restrict__ t0, const fg_params *__restrict__ gprm,
+                              const int32_t *__restrict__ sgrp, double *trac,
                               double *die, uint8_t *flag, double *qpT, double *qpD, double *qpNs)
 {
     int64_t iq = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -319,6 +333,8 @@ __global__ void k_cohesive_qp(int64_t nq, const int32_t *__restrict__ coh, const
     const int q = (int)(iq - 3 * t);
     const int32_t *c = coh + 6 * t;
     const double *gp = geo + 10 * t;
+    const fg_params &prm = group_params(gprm, sgrp, c[0]);
+    const double kn = prm.k_n, ks = prm.k_s, f = prm.friction;
     const V3 n = ld3(gp + 1), e1 = ld3(gp + 4), e2 = ld3(gp + 7);
     V3 jmp = {0, 0, 0};
     for (int a = 0; a < 3; ++a) {
@@ -359,11 +375,14 @@ __global__ void k_cohesive_qp(int64_t nq, const int32_t *__restrict__ coh, const
 }
 
 // Stick-and-contact tangent k_n n(x)n + k_s (t1(x)t1 + t2(x)t2) at every point.
-__global__ void k_stick_tangent(int64_t nq, const double *__restrict__ geo, double kn, double ks, double *qpD)
+__global__ void k_stick_tangent(int64_t nq, const int32_t *__restrict__ coh, const double *__restrict__ geo,
+                                const fg_params *__restrict__ gprm, const int32_t *__restrict__ sgrp, double *qpD)
 {
     int64_t iq = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (iq >= nq) return;
     const double *gp = geo + 10 * (iq / 3);
+    const fg_params &prm = group_params(gprm, sgrp, coh[6 * (iq / 3)]);
+    const double kn = prm.k_n, ks = prm.k_s;
     const int I[6] = {0, 1, 2, 1, 0, 0}, J[6] = {0, 1, 2, 2, 2, 1};
     for (int m = 0; m < 6; ++m)
         qpD[6 * iq + m] = kn * gp[1 + I[m]] * gp[1 + J[m]] +
@@ -495,7 +514,8 @@ __global__ void k_nt_rows(int64_t nfr, const int32_t *__restrict__ frows, const 
 // -V [lam1 tr eps(U) tr eps(lam) + 2 G1 eps(U):eps(lam)] with the E = 1 Lame constants, and
 // dJ/dln k_e = -dt lam_p^T C_e P_e = -dt (k_e/mu) V grad(lam_p) . grad(P).
 __global__ void k_sensitivity(int64_t ne, const int32_t *__restrict__ tets, const int32_t *__restrict__ orig,
-                              const double *__restrict__ xyz, const double *__restrict__ logk, fg_params prm,
+                              const double *__restrict__ xyz, const double *__restrict__ logk,
+                              const fg_params *__restrict__ gprm, const int32_t *__restrict__ sgrp,
                               const double *__restrict__ U, const double *__restrict__ P,
                               const double *__restrict__ lu, const double *__restrict__ lp,
                               const uint8_t *__restrict__ dir_u, const uint8_t *__restrict__ dir_p, double *dE,
@@ -525,6 +545,7 @@ __global__ void k_sensitivity(int64_t ne, const int32_t *__restrict__ tets, cons
         gp = {gp.x + pa * g[a].x, gp.y + pa * g[a].y, gp.z + pa * g[a].z};
         gl = {gl.x + qa * g[a].x, gl.y + qa * g[a].y, gl.z + qa * g[a].z};
     }
+    const fg_params &prm = group_params(gprm, sgrp, nd[0]);
     const double nu = prm.nu;
     const double lam1 = nu / ((1.0 + nu) * (1.0 - 2.0 * nu)), G1 = 1.0 / (2.0 * (1.0 + nu));
     double tru = eu[0][0] + eu[1][1] + eu[2][2], trl = el[0][0] + el[1][1] + el[2][2], dd = 0;
@@ -538,7 +559,8 @@ __global__ void k_sensitivity(int64_t ne, const int32_t *__restrict__ tets, cons
 // ----------------------------------------------------------------- coupling
 // A^m_pu p: per tetrahedron alpha (V/4) grad N_a sum_b p_b (eq. Apdp), one colour.
 __global__ void k_apu_tets(int64_t t0, int64_t t1, const int32_t *__restrict__ tets, const double *__restrict__ xyz,
-                           double alpha, const double *__restrict__ p, const uint8_t *__restrict__ dir_p, double *out)
+                           const fg_params *__restrict__ gprm, const int32_t *__restrict__ sgrp,
+                           const double *__restrict__ p, const uint8_t *__restrict__ dir_p, double *out)
 {
     int64_t t = t0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= t1) return;
@@ -547,7 +569,7 @@ __global__ void k_apu_tets(int64_t t0, int64_t t1, const int32_t *__restrict__ t
     const double V = tet_grads(xyz, nd, g);
     double sp = 0;
     for (int b = 0; b < 4; ++b) sp += dir_p[nd[b]] ? 0.0 : p[nd[b]];
-    const double c = alpha * 0.25 * V * sp;
+    const double c = group_params(gprm, sgrp, nd[0]).alpha * 0.25 * V * sp;
     for (int a = 0; a < 4; ++a) {
         double *o = out + 3 * (int64_t)nd[a];
         o[0] += c * g[a].x;
@@ -558,7 +580,8 @@ __global__ void k_apu_tets(int64_t t0, int64_t t1, const int32_t *__restrict__ t
 
 // A^m_up u: per tetrahedron alpha (V/4) div u added to each vertex (eq. Adpd), one colour.
 __global__ void k_aup_tets(int64_t t0, int64_t t1, const int32_t *__restrict__ tets, const double *__restrict__ xyz,
-                           double alpha, const double *__restrict__ u, const uint8_t *__restrict__ dir_u, double *out)
+                           const fg_params *__restrict__ gprm, const int32_t *__restrict__ sgrp,
+                           const double *__restrict__ u, const uint8_t *__restrict__ dir_u, double *out)
 {
     int64_t t = t0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= t1) return;
@@ -571,7 +594,7 @@ __global__ void k_aup_tets(int64_t t0, int64_t t1, const int32_t *__restrict__ t
         dv += (dir_u[o] ? 0.0 : u[o]) * g[a].x + (dir_u[o + 1] ? 0.0 : u[o + 1]) * g[a].y +
               (dir_u[o + 2] ? 0.0 : u[o + 2]) * g[a].z;
     }
-    const double c = alpha * 0.25 * V * dv;
+    const double c = group_params(gprm, sgrp, nd[0]).alpha * 0.25 * V * dv;
     for (int b = 0; b < 4; ++b) out[nd[b]] += c;
 }
 
@@ -671,80 +694,6 @@ __global__ __launch_bounds__(FIN) void k_dots_fin(const double *partials, int64_
 }
 
 // ----------------------------------------------------------------- SpMV
-// Each wavefront owns one slice.  It first copies x of the slice's halo (the
-// sorted distinct columns of its 64 rows) into its own LDS window, then walks
-// the slots: the 9 (or 1) values of a slot are 64-wide coalesced loads and the
-// x operands come from LDS through 16-bit local column indices.  A slice whose
-// halo exceeds the LDS window (irregular meshes) gathers x from global memory.
-template <int BS, typename T>
-__device__ __forceinline__ bool stage_halo(int64_t s, int lane, const int64_t *__restrict__ halo_ptr,
-                                           const int32_t *__restrict__ halo, int cap, const T *__restrict__ x, T *xs)
-{
-    const int64_t h0 = halo_ptr[s];
-    const int hn = (int)(halo_ptr[s + 1] - h0);
-    if (hn > cap) return false;
-    for (int i = lane; i < hn; i += SLICE) {
-        const int64_t node = halo[h0 + i];
-#pragma unroll
-        for (int k = 0; k < BS; ++k) xs[BS * i + k] = x[BS * node + k];
-    }
-    return true;
-}
-
-// y = A x for one row (lane) of a slice; IDX is uint16_t (halo-local, xs in LDS)
-// or int32_t (global, xs = x).  dj: slot of the row's diagonal, whose x is
-// returned in d0..d2 (for p.Ap).
-template <int BS, typename T, typename TV, typename IDX>
-__device__ __forceinline__ void slice_row(int64_t base, int w, int lane, int dj, const IDX *__restrict__ idx,
-                                          const TV *__restrict__ val, const T *xs, T (&y)[BS], T (&d)[BS])
-{
-    const IDX *c = idx + base + lane;
-    const TV *v = val + BS * BS * base + lane;
-#pragma unroll
-    for (int r = 0; r < BS; ++r) y[r] = 0, d[r] = 0;
-#pragma unroll 3
-    for (int j = 0; j < w; ++j) {
-        const int64_t cj = c[(int64_t)j * SLICE];
-        T xv[BS];
-#pragma unroll
-        for (int k = 0; k < BS; ++k) xv[k] = xs[BS * cj + k];
-        const TV *vb = v + (int64_t)BS * BS * j * SLICE;
-#pragma unroll
-        for (int r = 0; r < BS; ++r)
-#pragma unroll
-            for (int k = 0; k < BS; ++k) y[r] += (T)vb[(BS * r + k) * SLICE] * xv[k];
-        if (j == dj)
-#pragma unroll
-            for (int k = 0; k < BS; ++k) d[k] = xv[k];
-    }
-}
-
-// q = A p for the rows of one slice; returns p.q of the lane's row.
-template <int BS, typename T, typename TV>
-__device__ __forceinline__ double slice_spmv(int64_t s, int lane, bool staged, const int64_t *__restrict__ slice_ptr,
-                                             const int32_t *__restrict__ col, const uint16_t *__restrict__ lcol,
-                                             const int32_t *__restrict__ diag_slot, const TV *__restrict__ val,
-                                             const T *__restrict__ x, const T *xs, T *__restrict__ y)
-{
-    const int64_t base = slice_ptr[s];
-    const int w = (int)((slice_ptr[s + 1] - base) / SLICE);
-    const int64_t r = s * SLICE + lane;
-    const int dj = diag_slot[r];
-    T yv[BS], d[BS];
-    if (staged)
-        slice_row<BS, T, TV, uint16_t>(base, w, lane, dj, lcol, val, xs, yv, d);
-    else
-        slice_row<BS, T, TV, int32_t>(base, w, lane, dj, col, val, x, yv, d);
-    double pq = 0;
-#pragma unroll
-    for (int k = 0; k < BS; ++k) {
-        y[BS * r + k] = yv[k];
-        pq += (double)d[k] * (double)yv[k];
-    }
-    return pq;
-}
-
-
 template <int BS, typename T, typename TV>
 __global__ __launch_bounds__(WG) void k_spmv(SpmvArgs a, const TV *__restrict__ val, const T *__restrict__ x,
                                              T *__restrict__ y)
@@ -933,7 +882,7 @@ void perm_in(const fg_system *S, int bs, const double *nat, double *in, hipStrea
 
 void perm_out(const fg_system *S, int bs, const double *in, double *nat, hipStream_t st)
 {
-    LAUNCH(k_perm_out, grid_elems(S->N * bs), WG, st, S->N, bs, S->perm, in, nat);
+    LAUNCH(k_perm_out, grid_elems(S->Npad * bs), WG, st, S->Npad, bs, S->perm, in, nat);
 }
 
 void perm_in_u8(const fg_system *S, int bs, const uint8_t *nat, uint8_t *in, hipStream_t st)
@@ -1002,13 +951,13 @@ void assemble_all(fg_system *S, const double *E, const double *logk, hipStream_t
     for (size_t c = 0; c + 1 < P.colour_ptr.size(); ++c) {
         const int64_t a = P.colour_ptr[c], b = P.colour_ptr[c + 1];
         if (b > a)
-            LAUNCH(k_assemble_tets, (b - a + WG - 1) / WG, WG, st, a, b, S->tets, S->tet_orig, S->xyz, E, logk, S->prm,
-                   S->slice_ptr, S->col, S->rowlen, S->K, S->A22, S->Cm, bad);
+            LAUNCH(k_assemble_tets, (b - a + WG - 1) / WG, WG, st, a, b, S->tets, S->tet_orig, S->xyz, E, logk, S->gprm,
+                   S->slice_group, S->slice_ptr, S->col, S->rowlen, S->K, S->A22, S->Cm, bad);
     }
     if (S->nf > 0) {
         LAUNCH(k_tri_geo, (S->nf + WG - 1) / WG, WG, st, S->nf, S->coh, S->xyz, S->tri_geo);
         LAUNCH(k_fault_flow, (S->nfr * S->fault_w + WG - 1) / WG, WG, st, S->nfr, S->fault_w, S->frows, S->fadj_ptr,
-               S->fadj, S->coh, S->tri_geo, S->xyz, S->prm, S->slice_ptr, S->col, S->rowlen, S->A22, S->Cm);
+               S->fadj, S->coh, S->tri_geo, S->xyz, S->gprm, S->slice_group, S->slice_ptr, S->col, S->rowlen, S->A22, S->Cm);
     }
     LAUNCH(k_dirichlet, (S->Npad + WG - 1) / WG, WG, st, S->Npad, S->slice_ptr, S->col, S->rowlen, S->dir_u, S->dir_p,
            S->K, S->A22, S->dinvK, S->dinvA);
@@ -1020,7 +969,8 @@ void assemble_all(fg_system *S, const double *E, const double *logk, hipStream_t
 void stick_tangent(fg_system *S, hipStream_t st)
 {
     if (S->nq == 0) return;
-    LAUNCH(k_stick_tangent, (S->nq + WG - 1) / WG, WG, st, S->nq, S->tri_geo, S->prm.k_n, S->prm.k_s, S->qpD);
+    LAUNCH(k_stick_tangent, (S->nq + WG - 1) / WG, WG, st, S->nq, S->coh, S->tri_geo, S->gprm, S->slice_group,
+           S->qpD);
     cohesive_rows(S, S->fc, 1, st);
 }
 
@@ -1035,8 +985,8 @@ void cohesive_qp(fg_system *S, const double *U_int, const double *die_n, const d
                  uint8_t *flag, hipStream_t st)
 {
     if (S->nq == 0) return;
-    LAUNCH(k_cohesive_qp, (S->nq + WG - 1) / WG, WG, st, S->nq, S->coh, S->tri_geo, U_int, die_n, t0, S->prm.k_n,
-           S->prm.k_s, S->prm.friction, trac, die, flag, S->qpT, S->qpD, S->qpNs);
+    LAUNCH(k_cohesive_qp, (S->nq + WG - 1) / WG, WG, st, S->nq, S->coh, S->tri_geo, U_int, die_n, t0, S->gprm,
+           S->slice_group, trac, die, flag, S->qpT, S->qpD, S->qpNs);
 }
 
 void cohesive_rows(fg_system *S, double *fcoh_int, int write_tangent, hipStream_t st)
@@ -1063,7 +1013,7 @@ void apply_NT(fg_system *S, const double *x, double *y, hipStream_t st)
 void sensitivity(fg_system *S, const double *U, const double *P, const double *lu, const double *lp, double *dE,
                  double *dlogk, const double *logk, hipStream_t st)
 {
-    LAUNCH(k_sensitivity, (S->ne + WG - 1) / WG, WG, st, S->ne, S->tets, S->tet_orig, S->xyz, logk, S->prm, U, P, lu,
+    LAUNCH(k_sensitivity, (S->ne + WG - 1) / WG, WG, st, S->ne, S->tets, S->tet_orig, S->xyz, logk, S->gprm, S->slice_group, U, P, lu,
            lp, S->dir_u, S->dir_p, dE, dlogk);
 }
 
@@ -1073,7 +1023,8 @@ void apply_Apu(fg_system *S, const double *p, double *out, hipStream_t st)
     vfill(out, 0.0, 3 * S->Npad, st);
     for (size_t c = 0; c + 1 < P.colour_ptr.size(); ++c) {
         const int64_t a = P.colour_ptr[c], b = P.colour_ptr[c + 1];
-        if (b > a) LAUNCH(k_apu_tets, (b - a + WG - 1) / WG, WG, st, a, b, S->tets, S->xyz, S->prm.alpha, p, S->dir_p, out);
+        if (b > a) LAUNCH(k_apu_tets, (b - a + WG - 1) / WG, WG, st, a, b, S->tets, S->xyz, S->gprm, S->slice_group, p,
+                          S->dir_p, out);
     }
     if (S->nf > 0)
         LAUNCH(k_apu_fault, (S->nfr + WG - 1) / WG, WG, st, S->nfr, S->frows, S->fadj_ptr, S->fadj, S->coh, S->tri_geo,
@@ -1087,7 +1038,8 @@ void apply_Aup(fg_system *S, const double *u, double *out, hipStream_t st)
     vfill(out, 0.0, S->Npad, st);
     for (size_t c = 0; c + 1 < P.colour_ptr.size(); ++c) {
         const int64_t a = P.colour_ptr[c], b = P.colour_ptr[c + 1];
-        if (b > a) LAUNCH(k_aup_tets, (b - a + WG - 1) / WG, WG, st, a, b, S->tets, S->xyz, S->prm.alpha, u, S->dir_u, out);
+        if (b > a) LAUNCH(k_aup_tets, (b - a + WG - 1) / WG, WG, st, a, b, S->tets, S->xyz, S->gprm, S->slice_group, u,
+                          S->dir_u, out);
     }
     if (S->nf > 0)
         LAUNCH(k_aup_fault, (S->nfr + WG - 1) / WG, WG, st, S->nfr, S->frows, S->fadj_ptr, S->fadj, S->coh, S->tri_geo,
@@ -1214,6 +1166,7 @@ void drop_graphs(fg_system *S)
 fg_status cg_run(fg_system *S, int which, int precision, double tol, int64_t maxit, int check_every, int64_t *iters,
                  double *relres, hipStream_t st)
 {
+    if (S->ngroups > 1) return cg_run_grouped(S, which, precision, tol, maxit, check_every, iters, relres, st);
     const int bs = which == FG_K ? 3 : 1;
     const int64_t n = bs * S->Npad;
     CgScalars init{};

@@ -131,25 +131,70 @@ fg_status build_plan(const fg_mesh &m, Plan &P, std::string &err)
         }
         code[i] = c;
     }
-    P.perm.resize(N);
-    std::iota(P.perm.begin(), P.perm.end(), 0);
-    std::sort(P.perm.begin(), P.perm.end(), [&](int32_t a, int32_t b) {
+    // Groups (independent instances of a batch): rows of a group are contiguous
+    // and each group is padded to whole slices, so a slice never mixes groups.
+    std::vector<int32_t> grp(N, 0);
+    int ngroups = 1;
+    if (m.group_h) {
+        int gmax = 0;
+        for (int64_t i = 0; i < N; ++i) {
+            if (m.group_h[i] < 0 || m.group_h[i] >= MAX_GROUPS) {
+                err = "fg_system_create: group id out of range [0, 64)";
+                return FG_ERR_ARG;
+            }
+            grp[i] = m.group_h[i];
+            gmax = std::max(gmax, (int)grp[i]);
+        }
+        ngroups = gmax + 1;
+        // an element must not couple two groups
+        for (int64_t e = 0; e < ne; ++e)
+            for (int a = 1; a < 4; ++a)
+                if (grp[m.tets_h[4 * e + a]] != grp[m.tets_h[4 * e]]) {
+                    err = "fg_system_create: a tetrahedron spans two groups";
+                    return FG_ERR_ARG;
+                }
+        for (int64_t t = 0; t < nf; ++t)
+            for (int a = 1; a < 6; ++a)
+                if (grp[m.coh_h[6 * t + a]] != grp[m.coh_h[6 * t]]) {
+                    err = "fg_system_create: an interface element spans two groups";
+                    return FG_ERR_ARG;
+                }
+    }
+    std::vector<int32_t> order(N);
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        if (grp[a] != grp[b]) return grp[a] < grp[b];
         if (rlen[a] != rlen[b]) return rlen[a] > rlen[b];
         if (code[a] != code[b]) return code[a] < code[b];
         return a < b;
     });
+    P.ngroups = ngroups;
+    P.group_slice_ptr.assign(ngroups + 1, 0);
+    P.perm.clear();
+    {
+        int64_t k = 0;
+        for (int g = 0; g < ngroups; ++g) {
+            while (k < N && grp[order[k]] == g) P.perm.push_back(order[k++]);
+            while (P.perm.size() % SLICE) P.perm.push_back(-1);  // padding rows close the group's last slice
+            P.group_slice_ptr[g + 1] = (int64_t)P.perm.size() / SLICE;
+        }
+    }
     P.iperm.assign(N, 0);
-    for (int64_t r = 0; r < N; ++r) P.iperm[P.perm[r]] = (int32_t)r;
+    for (int64_t r = 0; r < (int64_t)P.perm.size(); ++r)
+        if (P.perm[r] >= 0) P.iperm[P.perm[r]] = (int32_t)r;
 
     // sliced block-ELL layout
-    P.nslices = (N + SLICE - 1) / SLICE;
-    P.Npad = P.nslices * SLICE;
+    P.Npad = (int64_t)P.perm.size();
+    P.nslices = P.Npad / SLICE;
+    P.slice_group.assign(P.nslices, 0);
+    for (int g = 0; g < ngroups; ++g)
+        for (int64_t s = P.group_slice_ptr[g]; s < P.group_slice_ptr[g + 1]; ++s) P.slice_group[s] = g;
     P.slice_ptr.assign(P.nslices + 1, 0);
     for (int64_t s = 0; s < P.nslices; ++s) {
         int w = 0;
         for (int l = 0; l < SLICE; ++l) {
             int64_t r = s * SLICE + l;
-            if (r < N) w = std::max(w, (int)rlen[P.perm[r]]);
+            if (P.perm[r] >= 0) w = std::max(w, (int)rlen[P.perm[r]]);
         }
         P.slice_ptr[s + 1] = P.slice_ptr[s] + (int64_t)w * SLICE;
     }
@@ -166,7 +211,7 @@ fg_status build_plan(const fg_mesh &m, Plan &P, std::string &err)
             int64_t base = P.slice_ptr[s];
             int w = (int)((P.slice_ptr[s + 1] - base) / SLICE);
             buf.clear();
-            if (r < N) {
+            if (P.perm[r] >= 0) {
                 int64_t i = P.perm[r];
                 for (int64_t k = inc_ptr[i]; k < inc_ptr[i + 1]; ++k) {
                     int64_t e = inc[k];
@@ -286,8 +331,9 @@ fg_status build_plan(const fg_mesh &m, Plan &P, std::string &err)
 
     P.dir_u.assign(3 * P.Npad, 0);
     P.dir_p.assign(P.Npad, 0);
-    for (int64_t r = 0; r < N; ++r) {
-        int64_t i = P.perm[r];
+    for (int64_t r = 0; r < P.Npad; ++r) {
+        const int64_t i = P.perm[r];
+        if (i < 0) continue;
         for (int c = 0; c < 3; ++c) P.dir_u[3 * r + c] = m.dir_u_h[3 * i + c] ? 1 : 0;
         P.dir_p[r] = m.dir_p_h[i] ? 1 : 0;
     }

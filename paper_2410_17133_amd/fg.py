@@ -20,7 +20,8 @@ FG_F64, FG_F32, FG_MIXED = 0, 1, 2
 
 SYMBOLS = ["fg_last_error", "fg_ctx_create", "fg_ctx_destroy", "fg_system_create", "fg_system_destroy",
            "fg_assemble", "fg_cohesive_update", "fg_pcg_solve", "fg_flow_solve", "fg_step", "fg_spmv",
-           "fg_coupling", "fg_residual", "fg_system_sizes", "fg_export", "fg_profile", "fg_profile_read", "fg_tune", "fg_adjoint_solve"]
+           "fg_coupling", "fg_residual", "fg_system_sizes", "fg_export", "fg_profile", "fg_profile_read", "fg_tune", "fg_adjoint_solve", "fg_group_stats",
+           "fg_assemble_groups"]
 
 
 class FgError(RuntimeError):
@@ -37,7 +38,7 @@ class Params(C.Structure):
 class Mesh(C.Structure):
     _fields_ = [("n_nodes", C.c_int64), ("n_tets", C.c_int64), ("n_coh", C.c_int64),
                 ("xyz_h", C.c_void_p), ("tets_h", C.c_void_p), ("coh_h", C.c_void_p),
-                ("dir_u_h", C.c_void_p), ("dir_p_h", C.c_void_p)]
+                ("dir_u_h", C.c_void_p), ("dir_p_h", C.c_void_p), ("group_h", C.c_void_p)]
 
 
 class PcgOpts(C.Structure):
@@ -76,6 +77,7 @@ def lib():
             "fg_system_create": [vp, C.POINTER(Mesh), C.POINTER(vp)],
             "fg_system_destroy": [vp],
             "fg_assemble": [vp, vp, C.POINTER(Params), vp, vp, vp],
+            "fg_assemble_groups": [vp, vp, C.POINTER(Params), i32, vp, vp, vp],
             "fg_cohesive_update": [vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp],
             "fg_pcg_solve": [vp, vp, i32, i32, vp, vp, C.POINTER(PcgOpts), C.POINTER(PcgInfo), vp],
             "fg_flow_solve": [vp, vp, vp, vp, vp, vp, C.POINTER(PcgOpts), C.POINTER(PcgOpts), dbl, i64,
@@ -89,6 +91,7 @@ def lib():
             "fg_export": [vp, vp, i32, vp, vp, vp, vp],
             "fg_profile": [vp, i32],
             "fg_tune": [vp, C.c_char_p, i64],
+            "fg_group_stats": [vp, vp, vp, vp, C.POINTER(i32)],
             "fg_adjoint_solve": [vp, vp] + [vp] * 11 + [C.POINTER(PcgOpts), C.POINTER(PcgOpts), dbl, dbl, i64,
                                                         C.POINTER(SolveInfo), vp],
             "fg_profile_read": [vp, i32, C.POINTER(i64), C.POINTER(dbl), i32],
@@ -143,16 +146,18 @@ class Context:
 class System:
     """A planned mesh with its assembled operators on the GPU."""
 
-    def __init__(self, ctx: Context, xyz, tets, coh, dir_u, dir_p):
+    def __init__(self, ctx: Context, xyz, tets, coh, dir_u, dir_p, group=None):
         self.ctx = ctx
         self._keep = [np.ascontiguousarray(xyz, np.float64), np.ascontiguousarray(tets, np.int32),
                       np.ascontiguousarray(coh if len(coh) else np.zeros((0, 6)), np.int32),
-                      np.ascontiguousarray(dir_u, np.uint8), np.ascontiguousarray(dir_p, np.uint8)]
-        x, t, c, du, dp = self._keep
+                      np.ascontiguousarray(dir_u, np.uint8), np.ascontiguousarray(dir_p, np.uint8),
+                      None if group is None else np.ascontiguousarray(group, np.int32)]
+        x, t, c, du, dp, gr = self._keep
+        self.ngroups = 1 if gr is None else int(gr.max()) + 1
         self.N, self.ne, self.nf = x.shape[0], t.shape[0], c.shape[0]
         self.nq = 3 * self.nf
         m = Mesh(self.N, self.ne, self.nf, x.ctypes.data, t.ctypes.data, c.ctypes.data if self.nf else None,
-                 du.ctypes.data, dp.ctypes.data)
+                 du.ctypes.data, dp.ctypes.data, None if gr is None else gr.ctypes.data)
         h = C.c_void_p()
         _check(lib().fg_system_create(ctx._h, C.byref(m), C.byref(h)))
         self._h = h
@@ -162,6 +167,11 @@ class System:
     def from_instance(cls, ctx, inst):
         m = inst.mesh
         return cls(ctx, m.xyz, m.tets, m.coh, inst.dir_u, inst.dir_p)
+
+    @classmethod
+    def from_batch(cls, ctx, batch):
+        """A batch of independent instances (inputs.concat_instances) as one grouped system."""
+        return cls(ctx, batch.xyz, batch.tets, batch.coh, batch.dir_u, batch.dir_p, batch.group)
 
     def __del__(self):
         if getattr(self, "_h", None) is not None and _lib is not None:
@@ -178,11 +188,17 @@ class System:
         return torch.zeros(n, dtype=dtype, device=self.dev)
 
     def assemble(self, params, E, logk):
-        self.params = Params(*params.as_tuple()) if hasattr(params, "as_tuple") else params
+        """params: one parameter set, or a list with one per group of a batch system."""
+        many = isinstance(params, (list, tuple))
+        conv = lambda p: Params(*p.as_tuple()) if hasattr(p, "as_tuple") else p
+        plist = [conv(p) for p in params] if many else [conv(params)]
+        arr = (Params * len(plist))(*plist)
+        self.params = plist[0]
         self.E = E if isinstance(E, torch.Tensor) else torch.as_tensor(np.asarray(E, np.float64), device=self.dev)
         self.logk = logk if isinstance(logk, torch.Tensor) else torch.as_tensor(np.asarray(logk, np.float64), device=self.dev)
-        _check(lib().fg_assemble(self.ctx._h, self._h, C.byref(self.params), _ptr(self.E, torch.float64, self.ne, "E"),
-                                 _ptr(self.logk, torch.float64, self.ne, "log_k"), _stream()))
+        _check(lib().fg_assemble_groups(self.ctx._h, self._h, arr, len(plist),
+                                        _ptr(self.E, torch.float64, self.ne, "E"),
+                                        _ptr(self.logk, torch.float64, self.ne, "log_k"), _stream()))
 
     def cohesive_update(self, U, die_n, t0, write_tangent=True):
         nq = self.nq
@@ -280,6 +296,14 @@ class System:
                                  _ptr(f_p, torch.float64, n1), _ptr(Rm, torch.float64), _ptr(Rf, torch.float64),
                                  _stream()), False)
         return Rm, Rf
+
+    def group_stats(self):
+        """Per-group (iterations, relative residual, status) of the last solve on a batched system."""
+        G = self.ngroups
+        it, rr, stt = np.zeros(G, np.int64), np.zeros(G), np.zeros(G, np.int32)
+        n = C.c_int()
+        _check(lib().fg_group_stats(self._h, it.ctypes.data, rr.ctypes.data, stt.ctypes.data, C.byref(n)), False)
+        return it, rr, stt
 
     def tune(self, key, value):
         _check(lib().fg_tune(self._h, key.encode(), int(value)), False)

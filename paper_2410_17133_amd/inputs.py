@@ -18,6 +18,10 @@ Mesh conventions (the library header states the same ones):
   * a dipping fault uses a column-shift map of the grid: node (i,j,k) keeps its
     topology and gets x = x_f(z) i/i_f on the - side and
     x_f + (Lx-x_f)(i-i_f)/(nx-i_f) on the + side, x_f(z) = x_mid + (z-z_mid)cot(dip)
+  * below 45 degrees that plane would leave the cube through its top and bottom,
+    so the fault is the grid plane k = n/2 with the z-layers shifted instead,
+    z_f(x) = z_mid + (x-x_mid) tan(dip) (built as the (90-dip) mesh with x and z
+    exchanged)
 """
 from __future__ import annotations
 
@@ -237,9 +241,22 @@ class Instance:
         return self.mesh.n_nodes
 
 
+def swap_xz(mesh: Mesh) -> Mesh:
+    """The mesh mirrored through the plane x = z (coordinates and grid indices
+    exchanged), with tetrahedra and interface triangles re-oriented."""
+    xyz = np.ascontiguousarray(mesh.xyz[:, [2, 1, 0]])
+    tets = np.ascontiguousarray(mesh.tets[:, [0, 1, 3, 2]])
+    coh = np.ascontiguousarray(mesh.coh[:, [0, 2, 1, 3, 5, 4]]) if mesh.coh.size else mesh.coh
+    grid = np.ascontiguousarray(mesh.grid[:, [2, 1, 0]])
+    return Mesh(mesh.nz, mesh.ny, mesh.nx, xyz, tets, coh, mesh.pairs, grid, mesh.n_orig)
+
+
 def make_instance(cfg: Config, seed: int = 0) -> Instance:
     n = cfg.n
-    mesh = make_mesh(n, n, n, fault_i=n // 2 if cfg.fault else None, dip_deg=cfg.dip_deg)
+    if cfg.fault and cfg.dip_deg < 45.0:
+        mesh = swap_xz(make_mesh(n, n, n, fault_i=n // 2, dip_deg=90.0 - cfg.dip_deg))
+    else:
+        mesh = make_mesh(n, n, n, fault_i=n // 2 if cfg.fault else None, dip_deg=cfg.dip_deg)
     ne = mesh.tets.shape[0]
     if cfg.heterogeneous:
         logk = rng(seed, STREAM_LOGK).normal(cfg.lnk_mean, cfg.lnk_sigma, size=ne)
@@ -299,3 +316,48 @@ def source_matrix(inst: Instance, pairs: np.ndarray, rates: np.ndarray) -> np.nd
         S[c, a] += 0.5 * q
         S[c, b] += 0.5 * q
     return S
+
+
+def batched_configs(count: int = 48, seed: int = 0, n_range=(16, 48), dip_range=(30.0, 90.0)):
+    """Seeded uneven instances: n ~ U{n_range}, dip ~ U[dip_range], heterogeneous."""
+    g = rng(seed, STREAM_INSTANCES)
+    ns = g.integers(n_range[0] // 2, n_range[1] // 2 + 1, size=count) * 2     # even n: the fault sits at n/2
+    dips = g.uniform(dip_range[0], dip_range[1], size=count)
+    return [cube_config(int(n), dip_deg=float(d), heterogeneous=True, name=f"batch{i}_n{n}_dip{d:.1f}")
+            for i, (n, d) in enumerate(zip(ns, dips))]
+
+
+@dataclass
+class Batch:
+    """Several instances concatenated into one disjoint mesh; group[node] = instance."""
+    instances: list
+    xyz: np.ndarray
+    tets: np.ndarray
+    coh: np.ndarray
+    group: np.ndarray
+    dir_u: np.ndarray
+    dir_p: np.ndarray
+    E: np.ndarray
+    logk: np.ndarray
+    source: np.ndarray
+    t0: np.ndarray
+    node_off: np.ndarray
+    tet_off: np.ndarray
+    coh_off: np.ndarray
+
+
+def concat_instances(instances) -> Batch:
+    node_off = np.cumsum([0] + [i.n_nodes for i in instances])
+    tet_off = np.cumsum([0] + [i.mesh.tets.shape[0] for i in instances])
+    coh_off = np.cumsum([0] + [i.mesh.coh.shape[0] for i in instances])
+    cat = lambda xs: np.ascontiguousarray(np.concatenate(xs))
+    return Batch(
+        instances,
+        cat([i.mesh.xyz for i in instances]),
+        cat([i.mesh.tets + o for i, o in zip(instances, node_off)]).astype(np.int32),
+        cat([i.mesh.coh + o for i, o in zip(instances, node_off)]).astype(np.int32),
+        cat([np.full(i.n_nodes, g, np.int32) for g, i in enumerate(instances)]),
+        cat([i.dir_u for i in instances]), cat([i.dir_p for i in instances]),
+        cat([i.E for i in instances]), cat([i.logk for i in instances]),
+        cat([i.source for i in instances]), cat([i.t0 for i in instances]),
+        node_off, tet_off, coh_off)

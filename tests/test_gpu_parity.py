@@ -47,6 +47,7 @@ CASES = {
     "cube8": lambda: I.make_instance(I.config(1)),
     "cube12_dip60_hetero": lambda: I.make_instance(I.cube_config(12, dip_deg=60, heterogeneous=True)),
     "cube16_dip70": lambda: I.make_instance(I.cube_config(16, dip_deg=70)),
+    "cube10_dip35_hetero": lambda: I.make_instance(I.cube_config(10, dip_deg=35, heterogeneous=True)),
 }
 
 _cache = {}
@@ -375,4 +376,76 @@ def test_block_solve_mixed_precision_and_errors():
     assert i32.status == 0
     with pytest.raises(fg.FgError) as e:
         S.pcg_solve(fg.FG_K, dev(np.zeros(3 * 3 * S.N)), nrhs=3)
+    assert e.value.status == fg.FG_ERR_ARG
+
+
+# ------------------------------------------------------------------ batched instances
+def _batch():
+    cfgs = [I.cube_config(4), I.cube_config(6, dip_deg=30, heterogeneous=True),
+            I.cube_config(8, dip_deg=60, heterogeneous=True), I.cube_config(6, dip_deg=40)]
+    return [I.make_instance(c, seed=i + 1) for i, c in enumerate(cfgs)]
+
+
+def test_batched_system_matches_separate_solves():
+    fg, O = _fg(), _oracle()
+    insts = _batch()
+    B = I.concat_instances(insts)
+    ctx = fg.Context(0)
+    S = fg.System.from_batch(ctx, B)
+    assert S.ngroups == len(insts)
+    assert len({i.params.k_n for i in insts}) > 1            # resolutions differ, so penalties differ
+    with pytest.raises(fg.FgError):
+        S.assemble([insts[0].params] * 2, B.E, B.logk)        # neither one set nor one per group
+    S.assemble([i.params for i in insts], B.E, B.logk)
+    S.cohesive_update(dev(np.zeros(3 * S.N)), dev(np.zeros(2 * S.nq)), dev(B.t0.reshape(-1)))
+    r = np.random.default_rng(11)
+    b = r.standard_normal(3 * S.N) * (1 - B.dir_u) * np.repeat(np.logspace(-2, 2, len(insts)), np.diff(B.node_off) * 3)
+    x, info = S.pcg_solve(fg.FG_K, dev(b), tol=1e-12)
+    assert info.status == 0
+    x = host(x)
+    iters, rel, stt = S.group_stats()
+    assert np.all(stt == 0) and np.all(rel <= 1e-12)
+    for g, inst in enumerate(insts):
+        lo, hi = 3 * B.node_off[g], 3 * B.node_off[g + 1]
+        Si = fg.System.from_instance(ctx, inst)
+        Si.assemble(inst.params, inst.E, inst.logk)
+        Si.cohesive_update(dev(np.zeros(3 * Si.N)), dev(np.zeros(2 * Si.nq)), dev(inst.t0.reshape(-1)))
+        xi, ii = Si.pcg_solve(fg.FG_K, dev(b[lo:hi]), tol=1e-12)
+        assert relerr(x[lo:hi], host(xi)) < 1e-10
+        assert abs(int(iters[g]) - ii.iters) <= 2 + ii.iters // 100     # reduction order differs
+        P = O.Problem(inst)
+        P.cohesive(np.zeros(3 * P.N), np.zeros((P.nq, 2)))
+        xo, st, it, rr = P.pcg(O.K_TANGENT, b[lo:hi], tol=1e-12)
+        assert relerr(x[lo:hi], xo) < 1e-9
+    # mixed precision: every group reaches 1e-8 by its own FP64 residual
+    xm, im = S.pcg_solve(fg.FG_K, dev(b), tol=1e-8, precision=fg.FG_MIXED)
+    assert im.status == 0
+    xm = host(xm)
+    for g, inst in enumerate(insts):
+        lo, hi = 3 * B.node_off[g], 3 * B.node_off[g + 1]
+        P = O.Problem(inst)
+        P.cohesive(np.zeros(3 * P.N), np.zeros((P.nq, 2)))
+        assert np.linalg.norm(b[lo:hi] - P.spmv(O.K_TANGENT, xm[lo:hi])) <= 1e-8 * np.linalg.norm(b[lo:hi])
+    # pressure operator, one group with a zero right-hand side
+    bp = r.standard_normal(S.N)
+    bp[B.node_off[1]:B.node_off[2]] = 0
+    xp, ip = S.pcg_solve(fg.FG_A22, dev(bp), tol=1e-12)
+    xp = host(xp)
+    assert np.all(xp[B.node_off[1]:B.node_off[2]] == 0)
+    for g in (0, 2, 3):
+        inst = insts[g]
+        P = O.Problem(inst)
+        xo, st, it, rr = P.pcg(O.A22, bp[B.node_off[g]:B.node_off[g + 1]], tol=1e-12)
+        assert relerr(xp[B.node_off[g]:B.node_off[g + 1]], xo) < 1e-9
+
+
+def test_batch_rejects_elements_across_groups():
+    fg = _fg()
+    insts = _batch()[:2]
+    B = I.concat_instances(insts)
+    group = B.group.copy()
+    group[B.tets[0, 0]] = 1                               # a tet now spans two groups
+    ctx = fg.Context(0)
+    with pytest.raises(fg.FgError) as e:
+        fg.System(ctx, B.xyz, B.tets, B.coh, B.dir_u, B.dir_p, group)
     assert e.value.status == fg.FG_ERR_ARG
