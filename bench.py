@@ -11,9 +11,14 @@ correction of an injection step, through the C-ABI:
   coupling A_pu, K solve to 1e-8 relative residual (FP64 Jacobi-PCG),
   coupling A_up, A22 product and the Schur-CG update.
 value = K-PCG iterations per second of wall time over the whole step.
-Also reported (outside the timed steps): time to a 1e-8 relative residual of
-the same K solve in FP64 and in mixed precision, and the live HIP-event
-duration of the CG SpMV kernel against the HBM roofline.
+Also reported, outside the timed steps (--extras selects them):
+  roofline  live HIP-event duration of the CG SpMV kernel against HBM peak
+  tt8       time to a 1e-8 relative residual of the step's K solve, FP64 vs mixed
+  adjoint   gradients/s of one implicit 64^3 step (forward timed separately)
+  block     32 right-hand sides on one 64^3 K: block CG vs 32 separate solves
+  batch     48 uneven instances (n 16..48, dip 30..90) in one grouped system vs
+            48 separate systems
+and the oracle on the same matrices (cpu_baseline at 128^3, and at 64^3).
 """
 import argparse
 import json
@@ -36,7 +41,9 @@ def main():
     ap.add_argument("--n", type=int, default=128, help="hexes per cube edge (128 = the 12.6M-tet workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=25, help="oracle PCG iterations timed for the CPU baseline")
-    ap.add_argument("--no-extras", action="store_true", help="skip the time-to-1e-8 comparison")
+    ap.add_argument("--no-extras", action="store_true", help="skip every extra measurement")
+    ap.add_argument("--extras", default="tt8,adjoint,block,batch",
+                    help="comma list of extra measurements: tt8, adjoint, block, batch")
     ap.add_argument("--profile-iters", type=int, default=0,
                     help="profiling mode for hardware counters: run exactly this many FP64 K-PCG iterations and "
                          "one 1 GiB device copy (counter calibration), print a short JSON line, skip the rest")
@@ -102,11 +109,15 @@ def main():
     # timed pass: production configuration (CG batches replayed as HIP graphs)
     torch.cuda.synchronize()
     k_iters = 0
+    per_step = []
     t = time.perf_counter()
     for s in range(args.steps):
+        ts = time.perf_counter()
         info = step()
         k_iters += info.inner_k_iters
-        log(f"step {s}: K iters {info.inner_k_iters} A22 iters {info.inner_a22_iters}")
+        per_step.append(info.inner_k_iters / (time.perf_counter() - ts))   # the step ends on a host sync
+        log(f"step {s}: K iters {info.inner_k_iters} A22 iters {info.inner_a22_iters} "
+            f"({per_step[-1]:.0f} K iters/s)")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t
     value = k_iters / elapsed
@@ -161,9 +172,12 @@ def main():
             "launches": launches,
             "timed_pass_iters_per_s": k_iters_p / elapsed_p,
         },
+        "per_step_iters_per_s": per_step,
+        "median_step_iters_per_s": float(np.median(per_step)),
     }
+    extras = set() if args.no_extras else set(e for e in args.extras.split(",") if e)
 
-    if not args.no_extras:
+    if "tt8" in extras:
         # time to 1e-8 of the step's K solve, FP64 vs mixed precision
         trac, die_new, flag, fcoh = S.cohesive_update(U, die, t0, write_tangent=True)
         Rm, Rf = S.residual(U, P, U, P, fcoh, load, src)
@@ -182,9 +196,170 @@ def main():
                                "mixed_inner_iters": res["mixed"][1], "mixed_cycles": res["mixed"][2],
                                "mixed_vs_f64_rel_l2": err, "speedup": res["f64"][0] / res["mixed"][0]}
 
+    del S
+    torch.cuda.empty_cache()
+    if "adjoint" in extras:
+        out["adjoint_64"] = extra_adjoint(ctx, log)
+    if "block" in extras:
+        out["block_64"] = extra_block(ctx, log)
+    if "batch" in extras:
+        out["batch_48"] = extra_batch(ctx, log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_iters, log)
+        if extras:
+            out["cpu_baseline_64"] = cpu_baseline(I.make_instance(I.config(2)), 4 * args.cpu_iters, log)
     print(json.dumps(out), flush=True)
+
+
+def _timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t, r
+
+
+def extra_adjoint(ctx, log):
+    """Gradient of J = sum over fault pairs of |tangential jump|^2 + squared uplift at 32 seeded top
+    nodes, w.r.t. ln k and E of every tetrahedron, after one implicit injection step at 64^3."""
+    import numpy as np
+    import torch
+
+    from paper_2410_17133_amd import fg
+    from paper_2410_17133_amd import inputs as I
+    from paper_2410_17133_amd.autograd import fault_slip_uplift_objective
+
+    inst = I.make_instance(I.config(4))
+    S = fg.System.from_instance(ctx, inst)
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float64)).cuda()
+    E, logk = d(inst.E), d(inst.logk)
+    S.assemble(inst.params, E, logk)
+    U, P, die = d(np.zeros(3 * S.N)), d(np.zeros(S.N)), d(np.zeros(2 * S.nq))
+    t0 = d(inst.t0.reshape(-1))
+    # tolerances: Newton 1e-8, partitioned CG 1e-8, inner K and A22 solves 1e-10 (relative)
+    inner = fg.opts(tol=1e-10, check_every=64)
+    t_fwd, (trac, flag, finfo) = _timed(lambda: S.step(U, P, die, t0, d(inst.load), d(inst.source), newton_tol=1e-8,
+                                                       inner_k=inner, inner_p=inner, outer_tol=1e-8))
+    log(f"adjoint: forward step {t_fwd:.2f}s newton {finfo.newton_iters} outer {finfo.outer_iters} "
+        f"K iters {finfo.inner_k_iters} status {finfo.status}; slip points {int((flag == 1).sum())}")
+    m = inst.mesh
+    X = m.xyz[m.coh[0, 3:]]
+    nrm = np.cross(X[1] - X[0], X[2] - X[0])
+    Uv = U.clone().requires_grad_(True)
+    J = fault_slip_uplift_objective(Uv, torch.as_tensor(m.pairs.astype(np.int64)).cuda(),
+                                    d(nrm / np.linalg.norm(nrm)),
+                                    torch.as_tensor(I.uplift_nodes(inst, 32).astype(np.int64)).cuda())
+    gU, = torch.autograd.grad(J, Uv)
+    gP = torch.zeros_like(P)
+    die0 = torch.zeros_like(die)
+    res = {}
+    for name, prec in (("f64", fg.FG_F64), ("mixed", fg.FG_MIXED)):
+        ik = fg.opts(tol=1e-10, check_every=64, precision=prec)
+        ip = fg.opts(tol=1e-10, check_every=64)
+        t_adj, (dE, dk, ainfo) = _timed(lambda: S.adjoint(U, P, die0, t0, logk, gU, gP, inner_k=ik, inner_p=ip,
+                                                           outer_tol=1e-8, defect_tol=1e-8))
+        log(f"adjoint {name}: {t_adj:.2f}s defect iters {ainfo.newton_iters} outer {ainfo.outer_iters} "
+            f"K iters {ainfo.inner_k_iters} status {ainfo.status}")
+        res[name] = (t_adj, ainfo, torch.cat([dE * E, dk]))
+    g64 = res["f64"][2]
+    return {"workload": f"cube64_dip60_hetero one implicit step, {inst.mesh.tets.shape[0]} tets, "
+                        f"{2 * inst.mesh.tets.shape[0]} parameters (ln k, E); tolerances Newton/outer/defect 1e-8, "
+                        f"inner 1e-10",
+            "forward_s": t_fwd, "forward_newton_iters": finfo.newton_iters, "forward_k_iters": finfo.inner_k_iters,
+            "grad_per_s_f64": 1.0 / res["f64"][0], "grad_per_s_mixed": 1.0 / res["mixed"][0],
+            "adjoint_s_f64": res["f64"][0], "adjoint_s_mixed": res["mixed"][0],
+            "defect_iters": res["f64"][1].newton_iters, "adjoint_k_iters_f64": res["f64"][1].inner_k_iters,
+            "mixed_vs_f64_grad_rel_l2": (torch.linalg.norm(res["mixed"][2] - g64) / torch.linalg.norm(g64)).item(),
+            "slip_points": int((flag == 1).sum())}
+
+
+def extra_block(ctx, log):
+    """32 injection scenarios on one 64^3 tangent: the first K solve of each scenario's partitioned
+    CG, b_s = A_pu A22^{-1} (dt q_s), solved to 1e-8 as one 32-column block and as 32 solves."""
+    import numpy as np
+    import torch
+
+    from paper_2410_17133_amd import fg
+    from paper_2410_17133_amd import inputs as I
+
+    inst = I.make_instance(I.config(5))
+    S = fg.System.from_instance(ctx, inst)
+    S.assemble(inst.params, inst.E, inst.logk)
+    pairs, rates = I.injection_scenarios(inst, 32)
+    Q = I.source_matrix(inst, pairs, rates) * inst.params.dt
+    cols = []
+    for q in Q:
+        z, _ = S.pcg_solve(fg.FG_A22, torch.as_tensor(q).cuda(), tol=1e-12)
+        cols.append(S.coupling(z))
+    B = torch.stack(cols).reshape(-1).contiguous()
+    res = {}
+    for name, prec in (("mixed", fg.FG_MIXED), ("f64", fg.FG_F64)):
+        S.pcg_solve(fg.FG_K, B, nrhs=32, tol=1e-8, precision=prec)          # graphs captured
+        tb, (Xb, ib) = _timed(lambda: S.pcg_solve(fg.FG_K, B, nrhs=32, tol=1e-8, precision=prec))
+        n3 = 3 * S.N
+
+        def separate():
+            it = 0
+            for c in range(32):
+                x, i1 = S.pcg_solve(fg.FG_K, B[c * n3:(c + 1) * n3], tol=1e-8, precision=prec, check_every=64)
+                it += i1.iters
+            return it
+        ts, its = _timed(separate)
+        log(f"block {name}: 32 columns {tb:.2f}s ({ib.iters} iters, {ib.cycles} cycles) vs separate {ts:.2f}s "
+            f"({its} iters)")
+        res[name] = {"block_s": tb, "separate_s": ts, "speedup": ts / tb, "block_iters": ib.iters,
+                     "block_cycles": ib.cycles, "separate_iters_total": its}
+    return {"workload": f"cube64_dip60_hetero, {S.N} nodes, 32 injection right-hand sides on one K, to 1e-8",
+            **res}
+
+
+def extra_batch(ctx, log):
+    """48 seeded uneven instances in one grouped system against 48 separate systems: the first K
+    solve of each instance's partitioned CG, b = A_pu A22^{-1} (dt q), to 1e-8 per instance."""
+    import numpy as np
+    import torch
+
+    from paper_2410_17133_amd import fg
+    from paper_2410_17133_amd import inputs as I
+
+    t = time.perf_counter()
+    insts = [I.make_instance(c) for c in I.batched_configs(48)]
+    Bt = I.concat_instances(insts)
+    G = fg.System.from_batch(ctx, Bt)
+    G.assemble([i.params for i in insts], Bt.E, Bt.logk)
+    log(f"batch: {len(insts)} instances, {Bt.xyz.shape[0]} nodes, {Bt.tets.shape[0]} tets "
+        f"({time.perf_counter() - t:.1f}s)")
+    dt = insts[0].params.dt
+    z, _ = G.pcg_solve(fg.FG_A22, torch.as_tensor(Bt.source * dt).cuda(), tol=1e-12)
+    b = G.coupling(z)
+    res = {}
+    singles = []
+    for i, inst in enumerate(insts):
+        Si = fg.System.from_instance(ctx, inst)
+        Si.assemble(inst.params, inst.E, inst.logk)
+        singles.append(Si)
+    for name, prec in (("f64", fg.FG_F64), ("mixed", fg.FG_MIXED)):
+        G.pcg_solve(fg.FG_K, b, tol=1e-8, precision=prec, check_every=64)
+        tg, (xg, ig) = _timed(lambda: G.pcg_solve(fg.FG_K, b, tol=1e-8, precision=prec, check_every=64))
+        iters, rel, stt = G.group_stats()
+
+        def separate():
+            it = 0
+            for i, Si in enumerate(singles):
+                lo, hi = 3 * Bt.node_off[i], 3 * Bt.node_off[i + 1]
+                x, i1 = Si.pcg_solve(fg.FG_K, b[lo:hi], tol=1e-8, precision=prec, check_every=64)
+                it += i1.iters
+            return it
+        separate()
+        ts, its = _timed(separate)
+        log(f"batch {name}: grouped {tg:.2f}s (max {ig.iters} iters, worst relres {ig.relres:.1e}) vs separate "
+            f"{ts:.2f}s ({its} iters)")
+        res[name] = {"grouped_s": tg, "separate_s": ts, "speedup": ts / tg, "grouped_max_iters": ig.iters,
+                     "group_iters_total": int(iters.sum()), "separate_iters_total": its,
+                     "all_converged": bool(np.all(stt == 0))}
+    return {"workload": f"48 instances n~U{{16..48}} dip~U[30,90] heterogeneous: {Bt.xyz.shape[0]} nodes, "
+                        f"{Bt.tets.shape[0]} tets; first K solve of each to 1e-8", **res}
 
 
 def cpu_baseline(inst, iters, log):
@@ -203,7 +378,11 @@ def cpu_baseline(inst, iters, log):
     x, st, it, rr = P.pcg(O.K_TANGENT, b, tol=1e-30, maxit=iters)
     dt = time.perf_counter() - t
     log(f"oracle: {it} PCG iterations in {dt:.2f}s")
+    nnz = P.scipy(O.K_TANGENT).nnz
+    # CSR value + column per stored entry, row pointers, and the vector passes of one iteration
+    bytes_it = 12.0 * nnz + 8.0 * (3 * P.N + 1) + 8.0 * 3 * P.N * 12
     return {"value": it / dt, "unit": "PCG iters/s", "cores": O.num_threads(), "kind": "oracle",
+            "gbs": bytes_it * it / dt / 1e9,
             "sample": f"{it} FP64 CSR Jacobi-PCG iterations of the oracle on the same {inst.mesh.tets.shape[0]}-tet "
                       f"tangent stiffness (assembly excluded)"}
 

@@ -279,11 +279,21 @@ fg_status fg_group_stats(const fg_system *sys, int64_t *iters_h, double *relres_
 /* Tuning knobs of the products (the autotuner's search space).
  *   "halo_cap": largest per-slice halo whose x is staged in LDS; slices with a
  *               larger halo gather x from global memory (0 = never stage).
- *               Clipped to what 64 KB of LDS per 4-wavefront workgroup holds.
+ *               Default: the largest halo, up to 384.  Clipped to what 64 KB
+ *               of LDS per 4-wavefront workgroup holds.
  *   "graphs":   1 (default) replays each batch of CG iterations as a captured
  *               HIP graph, 0 launches the kernels one by one (same results).
- *   "rhs_tile": columns per pass of the block (many right-hand sides) product:
- *               1, 2, 4, 8 (default) or 16; the matrix is streamed once per tile.
+ *   "spmv_unroll": slots per unrolled step of the CG product: 2 (default),
+ *               3, 4 or 6.
+ *   "spmv_nt":  nontemporal-access mask of the CG product: 1 matrix values,
+ *               2 column indices, 4 halo lists, 8 product stores; 0, 1, 3,
+ *               7 (default) or 15.  Results are identical for every value.
+ *   "rhs_tile": product of the block (many right-hand sides) solve.  0
+ *               (default): with 8 or more columns, the columns of a row are
+ *               spread over the lanes and the matrix is streamed once per
+ *               product (fewer columns: tiles of 8).  1, 2, 4, 8 or 16: one
+ *               lane per row with that many columns per pass, the matrix
+ *               streamed once per tile.  Results agree to rounding.
  * Returns FG_ERR_ARG for an unknown key or a negative value. */
 fg_status fg_tune(fg_system *sys, const char *key, int64_t value);
 

@@ -470,8 +470,9 @@ fg_status fg_system_create(fg_ctx *ctx, const fg_mesh *mesh, fg_system **out)
     CK(upload(&S->halo_ptr, P.halo_ptr));
     CK(upload(&S->halo, P.halo));
     CK(upload(&S->lcol, P.lcol));
-    // LDS window per wavefront: the largest halo, within 64 KB per 4-wave workgroup of FP64 3-vectors
-    S->halo_cap = (int)std::min<int64_t>(P.halo_max, 65536 / (4 * 3 * (int64_t)sizeof(double)));
+    // LDS window per wavefront: the largest halo up to 384 nodes (37 KB per 4-wave workgroup of FP64
+    // 3-vectors, so that four workgroups share a CU); slices with larger halos gather from memory
+    S->halo_cap = (int)std::min<int64_t>(P.halo_max, 384);
     std::vector<double> xyz(3 * S->Npad, 0.0);
     for (int64_t r = 0; r < S->Npad; ++r)
         if (P.perm[r] >= 0)
@@ -531,7 +532,7 @@ fg_status fg_system_create(fg_ctx *ctx, const fg_mesh *mesh, fg_system **out)
         fg_system_destroy(S);
         return FG_ERR_OOM;
     }
-    S->mpart_stride = std::max<int64_t>(((S->nslices + 3) / 4 + 7) / 8 * 8, 2048) + 8;
+    S->mpart_stride = std::max<int64_t>((S->nslices + 7) / 8 * 8, 2048) + 8;  // one partial per slice at most
     if (dalloc(&S->mpart, 2 * (int64_t)MR_MAX * S->mpart_stride) || dalloc(&S->msc, 1) || dalloc(&S->mred, MR_MAX) ||
         hipHostMalloc((void **)&S->msc_host, sizeof(MrScalars)) != hipSuccess ||
         hipHostMalloc((void **)&S->mred_host, MR_MAX * sizeof(double)) != hipSuccess) {
@@ -1006,9 +1007,27 @@ fg_status fg_tune(fg_system *S, const char *key, int64_t value)
         drop_group_graphs(S);
         return FG_OK;
     }
+    if (std::strcmp(key, "spmv_unroll") == 0) {
+        if (value != 2 && value != 3 && value != 4 && value != 6) {
+            set_error("fg_tune: spmv_unroll must be 2, 3, 4 or 6");
+            return FG_ERR_ARG;
+        }
+        S->spmv_unroll = (int)value;
+        drop_graphs(S);
+        return FG_OK;
+    }
+    if (std::strcmp(key, "spmv_nt") == 0) {
+        if (value != 0 && value != 1 && value != 3 && value != 7 && value != 15) {
+            set_error("fg_tune: spmv_nt must be 0, 1, 3, 7 or 15");
+            return FG_ERR_ARG;
+        }
+        S->spmv_nt = (int)value;
+        drop_graphs(S);
+        return FG_OK;
+    }
     if (std::strcmp(key, "rhs_tile") == 0) {
-        if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16) {
-            set_error("fg_tune: rhs_tile must be 1, 2, 4, 8 or 16");
+        if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8 && value != 16) {
+            set_error("fg_tune: rhs_tile must be 0, 1, 2, 4, 8 or 16");
             return FG_ERR_ARG;
         }
         S->mr_tile = (int)value;

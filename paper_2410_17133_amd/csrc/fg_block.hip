@@ -167,6 +167,122 @@ __global__ __launch_bounds__(WG) void k_mr_spmm(SpmvArgs a, int nrhs, const TV *
     }
 }
 
+// Q = K P with the columns of a row spread over the lanes: NR/2 lanes per row,
+// two adjacent columns per lane, so each gathered node's operands are one
+// contiguous run of 3*NR values read by a group of lanes together, and the
+// matrix is streamed once for all columns.  One workgroup per slice; its four
+// waves take 64/NR*2 rows at a time.  Per-column partials of P.Q go to
+// partials[c*stride + block] (P of the row itself comes from the diagonal slot).
+template <typename T>
+struct Pair;
+template <>
+struct Pair<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Pair<float> {
+    typedef float type __attribute__((ext_vector_type(2)));
+};
+
+// Slots j0 .. j0+U-1 of one row for the row-group product (slots past the
+// row's length multiply zeros against the row's own operands).
+template <typename T, typename TV, int NR, int U>
+__device__ __forceinline__ void mr_rows_slots(int j0, int len, int dj, int64_t r, int gb, int c2,
+                                              const int32_t *__restrict__ cl, const TV *__restrict__ vb,
+                                              const T *__restrict__ p, typename Pair<T>::type (&acc)[3],
+                                              typename Pair<T>::type (&dp)[3])
+{
+    typedef typename Pair<T>::type T2;
+    constexpr int LPR = NR / 2, NL = (9 + LPR - 1) / LPR;
+    int64_t cj[U];
+    T mv[U][NL];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int j = j0 + u;
+        const bool on = j < len;
+        cj[u] = on ? (int64_t)cl[(int64_t)j * SLICE] : r;
+#pragma unroll
+        for (int w = 0; w < NL; ++w) {
+            const int e = w * LPR + c2;
+            mv[u][w] = (on && e < 9) ? (T)vb[(int64_t)(9 * j + e) * SLICE] : (T)0;
+        }
+    }
+    T2 xv[U][3];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const T2 *xp = (const T2 *)(p + 3 * cj[u] * NR) + c2;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) xv[u][k] = xp[k * LPR];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        T m[9];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) m[e] = __shfl(mv[u][e / LPR], gb + e % LPR, 64);
+#pragma unroll
+        for (int rr = 0; rr < 3; ++rr)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc[rr] += m[3 * rr + k] * xv[u][k];
+        if (j0 + u == dj)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) dp[k] = xv[u][k];
+    }
+}
+
+template <typename T, typename TV, int NR>
+__global__ __launch_bounds__(WG) void k_mr_rows(SpmvArgs a, const uint8_t *__restrict__ rowlen,
+                                                const TV *__restrict__ val, const T *__restrict__ p,
+                                                T *__restrict__ q, double *partials, int64_t stride, int with_dot)
+{
+    typedef typename Pair<T>::type T2;
+    constexpr int LPR = NR / 2, RPW = SLICE / LPR, RPB = (WG / SLICE) * RPW, PASSES = SLICE / RPB;
+    constexpr int U = 1;  // deeper unrolling measured no faster: the gathers are bound by the cache, not latency
+    const int64_t s = xcd_block();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane / LPR, c2 = lane % LPR;
+    double v0 = 0, v1 = 0;
+    if (s < a.nslices) {
+        const int64_t base = a.slice_ptr[s];
+        for (int ps = 0; ps < PASSES; ++ps) {
+            const int l = ps * RPB + wave * RPW + g;
+            const int64_t r = s * SLICE + l;
+            const int len = rowlen[r], dj = a.diag_slot[r];
+            const int32_t *cl = a.col + base + l;
+            const TV *vb = val + 9 * base + l;
+            T2 acc[3], dp[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc[k] = T2{0, 0}, dp[k] = T2{0, 0};
+            // the 9 values of a slot are loaded once per row group, one per lane, and
+            // broadcast to the group's lanes (lane e mod LPR holds value e)
+            const int gb = lane - c2;
+            int len_w = len;  // the wave's longest row: every lane takes part in the broadcasts
+            for (int off = LPR; off < SLICE; off <<= 1) len_w = max(len_w, __shfl_xor(len_w, off, 64));
+            for (int j0 = 0; j0 < len_w; j0 += U) mr_rows_slots<T, TV, NR, U>(j0, len, dj, r, gb, c2, cl, vb, p, acc, dp);
+            T2 *qp = (T2 *)(q + 3 * r * NR) + c2;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                qp[k * LPR] = acc[k];
+                v0 += (double)dp[k].x * (double)acc[k].x;
+                v1 += (double)dp[k].y * (double)acc[k].y;
+            }
+        }
+    }
+    if (!with_dot) return;
+    // lanes with the same column pair: across the row groups of the wave, then across waves
+    for (int off = LPR; off < SLICE; off <<= 1) {
+        v0 += __shfl_xor(v0, off, 64);
+        v1 += __shfl_xor(v1, off, 64);
+    }
+    __shared__ double sh[WG / SLICE][NR];
+    if (g == 0) sh[wave][2 * c2] = v0, sh[wave][2 * c2 + 1] = v1;
+    __syncthreads();
+    if ((int)threadIdx.x < NR) {
+        double t = 0;
+        for (int w = 0; w < WG / SLICE; ++w) t += sh[w][threadIdx.x];
+        partials[(int64_t)threadIdx.x * stride + blockIdx.x] = t;
+    }
+}
+
 __global__ __launch_bounds__(FIN) void k_mr_alpha(const double *partials, int nrhs, int64_t stride, int64_t nparts,
                                                   MrScalars *sc)
 {
@@ -324,12 +440,33 @@ inline int log2i(int v)
 
 }  // namespace
 
+// Q = K P for all columns; returns the number of per-column partials written.
+// rhs_tile 0 (default): the row-group kernel for nrhs >= 8; otherwise the
+// column-tile kernel with rhs_tile columns per pass.
 template <typename T, typename TV>
-static void mr_launch_spmm(fg_system *S, int nrhs, const TV *val, const T *p, T *q, int with_dot, hipStream_t st)
+static int64_t mr_launch_spmm(fg_system *S, int nrhs, const TV *val, const T *p, T *q, int with_dot, hipStream_t st)
 {
-    const int64_t gx = grid_xcd((S->nslices + 3) / 4);
-    const int ct = std::min(S->mr_tile, nrhs);
     const SpmvArgs a = spmv_args(S);
+    if (S->mr_tile == 0 && nrhs >= 8) {
+        const int64_t gr = grid_xcd(S->nslices);
+        switch (nrhs) {
+        case 8:
+            LAUNCH((k_mr_rows<T, TV, 8>), gr, WG, st, a, S->rowlen, val, p, q, S->mpart, S->mpart_stride, with_dot);
+            break;
+        case 16:
+            LAUNCH((k_mr_rows<T, TV, 16>), gr, WG, st, a, S->rowlen, val, p, q, S->mpart, S->mpart_stride, with_dot);
+            break;
+        case 32:
+            LAUNCH((k_mr_rows<T, TV, 32>), gr, WG, st, a, S->rowlen, val, p, q, S->mpart, S->mpart_stride, with_dot);
+            break;
+        default:
+            LAUNCH((k_mr_rows<T, TV, 64>), gr, WG, st, a, S->rowlen, val, p, q, S->mpart, S->mpart_stride, with_dot);
+            break;
+        }
+        return gr;
+    }
+    const int64_t gx = grid_xcd((S->nslices + 3) / 4);
+    const int ct = S->mr_tile == 0 ? std::min(8, nrhs) : std::min(S->mr_tile, nrhs);
     switch (ct) {
     case 1:
         hipLaunchKernelGGL((k_mr_spmm<T, TV, 1>), dim3(gx, nrhs / 1), dim3(WG), 0, st, a, nrhs, val, p, q, S->mpart,
@@ -352,6 +489,7 @@ static void mr_launch_spmm(fg_system *S, int nrhs, const TV *val, const T *p, T 
                            S->mpart_stride, S->msc, with_dot);
         break;
     }
+    return gx;
 }
 
 template <typename T, typename TV>
@@ -359,9 +497,9 @@ static void mr_launch_batch(fg_system *S, int nrhs, const TV *val, const T *dinv
                             hipStream_t st)
 {
     const int64_t n = 3 * S->Npad * nrhs;
-    const int64_t ge = grid_cols(n), gx = grid_xcd((S->nslices + 3) / 4);
+    const int64_t ge = grid_cols(n);
     for (int it = 0; it < iters; ++it) {
-        mr_launch_spmm<T, TV>(S, nrhs, val, p, q, 1, st);
+        const int64_t gx = mr_launch_spmm<T, TV>(S, nrhs, val, p, q, 1, st);
         hipLaunchKernelGGL(k_mr_alpha, dim3(nrhs), dim3(FIN), 0, st, S->mpart, nrhs, S->mpart_stride, gx, S->msc);
         hipLaunchKernelGGL((k_mr_update<T>), dim3(ge), dim3(WG), 0, st, n, nrhs, log2i(nrhs), dinv, x, r, p, q, S->mpart,
                            S->mpart_stride, S->msc);

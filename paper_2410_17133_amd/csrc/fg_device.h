@@ -78,6 +78,16 @@ inline int64_t grid_elems(int64_t n)
     return g < 2048 ? (g < 1 ? 1 : g) : 2048;
 }
 
+// Load of data streamed once per product (nontemporal hint when NT).
+template <bool NT, typename TV>
+__device__ __forceinline__ TV ld_val(const TV *p)
+{
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
 struct SpmvArgs {
     int64_t nslices;
     const int64_t *slice_ptr;
@@ -94,7 +104,7 @@ struct SpmvArgs {
 // the slots: the 9 (or 1) values of a slot are 64-wide coalesced loads and the
 // x operands come from LDS through 16-bit local column indices.  A slice whose
 // halo exceeds the LDS window (irregular meshes) gathers x from global memory.
-template <int BS, typename T>
+template <int BS, typename T, bool NT = true>
 __device__ __forceinline__ bool stage_halo(int64_t s, int lane, const int64_t *__restrict__ halo_ptr,
                                            const int32_t *__restrict__ halo, int cap, const T *__restrict__ x, T *xs)
 {
@@ -102,7 +112,7 @@ __device__ __forceinline__ bool stage_halo(int64_t s, int lane, const int64_t *_
     const int hn = (int)(halo_ptr[s + 1] - h0);
     if (hn > cap) return false;
     for (int i = lane; i < hn; i += SLICE) {
-        const int64_t node = halo[h0 + i];
+        const int64_t node = ld_val<NT>(halo + h0 + i);
 #pragma unroll
         for (int k = 0; k < BS; ++k) xs[BS * i + k] = x[BS * node + k];
     }
@@ -111,8 +121,8 @@ __device__ __forceinline__ bool stage_halo(int64_t s, int lane, const int64_t *_
 
 // y = A x for one row (lane) of a slice; IDX is uint16_t (halo-local, xs in LDS)
 // or int32_t (global, xs = x).  dj: slot of the row's diagonal, whose x is
-// returned in d0..d2 (for p.Ap).
-template <int BS, typename T, typename TV, typename IDX>
+// returned in d0..d2 (for p.Ap).  UNR slots are unrolled per step.
+template <int BS, typename T, typename TV, typename IDX, int UNR = 2, int NT = 3>
 __device__ __forceinline__ void slice_row(int64_t base, int w, int lane, int dj, const IDX *__restrict__ idx,
                                           const TV *__restrict__ val, const T *xs, T (&y)[BS], T (&d)[BS])
 {
@@ -120,9 +130,9 @@ __device__ __forceinline__ void slice_row(int64_t base, int w, int lane, int dj,
     const TV *v = val + BS * BS * base + lane;
 #pragma unroll
     for (int r = 0; r < BS; ++r) y[r] = 0, d[r] = 0;
-#pragma unroll 3
+#pragma unroll UNR
     for (int j = 0; j < w; ++j) {
-        const int64_t cj = c[(int64_t)j * SLICE];
+        const int64_t cj = ld_val<(NT & 2) != 0>(c + (int64_t)j * SLICE);
         T xv[BS];
 #pragma unroll
         for (int k = 0; k < BS; ++k) xv[k] = xs[BS * cj + k];
@@ -130,7 +140,7 @@ __device__ __forceinline__ void slice_row(int64_t base, int w, int lane, int dj,
 #pragma unroll
         for (int r = 0; r < BS; ++r)
 #pragma unroll
-            for (int k = 0; k < BS; ++k) y[r] += (T)vb[(BS * r + k) * SLICE] * xv[k];
+            for (int k = 0; k < BS; ++k) y[r] += (T)ld_val<(NT & 1) != 0>(vb + (BS * r + k) * SLICE) * xv[k];
         if (j == dj)
 #pragma unroll
             for (int k = 0; k < BS; ++k) d[k] = xv[k];
@@ -138,7 +148,9 @@ __device__ __forceinline__ void slice_row(int64_t base, int w, int lane, int dj,
 }
 
 // q = A p for the rows of one slice; returns p.q of the lane's row.
-template <int BS, typename T, typename TV>
+// NT bit mask of nontemporal accesses: 1 matrix values, 2 column indices, 8 the
+// stores of y.
+template <int BS, typename T, typename TV, int UNR = 2, int NT = 3>
 __device__ __forceinline__ double slice_spmv(int64_t s, int lane, bool staged, const int64_t *__restrict__ slice_ptr,
                                              const int32_t *__restrict__ col, const uint16_t *__restrict__ lcol,
                                              const int32_t *__restrict__ diag_slot, const TV *__restrict__ val,
@@ -150,13 +162,16 @@ __device__ __forceinline__ double slice_spmv(int64_t s, int lane, bool staged, c
     const int dj = diag_slot[r];
     T yv[BS], d[BS];
     if (staged)
-        slice_row<BS, T, TV, uint16_t>(base, w, lane, dj, lcol, val, xs, yv, d);
+        slice_row<BS, T, TV, uint16_t, UNR, NT>(base, w, lane, dj, lcol, val, xs, yv, d);
     else
-        slice_row<BS, T, TV, int32_t>(base, w, lane, dj, col, val, x, yv, d);
+        slice_row<BS, T, TV, int32_t, UNR, NT>(base, w, lane, dj, col, val, x, yv, d);
     double pq = 0;
 #pragma unroll
     for (int k = 0; k < BS; ++k) {
-        y[BS * r + k] = yv[k];
+        if constexpr ((NT & 8) != 0)
+            __builtin_nontemporal_store(yv[k], y + BS * r + k);
+        else
+            y[BS * r + k] = yv[k];
         pq += (double)d[k] * (double)yv[k];
     }
     return pq;

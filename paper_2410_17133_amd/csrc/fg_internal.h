@@ -164,7 +164,10 @@ struct fg_system {
     fg::GraphCache cg_graph[3];
     // block solves (many right-hand sides), column-interleaved workspaces
     int mr_cap = 0;   // columns allocated
-    int mr_tile = 8;  // columns per SpMM pass (fg_tune "rhs_tile")
+    int spmv_unroll = 2;  // fg_tune "spmv_unroll": slots per unrolled step of the CG product (2, 3, 4, 6)
+    int spmv_nt = 7;      // fg_tune "spmv_nt": nontemporal-access mask of the CG product (values 1, indices 2,
+                          // halo lists 4, product stores 8)
+    int mr_tile = 0;  // fg_tune "rhs_tile": 0 = row-group product, else columns per column-tile pass
     double *mx = nullptr, *mr = nullptr, *mp = nullptr, *mq = nullptr, *mb = nullptr, *mx64 = nullptr, *mr64 = nullptr;
     float *mfx = nullptr, *mfr = nullptr, *mfp = nullptr, *mfq = nullptr;
     fg::MrScalars *msc = nullptr, *msc_host = nullptr;

@@ -772,7 +772,7 @@ __global__ __launch_bounds__(FIN) void k_cg_init_fin(const double *partials, int
 }
 
 // q = A p and the per-block partials of p.q.
-template <int BS, typename T, typename TV>
+template <int BS, typename T, typename TV, int UNR, int NT>
 __global__ __launch_bounds__(WG) void k_cg_spmv(SpmvArgs a, const TV *__restrict__ val, const T *__restrict__ p,
                                                 T *__restrict__ q, double *partials, int64_t stride,
                                                 const CgScalars *sc)
@@ -783,10 +783,11 @@ __global__ __launch_bounds__(WG) void k_cg_spmv(SpmvArgs a, const TV *__restrict
     T *xs = (T *)smem + (int64_t)wave * a.cap * BS;
     const int64_t s = xcd_block() * (WG / SLICE) + wave;
     bool staged = false;
-    if (s < a.nslices) staged = stage_halo<BS, T>(s, lane, a.halo_ptr, a.halo, a.cap, p, xs);
+    if (s < a.nslices) staged = stage_halo<BS, T, (NT & 4) != 0>(s, lane, a.halo_ptr, a.halo, a.cap, p, xs);
     __syncthreads();
     double v[1] = {0};
-    if (s < a.nslices) v[0] = slice_spmv<BS, T, TV>(s, lane, staged, a.slice_ptr, a.col, a.lcol, a.diag_slot, val, p, xs, q);
+    if (s < a.nslices)
+        v[0] = slice_spmv<BS, T, TV, UNR, NT & 11>(s, lane, staged, a.slice_ptr, a.col, a.lcol, a.diag_slot, val, p, xs, q);
     block_partials<1>(v, partials, stride);
 }
 
@@ -1087,6 +1088,32 @@ static void prof_collect(fg_system *S, int64_t worked)
     S->prof_pending = 0;
 }
 
+// The CG product with the tuned slot unroll depth and value-load hint.
+template <int BS, typename T, typename TV>
+static void cg_spmv_launch(fg_system *S, int64_t gs, const TV *val, const T *p, T *q, hipStream_t st)
+{
+    const size_t lds = spmv_lds<BS, T>(S);
+    const SpmvArgs a = spmv_args(S);
+#define FG_CG_SPMV(U, N)                                                                                    \
+    LAUNCH_SH((k_cg_spmv<BS, T, TV, U, N>), gs, WG, lds, st, a, val, p, q, S->partials, S->npartials, S->sc)
+#define FG_CG_SPMV_NT(U)                   \
+    switch (S->spmv_nt) {                  \
+    case 0: FG_CG_SPMV(U, 0); break;       \
+    case 1: FG_CG_SPMV(U, 1); break;       \
+    case 3: FG_CG_SPMV(U, 3); break;       \
+    case 7: FG_CG_SPMV(U, 7); break;       \
+    default: FG_CG_SPMV(U, 15); break;     \
+    }
+    switch (S->spmv_unroll) {
+    case 2: FG_CG_SPMV_NT(2); break;
+    case 4: FG_CG_SPMV_NT(4); break;
+    case 6: FG_CG_SPMV_NT(6); break;
+    default: FG_CG_SPMV_NT(3); break;
+    }
+#undef FG_CG_SPMV_NT
+#undef FG_CG_SPMV
+}
+
 template <int BS, typename T, typename TV>
 static void cg_launch_batch(fg_system *S, const TV *val, const T *dinv, T *x, T *r, T *p, T *q, int iters, int slot,
                             bool prof, hipStream_t st)
@@ -1096,8 +1123,7 @@ static void cg_launch_batch(fg_system *S, const TV *val, const T *dinv, T *x, T 
     const int64_t gs = grid_xcd((S->nslices + 3) / 4), ge = grid_elems(n);
     for (int it = 0; it < iters; ++it) {
         if (prof) hipEventRecord(ev[2 * it], st);
-        LAUNCH_SH((k_cg_spmv<BS, T, TV>), gs, WG, (spmv_lds<BS, T>(S)), st, spmv_args(S), val, p, q, S->partials,
-                  S->npartials, S->sc);
+        cg_spmv_launch<BS, T, TV>(S, gs, val, p, q, st);
         if (prof) hipEventRecord(ev[2 * it + 1], st);
         LAUNCH(k_cg_alpha, 1, FIN, st, S->partials, S->npartials, gs, S->sc);
         LAUNCH((k_cg_update<T>), ge, WG, st, n, dinv, x, r, p, q, S->partials, S->npartials, S->sc);

@@ -174,6 +174,34 @@ def test_pcg_global_gather_path_matches():
     assert relerr(host(x0), host(x1)) < 1e-10
 
 
+def test_product_tuning_knobs_do_not_change_results():
+    """Unroll depth and nontemporal access hints of the CG product change neither
+    the arithmetic nor its order: every setting gives bitwise the same iterates."""
+    fg, O = _fg(), _oracle()
+    inst, ctx, S, P = setup("cube12_dip60_hetero")
+    S.cohesive_update(dev(np.zeros(3 * S.N)), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)))
+    r = np.random.default_rng(12)
+    b = r.standard_normal(3 * S.N) * (1 - inst.dir_u)
+    bp = r.standard_normal(S.N)
+    ref = None
+    for unr, nt in ((2, 7), (3, 0), (4, 1), (6, 3), (2, 15), (3, 7)):
+        S.tune("spmv_unroll", unr)
+        S.tune("spmv_nt", nt)
+        xk, ik = S.pcg_solve(fg.FG_K, dev(b), tol=1e-10)
+        xa, ia = S.pcg_solve(fg.FG_A22, dev(bp), tol=1e-10)
+        xm, im = S.pcg_solve(fg.FG_K, dev(b), tol=1e-9, precision=fg.FG_MIXED)
+        got = (host(xk), ik.iters, host(xa), ia.iters, host(xm), im.iters)
+        if ref is None:
+            ref = got
+        for a_, b_ in zip(got, ref):
+            np.testing.assert_array_equal(a_, b_)
+    S.tune("spmv_unroll", 2)
+    S.tune("spmv_nt", 7)
+    for key, bad in (("spmv_unroll", 5), ("spmv_nt", 2)):
+        with pytest.raises(fg.FgError):
+            S.tune(key, bad)
+
+
 def test_graph_replay_matches_eager_launches():
     """CG batches replayed as captured graphs (many replays, host polls and eager
     kernels in between) give bitwise the same iterates as kernel-by-kernel launches."""
@@ -357,7 +385,14 @@ def test_block_solve_matches_single_column_solves():
         if ref is None:
             ref = Xt
         np.testing.assert_array_equal(Xt, ref)
-    S.tune("rhs_tile", 8)
+    # the row-group product (default) sums p.q in another order: same solution to rounding
+    S.tune("rhs_tile", 0)
+    X0, i0 = S.pcg_solve(fg.FG_K, dev(B.reshape(-1)), nrhs=nrhs, tol=1e-10)
+    X0 = host(X0).reshape(nrhs, -1)
+    for c in range(nrhs):
+        if c != 5:
+            assert relerr(X0[c], ref.reshape(nrhs, -1)[c]) < 1e-8
+    assert np.all(X0[5] == 0)
 
 
 def test_block_solve_mixed_precision_and_errors():
