@@ -115,6 +115,7 @@ typedef struct {
     double outer_relres;  /* last Prevost ||r||/||r0|| */
     double res_m, res_f;  /* scaled Newton residual norms at exit (fg_step) */
     int status;
+    int64_t step_cuts;    /* fg_step: halvings of the Newton step taken by the line search */
 } fg_solve_info;
 
 /* Thread-local message of the last failing call ("" if none). */
@@ -210,6 +211,11 @@ fg_status fg_flow_solve(fg_ctx *ctx, fg_system *sys, const double *b_u, const do
  *   R_f = A_up (U - U_n) + A22 (P - P_n) + dt (C P_n - f_p).
  * Stops when ||R_m|| <= tol s_m and ||R_f|| <= tol s_f, with
  * s_m = max(||R_m^0||, ||A_pu P||, ||F_u||) and s_f = max(||R_f^0||, dt ||f_p||).
+ * Newton steps are globalised by backtracking (on by default, fg_tune
+ * "line_search"): with s* = max(s_m, ||A_pu (P + dP)||) the merit
+ * (||R_m||/s*)^2 + (||R_f||/s_f)^2 must drop; step lengths 1, 1/2, ... 1/64 are
+ * tried in turn (1/64 is taken if none lowers it).  Full steps overshoot once
+ * slip spreads, because the Newton tangent omits the non-symmetric slip term.
  * In/out: U [3N], P [N], die [nq*2] (start-of-step inelastic slip in, final out).
  * Out: trac [nq*3], flag [nq].  In: t0 [nq*3], F_u [3N] total external force
  * change at t_n+1, f_p [N] volumetric sources. */
@@ -283,6 +289,8 @@ fg_status fg_group_stats(const fg_system *sys, int64_t *iters_h, double *relres_
  *               of LDS per 4-wavefront workgroup holds.
  *   "graphs":   1 (default) replays each batch of CG iterations as a captured
  *               HIP graph, 0 launches the kernels one by one (same results).
+ *   "line_search": 1 (default) backtracking on the Newton steps of fg_step,
+ *               0 full steps.
  *   "spmv_unroll": slots per unrolled step of the CG product: 2 (default),
  *               3, 4 or 6.
  *   "spmv_nt":  nontemporal-access mask of the CG product: 1 matrix values,

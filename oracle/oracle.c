@@ -935,9 +935,21 @@ void or_residual(or_problem *P, const double *U, const double *P_, const double 
  * In/out: U, P (totals since t = 0), die (inelastic slip per qp).
  * Out: trac, flag per qp.
  * info: [newton its, outer its, inner K its, inner A22 its, ||Rm||/s_m, ||Rf||/s_f, status] */
+/* Newton globalisation (not in the paper; the symmetric slip tangent makes full
+ * steps overshoot when slip spreads): the merit of an iterate is
+ *   phi = (||R_m|| / s*)^2 + (||R_f|| / s_f)^2,
+ * s* = max(s_m, ||A_pu (P + dP)||) fixed for the iteration (1 if zero), s_f the
+ * flow scale (1 if zero).  Step lengths 1, 1/2, ..., 1/64 are tried in turn and
+ * the first that lowers phi is taken; if none does, 1/64 is taken. */
+static double merit(double rm, double rf, double s_star, double sf)
+{
+    const double a = rm / (s_star > 0 ? s_star : 1.0), b = rf / (sf > 0 ? sf : 1.0);
+    return a * a + b * b;
+}
+
 int or_step(or_problem *P, double *U, double *Pp, double *die, double *trac, uint8_t *flag, const double *t0,
             const double *Fu, const double *fp, double tol_newton, int64_t max_newton, double tol_outer,
-            double tol_inner, int64_t maxit_outer, int64_t maxit_inner, double *info)
+            double tol_inner, int64_t maxit_outer, int64_t maxit_inner, int line_search, double *info)
 {
     int64_t N = P->N, nq = 3 * P->nf;
     double *Un = malloc(3 * N * sizeof(double)), *Pn = malloc(N * sizeof(double));
@@ -948,6 +960,11 @@ int or_step(or_problem *P, double *U, double *Pp, double *die, double *trac, uin
     double *fcoh = malloc(3 * N * sizeof(double)), *Rm = malloc(3 * N * sizeof(double)), *Rf = malloc(N * sizeof(double));
     double *du = malloc(3 * N * sizeof(double)), *dp = malloc(N * sizeof(double));
     double *t1 = malloc(3 * N * sizeof(double));
+    double *Ut = malloc(3 * N * sizeof(double)), *Pt = malloc(N * sizeof(double));
+    double *Rmt = malloc(3 * N * sizeof(double)), *Rft = malloc(N * sizeof(double));
+    double *tract = malloc((nq ? nq : 1) * 3 * sizeof(double)), *diet = malloc((nq ? nq : 1) * 2 * sizeof(double));
+    uint8_t *flagt = malloc(nq ? nq : 1);
+    int64_t cuts = 0;
     double sm = 0, sf = 0;
     int64_t it = 0;
     int status = 1;
@@ -984,8 +1001,24 @@ int or_step(or_problem *P, double *U, double *Pp, double *die, double *trac, uin
             status = s;
             break;
         }
-        for (int64_t i = 0; i < 3 * N; ++i) U[i] += du[i];
-        for (int64_t i = 0; i < N; ++i) Pp[i] += dp[i];
+        double step = 1.0;
+        if (line_search) {
+            for (int64_t i = 0; i < N; ++i) Pt[i] = Pp[i] + dp[i];
+            or_apply_Apu(P, Pt, t1);
+            const double s_star = fmax(sm, vnorm(3 * N, t1));
+            const double m0 = merit(rm, rf, s_star, sf);
+            for (;;) {
+                for (int64_t i = 0; i < 3 * N; ++i) Ut[i] = U[i] + step * du[i];
+                for (int64_t i = 0; i < N; ++i) Pt[i] = Pp[i] + step * dp[i];
+                or_cohesive(P, Ut, die_n, t0, tract, diet, flagt, fcoh);
+                or_residual(P, Ut, Pt, Un, Pn, fcoh, Fu, fp, Rmt, Rft);
+                if (merit(vnorm(3 * N, Rmt), vnorm(N, Rft), s_star, sf) < m0 || step <= 1.0 / 64) break;
+                step *= 0.5;
+                cuts++;
+            }
+        }
+        for (int64_t i = 0; i < 3 * N; ++i) U[i] += step * du[i];
+        for (int64_t i = 0; i < N; ++i) Pp[i] += step * dp[i];
         it++;
     }
     info[0] = (double)it;
@@ -995,6 +1028,14 @@ int or_step(or_problem *P, double *U, double *Pp, double *die, double *trac, uin
     info[4] = em;
     info[5] = ef;
     info[6] = (double)status;
+    info[7] = (double)cuts;
+    free(Ut);
+    free(Pt);
+    free(Rmt);
+    free(Rft);
+    free(tract);
+    free(diet);
+    free(flagt);
     free(Un);
     free(Pn);
     free(die_n);

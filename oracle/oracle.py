@@ -60,7 +60,7 @@ def lib():
         L.or_residual.argtypes = [C.c_void_p] + [_f64p] * 9
         L.or_step.restype = C.c_int
         L.or_step.argtypes = [C.c_void_p, _f64p, _f64p, _f64p, _f64p, _u8p, _f64p, _f64p, _f64p, C.c_double,
-                              C.c_int64, C.c_double, C.c_double, C.c_int64, C.c_int64, _f64p]
+                              C.c_int64, C.c_double, C.c_double, C.c_int64, C.c_int64, C.c_int, _f64p]
         L.or_tet_grad.argtypes = [_f64p, C.POINTER(C.c_double), _f64p]
         L.or_tet_stiffness.argtypes = [_f64p, C.c_double, C.c_double, _f64p]
         L.or_tet_coupling.argtypes = [_f64p, C.c_double, _f64p]
@@ -210,19 +210,21 @@ class Problem:
         return Rm, Rf
 
     def step(self, U, P, die, Fu=None, fp=None, tol_newton=1e-10, max_newton=30, tol_outer=1e-10,
-             tol_inner=1e-12, maxit_outer=500, maxit_inner=200000, t0=None):
-        """One implicit step; U, P, die are updated in place. Returns (trac, flag, info, status)."""
+             tol_inner=1e-12, maxit_outer=500, maxit_inner=200000, t0=None, line_search=True):
+        """One implicit step; U, P, die are updated in place. Returns (trac, flag, info, status);
+        info = (Newton iterations, outer, K and A22 inner iterations, scaled residuals m and f,
+        status, step-length cuts of the line search)."""
         Fu = np.zeros(3 * self.N) if Fu is None else _c(Fu, np.float64)
         fp = self.inst.source if fp is None else _c(fp, np.float64)
         t0 = self.inst.t0 if t0 is None else t0
         nq = max(self.nq, 1)
-        trac, flag, info = np.zeros(nq * 3), np.zeros(nq, np.uint8), np.zeros(7)
+        trac, flag, info = np.zeros(nq * 3), np.zeros(nq, np.uint8), np.zeros(8)
         dieb = np.zeros(nq * 2)
         dieb[: self.nq * 2] = die.reshape(-1)
         t0b = np.zeros(nq * 3)
         t0b[: self.nq * 3] = np.asarray(t0).reshape(-1)
         s = lib().or_step(self._h, U, P, dieb, trac, flag, t0b, Fu, fp, tol_newton, max_newton, tol_outer,
-                          tol_inner, maxit_outer, maxit_inner, info)
+                          tol_inner, maxit_outer, maxit_inner, int(bool(line_search)), info)
         die.reshape(-1)[:] = dieb[: self.nq * 2]
         return trac.reshape(-1, 3)[: self.nq], flag[: self.nq], info, s
 

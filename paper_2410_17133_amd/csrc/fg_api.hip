@@ -744,6 +744,40 @@ fg_status fg_residual(fg_ctx *ctx, fg_system *S, const double *U, const double *
     return check_hip("fg_residual");
 }
 
+// Newton globalisation of fg_step: merit phi = (||R_m|| / s*)^2 + (||R_f|| / s_f)^2
+// with s* = max(s_m, ||A_pu (P + dP)||) fixed for the iteration (1 if zero) and
+// s_f the flow scale (1 if zero); step lengths 1, 1/2, ..., 1/64 are tried and the
+// first that lowers phi is taken (1/64 if none does).  Trial states use the
+// interface forces only (no tangent); they leave S->ui, S->pi, du, dpv intact.
+static double newton_step_length(fg_system *S, double rm, double rf, double sm, double sf, const double *t0,
+                                 int64_t *cuts, hipStream_t st)
+{
+    const int64_t n1 = 3 * S->Npad, n2 = S->Npad;
+    double *ut = S->v1, *rmt = S->v2, *ap = S->pv2, *pt = S->s1, *rft = S->s2;
+    hipMemcpyAsync(pt, S->pi, n2 * sizeof(double), hipMemcpyDeviceToDevice, st);
+    vaxpby(n2, 1.0, S->dpv, 1.0, pt, st);
+    apply_Apu(S, pt, ap, st);
+    double s_star = std::max(sm, vnorm(S, n1, ap, st));
+    if (!(s_star > 0)) s_star = 1.0;
+    const double sfn = sf > 0 ? sf : 1.0;
+    auto phi = [&](double a, double b) { return (a / s_star) * (a / s_star) + (b / sfn) * (b / sfn); };
+    const double m0 = phi(rm, rf);
+    double step = 1.0;
+    for (;;) {
+        hipMemcpyAsync(ut, S->ui, n1 * sizeof(double), hipMemcpyDeviceToDevice, st);
+        vaxpby(n1, step, S->du, 1.0, ut, st);
+        hipMemcpyAsync(pt, S->pi, n2 * sizeof(double), hipMemcpyDeviceToDevice, st);
+        vaxpby(n2, step, S->dpv, 1.0, pt, st);
+        cohesive_qp(S, ut, S->die0, t0, S->adj_trac, S->adj_die, S->adj_flag, st);
+        cohesive_rows(S, S->fc, 0, st);
+        residual_int(S, ut, pt, S->ui0, S->pi0, S->fc, S->fi, S->qi, rmt, rft, st);
+        if (phi(vnorm(S, n1, rmt, st), vnorm(S, n2, rft, st)) < m0 || step <= 1.0 / 64) break;
+        step *= 0.5;
+        ++*cuts;
+    }
+    return step;
+}
+
 fg_status fg_step(fg_ctx *ctx, fg_system *S, double *U, double *P, double *die, double *trac, uint8_t *flag,
                   const double *t0, const double *F_u, const double *f_p, double newton_tol, int64_t newton_max_iter,
                   const fg_pcg_opts *inner_k, const fg_pcg_opts *inner_p, double outer_tol, int64_t outer_max_iter,
@@ -767,7 +801,7 @@ fg_status fg_step(fg_ctx *ctx, fg_system *S, double *U, double *P, double *die, 
     perm_in(S, 1, f_p, S->qi, st);
     if (S->nq) hipMemcpyAsync(S->die0, die, 2 * S->nq * sizeof(double), hipMemcpyDeviceToDevice, st);
     double sm = 0, sf = 0, em = 0, ef = 0;
-    int64_t it = 0;
+    int64_t it = 0, cuts = 0;
     fg_status status = FG_NOT_CONVERGED;
     for (;;) {
         cohesive_qp(S, S->ui, S->die0, t0, trac, die, flag, st);
@@ -805,8 +839,9 @@ fg_status fg_step(fg_ctx *ctx, fg_system *S, double *U, double *P, double *die, 
             status = s;
             break;
         }
-        vaxpby(n1, 1.0, S->du, 1.0, S->ui, st);
-        vaxpby(n2, 1.0, S->dpv, 1.0, S->pi, st);
+        const double step = S->line_search ? newton_step_length(S, rm, rf, sm, sf, t0, &cuts, st) : 1.0;
+        vaxpby(n1, step, S->du, 1.0, S->ui, st);
+        vaxpby(n2, step, S->dpv, 1.0, S->pi, st);
         it++;
     }
     perm_out(S, 3, S->ui, U, st);
@@ -816,6 +851,7 @@ fg_status fg_step(fg_ctx *ctx, fg_system *S, double *U, double *P, double *die, 
     si.res_m = em;
     si.res_f = ef;
     si.status = status;
+    si.step_cuts = cuts;
     if (info) *info = si;
     fg_status e = check_hip("fg_step");
     return e ? e : status;
@@ -1005,6 +1041,10 @@ fg_status fg_tune(fg_system *S, const char *key, int64_t value)
         drop_graphs(S);
         drop_mr_graphs(S);
         drop_group_graphs(S);
+        return FG_OK;
+    }
+    if (std::strcmp(key, "line_search") == 0) {
+        S->line_search = value != 0;
         return FG_OK;
     }
     if (std::strcmp(key, "spmv_unroll") == 0) {

@@ -160,6 +160,7 @@ struct fg_system {
     uint32_t *red_counter = nullptr;
     // captured CG batches per operator slot: K FP64, K FP32, A22
     bool use_graphs = true;
+    bool line_search = true;  // fg_tune "line_search": backtracking on the Newton steps of fg_step
     hipStream_t cap_stream = nullptr;
     fg::GraphCache cg_graph[3];
     // block solves (many right-hand sides), column-interleaved workspaces

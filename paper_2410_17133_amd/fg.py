@@ -53,7 +53,7 @@ class PcgInfo(C.Structure):
 class SolveInfo(C.Structure):
     _fields_ = [("newton_iters", C.c_int64), ("outer_iters", C.c_int64), ("inner_k_iters", C.c_int64),
                 ("inner_a22_iters", C.c_int64), ("outer_relres", C.c_double), ("res_m", C.c_double),
-                ("res_f", C.c_double), ("status", C.c_int)]
+                ("res_f", C.c_double), ("status", C.c_int), ("step_cuts", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

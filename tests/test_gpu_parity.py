@@ -282,6 +282,73 @@ def test_step_parity_config1():
     assert np.abs(host(trac).reshape(-1, 3) - trac_o).max() <= 1e-9 * inst.cfg.tn0
 
 
+def test_step_parity_with_line_search():
+    """16^3 dipping heterogeneous fault: the Newton line search shortens steps on
+    both sides; iterations, cuts, point states and the converged state agree."""
+    fg, O = _fg(), _oracle()
+    inst = I.make_instance(I.cube_config(16, dip_deg=60.0, heterogeneous=True))
+    print("[case] step cube16 dip60 hetero, line search", flush=True)
+    ctx = fg.Context(0)
+    S = fg.System.from_instance(ctx, inst)
+    S.assemble(inst.params, inst.E, inst.logk)
+    P = O.Problem(inst)
+    N, nq = S.N, S.nq
+    Uo, Po, dieo = np.zeros(3 * N), np.zeros(N), np.zeros((nq, 2))
+    trac_o, flag_o, info_o, st_o = P.step(Uo, Po, dieo, tol_newton=1e-10, max_newton=60, tol_outer=1e-12,
+                                          tol_inner=1e-13)
+    U, Pp, die = dev(np.zeros(3 * N)), dev(np.zeros(N)), dev(np.zeros(2 * nq))
+    trac, flag, info = S.step(U, Pp, die, dev(inst.t0.reshape(-1)), dev(inst.load), dev(inst.source),
+                              newton_tol=1e-10, newton_max_iter=60, inner_k=fg.opts(tol=1e-13),
+                              inner_p=fg.opts(tol=1e-13), outer_tol=1e-12)
+    print(f"[step] gpu {info.as_dict()} oracle {info_o}", flush=True)
+    assert info.status == 0 and st_o == 0
+    assert info.step_cuts == info_o[7] and info.step_cuts >= 1
+    assert info.newton_iters == info_o[0]
+    np.testing.assert_array_equal(host(flag), flag_o)
+    assert relerr(host(U), Uo) < 1e-9
+    assert relerr(host(Pp), Po) < 1e-9
+
+
+def test_line_search_converges_where_full_steps_do_not():
+    """32^3: full Newton steps let slip run over the whole fault and blow up; with
+    backtracking the step converges to an equilibrium that conserves fluid volume
+    (checked with the oracle's own operators)."""
+    fg, O = _fg(), _oracle()
+    inst = I.make_instance(I.cube_config(32, dip_deg=60.0, heterogeneous=True))
+    print("[case] step cube32 dip60 hetero, line search on/off", flush=True)
+    ctx = fg.Context(0)
+    S = fg.System.from_instance(ctx, inst)
+    S.assemble(inst.params, inst.E, inst.logk)
+    N, nq = S.N, S.nq
+    t0 = dev(inst.t0.reshape(-1))
+    inner = fg.opts(tol=1e-12, check_every=64)
+    U, Pp, die = dev(np.zeros(3 * N)), dev(np.zeros(N)), dev(np.zeros(2 * nq))
+    trac, flag, info = S.step(U, Pp, die, t0, dev(inst.load), dev(inst.source), newton_tol=1e-9,
+                              newton_max_iter=60, inner_k=inner, inner_p=inner, outer_tol=1e-10)
+    print(f"[step] line search {info.as_dict()}", flush=True)
+    assert info.status == 0 and info.step_cuts >= 1
+    P = O.Problem(inst)
+    Uh, Ph = host(U), host(Pp)
+    stored = P.apply_Aup(Uh).sum() + P.spmv(O.A22, Ph).sum()
+    assert stored == pytest.approx(inst.params.dt * inst.cfg.Q, rel=1e-8)
+    _, _, flag_o, fcoh = P.cohesive(Uh, np.zeros((nq, 2)))
+    np.testing.assert_array_equal(host(flag), flag_o)
+    Rm, Rf = P.residual(Uh, Ph, np.zeros_like(Uh), np.zeros_like(Ph), fcoh)
+    assert np.linalg.norm(Rm) <= 1e-8 * np.linalg.norm(P.apply_Apu(Ph))
+    slip = int((flag_o == 1).sum())
+    assert 0 < slip < nq // 4                      # a contained slip patch
+    S.tune("line_search", 0)
+    U2, P2, die2 = dev(np.zeros(3 * N)), dev(np.zeros(N)), dev(np.zeros(2 * nq))
+    try:
+        _, _, info2 = S.step(U2, P2, die2, t0, dev(inst.load), dev(inst.source), newton_tol=1e-9,
+                             newton_max_iter=40, inner_k=inner, inner_p=inner, outer_tol=1e-10)
+        assert info2.status != 0
+    except fg.FgError as e:                      # the full-step iterates overflow
+        assert e.status in (fg.FG_NOT_CONVERGED, fg.FG_ERR_NAN, fg.FG_ERR_BREAKDOWN)
+    finally:
+        S.tune("line_search", 1)
+
+
 def test_residual_parity():
     fg, O = _fg(), _oracle()
     inst, ctx, S, P = setup("cube12_dip60_hetero")

@@ -209,6 +209,28 @@ def test_step_volume_balance_and_equilibrium():
     assert Pp.max() == pytest.approx(Pp[inst.centre_pair[0]])
 
 
+def test_line_search_keeps_the_converged_step():
+    """Backtracking changes the path of Newton, not the state it converges to: on a
+    16^3 dipping-fault step where it shortens two steps, the result equals the
+    full-step Newton result and conserves the injected fluid volume."""
+    inst = I.make_instance(I.cube_config(16, dip_deg=60.0, heterogeneous=True))
+    P = O.Problem(inst)
+    out = {}
+    for ls in (True, False):
+        U, Pp, die = np.zeros(3 * P.N), np.zeros(P.N), np.zeros((P.nq, 2))
+        trac, flag, info, st = P.step(U, Pp, die, tol_newton=1e-10, max_newton=60, line_search=ls)
+        assert st == 0
+        out[ls] = (U, Pp, flag, info)
+    assert out[True][3][7] >= 1 and out[False][3][7] == 0
+    np.testing.assert_array_equal(out[True][2], out[False][2])
+    for k in (0, 1):
+        a, b = out[True][k], out[False][k]
+        assert np.linalg.norm(a - b) <= 1e-8 * np.linalg.norm(b)
+    U, Pp = out[True][0], out[True][1]
+    stored = P.apply_Aup(U).sum() + P.spmv(O.A22, Pp).sum()
+    assert stored == pytest.approx(inst.params.dt * inst.cfg.Q, rel=1e-9)
+
+
 # ------------------------------------------------------------ Terzaghi consolidation
 def terzaghi(zp, t, H, cv, p0, terms=400):
     m = np.arange(terms)[:, None]
