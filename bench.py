@@ -272,17 +272,18 @@ def extra_adjoint(ctx, log):
     die0 = torch.zeros_like(die)
     res = {}
     for name, prec in (("f64", fg.FG_F64), ("mixed", fg.FG_MIXED)):
-        ik = fg.opts(tol=1e-10, check_every=64, precision=prec)
-        ip = fg.opts(tol=1e-10, check_every=64)
+        # corrections solved loosely (outer 0.05, inner 1e-3); the defect tolerance sets the accuracy
+        ik = fg.opts(tol=1e-3, check_every=64, precision=prec)
+        ip = fg.opts(tol=1e-3, check_every=64)
         t_adj, (dE, dk, ainfo) = _timed(lambda: S.adjoint(U, P, die0, t0, logk, gU, gP, inner_k=ik, inner_p=ip,
-                                                           outer_tol=1e-8, defect_tol=1e-8))
+                                                           outer_tol=0.05, defect_tol=1e-8))
         log(f"adjoint {name}: {t_adj:.2f}s defect iters {ainfo.newton_iters} outer {ainfo.outer_iters} "
             f"K iters {ainfo.inner_k_iters} status {ainfo.status}")
         res[name] = (t_adj, ainfo, torch.cat([dE * E, dk]))
     g64 = res["f64"][2]
     return {"workload": f"cube64_dip60_hetero one implicit step, {inst.mesh.tets.shape[0]} tets, "
-                        f"{2 * inst.mesh.tets.shape[0]} parameters (ln k, E); tolerances Newton/outer/defect 1e-8, "
-                        f"inner 1e-10",
+                        f"{2 * inst.mesh.tets.shape[0]} parameters (ln k, E); forward: Newton and outer 1e-8, inner "
+                        f"1e-10; adjoint: defect 1e-8, corrections outer 0.05 inner 1e-3",
             "forward_s": t_fwd, "forward_newton_iters": finfo.newton_iters, "forward_k_iters": finfo.inner_k_iters,
             "grad_per_s_f64": 1.0 / res["f64"][0], "grad_per_s_mixed": 1.0 / res["mixed"][0],
             "adjoint_s_f64": res["f64"][0], "adjoint_s_mixed": res["mixed"][0],
@@ -310,8 +311,12 @@ def extra_block(ctx, log):
         z, _ = S.pcg_solve(fg.FG_A22, torch.as_tensor(q).cuda(), tol=1e-12)
         cols.append(S.coupling(z))
     B = torch.stack(cols).reshape(-1).contiguous()
+    from paper_2410_17133_amd import autotune as AT
     res = {}
     for name, prec in (("mixed", fg.FG_MIXED), ("f64", fg.FG_F64)):
+        tuned = AT.tune_block(S, 32, prec, B=B, iters=20)                   # product tile from the autotuner
+        log(f"block {name}: autotuner picked {tuned['config']} ({tuned['us_per_iteration']:.0f} us/iteration, "
+            f"{tuned['trials']} trials)")
         S.pcg_solve(fg.FG_K, B, nrhs=32, tol=1e-8, precision=prec)          # graphs captured
         tb, (Xb, ib) = _timed(lambda: S.pcg_solve(fg.FG_K, B, nrhs=32, tol=1e-8, precision=prec))
         n3 = 3 * S.N
@@ -326,7 +331,7 @@ def extra_block(ctx, log):
         log(f"block {name}: 32 columns {tb:.2f}s ({ib.iters} iters, {ib.cycles} cycles) vs separate {ts:.2f}s "
             f"({its} iters)")
         res[name] = {"block_s": tb, "separate_s": ts, "speedup": ts / tb, "block_iters": ib.iters,
-                     "block_cycles": ib.cycles, "separate_iters_total": its}
+                     "block_cycles": ib.cycles, "separate_iters_total": its, "autotuned": tuned["config"]}
     return {"workload": f"cube64_dip60_hetero, {S.N} nodes, 32 injection right-hand sides on one K, to 1e-8",
             **res}
 

@@ -231,10 +231,16 @@ fg_status fg_step(fg_ctx *ctx, fg_system *sys, double *U, double *P, double *die
  *   [ K_exact^T   A_pu ] [lam_u]   [dJ/dU]
  *   [ -A_up       A22  ] [lam_p] = [dJ/dP]
  * solved as the forward partitioned CG (Sec. 3.3.2) on mu = -lam_u, with the slip
- * part of the exact interface tangent, N = sum w N_a N_b (-f k_n tau (x) n), moved to
- * the right-hand side and iterated (defect correction) until ||mu_k+1 - mu_k|| <=
- * defect_tol ||mu_k+1||.  Then dJ/dE_e = -lam_u^T (K_e/E_e) U_e and
- * dJ/dln k_e = -dt lam_p^T C_e P_e.
+ * part of the exact interface tangent, N = sum w N_a N_b (-f k_n tau (x) n), lagged
+ * (defect correction) in refinement form: each iteration computes the true residual
+ * of the exact transposed system with the FP64 operators and solves only for the
+ * correction with the symmetric tangent, to relative tolerance outer_tol with the
+ * inner_k / inner_p solves.  Loose values (outer 0.05, inner 1e-3) make every
+ * correction cheap; the accuracy of the result is set by defect_tol, the stop test
+ * on the relative change of each multiplier block.  Then
+ * dJ/dE_e = -lam_u^T (K_e/E_e) U_e and dJ/dln k_e = -dt lam_p^T C_e P_e.
+ * info: newton_iters = defect iterations, outer/inner iterations summed over them,
+ * outer_relres = last relative change.
  *   U, P       converged state of fg_step (changes since t = 0), caller order
  *   die_n, t0  the step's start-of-step inelastic slip and initial tractions
  *   log_k      [n_tets] the log-permeability given to fg_assemble

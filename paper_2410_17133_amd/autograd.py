@@ -14,13 +14,15 @@ class ImplicitStep(torch.autograd.Function):
 
     logk, E: CUDA float64 [n_tets].  system: fg.System.  params: inputs.Params.
     t0 [3 nq], F_u [3N], f_p [N]: CUDA float64.  solver: dict of tolerances
-    (newton_tol, inner tol, outer_tol, defect_tol, precision of the K solves).
+    (newton_tol, inner_tol, outer_tol of the forward step; adjoint_outer_tol and
+    adjoint_inner_tol of each defect-correction solve, defect_tol of the adjoint;
+    precision of the K solves).
     The step starts from the initial state (U = P = 0, no inelastic slip)."""
 
     @staticmethod
     def forward(ctx, logk, E, system, params, t0, F_u, f_p, solver=None):
         s = dict(newton_tol=1e-12, inner_tol=1e-13, outer_tol=1e-12, defect_tol=1e-12, precision=fg.FG_F64,
-                 newton_max_iter=80)
+                 newton_max_iter=80, adjoint_outer_tol=0.05, adjoint_inner_tol=1e-3)
         s.update(solver or {})
         system.assemble(params, E.detach(), logk.detach())
         U = torch.zeros(3 * system.N, dtype=torch.float64, device=E.device)
@@ -44,10 +46,10 @@ class ImplicitStep(torch.autograd.Function):
         die0 = torch.zeros(2 * S.nq, dtype=torch.float64, device=E.device)
         gU = torch.zeros_like(U) if gU is None else gU.contiguous()
         gP = torch.zeros_like(P) if gP is None else gP.contiguous()
-        ik = fg.opts(tol=s["inner_tol"], precision=s["precision"])
-        ip = fg.opts(tol=s["inner_tol"])
-        dE, dk, info = S.adjoint(U, P, die0, t0, logk, gU, gP, inner_k=ik, inner_p=ip, outer_tol=s["outer_tol"],
-                                 defect_tol=s["defect_tol"])
+        ik = fg.opts(tol=s["adjoint_inner_tol"], precision=s["precision"])
+        ip = fg.opts(tol=s["adjoint_inner_tol"])
+        dE, dk, info = S.adjoint(U, P, die0, t0, logk, gU, gP, inner_k=ik, inner_p=ip,
+                                 outer_tol=s["adjoint_outer_tol"], defect_tol=s["defect_tol"])
         ctx.adjoint_info = info
         return dk, dE, None, None, None, None, None, None
 

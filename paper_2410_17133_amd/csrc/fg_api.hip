@@ -884,33 +884,66 @@ fg_status fg_adjoint_solve(fg_ctx *ctx, fg_system *S, const double *U, const dou
     vmask(n1, S->dir_u, S->fi, st);
     perm_in(S, 1, dJdP, S->qi, st);
     vmask(n2, S->dir_p, S->qi, st);
-    double *mu = S->ui0, *mu_new = S->du, *b1 = S->rm, *lp = S->dpv, *ntm = S->pv2;
+    // Defect correction in refinement form: the true residual of the exact transposed
+    // system, r = f - [(K + N^T) mu - A_pu lp ; A_up mu + A22 lp], is computed with the
+    // FP64 operators and only the correction is solved, with the symmetric tangent,
+    // to the caller's (possibly loose) tolerances.  The fixed point is that of the
+    // plain iteration K mu_k+1 - A_pu lp = -dJ/dU - N^T mu_k.
+    double *mu = S->ui0, *lp = S->pi0, *r1 = S->rm, *r2 = S->rf, *dmu = S->du, *dlp = S->dpv;
     vfill(mu, 0.0, n1, st);
+    vfill(lp, 0.0, n2, st);
+    hipMemcpyAsync(r1, S->fi, n1 * sizeof(double), hipMemcpyDeviceToDevice, st);
+    vaxpby(n1, 0.0, r1, -1.0, r1, st);  // r1 = -dJ/dU  (vaxpby: y = a x + b y)
+    hipMemcpyAsync(r2, S->qi, n2 * sizeof(double), hipMemcpyDeviceToDevice, st);
     fg_status status = FG_NOT_CONVERGED;
     double change = 0;
-    int64_t k = 0;
+    int64_t k = 0, outer = 0, kit = 0, ait = 0;
     while (k < max_defect_iters) {
-        apply_NT(S, mu, ntm, st);
-        hipMemcpyAsync(b1, S->fi, n1 * sizeof(double), hipMemcpyDeviceToDevice, st);
-        vaxpby(n1, -1.0, ntm, -1.0, b1, st);  // b1 = -dJ/dU - N^T mu
-        fg_status s = prevost(S, b1, S->qi, mu_new, lp, ok, op, outer_tol, 1000, &si, st);
+        fg_solve_info sk{};
+        fg_status s = prevost(S, r1, r2, dmu, dlp, ok, op, outer_tol, 1000, &sk, st);
+        outer += sk.outer_iters;
+        kit += sk.inner_k_iters;
+        ait += sk.inner_a22_iters;
         if (s < 0) {
             status = s;
             break;
         }
         ++k;
-        // relative change of mu, from the explicit difference (no cancellation)
-        vaxpby(n1, 1.0, mu_new, -1.0, mu, st);  // mu <- mu_new - mu
-        const double *A[2] = {mu, mu_new};
-        double dd[2];
-        vdots(S, n1, 2, A, A, dd, st);
-        change = dd[1] > 0 ? std::sqrt(dd[0] / dd[1]) : 0.0;
-        hipMemcpyAsync(mu, mu_new, n1 * sizeof(double), hipMemcpyDeviceToDevice, st);
+        vaxpby(n1, 1.0, dmu, 1.0, mu, st);
+        vaxpby(n2, 1.0, dlp, 1.0, lp, st);
+        // relative change of each block (a block that is zero does not count)
+        const double *A1[2] = {dmu, mu}, *A2[2] = {dlp, lp};
+        double d1[2], d2[2];
+        vdots(S, n1, 2, A1, A1, d1, st);
+        vdots(S, n2, 2, A2, A2, d2, st);
+        change = std::max(d1[1] > 0 ? std::sqrt(d1[0] / d1[1]) : 0.0, d2[1] > 0 ? std::sqrt(d2[0] / d2[1]) : 0.0);
+        if (!std::isfinite(change)) {
+            set_error("fg_adjoint_solve: NaN in the defect correction");
+            status = FG_ERR_NAN;
+            break;
+        }
         if (change <= defect_tol) {
             status = FG_OK;
             break;
         }
+        // r1 = -dJ/dU - K mu - N^T mu + A_pu lp;  r2 = dJ/dP - A_up mu - A22 lp
+        spmv(S, FG_K, mu, S->v1, st);
+        apply_NT(S, mu, S->v2, st);
+        apply_Apu(S, lp, S->pv1, st);
+        hipMemcpyAsync(r1, S->fi, n1 * sizeof(double), hipMemcpyDeviceToDevice, st);
+        vaxpby(n1, 0.0, r1, -1.0, r1, st);
+        vaxpby(n1, -1.0, S->v1, 1.0, r1, st);
+        vaxpby(n1, -1.0, S->v2, 1.0, r1, st);
+        vaxpby(n1, 1.0, S->pv1, 1.0, r1, st);
+        apply_Aup(S, mu, S->s7, st);
+        spmv(S, FG_A22, lp, S->s8, st);
+        hipMemcpyAsync(r2, S->qi, n2 * sizeof(double), hipMemcpyDeviceToDevice, st);
+        vaxpby(n2, -1.0, S->s7, 1.0, r2, st);
+        vaxpby(n2, -1.0, S->s8, 1.0, r2, st);
     }
+    si.outer_iters = outer;
+    si.inner_k_iters = kit;
+    si.inner_a22_iters = ait;
     if (status >= 0) {
         vaxpby(n1, 0.0, mu, -1.0, mu, st);  // lam_u = -mu
         sensitivity(S, S->ui, S->pi, mu, lp, dJ_dE, dJ_dlogk, log_k, st);

@@ -51,8 +51,11 @@ def objective_np(inst, U, uplift):
     return np.sum(slip * slip) + np.sum(U3[uplift, 2] ** 2), g.reshape(-1)
 
 
-@pytest.mark.parametrize("case", ["small_slip", "config1"])
-def test_adjoint_matches_oracle_at_the_same_state(case):
+@pytest.mark.parametrize("case,loose", [("small_slip", False), ("small_slip", True), ("config1", False),
+                                        ("config1", True)])
+def test_adjoint_matches_oracle_at_the_same_state(case, loose):
+    """loose: every defect correction solved to outer 0.05 / inner 1e-3 only; the
+    refinement on the true residual must still reach the same multipliers."""
     from oracle import oracle as O
     from paper_2410_17133_amd import fg
     inst = small_slip_instance() if case == "small_slip" else I.make_instance(I.config(1))
@@ -71,9 +74,11 @@ def test_adjoint_matches_oracle_at_the_same_state(case):
     ctx = fg.Context(0)
     S = fg.System.from_instance(ctx, inst)
     S.assemble(inst.params, inst.E, inst.logk)
+    kw = dict(inner_k=fg.opts(tol=1e-3), inner_p=fg.opts(tol=1e-3), outer_tol=0.05) if loose else {}
     dE, dk, lu, lp, ai = S.adjoint(dev(U), dev(Pp), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)), dev(inst.logk),
-                                   dev(gu), dev(gp), multipliers=True)
-    print(f"[adjoint] defect iterations gpu {ai.newton_iters} oracle {stats[0]:.0f}", flush=True)
+                                   dev(gu), dev(gp), multipliers=True, **kw)
+    print(f"[adjoint] loose={loose} defect iterations gpu {ai.newton_iters} (K iters {ai.inner_k_iters}) "
+          f"oracle {stats[0]:.0f}", flush=True)
     assert ai.status == 0
     assert rel(host(lu), lu_o) < 1e-9
     assert rel(host(lp), lp_o) < 1e-9
