@@ -1,0 +1,98 @@
+"""Parity at the full workload sizes (64^3 and 128^3 hexes), in the launch
+configuration the benchmark times (default product knobs, CG batches replayed as
+HIP graphs, checks every 64 iterations).
+
+Every element of the operator products is compared with the oracle's CSR
+products; the interface update at a displacement with stick, slip and open
+points is compared point by point; 50 PCG iterations of both sides are compared
+as iterates (the same Krylov sequence up to rounding)."""
+import numpy as np
+import pytest
+
+from paper_2410_17133_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def relerr(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.fixture(scope="module", params=[64, 128])
+def full(request):
+    from oracle import oracle as O
+    from paper_2410_17133_amd import fg
+    n = request.param
+    print(f"[case] full size {n}^3", flush=True)
+    inst = I.make_instance(I.config(3 if n == 128 else 2))
+    ctx = fg.Context(0)
+    S = fg.System.from_instance(ctx, inst)
+    S.assemble(inst.params, inst.E, inst.logk)
+    P = O.Problem(inst)
+    # interface jumps of a few times t'_n0/k_n: contact, opening and slip all occur
+    r = np.random.default_rng(100 + n)
+    scale = 2.4e-5 / n
+    U = r.normal(0.0, scale, 3 * P.N) * (1 - inst.dir_u)
+    die = np.zeros((P.nq, 2))
+    yield dict(n=n, inst=inst, ctx=ctx, S=S, P=P, U=U, die=die, O=O, fg=fg)
+    del S, P
+
+
+def test_interface_update_full_size(full):
+    S, P, U, inst = full["S"], full["P"], full["U"], full["inst"]
+    trac_o, die_o, flag_o, f_o = P.cohesive(U, full["die"])
+    trac, die, flag, f = S.cohesive_update(dev(U), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)))
+    flag = host(flag)
+    counts = [int((flag_o == k).sum()) for k in (0, 1, 2)]
+    print(f"[interface] stick/slip/open {counts}", flush=True)
+    assert min(counts) > 0
+    np.testing.assert_array_equal(flag, flag_o)
+    assert np.abs(host(trac).reshape(-1, 3) - trac_o).max() <= 1e-9 * inst.cfg.tn0
+    assert np.abs(host(die).reshape(-1, 2) - die_o).max() <= 1e-12 * max(np.abs(die_o).max(), 1e-300) + 1e-24
+    assert np.abs(host(f) - f_o).max() <= 1e-12 * np.abs(f_o).max()
+
+
+def test_products_full_size(full):
+    S, P, O, fg = full["S"], full["P"], full["O"], full["fg"]
+    P.cohesive(full["U"], full["die"])          # tangent of the same state on both sides
+    r = np.random.default_rng(7)
+    for which_g, which_o, bs in ((fg.FG_K, O.K_TANGENT, 3), (fg.FG_KBULK, O.K_BULK, 3), (fg.FG_A22, O.A22, 1),
+                                 (fg.FG_C, O.C_FLOW, 1)):
+        x = r.standard_normal(bs * S.N)
+        y = host(S.spmv(which_g, dev(x)))
+        yo = P.spmv(which_o, x)
+        print(f"[product] {which_g}: rel {relerr(y, yo):.2e}", flush=True)
+        assert np.abs(y - yo).max() <= 1e-12 * np.abs(yo).max()
+    p = r.standard_normal(S.N) * 1e6
+    assert relerr(host(S.coupling(dev(p))), P.apply_Apu(p)) < 1e-12
+    u = r.standard_normal(3 * S.N) * 1e-6
+    assert relerr(host(S.coupling(dev(u), transpose=True)), P.apply_Aup(u)) < 1e-12
+
+
+def test_pcg_iterates_full_size(full):
+    """50 iterations of the K and A22 PCG from the same right-hand side: the GPU
+    iterate (graph-replayed batches, default knobs) equals the oracle's."""
+    S, P, O, fg, inst = full["S"], full["P"], full["O"], full["fg"], full["inst"]
+    P.cohesive(full["U"], full["die"])
+    r = np.random.default_rng(8)
+    b = r.standard_normal(3 * S.N) * (1 - inst.dir_u)
+    x, info = S.pcg_solve(fg.FG_K, dev(b), tol=1e-300, max_iter=50, check_every=64)
+    xo, st, it, rr = P.pcg(O.K_TANGENT, b, tol=1e-300, maxit=50)
+    assert info.iters == it == 50
+    print(f"[pcg K] rel {relerr(host(x), xo):.2e} relres gpu {info.relres:.6e} oracle {rr:.6e}", flush=True)
+    assert relerr(host(x), xo) < 1e-10
+    assert abs(info.relres - rr) <= 1e-8 * rr
+    bp = r.standard_normal(S.N)
+    xp, ip = S.pcg_solve(fg.FG_A22, dev(bp), tol=1e-300, max_iter=50, check_every=64)
+    xpo, st, it, rr = P.pcg(O.A22, bp, tol=1e-300, maxit=50)
+    assert relerr(host(xp), xpo) < 1e-10
