@@ -282,6 +282,31 @@ def test_step_parity_config1():
     assert np.abs(host(trac).reshape(-1, 3) - trac_o).max() <= 1e-9 * inst.cfg.tn0
 
 
+def test_time_loop_parity_three_steps():
+    """Three consecutive steps of the 8^3 case: U, P and the inelastic slip of each
+    converged step start the next one, on both sides."""
+    fg, O = _fg(), _oracle()
+    inst, ctx, S, P = setup("cube8")
+    print("[case] three steps cube8", flush=True)
+    N, nq = S.N, S.nq
+    Uo, Po, dieo = np.zeros(3 * N), np.zeros(N), np.zeros((nq, 2))
+    U, Pp, die = dev(np.zeros(3 * N)), dev(np.zeros(N)), dev(np.zeros(2 * nq))
+    kw = dict(tol_newton=1e-11, max_newton=60, tol_outer=1e-12, tol_inner=1e-13)
+    for k in range(3):
+        trac_o, flag_o, info_o, st_o = P.step(Uo, Po, dieo, **kw)
+        trac, flag, info = S.step(U, Pp, die, dev(inst.t0.reshape(-1)), dev(inst.load), dev(inst.source),
+                                  newton_tol=1e-11, newton_max_iter=60, inner_k=fg.opts(tol=1e-13),
+                                  inner_p=fg.opts(tol=1e-13), outer_tol=1e-12)
+        print(f"[step {k}] gpu {info.as_dict()} oracle {info_o}", flush=True)
+        assert info.status == 0 and st_o == 0
+        assert info.newton_iters == info_o[0] and info.step_cuts == info_o[7]
+        np.testing.assert_array_equal(host(flag), flag_o)
+        assert relerr(host(U), Uo) < 1e-9
+        assert relerr(host(Pp), Po) < 1e-9
+        assert np.abs(host(die).reshape(-1, 2) - dieo).max() <= 1e-9 * max(np.abs(dieo).max(), 1e-300)
+    assert (flag_o == 1).sum() > 0 and np.abs(dieo).max() > 0      # slip has accumulated
+
+
 def test_step_parity_with_line_search():
     """16^3 dipping heterogeneous fault: the Newton line search shortens steps on
     both sides; iterations, cuts, point states and the converged state agree."""

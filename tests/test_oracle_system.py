@@ -209,6 +209,26 @@ def test_step_volume_balance_and_equilibrium():
     assert Pp.max() == pytest.approx(Pp[inst.centre_pair[0]])
 
 
+def test_time_loop_conserves_the_injected_volume():
+    """Three steps with the state carried over: the stored fluid volume grows by
+    dt Q per step (1^T C = 0 under no-flow), and slip accumulates monotonically."""
+    inst = I.make_instance(I.config(1))
+    P = O.Problem(inst)
+    U, Pp, die = np.zeros(3 * P.N), np.zeros(P.N), np.zeros((P.nq, 2))
+    dt, Q = inst.params.dt, inst.cfg.Q
+    S = P.scipy(O.A22) - dt * P.scipy(O.C_FLOW)       # storage part of A22 = S + dt C
+    prev = 0.0
+    for k in range(1, 4):
+        trac, flag, info, st = P.step(U, Pp, die)
+        assert st == 0
+        stored = P.apply_Aup(U).sum() + (S @ Pp).sum()
+        assert stored == pytest.approx(k * dt * Q, rel=1e-9)
+        slip = np.linalg.norm(die)
+        assert slip >= prev
+        prev = slip
+    assert prev > 0
+
+
 def test_line_search_keeps_the_converged_step():
     """Backtracking changes the path of Newton, not the state it converges to: on a
     16^3 dipping-fault step where it shortens two steps, the result equals the
