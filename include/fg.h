@@ -299,6 +299,11 @@ fg_status fg_group_stats(const fg_system *sys, int64_t *iters_h, double *relres_
  *               0 full steps.
  *   "spmv_unroll": slots per unrolled step of the CG product: 2 (default),
  *               3, 4 or 6.
+ *   "vec_grid": workgroups of the CG vector kernels: 512 (default), 1024 or
+ *               2048 (each adds the previous kernel's partial sums itself).
+ *   "spmv_wpb": slices (one wavefront each) per workgroup of the CG
+ *               product: 1, 2 or 4 (default); the slices of a workgroup
+ *               share its LDS and its staging barrier.
  *   "spmv_nt":  nontemporal-access mask of the CG product: 1 matrix values,
  *               2 column indices, 4 halo lists, 8 product stores; 0, 1, 3,
  *               7 (default) or 15.  Results are identical for every value.

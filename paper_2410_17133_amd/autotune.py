@@ -1,8 +1,11 @@
 """Autotuner for the launch parameters of the CG products (the fg_tune knobs).
 
-The knobs change how the products stream memory, never what they compute:
+The knobs change how the products stream memory, not what they compute
+(spmv_wpb and vec_grid regroup the partial sums of the dot products, so results
+agree to rounding; the others give bitwise the same iterates):
 
-  single-vector CG (K FP64, K FP32, A22):  halo_cap, spmv_unroll, spmv_nt
+  single-vector CG (K FP64, K FP32, A22):  halo_cap, spmv_unroll, spmv_nt,
+                                           spmv_wpb, vec_grid
   block CG (many right-hand sides on K):   rhs_tile
 
 Each candidate is timed on the system it will run on, a few dozen CG iterations
@@ -11,9 +14,9 @@ one knob with the others held, best kept, knobs in turn, twice over).  Results
 are cached in a JSON file keyed by device, operator sizes and workload, so a
 run tunes once per machine and problem shape.
 
-Timings come from the library itself: single-vector candidates from the
-fence-free HIP events around every product launch (fg_profile); block
-candidates from wall time of a fixed number of graph-replayed iterations.
+Each candidate is timed as wall time per CG iteration over a fixed number of
+graph-replayed iterations (after one untimed run that captures the graphs), the
+better of two runs; this covers the product and the vector kernels alike.
 """
 from __future__ import annotations
 
@@ -23,16 +26,16 @@ import time
 
 from . import fg
 
-SINGLE_KNOBS = ("halo_cap", "spmv_unroll", "spmv_nt")
+SINGLE_KNOBS = ("halo_cap", "spmv_unroll", "spmv_nt", "spmv_wpb", "vec_grid")
 BLOCK_KNOBS = ("rhs_tile",)
-DEFAULTS = {"spmv_unroll": 2, "spmv_nt": 7, "rhs_tile": 0}
-_SLOT = {("K", fg.FG_F64): 0, ("K", fg.FG_F32): 1, ("A22", fg.FG_F64): 2}
+DEFAULTS = {"spmv_unroll": 2, "spmv_nt": 7, "spmv_wpb": 4, "vec_grid": 512, "rhs_tile": 0}
 
 
 def single_candidates(mean_halo: float) -> dict:
     """Values tried per knob; halo caps are taken relative to the mean slice halo."""
     caps = sorted({0, 682, *(int(round(mean_halo * f / 32.0)) * 32 for f in (1.0, 1.25, 1.5, 2.0))})
-    return {"halo_cap": caps, "spmv_unroll": [2, 3, 4, 6], "spmv_nt": [0, 1, 3, 7, 15]}
+    return {"halo_cap": caps, "spmv_unroll": [2, 3, 4, 6], "spmv_nt": [0, 1, 3, 7, 15], "spmv_wpb": [1, 2, 4],
+            "vec_grid": [512, 1024, 2048]}
 
 
 def block_candidates(nrhs: int) -> dict:
@@ -100,10 +103,23 @@ def apply(S, config: dict):
         S.tune(k, int(v))
 
 
-def tune_single(S, which: int = fg.FG_K, precision: int = fg.FG_F64, b=None, iters: int = 40,
+def _iteration_time(S, run, iters):
+    import torch
+    run()
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(2):
+        t0 = time.perf_counter()
+        run()
+        torch.cuda.synchronize()
+        best = min(best, (time.perf_counter() - t0) / iters * 1e6)
+    return best
+
+
+def tune_single(S, which: int = fg.FG_K, precision: int = fg.FG_F64, b=None, iters: int = 64,
                 cache: Cache | None = None, passes: int = 2) -> dict:
-    """Tune the single-vector CG product of `which` on S (assembled); leaves the best
-    configuration applied and returns it with its mean product time in microseconds."""
+    """Tune the single-vector CG on `which` of S (assembled); leaves the best
+    configuration applied and returns it with its time per iteration in microseconds."""
     import torch
     op = "K" if which == fg.FG_K else "A22"
     if which == fg.FG_A22:
@@ -117,27 +133,18 @@ def tune_single(S, which: int = fg.FG_K, precision: int = fg.FG_F64, b=None, ite
     if b is None:
         g = torch.Generator(device="cpu").manual_seed(0)
         b = torch.randn(n, generator=g, dtype=torch.float64).cuda()
-    slot = _SLOT[(op, precision)]
     npairs, nblk, nslices, nhalo = S.sizes()
     cands = single_candidates(nhalo / max(nslices, 1))
-    start = {"halo_cap": 384, **{k: DEFAULTS[k] for k in ("spmv_unroll", "spmv_nt")}}
+    start = {"halo_cap": 384, **{k: DEFAULTS[k] for k in ("spmv_unroll", "spmv_nt", "spmv_wpb", "vec_grid")}}
 
     def measure(cfg):
         apply(S, cfg)
-        S.profile(True)
-        best = float("inf")
-        for _ in range(2):
-            S.profile_read(slot, reset=True)
-            S.pcg_solve(which, b, tol=1e-300, max_iter=iters, check_every=iters, precision=precision)
-            launches, ms = S.profile_read(slot, reset=True)
-            if launches:
-                best = min(best, 1e3 * ms / launches)
-        S.profile(False)
-        return best
+        return _iteration_time(S, lambda: S.pcg_solve(which, b, tol=1e-300, max_iter=iters, check_every=iters,
+                                                      precision=precision), iters)
 
     cfg, t, log = coordinate_descent({k: cands[k] for k in SINGLE_KNOBS}, start, measure, passes)
     apply(S, cfg)
-    rec = {"config": cfg, "us_per_product": t, "trials": len(log)}
+    rec = {"config": cfg, "us_per_iteration": t, "trials": len(log)}
     if cache is not None:
         cache.put(key, rec)
     return rec
@@ -160,15 +167,8 @@ def tune_block(S, nrhs: int, precision: int = fg.FG_F64, B=None, iters: int = 30
 
     def measure(cfg):
         apply(S, cfg)
-        S.pcg_solve(fg.FG_K, B, nrhs=nrhs, tol=1e-300, max_iter=iters, check_every=iters, precision=inner)
-        torch.cuda.synchronize()
-        best = float("inf")
-        for _ in range(2):
-            t0 = time.perf_counter()
-            S.pcg_solve(fg.FG_K, B, nrhs=nrhs, tol=1e-300, max_iter=iters, check_every=iters, precision=inner)
-            torch.cuda.synchronize()
-            best = min(best, (time.perf_counter() - t0) / iters * 1e6)
-        return best
+        return _iteration_time(S, lambda: S.pcg_solve(fg.FG_K, B, nrhs=nrhs, tol=1e-300, max_iter=iters,
+                                                      check_every=iters, precision=inner), iters)
 
     cfg, t, log = coordinate_descent(block_candidates(nrhs), {"rhs_tile": DEFAULTS["rhs_tile"]}, measure, 1)
     apply(S, cfg)

@@ -1089,6 +1089,28 @@ fg_status fg_tune(fg_system *S, const char *key, int64_t value)
         drop_graphs(S);
         return FG_OK;
     }
+    if (std::strcmp(key, "vec_grid") == 0) {
+        if (value != 512 && value != 1024 && value != 2048) {
+            set_error("fg_tune: vec_grid must be 512, 1024 or 2048");
+            return FG_ERR_ARG;
+        }
+        S->vec_grid = (int)value;
+        drop_graphs(S);
+        return FG_OK;
+    }
+    if (std::strcmp(key, "spmv_wpb") == 0) {
+        if (value != 1 && value != 2 && value != 4) {
+            set_error("fg_tune: spmv_wpb must be 1, 2 or 4");
+            return FG_ERR_ARG;
+        }
+        if ((S->nslices + value - 1) / value + 8 > S->npartials) {
+            set_error("fg_tune: spmv_wpb too small for the partial-sum buffer of this system");
+            return FG_ERR_ARG;
+        }
+        S->spmv_wpb = (int)value;
+        drop_graphs(S);
+        return FG_OK;
+    }
     if (std::strcmp(key, "spmv_nt") == 0) {
         if (value != 0 && value != 1 && value != 3 && value != 7 && value != 15) {
             set_error("fg_tune: spmv_nt must be 0, 1, 3, 7 or 15");

@@ -78,6 +78,14 @@ inline int64_t grid_elems(int64_t n)
     return g < 2048 ? (g < 1 ? 1 : g) : 2048;
 }
 
+// Grid of the CG vector kernels that also add the previous kernel's partial sums
+// in every block: fewer, longer-running blocks keep that redundant sum small.
+inline int64_t grid_vec(int64_t n)
+{
+    int64_t g = (n + WG - 1) / WG;
+    return g < 512 ? (g < 1 ? 1 : g) : 512;
+}
+
 // Load of data streamed once per product (nontemporal hint when NT).
 template <bool NT, typename TV>
 __device__ __forceinline__ TV ld_val(const TV *p)

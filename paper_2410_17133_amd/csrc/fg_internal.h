@@ -49,18 +49,21 @@ fg_status build_plan(const fg_mesh &m, Plan &P, std::string &err);
 
 // Per-solve scalars of a CG iteration, kept in device memory so that the
 // iteration never returns to the host.
+// Scalars of one device-resident CG.  rho and the iteration count are kept per
+// iteration parity: the kernel that produces the next value reads the current
+// slot and writes the other, so no block reads a slot another block of the
+// same kernel writes.
 struct CgScalars {
-    double rho;    // r.z of the current iterate
-    double pq;     // p.Ap
-    double rr;     // r.r
-    double bb;     // b.b
+    double rho[2];    // r.z of the current iterate, by parity
+    double pq;        // p.Ap
+    double rr;        // r.r
+    double bb;        // b.b
     double alpha, beta;
-    double tol2;   // tol^2 * b.b
-    double rz_new;
-    int64_t iter, maxit;
+    double tol2;      // tol^2 * b.b
+    int64_t iter[2];  // iterations done, by parity
+    int64_t iters;    // iterations done (for the host)
+    int64_t maxit;
     int32_t done, status;
-    uint32_t counter;  // blocks finished in the current reduction
-    uint32_t pad;
 };
 
 void set_error(const std::string &msg);
@@ -166,6 +169,8 @@ struct fg_system {
     // block solves (many right-hand sides), column-interleaved workspaces
     int mr_cap = 0;   // columns allocated
     int spmv_unroll = 2;  // fg_tune "spmv_unroll": slots per unrolled step of the CG product (2, 3, 4, 6)
+    int vec_grid = 512;   // fg_tune "vec_grid": workgroups of the CG vector kernels (512, 1024, 2048)
+    int spmv_wpb = 4;     // fg_tune "spmv_wpb": slices (wavefronts) per workgroup of the CG product (1, 2, 4)
     int spmv_nt = 7;      // fg_tune "spmv_nt": nontemporal-access mask of the CG product (values 1, indices 2,
                           // halo lists 4, product stores 8)
     int mr_tile = 0;  // fg_tune "rhs_tile": 0 = row-group product, else columns per column-tile pass

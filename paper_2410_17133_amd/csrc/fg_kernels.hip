@@ -753,11 +753,12 @@ __global__ __launch_bounds__(FIN) void k_cg_init_fin(const double *partials, int
     double tot[2];
     finalize_sum<2>(partials, stride, nparts, tot);
     if (threadIdx.x != 0) return;
-    sc->rho = tot[0];
+    sc->rho[0] = tot[0];
     sc->rr = tot[1];
     sc->bb = tot[1];
     sc->tol2 = tol * tol * tot[1];
-    sc->iter = 0;
+    sc->iter[0] = 0;
+    sc->iters = 0;
     sc->status = FG_OK;
     sc->done = 0;
     if (!isfinite(tot[0]) || !isfinite(tot[1])) {
@@ -772,7 +773,7 @@ __global__ __launch_bounds__(FIN) void k_cg_init_fin(const double *partials, int
 }
 
 // q = A p and the per-block partials of p.q.
-template <int BS, typename T, typename TV, int UNR, int NT>
+template <int BS, typename T, typename TV, int UNR, int NT, int WPB>
 __global__ __launch_bounds__(WG) void k_cg_spmv(SpmvArgs a, const TV *__restrict__ val, const T *__restrict__ p,
                                                 T *__restrict__ q, double *partials, int64_t stride,
                                                 const CgScalars *sc)
@@ -781,7 +782,7 @@ __global__ __launch_bounds__(WG) void k_cg_spmv(SpmvArgs a, const TV *__restrict
     extern __shared__ unsigned char smem[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     T *xs = (T *)smem + (int64_t)wave * a.cap * BS;
-    const int64_t s = xcd_block() * (WG / SLICE) + wave;
+    const int64_t s = xcd_block() * WPB + wave;
     bool staged = false;
     if (s < a.nslices) staged = stage_halo<BS, T, (NT & 4) != 0>(s, lane, a.halo_ptr, a.halo, a.cap, p, xs);
     __syncthreads();
@@ -791,34 +792,39 @@ __global__ __launch_bounds__(WG) void k_cg_spmv(SpmvArgs a, const TV *__restrict
     block_partials<1>(v, partials, stride);
 }
 
-__global__ __launch_bounds__(FIN) void k_cg_alpha(const double *partials, int64_t stride, int64_t nparts, CgScalars *sc)
-{
-    if (sc->done) return;
-    double tot[1];
-    finalize_sum<1>(partials, stride, nparts, tot);
-    if (threadIdx.x != 0) return;
-    const double pq = tot[0];
-    sc->pq = pq;
-    if (!isfinite(pq)) {
-        sc->status = FG_ERR_NAN;
-        sc->done = 1;
-    } else if (!(pq > 0.0)) {
-        sc->status = FG_ERR_BREAKDOWN;
-        sc->done = 1;
-    } else {
-        sc->alpha = sc->rho / pq;
-    }
-}
-
+// x += alpha p, r -= alpha q, z = D^-1 r and the per-block partials of r.z, r.r
+// (written to rows 2 and 3 of the partials).  alpha = rho / (p.q) is formed by
+// every block from the product's partials in the same fixed order, so all blocks
+// hold the same value; block 0 records it and any breakdown.
 template <typename T>
-__global__ __launch_bounds__(WG) void k_cg_update(int64_t n, const T *__restrict__ dinv, T *__restrict__ x,
+__global__ __launch_bounds__(WG) void k_cg_update(int64_t n, int par, const T *__restrict__ dinv, T *__restrict__ x,
                                                   T *__restrict__ r, const T *__restrict__ p,
                                                   const T *__restrict__ q, double *partials, int64_t stride,
-                                                  const CgScalars *sc)
+                                                  int64_t nparts, CgScalars *sc)
 {
-    if (sc->done) return;
-    const T al = (T)sc->alpha;
+    // block 0 may set the flag while this kernel runs: take it once per block
+    if (__syncthreads_or(sc->done)) return;
+    double tot[1];
+    finalize_sum<1>(partials, stride, nparts, tot);
+    const double pq = tot[0];
+    const bool ok = isfinite(pq) && pq > 0.0;
+    const double alpha = sc->rho[par] / pq;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->pq = pq;
+        if (!isfinite(pq)) {
+            sc->status = FG_ERR_NAN;
+            sc->done = 1;
+        } else if (!(pq > 0.0)) {
+            sc->status = FG_ERR_BREAKDOWN;
+            sc->done = 1;
+        } else {
+            sc->alpha = alpha;
+        }
+    }
+    if (!ok) return;
+    const T al = (T)alpha;
     double v[2] = {0, 0};
+#pragma unroll 4
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         x[i] += al * p[i];
         const T ri = r[i] - al * q[i];
@@ -827,38 +833,46 @@ __global__ __launch_bounds__(WG) void k_cg_update(int64_t n, const T *__restrict
         v[0] += (double)ri * (double)zi;
         v[1] += (double)ri * (double)ri;
     }
-    block_partials<2>(v, partials, stride);
+    block_partials<2>(v, partials + 2 * stride, stride);
 }
 
-__global__ __launch_bounds__(FIN) void k_cg_beta(const double *partials, int64_t stride, int64_t nparts, CgScalars *sc)
-{
-    if (sc->done) return;
-    double tot[2];
-    finalize_sum<2>(partials, stride, nparts, tot);
-    if (threadIdx.x != 0) return;
-    sc->iter += 1;
-    sc->rr = tot[1];
-    if (!isfinite(tot[0]) || !isfinite(tot[1])) {
-        sc->status = FG_ERR_NAN;
-        sc->done = 1;
-    } else if (tot[1] <= sc->tol2) {
-        sc->status = FG_OK;
-        sc->done = 1;
-    } else if (sc->iter >= sc->maxit) {
-        sc->status = FG_NOT_CONVERGED;
-        sc->done = 1;
-    } else {
-        sc->beta = tot[0] / sc->rho;
-        sc->rho = tot[0];
-    }
-}
-
+// Stop test and p = z + beta p.  Every block forms r.z and r.r from the update's
+// partials in the same fixed order and takes the same decision; block 0 records
+// the iteration count, the new rho (slot par^1) and the status.
 template <typename T>
-__global__ __launch_bounds__(WG) void k_cg_pupdate(int64_t n, const T *__restrict__ dinv, const T *__restrict__ r,
-                                                   T *__restrict__ p, const CgScalars *sc)
+__global__ __launch_bounds__(WG) void k_cg_pupdate(int64_t n, int par, const T *__restrict__ dinv,
+                                                   const T *__restrict__ r, T *__restrict__ p,
+                                                   const double *partials, int64_t stride, int64_t nparts,
+                                                   CgScalars *sc)
 {
-    if (sc->done) return;
-    const T be = (T)sc->beta;
+    if (__syncthreads_or(sc->done)) return;
+    double tot[2];
+    finalize_sum<2>(partials + 2 * stride, stride, nparts, tot);
+    const int64_t it = sc->iter[par] + 1;
+    const bool finite = isfinite(tot[0]) && isfinite(tot[1]);
+    const bool stop = !finite || tot[1] <= sc->tol2 || it >= sc->maxit;
+    const double beta = tot[0] / sc->rho[par];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->iter[par ^ 1] = it;
+        sc->iters = it;
+        sc->rr = tot[1];
+        if (!finite) {
+            sc->status = FG_ERR_NAN;
+            sc->done = 1;
+        } else if (tot[1] <= sc->tol2) {
+            sc->status = FG_OK;
+            sc->done = 1;
+        } else if (it >= sc->maxit) {
+            sc->status = FG_NOT_CONVERGED;
+            sc->done = 1;
+        } else {
+            sc->beta = beta;
+            sc->rho[par ^ 1] = tot[0];
+        }
+    }
+    if (stop) return;
+    const T be = (T)beta;
+#pragma unroll 4
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = dinv[i] * r[i] + be * p[i];
 }
@@ -1088,14 +1102,21 @@ static void prof_collect(fg_system *S, int64_t worked)
     S->prof_pending = 0;
 }
 
-// The CG product with the tuned slot unroll depth and value-load hint.
+// The CG product with the tuned slot unroll depth, access hints and waves per workgroup.
 template <int BS, typename T, typename TV>
 static void cg_spmv_launch(fg_system *S, int64_t gs, const TV *val, const T *p, T *q, hipStream_t st)
 {
-    const size_t lds = spmv_lds<BS, T>(S);
+    const size_t lds = (size_t)S->spmv_wpb * S->halo_cap * BS * sizeof(T);
     const SpmvArgs a = spmv_args(S);
-#define FG_CG_SPMV(U, N)                                                                                    \
-    LAUNCH_SH((k_cg_spmv<BS, T, TV, U, N>), gs, WG, lds, st, a, val, p, q, S->partials, S->npartials, S->sc)
+#define FG_CG_SPMV_W(U, N, W)                                                                               \
+    LAUNCH_SH((k_cg_spmv<BS, T, TV, U, N, W>), gs, 64 * W, lds, st, a, val, p, q, S->partials, S->npartials, \
+              S->sc)
+#define FG_CG_SPMV(U, N)                  \
+    switch (S->spmv_wpb) {                \
+    case 1: FG_CG_SPMV_W(U, N, 1); break; \
+    case 2: FG_CG_SPMV_W(U, N, 2); break; \
+    default: FG_CG_SPMV_W(U, N, 4); break; \
+    }
 #define FG_CG_SPMV_NT(U)                   \
     switch (S->spmv_nt) {                  \
     case 0: FG_CG_SPMV(U, 0); break;       \
@@ -1112,6 +1133,7 @@ static void cg_spmv_launch(fg_system *S, int64_t gs, const TV *val, const T *p, 
     }
 #undef FG_CG_SPMV_NT
 #undef FG_CG_SPMV
+#undef FG_CG_SPMV_W
 }
 
 template <int BS, typename T, typename TV>
@@ -1120,15 +1142,15 @@ static void cg_launch_batch(fg_system *S, const TV *val, const T *dinv, T *x, T 
 {
     const std::vector<hipEvent_t> &ev = S->prof_ev[slot];
     const int64_t n = BS * S->Npad;
-    const int64_t gs = grid_xcd((S->nslices + 3) / 4), ge = grid_elems(n);
+    const int64_t gs = grid_xcd((S->nslices + S->spmv_wpb - 1) / S->spmv_wpb);
+    const int64_t ge = std::min<int64_t>(grid_vec(n) * S->vec_grid / 512, std::max<int64_t>((n + WG - 1) / WG, 1));
     for (int it = 0; it < iters; ++it) {
+        const int par = it & 1;  // batches have an even length and start at parity 0
         if (prof) hipEventRecord(ev[2 * it], st);
         cg_spmv_launch<BS, T, TV>(S, gs, val, p, q, st);
         if (prof) hipEventRecord(ev[2 * it + 1], st);
-        LAUNCH(k_cg_alpha, 1, FIN, st, S->partials, S->npartials, gs, S->sc);
-        LAUNCH((k_cg_update<T>), ge, WG, st, n, dinv, x, r, p, q, S->partials, S->npartials, S->sc);
-        LAUNCH(k_cg_beta, 1, FIN, st, S->partials, S->npartials, ge, S->sc);
-        LAUNCH((k_cg_pupdate<T>), ge, WG, st, n, dinv, r, p, S->sc);
+        LAUNCH((k_cg_update<T>), ge, WG, st, n, par, dinv, x, r, p, q, S->partials, S->npartials, gs, S->sc);
+        LAUNCH((k_cg_pupdate<T>), ge, WG, st, n, par, dinv, r, p, S->partials, S->npartials, ge, S->sc);
     }
 }
 
@@ -1210,7 +1232,8 @@ fg_status cg_run(fg_system *S, int which, int precision, double tol, int64_t max
     LAUNCH(k_cg_init_fin, 1, FIN, st, S->partials, S->npartials, grid_elems(n), S->sc, tol);
     fg_status e = check_hip("cg init");
     if (e) return e;
-    const int batch = check_every > 0 ? check_every : 32;
+    // even batches keep the scalars' parity at 0 between polls
+    const int batch = check_every > 0 ? (check_every + 1) / 2 * 2 : 32;
     int64_t iter0 = 0;
     S->prof_pending = 0;
     for (;;) {
@@ -1218,9 +1241,9 @@ fg_status cg_run(fg_system *S, int which, int precision, double tol, int64_t max
         hipStreamSynchronize(st);
         e = check_hip("cg poll");
         if (e) return e;
-        if (S->prof_pending) prof_collect(S, S->sc_host->iter - iter0);
+        if (S->prof_pending) prof_collect(S, S->sc_host->iters - iter0);
         if (S->sc_host->done) break;
-        iter0 = S->sc_host->iter;
+        iter0 = S->sc_host->iters;
         if (f32)
             e = cg_batch<3, float, float>(S, S->K32, S->dinvK32, S->fx, S->fr, S->fp, S->fq, batch, 1, st);
         else if (which == FG_K)
@@ -1230,7 +1253,7 @@ fg_status cg_run(fg_system *S, int which, int precision, double tol, int64_t max
         if (e) return e;
     }
     const CgScalars &h = *S->sc_host;
-    *iters = h.iter;
+    *iters = h.iters;
     *relres = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
     if (h.status == FG_ERR_BREAKDOWN) set_error("fg_pcg_solve: CG breakdown (p.Ap <= 0): operator not SPD");
     if (h.status == FG_ERR_NAN) set_error("fg_pcg_solve: NaN or Inf in the CG iteration");

@@ -197,7 +197,14 @@ def test_product_tuning_knobs_do_not_change_results():
             np.testing.assert_array_equal(a_, b_)
     S.tune("spmv_unroll", 2)
     S.tune("spmv_nt", 7)
-    for key, bad in (("spmv_unroll", 5), ("spmv_nt", 2)):
+    # workgroup shapes regroup the partial sums of the dot products: same solution to rounding
+    for wpb, vg in ((1, 2048), (2, 1024), (4, 512)):
+        S.tune("spmv_wpb", wpb)
+        S.tune("vec_grid", vg)
+        xk, ik = S.pcg_solve(fg.FG_K, dev(b), tol=1e-10)
+        assert abs(ik.iters - ref[1]) <= 2
+        assert relerr(host(xk), ref[0]) < 1e-9
+    for key, bad in (("spmv_unroll", 5), ("spmv_nt", 2), ("spmv_wpb", 3), ("vec_grid", 256)):
         with pytest.raises(fg.FgError):
             S.tune(key, bad)
 

@@ -294,19 +294,54 @@ def test_terzaghi_column():
 
 
 # ------------------------------------------------------------ fracture flow from a point injection
+def golden_slip_benchmark():
+    """The Sec. 4.2 values of tests/golden/slip_benchmark_sec42.txt as a dict."""
+    import os
+    out = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "slip_benchmark_sec42.txt")) as f:
+        for line in f:
+            line = line.split("#")[0].split()
+            if line:
+                out[line[0]] = float(line[1])
+    return out
+
+
+def characteristic_pressure(Q, mu, wk_par):
+    """dp* = Q mu / (4 pi k_par w), the pressure scale of a constant-rate injection
+    into a fault (Sec. 4.2)."""
+    return Q * mu / (4 * math.pi * wk_par)
+
+
+def test_fault_stress_parameter_from_printed_values():
+    """T = (1 - tau0/(f sigma0)) / (dp*/sigma0) (Sec. 4.2) evaluated on the printed
+    loads: the marginally pressurized case gives the printed T = 4.  The printed shear
+    load of the critically stressed case gives T = 0.0235, not the printed 0.01 (the
+    paper is at odds with itself there); both are in the T << 1 regime."""
+    g = golden_slip_benchmark()
+    dps = characteristic_pressure(g["Q"], g["mu_f"], g["wk_par"])
+    assert dps == pytest.approx(70.82e3, rel=1e-3)
+    T = lambda tau0: (1 - tau0 / (g["f"] * g["sigma0"])) / (dps / g["sigma0"])
+    assert T(g["tau0_MP"]) == pytest.approx(g["T_MP"], rel=2e-3)
+    assert T(g["tau0_CS"]) == pytest.approx(0.02353, rel=1e-3)
+    assert T(g["tau0_CS"]) < 0.1 < 1 < T(g["tau0_MP"])
+
+
 @pytest.mark.slow
 def test_fracture_point_injection_theis():
     """Pressure on an isolated fracture fed at constant rate Q: with an
     impermeable, stiff-storage matrix it is the line-source solution
     p = dp* E1(r^2 / (4 a_f t)), dp* = Q mu / (4 pi k_par w) (Sec. 4.2),
     a_f = k_par M_F / mu (conductance w k_par / mu over storage w / M_F)."""
+    g = golden_slip_benchmark()
     n = 32
-    prm = I.Params(mu=0.89e-3, biot_M=1e14, k_par=1e-12, k_perp=1e-12, w0=1e-3, M_F=0.2e6, dt=0.25)
+    # Sec. 4.2 fluid and fracture (w k_par = 1e-15 m^3 split as w = 1 mm, k_par = 1e-12 m^2)
+    prm = I.Params(mu=g["mu_f"], biot_M=1e14, k_par=g["wk_par"] / 1e-3, k_perp=g["wk_par"] / 1e-3, w0=1e-3,
+                   M_F=g["M_F"], dt=0.25)
     inst = box_instance(n, n, n, fault_i=n // 2, params=prm, lnk=math.log(1e-30))
     m = inst.mesh
     P = O.Problem(inst)
     c = n // 2 + (n + 1) * (n // 2)
-    Q = 1e-6
+    Q = g["Q"]
     fp = np.zeros(P.N)
     fp[m.pairs[c]] = Q / 2
     p = np.zeros(P.N)
@@ -318,7 +353,7 @@ def test_fracture_point_injection_theis():
         p += dp
     t = steps * prm.dt
     af = prm.k_par * prm.M_F / prm.mu
-    dps = Q * prm.mu / (4 * math.pi * prm.k_par * prm.w0)
+    dps = characteristic_pressure(Q, prm.mu, prm.k_par * prm.w0)
     xy = m.xyz[m.pairs[:, 0]][:, 1:] - 0.5
     r = np.hypot(xy[:, 0], xy[:, 1])
     h = 1.0 / n
