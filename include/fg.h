@@ -66,6 +66,8 @@ typedef int fg_status;
 #define FG_F64 0    /* FP64 storage and arithmetic */
 #define FG_F32 1    /* FP32 matrix and vectors throughout (no refinement) */
 #define FG_MIXED 2  /* FP32 inner PCG, FP64 residual and iterative refinement */
+#define FG_MIXED_F32VAL 3  /* inner PCG on the FP32 matrix values with FP64 vectors and arithmetic,
+                              FP64 residual and refinement (single right-hand side, unbatched) */
 
 typedef struct fg_ctx fg_ctx;
 typedef struct fg_system fg_system;
@@ -97,7 +99,7 @@ typedef struct {
 typedef struct {
     double tol;          /* stop when ||b - A x||_2 <= tol ||b||_2 (K solves: FP64 residual for FG_MIXED) */
     int64_t max_iter;    /* CG iterations (inner iterations in total for FG_MIXED) */
-    int precision;       /* FG_F64 / FG_F32 / FG_MIXED (K only; A22 solves are FP64) */
+    int precision;       /* FG_F64 / FG_F32 / FG_MIXED / FG_MIXED_F32VAL (K only; A22 solves are FP64) */
     int check_every;     /* iterations between convergence polls by the host (0 = default 32) */
     double inner_tol;    /* FG_MIXED: relative tolerance of each FP32 inner solve (0 = default 1e-4) */
 } fg_pcg_opts;
@@ -320,7 +322,8 @@ fg_status fg_tune(fg_system *sys, const char *key, int64_t value);
  * enable != 0: CG iterations launch kernel by kernel (no graph replay) and
  * record a timing-only HIP event (no system-scope fence) on the solve's stream
  * before and after each SpMV launch; durations are summed per operator slot:
- * 0 = K in FP64, 1 = K in FP32, 2 = A22.  fg_profile_read returns the number of
+ * 0 = K in FP64, 1 = K in FP32, 2 = A22, 3 = K with FP32 values and FP64 vectors.
+ * fg_profile_read returns the number of
  * timed launches and their total milliseconds for `slot`, and clears the slot
  * when reset != 0. */
 fg_status fg_profile(fg_system *sys, int enable);

@@ -192,7 +192,8 @@ fg_status k_solve(fg_system *S, const double *rhs, double *out, const fg_pcg_opt
         }
         return s;
     }
-    // Mixed precision: FP32 inner CG on the correction equation, FP64 true
+    // Mixed precision: inner CG on the correction equation with the FP32 matrix
+    // (FP32 vectors for FG_MIXED, FP64 vectors for FG_MIXED_F32VAL), FP64 true
     // residual and accumulation (iterative refinement).
     if (!S->k32_valid) refresh_k32(S, st);
     if (S->ngroups > 1) return k_solve_mixed_grouped(S, rhs, out, o, info, st);
@@ -219,18 +220,27 @@ fg_status k_solve(fg_system *S, const double *rhs, double *out, const fg_pcg_opt
             s = FG_NOT_CONVERGED;
             break;
         }
-        to_f32(n, 1.0 / rn, r, S->fr, st);
+        const bool f32vec = o.precision == FG_MIXED;
+        if (f32vec) {
+            to_f32(n, 1.0 / rn, r, S->fr, st);
+        } else {
+            hipMemcpyAsync(S->wr, r, n * sizeof(double), hipMemcpyDeviceToDevice, st);
+            vaxpby(n, 0.0, S->wr, 1.0 / rn, S->wr, st);
+        }
         int64_t it = 0;
         double rr = 0;
-        fg_status si = cg_run(S, FG_K, FG_F32, std::max(o.inner_tol, o.tol * bn / rn), o.max_iter - total,
-                              o.check_every, &it, &rr, st);
+        fg_status si = cg_run(S, FG_K, f32vec ? FG_F32 : FG_MIXED_F32VAL, std::max(o.inner_tol, o.tol * bn / rn),
+                              o.max_iter - total, o.check_every, &it, &rr, st);
         total += it;
         cycles++;
         if (si < 0) {
             s = si;
             break;
         }
-        add_f32(n, rn, S->fx, x, st);
+        if (f32vec)
+            add_f32(n, rn, S->fx, x, st);
+        else
+            vaxpby(n, rn, S->wx, 1.0, x, st);
         spmv(S, FG_K, x, S->wq, st);
         hipMemcpyAsync(r, rhs, n * sizeof(double), hipMemcpyDeviceToDevice, st);
         vaxpby(n, -1.0, S->wq, 1.0, r, st);
@@ -646,6 +656,11 @@ fg_status fg_pcg_solve(fg_ctx *ctx, fg_system *S, int which, int nrhs, const dou
     fg_pcg_opts o = defaults(opts, 1e-10);
     if (opts && !(opts->tol > 0)) {
         set_error("fg_pcg_solve: tol must be positive");
+        return FG_ERR_ARG;
+    }
+    if (o.precision < FG_F64 || o.precision > FG_MIXED_F32VAL ||
+        (o.precision == FG_MIXED_F32VAL && (nrhs > 1 || S->ngroups > 1))) {
+        set_error("fg_pcg_solve: bad precision (FG_MIXED_F32VAL takes one right-hand side on an unbatched system)");
         return FG_ERR_ARG;
     }
     const int bs = which == FG_K ? 3 : 1;
@@ -1145,7 +1160,7 @@ fg_status fg_profile(fg_system *S, int enable)
 
 fg_status fg_profile_read(fg_system *S, int slot, int64_t *launches, double *ms, int reset)
 {
-    if (!S || slot < 0 || slot > 2) {
+    if (!S || slot < 0 || slot > 3) {
         set_error("fg_profile_read: bad argument");
         return FG_ERR_ARG;
     }

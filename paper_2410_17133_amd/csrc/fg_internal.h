@@ -165,7 +165,7 @@ struct fg_system {
     bool use_graphs = true;
     bool line_search = true;  // fg_tune "line_search": backtracking on the Newton steps of fg_step
     hipStream_t cap_stream = nullptr;
-    fg::GraphCache cg_graph[3];
+    fg::GraphCache cg_graph[4];  // K FP64, K FP32, A22, K with FP32 values and FP64 vectors
     // block solves (many right-hand sides), column-interleaved workspaces
     int mr_cap = 0;   // columns allocated
     int spmv_unroll = 2;  // fg_tune "spmv_unroll": slots per unrolled step of the CG product (2, 3, 4, 6)
@@ -183,9 +183,9 @@ struct fg_system {
     fg::GraphCache mr_graph[2];  // FP64, FP32
     // live kernel timing (fg_profile)
     bool prof = false;
-    std::vector<hipEvent_t> prof_ev[3];  // per operator slot: pairs (start, stop), one per launch of a batch
+    std::vector<hipEvent_t> prof_ev[4];  // per operator slot: pairs (start, stop), one per launch of a batch
     int prof_pending = 0;
     int prof_slot = 0;
-    int64_t prof_count[3] = {0, 0, 0};
-    double prof_ms[3] = {0, 0, 0};
+    int64_t prof_count[4] = {0, 0, 0, 0};
+    double prof_ms[4] = {0, 0, 0, 0};
 };

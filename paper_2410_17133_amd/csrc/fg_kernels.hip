@@ -1221,8 +1221,10 @@ fg_status cg_run(fg_system *S, int which, int precision, double tol, int64_t max
     init.maxit = maxit;
     hipMemcpyAsync(S->sc, &init, sizeof init, hipMemcpyHostToDevice, st);
     const bool f32 = (which == FG_K && precision == FG_F32);
-    if (f32) {
+    const bool f32val = (which == FG_K && precision == FG_MIXED_F32VAL);
+    if (f32 || f32val)
         if (!S->k32_valid) refresh_k32(S, st);
+    if (f32) {
         LAUNCH((k_cg_init<float>), grid_elems(n), WG, st, n, S->dinvK32, S->fx, S->fr, S->fp, S->partials, S->npartials);
     } else if (which == FG_K) {
         LAUNCH((k_cg_init<double>), grid_elems(n), WG, st, n, S->dinvK, S->wx, S->wr, S->wp, S->partials, S->npartials);
@@ -1246,6 +1248,8 @@ fg_status cg_run(fg_system *S, int which, int precision, double tol, int64_t max
         iter0 = S->sc_host->iters;
         if (f32)
             e = cg_batch<3, float, float>(S, S->K32, S->dinvK32, S->fx, S->fr, S->fp, S->fq, batch, 1, st);
+        else if (f32val)
+            e = cg_batch<3, double, float>(S, S->K32, S->dinvK, S->wx, S->wr, S->wp, S->wq, batch, 3, st);
         else if (which == FG_K)
             e = cg_batch<3, double, double>(S, S->K, S->dinvK, S->wx, S->wr, S->wp, S->wq, batch, 0, st);
         else

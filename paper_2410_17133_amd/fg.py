@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libfg.so")
 FG_OK, FG_NOT_CONVERGED = 0, 1
 FG_ERR_ARG, FG_ERR_OOM, FG_ERR_BREAKDOWN, FG_ERR_NAN, FG_ERR_HIP, FG_ERR_STATE = -1, -2, -3, -4, -5, -6
 FG_K, FG_A22, FG_KBULK, FG_C = 0, 1, 2, 3
-FG_F64, FG_F32, FG_MIXED = 0, 1, 2
+FG_F64, FG_F32, FG_MIXED, FG_MIXED_F32VAL = 0, 1, 2, 3
 
 SYMBOLS = ["fg_last_error", "fg_ctx_create", "fg_ctx_destroy", "fg_system_create", "fg_system_destroy",
            "fg_assemble", "fg_cohesive_update", "fg_pcg_solve", "fg_flow_solve", "fg_step", "fg_spmv",
@@ -312,7 +312,8 @@ class System:
         _check(lib().fg_profile(self._h, int(bool(enable))), False)
 
     def profile_read(self, slot=0, reset=True):
-        """(launches, milliseconds) of the timed CG product kernel for slot 0 = K FP64, 1 = K FP32, 2 = A22."""
+        """(launches, milliseconds) of the timed CG product kernel for slot 0 = K FP64, 1 = K FP32, 2 = A22,
+        3 = K with FP32 values and FP64 vectors."""
         n, ms = C.c_int64(), C.c_double()
         _check(lib().fg_profile_read(self._h, slot, C.byref(n), C.byref(ms), int(bool(reset))), False)
         return n.value, ms.value

@@ -247,6 +247,19 @@ def test_pcg_mixed_and_f32():
     x32, info32 = S.pcg_solve(fg.FG_K, dev(b), tol=1e-5, precision=fg.FG_F32)
     assert info32.status == 0
     assert np.linalg.norm(b - P.spmv(O.K_TANGENT, host(x32))) <= 5e-3 * np.linalg.norm(b)
+    # FP32 matrix values with FP64 vectors: refinement to the same FP64 true residual,
+    # with about the iteration count of the FP64 solve (no FP32 stagnation)
+    x64, i64 = S.pcg_solve(fg.FG_K, dev(b), tol=1e-8)
+    xv, iv = S.pcg_solve(fg.FG_K, dev(b), tol=1e-8, precision=fg.FG_MIXED_F32VAL)
+    print(f"[mixed f32 values] cycles {iv.cycles} iters {iv.iters} (fp64 {i64.iters})", flush=True)
+    assert iv.status == 0 and iv.cycles >= 1
+    assert np.linalg.norm(b - P.spmv(O.K_TANGENT, host(xv))) <= 1e-8 * np.linalg.norm(b)
+    assert iv.iters <= 1.5 * i64.iters
+    with pytest.raises(fg.FgError) as e:
+        S.pcg_solve(fg.FG_K, dev(np.zeros(2 * 3 * S.N)), nrhs=2, precision=fg.FG_MIXED_F32VAL)
+    assert e.value.status == fg.FG_ERR_ARG
+    with pytest.raises(fg.FgError):
+        S.pcg_solve(fg.FG_K, dev(b), precision=7)
 
 
 def test_flow_solve_parity():
