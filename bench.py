@@ -47,6 +47,9 @@ def main():
     ap.add_argument("--profile-iters", type=int, default=0,
                     help="profiling mode for hardware counters: run exactly this many FP64 K-PCG iterations and "
                          "one 1 GiB device copy (counter calibration), print a short JSON line, skip the rest")
+    ap.add_argument("--profile-block", type=int, default=0,
+                    help="profiling mode for the block product: this many FP64 block-CG iterations on 32 "
+                         "right-hand sides at 64^3, then one 1 GiB device copy; prints a short JSON line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the solver's multi-GPU sharding is not part of this build "
@@ -62,6 +65,9 @@ def main():
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
+    if args.profile_block > 0:
+        profile_block(args.profile_block)
+        return
     n = args.n
     cfg = I.config(3) if n == 128 else I.cube_config(n, dip_deg=60.0, heterogeneous=True)
     t = time.perf_counter()
@@ -217,6 +223,33 @@ def main():
         if extras:
             out["cpu_baseline_64"] = cpu_baseline(I.make_instance(I.config(2)), 4 * args.cpu_iters, log)
     print(json.dumps(out), flush=True)
+
+
+def profile_block(iters):
+    """Fixed-length FP64 block CG (32 columns, 64^3) for kernel-trace and counter runs."""
+    import numpy as np
+    import torch
+
+    from paper_2410_17133_amd import fg
+    from paper_2410_17133_amd import inputs as I
+
+    inst = I.make_instance(I.config(5))
+    ctx = fg.Context(0)
+    S = fg.System.from_instance(ctx, inst)
+    S.assemble(inst.params, inst.E, inst.logk)
+    npairs, nblk, nslices, nhalo = S.sizes()
+    B = torch.as_tensor(np.random.default_rng(0).standard_normal((32, 3 * S.N)) * (1 - inst.dir_u)).cuda()
+    X, info = S.pcg_solve(fg.FG_K, B.reshape(-1).contiguous(), nrhs=32, tol=1e-300, max_iter=iters,
+                          check_every=iters)
+    src_t = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+    dst_t = torch.empty_like(src_t)
+    dst_t.copy_(src_t)
+    torch.cuda.synchronize()
+    # algorithmic bytes of one 32-column FP64 row-group product: each stored block (72 B) and its
+    # column index (4 B) once; P read and Q written once (3 x 32 x 8 B per node each)
+    print(json.dumps({"profile_block_iters": info.iters, "nrhs": 32, "nodes": S.N, "blocks": npairs,
+                      "product_bytes_per_launch": 76.0 * npairs + 2 * 768.0 * S.N,
+                      "copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30}), flush=True)
 
 
 def measured_traffic(n):

@@ -225,7 +225,7 @@ fg_status k_solve(fg_system *S, const double *rhs, double *out, const fg_pcg_opt
             to_f32(n, 1.0 / rn, r, S->fr, st);
         } else {
             hipMemcpyAsync(S->wr, r, n * sizeof(double), hipMemcpyDeviceToDevice, st);
-            vaxpby(n, 0.0, S->wr, 1.0 / rn, S->wr, st);
+            vscale(n, 1.0 / rn, S->wr, st);
         }
         int64_t it = 0;
         double rr = 0;
@@ -846,8 +846,8 @@ fg_status fg_step(fg_ctx *ctx, fg_system *S, double *U, double *P, double *die, 
             status = FG_NOT_CONVERGED;
             break;
         }
-        vaxpby(n1, 0.0, S->rm, -1.0, S->rm, st);
-        vaxpby(n2, 0.0, S->rf, -1.0, S->rf, st);
+        vscale(n1, -1.0, S->rm, st);
+        vscale(n2, -1.0, S->rf, st);
         fg_status s = prevost(S, S->rm, S->rf, S->du, S->dpv, ok, op, outer_tol,
                               outer_max_iter > 0 ? outer_max_iter : 1000, &si, st);
         if (s < 0) {
@@ -908,7 +908,7 @@ fg_status fg_adjoint_solve(fg_ctx *ctx, fg_system *S, const double *U, const dou
     vfill(mu, 0.0, n1, st);
     vfill(lp, 0.0, n2, st);
     hipMemcpyAsync(r1, S->fi, n1 * sizeof(double), hipMemcpyDeviceToDevice, st);
-    vaxpby(n1, 0.0, r1, -1.0, r1, st);  // r1 = -dJ/dU  (vaxpby: y = a x + b y)
+    vscale(n1, -1.0, r1, st);  // r1 = -dJ/dU
     hipMemcpyAsync(r2, S->qi, n2 * sizeof(double), hipMemcpyDeviceToDevice, st);
     fg_status status = FG_NOT_CONVERGED;
     double change = 0;
@@ -946,7 +946,7 @@ fg_status fg_adjoint_solve(fg_ctx *ctx, fg_system *S, const double *U, const dou
         apply_NT(S, mu, S->v2, st);
         apply_Apu(S, lp, S->pv1, st);
         hipMemcpyAsync(r1, S->fi, n1 * sizeof(double), hipMemcpyDeviceToDevice, st);
-        vaxpby(n1, 0.0, r1, -1.0, r1, st);
+        vscale(n1, -1.0, r1, st);
         vaxpby(n1, -1.0, S->v1, 1.0, r1, st);
         vaxpby(n1, -1.0, S->v2, 1.0, r1, st);
         vaxpby(n1, 1.0, S->pv1, 1.0, r1, st);
@@ -960,7 +960,7 @@ fg_status fg_adjoint_solve(fg_ctx *ctx, fg_system *S, const double *U, const dou
     si.inner_k_iters = kit;
     si.inner_a22_iters = ait;
     if (status >= 0) {
-        vaxpby(n1, 0.0, mu, -1.0, mu, st);  // lam_u = -mu
+        vscale(n1, -1.0, mu, st);  // lam_u = -mu
         sensitivity(S, S->ui, S->pi, mu, lp, dJ_dE, dJ_dlogk, log_k, st);
         if (lam_u) perm_out(S, 3, mu, lam_u, st);
         if (lam_p) perm_out(S, 1, lp, lam_p, st);

@@ -38,6 +38,7 @@ void spmv_k32(fg_system *S, const float *x, float *y, hipStream_t st);
 void vfill(double *y, double v, int64_t n, hipStream_t st);
 // y = a*x + b*y
 void vaxpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t st);
+void vscale(int64_t n, double a, double *y, hipStream_t st);  // y = a y
 // y[i] = mask[i] ? 0 : y[i]
 void vmask(int64_t n, const uint8_t *mask, double *y, hipStream_t st);
 // red[slot+k] = dot(a_k, b_k) for k < nd; synchronous result in host[0..nd)

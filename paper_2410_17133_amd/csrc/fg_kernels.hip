@@ -663,6 +663,12 @@ __global__ void k_axpby(int64_t n, double a, const double *__restrict__ x, doubl
         y[i] = a * x[i] + b * y[i];
 }
 
+__global__ void k_scale(int64_t n, double a, double *y)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] *= a;
+}
+
 __global__ void k_mask(int64_t n, const uint8_t *__restrict__ m, double *y)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -911,6 +917,8 @@ void vaxpby(int64_t n, double a, const double *x, double b, double *y, hipStream
 {
     LAUNCH(k_axpby, grid_elems(n), WG, st, n, a, x, b, y);
 }
+
+void vscale(int64_t n, double a, double *y, hipStream_t st) { LAUNCH(k_scale, grid_elems(n), WG, st, n, a, y); }
 
 void vmask(int64_t n, const uint8_t *mask, double *y, hipStream_t st) { LAUNCH(k_mask, grid_elems(n), WG, st, n, mask, y); }
 

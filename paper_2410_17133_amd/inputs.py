@@ -212,7 +212,8 @@ def make_mesh(nx: int, ny: int, nz: int, L=(1.0, 1.0, 1.0), fault_i: int | None 
     if fault_i is not None and abs(dip_deg - 90.0) > 1e-12:
         x_mid = fault_i * Lx / nx
         xf = x_mid + (z - 0.5 * Lz) / math.tan(math.radians(dip_deg))
-        assert np.all(xf > 0) and np.all(xf < Lx), "fault plane leaves the box"
+        if not (np.all(xf > 0) and np.all(xf < Lx)):
+            raise ValueError(f"a fault dipping {dip_deg} degrees leaves the box through its side faces")
         x = np.where(fi <= fault_i, xf * fi / fault_i, xf + (Lx - xf) * (fi - fault_i) / (nx - fault_i))
     else:
         x = fi * (Lx / nx)
