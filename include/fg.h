@@ -101,7 +101,8 @@ typedef struct {
     int64_t max_iter;    /* CG iterations (inner iterations in total for FG_MIXED) */
     int precision;       /* FG_F64 / FG_F32 / FG_MIXED / FG_MIXED_F32VAL (K only; A22 solves are FP64) */
     int check_every;     /* iterations between convergence polls by the host (0 = default 32) */
-    double inner_tol;    /* FG_MIXED: relative tolerance of each FP32 inner solve (0 = default 1e-4) */
+    double inner_tol;    /* FG_MIXED / FG_MIXED_F32VAL: relative tolerance of each inner solve
+                            (0 = default 1e-4) */
 } fg_pcg_opts;
 
 typedef struct {
@@ -299,16 +300,18 @@ fg_status fg_group_stats(const fg_system *sys, int64_t *iters_h, double *relres_
  *               HIP graph, 0 launches the kernels one by one (same results).
  *   "line_search": 1 (default) backtracking on the Newton steps of fg_step,
  *               0 full steps.
- *   "spmv_unroll": slots per unrolled step of the CG product: 2 (default),
+ *   "spmv_unroll": slots per unrolled step of the CG product: 1, 2 (default),
  *               3, 4 or 6.
  *   "vec_grid": workgroups of the CG vector kernels: 512 (default), 1024 or
  *               2048 (each adds the previous kernel's partial sums itself).
  *   "spmv_wpb": slices (one wavefront each) per workgroup of the CG
  *               product: 1, 2 or 4 (default); the slices of a workgroup
  *               share its LDS and its staging barrier.
- *   "spmv_nt":  nontemporal-access mask of the CG product: 1 matrix values,
- *               2 column indices, 4 halo lists, 8 product stores; 0, 1, 3,
- *               7 (default) or 15.  Results are identical for every value.
+ *   "spmv_nt":  access mask of the CG product: nontemporal loads of matrix
+ *               values (1), column indices (2), halo lists (4), nontemporal
+ *               product stores (8), and (16) the next slots' loads issued
+ *               before the current ones are used; 0, 1, 3, 7, 15 or 23
+ *               (default).  Results are identical for every value.
  *   "rhs_tile": product of the block (many right-hand sides) solve.  0
  *               (default): with 8 or more columns, the columns of a row are
  *               spread over the lanes and the matrix is streamed once per

@@ -28,13 +28,13 @@ from . import fg
 
 SINGLE_KNOBS = ("halo_cap", "spmv_unroll", "spmv_nt", "spmv_wpb", "vec_grid")
 BLOCK_KNOBS = ("rhs_tile",)
-DEFAULTS = {"spmv_unroll": 2, "spmv_nt": 7, "spmv_wpb": 4, "vec_grid": 512, "rhs_tile": 0}
+DEFAULTS = {"spmv_unroll": 2, "spmv_nt": 23, "spmv_wpb": 4, "vec_grid": 512, "rhs_tile": 0}
 
 
 def single_candidates(mean_halo: float) -> dict:
     """Values tried per knob; halo caps are taken relative to the mean slice halo."""
     caps = sorted({0, 682, *(int(round(mean_halo * f / 32.0)) * 32 for f in (1.0, 1.25, 1.5, 2.0))})
-    return {"halo_cap": caps, "spmv_unroll": [2, 3, 4, 6], "spmv_nt": [0, 1, 3, 7, 15], "spmv_wpb": [1, 2, 4],
+    return {"halo_cap": caps, "spmv_unroll": [1, 2, 3, 4, 6], "spmv_nt": [0, 1, 3, 7, 15, 23], "spmv_wpb": [1, 2, 4],
             "vec_grid": [512, 1024, 2048]}
 
 

@@ -96,13 +96,15 @@ fg_pcg_opts defaults(const fg_pcg_opts *o, double tol)
     d.max_iter = 1000000;
     d.precision = FG_F64;
     d.check_every = 32;
-    d.inner_tol = 1e-4;
+    d.inner_tol = 0;
     if (o) {
         d = *o;
         if (d.check_every <= 0) d.check_every = 32;
-        if (d.inner_tol <= 0) d.inner_tol = 1e-4;
         if (d.max_iter <= 0) d.max_iter = 1000000;
     }
+    // inner solves of the refinement stop at 1e-4: each cycle gains about what the
+    // FP32 matrix values allow, with FP32 or FP64 vectors alike
+    if (d.inner_tol <= 0) d.inner_tol = 1e-4;
     return d;
 }
 
@@ -1096,8 +1098,8 @@ fg_status fg_tune(fg_system *S, const char *key, int64_t value)
         return FG_OK;
     }
     if (std::strcmp(key, "spmv_unroll") == 0) {
-        if (value != 2 && value != 3 && value != 4 && value != 6) {
-            set_error("fg_tune: spmv_unroll must be 2, 3, 4 or 6");
+        if (value != 1 && value != 2 && value != 3 && value != 4 && value != 6) {
+            set_error("fg_tune: spmv_unroll must be 1, 2, 3, 4 or 6");
             return FG_ERR_ARG;
         }
         S->spmv_unroll = (int)value;
@@ -1127,8 +1129,8 @@ fg_status fg_tune(fg_system *S, const char *key, int64_t value)
         return FG_OK;
     }
     if (std::strcmp(key, "spmv_nt") == 0) {
-        if (value != 0 && value != 1 && value != 3 && value != 7 && value != 15) {
-            set_error("fg_tune: spmv_nt must be 0, 1, 3, 7 or 15");
+        if (value != 0 && value != 1 && value != 3 && value != 7 && value != 15 && value != 23) {
+            set_error("fg_tune: spmv_nt must be 0, 1, 3, 7, 15 or 23");
             return FG_ERR_ARG;
         }
         S->spmv_nt = (int)value;

