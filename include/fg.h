@@ -65,7 +65,10 @@ typedef int fg_status;
 /* Arithmetic of a K solve. */
 #define FG_F64 0    /* FP64 storage and arithmetic */
 #define FG_F32 1    /* FP32 matrix and vectors throughout (no refinement) */
-#define FG_MIXED 2  /* FP32 inner PCG, FP64 residual and iterative refinement */
+#define FG_MIXED 2  /* FP32 PCG with FP64 residual replacement: whenever the FP32 residual has dropped
+                      tenfold, the FP32 solution is added to the FP64 one, b - K x is formed in FP64
+                      and replaces the FP32 residual, and CG continues (reliable updates); batched
+                      systems and the block solve refine with restarts of each inner solve */
 #define FG_MIXED_F32VAL 3  /* inner PCG on the FP32 matrix values with FP64 vectors and arithmetic,
                               FP64 residual and refinement (single right-hand side, unbatched) */
 
@@ -107,7 +110,7 @@ typedef struct {
 
 typedef struct {
     int64_t iters;       /* CG iterations performed (sum over refinement cycles) */
-    int64_t cycles;      /* refinement cycles (FG_MIXED), else 1 */
+    int64_t cycles;      /* FG_MIXED: FP64 residual replacements (or refinement cycles), else 1 */
     double relres;       /* final ||b - A x|| / ||b|| as tracked by the solver */
     int status;          /* same value as returned */
 } fg_pcg_info;
@@ -302,6 +305,8 @@ fg_status fg_group_stats(const fg_system *sys, int64_t *iters_h, double *relres_
  *               0 full steps.
  *   "spmv_unroll": slots per unrolled step of the CG product: 1, 2 (default),
  *               3, 4 or 6.
+ *   "mixed_update": FG_MIXED (unbatched): factor by which the FP32 residual
+ *               must drop before the FP64 residual replaces it (default 10).
  *   "vec_grid": workgroups of the CG vector kernels: 512 (default), 1024 or
  *               2048 (each adds the previous kernel's partial sums itself).
  *   "spmv_wpb": slices (one wavefront each) per workgroup of the CG

@@ -194,11 +194,27 @@ fg_status k_solve(fg_system *S, const double *rhs, double *out, const fg_pcg_opt
         }
         return s;
     }
-    // Mixed precision: inner CG on the correction equation with the FP32 matrix
-    // (FP32 vectors for FG_MIXED, FP64 vectors for FG_MIXED_F32VAL), FP64 true
-    // residual and accumulation (iterative refinement).
+    // FG_MIXED_F32VAL: inner CG on the correction equation with the FP32 matrix and
+    // FP64 vectors, FP64 true residual and accumulation (iterative refinement with
+    // restarts).
     if (!S->k32_valid) refresh_k32(S, st);
     if (S->ngroups > 1) return k_solve_mixed_grouped(S, rhs, out, o, info, st);
+    if (o.precision == FG_MIXED) {
+        // FP32 CG with reliable updates: the FP64 residual replaces the FP32 one each
+        // time the latter has dropped tenfold, and the search direction carries over
+        int64_t it = 0, up = 0;
+        double rel = 0;
+        fg_status s = cg_reliable(S, rhs, S->v3, o.tol, o.max_iter, o.check_every, 1.0 / S->mixed_update, &it, &up,
+                                  &rel, st);
+        hipMemcpyAsync(out, S->v3, n * sizeof(double), hipMemcpyDeviceToDevice, st);
+        if (info) {
+            info->iters = it;
+            info->cycles = up;
+            info->relres = rel;
+            info->status = s;
+        }
+        return s;
+    }
     double *x = S->v3, *r = S->v4;
     const double bn = vnorm(S, n, rhs, st);
     vfill(x, 0.0, n, st);
@@ -1104,6 +1120,14 @@ fg_status fg_tune(fg_system *S, const char *key, int64_t value)
         }
         S->spmv_unroll = (int)value;
         drop_graphs(S);
+        return FG_OK;
+    }
+    if (std::strcmp(key, "mixed_update") == 0) {
+        if (value < 2 || value > 1000000) {
+            set_error("fg_tune: mixed_update must be in [2, 1e6]");
+            return FG_ERR_ARG;
+        }
+        S->mixed_update = (int)value;
         return FG_OK;
     }
     if (std::strcmp(key, "vec_grid") == 0) {

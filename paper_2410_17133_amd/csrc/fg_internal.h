@@ -62,6 +62,7 @@ struct CgScalars {
     double tol2;      // tol^2 * b.b
     int64_t iter[2];  // iterations done, by parity
     int64_t iters;    // iterations done (for the host)
+    double rho_cur;   // rho of the iterate at which the stop test ended the iteration
     int64_t maxit;
     int32_t done, status;
 };
@@ -169,6 +170,7 @@ struct fg_system {
     // block solves (many right-hand sides), column-interleaved workspaces
     int mr_cap = 0;   // columns allocated
     int spmv_unroll = 2;  // fg_tune "spmv_unroll": slots per unrolled step of the CG product (2, 3, 4, 6)
+    int mixed_update = 10;  // fg_tune "mixed_update": FP32 residual reduction between FP64 replacements
     int vec_grid = 512;   // fg_tune "vec_grid": workgroups of the CG vector kernels (512, 1024, 2048)
     int spmv_wpb = 4;     // fg_tune "spmv_wpb": slices (wavefronts) per workgroup of the CG product (1, 2, 4)
     int spmv_nt = 23;     // fg_tune "spmv_nt": access mask of the CG product (nontemporal values 1, indices 2,

@@ -48,6 +48,9 @@ void vdots(fg_system *S, int64_t n, int nd, const double *const *a, const double
 // CG on internal-order vectors.  bs = 3 (K) or 1 (A22).  The right-hand side
 // must already be in S->wr (FP64) or S->fr (FP32); the solution is left in
 // S->wx / S->fx.  Returns the final status and fills iters/relres.
+// Mixed-precision K solve with reliable updates (FP32 CG, FP64 residual replacement).
+fg_status cg_reliable(fg_system *S, const double *b, double *x, double tol, int64_t maxit, int check_every,
+                      double delta, int64_t *iters, int64_t *updates, double *relres, hipStream_t st);
 fg_status cg_run(fg_system *S, int which, int precision, double tol, int64_t maxit, int check_every,
                  int64_t *iters, double *relres, hipStream_t st);
 

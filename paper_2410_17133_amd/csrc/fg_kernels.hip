@@ -862,6 +862,7 @@ __global__ __launch_bounds__(WG) void k_cg_pupdate(int64_t n, int par, const T *
         sc->iter[par ^ 1] = it;
         sc->iters = it;
         sc->rr = tot[1];
+        sc->rho_cur = sc->rho[par];
         if (!finite) {
             sc->status = FG_ERR_NAN;
             sc->done = 1;
@@ -879,6 +880,55 @@ __global__ __launch_bounds__(WG) void k_cg_pupdate(int64_t n, int par, const T *
     if (stop) return;
     const T be = (T)beta;
 #pragma unroll 4
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = dinv[i] * r[i] + be * p[i];
+}
+
+// Resumption of a stopped CG after its residual was replaced (reliable update):
+// partials of r.z and r.r of the new residual, then the scalars (beta against the
+// rho at which the iteration stopped, the next stop threshold, parity slot 0),
+// then p = z + beta p, so the search direction carries over.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_cg_resume(int64_t n, const T *__restrict__ dinv, const T *__restrict__ r,
+                                                  double *partials, int64_t stride)
+{
+    double v[2] = {0, 0};
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const T ri = r[i], zi = dinv[i] * ri;
+        v[0] += (double)ri * (double)zi;
+        v[1] += (double)ri * (double)ri;
+    }
+    block_partials<2>(v, partials, stride);
+}
+
+__global__ __launch_bounds__(FIN) void k_cg_resume_fin(const double *partials, int64_t stride, int64_t nparts,
+                                                      CgScalars *sc, double tol2)
+{
+    double tot[2];
+    finalize_sum<2>(partials, stride, nparts, tot);
+    if (threadIdx.x != 0) return;
+    sc->beta = tot[0] / sc->rho_cur;
+    sc->rho[0] = tot[0];
+    sc->rr = tot[1];
+    sc->tol2 = tol2;
+    sc->iter[0] = sc->iters;
+    sc->status = FG_OK;
+    sc->done = 0;
+    if (!isfinite(tot[0]) || !isfinite(tot[1]) || !isfinite(sc->beta)) {
+        sc->status = FG_ERR_NAN;
+        sc->done = 1;
+    } else if (sc->iters >= sc->maxit) {
+        sc->status = FG_NOT_CONVERGED;
+        sc->done = 1;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(WG) void k_cg_resume_p(int64_t n, const T *__restrict__ dinv, const T *__restrict__ r,
+                                                    T *__restrict__ p, const CgScalars *sc)
+{
+    if (sc->done) return;
+    const T be = (T)sc->beta;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = dinv[i] * r[i] + be * p[i];
 }
@@ -1221,10 +1271,43 @@ void drop_graphs(fg_system *S)
     }
 }
 
-fg_status cg_run(fg_system *S, int which, int precision, double tol, int64_t maxit, int check_every, int64_t *iters,
-                 double *relres, hipStream_t st)
+// Batches of CG iterations on the state the init (or a resume) left, polled every
+// check_every iterations until the device-side stop flag is set.
+static fg_status cg_loop(fg_system *S, int which, int precision, int check_every, hipStream_t st)
 {
-    if (S->ngroups > 1) return cg_run_grouped(S, which, precision, tol, maxit, check_every, iters, relres, st);
+    const bool f32 = (which == FG_K && precision == FG_F32);
+    const bool f32val = (which == FG_K && precision == FG_MIXED_F32VAL);
+    // even batches keep the scalars' parity at 0 between polls
+    const int batch = check_every > 0 ? (check_every + 1) / 2 * 2 : 32;
+    int64_t iter0 = -1;
+    S->prof_pending = 0;
+    fg_status e;
+    for (;;) {
+        hipMemcpyAsync(S->sc_host, S->sc, sizeof(CgScalars), hipMemcpyDeviceToHost, st);
+        hipStreamSynchronize(st);
+        e = check_hip("cg poll");
+        if (e) return e;
+        if (S->prof_pending && iter0 >= 0) prof_collect(S, S->sc_host->iters - iter0);
+        if (S->sc_host->done) break;
+        iter0 = S->sc_host->iters;
+        if (f32)
+            e = cg_batch<3, float, float>(S, S->K32, S->dinvK32, S->fx, S->fr, S->fp, S->fq, batch, 1, st);
+        else if (f32val)
+            e = cg_batch<3, double, float>(S, S->K32, S->dinvK, S->wx, S->wr, S->wp, S->wq, batch, 3, st);
+        else if (which == FG_K)
+            e = cg_batch<3, double, double>(S, S->K, S->dinvK, S->wx, S->wr, S->wp, S->wq, batch, 0, st);
+        else
+            e = cg_batch<1, double, double>(S, S->A22, S->dinvA, S->wx, S->wr, S->wp, S->wq, batch, 2, st);
+        if (e) return e;
+    }
+    const CgScalars &h = *S->sc_host;
+    if (h.status == FG_ERR_BREAKDOWN) set_error("fg_pcg_solve: CG breakdown (p.Ap <= 0): operator not SPD");
+    if (h.status == FG_ERR_NAN) set_error("fg_pcg_solve: NaN or Inf in the CG iteration");
+    return h.status;
+}
+
+static void cg_init(fg_system *S, int which, int precision, double tol, int64_t maxit, hipStream_t st)
+{
     const int bs = which == FG_K ? 3 : 1;
     const int64_t n = bs * S->Npad;
     CgScalars init{};
@@ -1242,36 +1325,79 @@ fg_status cg_run(fg_system *S, int which, int precision, double tol, int64_t max
         LAUNCH((k_cg_init<double>), grid_elems(n), WG, st, n, S->dinvA, S->wx, S->wr, S->wp, S->partials, S->npartials);
     }
     LAUNCH(k_cg_init_fin, 1, FIN, st, S->partials, S->npartials, grid_elems(n), S->sc, tol);
+}
+
+fg_status cg_run(fg_system *S, int which, int precision, double tol, int64_t maxit, int check_every, int64_t *iters,
+                 double *relres, hipStream_t st)
+{
+    if (S->ngroups > 1) return cg_run_grouped(S, which, precision, tol, maxit, check_every, iters, relres, st);
+    cg_init(S, which, precision, tol, maxit, st);
     fg_status e = check_hip("cg init");
     if (e) return e;
-    // even batches keep the scalars' parity at 0 between polls
-    const int batch = check_every > 0 ? (check_every + 1) / 2 * 2 : 32;
-    int64_t iter0 = 0;
-    S->prof_pending = 0;
-    for (;;) {
-        hipMemcpyAsync(S->sc_host, S->sc, sizeof(CgScalars), hipMemcpyDeviceToHost, st);
-        hipStreamSynchronize(st);
-        e = check_hip("cg poll");
-        if (e) return e;
-        if (S->prof_pending) prof_collect(S, S->sc_host->iters - iter0);
-        if (S->sc_host->done) break;
-        iter0 = S->sc_host->iters;
-        if (f32)
-            e = cg_batch<3, float, float>(S, S->K32, S->dinvK32, S->fx, S->fr, S->fp, S->fq, batch, 1, st);
-        else if (f32val)
-            e = cg_batch<3, double, float>(S, S->K32, S->dinvK, S->wx, S->wr, S->wp, S->wq, batch, 3, st);
-        else if (which == FG_K)
-            e = cg_batch<3, double, double>(S, S->K, S->dinvK, S->wx, S->wr, S->wp, S->wq, batch, 0, st);
-        else
-            e = cg_batch<1, double, double>(S, S->A22, S->dinvA, S->wx, S->wr, S->wp, S->wq, batch, 2, st);
-        if (e) return e;
-    }
+    e = cg_loop(S, which, precision, check_every, st);
     const CgScalars &h = *S->sc_host;
     *iters = h.iters;
     *relres = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
-    if (h.status == FG_ERR_BREAKDOWN) set_error("fg_pcg_solve: CG breakdown (p.Ap <= 0): operator not SPD");
-    if (h.status == FG_ERR_NAN) set_error("fg_pcg_solve: NaN or Inf in the CG iteration");
-    return h.status;
+    return e;
+}
+
+// Mixed-precision K solve with reliable updates: FP32 CG (matrix, vectors and
+// arithmetic) on the residual equation scaled by 1/||b||; whenever its recursive
+// residual has dropped by `delta` since the last update, the FP32 solution is
+// added to the FP64 one, the true residual b - K x is formed with the FP64
+// operator and replaces the FP32 residual, and CG continues with its search
+// direction (no restart).  Stops on the FP64 true residual.
+static double norm2(fg_system *S, int64_t n, const double *a, hipStream_t st)
+{
+    const double *A[1] = {a};
+    double r = 0;
+    vdots(S, n, 1, A, A, &r, st);
+    return std::sqrt(r);
+}
+
+fg_status cg_reliable(fg_system *S, const double *b, double *x, double tol, int64_t maxit, int check_every,
+                      double delta, int64_t *iters, int64_t *updates, double *relres, hipStream_t st)
+{
+    const int64_t n = 3 * S->Npad;
+    double *r = S->v4;
+    *iters = 0;
+    *updates = 0;
+    vfill(x, 0.0, n, st);
+    const double bn = norm2(S, n, b, st);
+    *relres = bn > 0 ? 1.0 : 0.0;
+    if (!(bn > 0)) return std::isfinite(bn) ? FG_OK : FG_ERR_NAN;
+    if (!S->k32_valid) refresh_k32(S, st);
+    to_f32(n, 1.0 / bn, b, S->fr, st);
+    cg_init(S, FG_K, FG_F32, delta, maxit, st);
+    fg_status e = check_hip("mixed cg init");
+    if (e) return e;
+    for (;;) {
+        fg_status s = cg_loop(S, FG_K, FG_F32, check_every, st);
+        if (s < 0) return s;
+        *iters = S->sc_host->iters;
+        // fold the FP32 correction into x and replace the residual by the FP64 one
+        add_f32(n, bn, S->fx, x, st);
+        hipMemsetAsync(S->fx, 0, n * sizeof(float), st);
+        spmv(S, FG_K, x, S->wq, st);
+        hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, st);
+        vaxpby(n, -1.0, S->wq, 1.0, r, st);
+        ++*updates;
+        const double rel = norm2(S, n, r, st) / bn;
+        *relres = rel;
+        if (!std::isfinite(rel)) {
+            set_error("fg_pcg_solve: NaN in the mixed-precision residual");
+            return FG_ERR_NAN;
+        }
+        if (rel <= tol) return FG_OK;
+        if (s == FG_NOT_CONVERGED || *iters >= maxit) return FG_NOT_CONVERGED;
+        to_f32(n, 1.0 / bn, r, S->fr, st);
+        const double next = std::max(delta * rel, 0.5 * tol);
+        LAUNCH((k_cg_resume<float>), grid_elems(n), WG, st, n, S->dinvK32, S->fr, S->partials, S->npartials);
+        LAUNCH(k_cg_resume_fin, 1, FIN, st, S->partials, S->npartials, grid_elems(n), S->sc, next * next);
+        LAUNCH((k_cg_resume_p<float>), grid_elems(n), WG, st, n, S->dinvK32, S->fr, S->fp, S->sc);
+        e = check_hip("mixed cg resume");
+        if (e) return e;
+    }
 }
 
 }  // namespace fg

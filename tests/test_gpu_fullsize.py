@@ -79,6 +79,22 @@ def test_products_full_size(full):
     assert relerr(host(S.coupling(dev(u), transpose=True)), P.apply_Aup(u)) < 1e-12
 
 
+def test_mixed_precision_solve_full_size(full):
+    """The mixed-precision K solve (FP32 CG with FP64 residual replacement) reaches a
+    1e-8 residual measured with the oracle's FP64 product, close to the FP64 solution."""
+    S, P, O, fg, inst = full["S"], full["P"], full["O"], full["fg"], full["inst"]
+    P.cohesive(full["U"], full["die"])
+    b = np.random.default_rng(9).standard_normal(3 * S.N) * (1 - inst.dir_u)
+    xm, im = S.pcg_solve(fg.FG_K, dev(b), tol=1e-8, precision=fg.FG_MIXED, check_every=64)
+    x64, i64 = S.pcg_solve(fg.FG_K, dev(b), tol=1e-8, check_every=64)
+    xm, x64 = host(xm), host(x64)
+    res = np.linalg.norm(b - P.spmv(O.K_TANGENT, xm)) / np.linalg.norm(b)
+    print(f"[mixed full] iters {im.iters} (fp64 {i64.iters}) replacements {im.cycles} residual {res:.2e} "
+          f"vs fp64 {relerr(xm, x64):.2e}", flush=True)
+    assert im.status == 0 and res <= 1e-8
+    assert relerr(xm, x64) < 1e-6
+
+
 def test_pcg_iterates_full_size(full):
     """50 iterations of the K and A22 PCG from the same right-hand side: the GPU
     iterate (graph-replayed batches, default knobs) equals the oracle's."""

@@ -243,6 +243,18 @@ def test_pcg_mixed_and_f32():
     assert np.linalg.norm(b - P.spmv(O.K_TANGENT, host(x))) <= 1e-8 * np.linalg.norm(b)
     xo, st, it, rr = P.pcg(O.K_TANGENT, b, tol=1e-13)
     print(f"[mixed] cycles {info.cycles} iters {info.iters} err vs fp64 {relerr(host(x), xo):.2e}", flush=True)
+    # reliable updates keep the search direction: no restarts, so the FP32 iteration
+    # count stays within a small factor of the FP64 one
+    x64_, i64_ = S.pcg_solve(fg.FG_K, dev(b), tol=1e-8)
+    assert info.iters <= 1.8 * i64_.iters
+    for k in (3, 30):
+        S.tune("mixed_update", k)
+        xk, ik = S.pcg_solve(fg.FG_K, dev(b), tol=1e-8, precision=fg.FG_MIXED)
+        assert ik.status == 0
+        assert np.linalg.norm(b - P.spmv(O.K_TANGENT, host(xk))) <= 1e-8 * np.linalg.norm(b)
+    S.tune("mixed_update", 10)
+    with pytest.raises(fg.FgError):
+        S.tune("mixed_update", 1)
     # FP32 alone: the recursive residual reaches the tolerance, the true residual stops
     # near kappa * u32 (about 1e4 * 6e-8 here), which is what refinement removes
     x32, info32 = S.pcg_solve(fg.FG_K, dev(b), tol=1e-5, precision=fg.FG_F32)
