@@ -323,6 +323,15 @@ fg_status fg_group_stats(const fg_system *sys, int64_t *iters_h, double *relres_
  *               product (fewer columns: tiles of 8).  1, 2, 4, 8 or 16: one
  *               lane per row with that many columns per pass, the matrix
  *               streamed once per tile.  Results agree to rounding.
+ *   "mr_form":  slot loop of the rhs_tile 0 product.  0: one column-index
+ *               load per slot.  Otherwise the columns of NR/2 slots are
+ *               loaded at once and shared by lane shuffles, and U =
+ *               mr_form & 7 (1, 2 or 4) slots' gathers are issued before any
+ *               is used (default 2); +8: nontemporal matrix value and column loads;
+ *               +16 (U 1 or 2): every lane loads a slot's nine values itself
+ *               instead of receiving them by shuffles.  Valid values: 0, 1, 2,
+ *               4, 9, 10, 12, 17, 18, 25, 26.  Results are identical for
+ *               every value.
  * Returns FG_ERR_ARG for an unknown key or a negative value. */
 fg_status fg_tune(fg_system *sys, const char *key, int64_t value);
 

@@ -6,7 +6,7 @@ agree to rounding; the others give bitwise the same iterates):
 
   single-vector CG (K FP64, K FP32, A22):  halo_cap, spmv_unroll, spmv_nt,
                                            spmv_wpb, vec_grid
-  block CG (many right-hand sides on K):   rhs_tile
+  block CG (many right-hand sides on K):   rhs_tile, mr_form
 
 Each candidate is timed on the system it will run on, a few dozen CG iterations
 long; the search is coordinate descent from the library defaults (every value of
@@ -27,8 +27,8 @@ import time
 from . import fg
 
 SINGLE_KNOBS = ("halo_cap", "spmv_unroll", "spmv_nt", "spmv_wpb", "vec_grid")
-BLOCK_KNOBS = ("rhs_tile",)
-DEFAULTS = {"spmv_unroll": 2, "spmv_nt": 23, "spmv_wpb": 4, "vec_grid": 512, "rhs_tile": 0}
+BLOCK_KNOBS = ("rhs_tile", "mr_form")
+DEFAULTS = {"spmv_unroll": 2, "spmv_nt": 23, "spmv_wpb": 4, "vec_grid": 512, "rhs_tile": 0, "mr_form": 2}
 
 
 def single_candidates(mean_halo: float) -> dict:
@@ -39,7 +39,8 @@ def single_candidates(mean_halo: float) -> dict:
 
 
 def block_candidates(nrhs: int) -> dict:
-    return {"rhs_tile": [0] + [t for t in (1, 2, 4, 8, 16) if t <= nrhs]}
+    forms = [0, 1, 2, 4, 9, 10, 12, 17, 18, 25, 26] if nrhs >= 8 else []
+    return {"rhs_tile": [0] + [t for t in (1, 2, 4, 8, 16) if t <= nrhs], "mr_form": forms}
 
 
 def coordinate_descent(candidates: dict, start: dict, measure, passes: int = 2) -> tuple:
@@ -170,7 +171,7 @@ def tune_block(S, nrhs: int, precision: int = fg.FG_F64, B=None, iters: int = 30
         return _iteration_time(S, lambda: S.pcg_solve(fg.FG_K, B, nrhs=nrhs, tol=1e-300, max_iter=iters,
                                                       check_every=iters, precision=inner), iters)
 
-    cfg, t, log = coordinate_descent(block_candidates(nrhs), {"rhs_tile": DEFAULTS["rhs_tile"]}, measure, 1)
+    cfg, t, log = coordinate_descent(block_candidates(nrhs), {k: DEFAULTS[k] for k in BLOCK_KNOBS}, measure, 1)
     apply(S, cfg)
     rec = {"config": cfg, "us_per_iteration": t, "trials": len(log)}
     if cache is not None:

@@ -1170,6 +1170,16 @@ fg_status fg_tune(fg_system *S, const char *key, int64_t value)
         drop_mr_graphs(S);
         return FG_OK;
     }
+    if (std::strcmp(key, "mr_form") == 0) {
+        const int ok[] = {0, 1, 2, 4, 9, 10, 12, 17, 18, 25, 26};
+        if (std::find(std::begin(ok), std::end(ok), (int)value) == std::end(ok) || value != (int)value) {
+            set_error("fg_tune: mr_form must be 0, 1, 2, 4, 9, 10, 12, 17, 18, 25 or 26");
+            return FG_ERR_ARG;
+        }
+        S->mr_form = (int)value;
+        drop_mr_graphs(S);
+        return FG_OK;
+    }
     set_error(std::string("fg_tune: unknown key ") + key);
     return FG_ERR_ARG;
 }

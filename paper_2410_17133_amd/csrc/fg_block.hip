@@ -229,7 +229,65 @@ __device__ __forceinline__ void mr_rows_slots(int j0, int len, int dj, int64_t r
     }
 }
 
-template <typename T, typename TV, int NR>
+// Slots of one row for the row-group product, a chunk of NR/2 slots at a time:
+// lane c2 of a row group loads the column of slot j0 + c2 once, and the lanes
+// take each slot's column from it by a shuffle, so the x gathers of a chunk
+// wait on one column load instead of one per slot; the loads of U slots are
+// issued before any of them is used.  Every load is unconditional and inside
+// the slice: slot indices are clamped to the wave's longest row (at most the
+// slice width), padding slots of shorter rows hold zero values against the
+// row's own column, and clamped repeats (the chunk's last U-group) are skipped.
+// FORM bits: U in 1..4, 8 = nontemporal value and column loads, 16 = every lane
+// loads the 9 values of a slot itself (no value broadcast).
+template <typename T, typename TV, int NR, int FORM>
+__device__ __forceinline__ void mr_rows_chunked(int len_w, int dj, int gb, int c2, const int32_t *__restrict__ cl,
+                                                const TV *__restrict__ vb, const T *__restrict__ p,
+                                                typename Pair<T>::type (&acc)[3], typename Pair<T>::type (&dp)[3])
+{
+    typedef typename Pair<T>::type T2;
+    constexpr int LPR = NR / 2, NL = (9 + LPR - 1) / LPR, U = FORM & 7;
+    constexpr bool NT = (FORM & 8) != 0, VD = (FORM & 16) != 0;
+    constexpr int NV = VD ? 9 : NL;
+    for (int j0 = 0; j0 < len_w; j0 += LPR) {
+        const int cown = ld_val<NT>(cl + (int64_t)min(j0 + c2, len_w - 1) * SLICE);
+        const int nj = min(LPR, len_w - j0);
+        for (int jj = 0; jj < nj; jj += U) {
+            T mv[U][NV];
+            T2 xv[U][3];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int js = min(jj + u, nj - 1);
+                const int j = j0 + js;
+                const int64_t cj = __shfl(cown, gb + js, 64);
+#pragma unroll
+                for (int w = 0; w < NV; ++w) {
+                    const int e = VD ? w : min(w * LPR + c2, 8);
+                    mv[u][w] = (T)ld_val<NT>(vb + (int64_t)(9 * j + e) * SLICE);
+                }
+                const T2 *xp = (const T2 *)(p + 3 * cj * NR) + c2;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) xv[u][k] = xp[k * LPR];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (jj + u >= nj) break;  // wave-uniform
+                T m[9];
+#pragma unroll
+                for (int e = 0; e < 9; ++e) m[e] = VD ? mv[u][e] : __shfl(mv[u][e / LPR], gb + e % LPR, 64);
+#pragma unroll
+                for (int rr = 0; rr < 3; ++rr)
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) acc[rr] += m[3 * rr + k] * xv[u][k];
+                if (j0 + jj + u == dj)
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) dp[k] = xv[u][k];
+            }
+        }
+    }
+}
+
+// FORM 0: one column load per slot (mr_rows_slots); else mr_rows_chunked.
+template <typename T, typename TV, int NR, int FORM>
 __global__ __launch_bounds__(WG) void k_mr_rows(SpmvArgs a, const uint8_t *__restrict__ rowlen,
                                                 const TV *__restrict__ val, const T *__restrict__ p,
                                                 T *__restrict__ q, double *partials, int64_t stride, int with_dot)
@@ -257,7 +315,11 @@ __global__ __launch_bounds__(WG) void k_mr_rows(SpmvArgs a, const uint8_t *__res
             const int gb = lane - c2;
             int len_w = len;  // the wave's longest row: every lane takes part in the broadcasts
             for (int off = LPR; off < SLICE; off <<= 1) len_w = max(len_w, __shfl_xor(len_w, off, 64));
-            for (int j0 = 0; j0 < len_w; j0 += U) mr_rows_slots<T, TV, NR, U>(j0, len, dj, r, gb, c2, cl, vb, p, acc, dp);
+            if constexpr (FORM == 0) {
+                for (int j0 = 0; j0 < len_w; j0 += U) mr_rows_slots<T, TV, NR, U>(j0, len, dj, r, gb, c2, cl, vb, p, acc, dp);
+            } else {
+                mr_rows_chunked<T, TV, NR, FORM>(__builtin_amdgcn_readfirstlane(len_w), dj, gb, c2, cl, vb, p, acc, dp);
+            }
             T2 *qp = (T2 *)(q + 3 * r * NR) + c2;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
@@ -287,12 +349,16 @@ __global__ __launch_bounds__(FIN) void k_mr_alpha(const double *partials, int nr
                                                   MrScalars *sc)
 {
     const int c = blockIdx.x;
-    if (sc->done[c]) return;
+    if (sc->done[c]) {
+        if (threadIdx.x == 0) sc->upd[c] = 0;
+        return;
+    }
     double tot[1];
     column_sum<1>(partials, nrhs, c, stride, nparts, tot);
     if (threadIdx.x != 0) return;
     const double pq = tot[0];
     sc->pq[c] = pq;
+    sc->upd[c] = 0;
     if (!isfinite(pq)) {
         sc->status[c] = FG_ERR_NAN;
         sc->done[c] = 1;
@@ -301,21 +367,23 @@ __global__ __launch_bounds__(FIN) void k_mr_alpha(const double *partials, int nr
         sc->done[c] = 1;
     } else {
         sc->alpha[c] = sc->rho[c] / pq;
+        sc->upd[c] = 1;
     }
 }
 
+// r -= alpha q and the per-column partials of r.z and r.r (x += alpha p is
+// left to k_mr_pupdate, which reads p anyway).
 template <typename T>
-__global__ __launch_bounds__(WG) void k_mr_update(int64_t n, int nrhs, int lg, const T *__restrict__ dinv, T *__restrict__ x,
-                                                  T *__restrict__ r, const T *__restrict__ p,
-                                                  const T *__restrict__ q, double *partials, int64_t stride,
-                                                  const MrScalars *sc)
+__global__ __launch_bounds__(WG) void k_mr_update(int64_t n, int nrhs, int lg, const T *__restrict__ dinv,
+                                                  T *__restrict__ r, const T *__restrict__ q, double *partials,
+                                                  int64_t stride, const MrScalars *sc)
 {
     const int c = elem_col(nrhs);
     double v[2] = {0, 0};
-    if (!sc->done[c]) {
+    if (sc->upd[c]) {
         const T al = (T)sc->alpha[c];
+#pragma unroll 4
         for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-            x[i] += al * p[i];
             const T ri = r[i] - al * q[i];
             r[i] = ri;
             const T zi = dinv[i >> lg] * ri;
@@ -351,15 +419,23 @@ __global__ __launch_bounds__(FIN) void k_mr_beta(const double *partials, int nrh
     }
 }
 
+// x += alpha p for the columns this iteration advanced, then p = z + beta p for
+// those that go on.
 template <typename T>
 __global__ __launch_bounds__(WG) void k_mr_pupdate(int64_t n, int nrhs, int lg, const T *__restrict__ dinv,
-                                                   const T *__restrict__ r, T *__restrict__ p, const MrScalars *sc)
+                                                   const T *__restrict__ r, T *__restrict__ x, T *__restrict__ p,
+                                                   const MrScalars *sc)
 {
     const int c = elem_col(nrhs);
-    if (sc->done[c]) return;
-    const T be = (T)sc->beta[c];
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = dinv[i >> lg] * r[i] + be * p[i];
+    const bool up = sc->upd[c] != 0, cont = !sc->done[c];
+    if (!up) return;  // a column that goes on was advanced
+    const T al = (T)sc->alpha[c], be = (T)sc->beta[c];
+#pragma unroll 4
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const T pi = p[i];
+        x[i] += al * pi;
+        if (cont) p[i] = dinv[i >> lg] * r[i] + be * pi;
+    }
 }
 
 // caller layout (column c of length 3N at c*3N, caller node order) <-> interleaved internal layout
@@ -440,6 +516,32 @@ inline int log2i(int v)
 
 }  // namespace
 
+// The row-group product in the slot-loop form that fg_tune "mr_form" selects.
+template <typename T, typename TV, int NR>
+static void mr_rows_launch(int form, int64_t gr, hipStream_t st, const SpmvArgs &a, fg_system *S, const TV *val,
+                           const T *p, T *q, int with_dot)
+{
+#define MR_FORM(F)                                                                                                  \
+    case F:                                                                                                         \
+        LAUNCH((k_mr_rows<T, TV, NR, F>), gr, WG, st, a, S->rowlen, val, p, q, S->mpart, S->mpart_stride, with_dot); \
+        break;
+    switch (form) {
+        MR_FORM(1)
+        MR_FORM(2)
+        MR_FORM(4)
+        MR_FORM(9)
+        MR_FORM(10)
+        MR_FORM(12)
+        MR_FORM(17)
+        MR_FORM(18)
+        MR_FORM(25)
+        MR_FORM(26)
+    default:
+        MR_FORM(0)
+    }
+#undef MR_FORM
+}
+
 // Q = K P for all columns; returns the number of per-column partials written.
 // rhs_tile 0 (default): the row-group kernel for nrhs >= 8; otherwise the
 // column-tile kernel with rhs_tile columns per pass.
@@ -451,16 +553,16 @@ static int64_t mr_launch_spmm(fg_system *S, int nrhs, const TV *val, const T *p,
         const int64_t gr = grid_xcd(S->nslices);
         switch (nrhs) {
         case 8:
-            LAUNCH((k_mr_rows<T, TV, 8>), gr, WG, st, a, S->rowlen, val, p, q, S->mpart, S->mpart_stride, with_dot);
+            mr_rows_launch<T, TV, 8>(S->mr_form, gr, st, a, S, val, p, q, with_dot);
             break;
         case 16:
-            LAUNCH((k_mr_rows<T, TV, 16>), gr, WG, st, a, S->rowlen, val, p, q, S->mpart, S->mpart_stride, with_dot);
+            mr_rows_launch<T, TV, 16>(S->mr_form, gr, st, a, S, val, p, q, with_dot);
             break;
         case 32:
-            LAUNCH((k_mr_rows<T, TV, 32>), gr, WG, st, a, S->rowlen, val, p, q, S->mpart, S->mpart_stride, with_dot);
+            mr_rows_launch<T, TV, 32>(S->mr_form, gr, st, a, S, val, p, q, with_dot);
             break;
         default:
-            LAUNCH((k_mr_rows<T, TV, 64>), gr, WG, st, a, S->rowlen, val, p, q, S->mpart, S->mpart_stride, with_dot);
+            mr_rows_launch<T, TV, 64>(S->mr_form, gr, st, a, S, val, p, q, with_dot);
             break;
         }
         return gr;
@@ -501,10 +603,10 @@ static void mr_launch_batch(fg_system *S, int nrhs, const TV *val, const T *dinv
     for (int it = 0; it < iters; ++it) {
         const int64_t gx = mr_launch_spmm<T, TV>(S, nrhs, val, p, q, 1, st);
         hipLaunchKernelGGL(k_mr_alpha, dim3(nrhs), dim3(FIN), 0, st, S->mpart, nrhs, S->mpart_stride, gx, S->msc);
-        hipLaunchKernelGGL((k_mr_update<T>), dim3(ge), dim3(WG), 0, st, n, nrhs, log2i(nrhs), dinv, x, r, p, q, S->mpart,
+        hipLaunchKernelGGL((k_mr_update<T>), dim3(ge), dim3(WG), 0, st, n, nrhs, log2i(nrhs), dinv, r, q, S->mpart,
                            S->mpart_stride, S->msc);
         hipLaunchKernelGGL(k_mr_beta, dim3(nrhs), dim3(FIN), 0, st, S->mpart, nrhs, S->mpart_stride, ge, S->msc);
-        hipLaunchKernelGGL((k_mr_pupdate<T>), dim3(ge), dim3(WG), 0, st, n, nrhs, log2i(nrhs), dinv, r, p, S->msc);
+        hipLaunchKernelGGL((k_mr_pupdate<T>), dim3(ge), dim3(WG), 0, st, n, nrhs, log2i(nrhs), dinv, r, x, p, S->msc);
     }
 }
 
@@ -586,7 +688,7 @@ static fg_status mr_cg(fg_system *S, int nrhs, bool f32, double tol, int64_t max
             else
                 mr_launch_batch<double, double>(S, nrhs, S->K, S->dinvK, S->mx, S->mr, S->mp, S->mq, batch, st);
         } else {
-            if (!g.exec || g.iters != batch || g.nrhs != nrhs || g.tile != S->mr_tile) {
+            if (!g.exec || g.iters != batch || g.nrhs != nrhs || g.tile != S->mr_tile + 256 * S->mr_form) {
                 if (g.exec) hipGraphExecDestroy(g.exec);
                 g.exec = nullptr;
                 hipGraph_t graph = nullptr;
@@ -607,7 +709,7 @@ static fg_status mr_cg(fg_system *S, int nrhs, bool f32, double tol, int64_t max
                 }
                 g.iters = batch;
                 g.nrhs = nrhs;
-                g.tile = S->mr_tile;
+                g.tile = S->mr_tile + 256 * S->mr_form;
             }
             hipGraphLaunch(g.exec, st);
         }

@@ -80,6 +80,7 @@ struct MrScalars {
     double rho[MR_MAX], pq[MR_MAX], rr[MR_MAX], bb[MR_MAX], alpha[MR_MAX], beta[MR_MAX], tol2[MR_MAX];
     int64_t iter[MR_MAX];
     int32_t done[MR_MAX], status[MR_MAX];
+    int32_t upd[MR_MAX];  // column advanced by this iteration's alpha (x += alpha p is still due)
     int64_t maxit;
     int32_t nrhs, pad;
 };
@@ -176,6 +177,7 @@ struct fg_system {
     int spmv_nt = 23;     // fg_tune "spmv_nt": access mask of the CG product (nontemporal values 1, indices 2,
                           // halo lists 4, product stores 8; 16 software-pipelined staged rows)
     int mr_tile = 0;  // fg_tune "rhs_tile": 0 = row-group product, else columns per column-tile pass
+    int mr_form = 2;  // fg_tune "mr_form": slot-loop form of the row-group product
     double *mx = nullptr, *mr = nullptr, *mp = nullptr, *mq = nullptr, *mb = nullptr, *mx64 = nullptr, *mr64 = nullptr;
     float *mfx = nullptr, *mfr = nullptr, *mfp = nullptr, *mfq = nullptr;
     fg::MrScalars *msc = nullptr, *msc_host = nullptr;

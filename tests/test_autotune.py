@@ -26,6 +26,8 @@ def test_candidates():
     assert c["halo_cap"][0] == 0 and 682 in c["halo_cap"] and c["halo_cap"] == sorted(c["halo_cap"])
     assert all(v % 32 == 0 for v in c["halo_cap"] if v not in (0, 682))
     assert AT.block_candidates(4)["rhs_tile"] == [0, 1, 2, 4]
+    assert AT.block_candidates(4)["mr_form"] == []            # the row-group product needs 8 columns
+    assert AT.DEFAULTS["mr_form"] in AT.block_candidates(32)["mr_form"]
 
 
 def test_cache_round_trip(tmp_path):
@@ -63,6 +65,7 @@ def test_tuning_a_system_keeps_its_results(tmp_path):
     X0, _ = S.pcg_solve(fg.FG_K, B.reshape(-1), nrhs=8, tol=1e-10)
     rb = AT.tune_block(S, 8, fg.FG_F64, iters=10, cache=cache)
     assert rb["config"]["rhs_tile"] in AT.block_candidates(8)["rhs_tile"]
+    assert rb["config"]["mr_form"] in AT.block_candidates(8)["mr_form"]
     X1, _ = S.pcg_solve(fg.FG_K, B.reshape(-1), nrhs=8, tol=1e-10)
     X0, X1 = X0.cpu().numpy().reshape(8, -1), X1.cpu().numpy().reshape(8, -1)
     for c in range(8):

@@ -521,6 +521,32 @@ def test_block_solve_matches_single_column_solves():
     assert np.all(X0[5] == 0)
 
 
+@pytest.mark.parametrize("nrhs", [8, 32])
+def test_block_product_forms_identical(nrhs):
+    """Every slot-loop form of the row-group product (column loads shared by
+    shuffles, U-slot gathers, nontemporal streams, direct value loads) performs
+    the same operations in the same order as the default: the block iterates are
+    bitwise equal, in FP64 and in the FP32 inner solver of the mixed mode."""
+    fg = _fg()
+    inst, ctx, S, P = setup("cube12_dip60_hetero")
+    S.cohesive_update(dev(np.zeros(3 * S.N)), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)))
+    B = np.random.default_rng(31).standard_normal((nrhs, 3 * S.N)) * (1 - inst.dir_u)
+    for prec in (fg.FG_F64, fg.FG_MIXED):
+        ref = None
+        for form in (0, 1, 2, 4, 9, 10, 12, 17, 18, 25, 26):
+            S.tune("mr_form", form)
+            X, info = S.pcg_solve(fg.FG_K, dev(B.reshape(-1)), nrhs=nrhs, tol=1e-300, max_iter=40,
+                                  precision=prec, check_every=40)
+            X = host(X)
+            if ref is None:
+                ref = X
+            print(f"[mr_form] nrhs {nrhs} precision {prec} form {form}", flush=True)
+            np.testing.assert_array_equal(X, ref)
+    S.tune("mr_form", 2)  # the library default
+    with pytest.raises(fg.FgError):
+        S.tune("mr_form", 3)
+
+
 def test_block_solve_mixed_precision_and_errors():
     fg, O = _fg(), _oracle()
     inst, ctx, S, P = setup("cube12_dip60_hetero")
