@@ -67,8 +67,9 @@ typedef int fg_status;
 #define FG_F32 1    /* FP32 matrix and vectors throughout (no refinement) */
 #define FG_MIXED 2  /* FP32 PCG with FP64 residual replacement: whenever the FP32 residual has dropped
                       tenfold, the FP32 solution is added to the FP64 one, b - K x is formed in FP64
-                      and replaces the FP32 residual, and CG continues (reliable updates); batched
-                      systems and the block solve refine with restarts of each inner solve */
+                      and replaces the FP32 residual, and CG continues (reliable updates; in the
+                      block solve per column); batched systems refine with restarts of each
+                      inner solve */
 #define FG_MIXED_F32VAL 3  /* inner PCG on the FP32 matrix values with FP64 vectors and arithmetic,
                               FP64 residual and refinement (single right-hand side, unbatched) */
 
@@ -104,8 +105,8 @@ typedef struct {
     int64_t max_iter;    /* CG iterations (inner iterations in total for FG_MIXED) */
     int precision;       /* FG_F64 / FG_F32 / FG_MIXED / FG_MIXED_F32VAL (K only; A22 solves are FP64) */
     int check_every;     /* iterations between convergence polls by the host (0 = default 32) */
-    double inner_tol;    /* FG_MIXED / FG_MIXED_F32VAL: relative tolerance of each inner solve
-                            (0 = default 1e-4) */
+    double inner_tol;    /* restarted refinement (FG_MIXED on batched systems, FG_MIXED_F32VAL):
+                            relative tolerance of each inner solve (0 = default 1e-4) */
 } fg_pcg_opts;
 
 typedef struct {
@@ -191,8 +192,9 @@ fg_status fg_cohesive_update(fg_ctx *ctx, fg_system *sys, const double *U, const
  * With FG_K and nrhs > 1 (a power of two up to 64) the columns are solved
  * together: independent CG recurrences (own alpha, beta, stop test) advanced in
  * lockstep so that each iteration streams the matrix once per tile of columns
- * (block product); converged columns are masked out.  FG_MIXED refines every
- * column in FP64 around FP32 block iterations.
+ * (block product); converged columns are masked out.  FG_MIXED replaces each
+ * column's FP32 residual by its FP64 one whenever it has dropped by the
+ * mixed_update factor (reliable updates, all columns at the same points).
  * Returns FG_OK, FG_NOT_CONVERGED (x holds the last iterate),
  * FG_ERR_BREAKDOWN, FG_ERR_NAN.  info (host) receives the worst column. */
 fg_status fg_pcg_solve(fg_ctx *ctx, fg_system *sys, int which, int nrhs, const double *b, double *x,
@@ -305,8 +307,9 @@ fg_status fg_group_stats(const fg_system *sys, int64_t *iters_h, double *relres_
  *               0 full steps.
  *   "spmv_unroll": slots per unrolled step of the CG product: 1, 2 (default),
  *               3, 4 or 6.
- *   "mixed_update": FG_MIXED (unbatched): factor by which the FP32 residual
- *               must drop before the FP64 residual replaces it (default 10).
+ *   "mixed_update": FG_MIXED (unbatched, one or many right-hand sides):
+ *               factor by which the FP32 residual must drop before the FP64
+ *               residual replaces it (default 10).
  *   "vec_grid": workgroups of the CG vector kernels: 512 (default), 1024 or
  *               2048 (each adds the previous kernel's partial sums itself).
  *   "spmv_wpb": slices (one wavefront each) per workgroup of the CG

@@ -561,7 +561,7 @@ fg_status fg_system_create(fg_ctx *ctx, const fg_mesh *mesh, fg_system **out)
         return FG_ERR_OOM;
     }
     S->mpart_stride = std::max<int64_t>((S->nslices + 7) / 8 * 8, 2048) + 8;  // one partial per slice at most
-    if (dalloc(&S->mpart, 2 * (int64_t)MR_MAX * S->mpart_stride) || dalloc(&S->msc, 1) || dalloc(&S->mred, MR_MAX) ||
+    if (dalloc(&S->mpart, 2 * (int64_t)MR_MAX * S->mpart_stride) || dalloc(&S->msc, 1) || dalloc(&S->mred, 2 * MR_MAX) ||
         hipHostMalloc((void **)&S->msc_host, sizeof(MrScalars)) != hipSuccess ||
         hipHostMalloc((void **)&S->mred_host, MR_MAX * sizeof(double)) != hipSuccess) {
         set_error("allocation of the block-solve scalars failed");

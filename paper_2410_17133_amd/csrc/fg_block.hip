@@ -503,6 +503,61 @@ __global__ void k_mr_resid(int64_t n, const double *__restrict__ b, const double
         r[i] = b[i] - q[i];
 }
 
+// Residual replacement of the FP32 block CG (reliable updates): per-column
+// partials of r.z and r.r of the new (FP64-derived) residual ...
+template <typename T>
+__global__ __launch_bounds__(WG) void k_mr_resume(int64_t n, int nrhs, int lg, const T *__restrict__ dinv,
+                                                  const T *__restrict__ r, double *partials, int64_t stride)
+{
+    double v[2] = {0, 0};
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const T ri = r[i], zi = dinv[i >> lg] * ri;
+        v[0] += (double)ri * (double)zi;
+        v[1] += (double)ri * (double)ri;
+    }
+    block_partials_cols<2>(v, nrhs, partials, stride);
+}
+
+// ... then, per column, beta against the rho the column stopped with (its last
+// direction p is kept), the new rho and stop threshold next2[c] (squared; a
+// column with next2[c] <= 0 is finished and stays done) ...
+__global__ __launch_bounds__(FIN) void k_mr_resume_fin(const double *partials, int nrhs, int64_t stride, int64_t nparts,
+                                                       MrScalars *sc, const double *next2)
+{
+    const int c = blockIdx.x;
+    double tot[2];
+    column_sum<2>(partials, nrhs, c, stride, nparts, tot);
+    if (threadIdx.x != 0) return;
+    sc->upd[c] = 0;
+    sc->status[c] = FG_OK;
+    sc->done[c] = 1;
+    if (!(next2[c] > 0.0)) return;
+    const double beta = tot[0] / sc->rho[c];
+    sc->rr[c] = tot[1];
+    if (!isfinite(tot[0]) || !isfinite(tot[1]) || !isfinite(beta)) {
+        sc->status[c] = FG_ERR_NAN;
+    } else if (sc->iter[c] >= sc->maxit) {
+        sc->status[c] = FG_NOT_CONVERGED;
+    } else {
+        sc->beta[c] = beta;
+        sc->rho[c] = tot[0];
+        sc->tol2[c] = next2[c];
+        sc->done[c] = 0;
+    }
+}
+
+// ... and p = z + beta p for the columns that go on.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_mr_resume_p(int64_t n, int nrhs, int lg, const T *__restrict__ dinv,
+                                                    const T *__restrict__ r, T *__restrict__ p, const MrScalars *sc)
+{
+    const int c = elem_col(nrhs);
+    if (sc->done[c]) return;
+    const T be = (T)sc->beta[c];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = dinv[i >> lg] * r[i] + be * p[i];
+}
+
 // element-wise grid for column-interleaved vectors; blocks of WG threads make the
 // grid a multiple of nrhs, so each thread keeps one column
 inline int64_t grid_cols(int64_t n) { return grid_elems(n); }
@@ -651,9 +706,9 @@ void drop_mr_graphs(fg_system *S)
     }
 }
 
-// Block CG on the interleaved right-hand sides already in S->mr (FP64) or S->mfr
-// (FP32); solutions left in S->mx / S->mfx.  Per-column results in S->msc_host.
-static fg_status mr_cg(fg_system *S, int nrhs, bool f32, double tol, int64_t maxit, int check_every, hipStream_t st)
+// Start of a block CG on the interleaved right-hand sides already in S->mr (FP64)
+// or S->mfr (FP32): x = 0, p = z, per-column rho, thresholds and flags.
+static fg_status mr_cg_init(fg_system *S, int nrhs, bool f32, double tol, int64_t maxit, hipStream_t st)
 {
     const int64_t n = 3 * S->Npad * nrhs;
     MrScalars init{};
@@ -670,8 +725,14 @@ static fg_status mr_cg(fg_system *S, int nrhs, bool f32, double tol, int64_t max
                            S->mpart, S->mpart_stride);
     }
     hipLaunchKernelGGL(k_mr_init_fin, dim3(nrhs), dim3(FIN), 0, st, S->mpart, nrhs, S->mpart_stride, ge, S->msc, tol);
-    fg_status e = check_hip("block cg init");
-    if (e) return e;
+    return check_hip("block cg init");
+}
+
+// Iterations until every column is done (batches of check_every, replayed as
+// HIP graphs); solutions in S->mx / S->mfx, per-column results in S->msc_host.
+static fg_status mr_cg_loop(fg_system *S, int nrhs, bool f32, int check_every, hipStream_t st)
+{
+    fg_status e = FG_OK;
     const int batch = check_every > 0 ? check_every : 32;
     GraphCache &g = S->mr_graph[f32 ? 1 : 0];
     for (;;) {
@@ -719,6 +780,12 @@ static fg_status mr_cg(fg_system *S, int nrhs, bool f32, double tol, int64_t max
     return FG_OK;
 }
 
+static fg_status mr_cg(fg_system *S, int nrhs, bool f32, double tol, int64_t maxit, int check_every, hipStream_t st)
+{
+    fg_status e = mr_cg_init(S, nrhs, f32, tol, maxit, st);
+    return e ? e : mr_cg_loop(S, nrhs, f32, check_every, st);
+}
+
 static void mr_colnorms(fg_system *S, int nrhs, const double *a, double *host, hipStream_t st)
 {
     const int64_t n = 3 * S->Npad * nrhs, ge = grid_cols(n);
@@ -727,6 +794,91 @@ static void mr_colnorms(fg_system *S, int nrhs, const double *a, double *host, h
     hipMemcpyAsync(S->mred_host, S->mred, nrhs * sizeof(double), hipMemcpyDeviceToHost, st);
     hipStreamSynchronize(st);
     for (int c = 0; c < nrhs; ++c) host[c] = std::sqrt(S->mred_host[c]);
+}
+
+// FG_MIXED block solve by reliable updates: one FP32 block CG on K32, each column
+// scaled by 1/||b_c||, runs until every column has cut its residual by `delta`
+// (or reached 0.5 tol); then every column's FP32 correction is added to the FP64
+// x, the FP64 residual b - K x replaces the FP32 one, and the columns above tol
+// go on from their last direction with the next threshold max(delta rel, 0.5 tol).
+static fg_status mr_reliable(fg_system *S, int nrhs, double tol, int64_t maxit, int check_every, double delta,
+                             int64_t *iters, int64_t *updates, double *worst_rel, fg_status *worst, hipStream_t st)
+{
+    const int64_t n = 3 * S->Npad * nrhs, ge = grid_cols(n);
+    const int lg = log2i(nrhs);
+    if (!S->k32_valid) refresh_k32(S, st);
+    std::vector<double> bn(nrhs), rn(nrhs), scale(nrhs), fold(nrhs), next2(nrhs);
+    mr_colnorms(S, nrhs, S->mb, bn.data(), st);
+    for (int c = 0; c < nrhs; ++c) {
+        if (!std::isfinite(bn[c])) {
+            set_error("fg_pcg_solve: NaN or Inf in a right-hand side");
+            return FG_ERR_NAN;
+        }
+        scale[c] = bn[c] > 0 ? 1.0 / bn[c] : 0.0;
+        fold[c] = bn[c];
+    }
+    double *next2_d = S->mred + MR_MAX;
+    hipMemcpyAsync(S->mred, scale.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st);
+    hipLaunchKernelGGL(k_mr_scale_to_f32, dim3(ge), dim3(WG), 0, st, n, nrhs, S->mred, S->mb, S->mfr);
+    hipMemsetAsync(S->mx64, 0, n * sizeof(double), st);
+    fg_status e = mr_cg_init(S, nrhs, true, delta, maxit, st);
+    if (e) return e;
+    *iters = 0;
+    *updates = 0;
+    *worst = FG_OK;
+    for (;;) {
+        e = mr_cg_loop(S, nrhs, true, check_every, st);
+        if (e) return e;
+        const MrScalars &h = *S->msc_host;
+        for (int c = 0; c < nrhs; ++c) {
+            *iters = std::max<int64_t>(*iters, h.iter[c]);
+            if (h.status[c] < 0) {
+                set_error(h.status[c] == FG_ERR_NAN ? "fg_pcg_solve: NaN or Inf in a column"
+                                                    : "fg_pcg_solve: CG breakdown in a column (p.Ap <= 0)");
+                return h.status[c];
+            }
+        }
+        std::vector<int64_t> it(h.iter, h.iter + nrhs);
+        // fold the FP32 corrections into x and replace the residuals by FP64 ones
+        hipMemcpyAsync(S->mred, fold.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st);
+        hipLaunchKernelGGL(k_mr_add_f32, dim3(ge), dim3(WG), 0, st, n, nrhs, S->mred, S->mfx, S->mx64);
+        hipMemsetAsync(S->mfx, 0, n * sizeof(float), st);
+        mr_launch_spmm<double, double>(S, nrhs, S->K, S->mx64, S->mq, 0, st);
+        hipLaunchKernelGGL(k_mr_resid, dim3(ge), dim3(WG), 0, st, n, S->mb, S->mq, S->mr64);
+        mr_colnorms(S, nrhs, S->mr64, rn.data(), st);
+        ++*updates;
+        bool any = false;
+        *worst_rel = 0;
+        for (int c = 0; c < nrhs; ++c) {
+            const double rel = bn[c] > 0 ? rn[c] / bn[c] : 0.0;
+            if (!std::isfinite(rel)) {
+                set_error("fg_pcg_solve: NaN in a block residual replacement");
+                return FG_ERR_NAN;
+            }
+            *worst_rel = std::max(*worst_rel, rel);
+            next2[c] = -1.0;
+            if (rel <= tol) continue;
+            if (it[c] >= maxit) {
+                *worst = FG_NOT_CONVERGED;
+                continue;
+            }
+            const double nx = std::max(delta * rel, 0.5 * tol);
+            next2[c] = nx * nx;
+            any = true;
+        }
+        if (!any) return FG_OK;
+        hipMemcpyAsync(S->mred, scale.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st);
+        hipLaunchKernelGGL(k_mr_scale_to_f32, dim3(ge), dim3(WG), 0, st, n, nrhs, S->mred, S->mr64, S->mfr);
+        hipMemcpyAsync(next2_d, next2.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st);
+        hipLaunchKernelGGL((k_mr_resume<float>), dim3(ge), dim3(WG), 0, st, n, nrhs, lg, S->dinvK32, S->mfr, S->mpart,
+                           S->mpart_stride);
+        hipLaunchKernelGGL(k_mr_resume_fin, dim3(nrhs), dim3(FIN), 0, st, S->mpart, nrhs, S->mpart_stride, ge, S->msc,
+                           next2_d);
+        hipLaunchKernelGGL((k_mr_resume_p<float>), dim3(ge), dim3(WG), 0, st, n, nrhs, lg, S->dinvK32, S->mfr, S->mfp,
+                           S->msc);
+        e = check_hip("block cg resume");
+        if (e) return e;
+    }
 }
 
 // Multi-right-hand-side K solve: b, x in the caller layout (column c at c*3N).
@@ -773,60 +925,10 @@ fg_status block_solve(fg_system *S, int nrhs, const double *b, double *x, int pr
         }
         cycles = 1;
     } else {
-        // FP32 inner block CG, FP64 residual and refinement per column
-        if (!S->k32_valid) refresh_k32(S, st);
-        std::vector<double> bn(nrhs), rn(nrhs), scale(nrhs);
-        mr_colnorms(S, nrhs, S->mb, bn.data(), st);
-        hipMemsetAsync(S->mx64, 0, n * sizeof(double), st);
-        hipMemcpyAsync(S->mr64, S->mb, n * sizeof(double), hipMemcpyDeviceToDevice, st);
-        int64_t total = 0;
-        for (;;) {
-            mr_colnorms(S, nrhs, S->mr64, rn.data(), st);
-            bool active = false;
-            worst_rel = 0;
-            for (int c = 0; c < nrhs; ++c) {
-                const double rel = bn[c] > 0 ? rn[c] / bn[c] : 0.0;
-                if (!std::isfinite(rel)) {
-                    set_error("fg_pcg_solve: NaN in a block refinement residual");
-                    return FG_ERR_NAN;
-                }
-                worst_rel = std::max(worst_rel, rel);
-                const bool act = rel > tol;
-                active = active || act;
-                scale[c] = act ? 1.0 / rn[c] : 0.0;  // a converged column gets a zero right-hand side
-            }
-            if (!active) {
-                worst = FG_OK;
-                break;
-            }
-            if (total >= maxit || cycles >= 200) {
-                worst = FG_NOT_CONVERGED;
-                break;
-            }
-            hipMemcpyAsync(S->mred, scale.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st);
-            hipLaunchKernelGGL(k_mr_scale_to_f32, dim3(ge), dim3(WG), 0, st, n, nrhs, S->mred, S->mr64, S->mfr);
-            double itol = inner_tol;
-            for (int c = 0; c < nrhs; ++c)
-                if (scale[c] > 0) itol = std::max(itol, std::min(inner_tol, tol * bn[c] / rn[c]));
-            e = mr_cg(S, nrhs, true, std::max(itol, inner_tol), maxit - total, check_every, st);
-            if (e) return e;
-            int64_t it_max = 0;
-            for (int c = 0; c < nrhs; ++c) {
-                it_max = std::max<int64_t>(it_max, S->msc_host->iter[c]);
-                if (S->msc_host->status[c] < 0) {
-                    set_error("fg_pcg_solve: breakdown or NaN in a block inner solve");
-                    return S->msc_host->status[c];
-                }
-            }
-            total += it_max;
-            cycles++;
-            for (int c = 0; c < nrhs; ++c) scale[c] = scale[c] > 0 ? rn[c] : 0.0;
-            hipMemcpyAsync(S->mred, scale.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st);
-            hipLaunchKernelGGL(k_mr_add_f32, dim3(ge), dim3(WG), 0, st, n, nrhs, S->mred, S->mfx, S->mx64);
-            mr_launch_spmm<double, double>(S, nrhs, S->K, S->mx64, S->mq, 0, st);
-            hipLaunchKernelGGL(k_mr_resid, dim3(ge), dim3(WG), 0, st, n, S->mb, S->mq, S->mr64);
-        }
-        max_iters = total;
+        // FP32 block CG with FP64 residual replacement per column
+        e = mr_reliable(S, nrhs, tol, maxit, check_every, 1.0 / S->mixed_update, &max_iters, &cycles, &worst_rel, &worst,
+                        st);
+        if (e) return e;
         hipLaunchKernelGGL(k_mr_out, dim3(ge), dim3(WG), 0, st, S->N, S->Npad, nrhs, S->perm, S->mx64, x);
     }
     hipStreamSynchronize(st);

@@ -559,6 +559,28 @@ def test_block_solve_mixed_precision_and_errors():
     X = host(X).reshape(nrhs, -1)
     for c in range(nrhs):
         assert np.linalg.norm(B[c] - P.spmv(O.K_TANGENT, X[c])) <= 1e-8 * np.linalg.norm(B[c])
+    # reliable updates keep the Krylov space: FP32 iterations close to the FP64 count
+    X64, i64 = S.pcg_solve(fg.FG_K, dev(B.reshape(-1)), nrhs=nrhs, tol=1e-8)
+    print(f"[block mixed] iters {info.iters} (fp64 {i64.iters}) replacements {info.cycles}", flush=True)
+    assert info.iters <= 1.8 * i64.iters
+    X64 = host(X64).reshape(nrhs, -1)
+    for c in range(nrhs):
+        assert relerr(X[c], X64[c]) < 1e-6
+    # columns eight orders of magnitude apart, a zero column, another replacement factor
+    Bs = B * np.logspace(-4, 4, nrhs)[:, None]
+    Bs[3] = 0.0
+    S.tune("mixed_update", 1000)
+    Xs, iS = S.pcg_solve(fg.FG_K, dev(Bs.reshape(-1)), nrhs=nrhs, tol=1e-9, precision=fg.FG_MIXED)
+    S.tune("mixed_update", 10)
+    assert iS.status == 0 and iS.relres <= 1e-9
+    Xs = host(Xs).reshape(nrhs, -1)
+    assert np.all(Xs[3] == 0)
+    for c in range(nrhs):
+        if c != 3:
+            assert np.linalg.norm(Bs[c] - P.spmv(O.K_TANGENT, Xs[c])) <= 1e-9 * np.linalg.norm(Bs[c])
+    # an iteration cap ends the solve with FG_NOT_CONVERGED and the iterate so far
+    Xc, ic = S.pcg_solve(fg.FG_K, dev(B.reshape(-1)), nrhs=nrhs, tol=1e-12, max_iter=30, precision=fg.FG_MIXED)
+    assert ic.status == fg.FG_NOT_CONVERGED and ic.iters == 30 and 0 < ic.relres < 1
     X32, i32 = S.pcg_solve(fg.FG_K, dev(B.reshape(-1)), nrhs=nrhs, tol=1e-5, precision=fg.FG_F32)
     assert i32.status == 0
     with pytest.raises(fg.FgError) as e:
