@@ -67,9 +67,8 @@ typedef int fg_status;
 #define FG_F32 1    /* FP32 matrix and vectors throughout (no refinement) */
 #define FG_MIXED 2  /* FP32 PCG with FP64 residual replacement: whenever the FP32 residual has dropped
                       tenfold, the FP32 solution is added to the FP64 one, b - K x is formed in FP64
-                      and replaces the FP32 residual, and CG continues (reliable updates; in the
-                      block solve per column); batched systems refine with restarts of each
-                      inner solve */
+                      and replaces the FP32 residual, and CG continues (reliable updates; per
+                      column in the block solve, per group on batched systems) */
 #define FG_MIXED_F32VAL 3  /* inner PCG on the FP32 matrix values with FP64 vectors and arithmetic,
                               FP64 residual and refinement (single right-hand side, unbatched) */
 
@@ -105,8 +104,8 @@ typedef struct {
     int64_t max_iter;    /* CG iterations (inner iterations in total for FG_MIXED) */
     int precision;       /* FG_F64 / FG_F32 / FG_MIXED / FG_MIXED_F32VAL (K only; A22 solves are FP64) */
     int check_every;     /* iterations between convergence polls by the host (0 = default 32) */
-    double inner_tol;    /* restarted refinement (FG_MIXED on batched systems, FG_MIXED_F32VAL):
-                            relative tolerance of each inner solve (0 = default 1e-4) */
+    double inner_tol;    /* FG_MIXED_F32VAL (restarted refinement): relative tolerance of each
+                            inner solve (0 = default 1e-4) */
 } fg_pcg_opts;
 
 typedef struct {
@@ -307,8 +306,8 @@ fg_status fg_group_stats(const fg_system *sys, int64_t *iters_h, double *relres_
  *               0 full steps.
  *   "spmv_unroll": slots per unrolled step of the CG product: 1, 2 (default),
  *               3, 4 or 6.
- *   "mixed_update": FG_MIXED (unbatched, one or many right-hand sides):
- *               factor by which the FP32 residual must drop before the FP64
+ *   "mixed_update": FG_MIXED: factor by which the FP32 residual (of the
+ *               solve, a column or a group) must drop before the FP64
  *               residual replaces it (default 10).
  *   "vec_grid": workgroups of the CG vector kernels: 512 (default), 1024 or
  *               2048 (each adds the previous kernel's partial sums itself).

@@ -108,66 +108,6 @@ fg_pcg_opts defaults(const fg_pcg_opts *o, double tol)
     return d;
 }
 
-// Mixed-precision K solve of a batched system: every group refines against its
-// own residual norm; groups that meet the tolerance get a zero inner right-hand side.
-fg_status k_solve_mixed_grouped(fg_system *S, const double *rhs, double *out, const fg_pcg_opts &o, fg_pcg_info *info,
-                                hipStream_t st)
-{
-    const int G = S->ngroups;
-    const int64_t n = 3 * S->Npad;
-    double *x = S->v3, *r = S->v4;
-    std::vector<double> bn(G), rn(G), scale(G);
-    group_norms(S, 3, rhs, bn.data(), st);
-    vfill(x, 0.0, n, st);
-    hipMemcpyAsync(r, rhs, n * sizeof(double), hipMemcpyDeviceToDevice, st);
-    int64_t total = 0, cycles = 0;
-    double worst_rel = 0;
-    fg_status s = FG_OK;
-    for (;;) {
-        group_norms(S, 3, r, rn.data(), st);
-        bool active = false;
-        worst_rel = 0;
-        double itol = o.inner_tol;
-        for (int g = 0; g < G; ++g) {
-            const double rel = bn[g] > 0 ? rn[g] / bn[g] : 0.0;
-            if (!std::isfinite(rel)) {
-                set_error("fg_pcg_solve: NaN in a group's refinement residual");
-                return FG_ERR_NAN;
-            }
-            worst_rel = std::max(worst_rel, rel);
-            const bool act = rel > o.tol;
-            active = active || act;
-            scale[g] = act ? 1.0 / rn[g] : 0.0;
-        }
-        if (!active) break;
-        if (total >= o.max_iter || cycles >= 200) {
-            s = FG_NOT_CONVERGED;
-            break;
-        }
-        group_to_f32(S, scale.data(), r, S->fr, st);
-        int64_t it = 0;
-        double rr = 0;
-        fg_status si = cg_run_grouped(S, FG_K, FG_F32, itol, o.max_iter - total, o.check_every, &it, &rr, st);
-        total += it;
-        cycles++;
-        if (si < 0) return si;
-        for (int g = 0; g < G; ++g) scale[g] = scale[g] > 0 ? rn[g] : 0.0;
-        group_add_f32(S, scale.data(), S->fx, x, st);
-        spmv(S, FG_K, x, S->wq, st);
-        hipMemcpyAsync(r, rhs, n * sizeof(double), hipMemcpyDeviceToDevice, st);
-        vaxpby(n, -1.0, S->wq, 1.0, r, st);
-    }
-    for (int g = 0; g < G; ++g) S->grp_relres[g] = bn[g] > 0 ? rn[g] / bn[g] : 0.0;
-    hipMemcpyAsync(out, x, n * sizeof(double), hipMemcpyDeviceToDevice, st);
-    if (info) {
-        info->iters = total;
-        info->cycles = cycles;
-        info->relres = worst_rel;
-        info->status = s;
-    }
-    return s;
-}
-
 // K solve on internal vectors: rhs (3 Npad) -> out (3 Npad).
 fg_status k_solve(fg_system *S, const double *rhs, double *out, const fg_pcg_opts &o, fg_pcg_info *info, hipStream_t st)
 {
@@ -198,7 +138,20 @@ fg_status k_solve(fg_system *S, const double *rhs, double *out, const fg_pcg_opt
     // FP64 vectors, FP64 true residual and accumulation (iterative refinement with
     // restarts).
     if (!S->k32_valid) refresh_k32(S, st);
-    if (S->ngroups > 1) return k_solve_mixed_grouped(S, rhs, out, o, info, st);
+    if (S->ngroups > 1) {
+        // every group by reliable updates of its own (FG_MIXED_F32VAL is rejected for groups)
+        int64_t it = 0, up = 0;
+        double rel = 0;
+        fg_status s = cg_reliable_grouped(S, rhs, out, o.tol, o.max_iter, o.check_every, 1.0 / S->mixed_update, &it,
+                                          &up, &rel, st);
+        if (info) {
+            info->iters = it;
+            info->cycles = up;
+            info->relres = rel;
+            info->status = s;
+        }
+        return s;
+    }
     if (o.precision == FG_MIXED) {
         // FP32 CG with reliable updates: the FP64 residual replaces the FP32 one each
         // time the latter has dropped tenfold, and the search direction carries over
@@ -553,7 +506,7 @@ fg_status fg_system_create(fg_ctx *ctx, const fg_mesh *mesh, fg_system **out)
     S->grp_iters.assign(S->ngroups, 0);
     S->grp_relres.assign(S->ngroups, 0.0);
     S->grp_status.assign(S->ngroups, 0);
-    if (dalloc(&S->gsc, 1) || dalloc(&S->gpart, 2 * S->nslices) || dalloc(&S->gred, MAX_GROUPS) ||
+    if (dalloc(&S->gsc, 1) || dalloc(&S->gpart, 2 * S->nslices) || dalloc(&S->gred, 2 * MAX_GROUPS) ||
         hipHostMalloc((void **)&S->gsc_host, sizeof(MrScalars)) != hipSuccess ||
         hipHostMalloc((void **)&S->gred_host, MAX_GROUPS * sizeof(double)) != hipSuccess) {
         set_error("allocation of the batched-solve scalars failed");

@@ -205,6 +205,71 @@ __global__ __launch_bounds__(WG) void k_g_pupdate(int64_t nslices, const int32_t
     }
 }
 
+// Residual replacement of the FP32 grouped CG (reliable updates): per-slice
+// partials of r.z and r.r of the new residual; then per group beta against the
+// rho the group stopped with (its last direction is kept), the new rho and the
+// stop threshold next2[g] (squared; next2[g] <= 0: the group is finished); then
+// p = z + beta p on the groups that go on.
+template <int BS, typename T>
+__global__ __launch_bounds__(WG) void k_g_resume(int64_t nslices, const T *__restrict__ dinv, const T *__restrict__ r,
+                                                 double *part, int64_t stride)
+{
+    const int64_t s = xcd_block() * (WG / SLICE) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (s >= nslices) return;
+    double v[2] = {0, 0};
+#pragma unroll
+    for (int k = 0; k < BS; ++k) {
+        const int64_t e = slice_elem(s, k, lane, BS);
+        const T ri = r[e], zi = dinv[e] * ri;
+        v[0] += (double)ri * (double)zi;
+        v[1] += (double)ri * (double)ri;
+    }
+    slice_partials<2>(v, s, lane, part, stride);
+}
+
+__global__ __launch_bounds__(FIN) void k_g_resume_fin(const double *part, int64_t stride, const int64_t *gsp,
+                                                      MrScalars *sc, const double *next2)
+{
+    const int g = blockIdx.x;
+    double tot[2];
+    group_sum<2>(part, stride, gsp[g], gsp[g + 1], tot);
+    if (threadIdx.x != 0) return;
+    sc->status[g] = FG_OK;
+    sc->done[g] = 1;
+    if (!(next2[g] > 0.0)) return;
+    const double beta = tot[0] / sc->rho[g];
+    sc->rr[g] = tot[1];
+    if (!isfinite(tot[0]) || !isfinite(tot[1]) || !isfinite(beta)) {
+        sc->status[g] = FG_ERR_NAN;
+    } else if (sc->iter[g] >= sc->maxit) {
+        sc->status[g] = FG_NOT_CONVERGED;
+    } else {
+        sc->beta[g] = beta;
+        sc->rho[g] = tot[0];
+        sc->tol2[g] = next2[g];
+        sc->done[g] = 0;
+    }
+}
+
+template <int BS, typename T>
+__global__ __launch_bounds__(WG) void k_g_resume_p(int64_t nslices, const int32_t *__restrict__ slice_group,
+                                                   const T *__restrict__ dinv, const T *__restrict__ r,
+                                                   T *__restrict__ p, const MrScalars *sc)
+{
+    const int64_t s = xcd_block() * (WG / SLICE) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (s >= nslices) return;
+    const int g = slice_group[s];
+    if (sc->done[g]) return;
+    const T be = (T)sc->beta[g];
+#pragma unroll
+    for (int k = 0; k < BS; ++k) {
+        const int64_t e = slice_elem(s, k, lane, BS);
+        p[e] = dinv[e] * r[e] + be * p[e];
+    }
+}
+
 // per-group squared norms of a vector (per-slice partials, then k_g_norm_fin)
 template <int BS>
 __global__ __launch_bounds__(WG) void k_g_sq(int64_t nslices, const double *__restrict__ a, double *part, int64_t stride)
@@ -316,10 +381,9 @@ void drop_group_graphs(fg_system *S)
     }
 }
 
-fg_status cg_run_grouped(fg_system *S, int which, int precision, double tol, int64_t maxit, int check_every,
-                         int64_t *iters, double *relres, hipStream_t st)
+// Start of the grouped CG on the right-hand side already in S->wr (FP64) or S->fr (FP32).
+static fg_status g_init(fg_system *S, int which, bool f32, double tol, int64_t maxit, hipStream_t st)
 {
-    const bool f32 = (which == FG_K && precision == FG_F32);
     MrScalars init{};
     init.maxit = maxit;
     init.nrhs = S->ngroups;
@@ -334,17 +398,21 @@ fg_status cg_run_grouped(fg_system *S, int which, int precision, double tol, int
         LAUNCH((k_g_init<1, double>), gs, WG, st, S->nslices, S->dinvA, S->wx, S->wr, S->wp, S->gpart, stride);
     }
     LAUNCH(k_g_init_fin, S->ngroups, FIN, st, S->gpart, stride, S->group_slice_ptr, S->gsc, tol);
-    fg_status e = check_hip("grouped cg init");
-    if (e) return e;
+    return check_hip("grouped cg init");
+}
+
+// Batches of iterations until every group is done; per-group results in S->gsc_host.
+static fg_status g_loop(fg_system *S, int which, bool f32, int check_every, hipStream_t st)
+{
     const int batch = check_every > 0 ? check_every : 32;
     for (;;) {
         hipMemcpyAsync(S->gsc_host, S->gsc, sizeof(MrScalars), hipMemcpyDeviceToHost, st);
         hipStreamSynchronize(st);
-        e = check_hip("grouped cg poll");
+        fg_status e = check_hip("grouped cg poll");
         if (e) return e;
         bool all = true;
         for (int g = 0; g < S->ngroups; ++g) all = all && S->gsc_host->done[g];
-        if (all) break;
+        if (all) return FG_OK;
         if (f32)
             e = g_batch<3, float, float>(S, S->K32, S->dinvK32, S->fx, S->fr, S->fp, S->fq, batch, 1, st);
         else if (which == FG_K)
@@ -353,6 +421,16 @@ fg_status cg_run_grouped(fg_system *S, int which, int precision, double tol, int
             e = g_batch<1, double, double>(S, S->A22, S->dinvA, S->wx, S->wr, S->wp, S->wq, batch, 2, st);
         if (e) return e;
     }
+}
+
+fg_status cg_run_grouped(fg_system *S, int which, int precision, double tol, int64_t maxit, int check_every,
+                         int64_t *iters, double *relres, hipStream_t st)
+{
+    const bool f32 = (which == FG_K && precision == FG_F32);
+    fg_status e = g_init(S, which, f32, tol, maxit, st);
+    if (e) return e;
+    e = g_loop(S, which, f32, check_every, st);
+    if (e) return e;
     const MrScalars &h = *S->gsc_host;
     fg_status worst = FG_OK;
     int64_t imax = 0;
@@ -372,6 +450,93 @@ fg_status cg_run_grouped(fg_system *S, int which, int precision, double tol, int
     if (worst == FG_ERR_BREAKDOWN) set_error("fg_pcg_solve: CG breakdown in a group (p.Ap <= 0)");
     if (worst == FG_ERR_NAN) set_error("fg_pcg_solve: NaN or Inf in a group");
     return worst;
+}
+
+// FG_MIXED K solve of a batched system by reliable updates, group by group: the
+// FP32 grouped CG (each group scaled by 1/||b_g||) runs until every group has cut
+// its residual by `delta` (or reached 0.5 tol); then each group's FP32 correction
+// is added to the FP64 x, the FP64 residual b - K x replaces the FP32 one, and the
+// groups above tol go on from their last direction with the threshold
+// max(delta rel, 0.5 tol).  rhs, x: internal layout (3 Npad).
+fg_status cg_reliable_grouped(fg_system *S, const double *rhs, double *x, double tol, int64_t maxit, int check_every,
+                              double delta, int64_t *iters, int64_t *updates, double *worst_rel, hipStream_t st)
+{
+    const int G = S->ngroups;
+    const int64_t n = 3 * S->Npad, gs = grid_xcd((S->nslices + 3) / 4), stride = S->nslices;
+    double *r = S->v4, *next2_d = S->gred + MAX_GROUPS;
+    std::vector<double> bn(G), rn(G), scale(G), next2(G), rel(G, 0.0);
+    if (!S->k32_valid) refresh_k32(S, st);
+    group_norms(S, 3, rhs, bn.data(), st);
+    for (int g = 0; g < G; ++g) {
+        if (!std::isfinite(bn[g])) {
+            set_error("fg_pcg_solve: NaN or Inf in a group's right-hand side");
+            return FG_ERR_NAN;
+        }
+        scale[g] = bn[g] > 0 ? 1.0 / bn[g] : 0.0;
+    }
+    vfill(x, 0.0, n, st);
+    group_to_f32(S, scale.data(), rhs, S->fr, st);
+    fg_status e = g_init(S, FG_K, true, delta, maxit, st);
+    if (e) return e;
+    *iters = 0;
+    *updates = 0;
+    fg_status worst = FG_OK;
+    for (;;) {
+        e = g_loop(S, FG_K, true, check_every, st);
+        if (e) return e;
+        const MrScalars &h = *S->gsc_host;
+        std::vector<int64_t> it(h.iter, h.iter + G);
+        for (int g = 0; g < G; ++g) {
+            *iters = std::max<int64_t>(*iters, it[g]);
+            if (h.status[g] < 0) {
+                set_error(h.status[g] == FG_ERR_NAN ? "fg_pcg_solve: NaN or Inf in a group"
+                                                    : "fg_pcg_solve: CG breakdown in a group (p.Ap <= 0)");
+                return h.status[g];
+            }
+        }
+        // fold the FP32 corrections into x and replace the residuals by FP64 ones
+        group_add_f32(S, bn.data(), S->fx, x, st);
+        hipMemsetAsync(S->fx, 0, n * sizeof(float), st);
+        spmv(S, FG_K, x, S->wq, st);
+        hipMemcpyAsync(r, rhs, n * sizeof(double), hipMemcpyDeviceToDevice, st);
+        vaxpby(n, -1.0, S->wq, 1.0, r, st);
+        group_norms(S, 3, r, rn.data(), st);
+        ++*updates;
+        bool any = false;
+        *worst_rel = 0;
+        for (int g = 0; g < G; ++g) {
+            rel[g] = bn[g] > 0 ? rn[g] / bn[g] : 0.0;
+            if (!std::isfinite(rel[g])) {
+                set_error("fg_pcg_solve: NaN in a group's residual replacement");
+                return FG_ERR_NAN;
+            }
+            *worst_rel = std::max(*worst_rel, rel[g]);
+            next2[g] = -1.0;
+            if (rel[g] <= tol) continue;
+            if (it[g] >= maxit) {
+                worst = FG_NOT_CONVERGED;
+                continue;
+            }
+            const double nx = std::max(delta * rel[g], 0.5 * tol);
+            next2[g] = nx * nx;
+            any = true;
+        }
+        if (!any) {
+            for (int g = 0; g < G; ++g) {
+                S->grp_iters[g] += it[g];
+                S->grp_relres[g] = rel[g];
+                S->grp_status[g] = rel[g] <= tol ? FG_OK : FG_NOT_CONVERGED;
+            }
+            return worst;
+        }
+        group_to_f32(S, scale.data(), r, S->fr, st);
+        hipMemcpyAsync(next2_d, next2.data(), G * sizeof(double), hipMemcpyHostToDevice, st);
+        LAUNCH((k_g_resume<3, float>), gs, WG, st, S->nslices, S->dinvK32, S->fr, S->gpart, stride);
+        LAUNCH(k_g_resume_fin, G, FIN, st, S->gpart, stride, S->group_slice_ptr, S->gsc, next2_d);
+        LAUNCH((k_g_resume_p<3, float>), gs, WG, st, S->nslices, S->slice_group, S->dinvK32, S->fr, S->fp, S->gsc);
+        e = check_hip("grouped cg resume");
+        if (e) return e;
+    }
 }
 
 // Per-group norms of an internal vector with BS values per row.

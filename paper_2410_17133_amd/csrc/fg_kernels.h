@@ -74,6 +74,8 @@ void drop_mr_graphs(fg_system *S);
 // S->wr / S->fr and the solution left in S->wx / S->fx, as cg_run.
 fg_status cg_run_grouped(fg_system *S, int which, int precision, double tol, int64_t maxit, int check_every,
                          int64_t *iters, double *relres, hipStream_t st);
+fg_status cg_reliable_grouped(fg_system *S, const double *rhs, double *x, double tol, int64_t maxit, int check_every,
+                              double delta, int64_t *iters, int64_t *updates, double *worst_rel, hipStream_t st);
 void group_norms(fg_system *S, int bs, const double *a, double *host, hipStream_t st);
 void group_to_f32(fg_system *S, const double *scale, const double *x, float *y, hipStream_t st);
 void group_add_f32(fg_system *S, const double *scale, const float *x, double *y, hipStream_t st);
