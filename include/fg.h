@@ -308,7 +308,9 @@ fg_status fg_group_stats(const fg_system *sys, int64_t *iters_h, double *relres_
  *               3, 4 or 6.
  *   "mixed_update": FG_MIXED: factor by which the FP32 residual (of the
  *               solve, a column or a group) must drop before the FP64
- *               residual replaces it (default 10).
+ *               residual replaces it: 2 to 100 (default 10).  Longer FP32
+ *               phases drift: larger factors multiplied the FP32 iterations
+ *               and, at 1000, let an FP32 recurrence diverge.
  *   "vec_grid": workgroups of the CG vector kernels: 512 (default), 1024 or
  *               2048 (each adds the previous kernel's partial sums itself).
  *   "spmv_wpb": slices (one wavefront each) per workgroup of the CG

@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <vector>
 
 #include "fg_device.h"
@@ -833,8 +834,13 @@ static fg_status mr_reliable(fg_system *S, int nrhs, double tol, int64_t maxit, 
         for (int c = 0; c < nrhs; ++c) {
             *iters = std::max<int64_t>(*iters, h.iter[c]);
             if (h.status[c] < 0) {
-                set_error(h.status[c] == FG_ERR_NAN ? "fg_pcg_solve: NaN or Inf in a column"
-                                                    : "fg_pcg_solve: CG breakdown in a column (p.Ap <= 0)");
+                char msg[256];
+                std::snprintf(msg, sizeof msg,
+                              "fg_pcg_solve: %s in column %d at FP32 iteration %lld after %lld residual replacements "
+                              "(rho %.3e, p.Ap %.3e, r.r %.3e, beta %.3e)",
+                              h.status[c] == FG_ERR_NAN ? "NaN or Inf" : "CG breakdown (p.Ap <= 0)", c,
+                              (long long)h.iter[c], (long long)*updates, h.rho[c], h.pq[c], h.rr[c], h.beta[c]);
+                set_error(msg);
                 return h.status[c];
             }
         }

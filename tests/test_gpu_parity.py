@@ -253,8 +253,9 @@ def test_pcg_mixed_and_f32():
         assert ik.status == 0
         assert np.linalg.norm(b - P.spmv(O.K_TANGENT, host(xk))) <= 1e-8 * np.linalg.norm(b)
     S.tune("mixed_update", 10)
-    with pytest.raises(fg.FgError):
-        S.tune("mixed_update", 1)
+    for bad in (1, 101):
+        with pytest.raises(fg.FgError):
+            S.tune("mixed_update", bad)
     # FP32 alone: the recursive residual reaches the tolerance, the true residual stops
     # near kappa * u32 (about 1e4 * 6e-8 here), which is what refinement removes
     x32, info32 = S.pcg_solve(fg.FG_K, dev(b), tol=1e-5, precision=fg.FG_F32)
@@ -569,7 +570,7 @@ def test_block_solve_mixed_precision_and_errors():
     # columns eight orders of magnitude apart, a zero column, another replacement factor
     Bs = B * np.logspace(-4, 4, nrhs)[:, None]
     Bs[3] = 0.0
-    S.tune("mixed_update", 1000)
+    S.tune("mixed_update", 100)
     Xs, iS = S.pcg_solve(fg.FG_K, dev(Bs.reshape(-1)), nrhs=nrhs, tol=1e-9, precision=fg.FG_MIXED)
     S.tune("mixed_update", 10)
     assert iS.status == 0 and iS.relres <= 1e-9
