@@ -40,7 +40,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=128, help="hexes per cube edge (128 = the 12.6M-tet workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=300,
+    ap.add_argument("--cpu-iters", type=int, default=700,
                     help="oracle PCG iterations timed for the CPU baseline (about 10 s at 128^3)")
     ap.add_argument("--no-extras", action="store_true", help="skip every extra measurement")
     ap.add_argument("--extras", default="tt8,adjoint,steps,block,batch",
@@ -222,7 +222,7 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_iters, log)
         if extras:
-            out["cpu_baseline_64"] = cpu_baseline(I.make_instance(I.config(2)), 15 * args.cpu_iters, log)
+            out["cpu_baseline_64"] = cpu_baseline(I.make_instance(I.config(2)), 8 * args.cpu_iters, log)
     print(json.dumps(out), flush=True)
 
 
