@@ -53,8 +53,8 @@ def main():
                          "right-hand sides at 64^3, then one 1 GiB device copy; prints a short JSON line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the solver's multi-GPU sharding is not part of this build "
-              "(--gpus must be 1)", file=sys.stderr)
+        print("bench.py measures one GPU: the solver has no multi-GPU path, so --gpus must be 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
