@@ -112,3 +112,83 @@ def test_pcg_iterates_full_size(full):
     xp, ip = S.pcg_solve(fg.FG_A22, dev(bp), tol=1e-300, max_iter=50, check_every=64)
     xpo, st, it, rr = P.pcg(O.A22, bp, tol=1e-300, maxit=50)
     assert relerr(host(xp), xpo) < 1e-10
+
+
+def test_adjoint_identities_full_size(full):
+    """The 64^3 adjoint workload after one implicit injection step (slip points present),
+    checked by identities that hold at any size instead of an oracle adjoint.  With
+    J^T lam = g: lam.(J v) = g.v for random v.  In displacement directions J v is
+    K_bulk v plus the central difference of the interface force (recomputed by the
+    return map at U +- eps v, so the slip part of the tangent is in it) and A_up v; in
+    pressure directions it is (-A_pu w, A22 w).  Then dJ/dtheta.d = -lam.(dR/dtheta d)
+    for random directions in E and ln k, with dR/dtheta d the central difference of
+    re-assembled residuals at the same state.  The pressure right-hand side is zero in
+    the displacement and parameter checks, as for the fault-slip objective: a random
+    one makes lam_p so large that lam.(J v) cancels to the last digits."""
+    if full["n"] != 64:
+        pytest.skip("the adjoint workload is the 64^3 mesh")
+    S, inst, fg = full["S"], full["inst"], full["fg"]
+    N = S.N
+    print("[case] adjoint identities 64^3", flush=True)
+    U, P, die = dev(np.zeros(3 * N)), dev(np.zeros(N)), dev(np.zeros(2 * S.nq))
+    t0 = dev(inst.t0.reshape(-1))
+    inner = fg.opts(tol=1e-4, check_every=64)
+    trac, flag, info = S.step(U, P, die, t0, dev(inst.load), dev(inst.source), newton_tol=1e-8, newton_max_iter=60,
+                              inner_k=inner, inner_p=inner, outer_tol=1e-2)
+    nslip = int((host(flag) == 1).sum())
+    print(f"[adjoint identities] forward newton {info.newton_iters} status {info.status} slip points {nslip}", flush=True)
+    assert info.status == 0 and nslip > 0
+    r = np.random.default_rng(31)
+    mu_, mp_ = 1 - inst.dir_u, 1 - inst.dir_p
+    die0 = dev(np.zeros(2 * S.nq))
+    loose = fg.opts(tol=1e-3, check_every=64)
+
+    def adjoint(gu, gp):
+        dE, dk, lu, lp, ai = S.adjoint(U, P, die0, t0, dev(inst.logk), dev(gu), dev(gp), inner_k=loose,
+                                       inner_p=loose, outer_tol=0.05, defect_tol=1e-11, multipliers=True)
+        assert ai.status == 0
+        return host(dE), host(dk), host(lu), host(lp)
+
+    gu = r.standard_normal(3 * N) * mu_
+    dE, dk, lu, lp = adjoint(gu, np.zeros(N))
+    Uh = host(U)
+    for trial in range(2):
+        v = r.standard_normal(3 * N) * mu_
+        eps = 1e-6 * np.linalg.norm(Uh) / np.linalg.norm(v)
+        fp_ = host(S.cohesive_update(dev(Uh + eps * v), die0, t0, write_tangent=False)[3])
+        fm_ = host(S.cohesive_update(dev(Uh - eps * v), die0, t0, write_tangent=False)[3])
+        Jm = host(S.spmv(fg.FG_KBULK, dev(v))) + (fp_ - fm_) / (2 * eps)
+        Jf = host(S.coupling(dev(v), transpose=True))
+        lhs, rhs = lu @ Jm + lp @ Jf, gu @ v
+        print(f"[adjoint identities] U direction: lam.Jv {lhs:.12e} g.v {rhs:.12e}", flush=True)
+        assert abs(lhs - rhs) <= 1e-7 * abs(rhs)
+    gp = r.standard_normal(N) * mp_
+    _, _, lu2, lp2 = adjoint(np.zeros(3 * N), gp)
+    for trial in range(2):
+        w = r.standard_normal(N) * mp_
+        lhs = -(lu2 @ host(S.coupling(dev(w)))) + lp2 @ host(S.spmv(fg.FG_A22, dev(w)))
+        rhs = gp @ w
+        print(f"[adjoint identities] P direction: lam.Jw {lhs:.12e} g.w {rhs:.12e}", flush=True)
+        assert abs(lhs - rhs) <= 1e-7 * abs(rhs)
+    # parameter directions at the same state (the residual does not read the tangent)
+    fcoh = S.cohesive_update(U, die0, t0, write_tangent=False)[3]
+    zN3, zN = dev(np.zeros(3 * N)), dev(np.zeros(N))
+    E0, lk0 = inst.E.copy(), inst.logk.copy()
+    try:
+        for name, eps in (("E", 1e-3), ("ln k", 1e-4)):
+            rho = r.standard_normal(E0.shape[0])
+            R = []
+            for sgn in (1, -1):
+                if name == "E":
+                    S.assemble(inst.params, E0 * (1 + sgn * eps * rho), lk0)
+                else:
+                    S.assemble(inst.params, E0, lk0 + sgn * eps * rho)
+                Rm, Rf = S.residual(U, P, zN3, zN, fcoh, zN3, zN)
+                R.append((host(Rm), host(Rf)))
+            dR_m, dR_f = (R[0][0] - R[1][0]) / (2 * eps), (R[0][1] - R[1][1]) / (2 * eps)
+            rhs = -(lu @ dR_m + lp @ dR_f)
+            lhs = (dE * E0) @ rho if name == "E" else dk @ rho
+            print(f"[adjoint identities] {name} direction: gradient.d {lhs:.12e} -lam.dR {rhs:.12e}", flush=True)
+            assert abs(lhs - rhs) <= 1e-6 * abs(rhs)
+    finally:
+        S.assemble(inst.params, E0, lk0)
