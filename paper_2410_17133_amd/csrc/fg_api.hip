@@ -639,7 +639,7 @@ fg_status fg_pcg_solve(fg_ctx *ctx, fg_system *S, int which, int nrhs, const dou
     std::fill(S->grp_iters.begin(), S->grp_iters.end(), 0);
     if (which == FG_K && nrhs > 1) {
         fg_pcg_info bi{};
-        fg_status s = block_solve(S, nrhs, b, x, o.precision, o.tol, o.max_iter, o.check_every, o.inner_tol, &bi, st);
+        fg_status s = block_solve(S, nrhs, b, x, o.precision, o.tol, o.max_iter, o.check_every, &bi, st);
         if (info) *info = bi;
         return s;
     }

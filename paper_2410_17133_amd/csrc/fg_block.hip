@@ -106,7 +106,7 @@ __global__ __launch_bounds__(FIN) void k_mr_init_fin(const double *partials, int
 template <typename T, typename TV, int CT>
 __global__ __launch_bounds__(WG) void k_mr_spmm(SpmvArgs a, int nrhs, const TV *__restrict__ val,
                                                 const T *__restrict__ p, T *__restrict__ q, double *partials,
-                                                int64_t stride, const MrScalars *sc, int with_dot)
+                                                int64_t stride, int with_dot)
 {
     const int c0 = blockIdx.y * CT;
     const int64_t s = xcd_block() * (WG / SLICE) + (threadIdx.x >> 6);
@@ -628,23 +628,23 @@ static int64_t mr_launch_spmm(fg_system *S, int nrhs, const TV *val, const T *p,
     switch (ct) {
     case 1:
         hipLaunchKernelGGL((k_mr_spmm<T, TV, 1>), dim3(gx, nrhs / 1), dim3(WG), 0, st, a, nrhs, val, p, q, S->mpart,
-                           S->mpart_stride, S->msc, with_dot);
+                           S->mpart_stride, with_dot);
         break;
     case 2:
         hipLaunchKernelGGL((k_mr_spmm<T, TV, 2>), dim3(gx, nrhs / 2), dim3(WG), 0, st, a, nrhs, val, p, q, S->mpart,
-                           S->mpart_stride, S->msc, with_dot);
+                           S->mpart_stride, with_dot);
         break;
     case 4:
         hipLaunchKernelGGL((k_mr_spmm<T, TV, 4>), dim3(gx, nrhs / 4), dim3(WG), 0, st, a, nrhs, val, p, q, S->mpart,
-                           S->mpart_stride, S->msc, with_dot);
+                           S->mpart_stride, with_dot);
         break;
     case 8:
         hipLaunchKernelGGL((k_mr_spmm<T, TV, 8>), dim3(gx, nrhs / 8), dim3(WG), 0, st, a, nrhs, val, p, q, S->mpart,
-                           S->mpart_stride, S->msc, with_dot);
+                           S->mpart_stride, with_dot);
         break;
     default:
         hipLaunchKernelGGL((k_mr_spmm<T, TV, 16>), dim3(gx, nrhs / 16), dim3(WG), 0, st, a, nrhs, val, p, q, S->mpart,
-                           S->mpart_stride, S->msc, with_dot);
+                           S->mpart_stride, with_dot);
         break;
     }
     return gx;
@@ -889,7 +889,7 @@ static fg_status mr_reliable(fg_system *S, int nrhs, double tol, int64_t maxit, 
 
 // Multi-right-hand-side K solve: b, x in the caller layout (column c at c*3N).
 fg_status block_solve(fg_system *S, int nrhs, const double *b, double *x, int precision, double tol, int64_t maxit,
-                      int check_every, double inner_tol, fg_pcg_info *info, hipStream_t st)
+                      int check_every, fg_pcg_info *info, hipStream_t st)
 {
     if (nrhs > MR_MAX || (nrhs & (nrhs - 1))) {
         set_error("fg_pcg_solve: the block solve takes a power-of-two number of right-hand sides up to 64");

@@ -66,7 +66,7 @@ void drop_graphs(fg_system *S);
 
 // Block solves of many right-hand sides on K (fg_block.hip).
 fg_status block_solve(fg_system *S, int nrhs, const double *b, double *x, int precision, double tol, int64_t maxit,
-                      int check_every, double inner_tol, fg_pcg_info *info, hipStream_t st);
+                      int check_every, fg_pcg_info *info, hipStream_t st);
 fg_status mr_reserve(fg_system *S, int nrhs);
 void drop_mr_graphs(fg_system *S);
 
