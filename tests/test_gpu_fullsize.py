@@ -192,3 +192,60 @@ def test_adjoint_identities_full_size(full):
             assert abs(lhs - rhs) <= 1e-6 * abs(rhs)
     finally:
         S.assemble(inst.params, E0, lk0)
+
+
+def test_block_and_batch_full_size():
+    """The many-right-hand-side workloads at full size, in the product forms the benchmark
+    uses: the 32 injection right-hand sides on the 64^3 K solved as one block, and the 48
+    uneven instances solved as one grouped system, each in FP64 and in mixed precision.
+    Every column's (instance's) residual, measured with the oracle's CSR product, is at
+    the 1e-8 tolerance, and the FP64 and mixed solutions agree."""
+    from oracle import oracle as O
+    from paper_2410_17133_amd import fg
+    print("[case] block 64^3 x 32", flush=True)
+    inst = I.make_instance(I.config(5))
+    ctx = fg.Context(0)
+    S = fg.System.from_instance(ctx, inst)
+    S.assemble(inst.params, inst.E, inst.logk)
+    pairs, rates = I.injection_scenarios(inst, 32)
+    Q = I.source_matrix(inst, pairs, rates) * inst.params.dt
+    B = torch.stack([S.coupling(S.pcg_solve(fg.FG_A22, dev(q), tol=1e-12)[0]) for q in Q]).reshape(-1).contiguous()
+    P = O.Problem(inst)
+    P.cohesive(np.zeros(3 * P.N), np.zeros((P.nq, 2)))       # the stick tangent fg_assemble starts from
+    Bh = host(B).reshape(32, -1)
+    sols = {}
+    for name, prec in (("f64", fg.FG_F64), ("mixed", fg.FG_MIXED)):
+        X, info = S.pcg_solve(fg.FG_K, B, nrhs=32, tol=1e-8, precision=prec, check_every=64)
+        assert info.status == 0
+        X = host(X).reshape(32, -1)
+        worst = max(np.linalg.norm(Bh[c] - P.spmv(O.K_TANGENT, X[c])) / np.linalg.norm(Bh[c]) for c in range(32))
+        print(f"[block] {name}: iterations {info.iters} worst column residual {worst:.2e}", flush=True)
+        assert worst <= 1e-8 * (1 + 1e-6)       # the recursive residual stops at 1e-8; rounding of the check
+        sols[name] = X
+    assert max(relerr(sols["mixed"][c], sols["f64"][c]) for c in range(32)) < 1e-6
+    del S, P
+    print("[case] batch of 48 instances", flush=True)
+    insts = [I.make_instance(c) for c in I.batched_configs(48)]
+    Bt = I.concat_instances(insts)
+    G = fg.System.from_batch(ctx, Bt)
+    G.assemble([i.params for i in insts], Bt.E, Bt.logk)
+    z, _ = G.pcg_solve(fg.FG_A22, dev(Bt.source * insts[0].params.dt), tol=1e-12)
+    b = host(G.coupling(z))
+    sols = {}
+    for name, prec in (("f64", fg.FG_F64), ("mixed", fg.FG_MIXED)):
+        x, info = G.pcg_solve(fg.FG_K, dev(b), tol=1e-8, precision=prec, check_every=64)
+        iters, rel, stt = G.group_stats()
+        assert info.status == 0 and np.all(stt == 0)
+        sols[name] = host(x)
+        print(f"[batch] {name}: max iterations {info.iters} worst group residual {rel.max():.2e}", flush=True)
+    worst = 0.0
+    for g, ig in enumerate(insts):
+        lo, hi = 3 * Bt.node_off[g], 3 * Bt.node_off[g + 1]
+        Pg = O.Problem(ig)
+        Pg.cohesive(np.zeros(3 * Pg.N), np.zeros((Pg.nq, 2)))
+        for name in ("f64", "mixed"):
+            r = np.linalg.norm(b[lo:hi] - Pg.spmv(O.K_TANGENT, sols[name][lo:hi])) / np.linalg.norm(b[lo:hi])
+            worst = max(worst, r)
+        assert relerr(sols["mixed"][lo:hi], sols["f64"][lo:hi]) < 1e-6
+    print(f"[batch] worst instance residual by the oracle's product {worst:.2e}", flush=True)
+    assert worst <= 1e-8 * (1 + 1e-6)
