@@ -1189,3 +1189,90 @@ void or_sensitivity(or_problem *P, const double *U, const double *Pp, const doub
         dJ_dlogk[e] = -P->p.dt * sk;
     }
 }
+
+/* ------------------------------------------------------------------ */
+/* adjoint through the inelastic slip state (time loop)                */
+/* ------------------------------------------------------------------ */
+/* The inelastic slip carried from step to step, die_new = Phi(U, die_old), is the
+ * return map of Sec. 2.2.1 (eq. plastic_slip_increment, eq. corrector) applied at
+ * every interface point, and the interface force of the step reads die_old through
+ * the trial traction.  For a time loop of steps the adjoint needs, per point:
+ *   gU    = (d Phi / d U)^T a_new                        (added to the step's dJ/dU)
+ *   a_old = (d Phi / d die_old)^T a_new - (d f_coh / d die_old)^T lam_u
+ * where a_new [nq*2] is the adjoint of the slip the step produced and lam_u [3N]
+ * the step's displacement multipliers.  With the local opening d = (d_n, d_s) in
+ * the frame (n, t1, t2), trial traction t_tr = k_s (d_s0 + d_s - die_old),
+ * t'_n = k_n max(-(d_n0 + d_n), 0), Pi = I - tau tau^T:
+ *   stick:  die = die_old;                 t_s = t_tr
+ *   slip:   die = die_old + (|t_tr| - f t'_n)/k_s tau;  t_s = f t'_n tau
+ * differentiated branch by branch (open points follow the slip branch with
+ * t'_n = 0).  gU (or a_old) may be NULL; lam_u NULL reads as zero.  Held
+ * displacement DOFs are zero in gU. */
+void or_slip_adjoint(or_problem *P, const double *U, const double *die_old, const double *t0, const double *a_new,
+                     const double *lam_u, double *gU, double *a_old)
+{
+    int64_t N = P->N;
+    if (gU) memset(gU, 0, 3 * N * sizeof(double));
+    const double kn = P->p.k_n, ks = P->p.k_s, f = P->p.friction;
+    for (int64_t t = 0; t < P->nf; ++t) {
+        const int32_t *nd = P->coh + 6 * t;
+        const double *n = P->tri_n + 3 * t, *t1 = P->tri_t1 + 3 * t, *t2 = P->tri_t2 + 3 * t;
+        const double *R[3] = {n, t1, t2};
+        double w = P->tri_A[t] / 3.0;
+        for (int q = 0; q < 3; ++q) {
+            int64_t iq = 3 * t + q;
+            double jump[3] = {0, 0, 0}, lj[3] = {0, 0, 0};
+            for (int a = 0; a < 3; ++a)
+                for (int r = 0; r < 3; ++r) {
+                    int64_t ip = 3 * (int64_t)nd[a] + r, im = 3 * (int64_t)nd[3 + a] + r;
+                    jump[r] += QP_N[q][a] * (U[ip] - U[im]);
+                    if (lam_u) lj[r] += QP_N[q][a] * ((P->dir_u[ip] ? 0.0 : lam_u[ip]) - (P->dir_u[im] ? 0.0 : lam_u[im]));
+                }
+            double d[3] = {dot3(n, jump), dot3(t1, jump), dot3(t2, jump)};
+            const double *dio = die_old + 2 * iq, *tz = t0 + 3 * iq;
+            double dnt = -tz[0] / kn + d[0];
+            double tn = dnt < 0 ? -kn * dnt : 0.0;
+            double dtn = dnt < 0 ? -kn : 0.0; /* d t'_n / d d_n */
+            double ttr[2] = {ks * (tz[1] / ks + d[1] - dio[0]), ks * (tz[2] / ks + d[2] - dio[1])};
+            double nt = sqrt(ttr[0] * ttr[0] + ttr[1] * ttr[1]);
+            /* D_d [2][3]: d die / d (d_n, d_s1, d_s2); D_o [2][2]: d die / d die_old;
+             * T_o [2][2]: d t_s / d die_old */
+            double D_d[2][3] = {{0, 0, 0}, {0, 0, 0}}, D_o[2][2] = {{1, 0}, {0, 1}}, T_o[2][2] = {{-ks, 0}, {0, -ks}};
+            if (nt - f * tn > 0.0) {
+                double tau[2] = {ttr[0] / nt, ttr[1] / nt};
+                double Pi[2][2] = {{1 - tau[0] * tau[0], -tau[0] * tau[1]}, {-tau[1] * tau[0], 1 - tau[1] * tau[1]}};
+                double c = f * tn / nt;
+                for (int i = 0; i < 2; ++i) {
+                    D_d[i][0] = -(f / ks) * tau[i] * dtn;
+                    for (int j = 0; j < 2; ++j) {
+                        D_d[i][1 + j] = (i == j ? 1.0 : 0.0) - c * Pi[i][j];
+                        D_o[i][j] = c * Pi[i][j];
+                        T_o[i][j] = -ks * c * Pi[i][j];
+                    }
+                }
+            }
+            const double *an = a_new + 2 * iq;
+            if (gU) {
+                /* (d die/d U)^T a: local (D_d^T a), rotated to global, spread with +-N_a */
+                double loc[3];
+                for (int k = 0; k < 3; ++k) loc[k] = D_d[0][k] * an[0] + D_d[1][k] * an[1];
+                double g[3];
+                for (int r = 0; r < 3; ++r) g[r] = R[0][r] * loc[0] + R[1][r] * loc[1] + R[2][r] * loc[2];
+                for (int a = 0; a < 3; ++a)
+                    for (int r = 0; r < 3; ++r) {
+                        gU[3 * (int64_t)nd[a] + r] += QP_N[q][a] * g[r];
+                        gU[3 * (int64_t)nd[3 + a] + r] -= QP_N[q][a] * g[r];
+                    }
+            }
+            if (a_old) {
+                /* f_coh on the lips is +- w N_a [t1 t2] t_s: its transpose applied to lam_u */
+                double ls[2] = {dot3(t1, lj), dot3(t2, lj)};
+                for (int j = 0; j < 2; ++j)
+                    a_old[2 * iq + j] = D_o[0][j] * an[0] + D_o[1][j] * an[1] - w * (T_o[0][j] * ls[0] + T_o[1][j] * ls[1]);
+            }
+        }
+    }
+    if (gU)
+        for (int64_t i = 0; i < 3 * N; ++i)
+            if (P->dir_u[i]) gU[i] = 0;
+}
