@@ -261,6 +261,25 @@ fg_status fg_adjoint_solve(fg_ctx *ctx, fg_system *sys, const double *U, const d
                            const fg_pcg_opts *inner_k, const fg_pcg_opts *inner_p, double outer_tol,
                            double defect_tol, int64_t max_defect_iters, fg_solve_info *info_h, void *stream);
 
+/* Adjoint through the inelastic slip a time loop carries from step to step.  A
+ * step maps its start-of-step slip die_old to die_new = Phi(U, die_old) by the
+ * return map of Sec. 2.2.1 (eq. plastic_slip_increment, eq. corrector) at every
+ * interface point, and its interface force reads die_old through the trial
+ * traction (see fg_cohesive_update).  For a reverse sweep over the steps:
+ *   gU    = (dPhi/dU)^T a_new                       [3N], added to the step's dJ/dU
+ *   a_old = (dPhi/ddie_old)^T a_new - (df_coh/ddie_old)^T lam_u    [nq*2]
+ *   U        [3N]   the step's converged displacement (caller order)
+ *   die_old  [nq*2] its start-of-step slip;  t0 [nq*3] initial tractions
+ *   a_new    [nq*2] adjoint of the slip the step produced
+ *   lam_u    [3N]   the step's displacement multipliers (fg_adjoint_solve), or NULL
+ *                   (read as zero: a_old then omits the force term)
+ * Either output may be NULL (not both).  gU is zero on held DOFs.  Derivatives
+ * are taken branch by branch (stick, slip; open points follow the slip branch
+ * with zero normal traction), like the step's own tangent.
+ * Errors: FG_ERR_ARG, FG_ERR_STATE (before fg_assemble). */
+fg_status fg_slip_adjoint(fg_ctx *ctx, fg_system *sys, const double *U, const double *die_old, const double *t0,
+                          const double *a_new, const double *lam_u, double *gU, double *a_old, void *stream);
+
 /* Products on the assembled system, caller order: y = A x for which in
  * {FG_K, FG_A22, FG_KBULK, FG_C}. */
 fg_status fg_spmv(fg_ctx *ctx, fg_system *sys, int which, const double *x, double *y, void *stream);

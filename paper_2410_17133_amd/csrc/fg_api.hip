@@ -945,6 +945,24 @@ fg_status fg_adjoint_solve(fg_ctx *ctx, fg_system *S, const double *U, const dou
     return e ? e : status;
 }
 
+fg_status fg_slip_adjoint(fg_ctx *ctx, fg_system *S, const double *U, const double *die_old, const double *t0,
+                          const double *a_new, const double *lam_u, double *gU, double *a_old, void *stream)
+{
+    if (!ctx || !S || !U || (S->nq && (!die_old || !t0 || !a_new)) || (!gU && !a_old)) {
+        set_error("fg_slip_adjoint: bad argument");
+        return FG_ERR_ARG;
+    }
+    if (!ready(S)) return FG_ERR_STATE;
+    Guard g(ctx->device);
+    hipStream_t st = S_(stream);
+    perm_in(S, 3, U, S->ui, st);
+    if (lam_u) perm_in(S, 3, lam_u, S->v1, st);
+    slip_adjoint(S, S->ui, die_old, t0, a_new, lam_u ? S->v1 : nullptr, gU ? S->v2 : nullptr, S->nq ? a_old : nullptr,
+                 st);
+    if (gU) perm_out(S, 3, S->v2, gU, st);
+    return check_hip("fg_slip_adjoint");
+}
+
 fg_status fg_spmv(fg_ctx *ctx, fg_system *S, int which, const double *x, double *y, void *stream)
 {
     if (!ctx || !S || !x || !y || which < 0 || which > 3) {

@@ -23,6 +23,8 @@ void cohesive_rows(fg_system *S, double *fcoh_int, int write_tangent, hipStream_
 // adjoint: y = N^T x (slip part of the exact interface tangent, last interface update)
 void apply_NT(fg_system *S, const double *x, double *y, hipStream_t st);
 // dJ/dE and dJ/dln k per tetrahedron (caller order) from the state and the multipliers
+void slip_adjoint(fg_system *S, const double *U_int, const double *die_old, const double *t0, const double *a_new,
+                  const double *lam_int, double *gU_int, double *a_old, hipStream_t st);
 void sensitivity(fg_system *S, const double *U, const double *P, const double *lu, const double *lp, double *dE,
                  double *dlogk, const double *logk, hipStream_t st);
 

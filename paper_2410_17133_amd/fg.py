@@ -21,7 +21,7 @@ FG_F64, FG_F32, FG_MIXED, FG_MIXED_F32VAL = 0, 1, 2, 3
 SYMBOLS = ["fg_last_error", "fg_ctx_create", "fg_ctx_destroy", "fg_system_create", "fg_system_destroy",
            "fg_assemble", "fg_cohesive_update", "fg_pcg_solve", "fg_flow_solve", "fg_step", "fg_spmv",
            "fg_coupling", "fg_residual", "fg_system_sizes", "fg_export", "fg_profile", "fg_profile_read", "fg_tune", "fg_adjoint_solve", "fg_group_stats",
-           "fg_assemble_groups"]
+           "fg_assemble_groups", "fg_slip_adjoint"]
 
 
 class FgError(RuntimeError):
@@ -95,6 +95,7 @@ def lib():
             "fg_adjoint_solve": [vp, vp] + [vp] * 11 + [C.POINTER(PcgOpts), C.POINTER(PcgOpts), dbl, dbl, i64,
                                                         C.POINTER(SolveInfo), vp],
             "fg_profile_read": [vp, i32, C.POINTER(i64), C.POINTER(dbl), i32],
+            "fg_slip_adjoint": [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -273,6 +274,17 @@ class System:
         if multipliers:
             return dE, dk, lu, lp, info
         return dE, dk, info
+
+    def slip_adjoint(self, U, die_old, t0, a_new, lam_u=None):
+        """(gU [3N], a_old [nq*2]) of the slip state carried between steps (fg_slip_adjoint)."""
+        nq = self.nq
+        gU, a_old = self._d(3 * self.N), self._d(2 * nq)
+        _check(lib().fg_slip_adjoint(self.ctx._h, self._h, _ptr(U, torch.float64, 3 * self.N, "U"),
+                                     _ptr(die_old, torch.float64, 2 * nq, "die_old"), _ptr(t0, torch.float64, 3 * nq, "t0"),
+                                     _ptr(a_new, torch.float64, 2 * nq, "a_new"),
+                                     None if lam_u is None else _ptr(lam_u, torch.float64, 3 * self.N, "lam_u"),
+                                     _ptr(gU, torch.float64), _ptr(a_old, torch.float64), _stream()), False)
+        return gU, a_old
 
     def spmv(self, which, x):
         n = (3 if which in (FG_K, FG_KBULK) else 1) * self.N
