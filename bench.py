@@ -339,35 +339,63 @@ def extra_adjoint(ctx, log):
 
 
 def extra_steps(ctx, log, nsteps=3):
-    """The first steps of the 20-step 64^3 trajectory: constant injection, the state
-    (U, P, inelastic slip) carried from step to step, inexact Newton as in the adjoint."""
+    """The first steps of the 20-step 64^3 trajectory (constant injection, the state U, P and
+    inelastic slip carried from step to step, inexact Newton as in the adjoint), checkpointed,
+    then the reverse sweep: the gradient of J = sum over the steps of the fault-slip and uplift
+    objective w.r.t. ln k and E through the whole loop, slip state included."""
     import numpy as np
     import torch
 
     from paper_2410_17133_amd import fg
     from paper_2410_17133_amd import inputs as I
+    from paper_2410_17133_amd import trajectory as T
+    from paper_2410_17133_amd.autograd import fault_slip_uplift_objective
 
     inst = I.make_instance(I.config(2))
     S = fg.System.from_instance(ctx, inst)
-    S.assemble(inst.params, inst.E, inst.logk)
     d = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float64)).cuda()
+    E, logk = d(inst.E), d(inst.logk)
+    S.assemble(inst.params, E, logk)
     U, P, die = d(np.zeros(3 * S.N)), d(np.zeros(S.N)), d(np.zeros(2 * S.nq))
     t0, load, src = d(inst.t0.reshape(-1)), d(inst.load), d(inst.source)
     inner = fg.opts(tol=1e-4, check_every=64)
-    steps = []
+    steps, ck = [], []
     for k in range(nsteps):
-        ts, (trac, flag, info) = _timed(lambda: S.step(U, P, die, t0, load, src, newton_tol=1e-8, newton_max_iter=60,
-                                                       inner_k=inner, inner_p=inner, outer_tol=1e-2))
-        fl = flag.cpu().numpy()
+        ts, (c, infos) = _timed(lambda: T.run(S, U, P, die, t0, load, src, 1, newton_tol=1e-8, newton_max_iter=60,
+                                              inner_k=inner, inner_p=inner, outer_tol=1e-2))
+        ck += c
+        info = infos[0]
+        fl = S.cohesive_update(U, c[0][2], t0, write_tangent=False)[2].cpu().numpy()
         rec = {"s": ts, "newton": info.newton_iters, "step_cuts": info.step_cuts, "outer": info.outer_iters,
                "k_iters": info.inner_k_iters, "status": info.status, "slip": int((fl == 1).sum()),
                "open": int((fl == 2).sum())}
         steps.append(rec)
         log(f"step {k + 1}: {ts:.1f}s newton {info.newton_iters} cuts {info.step_cuts} K iters {info.inner_k_iters} "
             f"slip {rec['slip']} open {rec['open']} status {info.status}")
+    m = inst.mesh
+    X = m.xyz[m.coh[0, 3:]]
+    nrm = np.cross(X[1] - X[0], X[2] - X[0])
+    pairs = torch.as_tensor(m.pairs.astype(np.int64)).cuda()
+    nrm_d = d(nrm / np.linalg.norm(nrm))
+    up = torch.as_tensor(I.uplift_nodes(inst, 32).astype(np.int64)).cuda()
+
+    def grad_y(n, Un, Pn):
+        Uv = Un.clone().requires_grad_(True)
+        g, = torch.autograd.grad(fault_slip_uplift_objective(Uv, pairs, nrm_d, up), Uv)
+        return g, torch.zeros_like(Pn)
+    # corrections solved loosely (outer 0.05, inner 1e-3); the defect tolerance sets the accuracy
+    corr = fg.opts(tol=1e-3, check_every=64)
+    tr, (dE, dk, ainfos) = _timed(lambda: T.gradient(S, ck, t0, logk, grad_y, inner_k=corr, inner_p=corr,
+                                                     outer_tol=0.05, defect_tol=1e-8))
+    defect = [i.newton_iters for i in ainfos]
+    log(f"reverse sweep over {nsteps} steps: {tr:.1f}s, defect iterations per step {defect}, "
+        f"K iters {sum(i.inner_k_iters for i in ainfos)}")
     return {"workload": f"cube64_dip60_hetero, {nsteps} consecutive 1 s steps of the 20-step trajectory; Newton 1e-8, "
-                        f"outer 1e-2, inner 1e-4", "steps": steps,
-            "mean_step_s": float(np.mean([s["s"] for s in steps]))}
+                        f"outer 1e-2, inner 1e-4; reverse sweep: defect 1e-8, corrections outer 0.05 inner 1e-3",
+            "steps": steps, "mean_step_s": float(np.mean([s["s"] for s in steps])),
+            "reverse_s": tr, "reverse_defect_iters": defect,
+            "reverse_k_iters": int(sum(i.inner_k_iters for i in ainfos)),
+            "gradient_norm": float(torch.linalg.norm(torch.cat([dE * E, dk])).item())}
 
 
 def extra_block(ctx, log):
