@@ -127,3 +127,28 @@ def test_loop_gradient_matches_oracle_and_differences(loop):
     S.assemble(inst.params, inst.E, inst.logk)
     print(f"[loop gradient] fd {fd:.9e} adjoint {grad @ d:.9e}", flush=True)
     assert abs(fd - grad @ d) <= 1e-5 * abs(fd)
+
+
+def test_autograd_loop_gradient_equals_reverse_sweep(loop):
+    """ImplicitLoop (torch.autograd.Function) on the same 4-step loop: the objective summed
+    over the steps in torch, backward through the loop, equals the oracle's reverse sweep."""
+    inst, P, ck_o, S, ck, t0, fg, T = loop
+    from paper_2410_17133_amd.autograd import ImplicitLoop, fault_slip_uplift_objective
+    uplift = I.uplift_nodes(inst, 8)
+    jg = objective(inst, uplift)
+    dE_o, dk_o = P.trajectory_gradient(ck_o, lambda n, U, Pp: (jg(U)[1], np.zeros(P.N)))
+    m = inst.mesh
+    X = m.xyz[m.coh[0, 3:]]
+    nrm = np.cross(X[1] - X[0], X[2] - X[0])
+    logk = dev(inst.logk).requires_grad_(True)
+    E = dev(inst.E).requires_grad_(True)
+    solver = dict(newton_tol=1e-13, inner_tol=1e-14, outer_tol=1e-13, adjoint_outer_tol=1e-13,
+                  adjoint_inner_tol=1e-14)
+    U_all, P_all = ImplicitLoop.apply(logk, E, S, inst.params, t0, dev(np.zeros(3 * S.N)), dev(inst.source), 4,
+                                      solver)
+    pairs = torch.as_tensor(m.pairs.astype(np.int64)).cuda()
+    up = torch.as_tensor(uplift.astype(np.int64)).cuda()
+    J = sum(fault_slip_uplift_objective(U_all[n], pairs, dev(nrm / np.linalg.norm(nrm)), up) for n in range(4))
+    J.backward()
+    print(f"[autograd loop] dE {rel(host(E.grad), dE_o):.1e} dlnk {rel(host(logk.grad), dk_o):.1e}", flush=True)
+    assert rel(host(E.grad), dE_o) < 1e-7 and rel(host(logk.grad), dk_o) < 1e-7
