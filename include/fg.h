@@ -323,6 +323,14 @@ fg_status fg_group_stats(const fg_system *sys, int64_t *iters_h, double *relres_
  *               HIP graph, 0 launches the kernels one by one (same results).
  *   "line_search": 1 (default) backtracking on the Newton steps of fg_step,
  *               0 full steps.
+ *   "k_precond": preconditioner of the FP64 single-right-hand-side K solves
+ *               (fg_pcg_solve, and the K solves inside fg_flow_solve, fg_step and
+ *               fg_adjoint_solve): 0 (default) point Jacobi; 1 block Jacobi, the
+ *               inverse of every node's 3x3 diagonal block except that the two
+ *               lips' nodes at one interface point share the inverse of their
+ *               6x6 block (the penalty stiffness couples them).  Rebuilt after
+ *               every change of K; FG_ERR_BREAKDOWN if a block is singular.
+ *               Block, batched and FP32 solves keep point Jacobi.
  *   "spmv_unroll": slots per unrolled step of the CG product: 1, 2 (default),
  *               3, 4 or 6.
  *   "mixed_update": FG_MIXED: factor by which the FP32 residual (of the

@@ -1276,3 +1276,163 @@ void or_slip_adjoint(or_problem *P, const double *U, const double *die_old, cons
         for (int64_t i = 0; i < 3 * N; ++i)
             if (P->dir_u[i]) gU[i] = 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* block-Jacobi preconditioned CG on K                                 */
+/* ------------------------------------------------------------------ */
+/* Inverse of an n x n matrix by Gauss-Jordan elimination with partial pivoting
+ * (row-major, a destroyed).  Returns 0 if a pivot vanishes. */
+static int gj_inverse(int n, double *a, double *inv)
+{
+    for (int i = 0; i < n * n; ++i) inv[i] = (i / n == i % n) ? 1.0 : 0.0;
+    for (int c = 0; c < n; ++c) {
+        int pr = c;
+        for (int r = c + 1; r < n; ++r)
+            if (fabs(a[r * n + c]) > fabs(a[pr * n + c])) pr = r;
+        if (a[pr * n + c] == 0.0) return 0;
+        for (int k = 0; k < n; ++k) {
+            double t = a[c * n + k];
+            a[c * n + k] = a[pr * n + k];
+            a[pr * n + k] = t;
+            t = inv[c * n + k];
+            inv[c * n + k] = inv[pr * n + k];
+            inv[pr * n + k] = t;
+        }
+        double d = a[c * n + c];
+        for (int k = 0; k < n; ++k) {
+            a[c * n + k] /= d;
+            inv[c * n + k] /= d;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            double m = a[r * n + c];
+            for (int k = 0; k < n; ++k) {
+                a[r * n + k] -= m * a[c * n + k];
+                inv[r * n + k] -= m * inv[c * n + k];
+            }
+        }
+    }
+    return 1;
+}
+
+void or_gj_inverse(int n, double *a, double *inv, int *ok) { *ok = gj_inverse(n, a, inv); }
+
+static double csr_at(const or_csr *A, int64_t row, int64_t col)
+{
+    for (int64_t k = A->rowptr[row]; k < A->rowptr[row + 1]; ++k)
+        if (A->col[k] == col) return A->val[k];
+    return 0.0;
+}
+
+/* PCG on the current tangent K_t with a block-Jacobi preconditioner: the inverse
+ * of the 3x3 diagonal block of every node, except that the two lips' nodes at the
+ * same interface point (+a, -a of an interface element) share the inverse of their
+ * 6x6 block.  Same recurrence and stop test as or_pcg. */
+int or_pcg_block(or_problem *P, const double *b, double *x, double tol, int64_t maxit, int64_t *iters, double *relres)
+{
+    const or_csr *A = &P->Kt;
+    int64_t N = P->N, n = 3 * N;
+    int32_t *partner = malloc(N * sizeof(int32_t));
+    for (int64_t i = 0; i < N; ++i) partner[i] = -1;
+    for (int64_t t = 0; t < P->nf; ++t)
+        for (int a = 0; a < 3; ++a) {
+            int32_t u = P->coh[6 * t + a], v = P->coh[6 * t + 3 + a];
+            partner[u] = (partner[u] == -1 || partner[u] == v) ? v : -2;
+            partner[v] = (partner[v] == -1 || partner[v] == u) ? u : -2;
+        }
+    for (int64_t i = 0; i < N; ++i)
+        if (partner[i] == -2 || partner[i] == i) partner[i] = -1;
+    /* per node: M^-1 rows of the node, own part Ai (3x3) and partner part Bi (3x3) */
+    double *Ai = calloc(9 * N, sizeof(double)), *Bi = calloc(9 * N, sizeof(double));
+    int singular = 0;
+    for (int64_t u = 0; u < N; ++u) {
+        int64_t v = partner[u];
+        if (v >= 0 && partner[v] != u) v = -1;
+        if (v < 0) {
+            double m[9], inv[9];
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) m[3 * r + c] = csr_at(A, 3 * u + r, 3 * u + c);
+            if (!gj_inverse(3, m, inv)) singular = 1;
+            memcpy(Ai + 9 * u, inv, sizeof inv);
+        } else {
+            double m[36], inv[36];
+            int64_t nd[2] = {u, v};
+            for (int bi = 0; bi < 2; ++bi)
+                for (int bj = 0; bj < 2; ++bj)
+                    for (int r = 0; r < 3; ++r)
+                        for (int c = 0; c < 3; ++c)
+                            m[6 * (3 * bi + r) + 3 * bj + c] = csr_at(A, 3 * nd[bi] + r, 3 * nd[bj] + c);
+            if (!gj_inverse(6, m, inv)) singular = 1;
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) {
+                    Ai[9 * u + 3 * r + c] = inv[6 * r + c];
+                    Bi[9 * u + 3 * r + c] = inv[6 * r + 3 + c];
+                }
+        }
+        partner[u] = (int32_t)v;
+    }
+    double *r = malloc(n * sizeof(double)), *z = malloc(n * sizeof(double));
+    double *p = malloc(n * sizeof(double)), *q = malloc(n * sizeof(double));
+    int status = 0;
+    int64_t it = 0;
+    double rel = 0;
+#define ZBLOCK()                                                                            \
+    for (int64_t u = 0; u < N; ++u)                                                         \
+        for (int c = 0; c < 3; ++c) {                                                       \
+            double s = 0;                                                                   \
+            for (int k = 0; k < 3; ++k) s += Ai[9 * u + 3 * c + k] * r[3 * u + k];          \
+            if (partner[u] >= 0)                                                            \
+                for (int k = 0; k < 3; ++k) s += Bi[9 * u + 3 * c + k] * r[3 * partner[u] + k]; \
+            z[3 * u + c] = s;                                                               \
+        }
+    for (int64_t i = 0; i < n; ++i) {
+        x[i] = 0;
+        r[i] = b[i];
+    }
+    ZBLOCK();
+    memcpy(p, z, n * sizeof(double));
+    double bn = sqrt(vdot(n, b, b));
+    if (singular) {
+        status = -3;
+        goto done;
+    }
+    if (bn == 0.0) goto done;
+    double rho = vdot(n, r, z);
+    for (;;) {
+        rel = sqrt(vdot(n, r, r)) / bn;
+        if (rel <= tol) break;
+        if (it >= maxit) {
+            status = 1;
+            break;
+        }
+        or_csr_spmv(A, p, q);
+        double pq = vdot(n, p, q);
+        if (!(pq > 0.0)) {
+            status = -3;
+            break;
+        }
+        double al = rho / pq;
+        for (int64_t i = 0; i < n; ++i) {
+            x[i] += al * p[i];
+            r[i] -= al * q[i];
+        }
+        ZBLOCK();
+        double rho2 = vdot(n, r, z);
+        double be = rho2 / rho;
+        rho = rho2;
+        for (int64_t i = 0; i < n; ++i) p[i] = z[i] + be * p[i];
+        ++it;
+    }
+#undef ZBLOCK
+done:
+    *iters = it;
+    *relres = rel;
+    free(partner);
+    free(Ai);
+    free(Bi);
+    free(r);
+    free(z);
+    free(p);
+    free(q);
+    return status;
+}

@@ -75,6 +75,10 @@ def lib():
                                  C.c_double, C.c_int64, C.c_int64, _f64p]
         L.or_sensitivity.argtypes = [C.c_void_p, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p]
         L.or_slip_adjoint.argtypes = [C.c_void_p, _f64p, _f64p, _f64p, _f64p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.or_pcg_block.restype = C.c_int
+        L.or_pcg_block.argtypes = [C.c_void_p, _f64p, _f64p, C.c_double, C.c_int64, C.POINTER(C.c_int64),
+                                   C.POINTER(C.c_double)]
+        L.or_gj_inverse.argtypes = [C.c_int, _f64p, _f64p, C.POINTER(C.c_int)]
         L.or_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -195,6 +199,13 @@ class Problem:
         x = np.zeros_like(b, dtype=np.float64)
         it, rr = C.c_int64(), C.c_double()
         st = lib().or_pcg(self._h, which, _c(b, np.float64), x, tol, maxit, C.byref(it), C.byref(rr))
+        return x, st, it.value, rr.value
+
+    def pcg_block(self, b, tol=1e-10, maxit=1000000):
+        """K_t x = b by PCG with the nodal / fault-pair block-Jacobi preconditioner: (x, status, iters, relres)."""
+        x = np.zeros(3 * self.N)
+        it, rr = C.c_int64(), C.c_double()
+        st = lib().or_pcg_block(self._h, _c(b, np.float64), x, tol, maxit, C.byref(it), C.byref(rr))
         return x, st, it.value, rr.value
 
     def prevost(self, b1, b2, tol_outer=1e-10, tol_inner=1e-12, maxit_outer=500, maxit_inner=200000):

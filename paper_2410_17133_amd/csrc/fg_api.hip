@@ -383,7 +383,8 @@ fg_status fg_system_destroy(fg_system *S)
                     S->Cm, S->dinvK, S->dinvK32, S->dinvA, S->qpD, S->qpT, S->qpNs, S->qpS, S->adj_trac, S->adj_die, S->adj_flag, S->wx, S->wr, S->wp, S->wq, S->fx,
                     S->fr, S->fp, S->fq, S->v1, S->v2, S->v3, S->v4, S->pv1, S->pv2, S->ui, S->ui0, S->fi, S->rm,
                     S->du, S->fc, S->s1, S->s2, S->s3, S->s4, S->s5, S->s6, S->s7, S->s8, S->pi, S->pi0, S->qi,
-                    S->rf, S->dpv, S->die0, S->partials, S->sc, S->red, S->red_counter};
+                    S->rf, S->dpv, S->die0, S->partials, S->sc, S->red, S->red_counter, S->fslot, S->fpart,
+                    S->bjA, S->bjB, S->wz};
     for (void *p : ptrs) dfree(p);
     drop_graphs(S);
     drop_mr_graphs(S);
@@ -468,6 +469,8 @@ fg_status fg_system_create(fg_ctx *ctx, const fg_mesh *mesh, fg_system **out)
     CK(upload(&S->frows, P.frows));
     CK(upload(&S->fadj_ptr, P.fadj_ptr));
     CK(upload(&S->fadj, P.fadj));
+    if (!P.fslot.empty()) CK(upload(&S->fslot, P.fslot));
+    if (!P.fpart.empty()) CK(upload(&S->fpart, P.fpart));
     CK(upload(&S->dir_u, P.dir_u));
     CK(upload(&S->dir_p, P.dir_p));
     CK(dalloc(&S->gprm, S->ngroups));
@@ -583,6 +586,7 @@ fg_status fg_assemble_groups(fg_ctx *ctx, fg_system *S, const fg_params *prm, in
         return check_hip("fg_assemble parameters");
     S->prm = prm[0];
     S->k32_valid = false;
+    S->bj_valid = false;
     assemble_all(S, E, log_k, st);
     TRY(check_hip("fg_assemble"));
     int bad = 0;
@@ -1078,6 +1082,23 @@ fg_status fg_tune(fg_system *S, const char *key, int64_t value)
         drop_graphs(S);
         drop_mr_graphs(S);
         drop_group_graphs(S);
+        return FG_OK;
+    }
+    if (std::strcmp(key, "k_precond") == 0) {
+        if (value > 1) {
+            set_error("fg_tune: k_precond must be 0 (point Jacobi) or 1 (nodal and fault-pair block Jacobi)");
+            return FG_ERR_ARG;
+        }
+        if (value == 1 && !S->bjA) {
+            if (dalloc(&S->bjA, 6 * S->Npad) || dalloc(&S->bjB, 9 * std::max<int64_t>(S->nfr, 1)) ||
+                dalloc(&S->wz, 3 * S->Npad)) {
+                set_error("fg_tune: device allocation for the block-Jacobi preconditioner failed");
+                return FG_ERR_OOM;
+            }
+            S->bj_valid = false;
+        }
+        S->k_precond = (int)value;
+        drop_graphs(S);
         return FG_OK;
     }
     if (std::strcmp(key, "line_search") == 0) {

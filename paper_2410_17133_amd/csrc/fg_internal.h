@@ -40,6 +40,8 @@ struct Plan {
     std::vector<int32_t> frows;      // internal rows of interface nodes, ascending
     std::vector<int32_t> fadj_ptr;   // [nfr+1]
     std::vector<int32_t> fadj;       // 6*t + local vertex (0..5) of each incident interface element
+    std::vector<int32_t> fslot;      // [Npad] index into frows, -1 for rows off the interface
+    std::vector<int32_t> fpart;      // [nfr] internal row of the other lip's node at the same point, -1 if none
     std::vector<uint8_t> dir_u;      // [3*Npad] internal order, padding rows 0
     std::vector<uint8_t> dir_p;      // [Npad]
 };
@@ -127,6 +129,13 @@ struct fg_system {
     int32_t *tets = nullptr, *tet_orig = nullptr;
     int32_t *coh = nullptr;
     int32_t *frows = nullptr, *fadj_ptr = nullptr, *fadj = nullptr;
+    int32_t *fslot = nullptr, *fpart = nullptr;  // fault-pair map (block-Jacobi preconditioner of K)
+    double *bjA = nullptr;      // [Npad*6] symmetric 3x3 inverse blocks, xx yy zz yz xz xy
+    double *bjB = nullptr;      // [nfr*9] pair coupling blocks of the inverse, row-major
+    double *wz = nullptr;       // [3*Npad] z = M^-1 r of the block-preconditioned CG
+    bool bj_valid = false;      // bjA/bjB built from the current K
+    bool bj_singular = false;   // the last build met a singular block
+    int k_precond = 0;          // fg_tune "k_precond": 0 point Jacobi, 1 nodal + fault-pair block Jacobi
     uint8_t *dir_u = nullptr, *dir_p = nullptr;
     double *tri_geo = nullptr;  // [nf*10]: area, n[3], t1[3], t2[3]
     // operators

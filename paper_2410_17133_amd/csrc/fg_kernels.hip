@@ -9,6 +9,8 @@
 // the same slots with one value each.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -884,6 +886,250 @@ __global__ __launch_bounds__(WG) void k_cg_pupdate(int64_t n, int par, const T *
         p[i] = dinv[i] * r[i] + be * p[i];
 }
 
+// ----------------------------------------------------------------- block Jacobi
+// Preconditioner of K built from its own blocks: the 3x3 diagonal block of every
+// node, and for the two lips' nodes at the same interface point the 6x6 block of
+// the pair (their diagonal blocks and the coupling the penalty stiffness puts
+// between them), inverted.  Row u keeps the symmetric 3x3 part A_u of its inverse
+// and, on the interface, the coupling part B_u (z_u = A_u r_u + B_u r_partner).
+struct BlockJacobi {
+    const double *A;       // [Npad*6] xx yy zz yz xz xy
+    const double *B;       // [nfr*9] row-major
+    const int32_t *fslot;  // [Npad] index into the fault rows, -1 off the interface
+    const int32_t *fpart;  // [nfr] partner row, -1 if none
+    double *z;             // [3*Npad]
+};
+
+// In-place inverse of an n x n matrix (row-major, n <= 6), Gauss-Jordan with
+// partial pivoting; false if a pivot vanishes.
+template <int NN>
+__device__ bool small_inverse(double (&a)[NN * NN], double (&inv)[NN * NN])
+{
+    for (int i = 0; i < NN * NN; ++i) inv[i] = (i / NN == i % NN) ? 1.0 : 0.0;
+    for (int c = 0; c < NN; ++c) {
+        int pr = c;
+        double pv = fabs(a[c * NN + c]);
+        for (int r = c + 1; r < NN; ++r)
+            if (fabs(a[r * NN + c]) > pv) pv = fabs(a[r * NN + c]), pr = r;
+        if (!(pv > 0.0)) return false;
+        if (pr != c)
+            for (int k = 0; k < NN; ++k) {
+                double t = a[c * NN + k];
+                a[c * NN + k] = a[pr * NN + k], a[pr * NN + k] = t;
+                t = inv[c * NN + k];
+                inv[c * NN + k] = inv[pr * NN + k], inv[pr * NN + k] = t;
+            }
+        const double d = 1.0 / a[c * NN + c];
+        for (int k = 0; k < NN; ++k) a[c * NN + k] *= d, inv[c * NN + k] *= d;
+        for (int r = 0; r < NN; ++r) {
+            if (r == c) continue;
+            const double m = a[r * NN + c];
+            if (m == 0.0) continue;
+            for (int k = 0; k < NN; ++k) a[r * NN + k] -= m * a[c * NN + k], inv[r * NN + k] -= m * inv[c * NN + k];
+        }
+    }
+    return true;
+}
+
+__device__ __forceinline__ void k_block(const double *K, const int64_t *slice_ptr, int64_t row, int slot, double (&b)[9])
+{
+    const int64_t s = row / SLICE, l = row % SLICE, base = slice_ptr[s];
+    for (int e = 0; e < 9; ++e) b[e] = K[9 * base + (int64_t)(9 * slot + e) * SLICE + l];
+}
+
+__global__ void k_bj_build(int64_t Npad, const double *__restrict__ K, const int64_t *__restrict__ slice_ptr,
+                           const int32_t *__restrict__ col, const uint8_t *__restrict__ rowlen,
+                           const int32_t *__restrict__ diag_slot, const int32_t *__restrict__ fslot,
+                           const int32_t *__restrict__ fpart, double *A, double *B, int *bad)
+{
+    const int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (u >= Npad) return;
+    const int dj = diag_slot[u];
+    if (dj < 0) {  // padding row: its residual is always zero
+        for (int e = 0; e < 6; ++e) A[6 * u + e] = 0.0;
+        return;
+    }
+    double D[9];
+    k_block(K, slice_ptr, u, dj, D);
+    const int k = fslot[u];
+    const int64_t v = k >= 0 ? fpart[k] : -1;
+    int cslot = -1;
+    if (v >= 0) {
+        const int64_t s = u / SLICE, l = u % SLICE, base = slice_ptr[s];
+        for (int j = 0; j < rowlen[u]; ++j)
+            if (col[base + (int64_t)j * SLICE + l] == v) cslot = j;
+    }
+    if (cslot < 0) {
+        double a[9], inv[9];
+        for (int e = 0; e < 9; ++e) a[e] = D[e];
+        if (!small_inverse<3>(a, inv)) *bad = 1;
+        const double sym[6] = {inv[0], inv[4], inv[8], 0.5 * (inv[5] + inv[7]), 0.5 * (inv[2] + inv[6]),
+                               0.5 * (inv[1] + inv[3])};
+        for (int e = 0; e < 6; ++e) A[6 * u + e] = sym[e];
+        if (k >= 0)
+            for (int e = 0; e < 9; ++e) B[9 * k + e] = 0.0;
+        return;
+    }
+    double C[9], Dp[9];
+    k_block(K, slice_ptr, u, cslot, C);
+    k_block(K, slice_ptr, v, diag_slot[v], Dp);
+    double a[36], inv[36];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            a[6 * r + c] = D[3 * r + c];
+            a[6 * r + 3 + c] = C[3 * r + c];
+            a[6 * (3 + r) + c] = C[3 * c + r];  // K is symmetric: the partner row's block is C^T
+            a[6 * (3 + r) + 3 + c] = Dp[3 * r + c];
+        }
+    if (!small_inverse<6>(a, inv)) *bad = 1;
+    const double sym[6] = {inv[0], inv[7], inv[14], 0.5 * (inv[8] + inv[13]), 0.5 * (inv[2] + inv[12]),
+                           0.5 * (inv[1] + inv[6])};
+    for (int e = 0; e < 6; ++e) A[6 * u + e] = sym[e];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) B[9 * k + 3 * r + c] = inv[6 * r + 3 + c];
+}
+
+// z of one unit (a node, or both nodes of a pair) from its residual values rr
+// (rows u and v); writes z, returns r.z.
+__device__ __forceinline__ double bj_unit_z(const BlockJacobi &bj, int64_t u, int64_t v, int ku, int kv,
+                                            const double (&rr)[6], int nr)
+{
+    double rz = 0;
+    for (int m = 0; m < nr; ++m) {
+        const int64_t row = m == 0 ? u : v;
+        const int kk = m == 0 ? ku : kv;
+        const double *a = bj.A + 6 * row;
+        const double *ro = rr + 3 * m, *rp = rr + 3 * (1 - m);
+        for (int c = 0; c < 3; ++c) {
+            double z = symD(a, c, 0) * ro[0] + symD(a, c, 1) * ro[1] + symD(a, c, 2) * ro[2];
+            if (nr == 2) {
+                const double *b = bj.B + 9 * kk + 3 * c;
+                z += b[0] * rp[0] + b[1] * rp[1] + b[2] * rp[2];
+            }
+            bj.z[3 * row + c] = z;
+            rz += ro[c] * z;
+        }
+    }
+    return rz;
+}
+
+// Start of the block-preconditioned CG: z = M^-1 r, p = z, x = 0; partials of r.z, r.r.
+// One thread per unit: a node off the interface pairs, or a pair (taken by its lower row).
+__global__ __launch_bounds__(WG) void k_cg_init_bj(int64_t Npad, BlockJacobi bj, double *__restrict__ x,
+                                                   const double *__restrict__ r, double *__restrict__ p,
+                                                   double *partials, int64_t stride)
+{
+    double v[2] = {0, 0};
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < Npad; u += (int64_t)gridDim.x * blockDim.x) {
+        const int ku = bj.fslot[u];
+        const int64_t w = ku >= 0 ? bj.fpart[ku] : -1;
+        if (w >= 0 && w < u) continue;
+        const int nr = w >= 0 ? 2 : 1;
+        const int kw = w >= 0 ? bj.fslot[w] : -1;
+        double rr[6] = {0, 0, 0, 0, 0, 0};
+        for (int m = 0; m < nr; ++m)
+            for (int c = 0; c < 3; ++c) {
+                const int64_t i = 3 * (m == 0 ? u : w) + c;
+                rr[3 * m + c] = r[i];
+                x[i] = 0.0;
+            }
+        v[0] += bj_unit_z(bj, u, w, ku, kw, rr, nr);
+        for (int m = 0; m < nr; ++m)
+            for (int c = 0; c < 3; ++c) {
+                const int64_t i = 3 * (m == 0 ? u : w) + c;
+                p[i] = bj.z[i];
+                v[1] += rr[3 * m + c] * rr[3 * m + c];
+            }
+    }
+    block_partials<2>(v, partials, stride);
+}
+
+// k_cg_update with the block preconditioner: x, r of a unit updated by the thread
+// that owns it, then z = M^-1 r of the unit from those values (no other thread
+// writes them), stored for k_cg_pupdate_bj.
+__global__ __launch_bounds__(WG) void k_cg_update_bj(int64_t Npad, int par, BlockJacobi bj, double *__restrict__ x,
+                                                     double *__restrict__ r, const double *__restrict__ p,
+                                                     const double *__restrict__ q, double *partials, int64_t stride,
+                                                     int64_t nparts, CgScalars *sc)
+{
+    if (__syncthreads_or(sc->done)) return;
+    double tot[1];
+    finalize_sum<1>(partials, stride, nparts, tot);
+    const double pq = tot[0];
+    const bool ok = isfinite(pq) && pq > 0.0;
+    const double alpha = sc->rho[par] / pq;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->pq = pq;
+        if (!isfinite(pq)) {
+            sc->status = FG_ERR_NAN;
+            sc->done = 1;
+        } else if (!(pq > 0.0)) {
+            sc->status = FG_ERR_BREAKDOWN;
+            sc->done = 1;
+        } else {
+            sc->alpha = alpha;
+        }
+    }
+    if (!ok) return;
+    double v[2] = {0, 0};
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < Npad; u += (int64_t)gridDim.x * blockDim.x) {
+        const int ku = bj.fslot[u];
+        const int64_t w = ku >= 0 ? bj.fpart[ku] : -1;
+        if (w >= 0 && w < u) continue;
+        const int nr = w >= 0 ? 2 : 1;
+        const int kw = w >= 0 ? bj.fslot[w] : -1;
+        double rr[6] = {0, 0, 0, 0, 0, 0};
+        for (int m = 0; m < nr; ++m)
+            for (int c = 0; c < 3; ++c) {
+                const int64_t i = 3 * (m == 0 ? u : w) + c;
+                x[i] += alpha * p[i];
+                const double ri = r[i] - alpha * q[i];
+                r[i] = ri;
+                rr[3 * m + c] = ri;
+                v[1] += ri * ri;
+            }
+        v[0] += bj_unit_z(bj, u, w, ku, kw, rr, nr);
+    }
+    block_partials<2>(v, partials + 2 * stride, stride);
+}
+
+// k_cg_pupdate with the stored z.
+__global__ __launch_bounds__(WG) void k_cg_pupdate_bj(int64_t n, int par, const double *__restrict__ z,
+                                                      double *__restrict__ p, const double *partials, int64_t stride,
+                                                      int64_t nparts, CgScalars *sc)
+{
+    if (__syncthreads_or(sc->done)) return;
+    double tot[2];
+    finalize_sum<2>(partials + 2 * stride, stride, nparts, tot);
+    const int64_t it = sc->iter[par] + 1;
+    const bool finite = isfinite(tot[0]) && isfinite(tot[1]);
+    const bool stop = !finite || tot[1] <= sc->tol2 || it >= sc->maxit;
+    const double beta = tot[0] / sc->rho[par];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->iter[par ^ 1] = it;
+        sc->iters = it;
+        sc->rr = tot[1];
+        sc->rho_cur = sc->rho[par];
+        if (!finite) {
+            sc->status = FG_ERR_NAN;
+            sc->done = 1;
+        } else if (tot[1] <= sc->tol2) {
+            sc->status = FG_OK;
+            sc->done = 1;
+        } else if (it >= sc->maxit) {
+            sc->status = FG_NOT_CONVERGED;
+            sc->done = 1;
+        } else {
+            sc->beta = beta;
+            sc->rho[par ^ 1] = tot[0];
+        }
+    }
+    if (stop) return;
+#pragma unroll 4
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = z[i] + beta * p[i];
+}
+
 // Resumption of a stopped CG after its residual was replaced (reliable update):
 // partials of r.z and r.r of the new residual, then the scalars (beta against the
 // rho at which the iteration stopped, the next stop threshold, parity slot 0),
@@ -1041,6 +1287,7 @@ void assemble_all(fg_system *S, const double *E, const double *logk, hipStream_t
 
 void stick_tangent(fg_system *S, hipStream_t st)
 {
+    S->bj_valid = false;
     if (S->nq == 0) return;
     LAUNCH(k_stick_tangent, (S->nq + WG - 1) / WG, WG, st, S->nq, S->coh, S->tri_geo, S->gprm, S->slice_group,
            S->qpD);
@@ -1064,6 +1311,7 @@ void cohesive_qp(fg_system *S, const double *U_int, const double *die_n, const d
 
 void cohesive_rows(fg_system *S, double *fcoh_int, int write_tangent, hipStream_t st)
 {
+    if (write_tangent) S->bj_valid = false;
     vfill(fcoh_int, 0.0, 3 * S->Npad, st);
     if (S->nq == 0) return;
     LAUNCH(k_cohesive_force, (S->nfr + WG - 1) / WG, WG, st, S->nfr, S->frows, S->fadj_ptr, S->fadj, S->tri_geo,
@@ -1209,6 +1457,14 @@ static void cg_launch_batch(fg_system *S, const TV *val, const T *dinv, T *x, T 
         if (prof) hipEventRecord(ev[2 * it], st);
         cg_spmv_launch<BS, T, TV>(S, gs, val, p, q, st);
         if (prof) hipEventRecord(ev[2 * it + 1], st);
+        if constexpr (BS == 3 && std::is_same<T, double>::value && std::is_same<TV, double>::value) {
+            if (S->k_precond) {
+                const BlockJacobi bj{S->bjA, S->bjB, S->fslot, S->fpart, S->wz};
+                LAUNCH(k_cg_update_bj, ge, WG, st, S->Npad, par, bj, x, r, p, q, S->partials, S->npartials, gs, S->sc);
+                LAUNCH(k_cg_pupdate_bj, ge, WG, st, n, par, S->wz, p, S->partials, S->npartials, ge, S->sc);
+                continue;
+            }
+        }
         LAUNCH((k_cg_update<T>), ge, WG, st, n, par, dinv, x, r, p, q, S->partials, S->npartials, gs, S->sc);
         LAUNCH((k_cg_pupdate<T>), ge, WG, st, n, par, dinv, r, p, S->partials, S->npartials, ge, S->sc);
     }
@@ -1271,6 +1527,21 @@ void drop_graphs(fg_system *S)
     }
 }
 
+// Block-Jacobi data of the current K, built on first use after K changed.
+void bj_ready(fg_system *S, hipStream_t st)
+{
+    if (S->bj_valid) return;
+    int *bad = (int *)S->red_counter + 2;
+    hipMemsetAsync(bad, 0, sizeof(int), st);
+    LAUNCH(k_bj_build, (S->Npad + WG - 1) / WG, WG, st, S->Npad, S->K, S->slice_ptr, S->col, S->rowlen, S->diag_slot,
+           S->fslot, S->fpart, S->bjA, S->bjB, bad);
+    int h = 0;
+    hipMemcpyAsync(&h, bad, sizeof(int), hipMemcpyDeviceToHost, st);
+    hipStreamSynchronize(st);
+    S->bj_singular = h != 0;
+    S->bj_valid = true;
+}
+
 // Batches of CG iterations on the state the init (or a resume) left, polled every
 // check_every iterations until the device-side stop flag is set.
 static fg_status cg_loop(fg_system *S, int which, int precision, int check_every, hipStream_t st)
@@ -1319,6 +1590,10 @@ static void cg_init(fg_system *S, int which, int precision, double tol, int64_t 
         if (!S->k32_valid) refresh_k32(S, st);
     if (f32) {
         LAUNCH((k_cg_init<float>), grid_elems(n), WG, st, n, S->dinvK32, S->fx, S->fr, S->fp, S->partials, S->npartials);
+    } else if (which == FG_K && !f32val && S->k_precond) {
+        bj_ready(S, st);
+        const BlockJacobi bj{S->bjA, S->bjB, S->fslot, S->fpart, S->wz};
+        LAUNCH(k_cg_init_bj, grid_elems(n), WG, st, S->Npad, bj, S->wx, S->wr, S->wp, S->partials, S->npartials);
     } else if (which == FG_K) {
         LAUNCH((k_cg_init<double>), grid_elems(n), WG, st, n, S->dinvK, S->wx, S->wr, S->wp, S->partials, S->npartials);
     } else {
@@ -1334,6 +1609,10 @@ fg_status cg_run(fg_system *S, int which, int precision, double tol, int64_t max
     cg_init(S, which, precision, tol, maxit, st);
     fg_status e = check_hip("cg init");
     if (e) return e;
+    if (which == FG_K && precision == FG_F64 && S->k_precond && S->bj_singular) {
+        set_error("fg_pcg_solve: a diagonal or fault-pair block of K is singular (block Jacobi)");
+        return FG_ERR_BREAKDOWN;
+    }
     e = cg_loop(S, which, precision, check_every, st);
     const CgScalars &h = *S->sc_host;
     *iters = h.iters;

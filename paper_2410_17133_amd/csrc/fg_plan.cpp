@@ -327,6 +327,25 @@ fg_status build_plan(const fg_mesh &m, Plan &P, std::string &err)
         P.fadj.resize(P.fadj_ptr.back());
         std::vector<int32_t> pos(P.fadj_ptr.begin(), P.fadj_ptr.end() - 1);
         for (int64_t i = 0; i < nf * 6; ++i) P.fadj[pos[is_f[P.coh[i]]]++] = (int32_t)i;
+        // the two lips' nodes at the same point pair up; a node met with two
+        // different partners keeps none (its block stays 3x3)
+        P.fslot = is_f;
+        P.fpart.assign(P.frows.size(), -1);
+        std::vector<uint8_t> bad(P.frows.size(), 0);
+        for (int64_t t = 0; t < nf; ++t)
+            for (int a = 0; a < 3; ++a) {
+                const int32_t u = P.coh[6 * t + a], v = P.coh[6 * t + 3 + a];
+                for (int side = 0; side < 2; ++side) {
+                    const int32_t x = side ? v : u, y = side ? u : v;
+                    const int32_t k = is_f[x];
+                    if (P.fpart[k] >= 0 && P.fpart[k] != y) bad[k] = 1;
+                    P.fpart[k] = y;
+                }
+            }
+        for (size_t k = 0; k < P.frows.size(); ++k)
+            if (bad[k] || P.fpart[k] == P.frows[k]) P.fpart[k] = -1;
+        for (size_t k = 0; k < P.frows.size(); ++k)   // keep the map symmetric
+            if (P.fpart[k] >= 0 && P.fpart[is_f[P.fpart[k]]] != P.frows[k]) P.fpart[k] = -1;
     }
 
     P.dir_u.assign(3 * P.Npad, 0);

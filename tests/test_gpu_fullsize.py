@@ -65,6 +65,7 @@ def test_interface_update_full_size(full):
 def test_products_full_size(full):
     S, P, O, fg = full["S"], full["P"], full["O"], full["fg"]
     P.cohesive(full["U"], full["die"])          # tangent of the same state on both sides
+    S.cohesive_update(dev(full["U"]), dev(np.zeros(2 * S.nq)), dev(full["inst"].t0.reshape(-1)))
     r = np.random.default_rng(7)
     for which_g, which_o, bs in ((fg.FG_K, O.K_TANGENT, 3), (fg.FG_KBULK, O.K_BULK, 3), (fg.FG_A22, O.A22, 1),
                                  (fg.FG_C, O.C_FLOW, 1)):
@@ -84,6 +85,7 @@ def test_mixed_precision_solve_full_size(full):
     1e-8 residual measured with the oracle's FP64 product, close to the FP64 solution."""
     S, P, O, fg, inst = full["S"], full["P"], full["O"], full["fg"], full["inst"]
     P.cohesive(full["U"], full["die"])
+    S.cohesive_update(dev(full["U"]), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)))   # the same tangent
     b = np.random.default_rng(9).standard_normal(3 * S.N) * (1 - inst.dir_u)
     xm, im = S.pcg_solve(fg.FG_K, dev(b), tol=1e-8, precision=fg.FG_MIXED, check_every=64)
     x64, i64 = S.pcg_solve(fg.FG_K, dev(b), tol=1e-8, check_every=64)
@@ -100,6 +102,7 @@ def test_pcg_iterates_full_size(full):
     iterate (graph-replayed batches, default knobs) equals the oracle's."""
     S, P, O, fg, inst = full["S"], full["P"], full["O"], full["fg"], full["inst"]
     P.cohesive(full["U"], full["die"])
+    S.cohesive_update(dev(full["U"]), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)))   # the same tangent
     r = np.random.default_rng(8)
     b = r.standard_normal(3 * S.N) * (1 - inst.dir_u)
     x, info = S.pcg_solve(fg.FG_K, dev(b), tol=1e-300, max_iter=50, check_every=64)
@@ -112,6 +115,15 @@ def test_pcg_iterates_full_size(full):
     xp, ip = S.pcg_solve(fg.FG_A22, dev(bp), tol=1e-300, max_iter=50, check_every=64)
     xpo, st, it, rr = P.pcg(O.A22, bp, tol=1e-300, maxit=50)
     assert relerr(host(xp), xpo) < 1e-10
+    # block-Jacobi K preconditioner (nodal 3x3, fault-pair 6x6): the same iterates too
+    S.tune("k_precond", 1)
+    try:
+        xb, ib = S.pcg_solve(fg.FG_K, dev(b), tol=1e-300, max_iter=50, check_every=64)
+    finally:
+        S.tune("k_precond", 0)
+    xbo, st, it, rr = P.pcg_block(b, tol=1e-300, maxit=50)
+    print(f"[pcg K block Jacobi] rel {relerr(host(xb), xbo):.2e}", flush=True)
+    assert ib.iters == it == 50 and relerr(host(xb), xbo) < 1e-10
 
 
 def test_adjoint_identities_full_size(full):

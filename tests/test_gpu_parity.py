@@ -166,6 +166,66 @@ def test_pcg_k_and_a22(name):
     assert relerr(host(xp), xpo) < 1e-9
 
 
+@pytest.mark.parametrize("name", ["cube2", "cube12_dip60_hetero", "cube10_dip35_hetero"])
+def test_pcg_block_jacobi_matches_oracle(name):
+    """fg_tune k_precond 1: the same 50 PCG iterates as the oracle's block-Jacobi CG
+    (nodal 3x3 and fault-pair 6x6 inverse blocks), the same converged solution as
+    point Jacobi, in fewer iterations; the tangent rewritten by an interface update
+    rebuilds the blocks."""
+    fg, O = _fg(), _oracle()
+    inst, ctx, S, P = setup(name)
+    print(f"[case] block Jacobi {name}", flush=True)
+    r = np.random.default_rng(12)
+    U = r.normal(0.0, 2e-5 / inst.cfg.n, 3 * S.N) * (1 - inst.dir_u)    # stick, slip and open points
+    P.cohesive(U, np.zeros((P.nq, 2)))
+    S.cohesive_update(dev(U), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)))
+    b = r.standard_normal(3 * S.N) * (1 - inst.dir_u)
+    x0, i0 = S.pcg_solve(fg.FG_K, dev(b), tol=1e-12)
+    S.tune("k_precond", 1)
+    try:
+        x50, i50 = S.pcg_solve(fg.FG_K, dev(b), tol=1e-300, max_iter=50)
+        xo, st, it, rr = P.pcg_block(b, tol=1e-300, maxit=50)
+        assert i50.iters == it == 50
+        assert relerr(host(x50), xo) < 1e-10
+        x1, i1 = S.pcg_solve(fg.FG_K, dev(b), tol=1e-12)
+        xo1, st, it1, rr = P.pcg_block(b, tol=1e-12)
+        print(f"[block Jacobi] point {i0.iters} block {i1.iters} (oracle {it1}) iterations", flush=True)
+        assert i1.status == 0 and abs(i1.iters - it1) <= max(3, 0.02 * it1)
+        assert relerr(host(x1), xo1) < 1e-9 and relerr(host(x1), host(x0)) < 1e-9
+        if name != "cube2":
+            assert i1.iters < 0.6 * i0.iters
+        # a new tangent: the blocks follow it
+        P.cohesive(np.zeros(3 * P.N), np.zeros((P.nq, 2)))
+        S.cohesive_update(dev(np.zeros(3 * S.N)), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)))
+        x2, i2 = S.pcg_solve(fg.FG_K, dev(b), tol=1e-300, max_iter=50)
+        xo2, st, it2, rr = P.pcg_block(b, tol=1e-300, maxit=50)
+        assert relerr(host(x2), xo2) < 1e-10
+    finally:
+        S.tune("k_precond", 0)
+    with pytest.raises(fg.FgError):
+        S.tune("k_precond", 2)
+
+
+def test_step_with_block_jacobi_reaches_the_same_state():
+    """A full implicit step (Newton, partitioned CG) with block-Jacobi K solves ends
+    in the oracle's converged state."""
+    fg, O = _fg(), _oracle()
+    inst, ctx, S, P = setup("cube8")
+    N, nq = S.N, S.nq
+    Uo, Po, dieo = np.zeros(3 * N), np.zeros(N), np.zeros((nq, 2))
+    P.step(Uo, Po, dieo, tol_newton=1e-11, max_newton=40, tol_outer=1e-12, tol_inner=1e-13)
+    S.tune("k_precond", 1)
+    try:
+        U, Pp, die = dev(np.zeros(3 * N)), dev(np.zeros(N)), dev(np.zeros(2 * nq))
+        trac, flag, info = S.step(U, Pp, die, dev(inst.t0.reshape(-1)), dev(inst.load), dev(inst.source),
+                                  newton_tol=1e-11, newton_max_iter=40, inner_k=fg.opts(tol=1e-13),
+                                  inner_p=fg.opts(tol=1e-13), outer_tol=1e-12)
+    finally:
+        S.tune("k_precond", 0)
+    assert info.status == 0
+    assert relerr(host(U), Uo) < 1e-9 and relerr(host(Pp), Po) < 1e-9
+
+
 def test_pcg_global_gather_path_matches():
     fg, O = _fg(), _oracle()
     inst, ctx, S, P = setup("cube16_dip70")
