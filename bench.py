@@ -194,7 +194,7 @@ def main():
         b = S.coupling(z)
         res = {}
         for name, prec in (("f64", fg.FG_F64), ("mixed", fg.FG_MIXED), ("mixed_f32val", fg.FG_MIXED_F32VAL),
-                           ("f64_block_jacobi", fg.FG_F64)):
+                           ("f64_block_jacobi", fg.FG_F64), ("mixed_block_jacobi", fg.FG_MIXED)):
             if name == "f64_block_jacobi":
                 S.tune("k_precond", 1)
                 S.pcg_solve(fg.FG_K, b, tol=1e-8, check_every=64)                 # blocks built, graphs captured
@@ -219,7 +219,14 @@ def main():
                                "f64_block_jacobi_iters": res["f64_block_jacobi"][1],
                                "block_jacobi_vs_f64_rel_l2": (torch.linalg.norm(res["f64_block_jacobi"][3] - res["f64"][3])
                                                               / torch.linalg.norm(res["f64"][3])).item(),
-                               "speedup_block_jacobi": res["f64"][0] / res["f64_block_jacobi"][0]}
+                               "speedup_block_jacobi": res["f64"][0] / res["f64_block_jacobi"][0],
+                               "mixed_block_jacobi_s": res["mixed_block_jacobi"][0],
+                               "mixed_block_jacobi_iters": res["mixed_block_jacobi"][1],
+                               "mixed_block_jacobi_cycles": res["mixed_block_jacobi"][2],
+                               "mixed_block_jacobi_vs_f64_rel_l2": (
+                                   torch.linalg.norm(res["mixed_block_jacobi"][3] - res["f64"][3])
+                                   / torch.linalg.norm(res["f64"][3])).item(),
+                               "speedup_mixed_block_jacobi": res["f64"][0] / res["mixed_block_jacobi"][0]}
 
     del S
     torch.cuda.empty_cache()

@@ -384,7 +384,7 @@ fg_status fg_system_destroy(fg_system *S)
                     S->fr, S->fp, S->fq, S->v1, S->v2, S->v3, S->v4, S->pv1, S->pv2, S->ui, S->ui0, S->fi, S->rm,
                     S->du, S->fc, S->s1, S->s2, S->s3, S->s4, S->s5, S->s6, S->s7, S->s8, S->pi, S->pi0, S->qi,
                     S->rf, S->dpv, S->die0, S->partials, S->sc, S->red, S->red_counter, S->fslot, S->fpart,
-                    S->bjA, S->bjB, S->wz};
+                    S->bjA, S->bjB, S->wz, S->bjA32, S->bjB32, S->wz32};
     for (void *p : ptrs) dfree(p);
     drop_graphs(S);
     drop_mr_graphs(S);
@@ -586,7 +586,7 @@ fg_status fg_assemble_groups(fg_ctx *ctx, fg_system *S, const fg_params *prm, in
         return check_hip("fg_assemble parameters");
     S->prm = prm[0];
     S->k32_valid = false;
-    S->bj_valid = false;
+    S->bj_valid = S->bj32_valid = false;
     assemble_all(S, E, log_k, st);
     TRY(check_hip("fg_assemble"));
     int bad = 0;
@@ -1091,7 +1091,8 @@ fg_status fg_tune(fg_system *S, const char *key, int64_t value)
         }
         if (value == 1 && !S->bjA) {
             if (dalloc(&S->bjA, 6 * S->Npad) || dalloc(&S->bjB, 9 * std::max<int64_t>(S->nfr, 1)) ||
-                dalloc(&S->wz, 3 * S->Npad)) {
+                dalloc(&S->wz, 3 * S->Npad) || dalloc(&S->bjA32, 6 * S->Npad) ||
+                dalloc(&S->bjB32, 9 * std::max<int64_t>(S->nfr, 1)) || dalloc(&S->wz32, 3 * S->Npad)) {
                 set_error("fg_tune: device allocation for the block-Jacobi preconditioner failed");
                 return FG_ERR_OOM;
             }

@@ -133,6 +133,8 @@ struct fg_system {
     double *bjA = nullptr;      // [Npad*6] symmetric 3x3 inverse blocks, xx yy zz yz xz xy
     double *bjB = nullptr;      // [nfr*9] pair coupling blocks of the inverse, row-major
     double *wz = nullptr;       // [3*Npad] z = M^-1 r of the block-preconditioned CG
+    float *bjA32 = nullptr, *bjB32 = nullptr, *wz32 = nullptr;  // FP32 copies (FP32 CG of the mixed mode)
+    bool bj32_valid = false;
     bool bj_valid = false;      // bjA/bjB built from the current K
     bool bj_singular = false;   // the last build met a singular block
     int k_precond = 0;          // fg_tune "k_precond": 0 point Jacobi, 1 nodal + fault-pair block Jacobi

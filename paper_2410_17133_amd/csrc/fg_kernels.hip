@@ -892,12 +892,13 @@ __global__ __launch_bounds__(WG) void k_cg_pupdate(int64_t n, int par, const T *
 // the pair (their diagonal blocks and the coupling the penalty stiffness puts
 // between them), inverted.  Row u keeps the symmetric 3x3 part A_u of its inverse
 // and, on the interface, the coupling part B_u (z_u = A_u r_u + B_u r_partner).
+template <typename T>
 struct BlockJacobi {
-    const double *A;       // [Npad*6] xx yy zz yz xz xy
-    const double *B;       // [nfr*9] row-major
+    const T *A;            // [Npad*6] xx yy zz yz xz xy
+    const T *B;            // [nfr*9] row-major
     const int32_t *fslot;  // [Npad] index into the fault rows, -1 off the interface
     const int32_t *fpart;  // [nfr] partner row, -1 if none
-    double *z;             // [3*Npad]
+    T *z;                  // [3*Npad]
 };
 
 // In-place inverse of an n x n matrix (row-major, n <= 6), Gauss-Jordan with
@@ -991,23 +992,33 @@ __global__ void k_bj_build(int64_t Npad, const double *__restrict__ K, const int
 
 // z of one unit (a node, or both nodes of a pair) from its residual values rr
 // (rows u and v); writes z, returns r.z.
-__device__ __forceinline__ double bj_unit_z(const BlockJacobi &bj, int64_t u, int64_t v, int ku, int kv,
-                                            const double (&rr)[6], int nr)
+template <typename T>
+__device__ __forceinline__ T symT(const T *d, int r, int c)
+{
+    // xx yy zz yz xz xy
+    if (r == c) return d[r];
+    const int s = r + c;  // 1: xy, 2: xz, 3: yz
+    return s == 3 ? d[3] : (s == 2 ? d[4] : d[5]);
+}
+
+template <typename T>
+__device__ __forceinline__ double bj_unit_z(const BlockJacobi<T> &bj, int64_t u, int64_t v, int ku, int kv,
+                                            const T (&rr)[6], int nr)
 {
     double rz = 0;
     for (int m = 0; m < nr; ++m) {
         const int64_t row = m == 0 ? u : v;
         const int kk = m == 0 ? ku : kv;
-        const double *a = bj.A + 6 * row;
-        const double *ro = rr + 3 * m, *rp = rr + 3 * (1 - m);
+        const T *a = bj.A + 6 * row;
+        const T *ro = rr + 3 * m, *rp = rr + 3 * (1 - m);
         for (int c = 0; c < 3; ++c) {
-            double z = symD(a, c, 0) * ro[0] + symD(a, c, 1) * ro[1] + symD(a, c, 2) * ro[2];
+            T z = symT(a, c, 0) * ro[0] + symT(a, c, 1) * ro[1] + symT(a, c, 2) * ro[2];
             if (nr == 2) {
-                const double *b = bj.B + 9 * kk + 3 * c;
+                const T *b = bj.B + 9 * kk + 3 * c;
                 z += b[0] * rp[0] + b[1] * rp[1] + b[2] * rp[2];
             }
             bj.z[3 * row + c] = z;
-            rz += ro[c] * z;
+            rz += (double)ro[c] * (double)z;
         }
     }
     return rz;
@@ -1015,9 +1026,12 @@ __device__ __forceinline__ double bj_unit_z(const BlockJacobi &bj, int64_t u, in
 
 // Start of the block-preconditioned CG: z = M^-1 r, p = z, x = 0; partials of r.z, r.r.
 // One thread per unit: a node off the interface pairs, or a pair (taken by its lower row).
-__global__ __launch_bounds__(WG) void k_cg_init_bj(int64_t Npad, BlockJacobi bj, double *__restrict__ x,
-                                                   const double *__restrict__ r, double *__restrict__ p,
-                                                   double *partials, int64_t stride)
+// With x == nullptr (a resumption after a residual replacement) only z and the
+// partials are formed.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_cg_init_bj(int64_t Npad, BlockJacobi<T> bj, T *__restrict__ x,
+                                                   const T *__restrict__ r, T *__restrict__ p, double *partials,
+                                                   int64_t stride)
 {
     double v[2] = {0, 0};
     for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < Npad; u += (int64_t)gridDim.x * blockDim.x) {
@@ -1026,19 +1040,19 @@ __global__ __launch_bounds__(WG) void k_cg_init_bj(int64_t Npad, BlockJacobi bj,
         if (w >= 0 && w < u) continue;
         const int nr = w >= 0 ? 2 : 1;
         const int kw = w >= 0 ? bj.fslot[w] : -1;
-        double rr[6] = {0, 0, 0, 0, 0, 0};
+        T rr[6] = {0, 0, 0, 0, 0, 0};
         for (int m = 0; m < nr; ++m)
             for (int c = 0; c < 3; ++c) {
                 const int64_t i = 3 * (m == 0 ? u : w) + c;
                 rr[3 * m + c] = r[i];
-                x[i] = 0.0;
+                if (x) x[i] = 0;
             }
         v[0] += bj_unit_z(bj, u, w, ku, kw, rr, nr);
         for (int m = 0; m < nr; ++m)
             for (int c = 0; c < 3; ++c) {
                 const int64_t i = 3 * (m == 0 ? u : w) + c;
-                p[i] = bj.z[i];
-                v[1] += rr[3 * m + c] * rr[3 * m + c];
+                if (x) p[i] = bj.z[i];
+                v[1] += (double)rr[3 * m + c] * (double)rr[3 * m + c];
             }
     }
     block_partials<2>(v, partials, stride);
@@ -1047,9 +1061,10 @@ __global__ __launch_bounds__(WG) void k_cg_init_bj(int64_t Npad, BlockJacobi bj,
 // k_cg_update with the block preconditioner: x, r of a unit updated by the thread
 // that owns it, then z = M^-1 r of the unit from those values (no other thread
 // writes them), stored for k_cg_pupdate_bj.
-__global__ __launch_bounds__(WG) void k_cg_update_bj(int64_t Npad, int par, BlockJacobi bj, double *__restrict__ x,
-                                                     double *__restrict__ r, const double *__restrict__ p,
-                                                     const double *__restrict__ q, double *partials, int64_t stride,
+template <typename T>
+__global__ __launch_bounds__(WG) void k_cg_update_bj(int64_t Npad, int par, BlockJacobi<T> bj, T *__restrict__ x,
+                                                     T *__restrict__ r, const T *__restrict__ p,
+                                                     const T *__restrict__ q, double *partials, int64_t stride,
                                                      int64_t nparts, CgScalars *sc)
 {
     if (__syncthreads_or(sc->done)) return;
@@ -1071,6 +1086,7 @@ __global__ __launch_bounds__(WG) void k_cg_update_bj(int64_t Npad, int par, Bloc
         }
     }
     if (!ok) return;
+    const T al = (T)alpha;
     double v[2] = {0, 0};
     for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < Npad; u += (int64_t)gridDim.x * blockDim.x) {
         const int ku = bj.fslot[u];
@@ -1078,15 +1094,15 @@ __global__ __launch_bounds__(WG) void k_cg_update_bj(int64_t Npad, int par, Bloc
         if (w >= 0 && w < u) continue;
         const int nr = w >= 0 ? 2 : 1;
         const int kw = w >= 0 ? bj.fslot[w] : -1;
-        double rr[6] = {0, 0, 0, 0, 0, 0};
+        T rr[6] = {0, 0, 0, 0, 0, 0};
         for (int m = 0; m < nr; ++m)
             for (int c = 0; c < 3; ++c) {
                 const int64_t i = 3 * (m == 0 ? u : w) + c;
-                x[i] += alpha * p[i];
-                const double ri = r[i] - alpha * q[i];
+                x[i] += al * p[i];
+                const T ri = r[i] - al * q[i];
                 r[i] = ri;
                 rr[3 * m + c] = ri;
-                v[1] += ri * ri;
+                v[1] += (double)ri * (double)ri;
             }
         v[0] += bj_unit_z(bj, u, w, ku, kw, rr, nr);
     }
@@ -1094,8 +1110,9 @@ __global__ __launch_bounds__(WG) void k_cg_update_bj(int64_t Npad, int par, Bloc
 }
 
 // k_cg_pupdate with the stored z.
-__global__ __launch_bounds__(WG) void k_cg_pupdate_bj(int64_t n, int par, const double *__restrict__ z,
-                                                      double *__restrict__ p, const double *partials, int64_t stride,
+template <typename T>
+__global__ __launch_bounds__(WG) void k_cg_pupdate_bj(int64_t n, int par, const T *__restrict__ z,
+                                                      T *__restrict__ p, const double *partials, int64_t stride,
                                                       int64_t nparts, CgScalars *sc)
 {
     if (__syncthreads_or(sc->done)) return;
@@ -1125,9 +1142,21 @@ __global__ __launch_bounds__(WG) void k_cg_pupdate_bj(int64_t n, int par, const 
         }
     }
     if (stop) return;
+    const T be = (T)beta;
 #pragma unroll 4
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = z[i] + beta * p[i];
+        p[i] = z[i] + be * p[i];
+}
+
+// p = z + beta p after a residual replacement (k_cg_resume_p with the stored z).
+template <typename T>
+__global__ __launch_bounds__(WG) void k_cg_resume_p_bj(int64_t n, const T *__restrict__ z, T *__restrict__ p,
+                                                       const CgScalars *sc)
+{
+    if (sc->done) return;
+    const T be = (T)sc->beta;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = z[i] + be * p[i];
 }
 
 // Resumption of a stopped CG after its residual was replaced (reliable update):
@@ -1287,7 +1316,7 @@ void assemble_all(fg_system *S, const double *E, const double *logk, hipStream_t
 
 void stick_tangent(fg_system *S, hipStream_t st)
 {
-    S->bj_valid = false;
+    S->bj_valid = S->bj32_valid = false;
     if (S->nq == 0) return;
     LAUNCH(k_stick_tangent, (S->nq + WG - 1) / WG, WG, st, S->nq, S->coh, S->tri_geo, S->gprm, S->slice_group,
            S->qpD);
@@ -1311,7 +1340,7 @@ void cohesive_qp(fg_system *S, const double *U_int, const double *die_n, const d
 
 void cohesive_rows(fg_system *S, double *fcoh_int, int write_tangent, hipStream_t st)
 {
-    if (write_tangent) S->bj_valid = false;
+    if (write_tangent) S->bj_valid = S->bj32_valid = false;
     vfill(fcoh_int, 0.0, 3 * S->Npad, st);
     if (S->nq == 0) return;
     LAUNCH(k_cohesive_force, (S->nfr + WG - 1) / WG, WG, st, S->nfr, S->frows, S->fadj_ptr, S->fadj, S->tri_geo,
@@ -1444,6 +1473,19 @@ static void cg_spmv_launch(fg_system *S, int64_t gs, const TV *val, const T *p, 
 #undef FG_CG_SPMV_W
 }
 
+template <typename T>
+static BlockJacobi<T> bj_args(fg_system *S);
+template <>
+BlockJacobi<double> bj_args<double>(fg_system *S)
+{
+    return BlockJacobi<double>{S->bjA, S->bjB, S->fslot, S->fpart, S->wz};
+}
+template <>
+BlockJacobi<float> bj_args<float>(fg_system *S)
+{
+    return BlockJacobi<float>{S->bjA32, S->bjB32, S->fslot, S->fpart, S->wz32};
+}
+
 template <int BS, typename T, typename TV>
 static void cg_launch_batch(fg_system *S, const TV *val, const T *dinv, T *x, T *r, T *p, T *q, int iters, int slot,
                             bool prof, hipStream_t st)
@@ -1457,11 +1499,12 @@ static void cg_launch_batch(fg_system *S, const TV *val, const T *dinv, T *x, T 
         if (prof) hipEventRecord(ev[2 * it], st);
         cg_spmv_launch<BS, T, TV>(S, gs, val, p, q, st);
         if (prof) hipEventRecord(ev[2 * it + 1], st);
-        if constexpr (BS == 3 && std::is_same<T, double>::value && std::is_same<TV, double>::value) {
+        if constexpr (BS == 3 && std::is_same<T, TV>::value) {
             if (S->k_precond) {
-                const BlockJacobi bj{S->bjA, S->bjB, S->fslot, S->fpart, S->wz};
-                LAUNCH(k_cg_update_bj, ge, WG, st, S->Npad, par, bj, x, r, p, q, S->partials, S->npartials, gs, S->sc);
-                LAUNCH(k_cg_pupdate_bj, ge, WG, st, n, par, S->wz, p, S->partials, S->npartials, ge, S->sc);
+                const BlockJacobi<T> bj = bj_args<T>(S);
+                LAUNCH((k_cg_update_bj<T>), ge, WG, st, S->Npad, par, bj, x, r, p, q, S->partials, S->npartials, gs,
+                       S->sc);
+                LAUNCH((k_cg_pupdate_bj<T>), ge, WG, st, n, par, bj.z, p, S->partials, S->npartials, ge, S->sc);
                 continue;
             }
         }
@@ -1540,6 +1583,17 @@ void bj_ready(fg_system *S, hipStream_t st)
     hipStreamSynchronize(st);
     S->bj_singular = h != 0;
     S->bj_valid = true;
+    S->bj32_valid = false;
+}
+
+// FP32 copy of the block-Jacobi data (FP32 CG of the mixed-precision solve).
+void bj_ready32(fg_system *S, hipStream_t st)
+{
+    bj_ready(S, st);
+    if (S->bj32_valid) return;
+    to_f32(6 * S->Npad, 1.0, S->bjA, S->bjA32, st);
+    if (S->nfr > 0) to_f32(9 * S->nfr, 1.0, S->bjB, S->bjB32, st);
+    S->bj32_valid = true;
 }
 
 // Batches of CG iterations on the state the init (or a resume) left, polled every
@@ -1588,12 +1642,16 @@ static void cg_init(fg_system *S, int which, int precision, double tol, int64_t 
     const bool f32val = (which == FG_K && precision == FG_MIXED_F32VAL);
     if (f32 || f32val)
         if (!S->k32_valid) refresh_k32(S, st);
-    if (f32) {
+    if (f32 && S->k_precond) {
+        bj_ready32(S, st);
+        LAUNCH((k_cg_init_bj<float>), grid_elems(n), WG, st, S->Npad, bj_args<float>(S), S->fx, S->fr, S->fp,
+               S->partials, S->npartials);
+    } else if (f32) {
         LAUNCH((k_cg_init<float>), grid_elems(n), WG, st, n, S->dinvK32, S->fx, S->fr, S->fp, S->partials, S->npartials);
     } else if (which == FG_K && !f32val && S->k_precond) {
         bj_ready(S, st);
-        const BlockJacobi bj{S->bjA, S->bjB, S->fslot, S->fpart, S->wz};
-        LAUNCH(k_cg_init_bj, grid_elems(n), WG, st, S->Npad, bj, S->wx, S->wr, S->wp, S->partials, S->npartials);
+        LAUNCH((k_cg_init_bj<double>), grid_elems(n), WG, st, S->Npad, bj_args<double>(S), S->wx, S->wr, S->wp,
+               S->partials, S->npartials);
     } else if (which == FG_K) {
         LAUNCH((k_cg_init<double>), grid_elems(n), WG, st, n, S->dinvK, S->wx, S->wr, S->wp, S->partials, S->npartials);
     } else {
@@ -1609,7 +1667,7 @@ fg_status cg_run(fg_system *S, int which, int precision, double tol, int64_t max
     cg_init(S, which, precision, tol, maxit, st);
     fg_status e = check_hip("cg init");
     if (e) return e;
-    if (which == FG_K && precision == FG_F64 && S->k_precond && S->bj_singular) {
+    if (which == FG_K && (precision == FG_F64 || precision == FG_F32) && S->k_precond && S->bj_singular) {
         set_error("fg_pcg_solve: a diagonal or fault-pair block of K is singular (block Jacobi)");
         return FG_ERR_BREAKDOWN;
     }
@@ -1671,9 +1729,17 @@ fg_status cg_reliable(fg_system *S, const double *b, double *x, double tol, int6
         if (s == FG_NOT_CONVERGED || *iters >= maxit) return FG_NOT_CONVERGED;
         to_f32(n, 1.0 / bn, r, S->fr, st);
         const double next = std::max(delta * rel, 0.5 * tol);
-        LAUNCH((k_cg_resume<float>), grid_elems(n), WG, st, n, S->dinvK32, S->fr, S->partials, S->npartials);
-        LAUNCH(k_cg_resume_fin, 1, FIN, st, S->partials, S->npartials, grid_elems(n), S->sc, next * next);
-        LAUNCH((k_cg_resume_p<float>), grid_elems(n), WG, st, n, S->dinvK32, S->fr, S->fp, S->sc);
+        if (S->k_precond) {
+            const BlockJacobi<float> bj = bj_args<float>(S);
+            LAUNCH((k_cg_init_bj<float>), grid_elems(n), WG, st, S->Npad, bj, (float *)nullptr, S->fr, (float *)nullptr,
+                   S->partials, S->npartials);
+            LAUNCH(k_cg_resume_fin, 1, FIN, st, S->partials, S->npartials, grid_elems(n), S->sc, next * next);
+            LAUNCH((k_cg_resume_p_bj<float>), grid_elems(n), WG, st, n, bj.z, S->fp, S->sc);
+        } else {
+            LAUNCH((k_cg_resume<float>), grid_elems(n), WG, st, n, S->dinvK32, S->fr, S->partials, S->npartials);
+            LAUNCH(k_cg_resume_fin, 1, FIN, st, S->partials, S->npartials, grid_elems(n), S->sc, next * next);
+            LAUNCH((k_cg_resume_p<float>), grid_elems(n), WG, st, n, S->dinvK32, S->fr, S->fp, S->sc);
+        }
         e = check_hip("mixed cg resume");
         if (e) return e;
     }

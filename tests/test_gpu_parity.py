@@ -194,6 +194,11 @@ def test_pcg_block_jacobi_matches_oracle(name):
         assert relerr(host(x1), xo1) < 1e-9 and relerr(host(x1), host(x0)) < 1e-9
         if name != "cube2":
             assert i1.iters < 0.6 * i0.iters
+        # the FP32 CG of the mixed mode with the same blocks (in FP32), FP64 residual replacement
+        xm, im = S.pcg_solve(fg.FG_K, dev(b), tol=1e-9, precision=fg.FG_MIXED)
+        assert im.status == 0
+        assert np.linalg.norm(b - P.spmv(O.K_TANGENT, host(xm))) <= 1e-9 * np.linalg.norm(b)
+        print(f"[block Jacobi] mixed: {im.iters} FP32 iterations, {im.cycles} replacements", flush=True)
         # a new tangent: the blocks follow it
         P.cohesive(np.zeros(3 * P.N), np.zeros((P.nq, 2)))
         S.cohesive_update(dev(np.zeros(3 * S.N)), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)))
