@@ -1324,14 +1324,21 @@ static double csr_at(const or_csr *A, int64_t row, int64_t col)
     return 0.0;
 }
 
-/* PCG on the current tangent K_t with a block-Jacobi preconditioner: the inverse
- * of the 3x3 diagonal block of every node, except that the two lips' nodes at the
- * same interface point (+a, -a of an interface element) share the inverse of their
- * 6x6 block.  Same recurrence and stop test as or_pcg. */
-int or_pcg_block(or_problem *P, const double *b, double *x, double tol, int64_t maxit, int64_t *iters, double *relres)
+/* Block-Jacobi preconditioner of K_t: the inverse of the 3x3 diagonal block of
+ * every node, except that the two lips' nodes at the same interface point (+a, -a
+ * of an interface element) share the inverse of their 6x6 block.  Per node: own
+ * part Ai (3x3) and partner part Bi (3x3) of the rows of M^-1; partner[u] = -1
+ * off the interface pairs.  Returns 1 if a block is singular. */
+typedef struct {
+    int64_t N;
+    int32_t *partner;
+    double *Ai, *Bi;
+} or_bj;
+
+static int bj_setup(const or_problem *P, or_bj *M)
 {
     const or_csr *A = &P->Kt;
-    int64_t N = P->N, n = 3 * N;
+    int64_t N = P->N;
     int32_t *partner = malloc(N * sizeof(int32_t));
     for (int64_t i = 0; i < N; ++i) partner[i] = -1;
     for (int64_t t = 0; t < P->nf; ++t)
@@ -1342,7 +1349,6 @@ int or_pcg_block(or_problem *P, const double *b, double *x, double tol, int64_t 
         }
     for (int64_t i = 0; i < N; ++i)
         if (partner[i] == -2 || partner[i] == i) partner[i] = -1;
-    /* per node: M^-1 rows of the node, own part Ai (3x3) and partner part Bi (3x3) */
     double *Ai = calloc(9 * N, sizeof(double)), *Bi = calloc(9 * N, sizeof(double));
     int singular = 0;
     for (int64_t u = 0; u < N; ++u) {
@@ -1371,31 +1377,54 @@ int or_pcg_block(or_problem *P, const double *b, double *x, double tol, int64_t 
         }
         partner[u] = (int32_t)v;
     }
+    M->N = N;
+    M->partner = partner;
+    M->Ai = Ai;
+    M->Bi = Bi;
+    return singular;
+}
+
+static void bj_free(or_bj *M)
+{
+    free(M->partner);
+    free(M->Ai);
+    free(M->Bi);
+}
+
+/* z = M^-1 r */
+static void bj_apply(const or_bj *M, const double *r, double *z)
+{
+    for (int64_t u = 0; u < M->N; ++u)
+        for (int c = 0; c < 3; ++c) {
+            double s = 0;
+            for (int k = 0; k < 3; ++k) s += M->Ai[9 * u + 3 * c + k] * r[3 * u + k];
+            if (M->partner[u] >= 0)
+                for (int k = 0; k < 3; ++k) s += M->Bi[9 * u + 3 * c + k] * r[3 * M->partner[u] + k];
+            z[3 * u + c] = s;
+        }
+}
+
+/* PCG on K_t with a preconditioner z = prec(r).  Same recurrence and stop test as
+ * or_pcg.  Returns 0, 1 (not converged) or -3 (p.Ap <= 0). */
+typedef void (*or_prec_fn)(const or_problem *P, const or_bj *M, const void *ctx, const double *r, double *z);
+
+static int pcg_prec(const or_problem *P, const or_bj *M, or_prec_fn prec, const void *ctx, const double *b,
+                    double *x, double tol, int64_t maxit, int64_t *iters, double *relres)
+{
+    const or_csr *A = &P->Kt;
+    int64_t n = 3 * P->N;
     double *r = malloc(n * sizeof(double)), *z = malloc(n * sizeof(double));
     double *p = malloc(n * sizeof(double)), *q = malloc(n * sizeof(double));
     int status = 0;
     int64_t it = 0;
     double rel = 0;
-#define ZBLOCK()                                                                            \
-    for (int64_t u = 0; u < N; ++u)                                                         \
-        for (int c = 0; c < 3; ++c) {                                                       \
-            double s = 0;                                                                   \
-            for (int k = 0; k < 3; ++k) s += Ai[9 * u + 3 * c + k] * r[3 * u + k];          \
-            if (partner[u] >= 0)                                                            \
-                for (int k = 0; k < 3; ++k) s += Bi[9 * u + 3 * c + k] * r[3 * partner[u] + k]; \
-            z[3 * u + c] = s;                                                               \
-        }
     for (int64_t i = 0; i < n; ++i) {
         x[i] = 0;
         r[i] = b[i];
     }
-    ZBLOCK();
+    prec(P, M, ctx, r, z);
     memcpy(p, z, n * sizeof(double));
     double bn = sqrt(vdot(n, b, b));
-    if (singular) {
-        status = -3;
-        goto done;
-    }
     if (bn == 0.0) goto done;
     double rho = vdot(n, r, z);
     for (;;) {
@@ -1416,23 +1445,183 @@ int or_pcg_block(or_problem *P, const double *b, double *x, double tol, int64_t 
             x[i] += al * p[i];
             r[i] -= al * q[i];
         }
-        ZBLOCK();
+        prec(P, M, ctx, r, z);
         double rho2 = vdot(n, r, z);
         double be = rho2 / rho;
         rho = rho2;
         for (int64_t i = 0; i < n; ++i) p[i] = z[i] + be * p[i];
         ++it;
     }
-#undef ZBLOCK
 done:
     *iters = it;
     *relres = rel;
-    free(partner);
-    free(Ai);
-    free(Bi);
     free(r);
     free(z);
     free(p);
     free(q);
     return status;
+}
+
+static void prec_bj(const or_problem *P, const or_bj *M, const void *ctx, const double *r, double *z)
+{
+    (void)P;
+    (void)ctx;
+    bj_apply(M, r, z);
+}
+
+/* PCG on the current tangent K_t with the block-Jacobi preconditioner. */
+int or_pcg_block(or_problem *P, const double *b, double *x, double tol, int64_t maxit, int64_t *iters, double *relres)
+{
+    or_bj M;
+    int singular = bj_setup(P, &M);
+    int status;
+    if (singular) {
+        memset(x, 0, 3 * P->N * sizeof(double));
+        *iters = 0;
+        *relres = 0;
+        status = -3;
+    } else {
+        status = pcg_prec(P, &M, prec_bj, NULL, b, x, tol, maxit, iters, relres);
+    }
+    bj_free(&M);
+    return status;
+}
+
+/* Chebyshev polynomial preconditioner over block Jacobi (Saad, Iterative Methods
+ * for Sparse Linear Systems, Sec. 12.3, Chebyshev acceleration): z = p(M^-1 K)
+ * M^-1 r is `degree` steps of the Chebyshev iteration for K z = r from z = 0 on
+ * the interval [lo, hi] of the spectrum of M^-1 K, so that the residual
+ * polynomial 1 - t p(t) is T_m((hi + lo - 2t)/(hi - lo)) / T_m((hi + lo)/(hi - lo)).
+ * With theta = (hi + lo)/2, delta = (hi - lo)/2, sigma = theta/delta:
+ *   d = M^-1 r / theta, z = d, s = r, rho = 1/sigma;
+ *   repeat degree-1 times: s -= K d, rho' = 1/(2 sigma - rho),
+ *                          d = rho' rho d + (2 rho'/delta) M^-1 s, z += d, rho = rho'. */
+typedef struct {
+    int degree;
+    double lo, hi;
+} or_cheb;
+
+static void cheb_apply(const or_problem *P, const or_bj *M, const or_cheb *C, const double *r, double *z)
+{
+    int64_t n = 3 * P->N;
+    double *d = malloc(n * sizeof(double)), *s = malloc(n * sizeof(double));
+    double *w = malloc(n * sizeof(double)), *kd = malloc(n * sizeof(double));
+    double theta = 0.5 * (C->hi + C->lo), delta = 0.5 * (C->hi - C->lo), sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    bj_apply(M, r, d);
+    for (int64_t i = 0; i < n; ++i) {
+        d[i] /= theta;
+        z[i] = d[i];
+        s[i] = r[i];
+    }
+    for (int k = 1; k < C->degree; ++k) {
+        or_csr_spmv(&P->Kt, d, kd);
+        for (int64_t i = 0; i < n; ++i) s[i] -= kd[i];
+        double rho1 = 1.0 / (2.0 * sigma - rho);
+        bj_apply(M, s, w);
+        for (int64_t i = 0; i < n; ++i) {
+            d[i] = rho1 * rho * d[i] + (2.0 * rho1 / delta) * w[i];
+            z[i] += d[i];
+        }
+        rho = rho1;
+    }
+    free(d);
+    free(s);
+    free(w);
+    free(kd);
+}
+
+static void prec_cheb(const or_problem *P, const or_bj *M, const void *ctx, const double *r, double *z)
+{
+    cheb_apply(P, M, (const or_cheb *)ctx, r, z);
+}
+
+/* z = p(M^-1 K) M^-1 r for the current K_t (as above); returns -3 if a block is singular. */
+int or_cheb_apply(or_problem *P, const double *r, double *z, int degree, double lo, double hi)
+{
+    or_bj M;
+    int singular = bj_setup(P, &M);
+    or_cheb C = {degree, lo, hi};
+    if (!singular) cheb_apply(P, &M, &C, r, z);
+    bj_free(&M);
+    return singular ? -3 : 0;
+}
+
+/* PCG on K_t with the Chebyshev polynomial preconditioner of the given degree and interval. */
+int or_pcg_cheb(or_problem *P, const double *b, double *x, double tol, int64_t maxit, int degree, double lo,
+                double hi, int64_t *iters, double *relres)
+{
+    or_bj M;
+    int singular = bj_setup(P, &M);
+    or_cheb C = {degree, lo, hi};
+    int status;
+    if (singular) {
+        memset(x, 0, 3 * P->N * sizeof(double));
+        *iters = 0;
+        *relres = 0;
+        status = -3;
+    } else {
+        status = pcg_prec(P, &M, prec_cheb, &C, b, x, tol, maxit, iters, relres);
+    }
+    bj_free(&M);
+    return status;
+}
+
+/* SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) of counter i, as a double in
+ * [-1/2, 1/2): the probe vector of the spectrum estimate, by caller-order DOF. */
+static double splitmix_unit(uint64_t i)
+{
+    uint64_t z = (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+}
+
+void or_probe_vector(or_problem *P, double *v)
+{
+    for (int64_t i = 0; i < 3 * P->N; ++i) v[i] = P->dir_u[i] ? 0.0 : splitmix_unit((uint64_t)i);
+}
+
+/* Lanczos coefficients of M^-1 K (block Jacobi) from `steps` PCG iterations on the
+ * probe vector (Saad, Sec. 6.7.3: the CG coefficients alpha_j, beta_j give the
+ * tridiagonal Lanczos matrix).  Returns the number of iterations taken (fewer if
+ * the residual vanishes), or -3 on a singular block or p.Ap <= 0. */
+int or_bj_lanczos(or_problem *P, int steps, double *alpha, double *beta)
+{
+    or_bj M;
+    int64_t n = 3 * P->N;
+    if (bj_setup(P, &M)) {
+        bj_free(&M);
+        return -3;
+    }
+    double *r = malloc(n * sizeof(double)), *z = malloc(n * sizeof(double));
+    double *p = malloc(n * sizeof(double)), *q = malloc(n * sizeof(double));
+    or_probe_vector(P, r);
+    bj_apply(&M, r, z);
+    memcpy(p, z, n * sizeof(double));
+    double rho = vdot(n, r, z);
+    int j = 0;
+    for (; j < steps && rho > 0.0; ++j) {
+        or_csr_spmv(&P->Kt, p, q);
+        double pq = vdot(n, p, q);
+        if (!(pq > 0.0)) {
+            j = -3;
+            break;
+        }
+        double al = rho / pq;
+        for (int64_t i = 0; i < n; ++i) r[i] -= al * q[i];
+        bj_apply(&M, r, z);
+        double rho2 = vdot(n, r, z);
+        alpha[j] = al;
+        beta[j] = rho2 / rho;
+        rho = rho2;
+        for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta[j] * p[i];
+    }
+    free(r);
+    free(z);
+    free(p);
+    free(q);
+    bj_free(&M);
+    return j;
 }

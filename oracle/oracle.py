@@ -79,6 +79,14 @@ def lib():
         L.or_pcg_block.argtypes = [C.c_void_p, _f64p, _f64p, C.c_double, C.c_int64, C.POINTER(C.c_int64),
                                    C.POINTER(C.c_double)]
         L.or_gj_inverse.argtypes = [C.c_int, _f64p, _f64p, C.POINTER(C.c_int)]
+        L.or_cheb_apply.restype = C.c_int
+        L.or_cheb_apply.argtypes = [C.c_void_p, _f64p, _f64p, C.c_int, C.c_double, C.c_double]
+        L.or_pcg_cheb.restype = C.c_int
+        L.or_pcg_cheb.argtypes = [C.c_void_p, _f64p, _f64p, C.c_double, C.c_int64, C.c_int, C.c_double, C.c_double,
+                                  C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+        L.or_probe_vector.argtypes = [C.c_void_p, _f64p]
+        L.or_bj_lanczos.restype = C.c_int
+        L.or_bj_lanczos.argtypes = [C.c_void_p, C.c_int, _f64p, _f64p]
         L.or_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -208,6 +216,43 @@ class Problem:
         st = lib().or_pcg_block(self._h, _c(b, np.float64), x, tol, maxit, C.byref(it), C.byref(rr))
         return x, st, it.value, rr.value
 
+    def cheb_apply(self, r, degree, lo, hi):
+        """z = p(M^-1 K_t) M^-1 r, the Chebyshev polynomial preconditioner over block Jacobi of
+        the given degree on the spectrum interval [lo, hi] (Saad, Sec. 12.3)."""
+        z = np.zeros(3 * self.N)
+        st = lib().or_cheb_apply(self._h, _c(r, np.float64), z, int(degree), float(lo), float(hi))
+        if st != 0:
+            raise RuntimeError("a block of the block-Jacobi preconditioner is singular")
+        return z
+
+    def pcg_cheb(self, b, degree, lo, hi, tol=1e-10, maxit=1000000):
+        """K_t x = b by PCG with the Chebyshev preconditioner: (x, status, iters, relres)."""
+        x = np.zeros(3 * self.N)
+        it, rr = C.c_int64(), C.c_double()
+        st = lib().or_pcg_cheb(self._h, _c(b, np.float64), x, tol, maxit, int(degree), float(lo), float(hi),
+                               C.byref(it), C.byref(rr))
+        return x, st, it.value, rr.value
+
+    def probe_vector(self):
+        """SplitMix64 probe vector of the spectrum estimate (caller order, zero on Dirichlet DOFs)."""
+        v = np.zeros(3 * self.N)
+        lib().or_probe_vector(self._h, v)
+        return v
+
+    def bj_lanczos(self, steps):
+        """CG coefficients (alpha, beta) of `steps` block-Jacobi PCG iterations on the probe vector."""
+        a, b = np.zeros(steps), np.zeros(steps)
+        j = lib().or_bj_lanczos(self._h, int(steps), a, b)
+        if j < 0:
+            raise RuntimeError("block-Jacobi Lanczos failed: singular block or K not SPD")
+        return a[:j], b[:j]
+
+    def cheb_bounds(self, steps, safety, ratio):
+        """Interval of the Chebyshev preconditioner: hi = safety * (largest Ritz value of the
+        Lanczos matrix of M^-1 K_t after `steps` iterations), lo = hi / ratio."""
+        hi = safety * ritz_values(*self.bj_lanczos(steps))[-1]
+        return hi / ratio, hi
+
     def prevost(self, b1, b2, tol_outer=1e-10, tol_inner=1e-12, maxit_outer=500, maxit_inner=200000):
         x1, x2, st = np.zeros(3 * self.N), np.zeros(self.N), np.zeros(5)
         s = lib().or_prevost(self._h, _c(b1, np.float64), _c(b2, np.float64), x1, x2, tol_outer, tol_inner,
@@ -328,6 +373,23 @@ def _adjoint_methods():
 
 
 _adjoint_methods()
+
+
+def lanczos_matrix(alpha, beta):
+    """Tridiagonal Lanczos matrix from CG coefficients (Saad, Sec. 6.7.3):
+    T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1}, T_{j,j+1} = sqrt(beta_j)/alpha_j."""
+    m = len(alpha)
+    T = np.zeros((m, m))
+    for j in range(m):
+        T[j, j] = 1.0 / alpha[j] + (beta[j - 1] / alpha[j - 1] if j > 0 else 0.0)
+        if j + 1 < m:
+            T[j, j + 1] = T[j + 1, j] = np.sqrt(beta[j]) / alpha[j]
+    return T
+
+
+def ritz_values(alpha, beta):
+    """Eigenvalues (ascending) of the Lanczos matrix of the CG coefficients."""
+    return np.linalg.eigvalsh(lanczos_matrix(alpha, beta))
 
 
 def num_threads() -> int:
