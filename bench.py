@@ -194,10 +194,21 @@ def main():
         b = S.coupling(z)
         res = {}
         for name, prec in (("f64", fg.FG_F64), ("mixed", fg.FG_MIXED), ("mixed_f32val", fg.FG_MIXED_F32VAL),
-                           ("f64_block_jacobi", fg.FG_F64), ("mixed_block_jacobi", fg.FG_MIXED)):
+                           ("f64_block_jacobi", fg.FG_F64), ("mixed_block_jacobi", fg.FG_MIXED),
+                           ("f64_chebyshev_d2", fg.FG_F64), ("f64_chebyshev_d4", fg.FG_F64)):
             if name == "f64_block_jacobi":
                 S.tune("k_precond", 1)
                 S.pcg_solve(fg.FG_K, b, tol=1e-8, check_every=64)                 # blocks built, graphs captured
+            if name.startswith("f64_chebyshev"):
+                S.tune("k_precond", 2)
+                S.tune("cheb_degree", int(name[-1]))
+                if name.endswith("d2"):
+                    S.tune("cheb_ratio", 300)                                      # drops the interval: time its estimate
+                    torch.cuda.synchronize()
+                    t = time.perf_counter()
+                    cheb_lo, cheb_hi = S.cheb_interval()
+                    cheb_est = time.perf_counter() - t
+                    log(f"chebyshev interval [{cheb_lo:.4e}, {cheb_hi:.4e}] estimated in {cheb_est:.3f}s")
             torch.cuda.synchronize()
             t = time.perf_counter()
             x, info = S.pcg_solve(fg.FG_K, b, tol=1e-8, precision=prec, check_every=64)
@@ -205,6 +216,7 @@ def main():
             res[name] = (time.perf_counter() - t, info.iters, info.cycles, x)
             log(f"{name}: {res[name][0]:.3f}s iters {info.iters} cycles {info.cycles} relres {info.relres:.2e}")
         S.tune("k_precond", 0)
+        S.tune("cheb_degree", 4)
         err = (torch.linalg.norm(res["mixed"][3] - res["f64"][3]) / torch.linalg.norm(res["f64"][3])).item()
         err2 = (torch.linalg.norm(res["mixed_f32val"][3] - res["f64"][3]) / torch.linalg.norm(res["f64"][3])).item()
         out["time_to_1e-8"] = {"f64_s": res["f64"][0], "mixed_s": res["mixed"][0], "f64_iters": res["f64"][1],
@@ -226,7 +238,16 @@ def main():
                                "mixed_block_jacobi_vs_f64_rel_l2": (
                                    torch.linalg.norm(res["mixed_block_jacobi"][3] - res["f64"][3])
                                    / torch.linalg.norm(res["f64"][3])).item(),
-                               "speedup_mixed_block_jacobi": res["f64"][0] / res["mixed_block_jacobi"][0]}
+                               "speedup_mixed_block_jacobi": res["f64"][0] / res["mixed_block_jacobi"][0],
+                               "chebyshev_interval": [cheb_lo, cheb_hi], "chebyshev_estimate_s": cheb_est}
+        for d in (2, 4):
+            r_ = res[f"f64_chebyshev_d{d}"]
+            out["time_to_1e-8"].update({
+                f"f64_chebyshev_d{d}_s": r_[0], f"f64_chebyshev_d{d}_iters": r_[1],
+                f"f64_chebyshev_d{d}_products": r_[1] * d,
+                f"chebyshev_d{d}_vs_f64_rel_l2": (torch.linalg.norm(r_[3] - res["f64"][3])
+                                                  / torch.linalg.norm(res["f64"][3])).item(),
+                f"speedup_chebyshev_d{d}": res["f64"][0] / r_[0]})
 
     del S
     torch.cuda.empty_cache()

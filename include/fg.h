@@ -280,6 +280,18 @@ fg_status fg_adjoint_solve(fg_ctx *ctx, fg_system *sys, const double *U, const d
 fg_status fg_slip_adjoint(fg_ctx *ctx, fg_system *sys, const double *U, const double *die_old, const double *t0,
                           const double *a_new, const double *lam_u, double *gU, double *a_old, void *stream);
 
+/* Interval [lo, hi] (host outputs) of the Chebyshev preconditioner of K
+ * ("k_precond" 2, see fg_tune) for the current K, estimated now if K changed
+ * since the last estimate: hi = 1.1 x the largest Ritz value of the Lanczos
+ * matrix that "cheb_lanczos" block-Jacobi CG steps on the probe vector give
+ * (Saad, Sec. 6.7.3: T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1}, T_j,j+1 =
+ * sqrt(beta_j)/alpha_j), lo = hi / "cheb_ratio".  The probe is, per caller-order
+ * DOF i, SplitMix64 (Steele, Lea and Flood 2014) of counter i mapped to
+ * [-1/2, 1/2) as (z >> 11) 2^-53 - 1/2, zero on held DOFs.  Synchronises the
+ * stream.  Errors: FG_ERR_ARG, FG_ERR_STATE (before fg_assemble, or k_precond is
+ * not 2), FG_ERR_BREAKDOWN (singular block, K not SPD, or the probe vanished). */
+fg_status fg_cheb_interval(fg_ctx *ctx, fg_system *sys, double *lo, double *hi, void *stream);
+
 /* Products on the assembled system, caller order: y = A x for which in
  * {FG_K, FG_A22, FG_KBULK, FG_C}. */
 fg_status fg_spmv(fg_ctx *ctx, fg_system *sys, int which, const double *x, double *y, void *stream);
@@ -323,14 +335,28 @@ fg_status fg_group_stats(const fg_system *sys, int64_t *iters_h, double *relres_
  *               HIP graph, 0 launches the kernels one by one (same results).
  *   "line_search": 1 (default) backtracking on the Newton steps of fg_step,
  *               0 full steps.
- *   "k_precond": preconditioner of the FP64 single-right-hand-side K solves
+ *   "k_precond": preconditioner of the single-right-hand-side K solves
  *               (fg_pcg_solve, and the K solves inside fg_flow_solve, fg_step and
  *               fg_adjoint_solve): 0 (default) point Jacobi; 1 block Jacobi, the
  *               inverse of every node's 3x3 diagonal block except that the two
  *               lips' nodes at one interface point share the inverse of their
- *               6x6 block (the penalty stiffness couples them).  Rebuilt after
- *               every change of K; FG_ERR_BREAKDOWN if a block is singular.
- *               Block, batched and FP32 solves keep point Jacobi.
+ *               6x6 block (the penalty stiffness couples them), also in the FP32
+ *               CG of FG_F32 and FG_MIXED (FP32 copy of the blocks); 2 as 1, and
+ *               FP64 solves are preconditioned by the Chebyshev polynomial over
+ *               block Jacobi: z = p(M^-1 K) M^-1 r with 1 - t p(t) the Chebyshev
+ *               polynomial of degree "cheb_degree" scaled to the interval
+ *               [hi/"cheb_ratio", hi] (Saad, Iterative Methods for Sparse Linear
+ *               Systems, Sec. 12.3), hi = 1.1 x the largest Ritz value of
+ *               "cheb_lanczos" block-Jacobi CG steps on a fixed SplitMix64 probe
+ *               vector (fg_cheb_interval).  Each CG iteration then costs
+ *               cheb_degree products with K and reduces twice.  Blocks and
+ *               interval are rebuilt after every change of K; FG_ERR_BREAKDOWN if
+ *               a block is singular.  Block (nrhs > 1), batched and
+ *               FG_MIXED_F32VAL solves keep point Jacobi.
+ *   "cheb_degree": degree of the Chebyshev polynomial, 1 to 16 (default 4;
+ *               1 is block Jacobi scaled by 1/theta: same iterates).
+ *   "cheb_ratio": hi / lo of the interval, 2 to 1000000 (default 300).
+ *   "cheb_lanczos": CG steps of the spectrum estimate, 5 to 500 (default 40).
  *   "spmv_unroll": slots per unrolled step of the CG product: 1, 2 (default),
  *               3, 4 or 6.
  *   "mixed_update": FG_MIXED: factor by which the FP32 residual (of the

@@ -116,7 +116,9 @@ fg_status k_solve(fg_system *S, const double *rhs, double *out, const fg_pcg_opt
         int64_t it = 0;
         double rr = 0;
         fg_status s;
-        if (o.precision == FG_F64) {
+        if (o.precision == FG_F64 && S->k_precond == 2 && S->ngroups == 1) {
+            s = cheb_cg(S, rhs, out, o.tol, o.max_iter, o.check_every, &it, &rr, st);
+        } else if (o.precision == FG_F64) {
             hipMemcpyAsync(S->wr, rhs, n * sizeof(double), hipMemcpyDeviceToDevice, st);
             s = cg_run(S, FG_K, FG_F64, o.tol, o.max_iter, o.check_every, &it, &rr, st);
             hipMemcpyAsync(out, S->wx, n * sizeof(double), hipMemcpyDeviceToDevice, st);
@@ -384,7 +386,7 @@ fg_status fg_system_destroy(fg_system *S)
                     S->fr, S->fp, S->fq, S->v1, S->v2, S->v3, S->v4, S->pv1, S->pv2, S->ui, S->ui0, S->fi, S->rm,
                     S->du, S->fc, S->s1, S->s2, S->s3, S->s4, S->s5, S->s6, S->s7, S->s8, S->pi, S->pi0, S->qi,
                     S->rf, S->dpv, S->die0, S->partials, S->sc, S->red, S->red_counter, S->fslot, S->fpart,
-                    S->bjA, S->bjB, S->wz, S->bjA32, S->bjB32, S->wz32};
+                    S->bjA, S->bjB, S->wz, S->bjA32, S->bjB32, S->wz32, S->chd, S->chs, S->chq};
     for (void *p : ptrs) dfree(p);
     drop_graphs(S);
     drop_mr_graphs(S);
@@ -967,6 +969,26 @@ fg_status fg_slip_adjoint(fg_ctx *ctx, fg_system *S, const double *U, const doub
     return check_hip("fg_slip_adjoint");
 }
 
+fg_status fg_cheb_interval(fg_ctx *ctx, fg_system *S, double *lo, double *hi, void *stream)
+{
+    if (!ctx || !S || !lo || !hi) {
+        set_error("fg_cheb_interval: bad argument");
+        return FG_ERR_ARG;
+    }
+    if (!ready(S)) return FG_ERR_STATE;
+    if (S->k_precond != 2) {
+        set_error("fg_cheb_interval: the Chebyshev preconditioner is not selected (fg_tune k_precond 2)");
+        return FG_ERR_STATE;
+    }
+    Guard g(ctx->device);
+    hipStream_t st = S_(stream);
+    fg_status e = cheb_interval_ready(S, st);
+    if (e) return e;
+    *lo = S->cheb_lo;
+    *hi = S->cheb_hi;
+    return check_hip("fg_cheb_interval");
+}
+
 fg_status fg_spmv(fg_ctx *ctx, fg_system *S, int which, const double *x, double *y, void *stream)
 {
     if (!ctx || !S || !x || !y || which < 0 || which > 3) {
@@ -1085,11 +1107,18 @@ fg_status fg_tune(fg_system *S, const char *key, int64_t value)
         return FG_OK;
     }
     if (std::strcmp(key, "k_precond") == 0) {
-        if (value > 1) {
-            set_error("fg_tune: k_precond must be 0 (point Jacobi) or 1 (nodal and fault-pair block Jacobi)");
+        if (value > 2) {
+            set_error("fg_tune: k_precond must be 0 (point Jacobi), 1 (nodal and fault-pair block Jacobi) or 2 "
+                      "(Chebyshev polynomial over block Jacobi)");
             return FG_ERR_ARG;
         }
-        if (value == 1 && !S->bjA) {
+        if (value == 2 && !S->chd) {
+            if (dalloc(&S->chd, 3 * S->Npad) || dalloc(&S->chs, 3 * S->Npad) || dalloc(&S->chq, 3 * S->Npad)) {
+                set_error("fg_tune: device allocation for the Chebyshev preconditioner failed");
+                return FG_ERR_OOM;
+            }
+        }
+        if (value >= 1 && !S->bjA) {
             if (dalloc(&S->bjA, 6 * S->Npad) || dalloc(&S->bjB, 9 * std::max<int64_t>(S->nfr, 1)) ||
                 dalloc(&S->wz, 3 * S->Npad) || dalloc(&S->bjA32, 6 * S->Npad) ||
                 dalloc(&S->bjB32, 9 * std::max<int64_t>(S->nfr, 1)) || dalloc(&S->wz32, 3 * S->Npad)) {
@@ -1113,6 +1142,32 @@ fg_status fg_tune(fg_system *S, const char *key, int64_t value)
         }
         S->spmv_unroll = (int)value;
         drop_graphs(S);
+        return FG_OK;
+    }
+    if (std::strcmp(key, "cheb_degree") == 0) {
+        if (value < 1 || value > 16) {
+            set_error("fg_tune: cheb_degree must be in [1, 16]");
+            return FG_ERR_ARG;
+        }
+        S->cheb_degree = (int)value;
+        return FG_OK;
+    }
+    if (std::strcmp(key, "cheb_ratio") == 0) {
+        if (value < 2 || value > 1000000) {
+            set_error("fg_tune: cheb_ratio must be in [2, 1000000]");
+            return FG_ERR_ARG;
+        }
+        S->cheb_ratio = (int)value;
+        S->cheb_epoch = -1;
+        return FG_OK;
+    }
+    if (std::strcmp(key, "cheb_lanczos") == 0) {
+        if (value < 5 || value > 500) {
+            set_error("fg_tune: cheb_lanczos must be in [5, 500]");
+            return FG_ERR_ARG;
+        }
+        S->cheb_lanczos = (int)value;
+        S->cheb_epoch = -1;
         return FG_OK;
     }
     if (std::strcmp(key, "mixed_update") == 0) {

@@ -137,7 +137,15 @@ struct fg_system {
     bool bj32_valid = false;
     bool bj_valid = false;      // bjA/bjB built from the current K
     bool bj_singular = false;   // the last build met a singular block
-    int k_precond = 0;          // fg_tune "k_precond": 0 point Jacobi, 1 nodal + fault-pair block Jacobi
+    int k_precond = 0;          // fg_tune "k_precond": 0 point Jacobi, 1 nodal + fault-pair block Jacobi,
+                                // 2 Chebyshev polynomial over block Jacobi (FP64 single-system K solves)
+    int64_t bj_epoch = 0;       // builds of bjA/bjB so far
+    double *chd = nullptr, *chs = nullptr, *chq = nullptr;  // [3*Npad] Chebyshev d, s and K d
+    int cheb_degree = 4;        // fg_tune "cheb_degree": degree of the Chebyshev polynomial
+    int cheb_ratio = 300;       // fg_tune "cheb_ratio": lower end of the interval = upper end / ratio
+    int cheb_lanczos = 40;      // fg_tune "cheb_lanczos": CG steps of the spectrum estimate
+    double cheb_lo = 0, cheb_hi = 0;  // interval of the last estimate
+    int64_t cheb_epoch = -1;    // bj_epoch of the last estimate
     uint8_t *dir_u = nullptr, *dir_p = nullptr;
     double *tri_geo = nullptr;  // [nf*10]: area, n[3], t1[3], t2[3]
     // operators

@@ -56,6 +56,18 @@ fg_status cg_reliable(fg_system *S, const double *b, double *x, double tol, int6
 fg_status cg_run(fg_system *S, int which, int precision, double tol, int64_t maxit, int check_every,
                  int64_t *iters, double *relres, hipStream_t st);
 
+// Block-Jacobi data of the current K (built on first use after K changed).
+void bj_ready(fg_system *S, hipStream_t st);
+// q = K p with the CG product kernel (reads the stop flag of S->sc; partials of
+// p.q in row 0 of S->partials); returns the number of partials.
+int64_t cg_spmv_k(fg_system *S, const double *p, double *q, hipStream_t st);
+
+// Chebyshev-over-block-Jacobi PCG on K (fg_cheb.hip): b, x internal order.
+fg_status cheb_cg(fg_system *S, const double *b, double *x, double tol, int64_t maxit, int check_every, int64_t *iters,
+                  double *relres, hipStream_t st);
+// Spectrum interval of the Chebyshev preconditioner for the current K (estimated if stale).
+fg_status cheb_interval_ready(fg_system *S, hipStream_t st);
+
 // float <-> double conversions with a scale: y = (T)(s * x)
 void to_f32(int64_t n, double s, const double *x, float *y, hipStream_t st);
 // y += s * (double)x

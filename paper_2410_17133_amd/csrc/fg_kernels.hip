@@ -1473,6 +1473,16 @@ static void cg_spmv_launch(fg_system *S, int64_t gs, const TV *val, const T *p, 
 #undef FG_CG_SPMV_W
 }
 
+// q = K p with the CG product kernel and launch parameters (stops with the solve's
+// flag in S->sc); the per-block partials of p.q go to row 0 of S->partials.
+// Returns the number of blocks (partials).
+int64_t cg_spmv_k(fg_system *S, const double *p, double *q, hipStream_t st)
+{
+    const int64_t gs = grid_xcd((S->nslices + S->spmv_wpb - 1) / S->spmv_wpb);
+    cg_spmv_launch<3, double, double>(S, gs, S->K, p, q, st);
+    return gs;
+}
+
 template <typename T>
 static BlockJacobi<T> bj_args(fg_system *S);
 template <>
@@ -1583,6 +1593,7 @@ void bj_ready(fg_system *S, hipStream_t st)
     hipStreamSynchronize(st);
     S->bj_singular = h != 0;
     S->bj_valid = true;
+    ++S->bj_epoch;
     S->bj32_valid = false;
 }
 

@@ -21,7 +21,7 @@ FG_F64, FG_F32, FG_MIXED, FG_MIXED_F32VAL = 0, 1, 2, 3
 SYMBOLS = ["fg_last_error", "fg_ctx_create", "fg_ctx_destroy", "fg_system_create", "fg_system_destroy",
            "fg_assemble", "fg_cohesive_update", "fg_pcg_solve", "fg_flow_solve", "fg_step", "fg_spmv",
            "fg_coupling", "fg_residual", "fg_system_sizes", "fg_export", "fg_profile", "fg_profile_read", "fg_tune", "fg_adjoint_solve", "fg_group_stats",
-           "fg_assemble_groups", "fg_slip_adjoint"]
+           "fg_assemble_groups", "fg_slip_adjoint", "fg_cheb_interval"]
 
 
 class FgError(RuntimeError):
@@ -96,6 +96,7 @@ def lib():
                                                         C.POINTER(SolveInfo), vp],
             "fg_profile_read": [vp, i32, C.POINTER(i64), C.POINTER(dbl), i32],
             "fg_slip_adjoint": [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
+            "fg_cheb_interval": [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double), vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -285,6 +286,12 @@ class System:
                                      None if lam_u is None else _ptr(lam_u, torch.float64, 3 * self.N, "lam_u"),
                                      _ptr(gU, torch.float64), _ptr(a_old, torch.float64), _stream()), False)
         return gU, a_old
+
+    def cheb_interval(self):
+        """(lo, hi) of the Chebyshev preconditioner of the current K (fg_cheb_interval)."""
+        lo, hi = C.c_double(), C.c_double()
+        _check(lib().fg_cheb_interval(self.ctx._h, self._h, C.byref(lo), C.byref(hi), _stream()), False)
+        return lo.value, hi.value
 
     def spmv(self, which, x):
         n = (3 if which in (FG_K, FG_KBULK) else 1) * self.N

@@ -124,6 +124,19 @@ def test_pcg_iterates_full_size(full):
     xbo, st, it, rr = P.pcg_block(b, tol=1e-300, maxit=50)
     print(f"[pcg K block Jacobi] rel {relerr(host(xb), xbo):.2e}", flush=True)
     assert ib.iters == it == 50 and relerr(host(xb), xbo) < 1e-10
+    # Chebyshev polynomial over block Jacobi (degree 4): the oracle's interval, the same iterates
+    S.tune("k_precond", 2)
+    try:
+        lo, hi = S.cheb_interval()
+        xc, ic = S.pcg_solve(fg.FG_K, dev(b), tol=1e-300, max_iter=50, check_every=64)
+    finally:
+        S.tune("k_precond", 0)
+    olo, ohi = P.cheb_bounds(40, 1.1, 300)
+    xco, st, it, rr = P.pcg_cheb(b, 4, lo, hi, tol=1e-300, maxit=50)
+    print(f"[pcg K Chebyshev] interval [{lo:.6e}, {hi:.6e}] oracle [{olo:.6e}, {ohi:.6e}] "
+          f"rel {relerr(host(xc), xco):.2e}", flush=True)
+    assert abs(hi - ohi) <= 1e-8 * ohi and abs(lo - olo) <= 1e-8 * olo
+    assert ic.iters == it == 50 and relerr(host(xc), xco) < 1e-10
 
 
 def test_adjoint_identities_full_size(full):

@@ -208,7 +208,7 @@ def test_pcg_block_jacobi_matches_oracle(name):
     finally:
         S.tune("k_precond", 0)
     with pytest.raises(fg.FgError):
-        S.tune("k_precond", 2)
+        S.tune("k_precond", 3)
 
 
 def test_step_with_block_jacobi_reaches_the_same_state():
@@ -220,6 +220,113 @@ def test_step_with_block_jacobi_reaches_the_same_state():
     Uo, Po, dieo = np.zeros(3 * N), np.zeros(N), np.zeros((nq, 2))
     P.step(Uo, Po, dieo, tol_newton=1e-11, max_newton=40, tol_outer=1e-12, tol_inner=1e-13)
     S.tune("k_precond", 1)
+    try:
+        U, Pp, die = dev(np.zeros(3 * N)), dev(np.zeros(N)), dev(np.zeros(2 * nq))
+        trac, flag, info = S.step(U, Pp, die, dev(inst.t0.reshape(-1)), dev(inst.load), dev(inst.source),
+                                  newton_tol=1e-11, newton_max_iter=40, inner_k=fg.opts(tol=1e-13),
+                                  inner_p=fg.opts(tol=1e-13), outer_tol=1e-12)
+    finally:
+        S.tune("k_precond", 0)
+    assert info.status == 0
+    assert relerr(host(U), Uo) < 1e-9 and relerr(host(Pp), Po) < 1e-9
+
+
+@pytest.mark.parametrize("name", ["cube2", "cube12_dip60_hetero", "cube10_dip35_hetero"])
+def test_pcg_chebyshev_matches_oracle(name):
+    """fg_tune k_precond 2: the interval of the Chebyshev preconditioner equals the
+    oracle's Lanczos estimate on the same SplitMix64 probe; with that interval the
+    first 50 PCG iterates and the converged solve equal the oracle's Chebyshev PCG;
+    every degree reaches the point-Jacobi solution; a new tangent gets a new interval."""
+    fg, O = _fg(), _oracle()
+    inst, ctx, S, P = setup(name)
+    print(f"[case] Chebyshev {name}", flush=True)
+    r = np.random.default_rng(12)
+    U = r.normal(0.0, 2e-5 / inst.cfg.n, 3 * S.N) * (1 - inst.dir_u)    # stick, slip and open points
+    P.cohesive(U, np.zeros((P.nq, 2)))
+    S.cohesive_update(dev(U), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)))
+    b = r.standard_normal(3 * S.N) * (1 - inst.dir_u)
+    x0, i0 = S.pcg_solve(fg.FG_K, dev(b), tol=1e-12)
+    with pytest.raises(fg.FgError):
+        S.cheb_interval()                       # not selected yet
+    S.tune("k_precond", 1)
+    xb, ib = S.pcg_solve(fg.FG_K, dev(b), tol=1e-12)
+    xb50, _ = S.pcg_solve(fg.FG_K, dev(b), tol=1e-300, max_iter=50)
+    S.tune("k_precond", 2)
+    try:
+        lo, hi = S.cheb_interval()
+        olo, ohi = P.cheb_bounds(40, 1.1, 300)
+        print(f"[Chebyshev] interval [{lo:.6e}, {hi:.6e}] oracle [{olo:.6e}, {ohi:.6e}]", flush=True)
+        assert abs(hi - ohi) <= 1e-8 * ohi and abs(lo - olo) <= 1e-8 * olo
+        x50, i50 = S.pcg_solve(fg.FG_K, dev(b), tol=1e-300, max_iter=50)
+        xo, st, it, rr = P.pcg_cheb(b, 4, lo, hi, tol=1e-300, maxit=50)
+        assert i50.iters == it == 50 and i50.status == fg.FG_NOT_CONVERGED
+        assert relerr(host(x50), xo) < 1e-10
+        x1, i1 = S.pcg_solve(fg.FG_K, dev(b), tol=1e-12)
+        xo1, st, it1, rr = P.pcg_cheb(b, 4, lo, hi, tol=1e-12)
+        print(f"[Chebyshev] point {i0.iters}, block {ib.iters}, degree 4: {i1.iters} (oracle {it1})", flush=True)
+        assert i1.status == 0 and abs(i1.iters - it1) <= max(2, 0.02 * it1)
+        assert relerr(host(x1), xo1) < 1e-9 and relerr(host(x1), host(x0)) < 1e-9
+        if name != "cube2":
+            assert 4 * i1.iters <= 1.3 * ib.iters and i1.iters <= 0.35 * ib.iters
+        for deg in (1, 2, 7):
+            S.tune("cheb_degree", deg)
+            xd, idg = S.pcg_solve(fg.FG_K, dev(b), tol=1e-12)
+            print(f"[Chebyshev] degree {deg}: {idg.iters} iterations", flush=True)
+            assert idg.status == 0 and relerr(host(xd), host(x0)) < 1e-9
+            if deg == 1:
+                # block Jacobi scaled by 1/theta: the same iterates (the stop near 1e-12 may drift by rounding)
+                xd50, _ = S.pcg_solve(fg.FG_K, dev(b), tol=1e-300, max_iter=50)
+                assert relerr(host(xd50), host(xb50)) < 1e-10 and abs(idg.iters - ib.iters) <= 0.02 * ib.iters
+        S.tune("cheb_degree", 4)
+        # mixed precision keeps block Jacobi in its FP32 CG
+        xm, im = S.pcg_solve(fg.FG_K, dev(b), tol=1e-9, precision=fg.FG_MIXED)
+        assert im.status == 0
+        assert np.linalg.norm(b - P.spmv(O.K_TANGENT, host(xm))) <= 1e-9 * np.linalg.norm(b)
+        # a new tangent: a new interval, the oracle's for that tangent
+        P.cohesive(np.zeros(3 * P.N), np.zeros((P.nq, 2)))
+        S.cohesive_update(dev(np.zeros(3 * S.N)), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)))
+        lo2, hi2 = S.cheb_interval()
+        olo2, ohi2 = P.cheb_bounds(40, 1.1, 300)
+        assert abs(hi2 - ohi2) <= 1e-8 * ohi2
+        x2, i2 = S.pcg_solve(fg.FG_K, dev(b), tol=1e-300, max_iter=50)
+        xo2, st, it2, rr = P.pcg_cheb(b, 4, lo2, hi2, tol=1e-300, maxit=50)
+        assert relerr(host(x2), xo2) < 1e-10
+        # another ratio and Lanczos length re-estimate
+        S.tune("cheb_ratio", 50)
+        S.tune("cheb_lanczos", 25)
+        lo3, hi3 = S.cheb_interval()
+        olo3, ohi3 = P.cheb_bounds(25, 1.1, 50)
+        assert abs(hi3 - ohi3) <= 1e-8 * ohi3 and abs(lo3 - olo3) <= 1e-8 * olo3
+        for key, bad in (("cheb_degree", 0), ("cheb_degree", 17), ("cheb_ratio", 1), ("cheb_lanczos", 4)):
+            with pytest.raises(fg.FgError):
+                S.tune(key, bad)
+    finally:
+        S.tune("cheb_ratio", 300)
+        S.tune("cheb_lanczos", 40)
+        S.tune("k_precond", 0)
+
+
+def test_pcg_chebyshev_zero_rhs():
+    fg, O = _fg(), _oracle()
+    inst, ctx, S, P = setup("cube8")
+    S.cohesive_update(dev(np.zeros(3 * S.N)), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)))
+    S.tune("k_precond", 2)
+    try:
+        x, info = S.pcg_solve(fg.FG_K, dev(np.zeros(3 * S.N)), tol=1e-10)
+    finally:
+        S.tune("k_precond", 0)
+    assert info.status == 0 and info.iters == 0 and not host(x).any()
+
+
+def test_step_with_chebyshev_reaches_the_same_state():
+    """A full implicit step (Newton, partitioned CG) with Chebyshev-preconditioned K
+    solves ends in the oracle's converged state."""
+    fg, O = _fg(), _oracle()
+    inst, ctx, S, P = setup("cube8")
+    N, nq = S.N, S.nq
+    Uo, Po, dieo = np.zeros(3 * N), np.zeros(N), np.zeros((nq, 2))
+    P.step(Uo, Po, dieo, tol_newton=1e-11, max_newton=40, tol_outer=1e-12, tol_inner=1e-13)
+    S.tune("k_precond", 2)
     try:
         U, Pp, die = dev(np.zeros(3 * N)), dev(np.zeros(N)), dev(np.zeros(2 * nq))
         trac, flag, info = S.step(U, Pp, die, dev(inst.t0.reshape(-1)), dev(inst.load), dev(inst.source),
