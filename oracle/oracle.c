@@ -1098,6 +1098,43 @@ void or_apply_NT(or_problem *P, const double *x_in, double *y)
         if (P->dir_u[i]) y[i] = 0;
 }
 
+/* N x: the slip part of the exact interface tangent that the symmetric Newton
+ * tangent omits (last or_cohesive call).  At a slip point the shear traction's
+ * magnitude f t'_n follows the normal opening, d t_s / d delta_n = -f k_n tau, so
+ * the force on the lips is +-w N_a tau (-f k_n)(n . jump(x)) (Sec. 2.2.1, return
+ * map; the transpose of or_apply_NT). */
+void or_apply_N(or_problem *P, const double *x_in, double *y)
+{
+    int64_t N = P->N;
+    memset(y, 0, 3 * N * sizeof(double));
+    const double kn = P->p.k_n, f = P->p.friction;
+    for (int64_t t = 0; t < P->nf; ++t) {
+        const int32_t *nd = P->coh + 6 * t;
+        const double *n = P->tri_n + 3 * t;
+        double w = P->tri_A[t] / 3.0;
+        for (int q = 0; q < 3; ++q) {
+            int64_t iq = 3 * t + q;
+            if (P->qp_flag[iq] != OR_SLIP) continue;
+            const double *tau = P->qp_tau + 3 * iq;
+            double jump[3] = {0, 0, 0};
+            for (int a = 0; a < 3; ++a)
+                for (int r = 0; r < 3; ++r) {
+                    int64_t ip = 3 * (int64_t)nd[a] + r, im = 3 * (int64_t)nd[3 + a] + r;
+                    double xp = P->dir_u[ip] ? 0.0 : x_in[ip], xm = P->dir_u[im] ? 0.0 : x_in[im];
+                    jump[r] += QP_N[q][a] * (xp - xm);
+                }
+            double s = -f * kn * dot3(n, jump);
+            for (int a = 0; a < 3; ++a)
+                for (int r = 0; r < 3; ++r) {
+                    y[3 * (int64_t)nd[a] + r] += w * QP_N[q][a] * s * tau[r];
+                    y[3 * (int64_t)nd[3 + a] + r] -= w * QP_N[q][a] * s * tau[r];
+                }
+        }
+    }
+    for (int64_t i = 0; i < 3 * N; ++i)
+        if (P->dir_u[i]) y[i] = 0;
+}
+
 /* Adjoint of one converged step (the transposed Newton system, Sec. 3.3.1):
  *   [K_exact^T  A_pu ] [lam_u]   [g_u]
  *   [-A_up      A22  ] [lam_p] = [g_p]
@@ -1624,4 +1661,94 @@ int or_bj_lanczos(or_problem *P, int steps, double *alpha, double *beta)
     free(q);
     bj_free(&M);
     return j;
+}
+
+/* (K_t + N) x = b, the exact interface tangent of the last or_cohesive call, by
+ * BiCGStab (van der Vorst, SIAM J. Sci. Stat. Comput. 13, 1992) with the block-
+ * Jacobi preconditioner M of K_t applied on the right (x = M^-1 y):
+ *   r = b, rh = r, rho = alpha = omega = 1, v = p = 0;
+ *   repeat: rho' = rh.r, beta = (rho'/rho)(alpha/omega), p = r + beta (p - omega v),
+ *           ph = M^-1 p, v = A ph, alpha = rho'/(rh.v), s = r - alpha v,
+ *           sh = M^-1 s, t = A sh, omega = (t.s)/(t.t),
+ *           x += alpha ph + omega sh, r = s - omega t
+ * until ||r|| <= tol ||b|| (r is the recursive residual).  Returns 0, 1 (not
+ * converged) or -3 (a breakdown: rho', rh.v, t.t or omega zero, or a singular block). */
+int or_bicgstab_exact(or_problem *P, const double *b, double *x, double tol, int64_t maxit, int64_t *iters,
+                      double *relres)
+{
+    int64_t n = 3 * P->N;
+    or_bj M;
+    int status = 0;
+    int64_t it = 0;
+    double rel = 0;
+    memset(x, 0, n * sizeof(double));
+    if (bj_setup(P, &M)) {
+        bj_free(&M);
+        *iters = 0;
+        *relres = 0;
+        return -3;
+    }
+    double *r = malloc(n * sizeof(double)), *rh = malloc(n * sizeof(double)), *p = calloc(n, sizeof(double));
+    double *v = calloc(n, sizeof(double)), *ph = malloc(n * sizeof(double)), *sv = malloc(n * sizeof(double));
+    double *sh = malloc(n * sizeof(double)), *t = malloc(n * sizeof(double)), *w = malloc(n * sizeof(double));
+    memcpy(r, b, n * sizeof(double));
+    memcpy(rh, b, n * sizeof(double));
+    double bn = sqrt(vdot(n, b, b)), rho = 1, alpha = 1, omega = 1;
+    if (bn == 0.0) goto done;
+    for (;;) {
+        rel = sqrt(vdot(n, r, r)) / bn;
+        if (rel <= tol) break;
+        if (it >= maxit) {
+            status = 1;
+            break;
+        }
+        double rho1 = vdot(n, rh, r);
+        if (rho1 == 0.0 || omega == 0.0) {
+            status = -3;
+            break;
+        }
+        double beta = (rho1 / rho) * (alpha / omega);
+        for (int64_t i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+        bj_apply(&M, p, ph);
+        or_csr_spmv(&P->Kt, ph, v);
+        or_apply_N(P, ph, w);
+        for (int64_t i = 0; i < n; ++i) v[i] += w[i];
+        double rv = vdot(n, rh, v);
+        if (rv == 0.0) {
+            status = -3;
+            break;
+        }
+        alpha = rho1 / rv;
+        for (int64_t i = 0; i < n; ++i) sv[i] = r[i] - alpha * v[i];
+        bj_apply(&M, sv, sh);
+        or_csr_spmv(&P->Kt, sh, t);
+        or_apply_N(P, sh, w);
+        for (int64_t i = 0; i < n; ++i) t[i] += w[i];
+        double tt = vdot(n, t, t);
+        if (tt == 0.0) {
+            status = -3;
+            break;
+        }
+        omega = vdot(n, t, sv) / tt;
+        for (int64_t i = 0; i < n; ++i) {
+            x[i] += alpha * ph[i] + omega * sh[i];
+            r[i] = sv[i] - omega * t[i];
+        }
+        rho = rho1;
+        ++it;
+    }
+done:
+    *iters = it;
+    *relres = rel;
+    free(r);
+    free(rh);
+    free(p);
+    free(v);
+    free(ph);
+    free(sv);
+    free(sh);
+    free(t);
+    free(w);
+    bj_free(&M);
+    return status;
 }

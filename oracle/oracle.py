@@ -87,6 +87,10 @@ def lib():
         L.or_probe_vector.argtypes = [C.c_void_p, _f64p]
         L.or_bj_lanczos.restype = C.c_int
         L.or_bj_lanczos.argtypes = [C.c_void_p, C.c_int, _f64p, _f64p]
+        L.or_apply_N.argtypes = [C.c_void_p, _f64p, _f64p]
+        L.or_bicgstab_exact.restype = C.c_int
+        L.or_bicgstab_exact.argtypes = [C.c_void_p, _f64p, _f64p, C.c_double, C.c_int64, C.POINTER(C.c_int64),
+                                        C.POINTER(C.c_double)]
         L.or_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -293,6 +297,19 @@ def _adjoint_methods():
         lib().or_apply_NT(self._h, _c(x, np.float64), y)
         return y
 
+    def apply_N(self, x):
+        """N x: the slip-tangent part the symmetric Newton tangent omits (last cohesive call)."""
+        y = np.zeros(3 * self.N)
+        lib().or_apply_N(self._h, _c(x, np.float64), y)
+        return y
+
+    def bicgstab_exact(self, b, tol=1e-10, maxit=100000):
+        """(K_t + N) x = b by BiCGStab with right block-Jacobi preconditioning: (x, status, iters, relres)."""
+        x = np.zeros(3 * self.N)
+        it, rr = C.c_int64(), C.c_double()
+        st = lib().or_bicgstab_exact(self._h, _c(b, np.float64), x, tol, maxit, C.byref(it), C.byref(rr))
+        return x, st, it.value, rr.value
+
     def adjoint(self, g_u, g_p, tol_defect=1e-12, max_defect=50, tol_outer=1e-12, tol_inner=1e-13,
                 maxit_outer=1000, maxit_inner=500000):
         """(lam_u, lam_p, status, stats) of the transposed Newton system at the state of the last cohesive call."""
@@ -365,6 +382,8 @@ def _adjoint_methods():
         return dE_t, dk_t
 
     Problem.apply_NT = apply_NT
+    Problem.apply_N = apply_N
+    Problem.bicgstab_exact = bicgstab_exact
     Problem.adjoint = adjoint
     Problem.sensitivity = sensitivity
     Problem.slip_adjoint = slip_adjoint

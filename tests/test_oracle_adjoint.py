@@ -117,3 +117,51 @@ def test_adjoint_gradient_matches_central_differences(converged):
         fd = (Jp - Jm) / (2 * eps)
         ad = dk @ dlk + grad_lnE @ dlE
         assert abs(fd - ad) <= 1e-5 * abs(ad), (fd, ad)
+
+
+def test_forward_slip_term_is_the_exact_tangent_defect(converged):
+    """N v (forward product) completes the symmetric tangent to central differences of the
+    interface force, and is the transpose of N^T (x.(N v) = (N^T x).v)."""
+    inst, P, U, Pp, uplift = converged
+    die = np.zeros((P.nq, 2))
+    free = 1.0 - inst.dir_u
+    r = np.random.default_rng(5)
+    v = r.standard_normal(3 * P.N) * free
+    x = r.standard_normal(3 * P.N) * free
+    P.cohesive(U, die)
+    Kt, Kb = P.scipy(O.K_TANGENT), P.scipy(O.K_BULK)
+    Nv = P.apply_N(v)
+    assert np.abs(Nv).max() > 0
+    assert abs(x @ Nv - P.apply_NT(x) @ v) <= 1e-12 * np.linalg.norm(x) * np.linalg.norm(Nv)
+    h = 1e-13
+    fd = (P.cohesive(U + h * v, die)[3] - P.cohesive(U - h * v, die)[3]) / (2 * h)
+    P.cohesive(U, die)
+    np.testing.assert_allclose((Kt - Kb) @ v + Nv, fd, rtol=0, atol=1e-5 * np.abs(fd).max())
+    # without it the symmetric tangent misses the force change along the slip direction
+    assert np.abs((Kt - Kb) @ v - fd).max() > 1e-3 * np.abs(fd).max()
+
+
+def test_bicgstab_solves_the_exact_tangent(converged):
+    """BiCGStab on K_t + N: its solution against a dense solve of the exact tangent, its
+    residual with independent products, and fewer iterations than point-Jacobi CG takes
+    on the symmetric part."""
+    inst, P, U, Pp, uplift = converged
+    P.cohesive(U, np.zeros((P.nq, 2)))
+    free = (1.0 - inst.dir_u).astype(bool)
+    b = np.random.default_rng(6).standard_normal(3 * P.N) * free
+    x, st, it, rr = P.bicgstab_exact(b, tol=1e-12)
+    assert st == 0 and rr <= 1e-12
+    K = P.scipy(O.K_TANGENT).toarray()
+    Nd = np.stack([P.apply_N(e) for e in np.eye(3 * P.N)], 1)
+    A = K + Nd
+    assert np.linalg.norm(b - A @ x) <= 1e-11 * np.linalg.norm(b)
+    xd = np.zeros(3 * P.N)
+    xd[free] = np.linalg.solve(A[np.ix_(free, free)], b[free])
+    assert np.linalg.norm(x - xd) <= 1e-9 * np.linalg.norm(xd)
+    # the symmetric tangent's solution is a different one
+    xs, s2, it2, _ = P.pcg(O.K_TANGENT, b, tol=1e-12)
+    assert np.linalg.norm(xs - xd) > 1e-6 * np.linalg.norm(xd)
+    print(f"[bicgstab] {it} iterations (2 products each); point-Jacobi CG on K_t {it2}")
+    # zero right-hand side
+    x0, st0, it0, _ = P.bicgstab_exact(np.zeros(3 * P.N))
+    assert st0 == 0 and it0 == 0 and not x0.any()
