@@ -364,6 +364,27 @@ def extra_adjoint(ctx, log):
             f"K iters {ainfo.inner_k_iters} status {ainfo.status}")
         res[name] = (t_adj, ainfo, torch.cat([dE * E, dk]))
     g64 = res["f64"][2]
+    # the exact tangent K_t + N at the converged state (slip points present): BiCGStab to 1e-8
+    # on b = dJ/dU, against CG on the symmetric tangent
+    S.cohesive_update(U, die0, t0, write_tangent=True)
+    ex = {}
+    for name, kp in (("bicgstab_block_jacobi", 1), ("bicgstab_point_jacobi", 0), ("cg_symmetric_block_jacobi", 1)):
+        S.tune("k_precond", kp)
+        solve = (lambda: S.pcg_solve(fg.FG_K, gU, tol=1e-8, check_every=64)) if name.startswith("cg") else \
+            (lambda: S.exact_solve(gU, tol=1e-8))
+        solve()
+        t_ex, (x_ex, i_ex) = _timed(solve)
+        ex[name] = (t_ex, i_ex.iters, x_ex, i_ex.status)
+        log(f"exact tangent {name}: {t_ex:.3f}s iters {i_ex.iters} status {i_ex.status}")
+    S.tune("k_precond", 0)
+    xb = ex["bicgstab_block_jacobi"][2]
+    r_true = (torch.linalg.norm(gU - S.spmv(fg.FG_K_EXACT, xb)) / torch.linalg.norm(gU)).item()
+    exact = {"rhs": "dJ/dU of the objective at the converged step", "tol": 1e-8, "true_relres_block_jacobi": r_true,
+             "symmetric_vs_exact_rel_l2": (torch.linalg.norm(ex["cg_symmetric_block_jacobi"][2] - xb)
+                                           / torch.linalg.norm(xb)).item()}
+    for name, (t_ex, it_ex, _, st_ex) in ex.items():
+        exact.update({f"{name}_s": t_ex, f"{name}_iters": it_ex, f"{name}_status": st_ex,
+                      f"{name}_k_products": it_ex * (1 if name.startswith("cg") else 2)})
     return {"workload": f"cube64_dip60_hetero one implicit step, {inst.mesh.tets.shape[0]} tets, "
                         f"{2 * inst.mesh.tets.shape[0]} parameters (ln k, E); forward: Newton 1e-8, outer 1e-2, inner "
                         f"1e-4; adjoint: defect 1e-8, corrections outer 0.05 inner 1e-3",
@@ -373,7 +394,7 @@ def extra_adjoint(ctx, log):
             "adjoint_s_f64": res["f64"][0], "adjoint_s_mixed": res["mixed"][0],
             "defect_iters": res["f64"][1].newton_iters, "adjoint_k_iters_f64": res["f64"][1].inner_k_iters,
             "mixed_vs_f64_grad_rel_l2": (torch.linalg.norm(res["mixed"][2] - g64) / torch.linalg.norm(g64)).item(),
-            "slip_points": int((flag == 1).sum())}
+            "slip_points": int((flag == 1).sum()), "exact_tangent_solve": exact}
 
 
 def extra_steps(ctx, log, nsteps=3):

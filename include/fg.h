@@ -61,6 +61,8 @@ typedef int fg_status;
 #define FG_A22 1    /* pressure operator A22 = S + dt C (eq. prevost_system) */
 #define FG_KBULK 2  /* bulk stiffness only (products and export, not solves) */
 #define FG_C 3      /* conductivity C (products and export) */
+#define FG_K_EXACT 4 /* exact tangent K_t + N: K plus the slip term the symmetric tangent omits
+                 (fg_spmv and fg_exact_solve only) */
 
 /* Arithmetic of a K solve. */
 #define FG_F64 0    /* FP64 storage and arithmetic */
@@ -280,6 +282,27 @@ fg_status fg_adjoint_solve(fg_ctx *ctx, fg_system *sys, const double *U, const d
 fg_status fg_slip_adjoint(fg_ctx *ctx, fg_system *sys, const double *U, const double *die_old, const double *t0,
                           const double *a_new, const double *lam_u, double *gU, double *a_old, void *stream);
 
+/* (K_t + N) x = b: the exact interface tangent.  K_t is the current K (its
+ * interface rows written by the last fg_cohesive_update with write_tangent); N is
+ * the part of the exact slip tangent that K_t omits, from the point states of
+ * the last fg_cohesive_update: at a slip point the return map of Sec. 2.2.1 makes
+ * the shear traction's magnitude f t'_n follow the normal opening, d t_s /
+ * d delta_n = -f k_n tau, so the force on the + / - lip of an interface element
+ * gets +-sum_q (A/3) N_a(q) (-f k_n tau_q)(n . jump(x)(q)) (zero at stick and
+ * open points; held DOFs are neither read nor written).  Solved by BiCGStab (van
+ * der Vorst, SIAM J. Sci. Stat. Comput. 13, 1992) from x0 = 0 with the K
+ * preconditioner chosen by fg_tune "k_precond" (0 point Jacobi, 1 or 2 block
+ * Jacobi) applied on the right, stopping on the recursive residual
+ * ||r|| <= opts->tol ||b|| (default 1e-10) or after opts->max_iter iterations
+ * (two products each).  b, x: [3N] device, caller order.  opts->precision must be
+ * FG_F64; check_every and inner_tol are ignored; opts may be NULL.  The host
+ * synchronises three times per iteration.  info (host, may be NULL): iters,
+ * relres (recursive), status.  Returns FG_OK, FG_NOT_CONVERGED, or
+ * FG_ERR_BREAKDOWN (rh.r, rh.v, t.t or omega vanished, or a singular block),
+ * FG_ERR_NAN, FG_ERR_ARG (also for batched systems), FG_ERR_STATE. */
+fg_status fg_exact_solve(fg_ctx *ctx, fg_system *sys, const double *b, double *x, const fg_pcg_opts *opts,
+                         fg_pcg_info *info, void *stream);
+
 /* Interval [lo, hi] (host outputs) of the Chebyshev preconditioner of K
  * ("k_precond" 2, see fg_tune) for the current K, estimated now if K changed
  * since the last estimate: hi = 1.1 x the largest Ritz value of the Lanczos
@@ -293,7 +316,7 @@ fg_status fg_slip_adjoint(fg_ctx *ctx, fg_system *sys, const double *U, const do
 fg_status fg_cheb_interval(fg_ctx *ctx, fg_system *sys, double *lo, double *hi, void *stream);
 
 /* Products on the assembled system, caller order: y = A x for which in
- * {FG_K, FG_A22, FG_KBULK, FG_C}. */
+ * {FG_K, FG_A22, FG_KBULK, FG_C, FG_K_EXACT} (FG_K_EXACT: see fg_exact_solve). */
 fg_status fg_spmv(fg_ctx *ctx, fg_system *sys, int which, const double *x, double *y, void *stream);
 
 /* Coupling products (Appendix A eq. Apdp / Adpd, Appendix B eq. afdpd and its

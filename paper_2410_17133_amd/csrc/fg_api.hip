@@ -969,6 +969,40 @@ fg_status fg_slip_adjoint(fg_ctx *ctx, fg_system *S, const double *U, const doub
     return check_hip("fg_slip_adjoint");
 }
 
+fg_status fg_exact_solve(fg_ctx *ctx, fg_system *S, const double *b, double *x, const fg_pcg_opts *opts,
+                         fg_pcg_info *info, void *stream)
+{
+    if (!ctx || !S || !b || !x) {
+        set_error("fg_exact_solve: bad argument");
+        return FG_ERR_ARG;
+    }
+    const fg_pcg_opts o = defaults(opts, 1e-10);
+    if (o.precision != FG_F64) {
+        set_error("fg_exact_solve: only FG_F64 is supported");
+        return FG_ERR_ARG;
+    }
+    if (!ready(S)) return FG_ERR_STATE;
+    if (S->ngroups > 1) {
+        set_error("fg_exact_solve: batched systems are not supported");
+        return FG_ERR_ARG;
+    }
+    Guard g(ctx->device);
+    hipStream_t st = S_(stream);
+    perm_in(S, 3, b, S->pv2, st);
+    int64_t it = 0;
+    double rel = 0;
+    fg_status s = bicgstab_exact(S, S->pv2, S->wx, o.tol, o.max_iter, &it, &rel, st);
+    perm_out(S, 3, S->wx, x, st);
+    if (info) {
+        info->iters = it;
+        info->cycles = 1;
+        info->relres = rel;
+        info->status = s;
+    }
+    fg_status e = check_hip("fg_exact_solve");
+    return e ? e : s;
+}
+
 fg_status fg_cheb_interval(fg_ctx *ctx, fg_system *S, double *lo, double *hi, void *stream)
 {
     if (!ctx || !S || !lo || !hi) {
@@ -991,17 +1025,20 @@ fg_status fg_cheb_interval(fg_ctx *ctx, fg_system *S, double *lo, double *hi, vo
 
 fg_status fg_spmv(fg_ctx *ctx, fg_system *S, int which, const double *x, double *y, void *stream)
 {
-    if (!ctx || !S || !x || !y || which < 0 || which > 3) {
+    if (!ctx || !S || !x || !y || which < 0 || which > FG_K_EXACT) {
         set_error("fg_spmv: bad argument");
         return FG_ERR_ARG;
     }
     if (!ready(S)) return FG_ERR_STATE;
     Guard g(ctx->device);
     hipStream_t st = S_(stream);
-    const int bs = (which == FG_K || which == FG_KBULK) ? 3 : 1;
+    const int bs = (which == FG_K || which == FG_KBULK || which == FG_K_EXACT) ? 3 : 1;
     double *xi = bs == 3 ? S->pv1 : S->s7, *yi = bs == 3 ? S->pv2 : S->s8;
     perm_in(S, bs, x, xi, st);
-    spmv(S, which, xi, yi, st);
+    if (which == FG_K_EXACT)
+        spmv_exact(S, xi, yi, st);
+    else
+        spmv(S, which, xi, yi, st);
     perm_out(S, bs, yi, y, st);
     return check_hip("fg_spmv");
 }

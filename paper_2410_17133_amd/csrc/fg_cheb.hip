@@ -349,6 +349,11 @@ fg_status cheb_estimate(fg_system *S, hipStream_t st)
 
 }  // namespace
 
+void bj_apply(fg_system *S, const double *in, double *out, hipStream_t st)
+{
+    LAUNCH(k_ch_bj, grid_elems(S->Npad), WG, st, S->Npad, bj_view(S), in, out);
+}
+
 fg_status cheb_interval_ready(fg_system *S, hipStream_t st)
 {
     bj_ready(S, st);

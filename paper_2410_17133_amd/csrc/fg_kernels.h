@@ -67,6 +67,15 @@ fg_status cheb_cg(fg_system *S, const double *b, double *x, double tol, int64_t 
                   double *relres, hipStream_t st);
 // Spectrum interval of the Chebyshev preconditioner for the current K (estimated if stale).
 fg_status cheb_interval_ready(fg_system *S, hipStream_t st);
+// out = M^-1 in with the block-Jacobi data (bj_ready first).
+void bj_apply(fg_system *S, const double *in, double *out, hipStream_t st);
+
+// Exact interface tangent (fg_exact.hip): y += N x (slip part of the last
+// interface update), y = (K_t + N) x, and BiCGStab on K_t + N (internal order).
+void apply_N_add(fg_system *S, const double *x, double *y, hipStream_t st);
+void spmv_exact(fg_system *S, const double *x, double *y, hipStream_t st);
+fg_status bicgstab_exact(fg_system *S, const double *b, double *x, double tol, int64_t maxit, int64_t *iters,
+                         double *relres, hipStream_t st);
 
 // float <-> double conversions with a scale: y = (T)(s * x)
 void to_f32(int64_t n, double s, const double *x, float *y, hipStream_t st);

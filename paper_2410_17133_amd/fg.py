@@ -15,13 +15,13 @@ LIB_PATH = os.path.join(HERE, "libfg.so")
 
 FG_OK, FG_NOT_CONVERGED = 0, 1
 FG_ERR_ARG, FG_ERR_OOM, FG_ERR_BREAKDOWN, FG_ERR_NAN, FG_ERR_HIP, FG_ERR_STATE = -1, -2, -3, -4, -5, -6
-FG_K, FG_A22, FG_KBULK, FG_C = 0, 1, 2, 3
+FG_K, FG_A22, FG_KBULK, FG_C, FG_K_EXACT = 0, 1, 2, 3, 4
 FG_F64, FG_F32, FG_MIXED, FG_MIXED_F32VAL = 0, 1, 2, 3
 
 SYMBOLS = ["fg_last_error", "fg_ctx_create", "fg_ctx_destroy", "fg_system_create", "fg_system_destroy",
            "fg_assemble", "fg_cohesive_update", "fg_pcg_solve", "fg_flow_solve", "fg_step", "fg_spmv",
            "fg_coupling", "fg_residual", "fg_system_sizes", "fg_export", "fg_profile", "fg_profile_read", "fg_tune", "fg_adjoint_solve", "fg_group_stats",
-           "fg_assemble_groups", "fg_slip_adjoint", "fg_cheb_interval"]
+           "fg_assemble_groups", "fg_slip_adjoint", "fg_cheb_interval", "fg_exact_solve"]
 
 
 class FgError(RuntimeError):
@@ -97,6 +97,7 @@ def lib():
             "fg_profile_read": [vp, i32, C.POINTER(i64), C.POINTER(dbl), i32],
             "fg_slip_adjoint": [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
             "fg_cheb_interval": [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double), vp],
+            "fg_exact_solve": [vp, vp, vp, vp, C.POINTER(PcgOpts), C.POINTER(PcgInfo), vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -223,6 +224,17 @@ class System:
         _check(st)
         return x, info
 
+    def exact_solve(self, b, **kw):
+        """(K_t + N) x = b by BiCGStab (fg_exact_solve): the exact interface tangent of the last
+        interface update.  Returns (x, info)."""
+        n = 3 * self.N
+        x = self._d(n)
+        info = PcgInfo()
+        st = lib().fg_exact_solve(self.ctx._h, self._h, _ptr(b, torch.float64, n, "b"), _ptr(x, torch.float64),
+                                  C.byref(opts(**kw)), C.byref(info), _stream())
+        _check(st)
+        return x, info
+
     def flow_solve(self, b_u, b_p, inner_k=None, inner_p=None, outer_tol=1e-10, outer_max_iter=1000):
         du, dp = self._d(3 * self.N), self._d(self.N)
         info = SolveInfo()
@@ -294,7 +306,7 @@ class System:
         return lo.value, hi.value
 
     def spmv(self, which, x):
-        n = (3 if which in (FG_K, FG_KBULK) else 1) * self.N
+        n = (3 if which in (FG_K, FG_KBULK, FG_K_EXACT) else 1) * self.N
         y = self._d(n)
         _check(lib().fg_spmv(self.ctx._h, self._h, which, _ptr(x, torch.float64, n, "x"), _ptr(y, torch.float64),
                              _stream()), False)

@@ -137,6 +137,17 @@ def test_pcg_iterates_full_size(full):
           f"rel {relerr(host(xc), xco):.2e}", flush=True)
     assert abs(hi - ohi) <= 1e-8 * ohi and abs(lo - olo) <= 1e-8 * olo
     assert ic.iters == it == 50 and relerr(host(xc), xco) < 1e-10
+    # exact tangent K_t + N: product, and 10 BiCGStab iterates with block Jacobi
+    yo = P.spmv(O.K_TANGENT, b) + P.apply_N(b)
+    assert relerr(host(S.spmv(fg.FG_K_EXACT, dev(b))), yo) < 1e-13
+    S.tune("k_precond", 1)
+    try:
+        xe, ie = S.exact_solve(dev(b), tol=1e-300, max_iter=10)
+    finally:
+        S.tune("k_precond", 0)
+    xeo, st, it, rr = P.bicgstab_exact(b, tol=1e-300, maxit=10)
+    print(f"[exact K] rel {relerr(host(xe), xeo):.2e}", flush=True)
+    assert ie.iters == it == 10 and relerr(host(xe), xeo) < 1e-9
 
 
 def test_adjoint_identities_full_size(full):

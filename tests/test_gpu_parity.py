@@ -338,6 +338,53 @@ def test_step_with_chebyshev_reaches_the_same_state():
     assert relerr(host(U), Uo) < 1e-9 and relerr(host(Pp), Po) < 1e-9
 
 
+@pytest.mark.parametrize("name", ["cube12_dip60_hetero", "cube10_dip35_hetero"])
+def test_exact_tangent_product_and_bicgstab_match_oracle(name):
+    """FG_K_EXACT / fg_exact_solve: (K_t + N) v equals the oracle's K_t v + N v with
+    slip points present; with block Jacobi the first 10 BiCGStab iterates and the
+    converged solve equal the oracle's; point Jacobi reaches the same solution."""
+    fg, O = _fg(), _oracle()
+    inst, ctx, S, P = setup(name)
+    print(f"[case] exact tangent {name}", flush=True)
+    r = np.random.default_rng(21)
+    U = r.normal(0.0, 2e-5 / inst.cfg.n, 3 * S.N) * (1 - inst.dir_u)
+    flags = P.cohesive(U, np.zeros((P.nq, 2)))[2]
+    S.cohesive_update(dev(U), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)))
+    assert (flags == 1).sum() > 0
+    free = 1.0 - inst.dir_u
+    v = r.standard_normal(3 * S.N) * free
+    yo = P.spmv(O.K_TANGENT, v) + P.apply_N(v)
+    y = host(S.spmv(fg.FG_K_EXACT, dev(v)))
+    assert relerr(y, yo) < 1e-13
+    assert np.abs(P.apply_N(v)).max() > 1e-6 * np.abs(yo).max()
+    b = r.standard_normal(3 * S.N) * free
+    xo1, st, it1, rr1 = P.bicgstab_exact(b, tol=1e-11)
+    assert st == 0
+    S.tune("k_precond", 1)
+    try:
+        x10, i10 = S.exact_solve(dev(b), tol=1e-300, max_iter=10)
+        xo10, st, it, rr = P.bicgstab_exact(b, tol=1e-300, maxit=10)
+        assert i10.iters == it == 10 and i10.status == fg.FG_NOT_CONVERGED
+        assert relerr(host(x10), xo10) < 1e-9
+        x1, i1 = S.exact_solve(dev(b), tol=1e-11)
+        print(f"[exact] block Jacobi BiCGStab {i1.iters} iterations (oracle {it1})", flush=True)
+        assert i1.status == 0 and abs(i1.iters - it1) <= max(3, 0.05 * it1)
+        res = np.linalg.norm(b - P.spmv(O.K_TANGENT, host(x1)) - P.apply_N(host(x1))) / np.linalg.norm(b)
+        assert res <= 1e-9 and relerr(host(x1), xo1) < 1e-8
+        with pytest.raises(fg.FgError):
+            S.exact_solve(dev(b), precision=fg.FG_F32)
+        x0, i0 = S.exact_solve(dev(np.zeros(3 * S.N)))
+        assert i0.status == 0 and i0.iters == 0 and not host(x0).any()
+    finally:
+        S.tune("k_precond", 0)
+    x2, i2 = S.exact_solve(dev(b), tol=1e-11)
+    print(f"[exact] point Jacobi BiCGStab {i2.iters} iterations", flush=True)
+    assert i2.status == 0 and relerr(host(x2), xo1) < 1e-8
+    # the symmetric tangent's solution differs: N matters at these slip points
+    xs, _ = S.pcg_solve(fg.FG_K, dev(b), tol=1e-11)
+    assert relerr(host(xs), xo1) > 1e-6
+
+
 def test_pcg_global_gather_path_matches():
     fg, O = _fg(), _oracle()
     inst, ctx, S, P = setup("cube16_dip70")
