@@ -378,6 +378,23 @@ def extra_adjoint(ctx, log):
         log(f"exact tangent {name}: {t_ex:.3f}s iters {i_ex.iters} status {i_ex.status}")
     S.tune("k_precond", 0)
     xb = ex["bicgstab_block_jacobi"][2]
+    # the forward step again, block-Jacobi K solves, with the symmetric and with the exact tangent
+    fwd = {}
+    S.tune("k_precond", 1)
+    for et in (0, 1):
+        S.tune("exact_tangent", et)
+        U2, P2, die2 = d(np.zeros(3 * S.N)), d(np.zeros(S.N)), d(np.zeros(2 * S.nq))
+        t_f, (_, flag2, finfo2) = _timed(lambda: S.step(U2, P2, die2, t0, d(inst.load), d(inst.source),
+                                                         newton_tol=1e-8, newton_max_iter=60, inner_k=inner,
+                                                         inner_p=inner, outer_tol=1e-2))
+        name = "exact" if et else "symmetric"
+        log(f"forward step, block Jacobi, {name} tangent: {t_f:.2f}s newton {finfo2.newton_iters} cuts "
+            f"{finfo2.step_cuts} K iters {finfo2.inner_k_iters} status {finfo2.status}")
+        fwd[name] = {"s": t_f, "newton": finfo2.newton_iters, "step_cuts": finfo2.step_cuts,
+                     "k_iters": finfo2.inner_k_iters, "status": finfo2.status,
+                     "vs_first_step_rel_l2": (torch.linalg.norm(U2 - U) / torch.linalg.norm(U)).item()}
+    S.tune("exact_tangent", 0)
+    S.tune("k_precond", 0)
     r_true = (torch.linalg.norm(gU - S.spmv(fg.FG_K_EXACT, xb)) / torch.linalg.norm(gU)).item()
     exact = {"rhs": "dJ/dU of the objective at the converged step", "tol": 1e-8, "true_relres_block_jacobi": r_true,
              "symmetric_vs_exact_rel_l2": (torch.linalg.norm(ex["cg_symmetric_block_jacobi"][2] - xb)
@@ -394,7 +411,8 @@ def extra_adjoint(ctx, log):
             "adjoint_s_f64": res["f64"][0], "adjoint_s_mixed": res["mixed"][0],
             "defect_iters": res["f64"][1].newton_iters, "adjoint_k_iters_f64": res["f64"][1].inner_k_iters,
             "mixed_vs_f64_grad_rel_l2": (torch.linalg.norm(res["mixed"][2] - g64) / torch.linalg.norm(g64)).item(),
-            "slip_points": int((flag == 1).sum()), "exact_tangent_solve": exact}
+            "slip_points": int((flag == 1).sum()), "exact_tangent_solve": exact,
+            "forward_block_jacobi": fwd}
 
 
 def extra_steps(ctx, log, nsteps=3):

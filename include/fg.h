@@ -376,6 +376,14 @@ fg_status fg_group_stats(const fg_system *sys, int64_t *iters_h, double *relres_
  *               interval are rebuilt after every change of K; FG_ERR_BREAKDOWN if
  *               a block is singular.  Block (nrhs > 1), batched and
  *               FG_MIXED_F32VAL solves keep point Jacobi.
+ *   "exact_tangent": 1 makes the FP64 K solves inside fg_flow_solve and fg_step
+ *               solve the exact tangent K_t + N by BiCGStab (as fg_exact_solve),
+ *               so that Newton uses the exact Jacobian of the interface force;
+ *               the outer partitioned CG then runs on a Schur complement that
+ *               is not exactly symmetric.  0 (default): the symmetric tangent.
+ *               fg_pcg_solve and fg_adjoint_solve always use the symmetric
+ *               tangent (the adjoint lags N^T by defect correction itself);
+ *               mixed-precision K solves stay symmetric.
  *   "cheb_degree": degree of the Chebyshev polynomial, 1 to 16 (default 4;
  *               1 is block Jacobi scaled by 1/theta: same iterates).
  *   "cheb_ratio": hi / lo of the interval, 2 to 1000000 (default 300).

@@ -108,6 +108,15 @@ fg_pcg_opts defaults(const fg_pcg_opts *o, double tol)
     return d;
 }
 
+// Holds the K solves on the symmetric tangent for its lifetime (restores fg_tune
+// "exact_tangent" on every return path).
+struct SymmetricSolves {
+    fg_system *S;
+    int saved;
+    explicit SymmetricSolves(fg_system *s) : S(s), saved(s->exact_tangent) { S->exact_tangent = 0; }
+    ~SymmetricSolves() { S->exact_tangent = saved; }
+};
+
 // K solve on internal vectors: rhs (3 Npad) -> out (3 Npad).
 fg_status k_solve(fg_system *S, const double *rhs, double *out, const fg_pcg_opts &o, fg_pcg_info *info, hipStream_t st)
 {
@@ -116,7 +125,9 @@ fg_status k_solve(fg_system *S, const double *rhs, double *out, const fg_pcg_opt
         int64_t it = 0;
         double rr = 0;
         fg_status s;
-        if (o.precision == FG_F64 && S->k_precond == 2 && S->ngroups == 1) {
+        if (o.precision == FG_F64 && S->exact_tangent && S->ngroups == 1) {
+            s = bicgstab_exact(S, rhs, out, o.tol, o.max_iter, &it, &rr, st);
+        } else if (o.precision == FG_F64 && S->k_precond == 2 && S->ngroups == 1) {
             s = cheb_cg(S, rhs, out, o.tol, o.max_iter, o.check_every, &it, &rr, st);
         } else if (o.precision == FG_F64) {
             hipMemcpyAsync(S->wr, rhs, n * sizeof(double), hipMemcpyDeviceToDevice, st);
@@ -386,7 +397,7 @@ fg_status fg_system_destroy(fg_system *S)
                     S->fr, S->fp, S->fq, S->v1, S->v2, S->v3, S->v4, S->pv1, S->pv2, S->ui, S->ui0, S->fi, S->rm,
                     S->du, S->fc, S->s1, S->s2, S->s3, S->s4, S->s5, S->s6, S->s7, S->s8, S->pi, S->pi0, S->qi,
                     S->rf, S->dpv, S->die0, S->partials, S->sc, S->red, S->red_counter, S->fslot, S->fpart,
-                    S->bjA, S->bjB, S->wz, S->bjA32, S->bjB32, S->wz32, S->chd, S->chs, S->chq};
+                    S->bjA, S->bjB, S->wz, S->bjA32, S->bjB32, S->wz32, S->chd, S->chs, S->chq, S->bx};
     for (void *p : ptrs) dfree(p);
     drop_graphs(S);
     drop_mr_graphs(S);
@@ -629,6 +640,7 @@ fg_status fg_pcg_solve(fg_ctx *ctx, fg_system *S, int which, int nrhs, const dou
     }
     if (!ready(S)) return FG_ERR_STATE;
     Guard g(ctx->device);
+    SymmetricSolves sym(S);  // CG: always the symmetric tangent
     hipStream_t st = S_(stream);
     fg_pcg_opts o = defaults(opts, 1e-10);
     if (opts && !(opts->tol > 0)) {
@@ -862,6 +874,8 @@ fg_status fg_adjoint_solve(fg_ctx *ctx, fg_system *S, const double *U, const dou
     }
     if (!ready(S)) return FG_ERR_STATE;
     Guard g(ctx->device);
+    // the defect correction solves with the symmetric tangent and lags N^T itself
+    SymmetricSolves sym(S);
     hipStream_t st = S_(stream);
     const int64_t n1 = 3 * S->Npad, n2 = S->Npad;
     fg_pcg_opts ok = defaults(inner_k, 1e-12), op = defaults(inner_p, 1e-12);
@@ -985,6 +999,10 @@ fg_status fg_exact_solve(fg_ctx *ctx, fg_system *S, const double *b, double *x, 
     if (S->ngroups > 1) {
         set_error("fg_exact_solve: batched systems are not supported");
         return FG_ERR_ARG;
+    }
+    if (!S->bx && dalloc(&S->bx, 15 * S->Npad)) {
+        set_error("fg_exact_solve: device allocation of the BiCGStab work vectors failed");
+        return FG_ERR_OOM;
     }
     Guard g(ctx->device);
     hipStream_t st = S_(stream);
@@ -1179,6 +1197,18 @@ fg_status fg_tune(fg_system *S, const char *key, int64_t value)
         }
         S->spmv_unroll = (int)value;
         drop_graphs(S);
+        return FG_OK;
+    }
+    if (std::strcmp(key, "exact_tangent") == 0) {
+        if (value > 1) {
+            set_error("fg_tune: exact_tangent must be 0 or 1");
+            return FG_ERR_ARG;
+        }
+        if (value == 1 && !S->bx && dalloc(&S->bx, 15 * S->Npad)) {
+            set_error("fg_tune: device allocation of the BiCGStab work vectors failed");
+            return FG_ERR_OOM;
+        }
+        S->exact_tangent = (int)value;
         return FG_OK;
     }
     if (std::strcmp(key, "cheb_degree") == 0) {

@@ -111,7 +111,13 @@ fg_status bicgstab_exact(fg_system *S, const double *b, double *x, double tol, i
             return FG_ERR_BREAKDOWN;
         }
     }
-    double *r = S->wr, *rh = S->v1, *p = S->wp, *v = S->wq, *ph = S->v2, *s = S->v3, *sh = S->v4, *t = S->pv1;
+    if (!S->bx) {
+        set_error("fg_exact_solve: BiCGStab work vectors not allocated");
+        return FG_ERR_STATE;
+    }
+    // r, p, v share CG's work vectors; the caller's b and x are none of these
+    double *r = S->wr, *p = S->wp, *v = S->wq;
+    double *rh = S->bx, *ph = S->bx + n, *s = S->bx + 2 * n, *sh = S->bx + 3 * n, *t = S->bx + 4 * n;
     auto dots2 = [&](const double *a0, const double *b0, const double *a1, const double *b1, double *h) {
         const double *A[2] = {a0, a1}, *B[2] = {b0, b1};
         vdots(S, n, 2, A, B, h, st);

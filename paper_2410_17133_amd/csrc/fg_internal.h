@@ -146,6 +146,8 @@ struct fg_system {
     int cheb_lanczos = 40;      // fg_tune "cheb_lanczos": CG steps of the spectrum estimate
     double cheb_lo = 0, cheb_hi = 0;  // interval of the last estimate
     int64_t cheb_epoch = -1;    // bj_epoch of the last estimate
+    int exact_tangent = 0;      // fg_tune "exact_tangent": FP64 K solves of the forward path on K_t + N
+    double *bx = nullptr;       // [5*3*Npad] BiCGStab work vectors (rh, ph, s, sh, t)
     uint8_t *dir_u = nullptr, *dir_p = nullptr;
     double *tri_geo = nullptr;  // [nf*10]: area, n[3], t1[3], t2[3]
     // operators

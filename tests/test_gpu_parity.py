@@ -385,6 +385,53 @@ def test_exact_tangent_product_and_bicgstab_match_oracle(name):
     assert relerr(host(xs), xo1) > 1e-6
 
 
+@pytest.mark.parametrize("case", ["cube8", "slip4"])
+def test_step_with_exact_tangent_reaches_the_same_state(case):
+    """fg_tune exact_tangent 1: Newton with K_t + N (BiCGStab K solves inside the
+    partitioned iteration) converges to the oracle's state (the root does not depend
+    on the tangent) in no more Newton iterations than the symmetric tangent; slip4 is
+    a 4^3 cube whose converged step has slip points."""
+    import dataclasses
+    fg, O = _fg(), _oracle()
+    if case == "slip4":
+        inst = I.make_instance(dataclasses.replace(I.cube_config(4), Q=4e-3))
+        ctx = fg.Context(0)
+        S = fg.System.from_instance(ctx, inst)
+        S.assemble(inst.params, inst.E, inst.logk)
+        P = O.Problem(inst)
+    else:
+        inst, ctx, S, P = setup("cube8")
+    print(f"[case] exact-tangent step {case}", flush=True)
+    N, nq = S.N, S.nq
+    Uo, Po, dieo = np.zeros(3 * N), np.zeros(N), np.zeros((nq, 2))
+    trac_o, flag_o, info_o, st_o = P.step(Uo, Po, dieo, tol_newton=1e-11, max_newton=60, tol_outer=1e-12,
+                                          tol_inner=1e-13)
+    assert st_o == 0
+    kw = dict(newton_tol=1e-11, newton_max_iter=60, inner_k=fg.opts(tol=1e-13), inner_p=fg.opts(tol=1e-13),
+              outer_tol=1e-12)
+    infos = {}
+    S.tune("k_precond", 1)
+    try:
+        for et in (0, 1):
+            S.tune("exact_tangent", et)
+            U, Pp, die = dev(np.zeros(3 * N)), dev(np.zeros(N)), dev(np.zeros(2 * nq))
+            trac, flag, info = S.step(U, Pp, die, dev(inst.t0.reshape(-1)), dev(inst.load), dev(inst.source), **kw)
+            assert info.status == 0
+            assert relerr(host(U), Uo) < 1e-9 and relerr(host(Pp), Po) < 1e-9
+            infos[et] = info
+    finally:
+        S.tune("exact_tangent", 0)
+        S.tune("k_precond", 0)
+    print(f"[exact step] slip points {int((flag_o == 1).sum())}; Newton iterations symmetric "
+          f"{infos[0].newton_iters} (cuts {infos[0].step_cuts}), exact {infos[1].newton_iters} "
+          f"(cuts {infos[1].step_cuts})", flush=True)
+    assert infos[1].newton_iters <= infos[0].newton_iters
+    if case == "slip4":
+        assert (flag_o == 1).sum() > 0 and infos[1].newton_iters < infos[0].newton_iters
+    with pytest.raises(fg.FgError):
+        S.tune("exact_tangent", 2)
+
+
 def test_pcg_global_gather_path_matches():
     fg, O = _fg(), _oracle()
     inst, ctx, S, P = setup("cube16_dip70")
