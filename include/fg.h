@@ -295,8 +295,8 @@ fg_status fg_slip_adjoint(fg_ctx *ctx, fg_system *sys, const double *U, const do
  * Jacobi) applied on the right, stopping on the recursive residual
  * ||r|| <= opts->tol ||b|| (default 1e-10) or after opts->max_iter iterations
  * (two products each).  b, x: [3N] device, caller order.  opts->precision must be
- * FG_F64; check_every and inner_tol are ignored; opts may be NULL.  The host
- * synchronises three times per iteration.  info (host, may be NULL): iters,
+ * FG_F64; check_every and inner_tol are ignored; opts may be NULL.  The
+ * iteration's scalars stay in device memory; the host polls every 16 iterations.  info (host, may be NULL): iters,
  * relres (recursive), status.  Returns FG_OK, FG_NOT_CONVERGED, or
  * FG_ERR_BREAKDOWN (rh.r, rh.v, t.t or omega vanished, or a singular block),
  * FG_ERR_NAN, FG_ERR_ARG (also for batched systems), FG_ERR_STATE. */

@@ -1000,7 +1000,7 @@ fg_status fg_exact_solve(fg_ctx *ctx, fg_system *S, const double *b, double *x, 
         set_error("fg_exact_solve: batched systems are not supported");
         return FG_ERR_ARG;
     }
-    if (!S->bx && dalloc(&S->bx, 15 * S->Npad)) {
+    if (!S->bx && dalloc(&S->bx, bx_len(S))) {
         set_error("fg_exact_solve: device allocation of the BiCGStab work vectors failed");
         return FG_ERR_OOM;
     }
@@ -1204,7 +1204,7 @@ fg_status fg_tune(fg_system *S, const char *key, int64_t value)
             set_error("fg_tune: exact_tangent must be 0 or 1");
             return FG_ERR_ARG;
         }
-        if (value == 1 && !S->bx && dalloc(&S->bx, 15 * S->Npad)) {
+        if (value == 1 && !S->bx && dalloc(&S->bx, bx_len(S))) {
             set_error("fg_tune: device allocation of the BiCGStab work vectors failed");
             return FG_ERR_OOM;
         }

@@ -66,6 +66,165 @@ __global__ void k_n_rows(int64_t nfr, const int32_t *__restrict__ frows, const i
         if (!dir_u[3 * row + r]) y[3 * row + r] += acc[r];
 }
 
+// Device-resident scalars of one BiCGStab solve, kept after the work vectors in
+// S->bx.  rho (rh.r) is kept per iteration parity: the kernel that forms the new
+// value reads the current slot and writes the other.
+struct BiScalars {
+    double rho[2];
+    double alpha, omega;
+    double rr, bb, tol2;
+    int64_t iters, maxit;
+    int32_t done, status;
+};
+static_assert(sizeof(BiScalars) <= BX_TAIL * sizeof(double), "BiCGStab scalars exceed their room");
+
+// x = 0, r = rh = b, p = v = 0; partials of rh.r and r.r (rows 2, 3); scalars reset.
+__global__ __launch_bounds__(WG) void k_bi_init(int64_t n, int64_t maxit, const double *__restrict__ b,
+                                                double *__restrict__ x, double *__restrict__ r,
+                                                double *__restrict__ rh, double *__restrict__ p,
+                                                double *__restrict__ v, double *partials, int64_t stride,
+                                                BiScalars *sc)
+{
+    double acc[2] = {0, 0};
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double bi = b[i];
+        x[i] = 0.0;
+        r[i] = bi;
+        rh[i] = bi;
+        p[i] = 0.0;
+        v[i] = 0.0;
+        acc[0] += bi * bi;
+    }
+    acc[1] = acc[0];
+    block_partials<2>(acc, partials + 2 * stride, stride);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->rho[0] = sc->rho[1] = 1.0;
+        sc->alpha = sc->omega = 1.0;
+        sc->rr = sc->bb = sc->tol2 = 0.0;
+        sc->iters = 0;
+        sc->maxit = maxit;
+        sc->done = 0;
+        sc->status = FG_OK;
+    }
+}
+
+// Top of an iteration: rho' = rh.r and r.r from rows 2, 3; the stop tests in the
+// order NaN, ||r|| <= tol ||b||, iteration cap, breakdown (rho' or omega zero);
+// beta = (rho'/rho)(alpha/omega), p = r + beta (p - omega v).
+__global__ __launch_bounds__(WG) void k_bi_p(int64_t n, int par, int first, double tol, const double *__restrict__ r,
+                                             double *__restrict__ p, const double *__restrict__ v,
+                                             const double *partials, int64_t stride, int64_t nparts, BiScalars *sc)
+{
+    if (__syncthreads_or(sc->done)) return;
+    double tot[2];
+    finalize_sum<2>(partials + 2 * stride, stride, nparts, tot);
+    const double rho1 = tot[0], rr = tot[1];
+    const double tol2 = first ? tol * tol * rr : sc->tol2;
+    const double omega = sc->omega;
+    const bool finite = isfinite(rho1) && isfinite(rr);
+    const bool conv = rr <= tol2;
+    const bool capped = sc->iters >= sc->maxit;
+    const bool broken = rho1 == 0.0 || omega == 0.0;
+    const bool stop = !finite || conv || capped || broken;
+    const double beta = (rho1 / sc->rho[par]) * (sc->alpha / omega);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (first) {
+            sc->bb = rr;
+            sc->tol2 = tol2;
+        }
+        sc->rr = rr;
+        sc->rho[par ^ 1] = rho1;
+        if (stop) {
+            sc->status = !finite ? FG_ERR_NAN : conv ? FG_OK : capped ? FG_NOT_CONVERGED : FG_ERR_BREAKDOWN;
+            sc->done = 1;
+        }
+    }
+    if (stop) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = r[i] + beta * (p[i] - omega * v[i]);
+}
+
+// Partials of a.b (row 0).
+__global__ __launch_bounds__(WG) void k_bi_dot(int64_t n, const double *__restrict__ a, const double *__restrict__ b,
+                                               double *partials, int64_t stride)
+{
+    double acc[1] = {0};
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        acc[0] += a[i] * b[i];
+    block_partials<1>(acc, partials, stride);
+}
+
+// alpha = rho' / (rh.v) from row 0; s = r - alpha v.
+__global__ __launch_bounds__(WG) void k_bi_s(int64_t n, int par, const double *__restrict__ r,
+                                             const double *__restrict__ v, double *__restrict__ s,
+                                             const double *partials, int64_t stride, int64_t nparts, BiScalars *sc)
+{
+    if (__syncthreads_or(sc->done)) return;
+    double tot[1];
+    finalize_sum<1>(partials, stride, nparts, tot);
+    const double rv = tot[0];
+    const bool ok = isfinite(rv) && rv != 0.0;
+    const double alpha = sc->rho[par ^ 1] / rv;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (ok) {
+            sc->alpha = alpha;
+        } else {
+            sc->status = isfinite(rv) ? FG_ERR_BREAKDOWN : FG_ERR_NAN;
+            sc->done = 1;
+        }
+    }
+    if (!ok) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        s[i] = r[i] - alpha * v[i];
+}
+
+// Partials of t.s and t.t (rows 0, 1).
+__global__ __launch_bounds__(WG) void k_bi_dot2(int64_t n, const double *__restrict__ t, const double *__restrict__ s,
+                                                double *partials, int64_t stride)
+{
+    double acc[2] = {0, 0};
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double ti = t[i];
+        acc[0] += ti * s[i];
+        acc[1] += ti * ti;
+    }
+    block_partials<2>(acc, partials, stride);
+}
+
+// omega = (t.s)/(t.t) from rows 0, 1; x += alpha ph + omega sh, r = s - omega t;
+// partials of rh.r and r.r for the next iteration (rows 2, 3).
+__global__ __launch_bounds__(WG) void k_bi_xr(int64_t n, double *__restrict__ x, double *__restrict__ r,
+                                              const double *__restrict__ ph, const double *__restrict__ sh,
+                                              const double *__restrict__ s, const double *__restrict__ t,
+                                              const double *__restrict__ rh, double *partials, int64_t stride,
+                                              int64_t nparts, BiScalars *sc)
+{
+    if (__syncthreads_or(sc->done)) return;
+    double tot[2];
+    finalize_sum<2>(partials, stride, nparts, tot);
+    const bool ok = isfinite(tot[0]) && isfinite(tot[1]) && tot[1] != 0.0;
+    const double omega = tot[0] / tot[1], alpha = sc->alpha;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (ok) {
+            sc->omega = omega;
+            sc->iters += 1;
+        } else {
+            sc->status = (isfinite(tot[0]) && isfinite(tot[1])) ? FG_ERR_BREAKDOWN : FG_ERR_NAN;
+            sc->done = 1;
+        }
+    }
+    if (!ok) return;
+    double acc[2] = {0, 0};
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        x[i] += alpha * ph[i] + omega * sh[i];
+        const double ri = s[i] - omega * t[i];
+        r[i] = ri;
+        acc[0] += rh[i] * ri;
+        acc[1] += ri * ri;
+    }
+    block_partials<2>(acc, partials + 2 * stride, stride);
+}
+
 __global__ void k_dmul(int64_t n, const double *__restrict__ d, const double *__restrict__ x, double *__restrict__ y)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -118,78 +277,37 @@ fg_status bicgstab_exact(fg_system *S, const double *b, double *x, double tol, i
     // r, p, v share CG's work vectors; the caller's b and x are none of these
     double *r = S->wr, *p = S->wp, *v = S->wq;
     double *rh = S->bx, *ph = S->bx + n, *s = S->bx + 2 * n, *sh = S->bx + 3 * n, *t = S->bx + 4 * n;
-    auto dots2 = [&](const double *a0, const double *b0, const double *a1, const double *b1, double *h) {
-        const double *A[2] = {a0, a1}, *B[2] = {b0, b1};
-        vdots(S, n, 2, A, B, h, st);
-    };
-    vfill(x, 0.0, n, st);
-    vfill(p, 0.0, n, st);
-    vfill(v, 0.0, n, st);
-    hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, st);
-    hipMemcpyAsync(rh, b, n * sizeof(double), hipMemcpyDeviceToDevice, st);
-    double h[2];
-    dots2(b, b, b, b, h);
-    const double bn = std::sqrt(h[0]);
-    if (!std::isfinite(bn)) {
-        set_error("fg_exact_solve: NaN or Inf in the right-hand side");
-        return FG_ERR_NAN;
+    BiScalars *sc = (BiScalars *)(S->bx + 5 * n);
+    double *part = S->partials;
+    const int64_t stride = S->npartials, gv = grid_vec(n);
+    LAUNCH(k_bi_init, gv, WG, st, n, maxit, b, x, r, rh, p, v, part, stride, sc);
+    fg_status e = check_hip("fg_exact_solve init");
+    if (e) return e;
+    BiScalars h{};
+    for (int64_t k = 0;;) {
+        for (int j = 0; j < 16; ++j, ++k) {
+            const int par = (int)(k & 1);
+            LAUNCH(k_bi_p, gv, WG, st, n, par, (int)(k == 0), tol, r, p, v, part, stride, gv, sc);
+            precond(S, p, ph, st);
+            spmv_exact(S, ph, v, st);
+            LAUNCH(k_bi_dot, gv, WG, st, n, rh, v, part, stride);
+            LAUNCH(k_bi_s, gv, WG, st, n, par, r, v, s, part, stride, gv, sc);
+            precond(S, s, sh, st);
+            spmv_exact(S, sh, t, st);
+            LAUNCH(k_bi_dot2, gv, WG, st, n, t, s, part, stride);
+            LAUNCH(k_bi_xr, gv, WG, st, n, x, r, ph, sh, s, t, rh, part, stride, gv, sc);
+        }
+        hipMemcpyAsync(&h, sc, sizeof h, hipMemcpyDeviceToHost, st);
+        hipStreamSynchronize(st);
+        e = check_hip("fg_exact_solve poll");
+        if (e) return e;
+        if (h.done) break;
     }
-    if (bn == 0.0) return check_hip("fg_exact_solve");
-    double rho = 1, alpha = 1, omega = 1;
-    int64_t it = 0;
-    fg_status status = FG_OK;
-    for (;;) {
-        dots2(rh, r, r, r, h);
-        const double rho1 = h[0], rel = std::sqrt(h[1]) / bn;
-        *relres = rel;
-        if (!std::isfinite(rho1) || !std::isfinite(rel)) {
-            set_error("fg_exact_solve: NaN or Inf in the BiCGStab iteration");
-            status = FG_ERR_NAN;
-            break;
-        }
-        if (rel <= tol) break;
-        if (it >= maxit) {
-            status = FG_NOT_CONVERGED;
-            break;
-        }
-        if (rho1 == 0.0 || omega == 0.0) {
-            set_error("fg_exact_solve: BiCGStab breakdown (rho or omega vanished)");
-            status = FG_ERR_BREAKDOWN;
-            break;
-        }
-        const double beta = (rho1 / rho) * (alpha / omega);
-        vaxpby(n, -omega, v, 1.0, p, st);  // p = r + beta (p - omega v)
-        vaxpby(n, 1.0, r, beta, p, st);
-        precond(S, p, ph, st);
-        spmv_exact(S, ph, v, st);
-        dots2(rh, v, rh, v, h);
-        if (!std::isfinite(h[0]) || h[0] == 0.0) {
-            set_error("fg_exact_solve: BiCGStab breakdown (rh.v vanished or is not finite)");
-            status = std::isfinite(h[0]) ? FG_ERR_BREAKDOWN : FG_ERR_NAN;
-            break;
-        }
-        alpha = rho1 / h[0];
-        hipMemcpyAsync(s, r, n * sizeof(double), hipMemcpyDeviceToDevice, st);  // s = r - alpha v
-        vaxpby(n, -alpha, v, 1.0, s, st);
-        precond(S, s, sh, st);
-        spmv_exact(S, sh, t, st);
-        dots2(t, s, t, t, h);
-        if (!std::isfinite(h[0]) || !std::isfinite(h[1]) || h[1] == 0.0) {
-            set_error("fg_exact_solve: BiCGStab breakdown (t.t vanished or is not finite)");
-            status = (std::isfinite(h[0]) && std::isfinite(h[1])) ? FG_ERR_BREAKDOWN : FG_ERR_NAN;
-            break;
-        }
-        omega = h[0] / h[1];
-        vaxpby(n, alpha, ph, 1.0, x, st);  // x += alpha ph + omega sh
-        vaxpby(n, omega, sh, 1.0, x, st);
-        hipMemcpyAsync(r, s, n * sizeof(double), hipMemcpyDeviceToDevice, st);  // r = s - omega t
-        vaxpby(n, -omega, t, 1.0, r, st);
-        rho = rho1;
-        ++it;
-    }
-    *iters = it;
-    fg_status e = check_hip("fg_exact_solve");
-    return e ? e : status;
+    *iters = h.iters;
+    *relres = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
+    if (h.status == FG_ERR_NAN) set_error("fg_exact_solve: NaN or Inf in the BiCGStab iteration");
+    if (h.status == FG_ERR_BREAKDOWN) set_error("fg_exact_solve: BiCGStab breakdown (rh.r, rh.v, t.t or omega vanished)");
+    return h.status;
 }
 
 }  // namespace fg

@@ -70,6 +70,10 @@ fg_status cheb_interval_ready(fg_system *S, hipStream_t st);
 // out = M^-1 in with the block-Jacobi data (bj_ready first).
 void bj_apply(fg_system *S, const double *in, double *out, hipStream_t st);
 
+// Length of S->bx: five BiCGStab work vectors and room for its device scalars.
+constexpr int64_t BX_TAIL = 16;
+inline int64_t bx_len(const fg_system *S) { return 15 * S->Npad + BX_TAIL; }
+
 // Exact interface tangent (fg_exact.hip): y += N x (slip part of the last
 // interface update), y = (K_t + N) x, and BiCGStab on K_t + N (internal order).
 void apply_N_add(fg_system *S, const double *x, double *y, hipStream_t st);
