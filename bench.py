@@ -354,8 +354,10 @@ def extra_adjoint(ctx, log):
     gP = torch.zeros_like(P)
     die0 = torch.zeros_like(die)
     res = {}
-    for name, prec in (("f64", fg.FG_F64), ("mixed", fg.FG_MIXED)):
+    for name, prec, kp in (("f64", fg.FG_F64, 0), ("mixed", fg.FG_MIXED, 0), ("f64_block_jacobi", fg.FG_F64, 1),
+                           ("mixed_block_jacobi", fg.FG_MIXED, 1)):
         # corrections solved loosely (outer 0.05, inner 1e-3); the defect tolerance sets the accuracy
+        S.tune("k_precond", kp)
         ik = fg.opts(tol=1e-3, check_every=64, precision=prec)
         ip = fg.opts(tol=1e-3, check_every=64)
         t_adj, (dE, dk, ainfo) = _timed(lambda: S.adjoint(U, P, die0, t0, logk, gU, gP, inner_k=ik, inner_p=ip,
@@ -363,7 +365,12 @@ def extra_adjoint(ctx, log):
         log(f"adjoint {name}: {t_adj:.2f}s defect iters {ainfo.newton_iters} outer {ainfo.outer_iters} "
             f"K iters {ainfo.inner_k_iters} status {ainfo.status}")
         res[name] = (t_adj, ainfo, torch.cat([dE * E, dk]))
+    S.tune("k_precond", 0)
     g64 = res["f64"][2]
+    bj = {name: {"s": res[name][0], "defect_iters": res[name][1].newton_iters, "k_iters": res[name][1].inner_k_iters,
+                 "status": res[name][1].status,
+                 "vs_f64_grad_rel_l2": (torch.linalg.norm(res[name][2] - g64) / torch.linalg.norm(g64)).item()}
+          for name in ("f64_block_jacobi", "mixed_block_jacobi")}
     # the exact tangent K_t + N at the converged state (slip points present): BiCGStab to 1e-8
     # on b = dJ/dU, against CG on the symmetric tangent
     S.cohesive_update(U, die0, t0, write_tangent=True)
@@ -412,7 +419,7 @@ def extra_adjoint(ctx, log):
             "defect_iters": res["f64"][1].newton_iters, "adjoint_k_iters_f64": res["f64"][1].inner_k_iters,
             "mixed_vs_f64_grad_rel_l2": (torch.linalg.norm(res["mixed"][2] - g64) / torch.linalg.norm(g64)).item(),
             "slip_points": int((flag == 1).sum()), "exact_tangent_solve": exact,
-            "forward_block_jacobi": fwd}
+            "forward_block_jacobi": fwd, "adjoint_block_jacobi": bj}
 
 
 def extra_steps(ctx, log, nsteps=3):
