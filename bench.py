@@ -354,10 +354,13 @@ def extra_adjoint(ctx, log):
     gP = torch.zeros_like(P)
     die0 = torch.zeros_like(die)
     res = {}
-    for name, prec, kp in (("f64", fg.FG_F64, 0), ("mixed", fg.FG_MIXED, 0), ("f64_block_jacobi", fg.FG_F64, 1),
-                           ("mixed_block_jacobi", fg.FG_MIXED, 1)):
-        # corrections solved loosely (outer 0.05, inner 1e-3); the defect tolerance sets the accuracy
+    for name, prec, kp, et in (("f64", fg.FG_F64, 0, 0), ("mixed", fg.FG_MIXED, 0, 0),
+                               ("f64_block_jacobi", fg.FG_F64, 1, 0), ("mixed_block_jacobi", fg.FG_MIXED, 1, 0),
+                               ("f64_block_jacobi_exact", fg.FG_F64, 1, 1)):
+        # corrections solved loosely (outer 0.05, inner 1e-3); the defect tolerance sets the accuracy;
+        # exact: the corrections solve with K_t + N^T (BiCGStab) instead of the symmetric tangent
         S.tune("k_precond", kp)
+        S.tune("exact_tangent", et)
         ik = fg.opts(tol=1e-3, check_every=64, precision=prec)
         ip = fg.opts(tol=1e-3, check_every=64)
         t_adj, (dE, dk, ainfo) = _timed(lambda: S.adjoint(U, P, die0, t0, logk, gU, gP, inner_k=ik, inner_p=ip,
@@ -366,11 +369,12 @@ def extra_adjoint(ctx, log):
             f"K iters {ainfo.inner_k_iters} status {ainfo.status}")
         res[name] = (t_adj, ainfo, torch.cat([dE * E, dk]))
     S.tune("k_precond", 0)
+    S.tune("exact_tangent", 0)
     g64 = res["f64"][2]
     bj = {name: {"s": res[name][0], "defect_iters": res[name][1].newton_iters, "k_iters": res[name][1].inner_k_iters,
                  "status": res[name][1].status,
                  "vs_f64_grad_rel_l2": (torch.linalg.norm(res[name][2] - g64) / torch.linalg.norm(g64)).item()}
-          for name in ("f64_block_jacobi", "mixed_block_jacobi")}
+          for name in ("f64_block_jacobi", "mixed_block_jacobi", "f64_block_jacobi_exact")}
     # the exact tangent K_t + N at the converged state (slip points present): BiCGStab to 1e-8
     # on b = dJ/dU, against CG on the symmetric tangent
     S.cohesive_update(U, die0, t0, write_tangent=True)

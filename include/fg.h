@@ -381,9 +381,12 @@ fg_status fg_group_stats(const fg_system *sys, int64_t *iters_h, double *relres_
  *               so that Newton uses the exact Jacobian of the interface force;
  *               the outer partitioned CG then runs on a Schur complement that
  *               is not exactly symmetric.  0 (default): the symmetric tangent.
- *               fg_pcg_solve and fg_adjoint_solve always use the symmetric
- *               tangent (the adjoint lags N^T by defect correction itself);
- *               mixed-precision K solves stay symmetric.
+ *               fg_adjoint_solve then solves its FP64 corrections with K_t + N^T
+ *               (BiCGStab, the transposed exact tangent) instead of the
+ *               symmetric tangent: the same multipliers (the refinement runs on
+ *               the true residual of the exact transposed system either way) in
+ *               fewer corrections.  fg_pcg_solve always uses the symmetric
+ *               tangent; mixed-precision K solves stay symmetric.
  *   "cheb_degree": degree of the Chebyshev polynomial, 1 to 16 (default 4;
  *               1 is block Jacobi scaled by 1/theta: same iterates).
  *   "cheb_ratio": hi / lo of the interval, 2 to 1000000 (default 300).

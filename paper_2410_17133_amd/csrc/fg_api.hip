@@ -117,6 +117,15 @@ struct SymmetricSolves {
     ~SymmetricSolves() { S->exact_tangent = saved; }
 };
 
+// The adjoint's K solves for its lifetime: K_t + N^T (exact_tangent 2, BiCGStab)
+// when fg_tune "exact_tangent" is on, else the symmetric tangent.
+struct AdjointSolves {
+    fg_system *S;
+    int saved;
+    explicit AdjointSolves(fg_system *s) : S(s), saved(s->exact_tangent) { S->exact_tangent = saved ? 2 : 0; }
+    ~AdjointSolves() { S->exact_tangent = saved; }
+};
+
 // K solve on internal vectors: rhs (3 Npad) -> out (3 Npad).
 fg_status k_solve(fg_system *S, const double *rhs, double *out, const fg_pcg_opts &o, fg_pcg_info *info, hipStream_t st)
 {
@@ -126,7 +135,7 @@ fg_status k_solve(fg_system *S, const double *rhs, double *out, const fg_pcg_opt
         double rr = 0;
         fg_status s;
         if (o.precision == FG_F64 && S->exact_tangent && S->ngroups == 1) {
-            s = bicgstab_exact(S, rhs, out, o.tol, o.max_iter, &it, &rr, st);
+            s = bicgstab_exact(S, rhs, out, o.tol, o.max_iter, S->exact_tangent == 2, &it, &rr, st);
         } else if (o.precision == FG_F64 && S->k_precond == 2 && S->ngroups == 1) {
             s = cheb_cg(S, rhs, out, o.tol, o.max_iter, o.check_every, &it, &rr, st);
         } else if (o.precision == FG_F64) {
@@ -874,8 +883,9 @@ fg_status fg_adjoint_solve(fg_ctx *ctx, fg_system *S, const double *U, const dou
     }
     if (!ready(S)) return FG_ERR_STATE;
     Guard g(ctx->device);
-    // the defect correction solves with the symmetric tangent and lags N^T itself
-    SymmetricSolves sym(S);
+    // the corrections solve with the symmetric tangent, or with K_t + N^T when the
+    // exact tangent is on; either way the true residual below carries N^T
+    AdjointSolves adj(S);
     hipStream_t st = S_(stream);
     const int64_t n1 = 3 * S->Npad, n2 = S->Npad;
     fg_pcg_opts ok = defaults(inner_k, 1e-12), op = defaults(inner_p, 1e-12);
@@ -1009,7 +1019,7 @@ fg_status fg_exact_solve(fg_ctx *ctx, fg_system *S, const double *b, double *x, 
     perm_in(S, 3, b, S->pv2, st);
     int64_t it = 0;
     double rel = 0;
-    fg_status s = bicgstab_exact(S, S->pv2, S->wx, o.tol, o.max_iter, &it, &rel, st);
+    fg_status s = bicgstab_exact(S, S->pv2, S->wx, o.tol, o.max_iter, false, &it, &rel, st);
     perm_out(S, 3, S->wx, x, st);
     if (info) {
         info->iters = it;
@@ -1054,7 +1064,7 @@ fg_status fg_spmv(fg_ctx *ctx, fg_system *S, int which, const double *x, double 
     double *xi = bs == 3 ? S->pv1 : S->s7, *yi = bs == 3 ? S->pv2 : S->s8;
     perm_in(S, bs, x, xi, st);
     if (which == FG_K_EXACT)
-        spmv_exact(S, xi, yi, st);
+        spmv_exact(S, xi, yi, false, st);
     else
         spmv(S, which, xi, yi, st);
     perm_out(S, bs, yi, y, st);

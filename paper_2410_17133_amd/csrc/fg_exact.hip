@@ -66,6 +66,46 @@ __global__ void k_n_rows(int64_t nfr, const int32_t *__restrict__ frows, const i
         if (!dir_u[3 * row + r]) y[3 * row + r] += acc[r];
 }
 
+// N^T x, step 1: per point s_q = (-f k_n tau_q) . jump(x)(q), held DOFs read as zero.
+__global__ void k_nt_jump(int64_t nq, const int32_t *__restrict__ coh, const double *__restrict__ qpNs,
+                          const double *__restrict__ x, const uint8_t *__restrict__ dir_u, double *qpS)
+{
+    const int64_t iq = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (iq >= nq) return;
+    const int64_t t = iq / 3;
+    const int q = (int)(iq - 3 * t);
+    const int32_t *c = coh + 6 * t;
+    double s = 0;
+    for (int a = 0; a < 3; ++a)
+        for (int r = 0; r < 3; ++r) {
+            const int64_t ip = 3 * (int64_t)c[a] + r, im = 3 * (int64_t)c[3 + a] + r;
+            s += qpNs[3 * iq + r] * bary(q, a) * ((dir_u[ip] ? 0.0 : x[ip]) - (dir_u[im] ? 0.0 : x[im]));
+        }
+    qpS[iq] = s;
+}
+
+// N^T x, step 2: per fault row, y += +-sum over incident elements and points of
+// w N_a(q) s_q n; held DOFs unchanged.
+__global__ void k_nt_rows_add(int64_t nfr, const int32_t *__restrict__ frows, const int32_t *__restrict__ fadj_ptr,
+                              const int32_t *__restrict__ fadj, const double *__restrict__ geo,
+                              const double *__restrict__ qpS, const uint8_t *__restrict__ dir_u, double *y)
+{
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= nfr) return;
+    const int64_t row = frows[k];
+    double acc[3] = {0, 0, 0};
+    for (int m = fadj_ptr[k]; m < fadj_ptr[k + 1]; ++m) {
+        const int64_t t = fadj[m] / 6;
+        const int la = fadj[m] % 6, va = la % 3;
+        const double w = (la < 3 ? 1.0 : -1.0) * geo[10 * t] / 3.0;
+        double sw = 0;
+        for (int q = 0; q < 3; ++q) sw += w * bary(q, va) * qpS[3 * t + q];
+        for (int r = 0; r < 3; ++r) acc[r] += sw * geo[10 * t + 1 + r];
+    }
+    for (int r = 0; r < 3; ++r)
+        if (!dir_u[3 * row + r]) y[3 * row + r] += acc[r];
+}
+
 // Device-resident scalars of one BiCGStab solve, kept after the work vectors in
 // S->bx.  rho (rh.r) is kept per iteration parity: the kernel that forms the new
 // value reads the current slot and writes the other.
@@ -251,14 +291,25 @@ void apply_N_add(fg_system *S, const double *x, double *y, hipStream_t st)
            S->qpNs, S->dir_u, y);
 }
 
-void spmv_exact(fg_system *S, const double *x, double *y, hipStream_t st)
+void apply_NT_add(fg_system *S, const double *x, double *y, hipStream_t st)
 {
-    spmv(S, FG_K, x, y, st);
-    apply_N_add(S, x, y, st);
+    if (S->nq == 0) return;
+    LAUNCH(k_nt_jump, (S->nq + WG - 1) / WG, WG, st, S->nq, S->coh, S->qpNs, x, S->dir_u, S->qpS);
+    LAUNCH(k_nt_rows_add, (S->nfr + WG - 1) / WG, WG, st, S->nfr, S->frows, S->fadj_ptr, S->fadj, S->tri_geo, S->qpS,
+           S->dir_u, y);
 }
 
-fg_status bicgstab_exact(fg_system *S, const double *b, double *x, double tol, int64_t maxit, int64_t *iters,
-                         double *relres, hipStream_t st)
+void spmv_exact(fg_system *S, const double *x, double *y, bool transposed, hipStream_t st)
+{
+    spmv(S, FG_K, x, y, st);
+    if (transposed)
+        apply_NT_add(S, x, y, st);
+    else
+        apply_N_add(S, x, y, st);
+}
+
+fg_status bicgstab_exact(fg_system *S, const double *b, double *x, double tol, int64_t maxit, bool transposed,
+                         int64_t *iters, double *relres, hipStream_t st)
 {
     const int64_t n = 3 * S->Npad;
     *iters = 0;
@@ -289,11 +340,11 @@ fg_status bicgstab_exact(fg_system *S, const double *b, double *x, double tol, i
             const int par = (int)(k & 1);
             LAUNCH(k_bi_p, gv, WG, st, n, par, (int)(k == 0), tol, r, p, v, part, stride, gv, sc);
             precond(S, p, ph, st);
-            spmv_exact(S, ph, v, st);
+            spmv_exact(S, ph, v, transposed, st);
             LAUNCH(k_bi_dot, gv, WG, st, n, rh, v, part, stride);
             LAUNCH(k_bi_s, gv, WG, st, n, par, r, v, s, part, stride, gv, sc);
             precond(S, s, sh, st);
-            spmv_exact(S, sh, t, st);
+            spmv_exact(S, sh, t, transposed, st);
             LAUNCH(k_bi_dot2, gv, WG, st, n, t, s, part, stride);
             LAUNCH(k_bi_xr, gv, WG, st, n, x, r, ph, sh, s, t, rh, part, stride, gv, sc);
         }

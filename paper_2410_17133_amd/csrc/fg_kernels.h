@@ -74,12 +74,14 @@ void bj_apply(fg_system *S, const double *in, double *out, hipStream_t st);
 constexpr int64_t BX_TAIL = 16;
 inline int64_t bx_len(const fg_system *S) { return 15 * S->Npad + BX_TAIL; }
 
-// Exact interface tangent (fg_exact.hip): y += N x (slip part of the last
-// interface update), y = (K_t + N) x, and BiCGStab on K_t + N (internal order).
+// Exact interface tangent (fg_exact.hip): y += N x or y += N^T x (slip part of the
+// last interface update), y = (K_t + N) x or (K_t + N^T) x, and BiCGStab on
+// either (internal order).
 void apply_N_add(fg_system *S, const double *x, double *y, hipStream_t st);
-void spmv_exact(fg_system *S, const double *x, double *y, hipStream_t st);
-fg_status bicgstab_exact(fg_system *S, const double *b, double *x, double tol, int64_t maxit, int64_t *iters,
-                         double *relres, hipStream_t st);
+void apply_NT_add(fg_system *S, const double *x, double *y, hipStream_t st);
+void spmv_exact(fg_system *S, const double *x, double *y, bool transposed, hipStream_t st);
+fg_status bicgstab_exact(fg_system *S, const double *b, double *x, double tol, int64_t maxit, bool transposed,
+                         int64_t *iters, double *relres, hipStream_t st);
 
 // float <-> double conversions with a scale: y = (T)(s * x)
 void to_f32(int64_t n, double s, const double *x, float *y, hipStream_t st);

@@ -51,11 +51,14 @@ def objective_np(inst, U, uplift):
     return np.sum(slip * slip) + np.sum(U3[uplift, 2] ** 2), g.reshape(-1)
 
 
-@pytest.mark.parametrize("case,loose", [("small_slip", False), ("small_slip", True), ("config1", False),
-                                        ("config1", True)])
-def test_adjoint_matches_oracle_at_the_same_state(case, loose):
+@pytest.mark.parametrize("case,loose,exact", [("small_slip", False, False), ("small_slip", True, False),
+                                              ("config1", False, False), ("config1", True, False),
+                                              ("small_slip", True, True), ("config1", True, True)])
+def test_adjoint_matches_oracle_at_the_same_state(case, loose, exact):
     """loose: every defect correction solved to outer 0.05 / inner 1e-3 only; the
-    refinement on the true residual must still reach the same multipliers."""
+    refinement on the true residual must still reach the same multipliers.  exact:
+    fg_tune exact_tangent 1, the corrections solve with K_t + N^T (BiCGStab) and need
+    no more of them than the symmetric corrections."""
     from oracle import oracle as O
     from paper_2410_17133_amd import fg
     inst = small_slip_instance() if case == "small_slip" else I.make_instance(I.config(1))
@@ -75,10 +78,19 @@ def test_adjoint_matches_oracle_at_the_same_state(case, loose):
     S = fg.System.from_instance(ctx, inst)
     S.assemble(inst.params, inst.E, inst.logk)
     kw = dict(inner_k=fg.opts(tol=1e-3), inner_p=fg.opts(tol=1e-3), outer_tol=0.05) if loose else {}
-    dE, dk, lu, lp, ai = S.adjoint(dev(U), dev(Pp), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)), dev(inst.logk),
-                                   dev(gu), dev(gp), multipliers=True, **kw)
-    print(f"[adjoint] loose={loose} defect iterations gpu {ai.newton_iters} (K iters {ai.inner_k_iters}) "
-          f"oracle {stats[0]:.0f}", flush=True)
+    args = (dev(U), dev(Pp), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)), dev(inst.logk), dev(gu), dev(gp))
+    if exact:
+        ai_sym = S.adjoint(*args, multipliers=True, **kw)[4]
+        S.tune("exact_tangent", 1)
+    try:
+        dE, dk, lu, lp, ai = S.adjoint(*args, multipliers=True, **kw)
+    finally:
+        S.tune("exact_tangent", 0)
+    print(f"[adjoint] loose={loose} exact={exact} defect iterations gpu {ai.newton_iters} (K iters "
+          f"{ai.inner_k_iters}) oracle {stats[0]:.0f}", flush=True)
+    if exact:
+        print(f"[adjoint] symmetric corrections {ai_sym.newton_iters}", flush=True)
+        assert ai.newton_iters <= ai_sym.newton_iters
     assert ai.status == 0
     assert rel(host(lu), lu_o) < 1e-9
     assert rel(host(lp), lp_o) < 1e-9
