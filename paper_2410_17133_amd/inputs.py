@@ -145,9 +145,11 @@ def _node_id(i, j, k, nx, ny):
 
 
 def make_mesh(nx: int, ny: int, nz: int, L=(1.0, 1.0, 1.0), fault_i: int | None = None,
-              dip_deg: float = 90.0) -> Mesh:
+              dip_deg: float = 90.0, lines=None) -> Mesh:
     """Structured Kuhn mesh of the box [0,Lx]x[0,Ly]x[0,Lz], optionally cut by a
-    fault on the grid plane i = fault_i."""
+    fault on the grid plane i = fault_i.  `lines` = (xs, ys, zs), increasing
+    grid-line positions (nx+1, ny+1, nz+1 values), replaces the uniform spacing
+    (a graded tensor-product grid; vertical faults only)."""
     Lx, Ly, Lz = L
     n_orig = (nx + 1) * (ny + 1) * (nz + 1)
     gi, gj, gk = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), np.arange(nz + 1), indexing="ij")
@@ -204,6 +206,16 @@ def make_mesh(nx: int, ny: int, nz: int, L=(1.0, 1.0, 1.0), fault_i: int | None 
         pk = pk.T.reshape(-1)
         pairs = np.stack([_node_id(fault_i, pj, pk, nx, ny), n_orig + pj + (ny + 1) * pk], 1).astype(np.int32)
         grid = np.concatenate([grid, np.stack([np.full(n_plane, fault_i), pj, pk], 1).astype(np.int32)])
+
+    if lines is not None:
+        xs, ys, zs = (np.asarray(a, dtype=np.float64) for a in lines)
+        if (xs.size, ys.size, zs.size) != (nx + 1, ny + 1, nz + 1) or abs(dip_deg - 90.0) > 1e-12:
+            raise ValueError("grid lines need nx+1, ny+1, nz+1 positions and a vertical fault")
+        if min(np.diff(xs).min(), np.diff(ys).min(), np.diff(zs).min()) <= 0:
+            raise ValueError("grid lines must increase")
+        xyz = np.stack([xs[grid[:, 0]], ys[grid[:, 1]], zs[grid[:, 2]]], axis=1)
+        return Mesh(nx, ny, nz, np.ascontiguousarray(xyz), np.ascontiguousarray(tets.reshape(-1, 4), dtype=np.int32),
+                    coh, pairs, grid, n_orig)
 
     # coordinates, with the column-shift map for a dipping fault
     fi = grid[:, 0].astype(np.float64)
@@ -362,3 +374,66 @@ def concat_instances(instances) -> Batch:
         cat([i.E for i in instances]), cat([i.logk for i in instances]),
         cat([i.source for i in instances]), cat([i.t0 for i in instances]),
         node_off, tet_off, coh_off)
+
+
+# ------------------------------------------------------------ injection into a frictional fault (Sec. 4.2)
+SLIP_BENCHMARK = dict(
+    E=60e9, nu=0.0, alpha=0.0, biot_M=1e14, mu=0.89e-3, friction=0.6,   # Table 1 (M = 1e5 GPa, k_M = 0)
+    k_n=6e12, k_s=6e11,            # Table 1 normal / shear stiffness, printed in GPa, read as Pa/m
+    wk_par=1e-15, M_F=0.2e6,       # Table 1 transmissibility w k_par [m^3], fracture Biot modulus [Pa]
+    sigma0=80e6, Q=1e-6,           # Sec. 4.2 normal load [Pa], injection 0.06 L/min [m^3/s]
+    tau0_CS=47.999e6, tau0_MP=47.830e6)
+
+
+def graded_lines(h: float, n_fine: int, n_grade: int, ratio: float, centre: float = 0.0) -> np.ndarray:
+    """Grid-line positions symmetric about `centre`: n_fine cells of width h
+    (n_fine even) around it, then n_grade cells on each side, each `ratio`
+    times wider than the one before."""
+    assert n_fine % 2 == 0
+    w = [h] * (n_fine // 2) + [h * ratio ** (k + 1) for k in range(n_grade)]
+    half = np.concatenate([[0.0], np.cumsum(w)])
+    return np.concatenate([centre - half[:0:-1], centre + half])
+
+
+def slip_benchmark_instance(tau0: float, h: float = 0.1, n_fine: int = 16, n_grade: int = 6, ratio: float = 1.5,
+                            nx_fine: int = 2, nx_grade: int = 7, dt: float = 1.0, k_perp: float = 1e-11,
+                            w0: float = 1e-3) -> Instance:
+    """The injection-into-a-frictional-fault workload of Sec. 4.2 on a graded box.
+
+    The paper's horizontal fault with shear along x is turned so that the fault is
+    the vertical grid plane through the box centre (normal +x) and the initial
+    shear acts along t1 (+z); with nu = 0 and isotropic elasticity the turn
+    changes nothing.  Cells are h wide over the central n_fine x n_fine patch of
+    the fault and grow by `ratio` outwards; across the fault the first nx_fine/2
+    cells on each side are h wide.  Table 1 materials: impermeable matrix
+    (ln k = ln 1e-30) with alpha = 0 and a stiff Biot modulus, fault flow only
+    (w0 k_par = 1e-15 m^3 with w0 = 1 mm, k_perp = 1e-11 m^2 so that the two lips'
+    pressures move together), penalties k_n, k_s, friction 0.6.  Initial
+    tractions t'_n0 = sigma0 = 80 MPa and t'_s0 = tau0 along t1; injection
+    Q = 0.06 L/min split over the centre node pair.  The face x = 0 (parallel to
+    the fault, on its - side) is clamped: it removes the rigid-body modes of the
+    increment problem, as the paper's restraints on its bottom face do."""
+    b = SLIP_BENCHMARK
+    xs = graded_lines(h, nx_fine, nx_grade, ratio)
+    ys = graded_lines(h, n_fine, n_grade, ratio)
+    xs, ys = xs - xs[0], ys - ys[0]
+    nx, ny = xs.size - 1, ys.size - 1
+    mesh = make_mesh(nx, ny, ny, (xs[-1], ys[-1], ys[-1]), fault_i=nx // 2, lines=(xs, ys, ys))
+    prm = Params(nu=b["nu"], alpha=b["alpha"], biot_M=b["biot_M"], mu=b["mu"], k_par=b["wk_par"] / w0,
+                 k_perp=k_perp, w0=w0, M_F=b["M_F"], k_n=b["k_n"], k_s=b["k_s"], friction=b["friction"], dt=dt)
+    cfg = Config(f"slip_benchmark_tau{tau0 / 1e6:.3f}", ny, 90.0, E0=b["E"], tn0=b["sigma0"],
+                 stress_ratio=tau0 / (b["friction"] * b["sigma0"]), Q=b["Q"], params=prm)
+    ne, N = mesh.tets.shape[0], mesh.n_nodes
+    dir_u = np.zeros(3 * N, dtype=np.uint8)
+    face = np.nonzero(mesh.grid[:, 0] == 0)[0]
+    for c in range(3):
+        dir_u[3 * face + c] = 1
+    pid = ny // 2 + (ny + 1) * (ny // 2)
+    centre = (int(mesh.pairs[pid, 0]), int(mesh.pairs[pid, 1]))
+    source = np.zeros(N)
+    source[list(centre)] = 0.5 * b["Q"]
+    t0 = np.zeros((mesh.coh.shape[0] * 3, 3))
+    t0[:, 0] = b["sigma0"]
+    t0[:, 1] = tau0
+    return Instance(cfg, mesh, prm, np.full(ne, b["E"]), np.full(ne, math.log(1e-30)), dir_u,
+                    np.zeros(N, dtype=np.uint8), source, np.zeros(3 * N), t0, centre)
