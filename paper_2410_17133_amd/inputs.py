@@ -437,3 +437,62 @@ def slip_benchmark_instance(tau0: float, h: float = 0.1, n_fine: int = 16, n_gra
     t0[:, 1] = tau0
     return Instance(cfg, mesh, prm, np.full(ne, b["E"]), np.full(ne, math.log(1e-30)), dir_u,
                     np.zeros(N, dtype=np.uint8), source, np.zeros(3 * N), t0, centre)
+
+
+# ------------------------------------------------------------ Cryer's sphere (Sec. 4.1)
+def sphere_octant_mesh(n: int, R: float = 1.0) -> Mesh:
+    """One octant (x, y, z >= 0) of a ball of radius R: the structured Kuhn mesh of
+    the unit cube with grid node v = (i, j, k) / n moved to R max(v) v / |v|, so
+    that every cube shell max(v) = m becomes the sphere of radius R m and the
+    three faces max(v) = 1 the spherical surface."""
+    m = make_mesh(n, n, n)
+    v = m.grid.astype(np.float64) / n
+    norm = np.linalg.norm(v, axis=1)
+    scale = np.where(norm > 0, v.max(axis=1) / np.where(norm > 0, norm, 1.0), 0.0)
+    m.xyz = np.ascontiguousarray(R * v * scale[:, None])
+    return m
+
+
+def sphere_surface_triangles(mesh: Mesh) -> np.ndarray:
+    """[T, 3] node triples of the tetrahedron faces on the spherical surface
+    (all three nodes on the shell max(i, j, k) = n), ordered so that the right-hand
+    normal points out of the ball."""
+    n = mesh.nx
+    shell = mesh.grid.max(axis=1) == n
+    tris = []
+    for t in mesh.tets:
+        for drop in range(4):
+            f = np.delete(t, drop)
+            if shell[f].all():
+                a, b, c = mesh.xyz[f]
+                if np.dot(np.cross(b - a, c - a), a - mesh.xyz[t[drop]]) < 0:
+                    f = f[[0, 2, 1]]
+                tris.append(f)
+    return np.array(tris, dtype=np.int64)
+
+
+def cryer_instance(n: int, R: float = 1.0, F: float = 1e6, E: float = 10e9, nu: float = 0.25, alpha: float = 1.0,
+                   biot_M: float = 22.7e9, k: float = 1e-15, mu: float = 0.89e-3, dt: float = 1.0) -> Instance:
+    """Cryer's problem of Sec. 4.1 on one octant of the sphere: a saturated
+    poroelastic ball, drained (p = 0) on its surface, loaded at t = 0+ by a
+    uniform compressive surface pressure F held constant.  The three symmetry
+    planes x = 0, y = 0, z = 0 carry no normal displacement and no flux.  No
+    fault.  The load is the consistent nodal force of the pressure F on the
+    surface triangles (F area / 3 per vertex, along the inward normal), the total
+    external force change F_u of every step."""
+    mesh = sphere_octant_mesh(n, R)
+    N, ne = mesh.n_nodes, mesh.tets.shape[0]
+    prm = Params(nu=nu, alpha=alpha, biot_M=biot_M, mu=mu, dt=dt)
+    cfg = Config(f"cryer_octant{n}", n, fault=False, E0=E, lnk_mean=math.log(k), Q=0.0, params=prm)
+    dir_u = np.zeros(3 * N, dtype=np.uint8)
+    for c in range(3):
+        dir_u[3 * np.nonzero(mesh.grid[:, c] == 0)[0] + c] = 1
+    dir_p = (mesh.grid.max(axis=1) == n).astype(np.uint8)
+    load = np.zeros((N, 3))
+    for f in sphere_surface_triangles(mesh):
+        a, b, c = mesh.xyz[f]
+        an = 0.5 * np.cross(b - a, c - a)          # area times outward unit normal
+        for v in f:
+            load[v] -= F * an / 3.0
+    return Instance(cfg, mesh, prm, np.full(ne, E), np.full(ne, math.log(k)), dir_u, dir_p, np.zeros(N),
+                    np.ascontiguousarray(load.reshape(-1)), np.zeros((0, 3)), (0, 0))
