@@ -1752,3 +1752,644 @@ done:
     bj_free(&M);
     return status;
 }
+
+/* ------------------------------------------------------------------ */
+/* smoothed-aggregation AMG preconditioner of K_t                      */
+/* ------------------------------------------------------------------ */
+/* Smoothed aggregation (Vanek, Mandel and Brezina, Computing 56, 1996) with the
+ * six rigid-body modes as near-null space, used as a preconditioner of the K_t
+ * solves (the stronger preconditioner after block Jacobi and Chebyshev):
+ *  - aggregates: three passes over the node graph of the level's matrix in
+ *    increasing node order (the two lips of a fault pair count as one node):
+ *    (1) a node whose neighbours are all free starts an aggregate with them;
+ *    (2) a free node joins the aggregate of its lowest-numbered neighbour
+ *    aggregated in pass 1; (3) a node still free starts an aggregate with its
+ *    free neighbours;
+ *  - tentative prolongator: per aggregate the near-null-space rows of its nodes
+ *    (level 0: translations and rotations about the aggregate centroid, zero on
+ *    held DOFs; below: the R factor of the aggregate's node), orthonormalised by
+ *    modified Gram-Schmidt (a column that vanishes is dropped: zero column, zero
+ *    R row); Q gives the prolongator's rows, R the coarse near-null space;
+ *  - prolongator smoothing P = (I - w D^-1 A) Ptent, D the block diagonal,
+ *    w = 4 / (3 rho), rho the Gershgorin bound max_r sum_c |(D^-1 A)_rc|;
+ *  - Galerkin coarse operator A_c = P^T A P; a coarse DOF with an empty row gets a
+ *    unit diagonal; coarsening stops at <= amg_coarse nodes or 6 levels, and the
+ *    coarsest level is solved by a dense Cholesky factor;
+ *  - V-cycle with pre- and post-smoothing by the degree-2 Chebyshev polynomial
+ *    over block Jacobi (level 0: the nodal / fault-pair blocks of or_pcg_block on
+ *    [hi0/30, hi0]; below: the 6x6 diagonal blocks on [rho/30, rho]), symmetric, so
+ *    that CG can use it. */
+#define OR_AMG_MAXLEV 6
+
+typedef struct {
+    int bs;             /* DOFs per node */
+    int64_t nn, nc;     /* nodes of this level, aggregates (nodes of the next) */
+    or_csr A;           /* this level's matrix (level 0: a copy of K_t) */
+    or_csr P, R;        /* prolongator (bs nn x 6 nc) and its transpose */
+    int32_t *agg;       /* node -> aggregate */
+    double *Dinv;       /* [nn bs bs] inverse diagonal blocks */
+    double rho;         /* Gershgorin bound of D^-1 A */
+} or_amg_level;
+
+typedef struct {
+    int nlev;
+    or_amg_level L[OR_AMG_MAXLEV];
+    or_bj bj0;
+    double hi0;
+    double *chol;       /* dense Cholesky factor (row-major lower) of the coarsest matrix */
+    int64_t nco;
+} or_amg;
+
+static void csr_alloc(or_csr *A, int64_t n, int64_t nnz)
+{
+    A->n = n;
+    A->nnz = nnz;
+    A->rowptr = calloc(n + 1, sizeof(int64_t));
+    A->col = malloc((nnz ? nnz : 1) * sizeof(int32_t));
+    A->val = malloc((nnz ? nnz : 1) * sizeof(double));
+}
+
+/* C = A B for scalar CSR (A: n x m, B: m x k) with a dense accumulator per row;
+ * entries whose column is touched are kept even if they sum to zero. */
+static void csr_matmul(const or_csr *A, const or_csr *B, int64_t k, or_csr *Cout)
+{
+    double *acc = calloc(k, sizeof(double));
+    int32_t *mark = malloc(k * sizeof(int32_t)), *touched = malloc(k * sizeof(int32_t));
+    for (int64_t j = 0; j < k; ++j) mark[j] = -1;
+    int64_t cap = A->n * 8 + 16, nnz = 0;
+    int32_t *col = malloc(cap * sizeof(int32_t));
+    double *val = malloc(cap * sizeof(double));
+    int64_t *rp = calloc(A->n + 1, sizeof(int64_t));
+    for (int64_t i = 0; i < A->n; ++i) {
+        int nt = 0;
+        for (int64_t p = A->rowptr[i]; p < A->rowptr[i + 1]; ++p) {
+            const int32_t m = A->col[p];
+            const double a = A->val[p];
+            for (int64_t q = B->rowptr[m]; q < B->rowptr[m + 1]; ++q) {
+                const int32_t c = B->col[q];
+                if (mark[c] != (int32_t)i) {
+                    mark[c] = (int32_t)i;
+                    acc[c] = 0;
+                    touched[nt++] = c;
+                }
+                acc[c] += a * B->val[q];
+            }
+        }
+        qsort(touched, nt, sizeof(int32_t), cmp_i32);
+        if (nnz + nt > cap) {
+            while (nnz + nt > cap) cap *= 2;
+            col = realloc(col, cap * sizeof(int32_t));
+            val = realloc(val, cap * sizeof(double));
+        }
+        for (int t = 0; t < nt; ++t) {
+            col[nnz] = touched[t];
+            val[nnz] = acc[touched[t]];
+            ++nnz;
+        }
+        rp[i + 1] = nnz;
+    }
+    Cout->n = A->n;
+    Cout->nnz = nnz;
+    Cout->rowptr = rp;
+    Cout->col = col;
+    Cout->val = val;
+    free(acc);
+    free(mark);
+    free(touched);
+}
+
+static void csr_transpose(const or_csr *A, int64_t ncols, or_csr *T)
+{
+    csr_alloc(T, ncols, A->nnz);
+    for (int64_t p = 0; p < A->nnz; ++p) T->rowptr[A->col[p] + 1]++;
+    for (int64_t j = 0; j < ncols; ++j) T->rowptr[j + 1] += T->rowptr[j];
+    int64_t *pos = malloc((ncols + 1) * sizeof(int64_t));
+    memcpy(pos, T->rowptr, (ncols + 1) * sizeof(int64_t));
+    for (int64_t i = 0; i < A->n; ++i)
+        for (int64_t p = A->rowptr[i]; p < A->rowptr[i + 1]; ++p) {
+            const int64_t q = pos[A->col[p]]++;
+            T->col[q] = (int32_t)i;
+            T->val[q] = A->val[p];
+        }
+    free(pos);
+}
+
+/* Node graph of a level's matrix (bs DOFs per node): sorted neighbour lists
+ * without the node itself. */
+static void amg_node_graph(const or_csr *A, int bs, int64_t nn, int64_t **rp_out, int32_t **adj_out)
+{
+    int64_t *rp = calloc(nn + 1, sizeof(int64_t));
+    int64_t cap = nn * 8 + 16, m = 0;
+    int32_t *adj = malloc(cap * sizeof(int32_t));
+    int32_t *mark = malloc(nn * sizeof(int32_t));
+    for (int64_t i = 0; i < nn; ++i) mark[i] = -1;
+    for (int64_t i = 0; i < nn; ++i) {
+        int64_t start = m;
+        for (int r = 0; r < bs; ++r)
+            for (int64_t p = A->rowptr[bs * i + r]; p < A->rowptr[bs * i + r + 1]; ++p) {
+                const int32_t j = A->col[p] / bs;
+                if (j == i || mark[j] == (int32_t)i) continue;
+                mark[j] = (int32_t)i;
+                if (m == cap) {
+                    cap *= 2;
+                    adj = realloc(adj, cap * sizeof(int32_t));
+                }
+                adj[m++] = j;
+            }
+        qsort(adj + start, m - start, sizeof(int32_t), cmp_i32);
+        rp[i + 1] = m;
+    }
+    free(mark);
+    *rp_out = rp;
+    *adj_out = adj;
+}
+
+/* The three aggregation passes; twin[i] is the other lip of a fault pair (or -1),
+ * at level 0 only.  Returns the number of aggregates. */
+static int64_t amg_aggregate(int64_t nn, const int64_t *rp, const int32_t *adj, const int32_t *twin, int32_t *agg)
+{
+    for (int64_t i = 0; i < nn; ++i) agg[i] = -1;
+    /* members of the unit led by node i: i and its twin */
+#define UNIT_MEMBERS(i, mem, nm)                                \
+    int32_t mem[2] = {(int32_t)(i), -1};                        \
+    int nm = 1;                                                 \
+    if (twin && twin[i] >= 0) mem[nm++] = twin[i];
+    int64_t na = 0;
+    /* pass 1 */
+    for (int64_t i = 0; i < nn; ++i) {
+        if (twin && twin[i] >= 0 && twin[i] < i) continue;   /* the pair is led by its lower node */
+        if (agg[i] >= 0) continue;
+        UNIT_MEMBERS(i, mem, nm)
+        int free_all = 1;
+        for (int u = 0; u < nm && free_all; ++u)
+            for (int64_t p = rp[mem[u]]; p < rp[mem[u] + 1]; ++p)
+                if (agg[adj[p]] >= 0) {
+                    free_all = 0;
+                    break;
+                }
+        if (!free_all) continue;
+        for (int u = 0; u < nm; ++u) {
+            agg[mem[u]] = (int32_t)na;
+            for (int64_t p = rp[mem[u]]; p < rp[mem[u] + 1]; ++p) {
+                const int32_t j = adj[p];
+                agg[j] = (int32_t)na;
+                if (twin && twin[j] >= 0) agg[twin[j]] = (int32_t)na;
+            }
+        }
+        ++na;
+    }
+    /* pass 2: join the lowest-numbered neighbour's pass-1 aggregate */
+    int32_t *agg1 = malloc((nn ? nn : 1) * sizeof(int32_t));
+    memcpy(agg1, agg, nn * sizeof(int32_t));
+    for (int64_t i = 0; i < nn; ++i) {
+        if (twin && twin[i] >= 0 && twin[i] < i) continue;
+        if (agg[i] >= 0) continue;
+        UNIT_MEMBERS(i, mem, nm)
+        int32_t best = -1, bestj = INT32_MAX;
+        for (int u = 0; u < nm; ++u)
+            for (int64_t p = rp[mem[u]]; p < rp[mem[u] + 1]; ++p)
+                if (agg1[adj[p]] >= 0 && adj[p] < bestj) {
+                    bestj = adj[p];
+                    best = agg1[adj[p]];
+                }
+        if (best >= 0)
+            for (int u = 0; u < nm; ++u) agg[mem[u]] = best;
+    }
+    free(agg1);
+    /* pass 3 */
+    for (int64_t i = 0; i < nn; ++i) {
+        if (twin && twin[i] >= 0 && twin[i] < i) continue;
+        if (agg[i] >= 0) continue;
+        UNIT_MEMBERS(i, mem, nm)
+        for (int u = 0; u < nm; ++u) {
+            agg[mem[u]] = (int32_t)na;
+            for (int64_t p = rp[mem[u]]; p < rp[mem[u] + 1]; ++p) {
+                const int32_t j = adj[p];
+                if (agg[j] < 0) {
+                    agg[j] = (int32_t)na;
+                    if (twin && twin[j] >= 0) agg[twin[j]] = (int32_t)na;
+                }
+            }
+        }
+        ++na;
+    }
+#undef UNIT_MEMBERS
+    return na;
+}
+
+/* Tentative prolongator of one level: B [bs nn x 6] near-null space rows; returns
+ * Ptent (bs nn x 6 na, 6 columns per aggregate) and Bc [6 na x 6]. */
+static void amg_tentative(int bs, int64_t nn, int64_t na, const int32_t *agg, const double *B, or_csr *Pt, double *Bc)
+{
+    int64_t *cnt = calloc(na + 1, sizeof(int64_t));
+    for (int64_t i = 0; i < nn; ++i) cnt[agg[i] + 1]++;
+    for (int64_t a = 0; a < na; ++a) cnt[a + 1] += cnt[a];
+    int32_t *members = malloc((nn ? nn : 1) * sizeof(int32_t));
+    int64_t *pos = malloc((na + 1) * sizeof(int64_t));
+    memcpy(pos, cnt, (na + 1) * sizeof(int64_t));
+    for (int64_t i = 0; i < nn; ++i) members[pos[agg[i]]++] = (int32_t)i;   /* ascending within each aggregate */
+    free(pos);
+    double *Q = calloc(bs * nn * 6, sizeof(double));   /* row (bs i + r), col k */
+    memset(Bc, 0, 6 * na * 6 * sizeof(double));
+    for (int64_t a = 0; a < na; ++a) {
+        const int64_t m0 = cnt[a], m1 = cnt[a + 1];
+        const int64_t rows = (m1 - m0) * bs;
+        double *M = malloc(rows * 6 * sizeof(double));
+        for (int64_t t = m0; t < m1; ++t)
+            for (int r = 0; r < bs; ++r)
+                for (int k = 0; k < 6; ++k) M[((t - m0) * bs + r) * 6 + k] = B[((int64_t)members[t] * bs + r) * 6 + k];
+        double Rm[36] = {0};
+        for (int k = 0; k < 6; ++k) {
+            double n0 = 0;
+            for (int64_t q = 0; q < rows; ++q) n0 += M[q * 6 + k] * M[q * 6 + k];
+            n0 = sqrt(n0);
+            for (int j = 0; j < k; ++j) {
+                double d = 0;
+                for (int64_t q = 0; q < rows; ++q) d += M[q * 6 + j] * M[q * 6 + k];
+                Rm[6 * j + k] = d;
+                for (int64_t q = 0; q < rows; ++q) M[q * 6 + k] -= d * M[q * 6 + j];
+            }
+            double nk = 0;
+            for (int64_t q = 0; q < rows; ++q) nk += M[q * 6 + k] * M[q * 6 + k];
+            nk = sqrt(nk);
+            if (!(nk > 1e-10 * n0) || nk == 0.0) {
+                for (int64_t q = 0; q < rows; ++q) M[q * 6 + k] = 0;
+                for (int j = 0; j < k; ++j) Rm[6 * j + k] = 0;   /* a dropped column: zero R row and column */
+                Rm[6 * k + k] = 0;
+            } else {
+                for (int64_t q = 0; q < rows; ++q) M[q * 6 + k] /= nk;
+                Rm[6 * k + k] = nk;
+            }
+        }
+        for (int64_t t = m0; t < m1; ++t)
+            for (int r = 0; r < bs; ++r)
+                for (int k = 0; k < 6; ++k) Q[((int64_t)members[t] * bs + r) * 6 + k] = M[((t - m0) * bs + r) * 6 + k];
+        for (int r = 0; r < 6; ++r)
+            for (int k = 0; k < 6; ++k) Bc[(a * 6 + r) * 6 + k] = Rm[6 * r + k];
+        free(M);
+    }
+    csr_alloc(Pt, bs * nn, bs * nn * 6);
+    for (int64_t i = 0; i < nn; ++i)
+        for (int r = 0; r < bs; ++r) {
+            const int64_t row = bs * i + r;
+            Pt->rowptr[row + 1] = Pt->rowptr[row] + 6;
+            for (int k = 0; k < 6; ++k) {
+                Pt->col[row * 6 + k] = (int32_t)(6 * agg[i] + k);
+                Pt->val[row * 6 + k] = Q[row * 6 + k];
+            }
+        }
+    free(Q);
+    free(cnt);
+    free(members);
+}
+
+/* Inverse diagonal blocks of a level and the Gershgorin bound of D^-1 A. */
+static int amg_diag(const or_csr *A, int bs, int64_t nn, double *Dinv, double *rho_out)
+{
+    int singular = 0;
+    double rho = 0;
+    for (int64_t i = 0; i < nn; ++i) {
+        double m[36], inv[36];
+        for (int r = 0; r < bs; ++r)
+            for (int c = 0; c < bs; ++c) m[bs * r + c] = csr_at(A, bs * i + r, bs * i + c);
+        if (!gj_inverse(bs, m, inv)) singular = 1;
+        memcpy(Dinv + (int64_t)bs * bs * i, inv, bs * bs * sizeof(double));
+        for (int r = 0; r < bs; ++r) {
+            double s = 0;
+            /* row r of D_i^-1 [A rows of node i]: entries per column */
+            int64_t p[6], e[6];
+            for (int k = 0; k < bs; ++k) {
+                p[k] = A->rowptr[bs * i + k];
+                e[k] = A->rowptr[bs * i + k + 1];
+            }
+            /* rows of one node share a column pattern in these matrices; walk them together */
+            for (int64_t q = 0; q < e[0] - p[0]; ++q) {
+                double v = 0;
+                for (int k = 0; k < bs; ++k) v += inv[bs * r + k] * A->val[p[k] + q];
+                s += fabs(v);
+            }
+            rho = fmax(rho, s);
+        }
+    }
+    *rho_out = rho;
+    return singular;
+}
+
+static void amg_free(or_amg *G)
+{
+    for (int l = 0; l < G->nlev; ++l) {
+        or_amg_level *L = &G->L[l];
+        csr_free(&L->A);
+        if (L->P.rowptr) csr_free(&L->P);
+        if (L->R.rowptr) csr_free(&L->R);
+        free(L->agg);
+        free(L->Dinv);
+    }
+    bj_free(&G->bj0);
+    free(G->chol);
+    memset(G, 0, sizeof *G);
+}
+
+/* D^-1 (block diagonal) applied to the rows of a matrix with the level's block
+ * pattern: Y = D^-1 X for X with node-aligned rows sharing a pattern. */
+static void amg_dinv_rows(const double *Dinv, int bs, int64_t nn, or_csr *X)
+{
+    double *tmp = malloc(bs * sizeof(double));
+    for (int64_t i = 0; i < nn; ++i) {
+        const int64_t len = X->rowptr[bs * i + 1] - X->rowptr[bs * i];
+        for (int64_t q = 0; q < len; ++q) {
+            for (int r = 0; r < bs; ++r) {
+                double s = 0;
+                for (int k = 0; k < bs; ++k) s += Dinv[(int64_t)bs * bs * i + bs * r + k] * X->val[X->rowptr[bs * i + k] + q];
+                tmp[r] = s;
+            }
+            for (int r = 0; r < bs; ++r) X->val[X->rowptr[bs * i + r] + q] = tmp[r];
+        }
+    }
+    free(tmp);
+}
+
+/* Build the hierarchy for the current K_t.  hi0: upper end of the level-0 smoother
+ * interval.  Returns 0, or -3 if a block of a smoother is singular. */
+static int amg_setup(const or_problem *P, or_amg *G, double hi0, int64_t coarse_nodes)
+{
+    memset(G, 0, sizeof *G);
+    G->hi0 = hi0;
+    if (bj_setup(P, &G->bj0)) return -3;
+    int64_t N = P->N;
+    /* the fault pairs (the twin of each lip) */
+    int32_t *twin = malloc(N * sizeof(int32_t));
+    for (int64_t i = 0; i < N; ++i) twin[i] = G->bj0.partner[i];
+    /* level-0 near-null space: translations and rotations, later taken about centroids */
+    double *B = calloc(3 * N * 6, sizeof(double));
+    int bs = 3;
+    int64_t nn = N;
+    or_csr A;
+    csr_alloc(&A, 3 * N, P->Kt.nnz);
+    memcpy(A.rowptr, P->Kt.rowptr, (3 * N + 1) * sizeof(int64_t));
+    memcpy(A.col, P->Kt.col, P->Kt.nnz * sizeof(int32_t));
+    memcpy(A.val, P->Kt.val, P->Kt.nnz * sizeof(double));
+    int status = 0;
+    for (int l = 0; l < OR_AMG_MAXLEV; ++l) {
+        or_amg_level *L = &G->L[l];
+        L->bs = bs;
+        L->nn = nn;
+        L->A = A;
+        L->Dinv = malloc((int64_t)bs * bs * nn * sizeof(double));
+        if (amg_diag(&A, bs, nn, L->Dinv, &L->rho)) status = -3;
+        G->nlev = l + 1;
+        if (nn <= coarse_nodes || l == OR_AMG_MAXLEV - 1) break;
+        int64_t *rp;
+        int32_t *adj;
+        amg_node_graph(&A, bs, nn, &rp, &adj);
+        L->agg = malloc(nn * sizeof(int32_t));
+        const int64_t na = amg_aggregate(nn, rp, adj, l == 0 ? twin : NULL, L->agg);
+        free(rp);
+        free(adj);
+        L->nc = na;
+        if (l == 0) {
+            /* rigid-body modes about each aggregate's centroid; zero on held DOFs */
+            double *cen = calloc(3 * na, sizeof(double));
+            int64_t *cnt = calloc(na, sizeof(int64_t));
+            for (int64_t i = 0; i < N; ++i) {
+                for (int c = 0; c < 3; ++c) cen[3 * L->agg[i] + c] += P->xyz[3 * i + c];
+                cnt[L->agg[i]]++;
+            }
+            for (int64_t a = 0; a < na; ++a)
+                for (int c = 0; c < 3; ++c) cen[3 * a + c] /= (double)cnt[a];
+            for (int64_t i = 0; i < N; ++i) {
+                const double *c0 = cen + 3 * L->agg[i];
+                const double dx = P->xyz[3 * i] - c0[0], dy = P->xyz[3 * i + 1] - c0[1], dz = P->xyz[3 * i + 2] - c0[2];
+                const double rows[3][6] = {{1, 0, 0, 0, dz, -dy}, {0, 1, 0, -dz, 0, dx}, {0, 0, 1, dy, -dx, 0}};
+                for (int r = 0; r < 3; ++r)
+                    for (int k = 0; k < 6; ++k) B[(3 * i + r) * 6 + k] = P->dir_u[3 * i + r] ? 0.0 : rows[r][k];
+            }
+            free(cen);
+            free(cnt);
+        }
+        double *Bc = malloc(6 * na * 6 * sizeof(double));
+        or_csr Pt, AP;
+        amg_tentative(bs, nn, na, L->agg, B, &Pt, Bc);
+        /* P = Pt - w D^-1 A Pt */
+        csr_matmul(&A, &Pt, 6 * na, &AP);
+        amg_dinv_rows(L->Dinv, bs, nn, &AP);
+        const double w = 4.0 / (3.0 * L->rho);
+        /* AP's pattern contains Pt's (every node neighbours itself) */
+        for (int64_t row = 0; row < AP.n; ++row) {
+            for (int64_t q = AP.rowptr[row]; q < AP.rowptr[row + 1]; ++q) AP.val[q] *= -w;
+            for (int64_t q = Pt.rowptr[row]; q < Pt.rowptr[row + 1]; ++q) {
+                int64_t lo = AP.rowptr[row], hi = AP.rowptr[row + 1] - 1;
+                while (lo < hi) {
+                    const int64_t mid = (lo + hi) / 2;
+                    if (AP.col[mid] < Pt.col[q]) lo = mid + 1;
+                    else hi = mid;
+                }
+                AP.val[lo] += Pt.val[q];
+            }
+        }
+        csr_free(&Pt);
+        L->P = AP;
+        csr_transpose(&L->P, 6 * na, &L->R);
+        /* A_c = R (A P) */
+        or_csr W, Ac;
+        csr_matmul(&A, &L->P, 6 * na, &W);
+        csr_matmul(&L->R, &W, 6 * na, &Ac);
+        csr_free(&W);
+        /* a coarse DOF whose prolongator column vanished keeps an empty row: unit diagonal */
+        for (int64_t row = 0; row < Ac.n; ++row) {
+            double s = 0;
+            int64_t d = -1;
+            for (int64_t q = Ac.rowptr[row]; q < Ac.rowptr[row + 1]; ++q) {
+                s += fabs(Ac.val[q]);
+                if (Ac.col[q] == row) d = q;
+            }
+            if (s == 0.0 && d >= 0) Ac.val[d] = 1.0;
+        }
+        free(B);
+        B = Bc;
+        A = Ac;
+        bs = 6;
+        nn = na;
+    }
+    free(B);
+    free(twin);
+    /* dense Cholesky of the coarsest matrix */
+    or_amg_level *C = &G->L[G->nlev - 1];
+    const int64_t n = (int64_t)C->bs * C->nn;
+    G->nco = n;
+    G->chol = calloc(n * n, sizeof(double));
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t q = C->A.rowptr[i]; q < C->A.rowptr[i + 1]; ++q) G->chol[i * n + C->A.col[q]] = C->A.val[q];
+    for (int64_t j = 0; j < n; ++j) {
+        double d = G->chol[j * n + j];
+        for (int64_t k = 0; k < j; ++k) d -= G->chol[j * n + k] * G->chol[j * n + k];
+        if (!(d > 0)) {
+            status = -3;
+            d = 1.0;
+        }
+        d = sqrt(d);
+        G->chol[j * n + j] = d;
+        for (int64_t i = j + 1; i < n; ++i) {
+            double s = G->chol[i * n + j];
+            for (int64_t k = 0; k < j; ++k) s -= G->chol[i * n + k] * G->chol[j * n + k];
+            G->chol[i * n + j] = s / d;
+        }
+        for (int64_t i = 0; i < j; ++i) G->chol[i * n + j] = 0;
+    }
+    return status;
+}
+
+/* x = p(M^-1 A) M^-1 b, the degree-2 Chebyshev polynomial on [hi/30, hi] (Saad,
+ * Sec. 12.3; the recurrence of cheb_apply) with M the level's block Jacobi. */
+static void amg_smooth(const or_amg *G, int l, const double *b, double *x)
+{
+    const or_amg_level *L = &G->L[l];
+    const int64_t n = (int64_t)L->bs * L->nn;
+    const double hi = l == 0 ? G->hi0 : L->rho, lo = hi / 30.0;
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+    double *d = malloc(n * sizeof(double)), *s = malloc(n * sizeof(double)), *w = malloc(n * sizeof(double));
+    double *kd = malloc(n * sizeof(double));
+    /* M^-1 v */
+#define AMG_MINV(v, out)                                                                                  \
+    if (l == 0)                                                                                           \
+        bj_apply(&G->bj0, v, out);                                                                        \
+    else                                                                                                  \
+        for (int64_t i = 0; i < L->nn; ++i)                                                               \
+            for (int r = 0; r < 6; ++r) {                                                                 \
+                double t_ = 0;                                                                            \
+                for (int k = 0; k < 6; ++k) t_ += L->Dinv[36 * i + 6 * r + k] * v[6 * i + k];             \
+                out[6 * i + r] = t_;                                                                      \
+            }
+    AMG_MINV(b, d)
+    for (int64_t i = 0; i < n; ++i) {
+        d[i] /= theta;
+        x[i] = d[i];
+        s[i] = b[i];
+    }
+    const double rho0 = 1.0 / sigma;
+    or_csr_spmv(&L->A, d, kd);
+    for (int64_t i = 0; i < n; ++i) s[i] -= kd[i];
+    const double rho1 = 1.0 / (2.0 * sigma - rho0);
+    AMG_MINV(s, w)
+    for (int64_t i = 0; i < n; ++i) {
+        d[i] = rho1 * rho0 * d[i] + (2.0 * rho1 / delta) * w[i];
+        x[i] += d[i];
+    }
+#undef AMG_MINV
+    free(d);
+    free(s);
+    free(w);
+    free(kd);
+}
+
+static void amg_vcycle(const or_amg *G, int l, const double *b, double *x)
+{
+    const or_amg_level *L = &G->L[l];
+    const int64_t n = (int64_t)L->bs * L->nn;
+    if (l == G->nlev - 1) {
+        /* L L^T x = b */
+        for (int64_t i = 0; i < n; ++i) {
+            double s = b[i];
+            for (int64_t k = 0; k < i; ++k) s -= G->chol[i * n + k] * x[k];
+            x[i] = s / G->chol[i * n + i];
+        }
+        for (int64_t i = n - 1; i >= 0; --i) {
+            double s = x[i];
+            for (int64_t k = i + 1; k < n; ++k) s -= G->chol[k * n + i] * x[k];
+            x[i] = s / G->chol[i * n + i];
+        }
+        return;
+    }
+    const int64_t nc = 6 * L->nc;
+    double *r = malloc(n * sizeof(double)), *t = malloc(n * sizeof(double));
+    double *bc = malloc(nc * sizeof(double)), *xc = calloc(nc, sizeof(double));
+    amg_smooth(G, l, b, x);                                       /* pre-smoothing from zero */
+    or_csr_spmv(&L->A, x, t);
+    for (int64_t i = 0; i < n; ++i) r[i] = b[i] - t[i];
+    or_csr_spmv(&L->R, r, bc);                                    /* restriction */
+    amg_vcycle(G, l + 1, bc, xc);
+    or_csr_spmv(&L->P, xc, t);                                    /* prolongation */
+    for (int64_t i = 0; i < n; ++i) x[i] += t[i];
+    or_csr_spmv(&L->A, x, t);
+    for (int64_t i = 0; i < n; ++i) r[i] = b[i] - t[i];
+    amg_smooth(G, l, r, t);                                       /* post-smoothing */
+    for (int64_t i = 0; i < n; ++i) x[i] += t[i];
+    free(r);
+    free(t);
+    free(bc);
+    free(xc);
+}
+
+static void prec_amg(const or_problem *P, const or_bj *M, const void *ctx, const double *r, double *z)
+{
+    (void)P;
+    (void)M;
+    amg_vcycle((const or_amg *)ctx, 0, r, z);
+}
+
+/* PCG on K_t with the smoothed-aggregation V-cycle (hierarchy built for the current
+ * K_t; hi0 the level-0 smoother's interval end; coarsening down to coarse_nodes).
+ * stats (may be NULL): [levels, nodes of level 0..5 (6 entries)].  Returns 0, 1,
+ * or -3 (singular block, coarse matrix not SPD or p.Ap <= 0). */
+int or_pcg_amg(or_problem *P, const double *b, double *x, double tol, int64_t maxit, double hi0, int64_t coarse_nodes,
+               int64_t *iters, double *relres, double *stats)
+{
+    or_amg G;
+    int status = amg_setup(P, &G, hi0, coarse_nodes);
+    if (stats) {
+        stats[0] = G.nlev;
+        for (int l = 0; l < OR_AMG_MAXLEV; ++l) stats[1 + l] = l < G.nlev ? (double)G.L[l].nn : 0.0;
+    }
+    if (status == 0) {
+        status = pcg_prec(P, &G.bj0, prec_amg, &G, b, x, tol, maxit, iters, relres);
+    } else {
+        memset(x, 0, 3 * P->N * sizeof(double));
+        *iters = 0;
+        *relres = 0;
+    }
+    amg_free(&G);
+    return status;
+}
+
+/* z = V-cycle(r) for the current K_t (one application of the preconditioner). */
+int or_amg_apply(or_problem *P, const double *r, double *z, double hi0, int64_t coarse_nodes)
+{
+    or_amg G;
+    int status = amg_setup(P, &G, hi0, coarse_nodes);
+    if (status == 0) amg_vcycle(&G, 0, r, z);
+    amg_free(&G);
+    return status;
+}
+
+/* Export of level l of the hierarchy: which 0 = A_l, 1 = P_l, 2 = the aggregate of
+ * each node of level l (into col, as int32; val unused).  With rowptr == NULL only
+ * the sizes are returned in dims = [rows, cols, nnz]. */
+int or_amg_export(or_problem *P, double hi0, int64_t coarse_nodes, int level, int which, int64_t *dims,
+                  int64_t *rowptr, int32_t *col, double *val)
+{
+    or_amg G;
+    int status = amg_setup(P, &G, hi0, coarse_nodes);
+    if (level >= G.nlev || (which != 0 && level >= G.nlev - 1)) {
+        amg_free(&G);
+        return -1;
+    }
+    const or_amg_level *L = &G.L[level];
+    if (which == 2) {
+        dims[0] = L->nn;
+        dims[1] = L->nc;
+        dims[2] = L->nn;
+        if (col) memcpy(col, L->agg, L->nn * sizeof(int32_t));
+    } else {
+        const or_csr *M = which == 0 ? &L->A : &L->P;
+        dims[0] = M->n;
+        dims[1] = which == 0 ? M->n : 6 * L->nc;
+        dims[2] = M->nnz;
+        if (rowptr) {
+            memcpy(rowptr, M->rowptr, (M->n + 1) * sizeof(int64_t));
+            memcpy(col, M->col, M->nnz * sizeof(int32_t));
+            memcpy(val, M->val, M->nnz * sizeof(double));
+        }
+    }
+    amg_free(&G);
+    return status;
+}

@@ -91,6 +91,14 @@ def lib():
         L.or_bicgstab_exact.restype = C.c_int
         L.or_bicgstab_exact.argtypes = [C.c_void_p, _f64p, _f64p, C.c_double, C.c_int64, C.POINTER(C.c_int64),
                                         C.POINTER(C.c_double)]
+        L.or_pcg_amg.restype = C.c_int
+        L.or_pcg_amg.argtypes = [C.c_void_p, _f64p, _f64p, C.c_double, C.c_int64, C.c_double, C.c_int64,
+                                 C.POINTER(C.c_int64), C.POINTER(C.c_double), _f64p]
+        L.or_amg_apply.restype = C.c_int
+        L.or_amg_apply.argtypes = [C.c_void_p, _f64p, _f64p, C.c_double, C.c_int64]
+        L.or_amg_export.restype = C.c_int
+        L.or_amg_export.argtypes = [C.c_void_p, C.c_double, C.c_int64, C.c_int, C.c_int, _i64p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p]
         L.or_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -381,6 +389,41 @@ def _adjoint_methods():
             lp_next = lp
         return dE_t, dk_t
 
+    def pcg_amg(self, b, hi0, coarse_nodes=64, tol=1e-10, maxit=100000):
+        """K_t x = b by PCG with the smoothed-aggregation V-cycle: (x, status, iters, relres, levels, nodes per level)."""
+        x = np.zeros(3 * self.N)
+        it, rr = C.c_int64(), C.c_double()
+        st = np.zeros(7)
+        s = lib().or_pcg_amg(self._h, _c(b, np.float64), x, tol, maxit, float(hi0), int(coarse_nodes), C.byref(it),
+                             C.byref(rr), st)
+        return x, s, it.value, rr.value, int(st[0]), st[1:1 + int(st[0])].astype(int)
+
+    def amg_apply(self, r, hi0, coarse_nodes=64):
+        """One V-cycle z = B r of the smoothed-aggregation preconditioner for the current K_t."""
+        z = np.zeros(3 * self.N)
+        s = lib().or_amg_apply(self._h, _c(r, np.float64), z, float(hi0), int(coarse_nodes))
+        if s != 0:
+            raise RuntimeError(f"AMG set-up failed ({s})")
+        return z
+
+    def amg_export(self, hi0, level, which, coarse_nodes=64):
+        """Level `level` of the hierarchy: which 0 -> A_l, 1 -> P_l (scipy CSR), 2 -> aggregate of each node."""
+        import scipy.sparse as sp
+        dims = np.zeros(3, np.int64)
+        if lib().or_amg_export(self._h, float(hi0), int(coarse_nodes), level, which, dims, None, None, None) == -1:
+            raise IndexError(level)
+        if which == 2:
+            agg = np.zeros(dims[0], np.int32)
+            lib().or_amg_export(self._h, float(hi0), int(coarse_nodes), level, which, dims, None, agg.ctypes.data, None)
+            return agg
+        rp, col, val = np.zeros(dims[0] + 1, np.int64), np.zeros(dims[2], np.int32), np.zeros(dims[2])
+        lib().or_amg_export(self._h, float(hi0), int(coarse_nodes), level, which, dims, rp.ctypes.data,
+                            col.ctypes.data, val.ctypes.data)
+        return sp.csr_matrix((val, col, rp), shape=(int(dims[0]), int(dims[1])))
+
+    Problem.pcg_amg = pcg_amg
+    Problem.amg_apply = amg_apply
+    Problem.amg_export = amg_export
     Problem.apply_NT = apply_NT
     Problem.apply_N = apply_N
     Problem.bicgstab_exact = bicgstab_exact
