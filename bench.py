@@ -44,7 +44,9 @@ def main():
                     help="oracle PCG iterations timed for the CPU baseline (about 10 s at 128^3)")
     ap.add_argument("--no-extras", action="store_true", help="skip every extra measurement")
     ap.add_argument("--extras", default="tt8,adjoint,steps,block,batch",
-                    help="comma list of extra measurements: tt8, adjoint, steps, block, batch")
+                    help="comma list of extra measurements: tt8, adjoint, steps, block, batch, and fd64 "
+                         "(central differences of the 64^3 adjoint along 20 directions: about 10 minutes, "
+                         "not in the default list)")
     ap.add_argument("--profile-iters", type=int, default=0,
                     help="profiling mode for hardware counters: run exactly this many FP64 K-PCG iterations and "
                          "one 1 GiB device copy (counter calibration), print a short JSON line, skip the rest")
@@ -255,6 +257,8 @@ def main():
         out["adjoint_64"] = extra_adjoint(ctx, log)
     if "steps" in extras:
         out["steps_64"] = extra_steps(ctx, log)
+    if "fd64" in extras:
+        out["fd_64"] = extra_fd64(ctx, log)
     if "block" in extras:
         out["block_64"] = extra_block(ctx, log)
     if "batch" in extras:
@@ -426,11 +430,12 @@ def extra_adjoint(ctx, log):
             "forward_block_jacobi": fwd, "adjoint_block_jacobi": bj}
 
 
-def extra_steps(ctx, log, nsteps=3):
-    """The first steps of the 20-step 64^3 trajectory (constant injection, the state U, P and
-    inelastic slip carried from step to step, inexact Newton as in the adjoint), checkpointed,
-    then the reverse sweep: the gradient of J = sum over the steps of the fault-slip and uplift
-    objective w.r.t. ln k and E through the whole loop, slip state included."""
+def extra_steps(ctx, log, nsteps=20):
+    """The 20-step 64^3 trajectory (constant injection, the state U, P and inelastic slip
+    carried from step to step, inexact Newton as in the adjoint, block-Jacobi K solves),
+    checkpointed, then the reverse sweep: the gradient of J = sum over the steps of the
+    fault-slip and uplift objective w.r.t. ln k and E through the whole loop, slip state
+    included."""
     import numpy as np
     import torch
 
@@ -447,6 +452,7 @@ def extra_steps(ctx, log, nsteps=3):
     U, P, die = d(np.zeros(3 * S.N)), d(np.zeros(S.N)), d(np.zeros(2 * S.nq))
     t0, load, src = d(inst.t0.reshape(-1)), d(inst.load), d(inst.source)
     inner = fg.opts(tol=1e-4, check_every=64)
+    S.tune("k_precond", 1)
     steps, ck = [], []
     for k in range(nsteps):
         ts, (c, infos) = _timed(lambda: T.run(S, U, P, die, t0, load, src, 1, newton_tol=1e-8, newton_max_iter=60,
@@ -475,15 +481,96 @@ def extra_steps(ctx, log, nsteps=3):
     corr = fg.opts(tol=1e-3, check_every=64)
     tr, (dE, dk, ainfos) = _timed(lambda: T.gradient(S, ck, t0, logk, grad_y, inner_k=corr, inner_p=corr,
                                                      outer_tol=0.05, defect_tol=1e-8))
+    S.tune("k_precond", 0)
     defect = [i.newton_iters for i in ainfos]
     log(f"reverse sweep over {nsteps} steps: {tr:.1f}s, defect iterations per step {defect}, "
         f"K iters {sum(i.inner_k_iters for i in ainfos)}")
-    return {"workload": f"cube64_dip60_hetero, {nsteps} consecutive 1 s steps of the 20-step trajectory; Newton 1e-8, "
-                        f"outer 1e-2, inner 1e-4; reverse sweep: defect 1e-8, corrections outer 0.05 inner 1e-3",
-            "steps": steps, "mean_step_s": float(np.mean([s["s"] for s in steps])),
-            "reverse_s": tr, "reverse_defect_iters": defect,
+    fwd = float(sum(s["s"] for s in steps))
+    return {"workload": f"cube64_dip60_hetero, {nsteps} consecutive 1 s steps (the 20-step trajectory); block-Jacobi "
+                        f"K solves; Newton 1e-8, outer 1e-2, inner 1e-4; reverse sweep: defect 1e-8, corrections "
+                        f"outer 0.05 inner 1e-3",
+            "steps": steps, "mean_step_s": float(np.mean([s["s"] for s in steps])), "forward_s": fwd,
+            "reverse_s": tr, "reverse_defect_iters": defect, "gradients_per_s": 1.0 / tr,
+            "forward_and_reverse_s": fwd + tr,
             "reverse_k_iters": int(sum(i.inner_k_iters for i in ainfos)),
             "gradient_norm": float(torch.linalg.norm(torch.cat([dE * E, dk])).item())}
+
+
+def extra_fd64(ctx, log, count=20, eps=1e-6):
+    """Central differences of the 64^3 injection step's objective (squared fault slip plus
+    squared uplift at 32 seeded top nodes) along `count` seeded unit directions in
+    (ln k, ln E), step eps, against the adjoint gradient in FP64 and in mixed precision.
+    Every forward is a step from rest with block-Jacobi K solves, the exact interface
+    tangent (quadratic Newton) and a tight Newton tolerance."""
+    import numpy as np
+    import torch
+
+    from paper_2410_17133_amd import fg
+    from paper_2410_17133_amd import inputs as I
+    from paper_2410_17133_amd.autograd import fault_slip_uplift_objective
+
+    inst = I.make_instance(I.config(4))
+    S = fg.System.from_instance(ctx, inst)
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float64)).cuda()
+    t0, load, src = d(inst.t0.reshape(-1)), d(inst.load), d(inst.source)
+    m = inst.mesh
+    X = m.xyz[m.coh[0, 3:]]
+    nrm = np.cross(X[1] - X[0], X[2] - X[0])
+    pairs, nrm_d = torch.as_tensor(m.pairs.astype(np.int64)).cuda(), d(nrm / np.linalg.norm(nrm))
+    up = torch.as_tensor(I.uplift_nodes(inst, 32).astype(np.int64)).cuda()
+    S.tune("k_precond", 1)
+    S.tune("exact_tangent", 1)
+    inner = fg.opts(tol=1e-6, check_every=64)
+
+    def forward(logk, E):
+        S.assemble(inst.params, E, logk)
+        U, P, die = d(np.zeros(3 * S.N)), d(np.zeros(S.N)), d(np.zeros(2 * S.nq))
+        _, flag, info = S.step(U, P, die, t0, load, src, newton_tol=1e-12, newton_max_iter=80, inner_k=inner,
+                               inner_p=inner, outer_tol=1e-3)
+        if info.status != 0:
+            raise RuntimeError(f"forward step failed: status {info.status}, residuals {info.res_m:.1e} {info.res_f:.1e}")
+        return U, P, flag, info
+
+    E0, lk0 = d(inst.E), d(inst.logk)
+    tf, (U, P, flag, info) = _timed(lambda: forward(lk0, E0))
+    log(f"fd64: base forward {tf:.1f}s newton {info.newton_iters} cuts {info.step_cuts} slip {int((flag == 1).sum())}")
+    Uv = U.clone().requires_grad_(True)
+    J0 = fault_slip_uplift_objective(Uv, pairs, nrm_d, up)
+    gU, = torch.autograd.grad(J0, Uv)
+    die0 = torch.zeros(2 * S.nq, dtype=torch.float64, device="cuda")
+    grads = {}
+    for name, prec in (("f64", fg.FG_F64), ("mixed", fg.FG_MIXED)):
+        S.tune("exact_tangent", 0)              # mixed K solves are symmetric; both refine on the exact residual
+        ik = fg.opts(tol=1e-3, check_every=64, precision=prec)
+        ip = fg.opts(tol=1e-3, check_every=64)
+        ta, (dE, dk, ainfo) = _timed(lambda: S.adjoint(U, P, die0, t0, lk0, gU, torch.zeros_like(P), inner_k=ik,
+                                                        inner_p=ip, outer_tol=0.05, defect_tol=1e-11))
+        log(f"fd64: adjoint {name} {ta:.2f}s defect iterations {ainfo.newton_iters} status {ainfo.status}")
+        grads[name] = (dk.cpu().numpy(), (dE * E0).cpu().numpy(), ta)   # dJ/dln k, dJ/dln E
+    S.tune("exact_tangent", 1)
+    ne = inst.E.size
+    rows = []
+    t = time.perf_counter()
+    for j, dvec in enumerate(I.fd_directions(2 * ne, count=count)):
+        dlk, dlE = dvec[:ne], dvec[ne:]
+        Jpm = []
+        for sgn in (1.0, -1.0):
+            Uj = forward(d(inst.logk + sgn * eps * dlk), d(inst.E * np.exp(sgn * eps * dlE)))[0]
+            Jpm.append(fault_slip_uplift_objective(Uj, pairs, nrm_d, up).item())
+        fd = (Jpm[0] - Jpm[1]) / (2 * eps)
+        ad = {k: float(g[0] @ dlk + g[1] @ dlE) for k, g in grads.items()}
+        rows.append({"fd": fd, "adjoint_f64": ad["f64"], "adjoint_mixed": ad["mixed"],
+                     "rel_f64": abs(fd - ad["f64"]) / abs(ad["f64"]), "rel_mixed": abs(fd - ad["mixed"]) / abs(ad["mixed"])})
+        log(f"fd64 direction {j}: fd {fd:.10e} adjoint f64 {ad['f64']:.10e} (rel {rows[-1]['rel_f64']:.1e}) mixed "
+            f"{ad['mixed']:.10e} (rel {rows[-1]['rel_mixed']:.1e}) [{time.perf_counter() - t:.0f}s]")
+    S.tune("k_precond", 0)
+    S.tune("exact_tangent", 0)
+    return {"workload": f"cube64_dip60_hetero one implicit step from rest, {2 * ne} parameters (ln k, ln E); "
+                        f"{count} seeded unit directions, central differences with step {eps}; forwards with "
+                        f"block-Jacobi K solves, exact interface tangent, Newton 1e-12; adjoint defect 1e-11",
+            "J": J0.item(), "base_forward_s": tf, "adjoint_f64_s": grads["f64"][2], "adjoint_mixed_s": grads["mixed"][2],
+            "max_rel_f64": max(r["rel_f64"] for r in rows), "max_rel_mixed": max(r["rel_mixed"] for r in rows),
+            "directions": rows}
 
 
 def extra_block(ctx, log):

@@ -282,6 +282,33 @@ fg_status fg_adjoint_solve(fg_ctx *ctx, fg_system *sys, const double *U, const d
 fg_status fg_slip_adjoint(fg_ctx *ctx, fg_system *sys, const double *U, const double *die_old, const double *t0,
                           const double *a_new, const double *lam_u, double *gU, double *a_old, void *stream);
 
+/* One step of the reverse sweep through a time loop of implicit steps (the adjoint
+ * of Sec. 3.3.1 carried backwards over the backward-Euler steps of eq. time_disc),
+ * for an objective J = sum_n j_n(U_n, P_n).  Going n = T..1, step n solves
+ *   J_n^T lam_n = dj_n/dy_n - (dR_{n+1}/dy_n)^T lam_{n+1} + (dPhi_n/dU_n)^T a_n
+ * where the next step's flow residual reads y_n = (U_n, P_n) through -A_up U_n and
+ * -(A22 - dt C) P_n (fg_step's R_f), so its multipliers add A_pu lam_{n+1,p} to
+ * the displacement block and (A22 - dt C) lam_{n+1,p} to the pressure block, and
+ * Phi_n is the return map that carries the slip (fg_slip_adjoint).  The system is
+ * solved as in fg_adjoint_solve (same options and stop test); then
+ *   a_{n-1} = (dPhi_n/ddie_{n-1})^T a_n - (df_coh/ddie_{n-1})^T lam_{n,u}
+ * and the step's share -lam_n^T dR_n/dtheta is ADDED to dJ_dE and dJ_dlogk.
+ *   U, P, die_old  step n's converged state and its start-of-step slip
+ *   t0, log_k      initial tractions and the log-permeability of the assembly
+ *   dJdU, dJdP     [3N], [N] dj_n/dU_n, dj_n/dP_n
+ *   lam_p_next     [N] lam_{n+1,p} (lam_p of the previous call), NULL for the last step
+ *   a              [nq*2] in: a_n (zero for the last step), out: a_{n-1}
+ *   dJ_dE, dJ_dlogk [n_tets] accumulated gradient (caller order)
+ *   lam_u, lam_p   [3N], [N] out, this step's multipliers (each may be NULL)
+ * All device pointers, caller order.  Returns as fg_adjoint_solve; outputs are
+ * unspecified after an error. */
+fg_status fg_adjoint_loop_step(fg_ctx *ctx, fg_system *sys, const double *U, const double *P, const double *die_old,
+                               const double *t0, const double *log_k, const double *dJdU, const double *dJdP,
+                               const double *lam_p_next, double *a, double *dJ_dE, double *dJ_dlogk, double *lam_u,
+                               double *lam_p, const fg_pcg_opts *inner_k, const fg_pcg_opts *inner_p,
+                               double outer_tol, double defect_tol, int64_t max_defect_iters, fg_solve_info *info,
+                               void *stream);
+
 /* (K_t + N) x = b: the exact interface tangent.  K_t is the current K (its
  * interface rows written by the last fg_cohesive_update with write_tangent); N is
  * the part of the exact slip tangent that K_t omits, from the point states of
@@ -314,6 +341,17 @@ fg_status fg_exact_solve(fg_ctx *ctx, fg_system *sys, const double *b, double *x
  * stream.  Errors: FG_ERR_ARG, FG_ERR_STATE (before fg_assemble, or k_precond is
  * not 2), FG_ERR_BREAKDOWN (singular block, K not SPD, or the probe vanished). */
 fg_status fg_cheb_interval(fg_ctx *ctx, fg_system *sys, double *lo, double *hi, void *stream);
+
+/* Extreme eigenvalue estimates of the block-Jacobi preconditioned tangent M^-1 K
+ * (M as "k_precond" 1): the smallest and largest Ritz values (host outputs) of the
+ * Lanczos matrix of `steps` block-Jacobi CG steps on the SplitMix64 probe vector
+ * of fg_cheb_interval (Saad, Sec. 6.7.3).  hi / lo estimates the condition
+ * number that bounds the forward error of a K solve (the Ritz values lie inside
+ * the spectrum, so the estimate is a lower bound).  steps in [2, 100000]; fewer
+ * steps are taken if r.z vanishes first.  Synchronises the stream.
+ * Errors: FG_ERR_ARG (also for batched systems), FG_ERR_STATE (before
+ * fg_assemble), FG_ERR_BREAKDOWN (singular block or K not SPD), FG_ERR_OOM. */
+fg_status fg_lanczos_bounds(fg_ctx *ctx, fg_system *sys, int steps, double *lo, double *hi, void *stream);
 
 /* Products on the assembled system, caller order: y = A x for which in
  * {FG_K, FG_A22, FG_KBULK, FG_C, FG_K_EXACT} (FG_K_EXACT: see fg_exact_solve). */
@@ -374,8 +412,10 @@ fg_status fg_group_stats(const fg_system *sys, int64_t *iters_h, double *relres_
  *               vector (fg_cheb_interval).  Each CG iteration then costs
  *               cheb_degree products with K and reduces twice.  Blocks and
  *               interval are rebuilt after every change of K; FG_ERR_BREAKDOWN if
- *               a block is singular.  Block (nrhs > 1), batched and
- *               FG_MIXED_F32VAL solves keep point Jacobi.
+ *               a block is singular.  Block solves (nrhs > 1) and
+ *               batched systems apply the block-Jacobi stage (1 and 2 alike) to
+ *               every column / group, in FP64 and in the FP32 CG of FG_F32 /
+ *               FG_MIXED; FG_MIXED_F32VAL solves keep point Jacobi.
  *   "exact_tangent": 1 makes the FP64 K solves inside fg_flow_solve and fg_step
  *               solve the exact tangent K_t + N by BiCGStab (as fg_exact_solve),
  *               so that Newton uses the exact Jacobian of the interface force;

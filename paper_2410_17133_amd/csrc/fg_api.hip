@@ -400,7 +400,7 @@ fg_status fg_system_destroy(fg_system *S)
     if (!S) return FG_OK;
     Guard g(S->device);
     hipDeviceSynchronize();
-    void *ptrs[] = {S->gprm, S->slice_group, S->group_slice_ptr, S->gsc, S->gpart, S->gred, S->halo_ptr, S->halo, S->lcol, S->slice_ptr, S->col, S->rowlen, S->diag_slot, S->perm, S->xyz, S->tets, S->tet_orig, S->coh,
+    void *ptrs[] = {S->gprm, S->slice_group, S->group_slice_ptr, S->gsc, S->gpart, S->gred, S->halo_ptr, S->halo, S->lcol, S->slice_ptr, S->col, S->rowlen, S->diag_slot, S->perm, S->xyz, S->tets, S->tet_orig, S->tslot, S->coh,
                     S->frows, S->fadj_ptr, S->fadj, S->dir_u, S->dir_p, S->tri_geo, S->K, S->K32, S->Kfb, S->A22,
                     S->Cm, S->dinvK, S->dinvK32, S->dinvA, S->qpD, S->qpT, S->qpNs, S->qpS, S->adj_trac, S->adj_die, S->adj_flag, S->wx, S->wr, S->wp, S->wq, S->fx,
                     S->fr, S->fp, S->fq, S->v1, S->v2, S->v3, S->v4, S->pv1, S->pv2, S->ui, S->ui0, S->fi, S->rm,
@@ -411,8 +411,8 @@ fg_status fg_system_destroy(fg_system *S)
     drop_graphs(S);
     drop_mr_graphs(S);
     drop_group_graphs(S);
-    void *mr_ptrs[] = {S->mx, S->mr, S->mp, S->mq, S->mb, S->mx64, S->mr64, S->mfx, S->mfr, S->mfp, S->mfq,
-                       S->msc, S->mpart, S->mred};
+    void *mr_ptrs[] = {S->mx, S->mr, S->mp, S->mq, S->mb, S->mx64, S->mr64, S->mz, S->mfx, S->mfr, S->mfp, S->mfq,
+                       S->mfz, S->msc, S->mpart, S->mred};
     for (void *p : mr_ptrs) dfree(p);
     if (S->msc_host) hipHostFree(S->msc_host);
     if (S->gsc_host) hipHostFree(S->gsc_host);
@@ -562,6 +562,18 @@ fg_status fg_system_create(fg_ctx *ctx, const fg_mesh *mesh, fg_system **out)
         set_error("fg_system_create: mesh too large for the reduction workspace");
         fg_system_destroy(S);
         return FG_ERR_ARG;
+    }
+    if (dalloc(&S->tslot, 16 * std::max<int64_t>(S->ne, 1))) {
+        set_error("fg_system_create: allocation of the tetrahedron slot table failed");
+        fg_system_destroy(S);
+        return FG_ERR_OOM;
+    }
+    {
+        fg_status e = tet_slots(S, nullptr);
+        if (e) {
+            fg_system_destroy(S);
+            return e;
+        }
     }
     *out = S;
     return check_hip("fg_system_create");
@@ -870,36 +882,26 @@ fg_status fg_step(fg_ctx *ctx, fg_system *S, double *U, double *P, double *die, 
     return e ? e : status;
 }
 
-fg_status fg_adjoint_solve(fg_ctx *ctx, fg_system *S, const double *U, const double *P, const double *die_n,
-                           const double *t0, const double *log_k, const double *dJdU, const double *dJdP,
-                           double *dJ_dE, double *dJ_dlogk, double *lam_u, double *lam_p,
-                           const fg_pcg_opts *inner_k, const fg_pcg_opts *inner_p, double outer_tol,
-                           double defect_tol, int64_t max_defect_iters, fg_solve_info *info, void *stream)
+// The transposed Newton system of one converged step and its gradient (the body of
+// fg_adjoint_solve).  On entry S->ui, S->pi hold the state and S->fi, S->qi the
+// objective gradient (internal order, zero on held DOFs).  On success the
+// multipliers are left in S->ui0 (lam_u) and S->pi0 (lam_p), and the gradient is
+// written to (or, with accumulate, added to) dJ_dE, dJ_dlogk.
+static fg_status adjoint_core(fg_system *S, const double *die_n, const double *t0, const double *log_k,
+                              double *dJ_dE, double *dJ_dlogk, bool accumulate, double *lam_u, double *lam_p,
+                              const fg_pcg_opts *inner_k, const fg_pcg_opts *inner_p, double outer_tol,
+                              double defect_tol, int64_t max_defect_iters, fg_solve_info *info, hipStream_t st)
 {
-    if (!ctx || !S || !U || !P || !log_k || !dJdU || !dJdP || !dJ_dE || !dJ_dlogk ||
-        (S->nq && (!die_n || !t0)) || !(outer_tol > 0) || !(defect_tol > 0)) {
-        set_error("fg_adjoint_solve: bad argument");
-        return FG_ERR_ARG;
-    }
-    if (!ready(S)) return FG_ERR_STATE;
-    Guard g(ctx->device);
     // the corrections solve with the symmetric tangent, or with K_t + N^T when the
     // exact tangent is on; either way the true residual below carries N^T
     AdjointSolves adj(S);
-    hipStream_t st = S_(stream);
     const int64_t n1 = 3 * S->Npad, n2 = S->Npad;
     fg_pcg_opts ok = defaults(inner_k, 1e-12), op = defaults(inner_p, 1e-12);
     fg_solve_info si{};
     // interface state and symmetric tangent at the converged state
-    perm_in(S, 3, U, S->ui, st);
-    perm_in(S, 1, P, S->pi, st);
     cohesive_qp(S, S->ui, die_n, t0, S->adj_trac, S->adj_die, S->adj_flag, st);
     cohesive_rows(S, S->fc, 1, st);
-    // right-hand sides: b1 = -dJ/dU - N^T mu, b2 = dJ/dP (held DOFs zero)
-    perm_in(S, 3, dJdU, S->fi, st);
-    vmask(n1, S->dir_u, S->fi, st);
-    perm_in(S, 1, dJdP, S->qi, st);
-    vmask(n2, S->dir_p, S->qi, st);
+    // right-hand sides: b1 = -dJ/dU - N^T mu, b2 = dJ/dP
     // Defect correction in refinement form: the true residual of the exact transposed
     // system, r = f - [(K + N^T) mu - A_pu lp ; A_up mu + A22 lp], is computed with the
     // FP64 operators and only the correction is solved, with the symmetric tangent,
@@ -962,7 +964,7 @@ fg_status fg_adjoint_solve(fg_ctx *ctx, fg_system *S, const double *U, const dou
     si.inner_a22_iters = ait;
     if (status >= 0) {
         vscale(n1, -1.0, mu, st);  // lam_u = -mu
-        sensitivity(S, S->ui, S->pi, mu, lp, dJ_dE, dJ_dlogk, log_k, st);
+        sensitivity(S, S->ui, S->pi, mu, lp, dJ_dE, dJ_dlogk, log_k, accumulate, st);
         if (lam_u) perm_out(S, 3, mu, lam_u, st);
         if (lam_p) perm_out(S, 1, lp, lam_p, st);
     }
@@ -971,7 +973,83 @@ fg_status fg_adjoint_solve(fg_ctx *ctx, fg_system *S, const double *U, const dou
     si.outer_relres = change;
     si.status = status;
     if (info) *info = si;
+    return status;
+}
+
+fg_status fg_adjoint_solve(fg_ctx *ctx, fg_system *S, const double *U, const double *P, const double *die_n,
+                           const double *t0, const double *log_k, const double *dJdU, const double *dJdP,
+                           double *dJ_dE, double *dJ_dlogk, double *lam_u, double *lam_p,
+                           const fg_pcg_opts *inner_k, const fg_pcg_opts *inner_p, double outer_tol,
+                           double defect_tol, int64_t max_defect_iters, fg_solve_info *info, void *stream)
+{
+    if (!ctx || !S || !U || !P || !log_k || !dJdU || !dJdP || !dJ_dE || !dJ_dlogk ||
+        (S->nq && (!die_n || !t0)) || !(outer_tol > 0) || !(defect_tol > 0)) {
+        set_error("fg_adjoint_solve: bad argument");
+        return FG_ERR_ARG;
+    }
+    if (!ready(S)) return FG_ERR_STATE;
+    Guard g(ctx->device);
+    hipStream_t st = S_(stream);
+    perm_in(S, 3, U, S->ui, st);
+    perm_in(S, 1, P, S->pi, st);
+    perm_in(S, 3, dJdU, S->fi, st);
+    vmask(3 * S->Npad, S->dir_u, S->fi, st);
+    perm_in(S, 1, dJdP, S->qi, st);
+    vmask(S->Npad, S->dir_p, S->qi, st);
+    fg_status status = adjoint_core(S, die_n, t0, log_k, dJ_dE, dJ_dlogk, false, lam_u, lam_p, inner_k, inner_p,
+                                    outer_tol, defect_tol, max_defect_iters, info, st);
     fg_status e = check_hip("fg_adjoint_solve");
+    return e ? e : status;
+}
+
+fg_status fg_adjoint_loop_step(fg_ctx *ctx, fg_system *S, const double *U, const double *P, const double *die_old,
+                               const double *t0, const double *log_k, const double *dJdU, const double *dJdP,
+                               const double *lam_p_next, double *a, double *dJ_dE, double *dJ_dlogk, double *lam_u,
+                               double *lam_p, const fg_pcg_opts *inner_k, const fg_pcg_opts *inner_p,
+                               double outer_tol, double defect_tol, int64_t max_defect_iters, fg_solve_info *info,
+                               void *stream)
+{
+    if (!ctx || !S || !U || !P || !log_k || !dJdU || !dJdP || !dJ_dE || !dJ_dlogk ||
+        (S->nq && (!die_old || !t0 || !a)) || !(outer_tol > 0) || !(defect_tol > 0)) {
+        set_error("fg_adjoint_loop_step: bad argument");
+        return FG_ERR_ARG;
+    }
+    if (!ready(S)) return FG_ERR_STATE;
+    Guard g(ctx->device);
+    hipStream_t st = S_(stream);
+    const int64_t n1 = 3 * S->Npad, n2 = S->Npad;
+    perm_in(S, 3, U, S->ui, st);
+    perm_in(S, 1, P, S->pi, st);
+    perm_in(S, 3, dJdU, S->fi, st);
+    vmask(n1, S->dir_u, S->fi, st);
+    perm_in(S, 1, dJdP, S->qi, st);
+    vmask(n2, S->dir_p, S->qi, st);
+    if (lam_p_next) {
+        // the next step's flow residual reads this state through -A_up U_n and
+        // -(A22 - dt C) P_n: its multipliers add A_pu lam and (A22 - dt C) lam
+        double *lam = S->s7, *a22 = S->s8, *cl = S->s6;
+        perm_in(S, 1, lam_p_next, lam, st);
+        apply_Apu(S, lam, S->pv1, st);
+        vaxpby(n1, 1.0, S->pv1, 1.0, S->fi, st);
+        spmv(S, FG_A22, lam, a22, st);
+        spmv(S, FG_C, lam, cl, st);
+        vaxpby(n2, -S->prm.dt, cl, 1.0, a22, st);
+        vmask(n2, S->dir_p, a22, st);
+        vaxpby(n2, 1.0, a22, 1.0, S->qi, st);
+    }
+    if (S->nq) {
+        // the slip this step produced, through the return map: (dPhi/dU)^T a
+        slip_adjoint(S, S->ui, die_old, t0, a, nullptr, S->v2, nullptr, st);
+        vaxpby(n1, 1.0, S->v2, 1.0, S->fi, st);
+    }
+    fg_status status = adjoint_core(S, die_old, t0, log_k, dJ_dE, dJ_dlogk, true, lam_u, lam_p, inner_k, inner_p,
+                                    outer_tol, defect_tol, max_defect_iters, info, st);
+    if (status >= 0 && S->nq) {
+        // the adjoint of the slip the step started from (lam_u is in S->ui0)
+        slip_adjoint(S, S->ui, die_old, t0, a, S->ui0, nullptr, S->adj_die, st);
+        hipMemcpyAsync(a, S->adj_die, 2 * S->nq * sizeof(double), hipMemcpyDeviceToDevice, st);
+    }
+    fg_status e = check_hip("fg_adjoint_loop_step");
     return e ? e : status;
 }
 
@@ -1029,6 +1107,46 @@ fg_status fg_exact_solve(fg_ctx *ctx, fg_system *S, const double *b, double *x, 
     }
     fg_status e = check_hip("fg_exact_solve");
     return e ? e : s;
+}
+
+// The block-Jacobi data and the Chebyshev work vectors (allocated on first use).
+static fg_status precond_buffers(fg_system *S, bool cheb)
+{
+    if (cheb && !S->chd) {
+        if (dalloc(&S->chd, 3 * S->Npad) || dalloc(&S->chs, 3 * S->Npad) || dalloc(&S->chq, 3 * S->Npad)) {
+            set_error("device allocation for the Chebyshev preconditioner failed");
+            return FG_ERR_OOM;
+        }
+    }
+    if (!S->bjA) {
+        if (dalloc(&S->bjA, 6 * S->Npad) || dalloc(&S->bjB, 9 * std::max<int64_t>(S->nfr, 1)) ||
+            dalloc(&S->wz, 3 * S->Npad) || dalloc(&S->bjA32, 6 * S->Npad) ||
+            dalloc(&S->bjB32, 9 * std::max<int64_t>(S->nfr, 1)) || dalloc(&S->wz32, 3 * S->Npad)) {
+            set_error("device allocation for the block-Jacobi preconditioner failed");
+            return FG_ERR_OOM;
+        }
+        S->bj_valid = false;
+    }
+    return FG_OK;
+}
+
+fg_status fg_lanczos_bounds(fg_ctx *ctx, fg_system *S, int steps, double *lo, double *hi, void *stream)
+{
+    if (!ctx || !S || !lo || !hi || steps < 2 || steps > 100000) {
+        set_error("fg_lanczos_bounds: bad argument");
+        return FG_ERR_ARG;
+    }
+    if (!ready(S)) return FG_ERR_STATE;
+    if (S->ngroups > 1) {
+        set_error("fg_lanczos_bounds: batched systems are not supported");
+        return FG_ERR_ARG;
+    }
+    Guard g(ctx->device);
+    fg_status e = precond_buffers(S, true);
+    if (e) return e;
+    e = lanczos_bounds(S, steps, lo, hi, S_(stream));
+    if (e) return e;
+    return check_hip("fg_lanczos_bounds");
 }
 
 fg_status fg_cheb_interval(fg_ctx *ctx, fg_system *S, double *lo, double *hi, void *stream)
@@ -1177,20 +1295,9 @@ fg_status fg_tune(fg_system *S, const char *key, int64_t value)
                       "(Chebyshev polynomial over block Jacobi)");
             return FG_ERR_ARG;
         }
-        if (value == 2 && !S->chd) {
-            if (dalloc(&S->chd, 3 * S->Npad) || dalloc(&S->chs, 3 * S->Npad) || dalloc(&S->chq, 3 * S->Npad)) {
-                set_error("fg_tune: device allocation for the Chebyshev preconditioner failed");
-                return FG_ERR_OOM;
-            }
-        }
-        if (value >= 1 && !S->bjA) {
-            if (dalloc(&S->bjA, 6 * S->Npad) || dalloc(&S->bjB, 9 * std::max<int64_t>(S->nfr, 1)) ||
-                dalloc(&S->wz, 3 * S->Npad) || dalloc(&S->bjA32, 6 * S->Npad) ||
-                dalloc(&S->bjB32, 9 * std::max<int64_t>(S->nfr, 1)) || dalloc(&S->wz32, 3 * S->Npad)) {
-                set_error("fg_tune: device allocation for the block-Jacobi preconditioner failed");
-                return FG_ERR_OOM;
-            }
-            S->bj_valid = false;
+        if (value >= 1) {
+            fg_status e = precond_buffers(S, value >= 2);
+            if (e) return e;
         }
         S->k_precond = (int)value;
         drop_graphs(S);

@@ -439,6 +439,109 @@ __global__ __launch_bounds__(WG) void k_mr_pupdate(int64_t n, int nrhs, int lg, 
     }
 }
 
+// ---- block-Jacobi preconditioner of the block CG ("k_precond" >= 1) ----
+// The nodal 3x3 / fault-pair 6x6 inverse blocks of the single-vector solve applied
+// to every column: one thread per (unit, column), a unit being a node off the
+// interface pairs or a fault pair (taken by its lower row), so each thread owns
+// the DOFs of its unit in its column and forms z = M^-1 r from values no other
+// thread writes.  z is stored column-interleaved like r.
+// Start (x != nullptr: x = 0, p = z) or resumption after a residual replacement
+// (x == nullptr: z only), with the per-column partials of r.z and r.r.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_mr_init_bj(int64_t Npad, int nrhs, int lg, BjCols<T> bj, T *__restrict__ x,
+                                                   const T *__restrict__ r, T *__restrict__ p, double *partials,
+                                                   int64_t stride)
+{
+    const int c = elem_col(nrhs);
+    double v[2] = {0, 0};
+    for (int64_t u = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> lg; u < Npad;
+         u += ((int64_t)gridDim.x * blockDim.x) >> lg) {
+        const int ku = bj.fslot[u];
+        const int64_t w = ku >= 0 ? bj.fpart[ku] : -1;
+        if (w >= 0 && w < u) continue;
+        const int nr = w >= 0 ? 2 : 1;
+        const int kw = w >= 0 ? bj.fslot[w] : -1;
+        T rr[6] = {0, 0, 0, 0, 0, 0};
+        for (int m = 0; m < nr; ++m)
+            for (int k = 0; k < 3; ++k) {
+                const int64_t i = (3 * (m == 0 ? u : w) + k) * nrhs + c;
+                rr[3 * m + k] = r[i];
+                v[1] += (double)rr[3 * m + k] * (double)rr[3 * m + k];
+            }
+        v[0] += bjc_unit_z(bj, u, w, ku, kw, rr, nr, nrhs, c);
+        if (x)
+            for (int m = 0; m < nr; ++m)
+                for (int k = 0; k < 3; ++k) {
+                    const int64_t i = (3 * (m == 0 ? u : w) + k) * nrhs + c;
+                    x[i] = 0;
+                    p[i] = bj.z[i];
+                }
+    }
+    block_partials_cols<2>(v, nrhs, partials, stride);
+}
+
+// r -= alpha q and z = M^-1 r per unit, with the per-column partials of r.z and r.r.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_mr_update_bj(int64_t Npad, int nrhs, int lg, BjCols<T> bj, T *__restrict__ r,
+                                                     const T *__restrict__ q, double *partials, int64_t stride,
+                                                     const MrScalars *sc)
+{
+    const int c = elem_col(nrhs);
+    double v[2] = {0, 0};
+    if (sc->upd[c]) {
+        const T al = (T)sc->alpha[c];
+        for (int64_t u = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> lg; u < Npad;
+             u += ((int64_t)gridDim.x * blockDim.x) >> lg) {
+            const int ku = bj.fslot[u];
+            const int64_t w = ku >= 0 ? bj.fpart[ku] : -1;
+            if (w >= 0 && w < u) continue;
+            const int nr = w >= 0 ? 2 : 1;
+            const int kw = w >= 0 ? bj.fslot[w] : -1;
+            T rr[6] = {0, 0, 0, 0, 0, 0};
+            for (int m = 0; m < nr; ++m)
+                for (int k = 0; k < 3; ++k) {
+                    const int64_t i = (3 * (m == 0 ? u : w) + k) * nrhs + c;
+                    const T ri = r[i] - al * q[i];
+                    r[i] = ri;
+                    rr[3 * m + k] = ri;
+                    v[1] += (double)ri * (double)ri;
+                }
+            v[0] += bjc_unit_z(bj, u, w, ku, kw, rr, nr, nrhs, c);
+        }
+    }
+    block_partials_cols<2>(v, nrhs, partials, stride);
+}
+
+// x += alpha p for the columns this iteration advanced, then p = z + beta p for
+// those that go on (z stored by k_mr_update_bj).
+template <typename T>
+__global__ __launch_bounds__(WG) void k_mr_pupdate_bj(int64_t n, int nrhs, const T *__restrict__ z, T *__restrict__ x,
+                                                      T *__restrict__ p, const MrScalars *sc)
+{
+    const int c = elem_col(nrhs);
+    const bool up = sc->upd[c] != 0, cont = !sc->done[c];
+    if (!up) return;
+    const T al = (T)sc->alpha[c], be = (T)sc->beta[c];
+#pragma unroll 4
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const T pi = p[i];
+        x[i] += al * pi;
+        if (cont) p[i] = z[i] + be * pi;
+    }
+}
+
+// p = z + beta p for the columns that go on after a residual replacement.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_mr_resume_p_bj(int64_t n, int nrhs, const T *__restrict__ z, T *__restrict__ p,
+                                                       const MrScalars *sc)
+{
+    const int c = elem_col(nrhs);
+    if (sc->done[c]) return;
+    const T be = (T)sc->beta[c];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = z[i] + be * p[i];
+}
+
 // caller layout (column c of length 3N at c*3N, caller node order) <-> interleaved internal layout
 __global__ void k_mr_in(int64_t N, int64_t Npad, int nrhs, const int32_t *__restrict__ perm,
                         const double *__restrict__ b, double *__restrict__ out)
@@ -570,6 +673,17 @@ inline int log2i(int v)
     return l;
 }
 
+// Block-Jacobi data of the block CG in precision T (the FP64 blocks, or their FP32
+// copies for the FP32 CG of FG_F32 / FG_MIXED), z in the block workspace.
+inline BjCols<double> mr_bj64(fg_system *S) { return BjCols<double>{S->bjA, S->bjB, S->fslot, S->fpart, S->mz}; }
+inline BjCols<float> mr_bj32(fg_system *S) { return BjCols<float>{S->bjA32, S->bjB32, S->fslot, S->fpart, S->mfz}; }
+template <typename T>
+inline BjCols<T> mr_bj(fg_system *S);
+template <>
+inline BjCols<double> mr_bj<double>(fg_system *S) { return mr_bj64(S); }
+template <>
+inline BjCols<float> mr_bj<float>(fg_system *S) { return mr_bj32(S); }
+
 }  // namespace
 
 // The row-group product in the slot-loop form that fg_tune "mr_form" selects.
@@ -656,9 +770,18 @@ static void mr_launch_batch(fg_system *S, int nrhs, const TV *val, const T *dinv
 {
     const int64_t n = 3 * S->Npad * nrhs;
     const int64_t ge = grid_cols(n);
+    const bool bj = S->k_precond != 0;
     for (int it = 0; it < iters; ++it) {
         const int64_t gx = mr_launch_spmm<T, TV>(S, nrhs, val, p, q, 1, st);
         hipLaunchKernelGGL(k_mr_alpha, dim3(nrhs), dim3(FIN), 0, st, S->mpart, nrhs, S->mpart_stride, gx, S->msc);
+        if (bj) {
+            const BjCols<T> m = mr_bj<T>(S);
+            hipLaunchKernelGGL((k_mr_update_bj<T>), dim3(ge), dim3(WG), 0, st, S->Npad, nrhs, log2i(nrhs), m, r, q,
+                               S->mpart, S->mpart_stride, S->msc);
+            hipLaunchKernelGGL(k_mr_beta, dim3(nrhs), dim3(FIN), 0, st, S->mpart, nrhs, S->mpart_stride, ge, S->msc);
+            hipLaunchKernelGGL((k_mr_pupdate_bj<T>), dim3(ge), dim3(WG), 0, st, n, nrhs, (const T *)m.z, x, p, S->msc);
+            continue;
+        }
         hipLaunchKernelGGL((k_mr_update<T>), dim3(ge), dim3(WG), 0, st, n, nrhs, log2i(nrhs), dinv, r, q, S->mpart,
                            S->mpart_stride, S->msc);
         hipLaunchKernelGGL(k_mr_beta, dim3(nrhs), dim3(FIN), 0, st, S->mpart, nrhs, S->mpart_stride, ge, S->msc);
@@ -670,8 +793,8 @@ static void mr_launch_batch(fg_system *S, int nrhs, const TV *val, const T *dinv
 fg_status mr_reserve(fg_system *S, int nrhs)
 {
     if (nrhs <= S->mr_cap) return FG_OK;
-    double **d[] = {&S->mx, &S->mr, &S->mp, &S->mq, &S->mb, &S->mx64, &S->mr64};
-    float **f[] = {&S->mfx, &S->mfr, &S->mfp, &S->mfq};
+    double **d[] = {&S->mx, &S->mr, &S->mp, &S->mq, &S->mb, &S->mx64, &S->mr64, &S->mz};
+    float **f[] = {&S->mfx, &S->mfr, &S->mfp, &S->mfq, &S->mfz};
     for (double **p : d) {
         if (*p) hipFree(*p);
         *p = nullptr;
@@ -717,8 +840,22 @@ static fg_status mr_cg_init(fg_system *S, int nrhs, bool f32, double tol, int64_
     init.nrhs = nrhs;
     hipMemcpyAsync(S->msc, &init, sizeof init, hipMemcpyHostToDevice, st);
     const int64_t ge = grid_cols(n);
-    if (f32) {
-        if (!S->k32_valid) refresh_k32(S, st);
+    if (f32 && !S->k32_valid) refresh_k32(S, st);
+    if (S->k_precond) {
+        if (f32) {
+            bj_ready32(S, st);
+            hipLaunchKernelGGL((k_mr_init_bj<float>), dim3(ge), dim3(WG), 0, st, S->Npad, nrhs, log2i(nrhs),
+                               mr_bj32(S), S->mfx, S->mfr, S->mfp, S->mpart, S->mpart_stride);
+        } else {
+            bj_ready(S, st);
+            hipLaunchKernelGGL((k_mr_init_bj<double>), dim3(ge), dim3(WG), 0, st, S->Npad, nrhs, log2i(nrhs),
+                               mr_bj64(S), S->mx, S->mr, S->mp, S->mpart, S->mpart_stride);
+        }
+        if (S->bj_singular) {
+            set_error("fg_pcg_solve: a diagonal or fault-pair block of K is singular (block Jacobi)");
+            return FG_ERR_BREAKDOWN;
+        }
+    } else if (f32) {
         hipLaunchKernelGGL((k_mr_init<float>), dim3(ge), dim3(WG), 0, st, n, nrhs, log2i(nrhs), S->dinvK32, S->mfx, S->mfr, S->mfp,
                            S->mpart, S->mpart_stride);
     } else {
@@ -750,7 +887,8 @@ static fg_status mr_cg_loop(fg_system *S, int nrhs, bool f32, int check_every, h
             else
                 mr_launch_batch<double, double>(S, nrhs, S->K, S->dinvK, S->mx, S->mr, S->mp, S->mq, batch, st);
         } else {
-            if (!g.exec || g.iters != batch || g.nrhs != nrhs || g.tile != S->mr_tile + 256 * S->mr_form) {
+            const int key = S->mr_tile + 256 * S->mr_form + 65536 * (S->k_precond != 0);
+            if (!g.exec || g.iters != batch || g.nrhs != nrhs || g.tile != key) {
                 if (g.exec) hipGraphExecDestroy(g.exec);
                 g.exec = nullptr;
                 hipGraph_t graph = nullptr;
@@ -771,7 +909,7 @@ static fg_status mr_cg_loop(fg_system *S, int nrhs, bool f32, int check_every, h
                 }
                 g.iters = batch;
                 g.nrhs = nrhs;
-                g.tile = S->mr_tile + 256 * S->mr_form;
+                g.tile = key;
             }
             hipGraphLaunch(g.exec, st);
         }
@@ -876,12 +1014,21 @@ static fg_status mr_reliable(fg_system *S, int nrhs, double tol, int64_t maxit, 
         hipMemcpyAsync(S->mred, scale.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st);
         hipLaunchKernelGGL(k_mr_scale_to_f32, dim3(ge), dim3(WG), 0, st, n, nrhs, S->mred, S->mr64, S->mfr);
         hipMemcpyAsync(next2_d, next2.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st);
-        hipLaunchKernelGGL((k_mr_resume<float>), dim3(ge), dim3(WG), 0, st, n, nrhs, lg, S->dinvK32, S->mfr, S->mpart,
-                           S->mpart_stride);
-        hipLaunchKernelGGL(k_mr_resume_fin, dim3(nrhs), dim3(FIN), 0, st, S->mpart, nrhs, S->mpart_stride, ge, S->msc,
-                           next2_d);
-        hipLaunchKernelGGL((k_mr_resume_p<float>), dim3(ge), dim3(WG), 0, st, n, nrhs, lg, S->dinvK32, S->mfr, S->mfp,
-                           S->msc);
+        if (S->k_precond) {
+            hipLaunchKernelGGL((k_mr_init_bj<float>), dim3(ge), dim3(WG), 0, st, S->Npad, nrhs, lg, mr_bj32(S),
+                               (float *)nullptr, S->mfr, (float *)nullptr, S->mpart, S->mpart_stride);
+            hipLaunchKernelGGL(k_mr_resume_fin, dim3(nrhs), dim3(FIN), 0, st, S->mpart, nrhs, S->mpart_stride, ge,
+                               S->msc, next2_d);
+            hipLaunchKernelGGL((k_mr_resume_p_bj<float>), dim3(ge), dim3(WG), 0, st, n, nrhs, (const float *)S->mfz,
+                               S->mfp, S->msc);
+        } else {
+            hipLaunchKernelGGL((k_mr_resume<float>), dim3(ge), dim3(WG), 0, st, n, nrhs, lg, S->dinvK32, S->mfr,
+                               S->mpart, S->mpart_stride);
+            hipLaunchKernelGGL(k_mr_resume_fin, dim3(nrhs), dim3(FIN), 0, st, S->mpart, nrhs, S->mpart_stride, ge,
+                               S->msc, next2_d);
+            hipLaunchKernelGGL((k_mr_resume_p<float>), dim3(ge), dim3(WG), 0, st, n, nrhs, lg, S->dinvK32, S->mfr,
+                               S->mfp, S->msc);
+        }
         e = check_hip("block cg resume");
         if (e) return e;
     }

@@ -250,10 +250,10 @@ __global__ __launch_bounds__(WG) void k_ch_pupdate(int64_t n, int par, int init,
 
 BjView bj_view(const fg_system *S) { return BjView{S->bjA, S->bjB, S->fslot, S->fpart}; }
 
-// Largest eigenvalue of the symmetric tridiagonal matrix (diag a, off-diagonal b)
-// by bisection on the Sturm count (number of eigenvalues below x from the signs of
-// the LDL^T pivots of T - x I).
-double tridiag_max_eig(const std::vector<double> &a, const std::vector<double> &b)
+// Smallest (lowest = true) or largest eigenvalue of the symmetric tridiagonal
+// matrix (diag a, off-diagonal b) by bisection on the Sturm count (number of
+// eigenvalues below x from the signs of the LDL^T pivots of T - x I).
+double tridiag_extreme_eig(const std::vector<double> &a, const std::vector<double> &b, bool lowest)
 {
     const size_t m = a.size();
     double lo = a[0], hi = a[0];
@@ -273,9 +273,10 @@ double tridiag_max_eig(const std::vector<double> &a, const std::vector<double> &
         }
         return cnt;
     };
-    for (int k = 0; k < 200 && hi - lo > 1e-15 * std::fabs(hi); ++k) {
+    const size_t target = lowest ? 1 : m;  // x is above the eigenvalue once below(x) reaches this count
+    for (int k = 0; k < 200 && hi - lo > 1e-15 * std::max(std::fabs(hi), std::fabs(lo)); ++k) {
         const double mid = 0.5 * (lo + hi);
-        if (below(mid) == m)
+        if (below(mid) >= target)
             hi = mid;
         else
             lo = mid;
@@ -283,9 +284,15 @@ double tridiag_max_eig(const std::vector<double> &a, const std::vector<double> &
     return hi;
 }
 
-// Interval [lo, hi] for the current K from cheb_lanczos block-Jacobi CG steps on
-// the probe vector.  Uses the Chebyshev work vectors and wz.
-fg_status cheb_estimate(fg_system *S, hipStream_t st)
+double tridiag_max_eig(const std::vector<double> &a, const std::vector<double> &b)
+{
+    return tridiag_extreme_eig(a, b, false);
+}
+
+// Lanczos matrix (diagonal a, off-diagonal b) of `steps` block-Jacobi CG steps on
+// the probe vector for the current K (Saad, Sec. 6.7.3).  Uses the Chebyshev work
+// vectors and wz; fewer steps if r.z vanishes first.
+fg_status bj_lanczos(fg_system *S, int steps, std::vector<double> &a, std::vector<double> &b, hipStream_t st)
 {
     const int64_t n = 3 * S->Npad;
     double *r = S->chd, *z = S->chs, *q = S->chq, *p = S->wz;
@@ -301,7 +308,7 @@ fg_status cheb_estimate(fg_system *S, hipStream_t st)
         vdots(S, n, 1, A, B, &rho, st);
     }
     std::vector<double> al, be;
-    for (int j = 0; j < S->cheb_lanczos && rho > 0.0; ++j) {
+    for (int j = 0; j < steps && rho > 0.0; ++j) {
         spmv(S, FG_K, p, q, st);
         double pq = 0;
         {
@@ -331,11 +338,22 @@ fg_status cheb_estimate(fg_system *S, hipStream_t st)
         set_error("fg_pcg_solve: the probe vector of the Chebyshev spectrum estimate vanished (all DOFs fixed?)");
         return FG_ERR_BREAKDOWN;
     }
-    std::vector<double> a(al.size()), b(al.size());
+    a.assign(al.size(), 0.0);
+    b.assign(al.size(), 0.0);
     for (size_t j = 0; j < al.size(); ++j) {
         a[j] = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
         b[j] = std::sqrt(be[j]) / al[j];
     }
+    return FG_OK;
+}
+
+// Interval [lo, hi] for the current K from cheb_lanczos block-Jacobi CG steps on
+// the probe vector.
+fg_status cheb_estimate(fg_system *S, hipStream_t st)
+{
+    std::vector<double> a, b;
+    fg_status e = bj_lanczos(S, S->cheb_lanczos, a, b, st);
+    if (e) return e;
     const double top = tridiag_max_eig(a, b);
     if (!(std::isfinite(top) && top > 0.0)) {
         set_error("fg_pcg_solve: the Chebyshev spectrum estimate is not positive and finite");
@@ -363,6 +381,25 @@ fg_status cheb_interval_ready(fg_system *S, hipStream_t st)
     }
     if (S->cheb_epoch == S->bj_epoch) return FG_OK;
     return cheb_estimate(S, st);
+}
+
+fg_status lanczos_bounds(fg_system *S, int steps, double *lo, double *hi, hipStream_t st)
+{
+    bj_ready(S, st);
+    if (S->bj_singular) {
+        set_error("fg_lanczos_bounds: a diagonal or fault-pair block of K is singular (block Jacobi)");
+        return FG_ERR_BREAKDOWN;
+    }
+    std::vector<double> a, b;
+    fg_status e = bj_lanczos(S, steps, a, b, st);
+    if (e) return e;
+    *lo = tridiag_extreme_eig(a, b, true);
+    *hi = tridiag_extreme_eig(a, b, false);
+    if (!(std::isfinite(*lo) && std::isfinite(*hi) && *hi > 0.0)) {
+        set_error("fg_lanczos_bounds: the Ritz values are not finite and positive");
+        return FG_ERR_NAN;
+    }
+    return FG_OK;
 }
 
 fg_status cheb_cg(fg_system *S, const double *b, double *x, double tol, int64_t maxit, int check_every, int64_t *iters,

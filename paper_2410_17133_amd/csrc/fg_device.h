@@ -96,6 +96,51 @@ __device__ __forceinline__ TV ld_val(const TV *p)
         return *p;
 }
 
+// Block-Jacobi preconditioner of K (nodal 3x3 inverse blocks, 6x6 over the two
+// lips' nodes of a fault pair) on column-interleaved vectors: element (DOF d,
+// column c) at d*nrhs + c (nrhs = 1: one vector).  A unit is a node off the
+// interface pairs or a fault pair, owned by its lower row.
+template <typename T>
+struct BjCols {
+    const T *A;            // [Npad*6] symmetric inverse blocks, xx yy zz yz xz xy
+    const T *B;            // [nfr*9] pair coupling blocks of the inverse, row-major
+    const int32_t *fslot;  // [Npad] index into the fault rows, -1 off the interface
+    const int32_t *fpart;  // [nfr] partner row, -1 if none
+    T *z;                  // [3*Npad*nrhs], column-interleaved like r
+};
+
+template <typename T>
+__device__ __forceinline__ T bjc_sym(const T *d, int r, int c)
+{
+    if (r == c) return d[r];
+    const int s = r + c;  // 1: xy, 2: xz, 3: yz
+    return s == 3 ? d[3] : (s == 2 ? d[4] : d[5]);
+}
+
+// z = M^-1 r of unit (u, w) in column c (r of the unit in rr); returns r.z of the unit.
+template <typename T>
+__device__ __forceinline__ double bjc_unit_z(const BjCols<T> &bj, int64_t u, int64_t w, int ku, int kw,
+                                            const T (&rr)[6], int nr, int nrhs, int c)
+{
+    double rz = 0;
+    for (int m = 0; m < nr; ++m) {
+        const int64_t row = m == 0 ? u : w;
+        const int kk = m == 0 ? ku : kw;
+        const T *a = bj.A + 6 * row;
+        const T *ro = rr + 3 * m, *rp = rr + 3 * (1 - m);
+        for (int k = 0; k < 3; ++k) {
+            T z = bjc_sym(a, k, 0) * ro[0] + bjc_sym(a, k, 1) * ro[1] + bjc_sym(a, k, 2) * ro[2];
+            if (nr == 2) {
+                const T *b = bj.B + 9 * kk + 3 * k;
+                z += b[0] * rp[0] + b[1] * rp[1] + b[2] * rp[2];
+            }
+            bj.z[(3 * row + k) * nrhs + c] = z;
+            rz += (double)ro[k] * (double)z;
+        }
+    }
+    return rz;
+}
+
 struct SpmvArgs {
     int64_t nslices;
     const int64_t *slice_ptr;

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 #include <vector>
 
@@ -270,6 +271,97 @@ __global__ __launch_bounds__(WG) void k_g_resume_p(int64_t nslices, const int32_
     }
 }
 
+// ---- block-Jacobi preconditioner of the grouped K solve ("k_precond" >= 1) ----
+// One thread per row: the lane of a slice's wavefront owns its row's unit (a node,
+// or a fault pair when it is the pair's lower row), so the per-slice partials of a
+// pair land on its lower row's slice; both lips of a pair belong to one group.
+// z = M^-1 r is stored in bj.z (single-vector layout).
+// Start (x != nullptr: x = 0, p = z) or resumption after a residual replacement
+// (x == nullptr: z only), with the per-slice partials of r.z and r.r.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_g_init_bj(int64_t nslices, BjCols<T> bj, T *__restrict__ x, const T *__restrict__ r,
+                                                  T *__restrict__ p, double *part, int64_t stride)
+{
+    const int64_t s = xcd_block() * (WG / SLICE) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (s >= nslices) return;
+    const int64_t u = s * SLICE + lane;
+    const int ku = bj.fslot[u];
+    const int64_t w = ku >= 0 ? bj.fpart[ku] : -1;
+    double v[2] = {0, 0};
+    if (!(w >= 0 && w < u)) {
+        const int nr = w >= 0 ? 2 : 1;
+        const int kw = w >= 0 ? bj.fslot[w] : -1;
+        T rr[6] = {0, 0, 0, 0, 0, 0};
+        for (int m = 0; m < nr; ++m)
+            for (int k = 0; k < 3; ++k) {
+                rr[3 * m + k] = r[3 * (m == 0 ? u : w) + k];
+                v[1] += (double)rr[3 * m + k] * (double)rr[3 * m + k];
+            }
+        v[0] = bjc_unit_z(bj, u, w, ku, kw, rr, nr, 1, 0);
+        if (x)
+            for (int m = 0; m < nr; ++m)
+                for (int k = 0; k < 3; ++k) {
+                    const int64_t i = 3 * (m == 0 ? u : w) + k;
+                    x[i] = 0;
+                    p[i] = bj.z[i];
+                }
+    }
+    slice_partials<2>(v, s, lane, part, stride);
+}
+
+template <typename T>
+__global__ __launch_bounds__(WG) void k_g_update_bj(int64_t nslices, const int32_t *__restrict__ slice_group,
+                                                    BjCols<T> bj, T *__restrict__ x, T *__restrict__ r,
+                                                    const T *__restrict__ p, const T *__restrict__ q, double *part,
+                                                    int64_t stride, const MrScalars *sc)
+{
+    const int64_t s = xcd_block() * (WG / SLICE) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (s >= nslices) return;
+    const int g = slice_group[s];
+    if (sc->done[g]) return;
+    const T al = (T)sc->alpha[g];
+    const int64_t u = s * SLICE + lane;
+    const int ku = bj.fslot[u];
+    const int64_t w = ku >= 0 ? bj.fpart[ku] : -1;
+    double v[2] = {0, 0};
+    if (!(w >= 0 && w < u)) {
+        const int nr = w >= 0 ? 2 : 1;
+        const int kw = w >= 0 ? bj.fslot[w] : -1;
+        T rr[6] = {0, 0, 0, 0, 0, 0};
+        for (int m = 0; m < nr; ++m)
+            for (int k = 0; k < 3; ++k) {
+                const int64_t i = 3 * (m == 0 ? u : w) + k;
+                x[i] += al * p[i];
+                const T ri = r[i] - al * q[i];
+                r[i] = ri;
+                rr[3 * m + k] = ri;
+                v[1] += (double)ri * (double)ri;
+            }
+        v[0] = bjc_unit_z(bj, u, w, ku, kw, rr, nr, 1, 0);
+    }
+    slice_partials<2>(v, s, lane, part, stride);
+}
+
+// p = z + beta p on the groups that go on (after an update or a residual replacement)
+template <typename T>
+__global__ __launch_bounds__(WG) void k_g_pupdate_bj(int64_t nslices, const int32_t *__restrict__ slice_group,
+                                                     const T *__restrict__ z, T *__restrict__ p, const MrScalars *sc)
+{
+    const int64_t s = xcd_block() * (WG / SLICE) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (s >= nslices) return;
+    const int g = slice_group[s];
+    if (sc->done[g]) return;
+    const T be = (T)sc->beta[g];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int64_t e = slice_elem(s, k, lane, 3);
+        p[e] = z[e] + be * p[e];
+    }
+}
+
 // per-group squared norms of a vector (per-slice partials, then k_g_norm_fin)
 template <int BS>
 __global__ __launch_bounds__(WG) void k_g_sq(int64_t nslices, const double *__restrict__ a, double *part, int64_t stride)
@@ -324,6 +416,14 @@ __global__ void k_g_add_f32(int64_t nslices, const int32_t *__restrict__ slice_g
     }
 }
 
+// Block-Jacobi data of the grouped CG in precision T (FP32 copies for the FP32 CG).
+template <typename T>
+inline BjCols<T> g_bj(fg_system *S);
+template <>
+inline BjCols<double> g_bj<double>(fg_system *S) { return BjCols<double>{S->bjA, S->bjB, S->fslot, S->fpart, S->wz}; }
+template <>
+inline BjCols<float> g_bj<float>(fg_system *S) { return BjCols<float>{S->bjA32, S->bjB32, S->fslot, S->fpart, S->wz32}; }
+
 }  // namespace
 
 template <int BS, typename T, typename TV>
@@ -337,6 +437,16 @@ static void g_launch_batch(fg_system *S, const TV *val, const T *dinv, T *x, T *
         LAUNCH_SH((k_g_spmv<BS, T, TV>), gs, WG, (spmv_lds<BS, T>(S)), st, spmv_args(S), S->slice_group, val, p, q,
                   S->gpart, stride, S->gsc);
         LAUNCH(k_g_alpha, G, FIN, st, S->gpart, stride, S->group_slice_ptr, S->gsc);
+        if constexpr (BS == 3 && std::is_same<T, TV>::value) {
+            if (S->k_precond) {
+                const BjCols<T> bj = g_bj<T>(S);
+                LAUNCH((k_g_update_bj<T>), gs, WG, st, S->nslices, S->slice_group, bj, x, r, p, q, S->gpart, stride,
+                       S->gsc);
+                LAUNCH(k_g_beta, G, FIN, st, S->gpart, stride, S->group_slice_ptr, S->gsc);
+                LAUNCH((k_g_pupdate_bj<T>), gs, WG, st, S->nslices, S->slice_group, (const T *)bj.z, p, S->gsc);
+                continue;
+            }
+        }
         LAUNCH((k_g_update<BS, T>), gs, WG, st, S->nslices, S->slice_group, dinv, x, r, p, q, S->gpart, stride, S->gsc);
         LAUNCH(k_g_beta, G, FIN, st, S->gpart, stride, S->group_slice_ptr, S->gsc);
         LAUNCH((k_g_pupdate<BS, T>), gs, WG, st, S->nslices, S->slice_group, dinv, r, p, S->gsc);
@@ -352,7 +462,8 @@ static fg_status g_batch(fg_system *S, const TV *val, const T *dinv, T *x, T *r,
         return check_hip("grouped cg batch");
     }
     GraphCache &g = S->g_graph[slot];
-    if (!g.exec || g.iters != iters) {
+    const int key = S->k_precond != 0;
+    if (!g.exec || g.iters != iters || g.tile != key) {
         if (g.exec) hipGraphExecDestroy(g.exec);
         g.exec = nullptr;
         hipGraph_t graph = nullptr;
@@ -367,6 +478,7 @@ static fg_status g_batch(fg_system *S, const TV *val, const T *dinv, T *x, T *r,
             return check_hip("grouped cg instantiate");
         }
         g.iters = iters;
+        g.tile = key;
     }
     hipGraphLaunch(g.exec, st);
     return check_hip("grouped cg launch");
@@ -389,8 +501,22 @@ static fg_status g_init(fg_system *S, int which, bool f32, double tol, int64_t m
     init.nrhs = S->ngroups;
     hipMemcpyAsync(S->gsc, &init, sizeof init, hipMemcpyHostToDevice, st);
     const int64_t gs = grid_xcd((S->nslices + 3) / 4), stride = S->nslices;
-    if (f32) {
-        if (!S->k32_valid) refresh_k32(S, st);
+    if (f32 && !S->k32_valid) refresh_k32(S, st);
+    if (which == FG_K && S->k_precond) {
+        if (f32) {
+            bj_ready32(S, st);
+            LAUNCH((k_g_init_bj<float>), gs, WG, st, S->nslices, g_bj<float>(S), S->fx, S->fr, S->fp, S->gpart,
+                   stride);
+        } else {
+            bj_ready(S, st);
+            LAUNCH((k_g_init_bj<double>), gs, WG, st, S->nslices, g_bj<double>(S), S->wx, S->wr, S->wp, S->gpart,
+                   stride);
+        }
+        if (S->bj_singular) {
+            set_error("fg_pcg_solve: a diagonal or fault-pair block of K is singular (block Jacobi)");
+            return FG_ERR_BREAKDOWN;
+        }
+    } else if (f32) {
         LAUNCH((k_g_init<3, float>), gs, WG, st, S->nslices, S->dinvK32, S->fx, S->fr, S->fp, S->gpart, stride);
     } else if (which == FG_K) {
         LAUNCH((k_g_init<3, double>), gs, WG, st, S->nslices, S->dinvK, S->wx, S->wr, S->wp, S->gpart, stride);
@@ -531,9 +657,18 @@ fg_status cg_reliable_grouped(fg_system *S, const double *rhs, double *x, double
         }
         group_to_f32(S, scale.data(), r, S->fr, st);
         hipMemcpyAsync(next2_d, next2.data(), G * sizeof(double), hipMemcpyHostToDevice, st);
-        LAUNCH((k_g_resume<3, float>), gs, WG, st, S->nslices, S->dinvK32, S->fr, S->gpart, stride);
-        LAUNCH(k_g_resume_fin, G, FIN, st, S->gpart, stride, S->group_slice_ptr, S->gsc, next2_d);
-        LAUNCH((k_g_resume_p<3, float>), gs, WG, st, S->nslices, S->slice_group, S->dinvK32, S->fr, S->fp, S->gsc);
+        if (S->k_precond) {
+            LAUNCH((k_g_init_bj<float>), gs, WG, st, S->nslices, g_bj<float>(S), (float *)nullptr, S->fr,
+                   (float *)nullptr, S->gpart, stride);
+            LAUNCH(k_g_resume_fin, G, FIN, st, S->gpart, stride, S->group_slice_ptr, S->gsc, next2_d);
+            LAUNCH((k_g_pupdate_bj<float>), gs, WG, st, S->nslices, S->slice_group, (const float *)S->wz32, S->fp,
+                   S->gsc);
+        } else {
+            LAUNCH((k_g_resume<3, float>), gs, WG, st, S->nslices, S->dinvK32, S->fr, S->gpart, stride);
+            LAUNCH(k_g_resume_fin, G, FIN, st, S->gpart, stride, S->group_slice_ptr, S->gsc, next2_d);
+            LAUNCH((k_g_resume_p<3, float>), gs, WG, st, S->nslices, S->slice_group, S->dinvK32, S->fr, S->fp,
+                   S->gsc);
+        }
         e = check_hip("grouped cg resume");
         if (e) return e;
     }

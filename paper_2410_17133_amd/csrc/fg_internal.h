@@ -71,6 +71,7 @@ struct CgScalars {
 
 void set_error(const std::string &msg);
 
+
 struct GraphCache {
     hipGraphExec_t exec = nullptr;
     int iters = 0, nrhs = 0, tile = 0;
@@ -127,6 +128,7 @@ struct fg_system {
     // device mesh (internal numbering)
     double *xyz = nullptr;
     int32_t *tets = nullptr, *tet_orig = nullptr;
+    uint8_t *tslot = nullptr;   // [ne*16] slot of block (a, b) of each grouped tetrahedron in row a
     int32_t *coh = nullptr;
     int32_t *frows = nullptr, *fadj_ptr = nullptr, *fadj = nullptr;
     int32_t *fslot = nullptr, *fpart = nullptr;  // fault-pair map (block-Jacobi preconditioner of K)
@@ -201,6 +203,8 @@ struct fg_system {
     int mr_form = 2;  // fg_tune "mr_form": slot-loop form of the row-group product
     double *mx = nullptr, *mr = nullptr, *mp = nullptr, *mq = nullptr, *mb = nullptr, *mx64 = nullptr, *mr64 = nullptr;
     float *mfx = nullptr, *mfr = nullptr, *mfp = nullptr, *mfq = nullptr;
+    double *mz = nullptr;  // block-Jacobi z of the block solve (FP64 CG)
+    float *mfz = nullptr;  // and of its FP32 CG
     fg::MrScalars *msc = nullptr, *msc_host = nullptr;
     double *mpart = nullptr;
     int64_t mpart_stride = 0;

@@ -10,7 +10,8 @@ void perm_in(const fg_system *S, int bs, const double *nat, double *in, hipStrea
 void perm_out(const fg_system *S, int bs, const double *in, double *nat, hipStream_t st);
 void perm_in_u8(const fg_system *S, int bs, const uint8_t *nat, uint8_t *in, hipStream_t st);
 
-// assembly
+// assembly: the per-tetrahedron slot table (once per mesh), then every assembly
+fg_status tet_slots(fg_system *S, hipStream_t st);
 void assemble_all(fg_system *S, const double *E, const double *logk, hipStream_t st);
 void refresh_k32(fg_system *S, hipStream_t st);
 void stick_tangent(fg_system *S, hipStream_t st);
@@ -22,11 +23,12 @@ void cohesive_rows(fg_system *S, double *fcoh_int, int write_tangent, hipStream_
 
 // adjoint: y = N^T x (slip part of the exact interface tangent, last interface update)
 void apply_NT(fg_system *S, const double *x, double *y, hipStream_t st);
-// dJ/dE and dJ/dln k per tetrahedron (caller order) from the state and the multipliers
+// dJ/dE and dJ/dln k per tetrahedron (caller order) from the state and the multipliers,
+// written, or added to dE / dlogk with accumulate
 void slip_adjoint(fg_system *S, const double *U_int, const double *die_old, const double *t0, const double *a_new,
                   const double *lam_int, double *gU_int, double *a_old, hipStream_t st);
 void sensitivity(fg_system *S, const double *U, const double *P, const double *lu, const double *lp, double *dE,
-                 double *dlogk, const double *logk, hipStream_t st);
+                 double *dlogk, const double *logk, bool accumulate, hipStream_t st);
 
 // coupling products, internal order, masked on both sides
 void apply_Apu(fg_system *S, const double *p, double *out, hipStream_t st);
@@ -56,8 +58,10 @@ fg_status cg_reliable(fg_system *S, const double *b, double *x, double tol, int6
 fg_status cg_run(fg_system *S, int which, int precision, double tol, int64_t maxit, int check_every,
                  int64_t *iters, double *relres, hipStream_t st);
 
-// Block-Jacobi data of the current K (built on first use after K changed).
+// Block-Jacobi data of the current K (built on first use after K changed), and its
+// FP32 copy for FP32 CG.
 void bj_ready(fg_system *S, hipStream_t st);
+void bj_ready32(fg_system *S, hipStream_t st);
 // q = K p with the CG product kernel (reads the stop flag of S->sc; partials of
 // p.q in row 0 of S->partials); returns the number of partials.
 int64_t cg_spmv_k(fg_system *S, const double *p, double *q, hipStream_t st);
@@ -67,6 +71,8 @@ fg_status cheb_cg(fg_system *S, const double *b, double *x, double tol, int64_t 
                   double *relres, hipStream_t st);
 // Spectrum interval of the Chebyshev preconditioner for the current K (estimated if stale).
 fg_status cheb_interval_ready(fg_system *S, hipStream_t st);
+// Smallest and largest Ritz values of `steps` block-Jacobi CG steps on the probe vector.
+fg_status lanczos_bounds(fg_system *S, int steps, double *lo, double *hi, hipStream_t st);
 // out = M^-1 in with the block-Jacobi data (bj_ready first).
 void bj_apply(fg_system *S, const double *in, double *out, hipStream_t st);
 

@@ -104,15 +104,38 @@ __device__ __forceinline__ const fg_params &group_params(const fg_params *gprm, 
 }
 
 // ----------------------------------------------------------------- assembly
+// Slot of block (a, b) of every tetrahedron in row a: tslot[16 t + 4 a + b] = j with
+// col[slice_ptr[s] + 64 j + l] = node b (row a = 64 s + l).  Once per mesh, so that
+// every assembly scatters without searching the rows.
+__global__ void k_tet_slots(int64_t ne, const int32_t *__restrict__ tets, const int64_t *__restrict__ slice_ptr,
+                            const int32_t *__restrict__ col, const uint8_t *__restrict__ rowlen, uint8_t *tslot,
+                            int *bad)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= ne) return;
+    const int32_t *nd = tets + 4 * t;
+    for (int a = 0; a < 4; ++a) {
+        const int64_t row = nd[a];
+        const int64_t base = slice_ptr[row / SLICE] + row % SLICE;
+        const int len = rowlen[row];
+        for (int b = 0; b < 4; ++b) {
+            const int j = find_slot(col + base, len, nd[b]);
+            if (j < 0) *bad = 1;
+            tslot[16 * t + 4 * a + b] = (uint8_t)(j < 0 ? 0 : j);
+        }
+    }
+}
+
 // One colour of tetrahedra: element stiffness V [lam g_a g_b^T + G (g_b g_a^T + (g_a.g_b) I)],
 // storage (V/(20 M))(1 + delta_ab) and conductivity (k/mu) V g_a.g_b, added to the
-// rows of the element's own nodes (no two elements of a colour share a node).
+// rows of the element's own nodes (no two elements of a colour share a node) at the
+// slots of the precomputed table.
 __global__ void k_assemble_tets(int64_t t0, int64_t t1, const int32_t *__restrict__ tets,
                                 const int32_t *__restrict__ orig, const double *__restrict__ xyz,
                                 const double *__restrict__ E, const double *__restrict__ logk,
                                 const fg_params *__restrict__ gprm, const int32_t *__restrict__ sgrp,
-                                const int64_t *__restrict__ slice_ptr, const int32_t *__restrict__ col,
-                                const uint8_t *__restrict__ rowlen, double *K, double *A22, double *Cm, int *bad)
+                                const int64_t *__restrict__ slice_ptr, const uint8_t *__restrict__ tslot, double *K,
+                                double *A22, double *Cm, int *bad)
 {
     int64_t t = t0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= t1) return;
@@ -130,17 +153,14 @@ __global__ void k_assemble_tets(int64_t t0, int64_t t1, const int32_t *__restric
     const double G = Ee / (2.0 * (1.0 + nu));
     const double kmu = exp(logk[e]) / prm.mu;
     const double sm = V / (20.0 * prm.biot_M);
+    uint32_t sl[4];
+    for (int a = 0; a < 4; ++a) sl[a] = ((const uint32_t *)(tslot + 16 * t))[a];
     for (int a = 0; a < 4; ++a) {
         const int64_t row = nd[a];
         const int64_t s = row / SLICE, l = row % SLICE;
         const int64_t base = slice_ptr[s];
-        const int len = rowlen[row];
         for (int b = 0; b < 4; ++b) {
-            int j = find_slot(col + base + l, len, nd[b]);
-            if (j < 0) {
-                *bad = 2;
-                return;
-            }
+            const int j = (int)((sl[a] >> (8 * b)) & 0xffu);
             const double gg = dt3(g[a], g[b]);
             double *kb = K + 9 * base + (int64_t)9 * j * SLICE + l;
             for (int r = 0; r < 3; ++r)
@@ -521,7 +541,7 @@ __global__ void k_sensitivity(int64_t ne, const int32_t *__restrict__ tets, cons
                               const double *__restrict__ U, const double *__restrict__ P,
                               const double *__restrict__ lu, const double *__restrict__ lp,
                               const uint8_t *__restrict__ dir_u, const uint8_t *__restrict__ dir_p, double *dE,
-                              double *dlogk)
+                              double *dlogk, int accumulate)
 {
     int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= ne) return;
@@ -554,8 +574,10 @@ __global__ void k_sensitivity(int64_t ne, const int32_t *__restrict__ tets, cons
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) dd += eu[i][j] * el[i][j];
     const int64_t e = orig[t];
-    dE[e] = -V * (lam1 * tru * trl + 2.0 * G1 * dd);
-    dlogk[e] = -prm.dt * exp(logk[e]) / prm.mu * V * dt3(gl, gp);
+    const double ge = -V * (lam1 * tru * trl + 2.0 * G1 * dd);
+    const double gk = -prm.dt * exp(logk[e]) / prm.mu * V * dt3(gl, gp);
+    dE[e] = accumulate ? dE[e] + ge : ge;
+    dlogk[e] = accumulate ? dlogk[e] + gk : gk;
 }
 
 // ----------------------------------------------------------------- coupling
@@ -1300,7 +1322,7 @@ void assemble_all(fg_system *S, const double *E, const double *logk, hipStream_t
         const int64_t a = P.colour_ptr[c], b = P.colour_ptr[c + 1];
         if (b > a)
             LAUNCH(k_assemble_tets, (b - a + WG - 1) / WG, WG, st, a, b, S->tets, S->tet_orig, S->xyz, E, logk, S->gprm,
-                   S->slice_group, S->slice_ptr, S->col, S->rowlen, S->K, S->A22, S->Cm, bad);
+                   S->slice_group, S->slice_ptr, S->tslot, S->K, S->A22, S->Cm, bad);
     }
     if (S->nf > 0) {
         LAUNCH(k_tri_geo, (S->nf + WG - 1) / WG, WG, st, S->nf, S->coh, S->xyz, S->tri_geo);
@@ -1312,6 +1334,25 @@ void assemble_all(fg_system *S, const double *E, const double *logk, hipStream_t
     if (S->nf > 0)
         LAUNCH(k_save_fault_bulk, (S->nfr * S->fault_w + WG - 1) / WG, WG, st, S->nfr, S->fault_w, S->frows,
                S->slice_ptr, S->rowlen, S->K, S->Kfb);
+}
+
+fg_status tet_slots(fg_system *S, hipStream_t st)
+{
+    int *bad = (int *)S->red_counter + 1;
+    hipMemsetAsync(bad, 0, sizeof(int), st);
+    if (S->ne > 0)
+        LAUNCH(k_tet_slots, (S->ne + WG - 1) / WG, WG, st, S->ne, S->tets, S->slice_ptr, S->col, S->rowlen, S->tslot,
+               bad);
+    int h = 0;
+    hipMemcpyAsync(&h, bad, sizeof(int), hipMemcpyDeviceToHost, st);
+    hipStreamSynchronize(st);
+    fg_status e = check_hip("tetrahedron slot table");
+    if (e) return e;
+    if (h) {
+        set_error("fg_system_create: a tetrahedron's node pair is missing from the planned graph");
+        return FG_ERR_ARG;
+    }
+    return FG_OK;
 }
 
 void stick_tangent(fg_system *S, hipStream_t st)
@@ -1361,10 +1402,10 @@ void apply_NT(fg_system *S, const double *x, double *y, hipStream_t st)
 }
 
 void sensitivity(fg_system *S, const double *U, const double *P, const double *lu, const double *lp, double *dE,
-                 double *dlogk, const double *logk, hipStream_t st)
+                 double *dlogk, const double *logk, bool accumulate, hipStream_t st)
 {
     LAUNCH(k_sensitivity, (S->ne + WG - 1) / WG, WG, st, S->ne, S->tets, S->tet_orig, S->xyz, logk, S->gprm, S->slice_group, U, P, lu,
-           lp, S->dir_u, S->dir_p, dE, dlogk);
+           lp, S->dir_u, S->dir_p, dE, dlogk, accumulate ? 1 : 0);
 }
 
 void apply_Apu(fg_system *S, const double *p, double *out, hipStream_t st)

@@ -21,7 +21,8 @@ FG_F64, FG_F32, FG_MIXED, FG_MIXED_F32VAL = 0, 1, 2, 3
 SYMBOLS = ["fg_last_error", "fg_ctx_create", "fg_ctx_destroy", "fg_system_create", "fg_system_destroy",
            "fg_assemble", "fg_cohesive_update", "fg_pcg_solve", "fg_flow_solve", "fg_step", "fg_spmv",
            "fg_coupling", "fg_residual", "fg_system_sizes", "fg_export", "fg_profile", "fg_profile_read", "fg_tune", "fg_adjoint_solve", "fg_group_stats",
-           "fg_assemble_groups", "fg_slip_adjoint", "fg_cheb_interval", "fg_exact_solve"]
+           "fg_assemble_groups", "fg_slip_adjoint", "fg_cheb_interval", "fg_exact_solve", "fg_adjoint_loop_step",
+           "fg_lanczos_bounds"]
 
 
 class FgError(RuntimeError):
@@ -98,6 +99,9 @@ def lib():
             "fg_slip_adjoint": [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
             "fg_cheb_interval": [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double), vp],
             "fg_exact_solve": [vp, vp, vp, vp, C.POINTER(PcgOpts), C.POINTER(PcgInfo), vp],
+            "fg_lanczos_bounds": [vp, vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_double), vp],
+            "fg_adjoint_loop_step": [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                     C.POINTER(PcgOpts), C.POINTER(PcgOpts), dbl, dbl, i64, C.POINTER(SolveInfo), vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -288,6 +292,26 @@ class System:
             return dE, dk, lu, lp, info
         return dE, dk, info
 
+    def adjoint_loop_step(self, U, P, die_old, t0, logk, dJdU, dJdP, lam_p_next, a, dJ_dE, dJ_dlogk, lam_p,
+                          inner_k=None, inner_p=None, outer_tol=1e-12, defect_tol=1e-12, max_defect_iters=50):
+        """One step of the reverse sweep through a time loop (fg_adjoint_loop_step): a [nq*2]
+        is updated in place (a_n in, a_{n-1} out), dJ_dE and dJ_dlogk are accumulated, and
+        lam_p receives the step's pressure multipliers (lam_p_next of the next call)."""
+        info = SolveInfo()
+        ik = inner_k or opts(tol=1e-13)
+        ip = inner_p or opts(tol=1e-13)
+        nq, N = self.nq, self.N
+        st = lib().fg_adjoint_loop_step(
+            self.ctx._h, self._h, _ptr(U, torch.float64, 3 * N, "U"), _ptr(P, torch.float64, N, "P"),
+            _ptr(die_old, torch.float64, 2 * nq, "die_old"), _ptr(t0, torch.float64, 3 * nq, "t0"),
+            _ptr(logk, torch.float64, self.ne, "log_k"), _ptr(dJdU, torch.float64, 3 * N, "dJdU"),
+            _ptr(dJdP, torch.float64, N, "dJdP"), _ptr(lam_p_next, torch.float64, N, "lam_p_next"),
+            _ptr(a, torch.float64, 2 * nq, "a"), _ptr(dJ_dE, torch.float64, self.ne, "dJ_dE"),
+            _ptr(dJ_dlogk, torch.float64, self.ne, "dJ_dlogk"), None, _ptr(lam_p, torch.float64, N, "lam_p"),
+            C.byref(ik), C.byref(ip), outer_tol, defect_tol, max_defect_iters, C.byref(info), _stream())
+        _check(st)
+        return info
+
     def slip_adjoint(self, U, die_old, t0, a_new, lam_u=None):
         """(gU [3N], a_old [nq*2]) of the slip state carried between steps (fg_slip_adjoint)."""
         nq = self.nq
@@ -298,6 +322,13 @@ class System:
                                      None if lam_u is None else _ptr(lam_u, torch.float64, 3 * self.N, "lam_u"),
                                      _ptr(gU, torch.float64), _ptr(a_old, torch.float64), _stream()), False)
         return gU, a_old
+
+    def lanczos_bounds(self, steps):
+        """(smallest, largest) Ritz values of `steps` block-Jacobi CG steps on the probe
+        vector: estimates of the extreme eigenvalues of M^-1 K (fg_lanczos_bounds)."""
+        lo, hi = C.c_double(), C.c_double()
+        _check(lib().fg_lanczos_bounds(self.ctx._h, self._h, int(steps), C.byref(lo), C.byref(hi), _stream()), False)
+        return lo.value, hi.value
 
     def cheb_interval(self):
         """(lo, hi) of the Chebyshev preconditioner of the current K (fg_cheb_interval)."""

@@ -35,32 +35,27 @@ def gradient(S, ck, t0, logk, grad_y, inner_k=None, inner_p=None, outer_tol=1e-1
              max_defect_iters=1000):
     """dJ/dE and dJ/dln k (per tetrahedron) of J = sum_n j_n(U_n, P_n) over the
     checkpointed loop.  grad_y(n, U, P) -> (dj/dU, dj/dP) as CUDA float64 tensors
-    (n counted from 0).  Returns (dJ_dE, dJ_dlogk, per-step adjoint infos)."""
+    (n counted from 0).  Returns (dJ_dE, dJ_dlogk, per-step adjoint infos).
+    Every step of the sweep is one fg_adjoint_loop_step call; this function only
+    allocates its buffers and passes them along."""
     import torch
-    dt = S.params.dt
-    a = torch.zeros(2 * S.nq, dtype=torch.float64, device=t0.device)
+    dev = t0.device
+    f64 = dict(dtype=torch.float64, device=dev)
+    a = torch.zeros(2 * S.nq, **f64)
+    dE, dk = torch.zeros(S.ne, **f64), torch.zeros(S.ne, **f64)
+    lam = [torch.zeros(S.N, **f64), torch.zeros(S.N, **f64)]
     lp_next = None
-    dE_t = dk_t = None
     infos = []
     for n in range(len(ck) - 1, -1, -1):
         U, P, die_prev, _ = ck[n]
         gu, gp = grad_y(n, U, P)
-        gu, gp = gu.clone(), gp.clone()
-        if lp_next is not None:
-            gu += S.coupling(lp_next)                                              # A_pu lam_{n+1,p}
-            gp += S.spmv(fg.FG_A22, lp_next) - dt * S.spmv(fg.FG_C, lp_next)         # S lam_{n+1,p}
-        if S.nq:
-            gu += S.slip_adjoint(U, die_prev, t0, a)[0]
-        dE, dk, lu, lp, info = S.adjoint(U, P, die_prev, t0, logk, gu, gp, inner_k=inner_k, inner_p=inner_p,
-                                         outer_tol=outer_tol, defect_tol=defect_tol,
-                                         max_defect_iters=max_defect_iters, multipliers=True)
+        lp = lam[n & 1]
+        info = S.adjoint_loop_step(U, P, die_prev, t0, logk, gu.contiguous(), gp.contiguous(), lp_next, a, dE, dk,
+                                   lp, inner_k=inner_k, inner_p=inner_p, outer_tol=outer_tol, defect_tol=defect_tol,
+                                   max_defect_iters=max_defect_iters)
         if info.status != fg.FG_OK:
             raise fg.FgError(info.status, f"the adjoint of step {n} did not converge within {max_defect_iters} "
                                           "defect iterations")
         infos.append(info)
-        dE_t = dE if dE_t is None else dE_t + dE
-        dk_t = dk if dk_t is None else dk_t + dk
-        if S.nq:
-            a = S.slip_adjoint(U, die_prev, t0, a, lu)[1]
         lp_next = lp
-    return dE_t, dk_t, infos[::-1]
+    return dE, dk, infos[::-1]

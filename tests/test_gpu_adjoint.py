@@ -51,29 +51,48 @@ def objective_np(inst, U, uplift):
     return np.sum(slip * slip) + np.sum(U3[uplift, 2] ** 2), g.reshape(-1)
 
 
+ADJOINT_CASES = {
+    "small_slip": small_slip_instance,
+    "config1": lambda: I.make_instance(I.config(1)),
+    # heterogeneous (seeded ln k and E per tetrahedron) 12^3 cube with a fault dipping 60 degrees
+    "dip60_hetero12": lambda: I.make_instance(I.cube_config(12, dip_deg=60, heterogeneous=True)),
+}
+_oracle_adjoint = {}
+
+
+def oracle_adjoint(case):
+    """The oracle's converged step and adjoint for a case (computed once per case)."""
+    from oracle import oracle as O
+    if case not in _oracle_adjoint:
+        inst = ADJOINT_CASES[case]()
+        P = O.Problem(inst)
+        U, Pp, die = np.zeros(3 * P.N), np.zeros(P.N), np.zeros((P.nq, 2))
+        trac, flag, info, st = P.step(U, Pp, die, **TIGHT)
+        assert st == 0 and (flag == 1).sum() > 0
+        uplift = I.uplift_nodes(inst, 8)
+        J, gu = objective_np(inst, U, uplift)
+        gp = np.random.default_rng(1).standard_normal(P.N) * 1e-20   # exercise the pressure right-hand side too
+        P.cohesive(U, np.zeros((P.nq, 2)))
+        lu_o, lp_o, st, stats = P.adjoint(gu, gp)
+        assert st == 0
+        dE_o, dk_o = P.sensitivity(U, Pp, lu_o, lp_o)
+        print(f"[oracle] {case}: {int((flag == 1).sum())} slip points, {stats[0]:.0f} defect iterations", flush=True)
+        _oracle_adjoint[case] = (inst, U, Pp, gu, gp, lu_o, lp_o, dE_o, dk_o, stats)
+    return _oracle_adjoint[case]
+
+
 @pytest.mark.parametrize("case,loose,exact", [("small_slip", False, False), ("small_slip", True, False),
                                               ("config1", False, False), ("config1", True, False),
-                                              ("small_slip", True, True), ("config1", True, True)])
+                                              ("small_slip", True, True), ("config1", True, True),
+                                              ("dip60_hetero12", True, False), ("dip60_hetero12", True, True)])
 def test_adjoint_matches_oracle_at_the_same_state(case, loose, exact):
     """loose: every defect correction solved to outer 0.05 / inner 1e-3 only; the
     refinement on the true residual must still reach the same multipliers.  exact:
     fg_tune exact_tangent 1, the corrections solve with K_t + N^T (BiCGStab) and need
     no more of them than the symmetric corrections."""
-    from oracle import oracle as O
     from paper_2410_17133_amd import fg
-    inst = small_slip_instance() if case == "small_slip" else I.make_instance(I.config(1))
     print(f"[case] adjoint parity {case}", flush=True)
-    P = O.Problem(inst)
-    U, Pp, die = np.zeros(3 * P.N), np.zeros(P.N), np.zeros((P.nq, 2))
-    trac, flag, info, st = P.step(U, Pp, die, **TIGHT)
-    assert st == 0 and (flag == 1).sum() > 0
-    uplift = I.uplift_nodes(inst, 8)
-    J, gu = objective_np(inst, U, uplift)
-    gp = np.random.default_rng(1).standard_normal(P.N) * 1e-20   # exercise the pressure right-hand side too
-    P.cohesive(U, np.zeros((P.nq, 2)))
-    lu_o, lp_o, st, stats = P.adjoint(gu, gp)
-    assert st == 0
-    dE_o, dk_o = P.sensitivity(U, Pp, lu_o, lp_o)
+    inst, U, Pp, gu, gp, lu_o, lp_o, dE_o, dk_o, stats = oracle_adjoint(case)
     ctx = fg.Context(0)
     S = fg.System.from_instance(ctx, inst)
     S.assemble(inst.params, inst.E, inst.logk)

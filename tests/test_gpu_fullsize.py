@@ -97,6 +97,56 @@ def test_mixed_precision_solve_full_size(full):
     assert relerr(xm, x64) < 1e-6
 
 
+def test_converged_k_solve_full_size(full):
+    """The benchmark's K system solved to the FP64 stagnation floor on both sides:
+    the stick tangent of the initial state and the right-hand side of the first
+    K solve of the partitioned iteration, A_pu A22^-1 (dt f_p), formed by the
+    oracle.  The GPU runs the benchmark's point-Jacobi CG (graph-replayed
+    batches) and its block-Jacobi CG; the oracle its block-Jacobi CG.  Each
+    solution's residual is measured with the oracle's FP64 product, and the
+    solutions are compared in relative L2.  The condition number of the
+    block-Jacobi preconditioned K is estimated from the Lanczos matrices of both
+    sides' CG coefficients (300 steps on the same probe vector) and printed: the
+    forward-error bound kappa 2^-53 stays far below the 1e-9 asked of the
+    solutions."""
+    S, P, O, fg, inst = full["S"], full["P"], full["O"], full["fg"], full["inst"]
+    n = full["n"]
+    U0, die0 = np.zeros(3 * P.N), np.zeros((P.nq, 2))
+    P.cohesive(U0, die0)
+    S.cohesive_update(dev(U0), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)))   # the same stick tangent
+    d, st, _, _ = P.pcg(O.A22, inst.params.dt * inst.source, tol=1e-13)
+    assert st == 0
+    b = P.apply_Apu(d)
+    nb = np.linalg.norm(b)
+    true_res = lambda x: np.linalg.norm(b - P.spmv(O.K_TANGENT, x)) / nb
+    xo, st, ito, rro = P.pcg_block(b, tol=1e-13, maxit=40000)
+    print(f"[converged {n}^3] oracle block Jacobi: {ito} iterations, relres {rro:.2e}, true {true_res(xo):.2e}",
+          flush=True)
+    assert st in (0, 1) and true_res(xo) <= 1e-10
+    x, info = S.pcg_solve(fg.FG_K, dev(b), tol=1e-13, max_iter=60000, check_every=64)
+    x = host(x)
+    print(f"[converged {n}^3] gpu point Jacobi: {info.iters} iterations, relres {info.relres:.2e}, "
+          f"true {true_res(x):.2e}, vs oracle {relerr(x, xo):.2e}", flush=True)
+    S.tune("k_precond", 1)
+    try:
+        xb, ib = S.pcg_solve(fg.FG_K, dev(b), tol=1e-13, max_iter=40000, check_every=64)
+        lo, hi = S.lanczos_bounds(300)
+    finally:
+        S.tune("k_precond", 0)
+    xb = host(xb)
+    print(f"[converged {n}^3] gpu block Jacobi: {ib.iters} iterations, relres {ib.relres:.2e}, "
+          f"true {true_res(xb):.2e}, vs oracle {relerr(xb, xo):.2e}", flush=True)
+    ritz = O.ritz_values(*P.bj_lanczos(300))
+    kappa_gpu, kappa_or = hi / lo, ritz[-1] / ritz[0]
+    print(f"[converged {n}^3] kappa(M^-1 K) from 300 Lanczos steps: gpu {kappa_gpu:.3e} "
+          f"[{lo:.4e}, {hi:.4e}], oracle {kappa_or:.3e} [{ritz[0]:.4e}, {ritz[-1]:.4e}]", flush=True)
+    assert abs(hi - ritz[-1]) <= 1e-6 * ritz[-1] and abs(lo - ritz[0]) <= 5e-2 * ritz[0]
+    assert max(kappa_gpu, kappa_or) * 2.0 ** -53 <= 1e-10
+    assert info.status == 0 and ib.status == 0
+    assert true_res(x) <= 1e-10 and true_res(xb) <= 1e-10
+    assert relerr(x, xo) <= 1e-9 and relerr(xb, xo) <= 1e-9
+
+
 def test_pcg_iterates_full_size(full):
     """50 iterations of the K and A22 PCG from the same right-hand side: the GPU
     iterate (graph-replayed batches, default knobs) equals the oracle's."""
