@@ -201,6 +201,22 @@ fg_status fg_cohesive_update(fg_ctx *ctx, fg_system *sys, const double *U, const
 fg_status fg_pcg_solve(fg_ctx *ctx, fg_system *sys, int which, int nrhs, const double *b, double *x,
                        const fg_pcg_opts *opts, fg_pcg_info *info_h, void *stream);
 
+/* fg_pcg_solve for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  One
+ * right-hand side, FG_K or FG_A22, FP64, point Jacobi (the paper's; "k_precond"
+ * and "exact_tangent" are ignored), kernels launched one by one.  The CG's work
+ * memory (device scalars, reduction partials and the x, r, p, q vectors) comes
+ * from one fixed 64 MiB array per GPU that the library holds until the process
+ * ends; the call allocates nothing and must not be given a solve that needs more
+ * (4 vectors of 3N (FG_K) or N (FG_A22) doubles plus the partials: about 2.09 M
+ * unknowns), which returns FG_ERR_ARG.  Every call on one GPU shares that array:
+ * calls that overlap on one GPU (other threads or streams) race and give wrong
+ * results.  Results equal fg_pcg_solve's with the default preconditioner.
+ * Arguments, returns and info as fg_pcg_solve (nrhs = 1); opts->precision must
+ * be FG_F64 (opts may be NULL: tol 1e-10).  Synchronises the stream. */
+fg_status fg_pcg_solve_noalloc(fg_ctx *ctx, fg_system *sys, int which, const double *b, double *x,
+                               const fg_pcg_opts *opts, fg_pcg_info *info_h, void *stream);
+
 /* One partitioned solve of the Newton system (eq. linear_system,
  * eq. prevost_system, eq. schur_system):
  *   [ K      -A_pu ] [du]   [b_u]

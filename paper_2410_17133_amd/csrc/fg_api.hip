@@ -382,6 +382,8 @@ fg_status fg_ctx_create(fg_ctx **ctx, int device)
         return FG_ERR_ARG;
     }
     Guard g(device);
+    fg_status e = noalloc_init(device);
+    if (e) return e;
     fg_ctx *c = new fg_ctx;
     c->device = device;
     hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device);

@@ -116,4 +116,8 @@ void group_to_f32(fg_system *S, const double *scale, const double *x, float *y, 
 void group_add_f32(fg_system *S, const double *scale, const float *x, double *y, hipStream_t st);
 void drop_group_graphs(fg_system *S);
 
+// Device address of the allocation-free solve's scratch on `device` (fg_noalloc.hip);
+// called once per device by fg_ctx_create.
+fg_status noalloc_init(int device);
+
 }  // namespace fg

@@ -21,7 +21,7 @@ FG_F64, FG_F32, FG_MIXED, FG_MIXED_F32VAL = 0, 1, 2, 3
 SYMBOLS = ["fg_last_error", "fg_ctx_create", "fg_ctx_destroy", "fg_system_create", "fg_system_destroy",
            "fg_assemble", "fg_cohesive_update", "fg_pcg_solve", "fg_flow_solve", "fg_step", "fg_spmv",
            "fg_coupling", "fg_residual", "fg_system_sizes", "fg_export", "fg_profile", "fg_profile_read", "fg_tune", "fg_adjoint_solve", "fg_group_stats",
-           "fg_assemble_groups", "fg_slip_adjoint", "fg_cheb_interval", "fg_exact_solve", "fg_adjoint_loop_step",
+           "fg_assemble_groups", "fg_slip_adjoint", "fg_cheb_interval", "fg_exact_solve", "fg_adjoint_loop_step", "fg_pcg_solve_noalloc",
            "fg_lanczos_bounds"]
 
 
@@ -100,6 +100,7 @@ def lib():
             "fg_cheb_interval": [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double), vp],
             "fg_exact_solve": [vp, vp, vp, vp, C.POINTER(PcgOpts), C.POINTER(PcgInfo), vp],
             "fg_lanczos_bounds": [vp, vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_double), vp],
+            "fg_pcg_solve_noalloc": [vp, vp, i32, vp, vp, C.POINTER(PcgOpts), C.POINTER(PcgInfo), vp],
             "fg_adjoint_loop_step": [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                      C.POINTER(PcgOpts), C.POINTER(PcgOpts), dbl, dbl, i64, C.POINTER(SolveInfo), vp],
         }
@@ -227,6 +228,16 @@ class System:
                                 _ptr(x, torch.float64), C.byref(opts(**kw)), C.byref(info), _stream())
         _check(st)
         return x, info
+
+    def pcg_solve_noalloc(self, which, b, x, **kw):
+        """fg_pcg_solve_noalloc: one right-hand side, the solution written into the caller's x
+        (the call allocates no device memory; x must be a CUDA float64 tensor).  Returns info."""
+        n = (3 if which == FG_K else 1) * self.N
+        info = PcgInfo()
+        st = lib().fg_pcg_solve_noalloc(self.ctx._h, self._h, which, _ptr(b, torch.float64, n, "b"),
+                                        _ptr(x, torch.float64, n, "x"), C.byref(opts(**kw)), C.byref(info), _stream())
+        _check(st)
+        return info
 
     def exact_solve(self, b, **kw):
         """(K_t + N) x = b by BiCGStab (fg_exact_solve): the exact interface tangent of the last
