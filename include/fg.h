@@ -369,6 +369,14 @@ fg_status fg_cheb_interval(fg_ctx *ctx, fg_system *sys, double *lo, double *hi, 
  * fg_assemble), FG_ERR_BREAKDOWN (singular block or K not SPD), FG_ERR_OOM. */
 fg_status fg_lanczos_bounds(fg_ctx *ctx, fg_system *sys, int steps, double *lo, double *hi, void *stream);
 
+/* Sizes of the smoothed-aggregation hierarchy of "k_precond" 3 for the current K
+ * (built now if needed): *nlev levels, nodes[l] (host, 6 entries) nodes of level
+ * l (level 0: the mesh nodes, 3 DOFs each; below: aggregates, 6 DOFs each; unused
+ * entries 0).  Synchronises the stream.  Errors: FG_ERR_ARG, FG_ERR_STATE (before
+ * fg_assemble, or k_precond is not 3), FG_ERR_BREAKDOWN (singular block or
+ * coarsest matrix not SPD), FG_ERR_OOM. */
+fg_status fg_amg_levels(fg_ctx *ctx, fg_system *sys, int *nlev, int64_t *nodes, void *stream);
+
 /* Products on the assembled system, caller order: y = A x for which in
  * {FG_K, FG_A22, FG_KBULK, FG_C, FG_K_EXACT} (FG_K_EXACT: see fg_exact_solve). */
 fg_status fg_spmv(fg_ctx *ctx, fg_system *sys, int which, const double *x, double *y, void *stream);
@@ -432,6 +440,18 @@ fg_status fg_group_stats(const fg_system *sys, int64_t *iters_h, double *relres_
  *               batched systems apply the block-Jacobi stage (1 and 2 alike) to
  *               every column / group, in FP64 and in the FP32 CG of FG_F32 /
  *               FG_MIXED; FG_MIXED_F32VAL solves keep point Jacobi.
+ *               3: the FP64 single-right-hand-side K solves use CG preconditioned
+ *               by a smoothed-aggregation AMG V-cycle (Vanek, Mandel and Brezina,
+ *               Computing 56, 1996): aggregates of the node graph (the two lips of
+ *               a fault pair together), the six rigid-body modes as near-null
+ *               space, prolongator (I - w D^-1 A) P_tent with w = 4/(3 rho), rho
+ *               the Gershgorin bound of D^-1 A, Galerkin coarse operators down to
+ *               "amg_coarse" nodes (at most 6 levels, the last inverted), and
+ *               degree-2 Chebyshev smoothing over block Jacobi (level 0: the
+ *               blocks of stage 1 on [hi/30, hi] with hi as for stage 2; below:
+ *               6x6 blocks on [rho/30, rho]).  The patterns are built on the host
+ *               once per mesh, the values on the GPU after every change of K;
+ *               other solves behave as with 1.
  *   "exact_tangent": 1 makes the FP64 K solves inside fg_flow_solve and fg_step
  *               solve the exact tangent K_t + N by BiCGStab (as fg_exact_solve),
  *               so that Newton uses the exact Jacobian of the interface force;
@@ -447,6 +467,8 @@ fg_status fg_group_stats(const fg_system *sys, int64_t *iters_h, double *relres_
  *               1 is block Jacobi scaled by 1/theta: same iterates).
  *   "cheb_ratio": hi / lo of the interval, 2 to 1000000 (default 300).
  *   "cheb_lanczos": CG steps of the spectrum estimate, 5 to 500 (default 40).
+ *   "amg_coarse": "k_precond" 3 coarsens down to at most this many nodes, 1 to
+ *               1000 (default 64).
  *   "spmv_unroll": slots per unrolled step of the CG product: 1, 2 (default),
  *               3, 4 or 6.
  *   "mixed_update": FG_MIXED: factor by which the FP32 residual (of the

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfg.so")
-SOURCES = ["fg_plan.cpp", "fg_kernels.hip", "fg_block.hip", "fg_group.hip", "fg_trajectory.hip", "fg_cheb.hip", "fg_exact.hip", "fg_noalloc.hip", "fg_api.hip"]
+SOURCES = ["fg_plan.cpp", "fg_kernels.hip", "fg_block.hip", "fg_group.hip", "fg_trajectory.hip", "fg_cheb.hip", "fg_exact.hip", "fg_amg.hip", "fg_noalloc.hip", "fg_api.hip"]
 ARCH = os.environ.get("FG_OFFLOAD_ARCH", "gfx950")
 
 HIP_FLAGS = [

@@ -1,0 +1,1028 @@
+// Smoothed-aggregation AMG preconditioner of K (fg_tune "k_precond" 3): the third
+// stage of the stronger preconditioner, after block Jacobi and Chebyshev.
+//
+// Smoothed aggregation (Vanek, Mandel and Brezina, Computing 56, 1996) with the six
+// rigid-body modes as near-null space:
+//  - aggregates: three passes over the node graph of each level in increasing node
+//    order (level 0 in the caller's numbering; the two lips of a fault pair count as
+//    one node): (1) a node whose neighbours are all free starts an aggregate with
+//    them; (2) a free node joins the aggregate of its lowest-numbered neighbour
+//    aggregated in pass 1; (3) a node still free starts one with its free neighbours;
+//  - tentative prolongator: per aggregate the near-null-space rows of its nodes
+//    (level 0: translations and rotations about the aggregate's centroid, zero on
+//    held DOFs; below: the R factor of the node's aggregate), orthonormalised by
+//    modified Gram-Schmidt, a vanishing column dropped;
+//  - P = (I - w D^-1 A) Ptent with D the block diagonal, w = 4 / (3 rho), rho the
+//    Gershgorin bound of D^-1 A; Galerkin A_c = P^T A P; a coarse DOF with an empty
+//    row gets a unit diagonal; at most 6 levels, the last solved by its dense inverse;
+//  - V-cycle: pre- and post-smoothing by the degree-2 Chebyshev polynomial over
+//    block Jacobi (level 0: the nodal / fault-pair blocks of "k_precond" 1 on
+//    [hi/30, hi], hi the Chebyshev preconditioner's upper end; below: 6x6 diagonal
+//    blocks on [rho/30, rho]).
+// The patterns (aggregates, P, W = A P, A_c) are symbolic and built on the host once
+// per mesh; every numeric step (diagonal blocks, Gershgorin bounds, P, W, A_c, the
+// cycle) runs on the GPU when K changes.  Only the coarsest matrix (a few hundred
+// unknowns) is inverted on the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <initializer_list>
+#include <vector>
+
+#include "fg_device.h"
+#include "fg_kernels.h"
+
+namespace fg {
+
+constexpr int AMG_MAXLEV = 6;
+
+struct AmgLevel {
+    int bs = 3;
+    int64_t nn = 0, nc = 0;            // nodes (level 0: Npad internal rows), aggregates
+    int64_t nnzb = 0, npz = 0, nwz = 0, nrz = 0;
+    int64_t *arow = nullptr;           // block CSR of A (level 0: K's slots, internal order)
+    int32_t *acol = nullptr;
+    double *aval = nullptr;            // [nnzb bs bs]
+    int32_t *agg = nullptr;            // [nn] aggregate of each node (-1: padding row)
+    double *q = nullptr;               // [nn bs 6] tentative prolongator rows
+    int64_t *prow = nullptr;           // P: per node, sorted aggregates
+    int32_t *pcol = nullptr;
+    double *pval = nullptr;            // [npz bs 6]
+    int64_t *wrow = nullptr;           // W = A P
+    int32_t *wcol = nullptr;
+    double *wval = nullptr;            // [nwz bs 6]
+    int64_t *rrow = nullptr;           // P^T: per aggregate, (node, P entry) in increasing node order
+    int32_t *rnode = nullptr;
+    int64_t *rent = nullptr;
+    double *dinv = nullptr;            // [nn bs bs]
+    double rho = 0;
+    // cycle vectors of the level: x, b (coarse levels), r residual, e post-smoothing
+    // correction, and the smoother's scratch d, s, w, t
+    double *x = nullptr, *b = nullptr, *r = nullptr, *e = nullptr, *t = nullptr, *d = nullptr, *s = nullptr,
+           *w = nullptr;
+};
+
+struct AmgData {
+    int nlev = 0;
+    AmgLevel L[AMG_MAXLEV];
+    int64_t nco = 0;                   // coarsest unknowns
+    double *cinv = nullptr;            // [nco nco] inverse of the coarsest matrix
+    double *part = nullptr;            // reduction partials
+    // the PCG's r, z, p, q (3 Npad each): its own, since callers of the K solve pass
+    // the system's shared work vectors as right-hand side and solution
+    double *cr = nullptr, *cz = nullptr, *cp = nullptr, *cq = nullptr;
+    int64_t epoch = -1;                // bj_epoch of the numeric set-up
+    int64_t coarse_nodes = 64;
+};
+
+namespace {
+
+// ------------------------------------------------------------ host symbolic set-up
+typedef std::vector<std::vector<int32_t>> Lists;
+
+// The three aggregation passes (see the file comment); twin[i] the other lip of a
+// fault pair or -1 (level 0 only).  Returns the number of aggregates.
+int64_t aggregate(int64_t nn, const Lists &adj, const std::vector<int32_t> *twin, std::vector<int32_t> &agg)
+{
+    agg.assign(nn, -1);
+    auto members = [&](int64_t i, int32_t (&mem)[2]) {
+        mem[0] = (int32_t)i;
+        mem[1] = -1;
+        int nm = 1;
+        if (twin && (*twin)[i] >= 0) mem[nm++] = (*twin)[i];
+        return nm;
+    };
+    auto led_by_other = [&](int64_t i) { return twin && (*twin)[i] >= 0 && (*twin)[i] < i; };
+    int64_t na = 0;
+    for (int64_t i = 0; i < nn; ++i) {
+        if (led_by_other(i) || agg[i] >= 0) continue;
+        int32_t mem[2];
+        const int nm = members(i, mem);
+        bool free_all = true;
+        for (int u = 0; u < nm && free_all; ++u)
+            for (int32_t j : adj[mem[u]])
+                if (agg[j] >= 0) {
+                    free_all = false;
+                    break;
+                }
+        if (!free_all) continue;
+        for (int u = 0; u < nm; ++u) {
+            agg[mem[u]] = (int32_t)na;
+            for (int32_t j : adj[mem[u]]) {
+                agg[j] = (int32_t)na;
+                if (twin && (*twin)[j] >= 0) agg[(*twin)[j]] = (int32_t)na;
+            }
+        }
+        ++na;
+    }
+    const std::vector<int32_t> agg1 = agg;
+    for (int64_t i = 0; i < nn; ++i) {
+        if (led_by_other(i) || agg[i] >= 0) continue;
+        int32_t mem[2];
+        const int nm = members(i, mem);
+        int32_t best = -1, bestj = INT32_MAX;
+        for (int u = 0; u < nm; ++u)
+            for (int32_t j : adj[mem[u]])
+                if (agg1[j] >= 0 && j < bestj) {
+                    bestj = j;
+                    best = agg1[j];
+                }
+        if (best >= 0)
+            for (int u = 0; u < nm; ++u) agg[mem[u]] = best;
+    }
+    for (int64_t i = 0; i < nn; ++i) {
+        if (led_by_other(i) || agg[i] >= 0) continue;
+        int32_t mem[2];
+        const int nm = members(i, mem);
+        for (int u = 0; u < nm; ++u) {
+            agg[mem[u]] = (int32_t)na;
+            for (int32_t j : adj[mem[u]])
+                if (agg[j] < 0) {
+                    agg[j] = (int32_t)na;
+                    if (twin && (*twin)[j] >= 0) agg[(*twin)[j]] = (int32_t)na;
+                }
+        }
+        ++na;
+    }
+    return na;
+}
+
+// Tentative prolongator rows Q [nn bs 6] and the coarse near-null space Bc
+// [na 6 6] from the near-null-space rows B [nn bs 6] (modified Gram-Schmidt per
+// aggregate over its nodes in increasing order).
+void tentative(int bs, int64_t nn, int64_t na, const std::vector<int32_t> &agg, const std::vector<double> &B,
+               std::vector<double> &Q, std::vector<double> &Bc)
+{
+    std::vector<std::vector<int32_t>> mem(na);
+    for (int64_t i = 0; i < nn; ++i) mem[agg[i]].push_back((int32_t)i);
+    Q.assign(nn * bs * 6, 0.0);
+    Bc.assign(na * 36, 0.0);
+    for (int64_t a = 0; a < na; ++a) {
+        const int64_t rows = (int64_t)mem[a].size() * bs;
+        std::vector<double> M(rows * 6);
+        for (size_t t = 0; t < mem[a].size(); ++t)
+            for (int r = 0; r < bs; ++r)
+                for (int k = 0; k < 6; ++k) M[(t * bs + r) * 6 + k] = B[((int64_t)mem[a][t] * bs + r) * 6 + k];
+        double R[36] = {0};
+        for (int k = 0; k < 6; ++k) {
+            double n0 = 0;
+            for (int64_t q = 0; q < rows; ++q) n0 += M[q * 6 + k] * M[q * 6 + k];
+            n0 = std::sqrt(n0);
+            for (int j = 0; j < k; ++j) {
+                double d = 0;
+                for (int64_t q = 0; q < rows; ++q) d += M[q * 6 + j] * M[q * 6 + k];
+                R[6 * j + k] = d;
+                for (int64_t q = 0; q < rows; ++q) M[q * 6 + k] -= d * M[q * 6 + j];
+            }
+            double nk = 0;
+            for (int64_t q = 0; q < rows; ++q) nk += M[q * 6 + k] * M[q * 6 + k];
+            nk = std::sqrt(nk);
+            if (!(nk > 1e-10 * n0) || nk == 0.0) {
+                for (int64_t q = 0; q < rows; ++q) M[q * 6 + k] = 0;
+                for (int j = 0; j < k; ++j) R[6 * j + k] = 0;
+                R[6 * k + k] = 0;
+            } else {
+                for (int64_t q = 0; q < rows; ++q) M[q * 6 + k] /= nk;
+                R[6 * k + k] = nk;
+            }
+        }
+        for (size_t t = 0; t < mem[a].size(); ++t)
+            for (int r = 0; r < bs; ++r)
+                for (int k = 0; k < 6; ++k) Q[((int64_t)mem[a][t] * bs + r) * 6 + k] = M[(t * bs + r) * 6 + k];
+        std::memcpy(&Bc[a * 36], R, sizeof R);
+    }
+}
+
+void sorted_union(std::vector<int32_t> &v)
+{
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+}
+
+template <typename T>
+fg_status up(T **p, const std::vector<T> &v)
+{
+    const size_t n = std::max<size_t>(v.size(), 1);
+    if (hipMalloc((void **)p, n * sizeof(T)) != hipSuccess) {
+        hipGetLastError();
+        return FG_ERR_OOM;
+    }
+    if (!v.empty()) hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+    return FG_OK;
+}
+
+fg_status dmal(double **p, int64_t n)
+{
+    if (hipMalloc((void **)p, std::max<int64_t>(n, 1) * sizeof(double)) != hipSuccess) {
+        hipGetLastError();
+        return FG_ERR_OOM;
+    }
+    return FG_OK;
+}
+
+// CSR of per-row sorted lists.
+void to_csr(const Lists &l, std::vector<int64_t> &row, std::vector<int32_t> &col)
+{
+    row.assign(l.size() + 1, 0);
+    for (size_t i = 0; i < l.size(); ++i) row[i + 1] = row[i] + (int64_t)l[i].size();
+    col.clear();
+    col.reserve(row.back());
+    for (const auto &v : l) col.insert(col.end(), v.begin(), v.end());
+}
+
+// ------------------------------------------------------------ numeric kernels
+// A entry (row, k) of level 0 = K's slots (block CSR copy).
+__global__ void k_amg_copy_k(int64_t Npad, const int64_t *__restrict__ slice_ptr, const uint8_t *__restrict__ rowlen,
+                             const int32_t *__restrict__ col, const double *__restrict__ K,
+                             const int64_t *__restrict__ arow, int32_t *acol, double *aval)
+{
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= Npad) return;
+    const int64_t base = slice_ptr[r / SLICE], l = r % SLICE;
+    const int len = rowlen[r];
+    for (int j = 0; j < len; ++j) {
+        const int64_t o = arow[r] + j;
+        acol[o] = col[base + (int64_t)j * SLICE + l];
+        for (int e = 0; e < 9; ++e) aval[9 * o + e] = K[9 * base + (int64_t)(9 * j + e) * SLICE + l];
+    }
+}
+
+// In-place Gauss-Jordan inverse with partial pivoting of an n x n block (n <= 6).
+__device__ bool amg_inverse(int n, double *a, double *inv)
+{
+    for (int i = 0; i < n * n; ++i) inv[i] = (i / n == i % n) ? 1.0 : 0.0;
+    for (int c = 0; c < n; ++c) {
+        int pr = c;
+        for (int r = c + 1; r < n; ++r)
+            if (fabs(a[n * r + c]) > fabs(a[n * pr + c])) pr = r;
+        if (!(fabs(a[n * pr + c]) > 0.0)) return false;
+        if (pr != c)
+            for (int k = 0; k < n; ++k) {
+                double t = a[n * c + k];
+                a[n * c + k] = a[n * pr + k];
+                a[n * pr + k] = t;
+                t = inv[n * c + k];
+                inv[n * c + k] = inv[n * pr + k];
+                inv[n * pr + k] = t;
+            }
+        const double p = 1.0 / a[n * c + c];
+        for (int k = 0; k < n; ++k) {
+            a[n * c + k] *= p;
+            inv[n * c + k] *= p;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            const double f = a[n * r + c];
+            if (f == 0.0) continue;
+            for (int k = 0; k < n; ++k) {
+                a[n * r + k] -= f * a[n * c + k];
+                inv[n * r + k] -= f * inv[n * c + k];
+            }
+        }
+    }
+    return true;
+}
+
+// Inverse diagonal blocks and the per-node maximum scalar-row sum of |D^-1 A|
+// (one partial per block; the host takes the maximum).
+template <int BS>
+__global__ void k_amg_diag(int64_t nn, const int64_t *__restrict__ arow, const int32_t *__restrict__ acol,
+                           const double *__restrict__ aval, double *dinv, double *part, int *bad)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    double mx = 0;
+    if (i < nn && arow[i + 1] > arow[i]) {
+        double a[BS * BS], inv[BS * BS];
+        int64_t dslot = -1;
+        for (int64_t o = arow[i]; o < arow[i + 1]; ++o)
+            if (acol[o] == i) dslot = o;
+        if (dslot < 0) {
+            *bad = 1;
+        } else {
+            for (int e = 0; e < BS * BS; ++e) a[e] = aval[BS * BS * dslot + e];
+            if (!amg_inverse(BS, a, inv)) *bad = 1;
+            for (int e = 0; e < BS * BS; ++e) dinv[BS * BS * i + e] = inv[e];
+            double s[BS];
+            for (int r = 0; r < BS; ++r) s[r] = 0;
+            for (int64_t o = arow[i]; o < arow[i + 1]; ++o) {
+                const double *m = aval + BS * BS * o;
+                for (int r = 0; r < BS; ++r)
+                    for (int c = 0; c < BS; ++c) {
+                        double v = 0;
+                        for (int k = 0; k < BS; ++k) v += inv[BS * r + k] * m[BS * k + c];
+                        s[r] += fabs(v);
+                    }
+            }
+            for (int r = 0; r < BS; ++r) mx = fmax(mx, s[r]);
+        }
+    }
+    __shared__ double sh[WG];
+    sh[threadIdx.x] = mx;
+    __syncthreads();
+    for (int o = WG / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// Position of aggregate c in the sorted list col[lo, hi), -1 if absent.
+__device__ __forceinline__ int64_t amg_find(const int32_t *__restrict__ col, int64_t lo, int64_t hi, int32_t c)
+{
+    const int64_t end = hi;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (col[mid] < c) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < end && col[lo] == c) ? lo : -1;
+}
+
+// P entry (i, a) = [i in a] Q_i - w D_i^-1 sum_{j in row i, agg(j) = a} A_ij Q_j.
+template <int BS>
+__global__ void k_amg_prolong(int64_t nn, const int64_t *__restrict__ arow, const int32_t *__restrict__ acol,
+                              const double *__restrict__ aval, const int32_t *__restrict__ agg,
+                              const double *__restrict__ q, const double *__restrict__ dinv,
+                              const int64_t *__restrict__ prow, const int32_t *__restrict__ pcol, double w,
+                              double *pval)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nn) return;
+    for (int64_t e = prow[i]; e < prow[i + 1]; ++e) {
+        const int32_t a = pcol[e];
+        double acc[BS * 6];
+        for (int k = 0; k < BS * 6; ++k) acc[k] = 0;
+        for (int64_t o = arow[i]; o < arow[i + 1]; ++o) {
+            const int32_t j = acol[o];
+            if (agg[j] != a) continue;
+            const double *m = aval + BS * BS * o, *qj = q + (int64_t)BS * 6 * j;
+            for (int r = 0; r < BS; ++r)
+                for (int k = 0; k < BS; ++k) {
+                    const double mv = m[BS * r + k];
+                    for (int c = 0; c < 6; ++c) acc[6 * r + c] += mv * qj[6 * k + c];
+                }
+        }
+        const double *di = dinv + BS * BS * i;
+        const bool own = agg[i] == a;
+        for (int r = 0; r < BS; ++r)
+            for (int c = 0; c < 6; ++c) {
+                double v = 0;
+                for (int k = 0; k < BS; ++k) v += di[BS * r + k] * acc[6 * k + c];
+                pval[BS * 6 * e + 6 * r + c] = (own ? q[(int64_t)BS * 6 * i + 6 * r + c] : 0.0) - w * v;
+            }
+    }
+}
+
+// W entry (i, J) = sum_{j in row i} A_ij P(j, J).
+template <int BS>
+__global__ void k_amg_ap(int64_t nn, const int64_t *__restrict__ arow, const int32_t *__restrict__ acol,
+                         const double *__restrict__ aval, const int64_t *__restrict__ prow,
+                         const int32_t *__restrict__ pcol, const double *__restrict__ pval,
+                         const int64_t *__restrict__ wrow, const int32_t *__restrict__ wcol, double *wval)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nn) return;
+    for (int64_t e = wrow[i]; e < wrow[i + 1]; ++e) {
+        const int32_t J = wcol[e];
+        double acc[BS * 6];
+        for (int k = 0; k < BS * 6; ++k) acc[k] = 0;
+        for (int64_t o = arow[i]; o < arow[i + 1]; ++o) {
+            const int32_t j = acol[o];
+            const int64_t f = amg_find(pcol, prow[j], prow[j + 1], J);
+            if (f < 0) continue;
+            const double *m = aval + BS * BS * o, *pj = pval + BS * 6 * f;
+            for (int r = 0; r < BS; ++r)
+                for (int k = 0; k < BS; ++k) {
+                    const double mv = m[BS * r + k];
+                    for (int c = 0; c < 6; ++c) acc[6 * r + c] += mv * pj[6 * k + c];
+                }
+        }
+        for (int k = 0; k < BS * 6; ++k) wval[BS * 6 * e + k] = acc[k];
+    }
+}
+
+// A_c entry (I, J) = sum_{(i, e) in P^T row I} P_e^T W(i, J); an empty coarse row
+// gets a unit diagonal.
+template <int BS>
+__global__ void k_amg_rap(int64_t nc, const int64_t *__restrict__ rrow, const int32_t *__restrict__ rnode,
+                          const int64_t *__restrict__ rent, const double *__restrict__ pval,
+                          const int64_t *__restrict__ wrow, const int32_t *__restrict__ wcol,
+                          const double *__restrict__ wval, const int64_t *__restrict__ crow,
+                          const int32_t *__restrict__ ccol, double *cval)
+{
+    const int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (I >= nc) return;
+    double rs[6] = {0, 0, 0, 0, 0, 0};
+    int64_t dslot = -1;
+    for (int64_t e = crow[I]; e < crow[I + 1]; ++e) {
+        const int32_t J = ccol[e];
+        if (J == I) dslot = e;
+        double acc[36];
+        for (int k = 0; k < 36; ++k) acc[k] = 0;
+        for (int64_t t = rrow[I]; t < rrow[I + 1]; ++t) {
+            const int32_t i = rnode[t];
+            const int64_t f = amg_find(wcol, wrow[i], wrow[i + 1], J);
+            if (f < 0) continue;
+            const double *p = pval + BS * 6 * rent[t], *wv = wval + BS * 6 * f;
+            for (int k = 0; k < BS; ++k)
+                for (int r = 0; r < 6; ++r) {
+                    const double pv = p[6 * k + r];
+                    for (int c = 0; c < 6; ++c) acc[6 * r + c] += pv * wv[6 * k + c];
+                }
+        }
+        for (int k = 0; k < 36; ++k) cval[36 * e + k] = acc[k];
+        for (int r = 0; r < 6; ++r)
+            for (int c = 0; c < 6; ++c) rs[r] += fabs(acc[6 * r + c]);
+    }
+    if (dslot >= 0)
+        for (int r = 0; r < 6; ++r)
+            if (rs[r] == 0.0) cval[36 * dslot + 7 * r] = 1.0;
+}
+
+// ------------------------------------------------------------ cycle kernels
+template <int BS>
+__global__ void k_amg_spmv(int64_t nn, const int64_t *__restrict__ arow, const int32_t *__restrict__ acol,
+                           const double *__restrict__ aval, const double *__restrict__ x, double *y)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= nn * BS) return;
+    const int64_t i = g / BS;
+    const int r = (int)(g - i * BS);
+    double s = 0;
+    for (int64_t o = arow[i]; o < arow[i + 1]; ++o) {
+        const double *m = aval + BS * BS * o + BS * r;
+        const double *xj = x + (int64_t)BS * acol[o];
+        for (int k = 0; k < BS; ++k) s += m[k] * xj[k];
+    }
+    y[g] = s;
+}
+
+// out = dinv x per node (6x6 blocks of the coarse levels), scaled by sc.
+__global__ void k_amg_dapply(int64_t nn, const double *__restrict__ dinv, const double *__restrict__ x, double sc,
+                             double *out)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= nn * 6) return;
+    const int64_t i = g / 6;
+    const int r = (int)(g - i * 6);
+    double s = 0;
+    for (int k = 0; k < 6; ++k) s += dinv[36 * i + 6 * r + k] * x[6 * i + k];
+    out[g] = sc * s;
+}
+
+// bc(I) = sum_{(i, e)} P_e^T r_i
+template <int BS>
+__global__ void k_amg_restrict(int64_t nc, const int64_t *__restrict__ rrow, const int32_t *__restrict__ rnode,
+                               const int64_t *__restrict__ rent, const double *__restrict__ pval,
+                               const double *__restrict__ r, double *bc)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= nc * 6) return;
+    const int64_t I = g / 6;
+    const int c = (int)(g - I * 6);
+    double s = 0;
+    for (int64_t t = rrow[I]; t < rrow[I + 1]; ++t) {
+        const double *p = pval + BS * 6 * rent[t];
+        const double *ri = r + (int64_t)BS * rnode[t];
+        for (int k = 0; k < BS; ++k) s += p[6 * k + c] * ri[k];
+    }
+    bc[g] = s;
+}
+
+// x_i += sum_{e in P row i} P_e xc(agg)
+template <int BS>
+__global__ void k_amg_prolong_add(int64_t nn, const int64_t *__restrict__ prow, const int32_t *__restrict__ pcol,
+                                  const double *__restrict__ pval, const double *__restrict__ xc, double *x)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= nn * BS) return;
+    const int64_t i = g / BS;
+    const int r = (int)(g - i * BS);
+    double s = 0;
+    for (int64_t e = prow[i]; e < prow[i + 1]; ++e) {
+        const double *p = pval + BS * 6 * e + 6 * r;
+        const double *xa = xc + 6 * (int64_t)pcol[e];
+        for (int c = 0; c < 6; ++c) s += p[c] * xa[c];
+    }
+    x[g] += s;
+}
+
+__global__ void k_amg_dense(int64_t n, const double *__restrict__ Ainv, const double *__restrict__ x, double *y)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0;
+    for (int64_t k = 0; k < n; ++k) s += Ainv[i * n + k] * x[k];
+    y[i] = s;
+}
+
+inline int64_t nb(int64_t n) { return std::max<int64_t>((n + WG - 1) / WG, 1); }
+
+void free_level(AmgLevel &L)
+{
+    void *p[] = {L.arow, L.acol, L.aval, L.agg, L.q, L.prow, L.pcol, L.pval, L.wrow, L.wcol, L.wval,
+                 L.rrow, L.rnode, L.rent, L.dinv, L.x, L.b, L.r, L.e, L.t, L.d, L.s, L.w};
+    for (void *v : p)
+        if (v) hipFree(v);
+    L = AmgLevel{};
+}
+
+}  // namespace
+
+void amg_destroy(fg_system *S)
+{
+    if (!S->amg) return;
+    for (AmgLevel &L : S->amg->L) free_level(L);
+    if (S->amg->cinv) hipFree(S->amg->cinv);
+    if (S->amg->part) hipFree(S->amg->part);
+    for (double *v : {S->amg->cr, S->amg->cz, S->amg->cp, S->amg->cq})
+        if (v) hipFree(v);
+    delete S->amg;
+    S->amg = nullptr;
+}
+
+// ------------------------------------------------------------ symbolic set-up (host, once per mesh)
+static fg_status amg_plan(fg_system *S)
+{
+    const Plan &P = S->plan;
+    const int64_t N = S->N, Npad = S->Npad;
+    AmgData *G = new AmgData();
+    G->coarse_nodes = S->amg_coarse;
+    S->amg = G;
+    // level 0 in the caller's numbering: node graph, fault twins, coordinates, held DOFs
+    Lists adj(N);
+    std::vector<int32_t> twin(N, -1);
+    std::vector<double> xyz(3 * N);
+    std::vector<uint8_t> held(3 * N);
+    for (int64_t r = 0; r < Npad; ++r) {
+        const int32_t i = P.perm[r];
+        if (i < 0) continue;
+        const int64_t base = P.slice_ptr[r / SLICE] + r % SLICE;
+        for (int j = 0; j < P.rowlen[r]; ++j) {
+            const int32_t c = P.perm[P.col[base + (int64_t)j * SLICE]];
+            if (c != i && c >= 0) adj[i].push_back(c);
+        }
+        sorted_union(adj[i]);
+        const int32_t k = P.fslot.empty() ? -1 : P.fslot[r];
+        if (k >= 0 && P.fpart[k] >= 0) twin[i] = P.perm[P.fpart[k]];
+        for (int c = 0; c < 3; ++c) {
+            xyz[3 * i + c] = P.xyz[3 * r + c];
+            held[3 * i + c] = P.dir_u[3 * r + c];
+        }
+    }
+    for (int64_t i = 0; i < N; ++i)
+        if (twin[i] >= 0 && twin[twin[i]] != i) twin[i] = -1;
+    std::vector<double> B(N * 18, 0.0);
+    int64_t nn = N;
+    int bs = 3;
+    Lists A_pat = adj;   // per node, neighbours and itself, sorted (built below)
+    for (int64_t i = 0; i < N; ++i) {
+        A_pat[i].push_back((int32_t)i);
+        sorted_union(A_pat[i]);
+    }
+    fg_status st = FG_OK;
+#define AMG_CK(x)                         \
+    do {                                  \
+        if ((st = (x)) != FG_OK) {        \
+            amg_destroy(S);               \
+            set_error("AMG set-up: device allocation failed"); \
+            return st;                    \
+        }                                 \
+    } while (0)
+    for (int l = 0; l < AMG_MAXLEV; ++l) {
+        AmgLevel &L = G->L[l];
+        L.bs = bs;
+        G->nlev = l + 1;
+        // this level's matrix pattern on the device (level 0: rows in internal order)
+        const int64_t rows = l == 0 ? Npad : nn;
+        if (l == 0) {
+            std::vector<int64_t> arow(Npad + 1, 0);
+            for (int64_t r = 0; r < Npad; ++r) arow[r + 1] = arow[r] + P.rowlen[r];
+            L.nnzb = arow.back();
+            AMG_CK(up(&L.arow, arow));
+            AMG_CK(up(&L.acol, std::vector<int32_t>((size_t)L.nnzb)));
+        } else {
+            std::vector<int64_t> arow;
+            std::vector<int32_t> acol;
+            to_csr(A_pat, arow, acol);
+            L.nnzb = arow.back();
+            AMG_CK(up(&L.arow, arow));
+            AMG_CK(up(&L.acol, acol));
+        }
+        L.nn = rows;
+        AMG_CK(dmal(&L.aval, L.nnzb * bs * bs));
+        AMG_CK(dmal(&L.dinv, rows * bs * bs));
+        double **vec[] = {&L.x, &L.b, &L.r, &L.e, &L.t, &L.d, &L.s, &L.w};
+        for (double **v : vec) AMG_CK(dmal(v, rows * bs));
+        if (nn <= G->coarse_nodes || l == AMG_MAXLEV - 1) break;
+        // aggregation on the level's node graph
+        Lists nb_l(nn);
+        for (int64_t i = 0; i < nn; ++i)
+            for (int32_t j : A_pat[i])
+                if (j != i) nb_l[i].push_back(j);
+        std::vector<int32_t> agg;
+        const int64_t na = aggregate(nn, nb_l, l == 0 ? &twin : nullptr, agg);
+        L.nc = na;
+        if (l == 0) {
+            std::vector<double> cen(3 * na, 0.0);
+            std::vector<int64_t> cnt(na, 0);
+            for (int64_t i = 0; i < N; ++i) {
+                for (int c = 0; c < 3; ++c) cen[3 * agg[i] + c] += xyz[3 * i + c];
+                cnt[agg[i]]++;
+            }
+            for (int64_t a = 0; a < na; ++a)
+                for (int c = 0; c < 3; ++c) cen[3 * a + c] /= (double)cnt[a];
+            for (int64_t i = 0; i < N; ++i) {
+                const double *c0 = &cen[3 * agg[i]];
+                const double dx = xyz[3 * i] - c0[0], dy = xyz[3 * i + 1] - c0[1], dz = xyz[3 * i + 2] - c0[2];
+                const double rw[3][6] = {{1, 0, 0, 0, dz, -dy}, {0, 1, 0, -dz, 0, dx}, {0, 0, 1, dy, -dx, 0}};
+                for (int r = 0; r < 3; ++r)
+                    for (int k = 0; k < 6; ++k) B[(3 * i + r) * 6 + k] = held[3 * i + r] ? 0.0 : rw[r][k];
+            }
+        }
+        std::vector<double> Q, Bc;
+        tentative(bs, nn, na, agg, B, Q, Bc);
+        // patterns of P, W = A P and A_c = P^T W (entries touched by the products)
+        Lists Pp(nn), Wp(nn), Cp(na);
+        for (int64_t i = 0; i < nn; ++i) {
+            for (int32_t j : A_pat[i]) Pp[i].push_back(agg[j]);
+            sorted_union(Pp[i]);
+        }
+        for (int64_t i = 0; i < nn; ++i) {
+            for (int32_t j : A_pat[i]) Wp[i].insert(Wp[i].end(), Pp[j].begin(), Pp[j].end());
+            sorted_union(Wp[i]);
+        }
+        std::vector<std::vector<std::pair<int32_t, int64_t>>> Rl(na);   // (node, P entry), increasing node
+        std::vector<int64_t> prow_c(nn + 1, 0);
+        for (int64_t i = 0; i < nn; ++i) prow_c[i + 1] = prow_c[i] + (int64_t)Pp[i].size();
+        for (int64_t i = 0; i < nn; ++i)
+            for (size_t t = 0; t < Pp[i].size(); ++t) {
+                Rl[Pp[i][t]].push_back({(int32_t)i, prow_c[i] + (int64_t)t});
+                Cp[Pp[i][t]].insert(Cp[Pp[i][t]].end(), Wp[i].begin(), Wp[i].end());
+            }
+        for (auto &v : Cp) sorted_union(v);
+        // to the device; level 0 rows go to internal order
+        std::vector<int64_t> prow, wrow, rrow(na + 1, 0), rent;
+        std::vector<int32_t> pcol, wcol, rnode, aggd;
+        std::vector<double> qd;
+        if (l == 0) {
+            Lists Pi(Npad), Wi(Npad);
+            std::vector<int32_t> ag(Npad, -1);
+            qd.assign(Npad * 18, 0.0);
+            for (int64_t r = 0; r < Npad; ++r) {
+                const int32_t i = P.perm[r];
+                if (i < 0) continue;
+                Pi[r] = Pp[i];
+                Wi[r] = Wp[i];
+                ag[r] = agg[i];
+                std::memcpy(&qd[r * 18], &Q[(int64_t)i * 18], 18 * sizeof(double));
+            }
+            to_csr(Pi, prow, pcol);
+            to_csr(Wi, wrow, wcol);
+            aggd = ag;
+            // P^T lists: internal row and internal P entry, in increasing caller node order
+            for (int64_t a = 0; a < na; ++a) {
+                rrow[a + 1] = rrow[a] + (int64_t)Rl[a].size();
+                for (auto &pr : Rl[a]) {
+                    const int32_t r = P.iperm[pr.first];
+                    const int64_t t = pr.second - prow_c[pr.first];
+                    rnode.push_back(r);
+                    rent.push_back(prow[r] + t);
+                }
+            }
+        } else {
+            to_csr(Pp, prow, pcol);
+            to_csr(Wp, wrow, wcol);
+            aggd = agg;
+            qd = Q;
+            for (int64_t a = 0; a < na; ++a) {
+                rrow[a + 1] = rrow[a] + (int64_t)Rl[a].size();
+                for (auto &pr : Rl[a]) {
+                    rnode.push_back(pr.first);
+                    rent.push_back(pr.second);
+                }
+            }
+        }
+        L.npz = (int64_t)pcol.size();
+        L.nwz = (int64_t)wcol.size();
+        L.nrz = (int64_t)rnode.size();
+        AMG_CK(up(&L.agg, aggd));
+        AMG_CK(up(&L.q, qd));
+        AMG_CK(up(&L.prow, prow));
+        AMG_CK(up(&L.pcol, pcol));
+        AMG_CK(dmal(&L.pval, L.npz * bs * 6));
+        AMG_CK(up(&L.wrow, wrow));
+        AMG_CK(up(&L.wcol, wcol));
+        AMG_CK(dmal(&L.wval, L.nwz * bs * 6));
+        AMG_CK(up(&L.rrow, rrow));
+        AMG_CK(up(&L.rnode, rnode));
+        AMG_CK(up(&L.rent, rent));
+        // next level
+        A_pat.swap(Cp);
+        for (int64_t a = 0; a < na; ++a) {
+            bool self = std::binary_search(A_pat[a].begin(), A_pat[a].end(), (int32_t)a);
+            if (!self) {
+                A_pat[a].push_back((int32_t)a);
+                sorted_union(A_pat[a]);
+            }
+        }
+        B.assign(na * 36, 0.0);
+        for (int64_t a = 0; a < na; ++a)
+            for (int k = 0; k < 36; ++k) B[a * 36 + k] = Bc[a * 36 + k];
+        nn = na;
+        bs = 6;
+    }
+#undef AMG_CK
+    const AmgLevel &C = G->L[G->nlev - 1];
+    G->nco = C.nn * C.bs;
+    const bool too_big = G->nco > 8192;
+    if (too_big || dmal(&G->cinv, G->nco * G->nco) || dmal(&G->part, 1 << 16) || dmal(&G->cr, 3 * Npad) ||
+        dmal(&G->cz, 3 * Npad) || dmal(&G->cp, 3 * Npad) || dmal(&G->cq, 3 * Npad)) {
+        amg_destroy(S);   // frees G
+        set_error(too_big ? "AMG set-up: the coarsest level stays above 8192 unknowns"
+                          : "AMG set-up: device allocation failed");
+        return too_big ? FG_ERR_ARG : FG_ERR_OOM;
+    }
+    return FG_OK;
+}
+
+// ------------------------------------------------------------ numeric set-up (GPU, per K)
+static fg_status amg_diag_level(fg_system *S, AmgLevel &L, hipStream_t st)
+{
+    AmgData *G = S->amg;
+    int *bad = (int *)S->red_counter + 3;
+    hipMemsetAsync(bad, 0, sizeof(int), st);
+    const int64_t blocks = nb(L.nn);
+    if (blocks > (1 << 16)) {
+        set_error("AMG set-up: level too large for the reduction workspace");
+        return FG_ERR_ARG;
+    }
+    if (L.bs == 3)
+        LAUNCH((k_amg_diag<3>), blocks, WG, st, L.nn, L.arow, L.acol, L.aval, L.dinv, G->part, bad);
+    else
+        LAUNCH((k_amg_diag<6>), blocks, WG, st, L.nn, L.arow, L.acol, L.aval, L.dinv, G->part, bad);
+    std::vector<double> part(blocks);
+    int h = 0;
+    hipMemcpyAsync(part.data(), G->part, blocks * sizeof(double), hipMemcpyDeviceToHost, st);
+    hipMemcpyAsync(&h, bad, sizeof(int), hipMemcpyDeviceToHost, st);
+    hipStreamSynchronize(st);
+    L.rho = 0;
+    for (double v : part) L.rho = std::max(L.rho, v);
+    if (h || !(L.rho > 0) || !std::isfinite(L.rho)) {
+        set_error("AMG set-up: a diagonal block is singular");
+        return FG_ERR_BREAKDOWN;
+    }
+    return check_hip("AMG diagonal blocks");
+}
+
+static fg_status amg_numeric(fg_system *S, hipStream_t st)
+{
+    AmgData *G = S->amg;
+    bj_ready(S, st);
+    if (S->bj_singular) {
+        set_error("AMG set-up: a diagonal or fault-pair block of K is singular");
+        return FG_ERR_BREAKDOWN;
+    }
+    fg_status e = cheb_interval_ready(S, st);   // the level-0 smoother's interval
+    if (e) return e;
+    LAUNCH(k_amg_copy_k, nb(S->Npad), WG, st, S->Npad, S->slice_ptr, S->rowlen, S->col, S->K, G->L[0].arow,
+           G->L[0].acol, G->L[0].aval);
+    for (int l = 0; l < G->nlev; ++l) {
+        AmgLevel &L = G->L[l];
+        e = amg_diag_level(S, L, st);
+        if (e) return e;
+        if (l == G->nlev - 1) break;
+        AmgLevel &C = G->L[l + 1];
+        const double w = 4.0 / (3.0 * L.rho);
+        if (L.bs == 3) {
+            LAUNCH((k_amg_prolong<3>), nb(L.nn), WG, st, L.nn, L.arow, L.acol, L.aval, L.agg, L.q, L.dinv, L.prow,
+                   L.pcol, w, L.pval);
+            LAUNCH((k_amg_ap<3>), nb(L.nn), WG, st, L.nn, L.arow, L.acol, L.aval, L.prow, L.pcol, L.pval, L.wrow,
+                   L.wcol, L.wval);
+            LAUNCH((k_amg_rap<3>), nb(L.nc), WG, st, L.nc, L.rrow, L.rnode, L.rent, L.pval, L.wrow, L.wcol, L.wval,
+                   C.arow, C.acol, C.aval);
+        } else {
+            LAUNCH((k_amg_prolong<6>), nb(L.nn), WG, st, L.nn, L.arow, L.acol, L.aval, L.agg, L.q, L.dinv, L.prow,
+                   L.pcol, w, L.pval);
+            LAUNCH((k_amg_ap<6>), nb(L.nn), WG, st, L.nn, L.arow, L.acol, L.aval, L.prow, L.pcol, L.pval, L.wrow,
+                   L.wcol, L.wval);
+            LAUNCH((k_amg_rap<6>), nb(L.nc), WG, st, L.nc, L.rrow, L.rnode, L.rent, L.pval, L.wrow, L.wcol, L.wval,
+                   C.arow, C.acol, C.aval);
+        }
+        e = check_hip("AMG prolongator and coarse operator");
+        if (e) return e;
+    }
+    // the coarsest matrix: dense inverse on the host (Cholesky, then columns of the inverse)
+    const AmgLevel &C = G->L[G->nlev - 1];
+    const int64_t n = G->nco;
+    std::vector<int64_t> arow(C.nn + 1);
+    std::vector<int32_t> acol(C.nnzb);
+    std::vector<double> aval(C.nnzb * C.bs * C.bs);
+    hipMemcpyAsync(arow.data(), C.arow, arow.size() * sizeof(int64_t), hipMemcpyDeviceToHost, st);
+    hipMemcpyAsync(acol.data(), C.acol, acol.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    hipMemcpyAsync(aval.data(), C.aval, aval.size() * sizeof(double), hipMemcpyDeviceToHost, st);
+    hipStreamSynchronize(st);
+    const int bs = C.bs;
+    std::vector<double> L(n * n, 0.0), inv(n * n, 0.0);
+    for (int64_t i = 0; i < C.nn; ++i)
+        for (int64_t o = arow[i]; o < arow[i + 1]; ++o)
+            for (int r = 0; r < bs; ++r)
+                for (int c = 0; c < bs; ++c) L[(bs * i + r) * n + bs * (int64_t)acol[o] + c] = aval[bs * bs * o + bs * r + c];
+    for (int64_t j = 0; j < n; ++j) {
+        double d = L[j * n + j];
+        for (int64_t k = 0; k < j; ++k) d -= L[j * n + k] * L[j * n + k];
+        if (!(d > 0)) {
+            set_error("AMG set-up: the coarsest matrix is not positive definite");
+            return FG_ERR_BREAKDOWN;
+        }
+        d = std::sqrt(d);
+        L[j * n + j] = d;
+        for (int64_t i = j + 1; i < n; ++i) {
+            double s = L[i * n + j];
+            for (int64_t k = 0; k < j; ++k) s -= L[i * n + k] * L[j * n + k];
+            L[i * n + j] = s / d;
+        }
+    }
+    std::vector<double> col(n);
+    for (int64_t c = 0; c < n; ++c) {
+        for (int64_t i = 0; i < n; ++i) {
+            double s = i == c ? 1.0 : 0.0;
+            for (int64_t k = 0; k < i; ++k) s -= L[i * n + k] * col[k];
+            col[i] = s / L[i * n + i];
+        }
+        for (int64_t i = n - 1; i >= 0; --i) {
+            double s = col[i];
+            for (int64_t k = i + 1; k < n; ++k) s -= L[k * n + i] * col[k];
+            col[i] = s / L[i * n + i];
+        }
+        for (int64_t i = 0; i < n; ++i) inv[i * n + c] = col[i];
+    }
+    hipMemcpyAsync(G->cinv, inv.data(), n * n * sizeof(double), hipMemcpyHostToDevice, st);
+    hipStreamSynchronize(st);
+    G->epoch = S->bj_epoch;
+    return check_hip("AMG coarsest inverse");
+}
+
+fg_status amg_ready(fg_system *S, hipStream_t st)
+{
+    if (S->ngroups > 1) {
+        set_error("AMG: batched systems are not supported");
+        return FG_ERR_ARG;
+    }
+    if (!S->amg) {
+        fg_status e = amg_plan(S);
+        if (e) return e;
+    }
+    bj_ready(S, st);
+    if (S->amg->epoch == S->bj_epoch) return FG_OK;
+    return amg_numeric(S, st);
+}
+
+// ------------------------------------------------------------ the V-cycle
+// x = p(M^-1 A) M^-1 b, degree-2 Chebyshev over the level's block Jacobi (x, b on the level).
+static void amg_smooth(fg_system *S, int l, const double *b, double *x, hipStream_t st)
+{
+    AmgData *G = S->amg;
+    AmgLevel &L = G->L[l];
+    const int64_t n = L.nn * L.bs;
+    const double hi = l == 0 ? S->cheb_hi : L.rho, lo = hi / 30.0;
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+    auto minv = [&](const double *v, double *out) {
+        if (l == 0)
+            bj_apply(S, v, out, st);
+        else
+            LAUNCH(k_amg_dapply, nb(n), WG, st, L.nn, L.dinv, v, 1.0, out);
+    };
+    auto amul = [&](const double *v, double *out) {
+        if (l == 0)
+            spmv(S, FG_K, v, out, st);
+        else
+            LAUNCH((k_amg_spmv<6>), nb(n), WG, st, L.nn, L.arow, L.acol, L.aval, v, out);
+    };
+    double *d = L.d, *s = L.s, *w = L.w, *kd = L.t;
+    minv(b, d);
+    vscale(n, 1.0 / theta, d, st);
+    hipMemcpyAsync(x, d, n * sizeof(double), hipMemcpyDeviceToDevice, st);
+    hipMemcpyAsync(s, b, n * sizeof(double), hipMemcpyDeviceToDevice, st);
+    const double rho0 = 1.0 / sigma;
+    amul(d, kd);
+    vaxpby(n, -1.0, kd, 1.0, s, st);
+    const double rho1 = 1.0 / (2.0 * sigma - rho0);
+    minv(s, w);
+    vaxpby(n, 2.0 * rho1 / delta, w, rho1 * rho0, d, st);
+    vaxpby(n, 1.0, d, 1.0, x, st);
+}
+
+static void amg_vcycle(fg_system *S, int l, const double *b, double *x, hipStream_t st)
+{
+    AmgData *G = S->amg;
+    AmgLevel &L = G->L[l];
+    const int64_t n = L.nn * L.bs;
+    if (l == G->nlev - 1) {
+        LAUNCH(k_amg_dense, nb(n), WG, st, n, G->cinv, b, x);
+        return;
+    }
+    AmgLevel &C = G->L[l + 1];
+    auto amul = [&](const double *v, double *out) {
+        if (l == 0)
+            spmv(S, FG_K, v, out, st);
+        else
+            LAUNCH((k_amg_spmv<6>), nb(n), WG, st, L.nn, L.arow, L.acol, L.aval, v, out);
+    };
+    amg_smooth(S, l, b, x, st);                       // pre-smoothing from zero
+    amul(x, L.r);
+    vaxpby(n, 1.0, b, -1.0, L.r, st);                 // r = b - A x
+    if (L.bs == 3)
+        LAUNCH((k_amg_restrict<3>), nb(6 * L.nc), WG, st, L.nc, L.rrow, L.rnode, L.rent, L.pval, L.r, C.b);
+    else
+        LAUNCH((k_amg_restrict<6>), nb(6 * L.nc), WG, st, L.nc, L.rrow, L.rnode, L.rent, L.pval, L.r, C.b);
+    amg_vcycle(S, l + 1, C.b, C.x, st);
+    if (L.bs == 3)
+        LAUNCH((k_amg_prolong_add<3>), nb(n), WG, st, L.nn, L.prow, L.pcol, L.pval, C.x, x);
+    else
+        LAUNCH((k_amg_prolong_add<6>), nb(n), WG, st, L.nn, L.prow, L.pcol, L.pval, C.x, x);
+    amul(x, L.r);
+    vaxpby(n, 1.0, b, -1.0, L.r, st);
+    amg_smooth(S, l, L.r, L.e, st);                   // post-smoothing on the residual
+    vaxpby(n, 1.0, L.e, 1.0, x, st);
+}
+
+void amg_levels(const fg_system *S, int *nlev, int64_t *nodes)
+{
+    *nlev = S->amg ? S->amg->nlev : 0;
+    for (int l = 0; l < AMG_MAXLEV; ++l)
+        nodes[l] = (S->amg && l < S->amg->nlev) ? (l == 0 ? S->N : S->amg->L[l].nn) : 0;
+}
+
+// PCG on K with the V-cycle (internal vectors; same recurrence and stop test as cg_run).
+fg_status amg_pcg(fg_system *S, const double *b, double *x, double tol, int64_t maxit, int64_t *iters, double *relres,
+                  hipStream_t st)
+{
+    *iters = 0;
+    *relres = 0;
+    fg_status e = amg_ready(S, st);
+    if (e) return e;
+    const int64_t n = 3 * S->Npad;
+    double *r = S->amg->cr, *z = S->amg->cz, *p = S->amg->cp, *q = S->amg->cq;
+    vfill(x, 0.0, n, st);
+    hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, st);
+    amg_vcycle(S, 0, r, z, st);
+    hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, st);
+    double d2[2];
+    {
+        const double *A[2] = {b, r}, *B2[2] = {b, z};
+        vdots(S, n, 2, A, B2, d2, st);
+    }
+    const double bn = std::sqrt(d2[0]);
+    double rho = d2[1];
+    if (!(bn > 0)) return std::isfinite(bn) ? FG_OK : FG_ERR_NAN;
+    int64_t it = 0;
+    for (;;) {
+        double rr;
+        {
+            const double *A[1] = {r};
+            vdots(S, n, 1, A, A, &rr, st);
+        }
+        const double rel = std::sqrt(rr) / bn;
+        *relres = rel;
+        if (!std::isfinite(rel)) {
+            set_error("fg_pcg_solve: NaN in the AMG-preconditioned CG");
+            return FG_ERR_NAN;
+        }
+        if (rel <= tol) break;
+        if (it >= maxit) {
+            *iters = it;
+            return FG_NOT_CONVERGED;
+        }
+        spmv(S, FG_K, p, q, st);
+        double pq;
+        {
+            const double *A[1] = {p}, *B1[1] = {q};
+            vdots(S, n, 1, A, B1, &pq, st);
+        }
+        if (!(pq > 0.0)) {
+            set_error("fg_pcg_solve: CG breakdown (p.Ap <= 0) with the AMG preconditioner");
+            *iters = it;
+            return FG_ERR_BREAKDOWN;
+        }
+        const double al = rho / pq;
+        vaxpby(n, al, p, 1.0, x, st);
+        vaxpby(n, -al, q, 1.0, r, st);
+        amg_vcycle(S, 0, r, z, st);
+        double rho2;
+        {
+            const double *A[1] = {r}, *B1[1] = {z};
+            vdots(S, n, 1, A, B1, &rho2, st);
+        }
+        const double be = rho2 / rho;
+        rho = rho2;
+        vaxpby(n, 1.0, z, be, p, st);
+        ++it;
+    }
+    *iters = it;
+    return check_hip("AMG PCG");
+}
+
+}  // namespace fg

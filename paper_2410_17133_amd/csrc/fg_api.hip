@@ -134,7 +134,9 @@ fg_status k_solve(fg_system *S, const double *rhs, double *out, const fg_pcg_opt
         int64_t it = 0;
         double rr = 0;
         fg_status s;
-        if (o.precision == FG_F64 && S->exact_tangent && S->ngroups == 1) {
+        if (o.precision == FG_F64 && S->k_precond == 3 && !S->exact_tangent && S->ngroups == 1) {
+            s = amg_pcg(S, rhs, out, o.tol, o.max_iter, &it, &rr, st);
+        } else if (o.precision == FG_F64 && S->exact_tangent && S->ngroups == 1) {
             s = bicgstab_exact(S, rhs, out, o.tol, o.max_iter, S->exact_tangent == 2, &it, &rr, st);
         } else if (o.precision == FG_F64 && S->k_precond == 2 && S->ngroups == 1) {
             s = cheb_cg(S, rhs, out, o.tol, o.max_iter, o.check_every, &it, &rr, st);
@@ -413,6 +415,7 @@ fg_status fg_system_destroy(fg_system *S)
     drop_graphs(S);
     drop_mr_graphs(S);
     drop_group_graphs(S);
+    amg_destroy(S);
     void *mr_ptrs[] = {S->mx, S->mr, S->mp, S->mq, S->mb, S->mx64, S->mr64, S->mz, S->mfx, S->mfr, S->mfp, S->mfq,
                        S->mfz, S->msc, S->mpart, S->mred};
     for (void *p : mr_ptrs) dfree(p);
@@ -487,6 +490,7 @@ fg_status fg_system_create(fg_ctx *ctx, const fg_mesh *mesh, fg_system **out)
     CK(upload(&S->slice_group, P.slice_group));
     CK(upload(&S->group_slice_ptr, P.group_slice_ptr));
     CK(upload(&S->xyz, xyz));
+    S->plan.xyz = xyz;
     CK(upload(&S->tets, P.tets));
     CK(upload(&S->tet_orig, P.tet_orig));
     CK(upload(&S->coh, P.coh));
@@ -1151,6 +1155,24 @@ fg_status fg_lanczos_bounds(fg_ctx *ctx, fg_system *S, int steps, double *lo, do
     return check_hip("fg_lanczos_bounds");
 }
 
+fg_status fg_amg_levels(fg_ctx *ctx, fg_system *S, int *nlev, int64_t *nodes, void *stream)
+{
+    if (!ctx || !S || !nlev || !nodes) {
+        set_error("fg_amg_levels: bad argument");
+        return FG_ERR_ARG;
+    }
+    if (!ready(S)) return FG_ERR_STATE;
+    if (S->k_precond != 3) {
+        set_error("fg_amg_levels: the AMG preconditioner is not selected (fg_tune k_precond 3)");
+        return FG_ERR_STATE;
+    }
+    Guard g(ctx->device);
+    fg_status e = amg_ready(S, S_(stream));
+    if (e) return e;
+    amg_levels(S, nlev, nodes);
+    return check_hip("fg_amg_levels");
+}
+
 fg_status fg_cheb_interval(fg_ctx *ctx, fg_system *S, double *lo, double *hi, void *stream)
 {
     if (!ctx || !S || !lo || !hi) {
@@ -1292,9 +1314,9 @@ fg_status fg_tune(fg_system *S, const char *key, int64_t value)
         return FG_OK;
     }
     if (std::strcmp(key, "k_precond") == 0) {
-        if (value > 2) {
-            set_error("fg_tune: k_precond must be 0 (point Jacobi), 1 (nodal and fault-pair block Jacobi) or 2 "
-                      "(Chebyshev polynomial over block Jacobi)");
+        if (value > 3) {
+            set_error("fg_tune: k_precond must be 0 (point Jacobi), 1 (nodal and fault-pair block Jacobi), 2 "
+                      "(Chebyshev polynomial over block Jacobi) or 3 (smoothed-aggregation AMG)");
             return FG_ERR_ARG;
         }
         if (value >= 1) {
@@ -1303,6 +1325,15 @@ fg_status fg_tune(fg_system *S, const char *key, int64_t value)
         }
         S->k_precond = (int)value;
         drop_graphs(S);
+        return FG_OK;
+    }
+    if (std::strcmp(key, "amg_coarse") == 0) {
+        if (value < 1 || value > 1000) {
+            set_error("fg_tune: amg_coarse must be 1 to 1000 nodes");
+            return FG_ERR_ARG;
+        }
+        if (value != S->amg_coarse) amg_destroy(S);
+        S->amg_coarse = value;
         return FG_OK;
     }
     if (std::strcmp(key, "line_search") == 0) {

@@ -43,6 +43,7 @@ struct Plan {
     std::vector<int32_t> fslot;      // [Npad] index into frows, -1 for rows off the interface
     std::vector<int32_t> fpart;      // [nfr] internal row of the other lip's node at the same point, -1 if none
     std::vector<uint8_t> dir_u;      // [3*Npad] internal order, padding rows 0
+    std::vector<double> xyz;         // [3*Npad] coordinates, internal order (host copy; AMG set-up)
     std::vector<uint8_t> dir_p;      // [Npad]
 };
 
@@ -71,6 +72,7 @@ struct CgScalars {
 
 void set_error(const std::string &msg);
 
+struct AmgData;  // smoothed-aggregation hierarchy (fg_amg.hip)
 
 struct GraphCache {
     hipGraphExec_t exec = nullptr;
@@ -149,6 +151,8 @@ struct fg_system {
     double cheb_lo = 0, cheb_hi = 0;  // interval of the last estimate
     int64_t cheb_epoch = -1;    // bj_epoch of the last estimate
     int exact_tangent = 0;      // fg_tune "exact_tangent": FP64 K solves of the forward path on K_t + N
+    fg::AmgData *amg = nullptr; // "k_precond" 3: the smoothed-aggregation hierarchy (symbolic part once per mesh)
+    int64_t amg_coarse = 64;    // fg_tune "amg_coarse": coarsening stops at this many nodes
     double *bx = nullptr;       // [5*3*Npad] BiCGStab work vectors (rh, ph, s, sh, t)
     uint8_t *dir_u = nullptr, *dir_p = nullptr;
     double *tri_geo = nullptr;  // [nf*10]: area, n[3], t1[3], t2[3]

@@ -73,6 +73,14 @@ fg_status cheb_cg(fg_system *S, const double *b, double *x, double tol, int64_t 
 fg_status cheb_interval_ready(fg_system *S, hipStream_t st);
 // Smallest and largest Ritz values of `steps` block-Jacobi CG steps on the probe vector.
 fg_status lanczos_bounds(fg_system *S, int steps, double *lo, double *hi, hipStream_t st);
+// Smoothed-aggregation AMG (fg_amg.hip): hierarchy for the current K (symbolic part
+// once per mesh, numeric part when K changed), PCG with its V-cycle on internal
+// vectors, and release.
+fg_status amg_ready(fg_system *S, hipStream_t st);
+fg_status amg_pcg(fg_system *S, const double *b, double *x, double tol, int64_t maxit, int64_t *iters, double *relres,
+                  hipStream_t st);
+void amg_destroy(fg_system *S);
+void amg_levels(const fg_system *S, int *nlev, int64_t *nodes);  // nodes[6]
 // out = M^-1 in with the block-Jacobi data (bj_ready first).
 void bj_apply(fg_system *S, const double *in, double *out, hipStream_t st);
 

@@ -22,7 +22,7 @@ SYMBOLS = ["fg_last_error", "fg_ctx_create", "fg_ctx_destroy", "fg_system_create
            "fg_assemble", "fg_cohesive_update", "fg_pcg_solve", "fg_flow_solve", "fg_step", "fg_spmv",
            "fg_coupling", "fg_residual", "fg_system_sizes", "fg_export", "fg_profile", "fg_profile_read", "fg_tune", "fg_adjoint_solve", "fg_group_stats",
            "fg_assemble_groups", "fg_slip_adjoint", "fg_cheb_interval", "fg_exact_solve", "fg_adjoint_loop_step", "fg_pcg_solve_noalloc",
-           "fg_lanczos_bounds"]
+           "fg_lanczos_bounds", "fg_amg_levels"]
 
 
 class FgError(RuntimeError):
@@ -99,6 +99,7 @@ def lib():
             "fg_slip_adjoint": [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
             "fg_cheb_interval": [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double), vp],
             "fg_exact_solve": [vp, vp, vp, vp, C.POINTER(PcgOpts), C.POINTER(PcgInfo), vp],
+            "fg_amg_levels": [vp, vp, C.POINTER(C.c_int), vp, vp],
             "fg_lanczos_bounds": [vp, vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_double), vp],
             "fg_pcg_solve_noalloc": [vp, vp, i32, vp, vp, C.POINTER(PcgOpts), C.POINTER(PcgInfo), vp],
             "fg_adjoint_loop_step": [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
@@ -333,6 +334,13 @@ class System:
                                      None if lam_u is None else _ptr(lam_u, torch.float64, 3 * self.N, "lam_u"),
                                      _ptr(gU, torch.float64), _ptr(a_old, torch.float64), _stream()), False)
         return gU, a_old
+
+    def amg_levels(self):
+        """(levels, nodes per level) of the AMG hierarchy of k_precond 3 (fg_amg_levels)."""
+        nl = C.c_int()
+        nodes = np.zeros(6, np.int64)
+        _check(lib().fg_amg_levels(self.ctx._h, self._h, C.byref(nl), nodes.ctypes.data, _stream()), False)
+        return nl.value, nodes[:nl.value]
 
     def lanczos_bounds(self, steps):
         """(smallest, largest) Ritz values of `steps` block-Jacobi CG steps on the probe
