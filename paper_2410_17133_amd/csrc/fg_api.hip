@@ -404,7 +404,7 @@ fg_status fg_system_destroy(fg_system *S)
     if (!S) return FG_OK;
     Guard g(S->device);
     hipDeviceSynchronize();
-    void *ptrs[] = {S->gprm, S->slice_group, S->group_slice_ptr, S->gsc, S->gpart, S->gred, S->halo_ptr, S->halo, S->lcol, S->slice_ptr, S->col, S->rowlen, S->diag_slot, S->perm, S->xyz, S->tets, S->tet_orig, S->tslot, S->coh,
+    void *ptrs[] = {S->gprm, S->slice_group, S->group_slice_ptr, S->gsc, S->gpart, S->gred, S->halo_ptr, S->halo, S->lcol, S->slice_ptr, S->col, S->rowlen, S->diag_slot, S->perm, S->xyz, S->tets, S->tet_orig, S->tslot, S->rinc_ptr, S->rinc, S->coh,
                     S->frows, S->fadj_ptr, S->fadj, S->dir_u, S->dir_p, S->tri_geo, S->K, S->K32, S->Kfb, S->A22,
                     S->Cm, S->dinvK, S->dinvK32, S->dinvA, S->qpD, S->qpT, S->qpNs, S->qpS, S->adj_trac, S->adj_die, S->adj_flag, S->wx, S->wr, S->wp, S->wq, S->fx,
                     S->fr, S->fp, S->fq, S->v1, S->v2, S->v3, S->v4, S->pv1, S->pv2, S->ui, S->ui0, S->fi, S->rm,
@@ -573,6 +573,29 @@ fg_status fg_system_create(fg_ctx *ctx, const fg_mesh *mesh, fg_system **out)
         set_error("fg_system_create: allocation of the tetrahedron slot table failed");
         fg_system_destroy(S);
         return FG_ERR_OOM;
+    }
+    {
+        // row incidence list of the assembly: per internal row, an entry for every
+        // element t whose local node a is the row's node, in increasing t; the host
+        // leaves 4 t + a in each entry, tet_slots fills in the rest on the device
+        if (4 * S->ne >= (int64_t(1) << 32)) {
+            set_error("fg_system_create: more than 2^30 tetrahedra");
+            fg_system_destroy(S);
+            return FG_ERR_ARG;
+        }
+        const std::vector<int32_t> &T = S->plan.tets;
+        for (uint8_t w : S->plan.rowlen) S->max_rowlen = std::max(S->max_rowlen, (int)w);
+        std::vector<int64_t> rp(S->Npad + 1, 0);
+        for (int64_t k = 0; k < 4 * S->ne; ++k) rp[T[k] + 1]++;
+        for (int64_t r = 0; r < S->Npad; ++r) rp[r + 1] += rp[r];
+        std::vector<uint32_t> ri(6 * std::max<int64_t>(4 * S->ne, 1), 0);
+        std::vector<int64_t> fill(rp.begin(), rp.end() - 1);
+        for (int64_t k = 0; k < 4 * S->ne; ++k) ri[6 * fill[T[k]]++] = (uint32_t)k;  // k = 4 t + a
+        if (upload(&S->rinc_ptr, rp) || upload(&S->rinc, ri)) {
+            set_error("fg_system_create: allocation of the assembly incidence list failed");
+            fg_system_destroy(S);
+            return FG_ERR_OOM;
+        }
     }
     {
         fg_status e = tet_slots(S, nullptr);

@@ -111,6 +111,7 @@ struct fg_system {
     int64_t *slice_ptr = nullptr;
     int32_t *col = nullptr;
     uint8_t *rowlen = nullptr;
+    int max_rowlen = 0;         // longest row (stored blocks)
     int32_t *diag_slot = nullptr;
     int32_t *perm = nullptr;  // [Npad] internal -> caller, -1 for padding rows
     int ngroups = 1;
@@ -131,6 +132,8 @@ struct fg_system {
     double *xyz = nullptr;
     int32_t *tets = nullptr, *tet_orig = nullptr;
     uint8_t *tslot = nullptr;   // [ne*16] slot of block (a, b) of each grouped tetrahedron in row a
+    int64_t *rinc_ptr = nullptr; // [Npad+1] per row, its range of rinc
+    uint32_t *rinc = nullptr;   // [6 * 4ne] per row, in increasing element order: the element's 4 nodes, its caller index, the 4 slots of the row
     int32_t *coh = nullptr;
     int32_t *frows = nullptr, *fadj_ptr = nullptr, *fadj = nullptr;
     int32_t *fslot = nullptr, *fpart = nullptr;  // fault-pair map (block-Jacobi preconditioner of K)

@@ -126,54 +126,99 @@ __global__ void k_tet_slots(int64_t ne, const int32_t *__restrict__ tets, const 
     }
 }
 
-// One colour of tetrahedra: element stiffness V [lam g_a g_b^T + G (g_b g_a^T + (g_a.g_b) I)],
-// storage (V/(20 M))(1 + delta_ab) and conductivity (k/mu) V g_a.g_b, added to the
-// rows of the element's own nodes (no two elements of a colour share a node) at the
-// slots of the precomputed table.
-__global__ void k_assemble_tets(int64_t t0, int64_t t1, const int32_t *__restrict__ tets,
-                                const int32_t *__restrict__ orig, const double *__restrict__ xyz,
+// Entries of the row incidence list: the host leaves 4 t + a in word 0 of each
+// 6-word entry; this writes the element's 4 nodes starting with the row's own node
+// (a, then the other three in order), its caller index, and the slots of those four
+// blocks of row a in the same order, so the assembly reads one contiguous run per
+// row and the row's node is always local node 0.
+__global__ void k_rinc_fill(int64_t nent, const int32_t *__restrict__ tets, const int32_t *__restrict__ orig,
+                            const uint8_t *__restrict__ tslot, uint32_t *rinc)
+{
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= nent) return;
+    uint32_t *en = rinc + 6 * k;
+    const uint32_t ta = en[0];
+    const int64_t t = ta >> 2;
+    const int a = (int)(ta & 3u);
+    uint32_t sl = 0;
+    for (int v = 0; v < 4; ++v) {
+        const int src = v == 0 ? a : (v - 1) + (v - 1 >= a ? 1 : 0);
+        en[v] = (uint32_t)tets[4 * t + src];
+        sl |= (uint32_t)tslot[16 * t + 4 * a + src] << (8 * v);
+    }
+    en[4] = (uint32_t)orig[t];
+    en[5] = sl;
+}
+
+// Element terms gathered per row: element stiffness V [lam g_a g_b^T + G (g_b g_a^T + (g_a.g_b) I)],
+// storage (V/(20 M))(1 + delta_ab) and conductivity (k/mu) V g_a.g_b.  One thread per
+// internal row and group of four consecutive slots (blockIdx.y): it sums, over the
+// elements containing the row's node in increasing element order (the node first in
+// each entry), the element's blocks of that row that fall in its slots, in registers,
+// and writes each of its entries once.  Lanes are consecutive rows of a slice, so the stores are coalesced.
+__global__ __launch_bounds__(WG) void k_assemble_rows(int64_t Npad, const int64_t *__restrict__ rinc_ptr, const uint32_t *__restrict__ rinc,
+                                const uint8_t *__restrict__ rowlen, const double *__restrict__ xyz,
                                 const double *__restrict__ E, const double *__restrict__ logk,
                                 const fg_params *__restrict__ gprm, const int32_t *__restrict__ sgrp,
-                                const int64_t *__restrict__ slice_ptr, const uint8_t *__restrict__ tslot, double *K,
-                                double *A22, double *Cm, int *bad)
+                                const int64_t *__restrict__ slice_ptr, double *__restrict__ K,
+                                double *__restrict__ A22, double *__restrict__ Cm, int *bad)
 {
-    int64_t t = t0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= t1) return;
-    const int32_t *nd = tets + 4 * t;
-    V3 g[4];
-    double V = tet_grads(xyz, nd, g);
-    if (!(V > 0)) {
-        *bad = 1;
-        return;
-    }
-    const int64_t e = orig[t];
-    const fg_params &prm = group_params(gprm, sgrp, nd[0]);
-    const double Ee = E[e], nu = prm.nu;
-    const double lam = Ee * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
-    const double G = Ee / (2.0 * (1.0 + nu));
-    const double kmu = exp(logk[e]) / prm.mu;
-    const double sm = V / (20.0 * prm.biot_M);
-    uint32_t sl[4];
-    for (int a = 0; a < 4; ++a) sl[a] = ((const uint32_t *)(tslot + 16 * t))[a];
-    for (int a = 0; a < 4; ++a) {
-        const int64_t row = nd[a];
-        const int64_t s = row / SLICE, l = row % SLICE;
-        const int64_t base = slice_ptr[s];
-        for (int b = 0; b < 4; ++b) {
-            const int j = (int)((sl[a] >> (8 * b)) & 0xffu);
-            const double gg = dt3(g[a], g[b]);
-            double *kb = K + 9 * base + (int64_t)9 * j * SLICE + l;
-            for (int r = 0; r < 3; ++r)
-                for (int c = 0; c < 3; ++c) {
-                    double v = lam * cmp(g[a], r) * cmp(g[b], c) + G * (cmp(g[a], c) * cmp(g[b], r) + (r == c ? gg : 0.0));
-                    kb[(int64_t)(3 * r + c) * SLICE] += V * v;
-                }
-            const double cab = kmu * V * gg;
-            const double sab = sm * (a == b ? 2.0 : 1.0);
-            const int64_t k = base + (int64_t)j * SLICE + l;
-            A22[k] += sab + prm.dt * cab;
-            Cm[k] += cab;
+    const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (row >= Npad) return;
+    const int j0 = 4 * (int)blockIdx.y, len = rowlen[row];
+    if (j0 >= len) return;
+    double acc[4][11];
+    for (int q = 0; q < 4; ++q)
+        for (int m = 0; m < 11; ++m) acc[q][m] = 0.0;
+    const int64_t k1 = rinc_ptr[row + 1];
+    for (int64_t k = rinc_ptr[row]; k < k1; ++k) {
+        const uint32_t *en = rinc + 6 * k;
+        const uint32_t sl = en[5];
+        bool hit = false;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) hit |= (unsigned)((int)((sl >> (8 * b)) & 0xffu) - j0) < 4u;
+        if (!hit) continue;
+        const int32_t nd[4] = {(int32_t)en[0], (int32_t)en[1], (int32_t)en[2], (int32_t)en[3]};
+        const int64_t e = en[4];
+        V3 g[4];
+        const double V = tet_grads(xyz, nd, g);
+        if (!(V > 0)) {
+            *bad = 1;
+            continue;
         }
+        const fg_params &prm = group_params(gprm, sgrp, nd[0]);
+        const double Ee = E[e], nu = prm.nu;
+        const double lam = Ee * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+        const double G = Ee / (2.0 * (1.0 + nu));
+        const double kmu = exp(logk[e]) / prm.mu;
+        const double sm = V / (20.0 * prm.biot_M);
+        const V3 ga = g[0];   // the row's node
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int jq = (int)((sl >> (8 * b)) & 0xffu) - j0;
+            if ((unsigned)jq >= 4u) continue;
+            const double gg = dt3(ga, g[b]);
+            double t[11];
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c)
+                    t[3 * r + c] = V * (lam * cmp(ga, r) * cmp(g[b], c) + G * (cmp(ga, c) * cmp(g[b], r) + (r == c ? gg : 0.0)));
+            const double cab = kmu * V * gg;
+            t[9] = sm * (b == 0 ? 2.0 : 1.0) + prm.dt * cab;
+            t[10] = cab;
+            for (int q = 0; q < 4; ++q)     // constant register indices: acc stays in registers
+                if (jq == q)
+                    for (int m = 0; m < 11; ++m) acc[q][m] += t[m];
+        }
+    }
+    const int64_t l = row % SLICE, base = slice_ptr[row / SLICE];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (j0 + q >= len) break;
+        const int64_t js = (int64_t)(j0 + q) * SLICE;
+        double *kb = K + 9 * (base + js) + l;
+        for (int m = 0; m < 9; ++m) kb[(int64_t)m * SLICE] = acc[q][m];
+        A22[base + js + l] = acc[q][9];
+        Cm[base + js + l] = acc[q][10];
     }
 }
 
@@ -1312,18 +1357,15 @@ void vdots(fg_system *S, int64_t n, int nd, const double *const *a, const double
 
 void assemble_all(fg_system *S, const double *E, const double *logk, hipStream_t st)
 {
-    const Plan &P = S->plan;
     hipMemsetAsync(S->K, 0, S->nblk * 9 * sizeof(double), st);
     hipMemsetAsync(S->A22, 0, S->nblk * sizeof(double), st);
     hipMemsetAsync(S->Cm, 0, S->nblk * sizeof(double), st);
     int *bad = (int *)S->red_counter + 1;
     hipMemsetAsync(bad, 0, sizeof(int), st);
-    for (size_t c = 0; c + 1 < P.colour_ptr.size(); ++c) {
-        const int64_t a = P.colour_ptr[c], b = P.colour_ptr[c + 1];
-        if (b > a)
-            LAUNCH(k_assemble_tets, (b - a + WG - 1) / WG, WG, st, a, b, S->tets, S->tet_orig, S->xyz, E, logk, S->gprm,
-                   S->slice_group, S->slice_ptr, S->tslot, S->K, S->A22, S->Cm, bad);
-    }
+    if (S->ne > 0)
+        LAUNCH(k_assemble_rows, dim3((unsigned)((S->Npad + WG - 1) / WG), (unsigned)((S->max_rowlen + 3) / 4)), WG, st,
+               S->Npad, S->rinc_ptr, S->rinc, S->rowlen, S->xyz, E, logk, S->gprm, S->slice_group, S->slice_ptr, S->K,
+               S->A22, S->Cm, bad);
     if (S->nf > 0) {
         LAUNCH(k_tri_geo, (S->nf + WG - 1) / WG, WG, st, S->nf, S->coh, S->xyz, S->tri_geo);
         LAUNCH(k_fault_flow, (S->nfr * S->fault_w + WG - 1) / WG, WG, st, S->nfr, S->fault_w, S->frows, S->fadj_ptr,
@@ -1340,9 +1382,11 @@ fg_status tet_slots(fg_system *S, hipStream_t st)
 {
     int *bad = (int *)S->red_counter + 1;
     hipMemsetAsync(bad, 0, sizeof(int), st);
-    if (S->ne > 0)
+    if (S->ne > 0) {
         LAUNCH(k_tet_slots, (S->ne + WG - 1) / WG, WG, st, S->ne, S->tets, S->slice_ptr, S->col, S->rowlen, S->tslot,
                bad);
+        LAUNCH(k_rinc_fill, (4 * S->ne + WG - 1) / WG, WG, st, 4 * S->ne, S->tets, S->tet_orig, S->tslot, S->rinc);
+    }
     int h = 0;
     hipMemcpyAsync(&h, bad, sizeof(int), hipMemcpyDeviceToHost, st);
     hipStreamSynchronize(st);
