@@ -86,6 +86,7 @@ __global__ __launch_bounds__(FIN) void k_mr_init_fin(const double *partials, int
     sc->rr[c] = tot[1];
     sc->bb[c] = tot[1];
     sc->tol2[c] = tol * tol * tot[1];
+    sc->soft2[c] = sc->overrun2 * sc->tol2[c];
     sc->iter[c] = 0;
     sc->status[c] = FG_OK;
     sc->done[c] = 0;
@@ -98,6 +99,7 @@ __global__ __launch_bounds__(FIN) void k_mr_init_fin(const double *partials, int
         sc->status[c] = FG_NOT_CONVERGED;
         sc->done[c] = 1;
     }
+    sc->ready[c] = sc->done[c];
 }
 
 // Q = K P for the columns [c0, c0 + CT) of one slice per wavefront, with the
@@ -408,13 +410,15 @@ __global__ __launch_bounds__(FIN) void k_mr_beta(const double *partials, int nrh
     if (!isfinite(tot[0]) || !isfinite(tot[1])) {
         sc->status[c] = FG_ERR_NAN;
         sc->done[c] = 1;
-    } else if (tot[1] <= sc->tol2[c]) {
+    } else if (tot[1] <= sc->soft2[c]) {
         sc->status[c] = FG_OK;
         sc->done[c] = 1;
+        sc->ready[c] = 1;
     } else if (sc->iter[c] >= sc->maxit) {
         sc->status[c] = FG_NOT_CONVERGED;
         sc->done[c] = 1;
     } else {
+        if (tot[1] <= sc->tol2[c]) sc->ready[c] = 1;
         sc->beta[c] = tot[0] / sc->rho[c];
         sc->rho[c] = tot[0];
     }
@@ -622,9 +626,35 @@ __global__ __launch_bounds__(WG) void k_mr_resume(int64_t n, int nrhs, int lg, c
     block_partials_cols<2>(v, nrhs, partials, stride);
 }
 
+// Before a residual replacement, a column still iterating (done = 0) holds
+// p_{k+1} = z_{k+1} + beta_k p_k and rho_{k+1}; subtracting its recursive z_{k+1}
+// leaves beta_k p_k, so that the resume's p = z + (rho_new / rho_{k+1}) p gives
+// z + (rho_new / rho_k) p_k, as for a column that stopped at iteration k.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_mr_strip_z(int64_t n, int nrhs, int lg, const T *__restrict__ dinv,
+                                                   const T *__restrict__ r, T *__restrict__ p, const MrScalars *sc)
+{
+    const int c = elem_col(nrhs);
+    if (sc->done[c]) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] -= dinv[i >> lg] * r[i];
+}
+
+// The same with the block-Jacobi z stored by the last update.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_mr_strip_z_bj(int64_t n, int nrhs, const T *__restrict__ z, T *__restrict__ p,
+                                                      const MrScalars *sc)
+{
+    const int c = elem_col(nrhs);
+    if (sc->done[c]) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] -= z[i];
+}
+
 // ... then, per column, beta against the rho the column stopped with (its last
-// direction p is kept), the new rho and stop threshold next2[c] (squared; a
-// column with next2[c] <= 0 is finished and stays done) ...
+// direction p is kept; a column still iterating at the replacement was brought to
+// that state by k_mr_strip_z), the new rho and stop thresholds from next2[c]
+// (squared; a column with next2[c] <= 0 is finished and stays done) ...
 __global__ __launch_bounds__(FIN) void k_mr_resume_fin(const double *partials, int nrhs, int64_t stride, int64_t nparts,
                                                        MrScalars *sc, const double *next2)
 {
@@ -635,6 +665,7 @@ __global__ __launch_bounds__(FIN) void k_mr_resume_fin(const double *partials, i
     sc->upd[c] = 0;
     sc->status[c] = FG_OK;
     sc->done[c] = 1;
+    sc->ready[c] = 1;
     if (!(next2[c] > 0.0)) return;
     const double beta = tot[0] / sc->rho[c];
     sc->rr[c] = tot[1];
@@ -646,7 +677,9 @@ __global__ __launch_bounds__(FIN) void k_mr_resume_fin(const double *partials, i
         sc->beta[c] = beta;
         sc->rho[c] = tot[0];
         sc->tol2[c] = next2[c];
+        sc->soft2[c] = sc->overrun2 * next2[c];
         sc->done[c] = 0;
+        sc->ready[c] = 0;
     }
 }
 
@@ -832,11 +865,13 @@ void drop_mr_graphs(fg_system *S)
 
 // Start of a block CG on the interleaved right-hand sides already in S->mr (FP64)
 // or S->mfr (FP32): x = 0, p = z, per-column rho, thresholds and flags.
-static fg_status mr_cg_init(fg_system *S, int nrhs, bool f32, double tol, int64_t maxit, hipStream_t st)
+static fg_status mr_cg_init(fg_system *S, int nrhs, bool f32, double tol, int64_t maxit, double overrun2,
+                            hipStream_t st)
 {
     const int64_t n = 3 * S->Npad * nrhs;
     MrScalars init{};
     init.maxit = maxit;
+    init.overrun2 = overrun2;
     init.nrhs = nrhs;
     hipMemcpyAsync(S->msc, &init, sizeof init, hipMemcpyHostToDevice, st);
     const int64_t ge = grid_cols(n);
@@ -879,7 +914,7 @@ static fg_status mr_cg_loop(fg_system *S, int nrhs, bool f32, int check_every, h
         e = check_hip("block cg poll");
         if (e) return e;
         bool all = true;
-        for (int c = 0; c < nrhs; ++c) all = all && S->msc_host->done[c];
+        for (int c = 0; c < nrhs; ++c) all = all && (S->msc_host->done[c] || S->msc_host->ready[c]);
         if (all) break;
         if (!S->use_graphs) {
             if (f32)
@@ -921,7 +956,7 @@ static fg_status mr_cg_loop(fg_system *S, int nrhs, bool f32, int check_every, h
 
 static fg_status mr_cg(fg_system *S, int nrhs, bool f32, double tol, int64_t maxit, int check_every, hipStream_t st)
 {
-    fg_status e = mr_cg_init(S, nrhs, f32, tol, maxit, st);
+    fg_status e = mr_cg_init(S, nrhs, f32, tol, maxit, 1.0, st);
     return e ? e : mr_cg_loop(S, nrhs, f32, check_every, st);
 }
 
@@ -940,6 +975,13 @@ static void mr_colnorms(fg_system *S, int nrhs, const double *a, double *host, h
 // (or reached 0.5 tol); then every column's FP32 correction is added to the FP64
 // x, the FP64 residual b - K x replaces the FP32 one, and the columns above tol
 // go on from their last direction with the next threshold max(delta rel, 0.5 tol).
+// Extra reduction (squared) a column may make past its replacement threshold
+// while it waits for the others: a factor 10 in norm.  The recursive residual must
+// stay well above its rounding gap to the true one (about the FP32 unit roundoff
+// times the residual at the last replacement, times a growth factor): a column
+// let run 1e3 past a 1e-2 threshold has diverged after the replacement.
+constexpr double MR_OVERRUN2 = 1e-2;
+
 static fg_status mr_reliable(fg_system *S, int nrhs, double tol, int64_t maxit, int check_every, double delta,
                              int64_t *iters, int64_t *updates, double *worst_rel, fg_status *worst, hipStream_t st)
 {
@@ -960,7 +1002,7 @@ static fg_status mr_reliable(fg_system *S, int nrhs, double tol, int64_t maxit, 
     hipMemcpyAsync(S->mred, scale.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st);
     hipLaunchKernelGGL(k_mr_scale_to_f32, dim3(ge), dim3(WG), 0, st, n, nrhs, S->mred, S->mb, S->mfr);
     hipMemsetAsync(S->mx64, 0, n * sizeof(double), st);
-    fg_status e = mr_cg_init(S, nrhs, true, delta, maxit, st);
+    fg_status e = mr_cg_init(S, nrhs, true, delta, maxit, MR_OVERRUN2, st);
     if (e) return e;
     *iters = 0;
     *updates = 0;
@@ -983,6 +1025,13 @@ static fg_status mr_reliable(fg_system *S, int nrhs, double tol, int64_t maxit, 
             }
         }
         std::vector<int64_t> it(h.iter, h.iter + nrhs);
+        // columns still iterating: back to the state of a column that stopped
+        if (S->k_precond)
+            hipLaunchKernelGGL((k_mr_strip_z_bj<float>), dim3(ge), dim3(WG), 0, st, n, nrhs, (const float *)S->mfz,
+                               S->mfp, S->msc);
+        else
+            hipLaunchKernelGGL((k_mr_strip_z<float>), dim3(ge), dim3(WG), 0, st, n, nrhs, lg, S->dinvK32, S->mfr,
+                               S->mfp, S->msc);
         // fold the FP32 corrections into x and replace the residuals by FP64 ones
         hipMemcpyAsync(S->mred, fold.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, st);
         hipLaunchKernelGGL(k_mr_add_f32, dim3(ge), dim3(WG), 0, st, n, nrhs, S->mred, S->mfx, S->mx64);

@@ -86,6 +86,13 @@ struct MrScalars {
     int64_t iter[MR_MAX];
     int32_t done[MR_MAX], status[MR_MAX];
     int32_t upd[MR_MAX];  // column advanced by this iteration's alpha (x += alpha p is still due)
+    // Block CG with residual replacement: a column is ready for the next replacement
+    // once r.r <= tol2 and keeps iterating (instead of idling while the block
+    // product still costs the same) until r.r <= soft2 = overrun2 tol2.
+    // overrun2 = 1 (plain block CG): ready and done coincide.
+    double soft2[MR_MAX];
+    int32_t ready[MR_MAX];
+    double overrun2;
     int64_t maxit;
     int32_t nrhs, pad;
 };
