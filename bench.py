@@ -381,7 +381,7 @@ def extra_adjoint(ctx, log):
     res = {}
     for name, prec, kp, et in (("f64", fg.FG_F64, 0, 0), ("mixed", fg.FG_MIXED, 0, 0),
                                ("f64_block_jacobi", fg.FG_F64, 1, 0), ("mixed_block_jacobi", fg.FG_MIXED, 1, 0),
-                               ("f64_block_jacobi_exact", fg.FG_F64, 1, 1)):
+                               ("f64_block_jacobi_exact", fg.FG_F64, 1, 1), ("f64_amg", fg.FG_F64, 3, 0)):
         # corrections solved loosely (outer 0.05, inner 1e-3); the defect tolerance sets the accuracy;
         # exact: the corrections solve with K_t + N^T (BiCGStab) instead of the symmetric tangent
         S.tune("k_precond", kp)
@@ -399,7 +399,7 @@ def extra_adjoint(ctx, log):
     bj = {name: {"s": res[name][0], "defect_iters": res[name][1].newton_iters, "k_iters": res[name][1].inner_k_iters,
                  "status": res[name][1].status,
                  "vs_f64_grad_rel_l2": (torch.linalg.norm(res[name][2] - g64) / torch.linalg.norm(g64)).item()}
-          for name in ("f64_block_jacobi", "mixed_block_jacobi", "f64_block_jacobi_exact")}
+          for name in ("f64_block_jacobi", "mixed_block_jacobi", "f64_block_jacobi_exact", "f64_amg")}
     # the exact tangent K_t + N at the converged state (slip points present): BiCGStab to 1e-8
     # on b = dJ/dU, against CG on the symmetric tangent
     S.cohesive_update(U, die0, t0, write_tangent=True)
@@ -414,17 +414,18 @@ def extra_adjoint(ctx, log):
         log(f"exact tangent {name}: {t_ex:.3f}s iters {i_ex.iters} status {i_ex.status}")
     S.tune("k_precond", 0)
     xb = ex["bicgstab_block_jacobi"][2]
-    # the forward step again, block-Jacobi K solves, with the symmetric and with the exact tangent
+    # the forward step again, block-Jacobi K solves with the symmetric and with the exact tangent,
+    # and AMG-preconditioned K solves (symmetric tangent; hierarchy values rebuilt at every change of K)
     fwd = {}
-    S.tune("k_precond", 1)
-    for et in (0, 1):
+    for kp, et in ((1, 0), (1, 1), (3, 0)):
+        S.tune("k_precond", kp)
         S.tune("exact_tangent", et)
         U2, P2, die2 = d(np.zeros(3 * S.N)), d(np.zeros(S.N)), d(np.zeros(2 * S.nq))
         t_f, (_, flag2, finfo2) = _timed(lambda: S.step(U2, P2, die2, t0, d(inst.load), d(inst.source),
                                                          newton_tol=1e-8, newton_max_iter=60, inner_k=inner,
                                                          inner_p=inner, outer_tol=1e-2))
-        name = "exact" if et else "symmetric"
-        log(f"forward step, block Jacobi, {name} tangent: {t_f:.2f}s newton {finfo2.newton_iters} cuts "
+        name = "amg_symmetric" if kp == 3 else "exact" if et else "symmetric"
+        log(f"forward step, {'AMG' if kp == 3 else 'block Jacobi'}, {name} tangent: {t_f:.2f}s newton {finfo2.newton_iters} cuts "
             f"{finfo2.step_cuts} K iters {finfo2.inner_k_iters} status {finfo2.status}")
         fwd[name] = {"s": t_f, "newton": finfo2.newton_iters, "step_cuts": finfo2.step_cuts,
                      "k_iters": finfo2.inner_k_iters, "status": finfo2.status,
@@ -519,8 +520,9 @@ def extra_steps(ctx, log, nsteps=20):
 
 def extra_fd64(ctx, log, count=20, eps=1e-6):
     """Central differences of the 64^3 injection step's objective (squared fault slip plus
-    squared uplift at 32 seeded top nodes) along `count` seeded unit directions in
-    (ln k, ln E), step eps, against the adjoint gradient in FP64 and in mixed precision.
+    squared uplift at 32 seeded top nodes) along `count` seeded random directions in
+    (ln k, ln E) with standard normal components (every parameter moves by about eps),
+    step eps, against the adjoint gradient in FP64 and in mixed precision.
     Every forward is a step from rest with block-Jacobi K solves, the exact interface
     tangent (quadratic Newton) and a tight Newton tolerance."""
     import numpy as np
@@ -572,7 +574,7 @@ def extra_fd64(ctx, log, count=20, eps=1e-6):
     ne = inst.E.size
     rows = []
     t = time.perf_counter()
-    for j, dvec in enumerate(I.fd_directions(2 * ne, count=count)):
+    for j, dvec in enumerate(I.fd_directions(2 * ne, count=count, unit=False)):
         dlk, dlE = dvec[:ne], dvec[ne:]
         Jpm = []
         for sgn in (1.0, -1.0):
@@ -587,7 +589,7 @@ def extra_fd64(ctx, log, count=20, eps=1e-6):
     S.tune("k_precond", 0)
     S.tune("exact_tangent", 0)
     return {"workload": f"cube64_dip60_hetero one implicit step from rest, {2 * ne} parameters (ln k, ln E); "
-                        f"{count} seeded unit directions, central differences with step {eps}; forwards with "
+                        f"{count} seeded random directions (standard normal components), central differences with step {eps}; forwards with "
                         f"block-Jacobi K solves, exact interface tangent, Newton 1e-12; adjoint defect 1e-11",
             "J": J0.item(), "base_forward_s": tf, "adjoint_f64_s": grads["f64"][2], "adjoint_mixed_s": grads["mixed"][2],
             "max_rel_f64": max(r["rel_f64"] for r in rows), "max_rel_mixed": max(r["rel_mixed"] for r in rows),

@@ -44,6 +44,7 @@ struct AmgLevel {
     int64_t nnzb = 0, npz = 0, nwz = 0, nrz = 0;
     int64_t *arow = nullptr;           // block CSR of A (level 0: K's slots, internal order)
     int32_t *acol = nullptr;
+    int32_t *arid = nullptr;           // coarse levels: row of each block
     double *aval = nullptr;            // [nnzb bs bs]
     int32_t *agg = nullptr;            // [nn] aggregate of each node (-1: padding row)
     double *q = nullptr;               // [nn bs 6] tentative prolongator rows
@@ -403,38 +404,46 @@ __global__ void k_amg_ap(int64_t nn, const int64_t *__restrict__ arow, const int
     }
 }
 
-// A_c entry (I, J) = sum_{(i, e) in P^T row I} P_e^T W(i, J); an empty coarse row
-// gets a unit diagonal.
+// A_c entry (I, J) = sum_{(i, e) in P^T row I} P_e^T W(i, J): one thread per coarse block.
 template <int BS>
-__global__ void k_amg_rap(int64_t nc, const int64_t *__restrict__ rrow, const int32_t *__restrict__ rnode,
+__global__ void k_amg_rap(int64_t nnzc, const int32_t *__restrict__ crid, const int32_t *__restrict__ ccol,
+                          const int64_t *__restrict__ rrow, const int32_t *__restrict__ rnode,
                           const int64_t *__restrict__ rent, const double *__restrict__ pval,
                           const int64_t *__restrict__ wrow, const int32_t *__restrict__ wcol,
-                          const double *__restrict__ wval, const int64_t *__restrict__ crow,
-                          const int32_t *__restrict__ ccol, double *cval)
+                          const double *__restrict__ wval, double *cval)
+{
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= nnzc) return;
+    const int32_t I = crid[e], J = ccol[e];
+    double acc[36];
+    for (int k = 0; k < 36; ++k) acc[k] = 0;
+    for (int64_t t = rrow[I]; t < rrow[I + 1]; ++t) {
+        const int32_t i = rnode[t];
+        const int64_t f = amg_find(wcol, wrow[i], wrow[i + 1], J);
+        if (f < 0) continue;
+        const double *p = pval + BS * 6 * rent[t], *wv = wval + BS * 6 * f;
+        for (int k = 0; k < BS; ++k)
+            for (int r = 0; r < 6; ++r) {
+                const double pv = p[6 * k + r];
+                for (int c = 0; c < 6; ++c) acc[6 * r + c] += pv * wv[6 * k + c];
+            }
+    }
+    for (int k = 0; k < 36; ++k) cval[36 * e + k] = acc[k];
+}
+
+// A coarse DOF whose row of A_c is empty (its prolongator column vanished) gets a
+// unit diagonal, so the coarse matrix stays invertible.
+__global__ void k_amg_unit_empty(int64_t nc, const int64_t *__restrict__ crow, const int32_t *__restrict__ ccol,
+                                 double *cval)
 {
     const int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (I >= nc) return;
     double rs[6] = {0, 0, 0, 0, 0, 0};
     int64_t dslot = -1;
     for (int64_t e = crow[I]; e < crow[I + 1]; ++e) {
-        const int32_t J = ccol[e];
-        if (J == I) dslot = e;
-        double acc[36];
-        for (int k = 0; k < 36; ++k) acc[k] = 0;
-        for (int64_t t = rrow[I]; t < rrow[I + 1]; ++t) {
-            const int32_t i = rnode[t];
-            const int64_t f = amg_find(wcol, wrow[i], wrow[i + 1], J);
-            if (f < 0) continue;
-            const double *p = pval + BS * 6 * rent[t], *wv = wval + BS * 6 * f;
-            for (int k = 0; k < BS; ++k)
-                for (int r = 0; r < 6; ++r) {
-                    const double pv = p[6 * k + r];
-                    for (int c = 0; c < 6; ++c) acc[6 * r + c] += pv * wv[6 * k + c];
-                }
-        }
-        for (int k = 0; k < 36; ++k) cval[36 * e + k] = acc[k];
+        if (ccol[e] == I) dslot = e;
         for (int r = 0; r < 6; ++r)
-            for (int c = 0; c < 6; ++c) rs[r] += fabs(acc[6 * r + c]);
+            for (int c = 0; c < 6; ++c) rs[r] += fabs(cval[36 * e + 6 * r + c]);
     }
     if (dslot >= 0)
         for (int r = 0; r < 6; ++r)
@@ -472,23 +481,31 @@ __global__ void k_amg_dapply(int64_t nn, const double *__restrict__ dinv, const 
     out[g] = sc * s;
 }
 
-// bc(I) = sum_{(i, e)} P_e^T r_i
+// bc(I) = sum_{(i, e)} P_e^T r_i: one wavefront per aggregate, its lanes taking
+// every 64th entry of the aggregate's P^T list, then a fixed-order lane reduction.
 template <int BS>
-__global__ void k_amg_restrict(int64_t nc, const int64_t *__restrict__ rrow, const int32_t *__restrict__ rnode,
-                               const int64_t *__restrict__ rent, const double *__restrict__ pval,
-                               const double *__restrict__ r, double *bc)
+__global__ __launch_bounds__(WG) void k_amg_restrict(int64_t nc, const int64_t *__restrict__ rrow,
+                                                     const int32_t *__restrict__ rnode, const int64_t *__restrict__ rent,
+                                                     const double *__restrict__ pval, const double *__restrict__ r,
+                                                     double *bc)
 {
-    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (g >= nc * 6) return;
-    const int64_t I = g / 6;
-    const int c = (int)(g - I * 6);
-    double s = 0;
-    for (int64_t t = rrow[I]; t < rrow[I + 1]; ++t) {
+    const int64_t I = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;   // uniform per wavefront
+    const int lane = threadIdx.x & 63;
+    if (I >= nc) return;
+    double s[6] = {0, 0, 0, 0, 0, 0};
+    const int64_t t1 = rrow[I + 1];
+    for (int64_t t = rrow[I] + lane; t < t1; t += 64) {
         const double *p = pval + BS * 6 * rent[t];
         const double *ri = r + (int64_t)BS * rnode[t];
-        for (int k = 0; k < BS; ++k) s += p[6 * k + c] * ri[k];
+        for (int k = 0; k < BS; ++k) {
+            const double rk = ri[k];
+            for (int c = 0; c < 6; ++c) s[c] += p[6 * k + c] * rk;
+        }
     }
-    bc[g] = s;
+    for (int c = 0; c < 6; ++c)
+        for (int o = 32; o > 0; o >>= 1) s[c] += __shfl_down(s[c], o, 64);
+    if (lane == 0)
+        for (int c = 0; c < 6; ++c) bc[6 * I + c] = s[c];
 }
 
 // x_i += sum_{e in P row i} P_e xc(agg)
@@ -509,20 +526,24 @@ __global__ void k_amg_prolong_add(int64_t nn, const int64_t *__restrict__ prow, 
     x[g] += s;
 }
 
-__global__ void k_amg_dense(int64_t n, const double *__restrict__ Ainv, const double *__restrict__ x, double *y)
+// y = Ainv x for the coarsest level: one wavefront per row.
+__global__ __launch_bounds__(WG) void k_amg_dense(int64_t n, const double *__restrict__ Ainv,
+                                                  const double *__restrict__ x, double *y)
 {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
     if (i >= n) return;
     double s = 0;
-    for (int64_t k = 0; k < n; ++k) s += Ainv[i * n + k] * x[k];
-    y[i] = s;
+    for (int64_t k = lane; k < n; k += 64) s += Ainv[i * n + k] * x[k];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if (lane == 0) y[i] = s;
 }
 
 inline int64_t nb(int64_t n) { return std::max<int64_t>((n + WG - 1) / WG, 1); }
 
 void free_level(AmgLevel &L)
 {
-    void *p[] = {L.arow, L.acol, L.aval, L.agg, L.q, L.prow, L.pcol, L.pval, L.wrow, L.wcol, L.wval,
+    void *p[] = {L.arow, L.acol, L.arid, L.aval, L.agg, L.q, L.prow, L.pcol, L.pval, L.wrow, L.wcol, L.wval,
                  L.rrow, L.rnode, L.rent, L.dinv, L.x, L.b, L.r, L.e, L.t, L.d, L.s, L.w};
     for (void *v : p)
         if (v) hipFree(v);
@@ -608,8 +629,12 @@ static fg_status amg_plan(fg_system *S)
             std::vector<int32_t> acol;
             to_csr(A_pat, arow, acol);
             L.nnzb = arow.back();
+            std::vector<int32_t> arid((size_t)L.nnzb);
+            for (int64_t i = 0; i < nn; ++i)
+                for (int64_t o = arow[i]; o < arow[i + 1]; ++o) arid[o] = (int32_t)i;
             AMG_CK(up(&L.arow, arow));
             AMG_CK(up(&L.acol, acol));
+            AMG_CK(up(&L.arid, arid));
         }
         L.nn = rows;
         AMG_CK(dmal(&L.aval, L.nnzb * bs * bs));
@@ -801,16 +826,17 @@ static fg_status amg_numeric(fg_system *S, hipStream_t st)
                    L.pcol, w, L.pval);
             LAUNCH((k_amg_ap<3>), nb(L.nn), WG, st, L.nn, L.arow, L.acol, L.aval, L.prow, L.pcol, L.pval, L.wrow,
                    L.wcol, L.wval);
-            LAUNCH((k_amg_rap<3>), nb(L.nc), WG, st, L.nc, L.rrow, L.rnode, L.rent, L.pval, L.wrow, L.wcol, L.wval,
-                   C.arow, C.acol, C.aval);
+            LAUNCH((k_amg_rap<3>), nb(C.nnzb), WG, st, C.nnzb, C.arid, C.acol, L.rrow, L.rnode, L.rent, L.pval,
+                   L.wrow, L.wcol, L.wval, C.aval);
         } else {
             LAUNCH((k_amg_prolong<6>), nb(L.nn), WG, st, L.nn, L.arow, L.acol, L.aval, L.agg, L.q, L.dinv, L.prow,
                    L.pcol, w, L.pval);
             LAUNCH((k_amg_ap<6>), nb(L.nn), WG, st, L.nn, L.arow, L.acol, L.aval, L.prow, L.pcol, L.pval, L.wrow,
                    L.wcol, L.wval);
-            LAUNCH((k_amg_rap<6>), nb(L.nc), WG, st, L.nc, L.rrow, L.rnode, L.rent, L.pval, L.wrow, L.wcol, L.wval,
-                   C.arow, C.acol, C.aval);
+            LAUNCH((k_amg_rap<6>), nb(C.nnzb), WG, st, C.nnzb, C.arid, C.acol, L.rrow, L.rnode, L.rent, L.pval,
+                   L.wrow, L.wcol, L.wval, C.aval);
         }
+        LAUNCH(k_amg_unit_empty, nb(L.nc), WG, st, L.nc, C.arow, C.acol, C.aval);
         e = check_hip("AMG prolongator and coarse operator");
         if (e) return e;
     }
@@ -921,7 +947,7 @@ static void amg_vcycle(fg_system *S, int l, const double *b, double *x, hipStrea
     AmgLevel &L = G->L[l];
     const int64_t n = L.nn * L.bs;
     if (l == G->nlev - 1) {
-        LAUNCH(k_amg_dense, nb(n), WG, st, n, G->cinv, b, x);
+        LAUNCH(k_amg_dense, nb(64 * n), WG, st, n, G->cinv, b, x);
         return;
     }
     AmgLevel &C = G->L[l + 1];
@@ -935,9 +961,9 @@ static void amg_vcycle(fg_system *S, int l, const double *b, double *x, hipStrea
     amul(x, L.r);
     vaxpby(n, 1.0, b, -1.0, L.r, st);                 // r = b - A x
     if (L.bs == 3)
-        LAUNCH((k_amg_restrict<3>), nb(6 * L.nc), WG, st, L.nc, L.rrow, L.rnode, L.rent, L.pval, L.r, C.b);
+        LAUNCH((k_amg_restrict<3>), nb(64 * L.nc), WG, st, L.nc, L.rrow, L.rnode, L.rent, L.pval, L.r, C.b);
     else
-        LAUNCH((k_amg_restrict<6>), nb(6 * L.nc), WG, st, L.nc, L.rrow, L.rnode, L.rent, L.pval, L.r, C.b);
+        LAUNCH((k_amg_restrict<6>), nb(64 * L.nc), WG, st, L.nc, L.rrow, L.rnode, L.rent, L.pval, L.r, C.b);
     amg_vcycle(S, l + 1, C.b, C.x, st);
     if (L.bs == 3)
         LAUNCH((k_amg_prolong_add<3>), nb(n), WG, st, L.nn, L.prow, L.pcol, L.pval, C.x, x);

@@ -305,10 +305,12 @@ def uplift_nodes(inst: Instance, count: int = 32, seed: int = 0) -> np.ndarray:
     return np.sort(rng(seed, STREAM_UPLIFT).choice(top, size=count, replace=False)).astype(np.int32)
 
 
-def fd_directions(n_params: int, count: int = 20, seed: int = 0) -> np.ndarray:
-    """Unit-norm random directions for finite-difference gradient checks."""
+def fd_directions(n_params: int, count: int = 20, seed: int = 0, unit: bool = True) -> np.ndarray:
+    """Random directions for finite-difference gradient checks: independent standard
+    normal components, normalised to unit length unless unit is False (then a step h
+    moves every parameter by about h)."""
     d = rng(seed, STREAM_FD).standard_normal((count, n_params))
-    return d / np.linalg.norm(d, axis=1, keepdims=True)
+    return d / np.linalg.norm(d, axis=1, keepdims=True) if unit else d
 
 
 def injection_scenarios(inst: Instance, count: int = 32, seed: int = 0):

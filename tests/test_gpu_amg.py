@@ -57,3 +57,39 @@ def test_amg_pcg_matches_oracle(n, dip, slip):
     assert relerr(x, xo) < 1e-9
     assert np.linalg.norm(b - P.spmv(O.K_TANGENT, x)) <= 1e-11 * np.linalg.norm(b)
     assert 4 * info.iters < itb
+
+
+@pytest.mark.parametrize("cfg", ["cube8", "slip4"])
+def test_step_with_amg_reaches_the_same_state(cfg):
+    """A full implicit step (Newton, partitioned CG) whose FP64 K solves are
+    preconditioned by the AMG V-cycle ends in the oracle's converged state; the
+    hierarchy's values are rebuilt at every change of the tangent."""
+    from oracle import oracle as O
+    from paper_2410_17133_amd import fg
+    import dataclasses
+    if cfg == "cube8":
+        inst = I.make_instance(I.cube_config(8))
+    else:                                              # a higher injection rate: slip points in the step
+        inst = I.make_instance(dataclasses.replace(I.cube_config(4), Q=4e-3))
+    print(f"[case] AMG step {cfg}", flush=True)
+    ctx = fg.Context(0)
+    S = fg.System.from_instance(ctx, inst)
+    S.assemble(inst.params, inst.E, inst.logk)
+    P = O.Problem(inst)
+    N, nq = S.N, S.nq
+    Uo, Po, dieo = np.zeros(3 * N), np.zeros(N), np.zeros((nq, 2))
+    _, flag_o, _, st = P.step(Uo, Po, dieo, tol_newton=1e-11, max_newton=60, tol_outer=1e-12, tol_inner=1e-13)
+    assert st == 0
+    S.tune("k_precond", 3)
+    try:
+        U, Pp, die = dev(np.zeros(3 * N)), dev(np.zeros(N)), dev(np.zeros(2 * nq))
+        trac, flag, info = S.step(U, Pp, die, dev(inst.t0.reshape(-1)), dev(inst.load), dev(inst.source),
+                                  newton_tol=1e-11, newton_max_iter=60, inner_k=fg.opts(tol=1e-13),
+                                  inner_p=fg.opts(tol=1e-13), outer_tol=1e-12)
+    finally:
+        S.tune("k_precond", 0)
+    eu, ep = relerr(U.cpu().numpy(), Uo), relerr(Pp.cpu().numpy(), Po)
+    print(f"[amg step] {cfg}: newton {info.newton_iters}, K iterations {info.inner_k_iters}, slip points "
+          f"{int((flag_o == 1).sum())}; rel err U {eu:.1e} P {ep:.1e}", flush=True)
+    assert info.status == 0
+    assert eu < 1e-9 and ep < 1e-9
