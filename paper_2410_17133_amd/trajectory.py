@@ -32,10 +32,11 @@ def run(S, U, P, die, t0, F_u, f_p, steps: int, **step_kw):
 
 
 def gradient(S, ck, t0, logk, grad_y, inner_k=None, inner_p=None, outer_tol=1e-12, defect_tol=1e-12,
-             max_defect_iters=1000):
+             max_defect_iters=1000, log=None):
     """dJ/dE and dJ/dln k (per tetrahedron) of J = sum_n j_n(U_n, P_n) over the
     checkpointed loop.  grad_y(n, U, P) -> (dj/dU, dj/dP) as CUDA float64 tensors
-    (n counted from 0).  Returns (dJ_dE, dJ_dlogk, per-step adjoint infos).
+    (n counted from 0).  Returns (dJ_dE, dJ_dlogk, per-step adjoint infos); log(str),
+    if given, receives one line per step of the sweep.
     Every step of the sweep is one fg_adjoint_loop_step call; this function only
     allocates its buffers and passes them along."""
     import torch
@@ -53,6 +54,9 @@ def gradient(S, ck, t0, logk, grad_y, inner_k=None, inner_p=None, outer_tol=1e-1
         info = S.adjoint_loop_step(U, P, die_prev, t0, logk, gu.contiguous(), gp.contiguous(), lp_next, a, dE, dk,
                                    lp, inner_k=inner_k, inner_p=inner_p, outer_tol=outer_tol, defect_tol=defect_tol,
                                    max_defect_iters=max_defect_iters)
+        if log:
+            log(f"[sweep] step {n}: status {info.status}, defect iterations {info.newton_iters}, outer "
+                f"{info.outer_iters}, K iterations {info.inner_k_iters}")
         if info.status != fg.FG_OK:
             raise fg.FgError(info.status, f"the adjoint of step {n} did not converge within {max_defect_iters} "
                                           "defect iterations")

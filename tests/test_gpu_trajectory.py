@@ -33,8 +33,9 @@ def instance():
 
 
 def tight(fg, newton_tol=1e-13):
-    return dict(newton_tol=newton_tol, newton_max_iter=80, inner_k=fg.opts(tol=1e-14), inner_p=fg.opts(tol=1e-14),
-                outer_tol=1e-13)
+    # iteration caps about 100 times what these solves take (a stalled solve ends with an error)
+    return dict(newton_tol=newton_tol, newton_max_iter=80, inner_k=fg.opts(tol=1e-14, max_iter=50000),
+                inner_p=fg.opts(tol=1e-14, max_iter=50000), outer_tol=1e-13)
 
 
 def objective(inst, uplift):
@@ -103,10 +104,14 @@ def test_loop_gradient_matches_oracle_and_differences(loop):
     uplift = I.uplift_nodes(inst, 8)
     jg = objective(inst, uplift)
     dE_o, dk_o = P.trajectory_gradient(ck_o, lambda n, U, Pp: (jg(U)[1], np.zeros(P.N)))
+    print("[loop gradient] oracle reverse sweep done", flush=True)
     logk = dev(inst.logk)
+    # iteration caps about 100 times the counts these solves take, so that a solve that
+    # stalls at its floor ends with an error instead of running a million iterations
     dE, dk, infos = T.gradient(S, ck, t0, logk, lambda n, U, Pp: (dev(jg(host(U))[1]), torch.zeros_like(Pp)),
-                               inner_k=fg.opts(tol=1e-14), inner_p=fg.opts(tol=1e-14), outer_tol=1e-13,
-                               defect_tol=1e-12)
+                               inner_k=fg.opts(tol=1e-14, max_iter=50000), inner_p=fg.opts(tol=1e-14, max_iter=50000),
+                               outer_tol=1e-13, defect_tol=1e-12, max_defect_iters=100,
+                               log=lambda s: print(s, flush=True))
     print(f"[loop gradient] dE {rel(host(dE), dE_o):.1e} dlnk {rel(host(dk), dk_o):.1e}; defect iterations "
           f"{[i.newton_iters for i in infos]}", flush=True)
     assert rel(host(dE), dE_o) < 1e-7 and rel(host(dk), dk_o) < 1e-7
@@ -121,6 +126,7 @@ def test_loop_gradient_matches_oracle_and_differences(loop):
         # 1e-12: the perturbed loops' Newton floors sit just above 1e-13; 1e-12 in J is
         # 1e-7 of the difference quotient at this step
         ckx, _ = T.run(S, U, Pp, die, t0, dev(np.zeros(3 * S.N)), dev(inst.source), 4, **tight(fg, 1e-12))
+        print("[loop gradient] perturbed forward loop done", flush=True)
         return sum(jg(host(c[0]))[0] for c in ckx)
     eps = 1e-5
     fd = (J(eps * d) - J(-eps * d)) / (2 * eps)
@@ -137,6 +143,7 @@ def test_autograd_loop_gradient_equals_reverse_sweep(loop):
     uplift = I.uplift_nodes(inst, 8)
     jg = objective(inst, uplift)
     dE_o, dk_o = P.trajectory_gradient(ck_o, lambda n, U, Pp: (jg(U)[1], np.zeros(P.N)))
+    print("[autograd loop] oracle reverse sweep done", flush=True)
     m = inst.mesh
     X = m.xyz[m.coh[0, 3:]]
     nrm = np.cross(X[1] - X[0], X[2] - X[0])
@@ -149,6 +156,7 @@ def test_autograd_loop_gradient_equals_reverse_sweep(loop):
     pairs = torch.as_tensor(m.pairs.astype(np.int64)).cuda()
     up = torch.as_tensor(uplift.astype(np.int64)).cuda()
     J = sum(fault_slip_uplift_objective(U_all[n], pairs, dev(nrm / np.linalg.norm(nrm)), up) for n in range(4))
+    print("[autograd loop] forward loop done", flush=True)
     J.backward()
     print(f"[autograd loop] dE {rel(host(E.grad), dE_o):.1e} dlnk {rel(host(logk.grad), dk_o):.1e}", flush=True)
     assert rel(host(E.grad), dE_o) < 1e-7 and rel(host(logk.grad), dk_o) < 1e-7
