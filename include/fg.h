@@ -51,7 +51,7 @@ typedef int fg_status;
 #define FG_NOT_CONVERGED 1   /* result valid, tolerance not reached within max_iter */
 #define FG_ERR_ARG (-1)      /* bad argument: null pointer, size mismatch, malformed mesh */
 #define FG_ERR_OOM (-2)      /* device or host allocation failed */
-#define FG_ERR_BREAKDOWN (-3) /* CG breakdown: p.Ap <= 0 (matrix not SPD) */
+#define FG_ERR_BREAKDOWN (-3) /* CG breakdown: p.Ap <= 0 (matrix not SPD), or a singular preconditioner */
 #define FG_ERR_NAN (-4)      /* NaN or Inf met in a residual or a CG scalar */
 #define FG_ERR_HIP (-5)      /* HIP runtime error (launch, copy) */
 #define FG_ERR_STATE (-6)    /* call out of order (e.g. solve before fg_assemble) */

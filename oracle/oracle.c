@@ -401,9 +401,14 @@ static void csr_eliminate(or_csr *A, const uint8_t *mask)
         }
 }
 
+/* Loops shorter than this run on one thread: on the small test meshes the
+ * threads' start and barrier cost more than the loop itself.  Only the grouping
+ * of the partial sums of dot products depends on it. */
+#define OR_PAR_MIN 20000
+
 void or_csr_spmv(const or_csr *A, const double *x, double *y)
 {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (A->n > OR_PAR_MIN)
     for (int64_t r = 0; r < A->n; ++r) {
         double s = 0;
         for (int64_t k = A->rowptr[r]; k < A->rowptr[r + 1]; ++k) s += A->val[k] * x[A->col[k]];
@@ -414,7 +419,7 @@ void or_csr_spmv(const or_csr *A, const double *x, double *y)
 static double vdot(int64_t n, const double *a, const double *b)
 {
     double s = 0;
-#pragma omp parallel for reduction(+ : s) schedule(static)
+#pragma omp parallel for reduction(+ : s) schedule(static) if (n > OR_PAR_MIN)
     for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
     return s;
 }
@@ -778,7 +783,7 @@ static or_cg_info pcg(const or_csr *A, const double *b, double *x, double tol, i
             break;
         }
         double al = rho / pq;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n > OR_PAR_MIN)
         for (int64_t i = 0; i < n; ++i) {
             x[i] += al * p[i];
             r[i] -= al * q[i];
@@ -787,7 +792,7 @@ static or_cg_info pcg(const or_csr *A, const double *b, double *x, double tol, i
         double rho2 = vdot(n, r, z);
         double be = rho2 / rho;
         rho = rho2;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n > OR_PAR_MIN)
         for (int64_t i = 0; i < n; ++i) p[i] = z[i] + be * p[i];
         info.iters++;
     }
@@ -1201,7 +1206,7 @@ int or_adjoint(or_problem *P, const double *g_u, const double *g_p, double *lam_
 void or_sensitivity(or_problem *P, const double *U, const double *Pp, const double *lam_u, const double *lam_p,
                     double *dJ_dE, double *dJ_dlogk)
 {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (P->ne > OR_PAR_MIN)
     for (int64_t e = 0; e < P->ne; ++e) {
         double X[12], Ke[144], Se[16], Ce[16], ue[12], le[12], pe[4], qe[4];
         tet_coords(P, e, X);

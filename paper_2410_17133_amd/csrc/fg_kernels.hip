@@ -836,8 +836,11 @@ __global__ __launch_bounds__(FIN) void k_cg_init_fin(const double *partials, int
     sc->iters = 0;
     sc->status = FG_OK;
     sc->done = 0;
-    if (!isfinite(tot[0]) || !isfinite(tot[1])) {
+    if (!isfinite(tot[1])) {
         sc->status = FG_ERR_NAN;
+        sc->done = 1;
+    } else if (!isfinite(tot[0])) {   // finite r, non-finite r.z: a zero diagonal entry
+        sc->status = FG_ERR_BREAKDOWN;
         sc->done = 1;
     } else if (tot[1] == 0.0) {
         sc->done = 1;
@@ -933,7 +936,8 @@ __global__ __launch_bounds__(WG) void k_cg_pupdate(int64_t n, int par, const T *
         sc->rr = tot[1];
         sc->rho_cur = sc->rho[par];
         if (!finite) {
-            sc->status = FG_ERR_NAN;
+            // finite r with a non-finite r.z: the preconditioner is singular
+            sc->status = isfinite(tot[1]) ? FG_ERR_BREAKDOWN : FG_ERR_NAN;
             sc->done = 1;
         } else if (tot[1] <= sc->tol2) {
             sc->status = FG_OK;
@@ -1195,7 +1199,8 @@ __global__ __launch_bounds__(WG) void k_cg_pupdate_bj(int64_t n, int par, const 
         sc->rr = tot[1];
         sc->rho_cur = sc->rho[par];
         if (!finite) {
-            sc->status = FG_ERR_NAN;
+            // finite r with a non-finite r.z: the preconditioner is singular
+            sc->status = isfinite(tot[1]) ? FG_ERR_BREAKDOWN : FG_ERR_NAN;
             sc->done = 1;
         } else if (tot[1] <= sc->tol2) {
             sc->status = FG_OK;
@@ -1722,7 +1727,8 @@ static fg_status cg_loop(fg_system *S, int which, int precision, int check_every
         if (e) return e;
     }
     const CgScalars &h = *S->sc_host;
-    if (h.status == FG_ERR_BREAKDOWN) set_error("fg_pcg_solve: CG breakdown (p.Ap <= 0): operator not SPD");
+    if (h.status == FG_ERR_BREAKDOWN)
+        set_error("fg_pcg_solve: CG breakdown (p.Ap <= 0, or a zero diagonal entry under point Jacobi): operator not SPD");
     if (h.status == FG_ERR_NAN) set_error("fg_pcg_solve: NaN or Inf in the CG iteration");
     return h.status;
 }

@@ -6,6 +6,8 @@ Every element of the operator products is compared with the oracle's CSR
 products; the interface update at a displacement with stick, slip and open
 points is compared point by point; 50 PCG iterations of both sides are compared
 as iterates (the same Krylov sequence up to rounding)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -111,6 +113,9 @@ def test_converged_k_solve_full_size(full):
     solutions."""
     S, P, O, fg, inst = full["S"], full["P"], full["O"], full["fg"], full["inst"]
     n = full["n"]
+    if n == 128 and not os.environ.get("FG_LONG_TESTS"):
+        pytest.skip("128^3 converged solve: the oracle side is about 4,000 block-Jacobi CG iterations on the host "
+                    "(about 3 minutes with the GPU side); set FG_LONG_TESTS=1 to run it")
     U0, die0 = np.zeros(3 * P.N), np.zeros((P.nq, 2))
     P.cohesive(U0, die0)
     S.cohesive_update(dev(U0), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)))   # the same stick tangent

@@ -214,7 +214,7 @@ def test_pcg_block_jacobi_matches_oracle(name):
     finally:
         S.tune("k_precond", 0)
     with pytest.raises(fg.FgError):
-        S.tune("k_precond", 3)
+        S.tune("k_precond", 4)          # 0-3 are the preconditioners
 
 
 def test_step_with_block_jacobi_reaches_the_same_state():
@@ -721,9 +721,10 @@ def test_line_search_converges_where_full_steps_do_not():
     assert 0 < slip < nq // 4                      # a contained slip patch
     S.tune("line_search", 0)
     U2, P2, die2 = dev(np.zeros(3 * N)), dev(np.zeros(N)), dev(np.zeros(2 * nq))
+    loose = fg.opts(tol=1e-8, check_every=64)     # this run only has to fail
     try:
         _, _, info2 = S.step(U2, P2, die2, t0, dev(inst.load), dev(inst.source), newton_tol=1e-9,
-                             newton_max_iter=40, inner_k=inner, inner_p=inner, outer_tol=1e-10)
+                             newton_max_iter=25, inner_k=loose, inner_p=loose, outer_tol=1e-6)
         assert info2.status != 0
     except fg.FgError as e:                      # the full-step iterates overflow
         assert e.status in (fg.FG_NOT_CONVERGED, fg.FG_ERR_NAN, fg.FG_ERR_BREAKDOWN)
