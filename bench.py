@@ -50,6 +50,9 @@ def main():
     ap.add_argument("--profile-iters", type=int, default=0,
                     help="profiling mode for hardware counters: run exactly this many FP64 K-PCG iterations and "
                          "one 1 GiB device copy (counter calibration), print a short JSON line, skip the rest")
+    ap.add_argument("--profile-amg", type=int, default=0,
+                    help="profiling mode for the AMG preconditioner: this many FP64 AMG-PCG solves to 1e-8 of the "
+                         "benchmark's first K system (the first also builds the hierarchy); prints a short JSON line")
     ap.add_argument("--profile-block", type=int, default=0,
                     help="profiling mode for the block product: this many FP64 block-CG iterations on 32 "
                          "right-hand sides at 64^3, then one 1 GiB device copy; prints a short JSON line")
@@ -100,6 +103,23 @@ def main():
         bytes_launch = 74.0 * npairs + 4.0 * nhalo + 52.0 * N
         print(json.dumps({"profile_iters": info.iters, "spmv_bytes_per_launch": bytes_launch,
                           "copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30}), flush=True)
+        return
+    if args.profile_amg > 0:
+        S.cohesive_update(d(np.zeros(3 * N)), d(np.zeros(2 * nq)), d(inst.t0.reshape(-1)))
+        z, _ = S.pcg_solve(fg.FG_A22, d(inst.source * inst.params.dt), tol=1e-12)
+        b = S.coupling(z)
+        S.tune("k_precond", 3)
+        times = []
+        for _ in range(args.profile_amg):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            x, info = S.pcg_solve(fg.FG_K, b, tol=1e-8)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t)
+        levels = S.amg_levels()
+        S.tune("k_precond", 0)
+        print(json.dumps({"profile_amg_solves": args.profile_amg, "iters": info.iters, "seconds": times,
+                          "levels": int(levels[0]), "nodes": [int(v) for v in levels[1]]}), flush=True)
         return
     t0, src, load = d(inst.t0.reshape(-1)), d(inst.source), d(inst.load)
     U, P, die = d(np.zeros(3 * N)), d(np.zeros(N)), d(np.zeros(2 * nq))
