@@ -238,7 +238,10 @@ def test_line_search_keeps_the_converged_step():
     out = {}
     for ls in (True, False):
         U, Pp, die = np.zeros(3 * P.N), np.zeros(P.N), np.zeros((P.nq, 2))
-        trac, flag, info, st = P.step(U, Pp, die, tol_newton=1e-10, max_newton=60, line_search=ls)
+        # inexact Newton (partitioned solves to 1e-6, inner 1e-8): the inner tolerances
+        # set the path, the Newton tolerance the state both runs must reach
+        trac, flag, info, st = P.step(U, Pp, die, tol_newton=1e-10, max_newton=60, line_search=ls, tol_outer=1e-6,
+                                      tol_inner=1e-8)
         assert st == 0
         out[ls] = (U, Pp, flag, info)
     assert out[True][3][7] >= 1 and out[False][3][7] == 0
