@@ -377,6 +377,14 @@ fg_status fg_lanczos_bounds(fg_ctx *ctx, fg_system *sys, int steps, double *lo, 
  * coarsest matrix not SPD), FG_ERR_OOM. */
 fg_status fg_amg_levels(fg_ctx *ctx, fg_system *sys, int *nlev, int64_t *nodes, void *stream);
 
+/* The aggregate of every node of level `level` (0 to nlev-2) of that hierarchy
+ * (built now if needed): agg (host, int32, nodes[level] entries; level 0 in the
+ * caller's node numbering) receives aggregate numbers 0 .. nodes[level+1]-1, the
+ * integer output of the aggregation passes.  Synchronises the stream.  Errors:
+ * FG_ERR_ARG (level out of range), FG_ERR_STATE (before fg_assemble, or
+ * k_precond is not 3), and those of fg_amg_levels. */
+fg_status fg_amg_aggregates(fg_ctx *ctx, fg_system *sys, int level, int32_t *agg, void *stream);
+
 /* Products on the assembled system, caller order: y = A x for which in
  * {FG_K, FG_A22, FG_KBULK, FG_C, FG_K_EXACT} (FG_K_EXACT: see fg_exact_solve). */
 fg_status fg_spmv(fg_ctx *ctx, fg_system *sys, int which, const double *x, double *y, void *stream);

@@ -404,7 +404,7 @@ static void csr_eliminate(or_csr *A, const uint8_t *mask)
 /* Loops shorter than this run on one thread: on the small test meshes the
  * threads' start and barrier cost more than the loop itself.  Only the grouping
  * of the partial sums of dot products depends on it. */
-#define OR_PAR_MIN 20000
+#define OR_PAR_MIN 4096
 
 void or_csr_spmv(const or_csr *A, const double *x, double *y)
 {

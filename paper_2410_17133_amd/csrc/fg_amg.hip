@@ -975,6 +975,24 @@ static void amg_vcycle(fg_system *S, int l, const double *b, double *x, hipStrea
     vaxpby(n, 1.0, L.e, 1.0, x, st);
 }
 
+fg_status amg_aggregates(const fg_system *S, int level, int32_t *out)
+{
+    const AmgData *G = S->amg;
+    if (!G || level < 0 || level >= G->nlev - 1) {
+        set_error("fg_amg_aggregates: level must be below the coarsest level of the hierarchy");
+        return FG_ERR_ARG;
+    }
+    const AmgLevel &L = G->L[level];
+    std::vector<int32_t> a((size_t)L.nn);
+    if (hipMemcpy(a.data(), L.agg, a.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+        return check_hip("fg_amg_aggregates");
+    if (level == 0)   // internal rows to the caller's node numbering
+        for (int64_t i = 0; i < S->N; ++i) out[i] = a[(size_t)S->plan.iperm[i]];
+    else
+        std::memcpy(out, a.data(), a.size() * sizeof(int32_t));
+    return FG_OK;
+}
+
 void amg_levels(const fg_system *S, int *nlev, int64_t *nodes)
 {
     *nlev = S->amg ? S->amg->nlev : 0;

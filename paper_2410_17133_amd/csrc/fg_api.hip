@@ -1196,6 +1196,24 @@ fg_status fg_amg_levels(fg_ctx *ctx, fg_system *S, int *nlev, int64_t *nodes, vo
     return check_hip("fg_amg_levels");
 }
 
+fg_status fg_amg_aggregates(fg_ctx *ctx, fg_system *S, int level, int32_t *agg, void *stream)
+{
+    if (!ctx || !S || !agg) {
+        set_error("fg_amg_aggregates: bad argument");
+        return FG_ERR_ARG;
+    }
+    if (!ready(S)) return FG_ERR_STATE;
+    if (S->k_precond != 3) {
+        set_error("fg_amg_aggregates: the AMG preconditioner is not selected (fg_tune k_precond 3)");
+        return FG_ERR_STATE;
+    }
+    Guard g(ctx->device);
+    fg_status e = amg_ready(S, S_(stream));
+    if (e) return e;
+    hipStreamSynchronize(S_(stream));
+    return amg_aggregates(S, level, agg);
+}
+
 fg_status fg_cheb_interval(fg_ctx *ctx, fg_system *S, double *lo, double *hi, void *stream)
 {
     if (!ctx || !S || !lo || !hi) {

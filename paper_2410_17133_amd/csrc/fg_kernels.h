@@ -81,6 +81,7 @@ fg_status amg_pcg(fg_system *S, const double *b, double *x, double tol, int64_t 
                   hipStream_t st);
 void amg_destroy(fg_system *S);
 void amg_levels(const fg_system *S, int *nlev, int64_t *nodes);  // nodes[6]
+fg_status amg_aggregates(const fg_system *S, int level, int32_t *out);  // host out, level's nodes
 // out = M^-1 in with the block-Jacobi data (bj_ready first).
 void bj_apply(fg_system *S, const double *in, double *out, hipStream_t st);
 

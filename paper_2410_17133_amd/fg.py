@@ -22,7 +22,7 @@ SYMBOLS = ["fg_last_error", "fg_ctx_create", "fg_ctx_destroy", "fg_system_create
            "fg_assemble", "fg_cohesive_update", "fg_pcg_solve", "fg_flow_solve", "fg_step", "fg_spmv",
            "fg_coupling", "fg_residual", "fg_system_sizes", "fg_export", "fg_profile", "fg_profile_read", "fg_tune", "fg_adjoint_solve", "fg_group_stats",
            "fg_assemble_groups", "fg_slip_adjoint", "fg_cheb_interval", "fg_exact_solve", "fg_adjoint_loop_step", "fg_pcg_solve_noalloc",
-           "fg_lanczos_bounds", "fg_amg_levels"]
+           "fg_lanczos_bounds", "fg_amg_levels", "fg_amg_aggregates"]
 
 
 class FgError(RuntimeError):
@@ -100,6 +100,7 @@ def lib():
             "fg_cheb_interval": [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double), vp],
             "fg_exact_solve": [vp, vp, vp, vp, C.POINTER(PcgOpts), C.POINTER(PcgInfo), vp],
             "fg_amg_levels": [vp, vp, C.POINTER(C.c_int), vp, vp],
+            "fg_amg_aggregates": [vp, vp, i32, vp, vp],
             "fg_lanczos_bounds": [vp, vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_double), vp],
             "fg_pcg_solve_noalloc": [vp, vp, i32, vp, vp, C.POINTER(PcgOpts), C.POINTER(PcgInfo), vp],
             "fg_adjoint_loop_step": [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
@@ -341,6 +342,16 @@ class System:
         nodes = np.zeros(6, np.int64)
         _check(lib().fg_amg_levels(self.ctx._h, self._h, C.byref(nl), nodes.ctypes.data, _stream()), False)
         return nl.value, nodes[:nl.value]
+
+    def amg_aggregates(self, level):
+        """Aggregate number of every node of AMG level `level` (fg_amg_aggregates; level 0 in
+        the caller's node numbering), as a numpy int32 array."""
+        nl, nodes = self.amg_levels()
+        if not 0 <= level < nl - 1:
+            raise ValueError(f"level must be in [0, {nl - 2}]")
+        out = np.zeros(int(nodes[level]), np.int32)
+        _check(lib().fg_amg_aggregates(self.ctx._h, self._h, int(level), out.ctypes.data, _stream()), False)
+        return out
 
     def lanczos_bounds(self, steps):
         """(smallest, largest) Ritz values of `steps` block-Jacobi CG steps on the probe

@@ -43,6 +43,9 @@ def test_amg_pcg_matches_oracle(n, dip, slip):
     S.tune("k_precond", 3)
     try:
         gl, gnodes = S.amg_levels()
+        # the aggregation is integer work: every level's aggregate map equals the oracle's exactly
+        for lev in range(gl - 1):
+            np.testing.assert_array_equal(S.amg_aggregates(lev), P.amg_export(hi0, lev, 2))
         x20, i20 = S.pcg_solve(fg.FG_K, dev(b), tol=1e-300, max_iter=20)
         x, info = S.pcg_solve(fg.FG_K, dev(b), tol=1e-12)
     finally:
