@@ -111,11 +111,11 @@ def check_self_similar(fronts, h):
 @pytest.mark.slow
 def test_slip_front_critically_stressed_runs_ahead_of_the_pressure():
     """tau0 = 47.999 MPa (T = 0.0235 << 1): the rupture front is several times
-    the diffusion front.  h = 0.1 m cells over the central 1.6 m of the fault;
-    the front reaches 0.8 m at t = 32 s (L = 0.17 m)."""
+    the diffusion front from the first step on.  h = 0.1 m cells over the central
+    1.6 m of the fault; the front reaches about 0.57 m at t = 16 s (L = 0.12 m)."""
     assert fault_stress_parameter(B["tau0_CS"]) < 0.05
     inst = I.slip_benchmark_instance(B["tau0_CS"], h=0.1, n_fine=16, n_grade=6, nx_grade=7, dt=4.0)
-    fronts = run_fronts(inst, steps=8, measure_from=2)
+    fronts = run_fronts(inst, steps=4, measure_from=1)
     lam = check_self_similar(fronts, h=0.1)
     assert lam > 2 and np.all(fronts[:, 2] > fronts[:, 1])
 
