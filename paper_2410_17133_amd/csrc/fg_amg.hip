@@ -856,6 +856,14 @@ static fg_status amg_numeric(fg_system *S, hipStream_t st)
         for (int64_t o = arow[i]; o < arow[i + 1]; ++o)
             for (int r = 0; r < bs; ++r)
                 for (int c = 0; c < bs; ++c) L[(bs * i + r) * n + bs * (int64_t)acol[o] + c] = aval[bs * bs * o + bs * r + c];
+    // rows without entries (the slices' padding rows when the whole mesh is the coarsest
+    // level) are decoupled: a unit diagonal keeps the matrix invertible, and their
+    // right-hand sides are zero, so the other unknowns do not change
+    for (int64_t j = 0; j < n; ++j) {
+        bool empty = true;
+        for (int64_t k = 0; k < n && empty; ++k) empty = L[j * n + k] == 0.0;
+        if (empty) L[j * n + j] = 1.0;
+    }
     for (int64_t j = 0; j < n; ++j) {
         double d = L[j * n + j];
         for (int64_t k = 0; k < j; ++k) d -= L[j * n + k] * L[j * n + k];

@@ -96,3 +96,34 @@ def test_step_with_amg_reaches_the_same_state(cfg):
           f"{int((flag_o == 1).sum())}; rel err U {eu:.1e} P {ep:.1e}", flush=True)
     assert info.status == 0
     assert eu < 1e-9 and ep < 1e-9
+
+
+def test_amg_on_a_mesh_below_the_coarsening_threshold_is_a_direct_solve():
+    """A mesh of no more than "amg_coarse" nodes is the coarsest level itself: the
+    preconditioner is the exact inverse (the slices' padding rows decoupled), PCG
+    converges in one or two iterations, and the solution equals the oracle's."""
+    from oracle import oracle as O
+    from paper_2410_17133_amd import fg
+    inst = I.make_instance(I.cube_config(2))
+    print(f"[case] AMG one level, {inst.mesh.n_nodes} nodes", flush=True)
+    ctx = fg.Context(0)
+    S = fg.System.from_instance(ctx, inst)
+    S.assemble(inst.params, inst.E, inst.logk)
+    P = O.Problem(inst)
+    P.cohesive(np.zeros(3 * P.N), np.zeros((P.nq, 2)))
+    S.cohesive_update(dev(np.zeros(3 * S.N)), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)))
+    hi0 = P.cheb_bounds(40, 1.1, 300)[1]
+    b = np.random.default_rng(7).standard_normal(3 * S.N) * (1 - inst.dir_u)
+    xo, st, ito, rro, levels, nodes = P.pcg_amg(b, hi0, tol=1e-12)
+    S.tune("k_precond", 3)
+    try:
+        gl, gnodes = S.amg_levels()
+        x, info = S.pcg_solve(fg.FG_K, dev(b), tol=1e-12)
+    finally:
+        S.tune("k_precond", 0)
+    x = x.cpu().numpy()
+    print(f"[amg one level] levels gpu {gl} oracle {levels}; iterations gpu {info.iters} oracle {ito}; "
+          f"solution {relerr(x, xo):.1e}", flush=True)
+    assert gl == levels == 1 and list(gnodes) == list(nodes)
+    assert info.status == 0 and st == 0 and info.iters <= 2 and abs(info.iters - ito) <= 1
+    assert relerr(x, xo) < 1e-9
