@@ -127,3 +127,47 @@ def test_amg_on_a_mesh_below_the_coarsening_threshold_is_a_direct_solve():
     assert gl == levels == 1 and list(gnodes) == list(nodes)
     assert info.status == 0 and st == 0 and info.iters <= 2 and abs(info.iters - ito) <= 1
     assert relerr(x, xo) < 1e-9
+
+
+def test_amg_edge_cases():
+    """A zero right-hand side (x = 0 at once), an iteration cap (FG_NOT_CONVERGED with
+    the iterate so far, as the oracle's capped AMG-PCG), a new "amg_coarse" (the
+    hierarchy rebuilt, as the oracle builds it with the same threshold) and
+    out-of-range knobs (rejected)."""
+    from oracle import oracle as O
+    from paper_2410_17133_amd import fg
+    inst = I.make_instance(I.cube_config(12, dip_deg=60.0, heterogeneous=True))
+    print("[case] AMG edge cases 12^3", flush=True)
+    ctx = fg.Context(0)
+    S = fg.System.from_instance(ctx, inst)
+    S.assemble(inst.params, inst.E, inst.logk)
+    P = O.Problem(inst)
+    P.cohesive(np.zeros(3 * P.N), np.zeros((P.nq, 2)))
+    S.cohesive_update(dev(np.zeros(3 * S.N)), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)))
+    hi0 = P.cheb_bounds(40, 1.1, 300)[1]
+    b = np.random.default_rng(3).standard_normal(3 * S.N) * (1 - inst.dir_u)
+    S.tune("k_precond", 3)
+    try:
+        x0, i0 = S.pcg_solve(fg.FG_K, dev(np.zeros(3 * S.N)), tol=1e-10)
+        assert i0.status == 0 and i0.iters == 0 and not x0.abs().max().item()
+        xc, ic = S.pcg_solve(fg.FG_K, dev(b), tol=1e-14, max_iter=7)
+        xoc, stc, itc, _, _, _ = P.pcg_amg(b, hi0, tol=1e-14, maxit=7)
+        assert ic.status == fg.FG_NOT_CONVERGED and ic.iters == itc == 7 and stc == 1
+        assert relerr(xc.cpu().numpy(), xoc) < 1e-6
+        levels_64 = S.amg_levels()
+        S.tune("amg_coarse", 200)                   # coarsening stops one level earlier
+        gl, gnodes = S.amg_levels()
+        _, st, ito, _, levels, nodes = P.pcg_amg(b, hi0, coarse_nodes=200, tol=1e-12)
+        assert gl == levels < levels_64[0] and list(gnodes) == list(nodes)
+        x, info = S.pcg_solve(fg.FG_K, dev(b), tol=1e-12)
+        assert info.status == 0 and abs(info.iters - ito) <= 1
+        for bad in (0, 1001):
+            with pytest.raises(fg.FgError):
+                S.tune("amg_coarse", bad)
+        with pytest.raises(fg.FgError):
+            S.tune("k_precond", 4)
+    finally:
+        S.tune("amg_coarse", 64)
+        S.tune("k_precond", 0)
+    print(f"[amg edge] levels {levels_64[0]} -> {gl} with amg_coarse 200; capped at 7 iterations; zero rhs ok",
+          flush=True)
