@@ -53,6 +53,8 @@ def main():
     ap.add_argument("--profile-amg", type=int, default=0,
                     help="profiling mode for the AMG preconditioner: this many FP64 AMG-PCG solves to 1e-8 of the "
                          "benchmark's first K system (the first also builds the hierarchy); prints a short JSON line")
+    ap.add_argument("--amg-mixed", action="store_true",
+                    help="with --profile-amg: FG_MIXED solves (the V-cycle in FP32 inside the FP64 CG)")
     ap.add_argument("--profile-block", type=int, default=0,
                     help="profiling mode for the block product: this many FP64 block-CG iterations on 32 "
                          "right-hand sides at 64^3, then one 1 GiB device copy; prints a short JSON line")
@@ -110,15 +112,17 @@ def main():
         b = S.coupling(z)
         S.tune("k_precond", 3)
         times = []
+        prec = fg.FG_MIXED if args.amg_mixed else fg.FG_F64
         for _ in range(args.profile_amg):
             torch.cuda.synchronize()
             t = time.perf_counter()
-            x, info = S.pcg_solve(fg.FG_K, b, tol=1e-8)
+            x, info = S.pcg_solve(fg.FG_K, b, tol=1e-8, precision=prec)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t)
         levels = S.amg_levels()
         S.tune("k_precond", 0)
-        print(json.dumps({"profile_amg_solves": args.profile_amg, "iters": info.iters, "seconds": times,
+        print(json.dumps({"profile_amg_solves": args.profile_amg, "fp32_cycle": args.amg_mixed,
+                          "iters": info.iters, "seconds": times,
                           "levels": int(levels[0]), "nodes": [int(v) for v in levels[1]]}), flush=True)
         return
     t0, src, load = d(inst.t0.reshape(-1)), d(inst.source), d(inst.load)
@@ -275,14 +279,25 @@ def main():
         torch.cuda.synchronize()
         amg_s = time.perf_counter() - t
         amg_levels = S.amg_levels()
+        # the same CG with the V-cycle in FP32 (FG_MIXED); the first call rounds the hierarchy
+        S.pcg_solve(fg.FG_K, b, tol=1e-8, precision=fg.FG_MIXED)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        xam, iam = S.pcg_solve(fg.FG_K, b, tol=1e-8, precision=fg.FG_MIXED)
+        torch.cuda.synchronize()
+        amg32_s = time.perf_counter() - t
         S.tune("k_precond", 0)
         log(f"f64_amg: {amg_s:.3f}s iters {ia.iters} relres {ia.relres:.2e} (first solve with set-up {amg_first:.2f}s); "
-            f"levels {amg_levels[0]} nodes {list(amg_levels[1])}")
+            f"levels {amg_levels[0]} nodes {list(amg_levels[1])}; FP32 cycle {amg32_s:.3f}s iters {iam.iters}")
         out["time_to_1e-8"].update({
             "f64_amg_s": amg_s, "f64_amg_iters": ia.iters, "f64_amg_first_solve_with_setup_s": amg_first,
             "amg_levels": int(amg_levels[0]), "amg_nodes": [int(v) for v in amg_levels[1]],
             "amg_vs_f64_rel_l2": (torch.linalg.norm(xa - res["f64"][3]) / torch.linalg.norm(res["f64"][3])).item(),
-            "speedup_amg": res["f64"][0] / amg_s})
+            "speedup_amg": res["f64"][0] / amg_s,
+            "mixed_amg_s": amg32_s, "mixed_amg_iters": iam.iters, "mixed_amg_status": iam.status,
+            "mixed_amg_vs_f64_rel_l2": (torch.linalg.norm(xam - res["f64"][3])
+                                        / torch.linalg.norm(res["f64"][3])).item(),
+            "speedup_mixed_amg": res["f64"][0] / amg32_s})
         for d in (2, 4):
             r_ = res[f"f64_chebyshev_d{d}"]
             out["time_to_1e-8"].update({
@@ -401,7 +416,8 @@ def extra_adjoint(ctx, log):
     res = {}
     for name, prec, kp, et in (("f64", fg.FG_F64, 0, 0), ("mixed", fg.FG_MIXED, 0, 0),
                                ("f64_block_jacobi", fg.FG_F64, 1, 0), ("mixed_block_jacobi", fg.FG_MIXED, 1, 0),
-                               ("f64_block_jacobi_exact", fg.FG_F64, 1, 1), ("f64_amg", fg.FG_F64, 3, 0)):
+                               ("f64_block_jacobi_exact", fg.FG_F64, 1, 1), ("f64_amg", fg.FG_F64, 3, 0),
+                               ("mixed_amg", fg.FG_MIXED, 3, 0)):
         # corrections solved loosely (outer 0.05, inner 1e-3); the defect tolerance sets the accuracy;
         # exact: the corrections solve with K_t + N^T (BiCGStab) instead of the symmetric tangent
         S.tune("k_precond", kp)
@@ -419,7 +435,7 @@ def extra_adjoint(ctx, log):
     bj = {name: {"s": res[name][0], "defect_iters": res[name][1].newton_iters, "k_iters": res[name][1].inner_k_iters,
                  "status": res[name][1].status,
                  "vs_f64_grad_rel_l2": (torch.linalg.norm(res[name][2] - g64) / torch.linalg.norm(g64)).item()}
-          for name in ("f64_block_jacobi", "mixed_block_jacobi", "f64_block_jacobi_exact", "f64_amg")}
+          for name in ("f64_block_jacobi", "mixed_block_jacobi", "f64_block_jacobi_exact", "f64_amg", "mixed_amg")}
     # the exact tangent K_t + N at the converged state (slip points present): BiCGStab to 1e-8
     # on b = dJ/dU, against CG on the symmetric tangent
     S.cohesive_update(U, die0, t0, write_tangent=True)
@@ -437,14 +453,16 @@ def extra_adjoint(ctx, log):
     # the forward step again, block-Jacobi K solves with the symmetric and with the exact tangent,
     # and AMG-preconditioned K solves (symmetric tangent; hierarchy values rebuilt at every change of K)
     fwd = {}
-    for kp, et in ((1, 0), (1, 1), (3, 0)):
+    inner32 = fg.opts(tol=1e-4, check_every=64, precision=fg.FG_MIXED)
+    for kp, et, ik in ((1, 0, inner), (1, 1, inner), (3, 0, inner), (3, 0, inner32)):
         S.tune("k_precond", kp)
         S.tune("exact_tangent", et)
         U2, P2, die2 = d(np.zeros(3 * S.N)), d(np.zeros(S.N)), d(np.zeros(2 * S.nq))
         t_f, (_, flag2, finfo2) = _timed(lambda: S.step(U2, P2, die2, t0, d(inst.load), d(inst.source),
-                                                         newton_tol=1e-8, newton_max_iter=60, inner_k=inner,
+                                                         newton_tol=1e-8, newton_max_iter=60, inner_k=ik,
                                                          inner_p=inner, outer_tol=1e-2))
-        name = "amg_symmetric" if kp == 3 else "exact" if et else "symmetric"
+        name = ("amg_mixed_symmetric" if ik is inner32 else "amg_symmetric") if kp == 3 else \
+            "exact" if et else "symmetric"
         log(f"forward step, {'AMG' if kp == 3 else 'block Jacobi'}, {name} tangent: {t_f:.2f}s newton {finfo2.newton_iters} cuts "
             f"{finfo2.step_cuts} K iters {finfo2.inner_k_iters} status {finfo2.status}")
         fwd[name] = {"s": t_f, "newton": finfo2.newton_iters, "step_cuts": finfo2.step_cuts,

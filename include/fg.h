@@ -70,7 +70,9 @@ typedef int fg_status;
 #define FG_MIXED 2  /* FP32 PCG with FP64 residual replacement: whenever the FP32 residual has dropped
                       tenfold, the FP32 solution is added to the FP64 one, b - K x is formed in FP64
                       and replaces the FP32 residual, and CG continues (reliable updates; per
-                      column in the block solve, per group on batched systems) */
+                      column in the block solve, per group on batched systems).  With the AMG
+                      preconditioner ("k_precond" 3, see fg_tune): FP64 CG whose V-cycle runs in
+                      FP32 */
 #define FG_MIXED_F32VAL 3  /* inner PCG on the FP32 matrix values with FP64 vectors and arithmetic,
                               FP64 residual and refinement (single right-hand side, unbatched) */
 
@@ -459,7 +461,14 @@ fg_status fg_group_stats(const fg_system *sys, int64_t *iters_h, double *relres_
  *               blocks of stage 1 on [hi/30, hi] with hi as for stage 2; below:
  *               6x6 blocks on [rho/30, rho]).  The patterns are built on the host
  *               once per mesh, the values on the GPU after every change of K;
- *               other solves behave as with 1.
+ *               other solves behave as with 1.  FG_MIXED single-right-hand-side
+ *               K solves run the same FP64 CG with the V-cycle in FP32: every
+ *               level's values rounded once per change of K (level 0: K's FP32
+ *               copy and the FP32 blocks of stage 1), the cycle's input scaled
+ *               to unit norm by the last residual norm and its output scaled
+ *               back, and beta = r_{k+1}.(z_{k+1} - z_k) / r_k.z_k, the
+ *               flexible form that tolerates the rounding's asymmetry (Golub
+ *               and Ye, SIAM J. Sci. Comput. 21, 1999); info.cycles is 1.
  *   "exact_tangent": 1 makes the FP64 K solves inside fg_flow_solve and fg_step
  *               solve the exact tangent K_t + N by BiCGStab (as fg_exact_solve),
  *               so that Newton uses the exact Jacobian of the interface force;

@@ -63,6 +63,11 @@ struct AmgLevel {
     // correction, and the smoother's scratch d, s, w, t
     double *x = nullptr, *b = nullptr, *r = nullptr, *e = nullptr, *t = nullptr, *d = nullptr, *s = nullptr,
            *w = nullptr;
+    // FP32 copies for the mixed-precision cycle (allocated on its first use): A and
+    // dinv (coarse levels), P (every level but the coarsest), the cycle vectors
+    float *aval32 = nullptr, *dinv32 = nullptr, *pval32 = nullptr;
+    float *x32 = nullptr, *b32 = nullptr, *r32 = nullptr, *e32 = nullptr, *t32 = nullptr, *d32 = nullptr,
+          *s32 = nullptr, *w32 = nullptr;
 };
 
 struct AmgData {
@@ -75,6 +80,11 @@ struct AmgData {
     // the system's shared work vectors as right-hand side and solution
     double *cr = nullptr, *cz = nullptr, *cp = nullptr, *cq = nullptr;
     int64_t epoch = -1;                // bj_epoch of the numeric set-up
+    // mixed precision: FP32 coarsest inverse, the cycle's FP32 right-hand side and
+    // result, the previous preconditioned residual of the flexible CG
+    float *cinv32 = nullptr, *cr32 = nullptr, *cz32 = nullptr;
+    double *cz0 = nullptr;
+    int64_t epoch32 = -1;              // bj_epoch of the FP32 copies
     int64_t coarse_nodes = 64;
 };
 
@@ -214,9 +224,10 @@ fg_status up(T **p, const std::vector<T> &v)
     return FG_OK;
 }
 
-fg_status dmal(double **p, int64_t n)
+template <typename T>
+fg_status dmal(T **p, int64_t n)
 {
-    if (hipMalloc((void **)p, std::max<int64_t>(n, 1) * sizeof(double)) != hipSuccess) {
+    if (hipMalloc((void **)p, std::max<int64_t>(n, 1) * sizeof(T)) != hipSuccess) {
         hipGetLastError();
         return FG_ERR_OOM;
     }
@@ -451,54 +462,54 @@ __global__ void k_amg_unit_empty(int64_t nc, const int64_t *__restrict__ crow, c
 }
 
 // ------------------------------------------------------------ cycle kernels
-template <int BS>
+// T: double for the FP64 cycle, float for the FP32 cycle of the mixed-precision solve.
+template <int BS, typename T>
 __global__ void k_amg_spmv(int64_t nn, const int64_t *__restrict__ arow, const int32_t *__restrict__ acol,
-                           const double *__restrict__ aval, const double *__restrict__ x, double *y)
+                           const T *__restrict__ aval, const T *__restrict__ x, T *y)
 {
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (g >= nn * BS) return;
     const int64_t i = g / BS;
     const int r = (int)(g - i * BS);
-    double s = 0;
+    T s = 0;
     for (int64_t o = arow[i]; o < arow[i + 1]; ++o) {
-        const double *m = aval + BS * BS * o + BS * r;
-        const double *xj = x + (int64_t)BS * acol[o];
+        const T *m = aval + BS * BS * o + BS * r;
+        const T *xj = x + (int64_t)BS * acol[o];
         for (int k = 0; k < BS; ++k) s += m[k] * xj[k];
     }
     y[g] = s;
 }
 
 // out = dinv x per node (6x6 blocks of the coarse levels), scaled by sc.
-__global__ void k_amg_dapply(int64_t nn, const double *__restrict__ dinv, const double *__restrict__ x, double sc,
-                             double *out)
+template <typename T>
+__global__ void k_amg_dapply(int64_t nn, const T *__restrict__ dinv, const T *__restrict__ x, T sc, T *out)
 {
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (g >= nn * 6) return;
     const int64_t i = g / 6;
     const int r = (int)(g - i * 6);
-    double s = 0;
+    T s = 0;
     for (int k = 0; k < 6; ++k) s += dinv[36 * i + 6 * r + k] * x[6 * i + k];
     out[g] = sc * s;
 }
 
 // bc(I) = sum_{(i, e)} P_e^T r_i: one wavefront per aggregate, its lanes taking
 // every 64th entry of the aggregate's P^T list, then a fixed-order lane reduction.
-template <int BS>
+template <int BS, typename T>
 __global__ __launch_bounds__(WG) void k_amg_restrict(int64_t nc, const int64_t *__restrict__ rrow,
                                                      const int32_t *__restrict__ rnode, const int64_t *__restrict__ rent,
-                                                     const double *__restrict__ pval, const double *__restrict__ r,
-                                                     double *bc)
+                                                     const T *__restrict__ pval, const T *__restrict__ r, T *bc)
 {
     const int64_t I = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;   // uniform per wavefront
     const int lane = threadIdx.x & 63;
     if (I >= nc) return;
-    double s[6] = {0, 0, 0, 0, 0, 0};
+    T s[6] = {0, 0, 0, 0, 0, 0};
     const int64_t t1 = rrow[I + 1];
     for (int64_t t = rrow[I] + lane; t < t1; t += 64) {
-        const double *p = pval + BS * 6 * rent[t];
-        const double *ri = r + (int64_t)BS * rnode[t];
+        const T *p = pval + BS * 6 * rent[t];
+        const T *ri = r + (int64_t)BS * rnode[t];
         for (int k = 0; k < BS; ++k) {
-            const double rk = ri[k];
+            const T rk = ri[k];
             for (int c = 0; c < 6; ++c) s[c] += p[6 * k + c] * rk;
         }
     }
@@ -509,34 +520,54 @@ __global__ __launch_bounds__(WG) void k_amg_restrict(int64_t nc, const int64_t *
 }
 
 // x_i += sum_{e in P row i} P_e xc(agg)
-template <int BS>
+template <int BS, typename T>
 __global__ void k_amg_prolong_add(int64_t nn, const int64_t *__restrict__ prow, const int32_t *__restrict__ pcol,
-                                  const double *__restrict__ pval, const double *__restrict__ xc, double *x)
+                                  const T *__restrict__ pval, const T *__restrict__ xc, T *x)
 {
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (g >= nn * BS) return;
     const int64_t i = g / BS;
     const int r = (int)(g - i * BS);
-    double s = 0;
+    T s = 0;
     for (int64_t e = prow[i]; e < prow[i + 1]; ++e) {
-        const double *p = pval + BS * 6 * e + 6 * r;
-        const double *xa = xc + 6 * (int64_t)pcol[e];
+        const T *p = pval + BS * 6 * e + 6 * r;
+        const T *xa = xc + 6 * (int64_t)pcol[e];
         for (int c = 0; c < 6; ++c) s += p[c] * xa[c];
     }
     x[g] += s;
 }
 
 // y = Ainv x for the coarsest level: one wavefront per row.
-__global__ __launch_bounds__(WG) void k_amg_dense(int64_t n, const double *__restrict__ Ainv,
-                                                  const double *__restrict__ x, double *y)
+template <typename T>
+__global__ __launch_bounds__(WG) void k_amg_dense(int64_t n, const T *__restrict__ Ainv, const T *__restrict__ x, T *y)
 {
     const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (i >= n) return;
-    double s = 0;
+    T s = 0;
     for (int64_t k = lane; k < n; k += 64) s += Ainv[i * n + k] * x[k];
     for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
     if (lane == 0) y[i] = s;
+}
+
+// FP32 vector helpers of the mixed cycle (the FP64 cycle uses the library's).
+__global__ void k_amg_axpby32(int64_t n, float a, const float *__restrict__ x, float b, float *__restrict__ y)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) y[i] = a * x[i] + b * y[i];
+}
+
+__global__ void k_amg_scale32(int64_t n, float a, float *y)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) y[i] *= a;
+}
+
+// y = s x, FP32 to FP64 (the preconditioned residual of the mixed cycle).
+__global__ void k_amg_widen(int64_t n, double s, const float *__restrict__ x, double *__restrict__ y)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) y[i] = s * (double)x[i];
 }
 
 inline int64_t nb(int64_t n) { return std::max<int64_t>((n + WG - 1) / WG, 1); }
@@ -544,7 +575,8 @@ inline int64_t nb(int64_t n) { return std::max<int64_t>((n + WG - 1) / WG, 1); }
 void free_level(AmgLevel &L)
 {
     void *p[] = {L.arow, L.acol, L.arid, L.aval, L.agg, L.q, L.prow, L.pcol, L.pval, L.wrow, L.wcol, L.wval,
-                 L.rrow, L.rnode, L.rent, L.dinv, L.x, L.b, L.r, L.e, L.t, L.d, L.s, L.w};
+                 L.rrow, L.rnode, L.rent, L.dinv, L.x, L.b, L.r, L.e, L.t, L.d, L.s, L.w,
+                 L.aval32, L.dinv32, L.pval32, L.x32, L.b32, L.r32, L.e32, L.t32, L.d32, L.s32, L.w32};
     for (void *v : p)
         if (v) hipFree(v);
     L = AmgLevel{};
@@ -558,7 +590,9 @@ void amg_destroy(fg_system *S)
     for (AmgLevel &L : S->amg->L) free_level(L);
     if (S->amg->cinv) hipFree(S->amg->cinv);
     if (S->amg->part) hipFree(S->amg->part);
-    for (double *v : {S->amg->cr, S->amg->cz, S->amg->cp, S->amg->cq})
+    for (double *v : {S->amg->cr, S->amg->cz, S->amg->cp, S->amg->cq, S->amg->cz0})
+        if (v) hipFree(v);
+    for (float *v : {S->amg->cinv32, S->amg->cr32, S->amg->cz32})
         if (v) hipFree(v);
     delete S->amg;
     S->amg = nullptr;
@@ -914,73 +948,169 @@ fg_status amg_ready(fg_system *S, hipStream_t st)
     return amg_numeric(S, st);
 }
 
+// ------------------------------------------------------------ FP32 copies (mixed precision)
+static void free32(AmgData *G)
+{
+    for (AmgLevel &L : G->L) {
+        float **p[] = {&L.aval32, &L.dinv32, &L.pval32, &L.x32, &L.b32, &L.r32, &L.e32, &L.t32, &L.d32, &L.s32, &L.w32};
+        for (float **v : p) {
+            if (*v) hipFree(*v);
+            *v = nullptr;
+        }
+    }
+    for (float **v : {&G->cinv32, &G->cr32, &G->cz32}) {
+        if (*v) hipFree(*v);
+        *v = nullptr;
+    }
+    if (G->cz0) hipFree(G->cz0);
+    G->cz0 = nullptr;
+    G->epoch32 = -1;
+}
+
+// The hierarchy's values in FP32 for the current K (after amg_ready): every level's
+// matrix (level 0: K's own FP32 copy), block-Jacobi inverses, prolongator and the
+// coarsest inverse, rounded from the FP64 set-up.
+static fg_status amg_ready32(fg_system *S, hipStream_t st)
+{
+    AmgData *G = S->amg;
+    if (!G->cr32) {
+        bool ok = true;
+        for (int l = 0; l < G->nlev && ok; ++l) {
+            AmgLevel &L = G->L[l];
+            const int64_t n = L.nn * L.bs;
+            if (l > 0) ok = ok && !dmal(&L.aval32, L.nnzb * L.bs * L.bs) && !dmal(&L.dinv32, n * L.bs);
+            if (l < G->nlev - 1) ok = ok && !dmal(&L.pval32, L.npz * L.bs * 6);
+            float **vec[] = {&L.x32, &L.b32, &L.r32, &L.e32, &L.t32, &L.d32, &L.s32, &L.w32};
+            for (float **v : vec) ok = ok && !dmal(v, n);
+        }
+        const int64_t n0 = 3 * S->Npad;
+        ok = ok && !dmal(&G->cinv32, G->nco * G->nco) && !dmal(&G->cr32, n0) && !dmal(&G->cz32, n0) &&
+             !dmal(&G->cz0, n0);
+        if (!ok) {
+            free32(G);
+            set_error("AMG: device allocation for the FP32 cycle failed");
+            return FG_ERR_OOM;
+        }
+    }
+    if (!S->k32_valid) refresh_k32(S, st);
+    bj_ready32(S, st);
+    if (G->epoch32 == G->epoch) return FG_OK;
+    for (int l = 0; l < G->nlev; ++l) {
+        AmgLevel &L = G->L[l];
+        if (l > 0) {
+            to_f32(L.nnzb * L.bs * L.bs, 1.0, L.aval, L.aval32, st);
+            to_f32(L.nn * L.bs * L.bs, 1.0, L.dinv, L.dinv32, st);
+        }
+        if (l < G->nlev - 1) to_f32(L.npz * L.bs * 6, 1.0, L.pval, L.pval32, st);
+    }
+    to_f32(G->nco * G->nco, 1.0, G->cinv, G->cinv32, st);
+    G->epoch32 = G->epoch;
+    return check_hip("AMG FP32 copies");
+}
+
 // ------------------------------------------------------------ the V-cycle
+// One level's cycle arrays in the cycle's precision.
+template <typename T>
+struct Lv {
+    const T *aval, *dinv, *pval;
+    T *x, *b, *r, *e, *t, *d, *s, *w;
+};
+static Lv<double> lv(const AmgLevel &L, double)
+{
+    return {L.aval, L.dinv, L.pval, L.x, L.b, L.r, L.e, L.t, L.d, L.s, L.w};
+}
+static Lv<float> lv(const AmgLevel &L, float)
+{
+    return {L.aval32, L.dinv32, L.pval32, L.x32, L.b32, L.r32, L.e32, L.t32, L.d32, L.s32, L.w32};
+}
+static const double *cinv_of(const AmgData *G, double) { return G->cinv; }
+static const float *cinv_of(const AmgData *G, float) { return G->cinv32; }
+
+// Level 0 works on K itself: the library's product and block-Jacobi apply.
+static void l0_mul(fg_system *S, const double *x, double *y, hipStream_t st) { spmv(S, FG_K, x, y, st); }
+static void l0_mul(fg_system *S, const float *x, float *y, hipStream_t st) { spmv_k32(S, x, y, st); }
+static void l0_minv(fg_system *S, const double *x, double *y, hipStream_t st) { bj_apply(S, x, y, st); }
+static void l0_minv(fg_system *S, const float *x, float *y, hipStream_t st) { bj_apply32(S, x, y, st); }
+static void axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t st)
+{
+    vaxpby(n, a, x, b, y, st);
+}
+static void axpby(int64_t n, double a, const float *x, double b, float *y, hipStream_t st)
+{
+    LAUNCH(k_amg_axpby32, nb(n), WG, st, n, (float)a, x, (float)b, y);
+}
+static void scale(int64_t n, double a, double *y, hipStream_t st) { vscale(n, a, y, st); }
+static void scale(int64_t n, double a, float *y, hipStream_t st) { LAUNCH(k_amg_scale32, nb(n), WG, st, n, (float)a, y); }
+
+// y = A_l x on level l.
+template <typename T>
+static void amg_mul(fg_system *S, int l, const T *x, T *y, hipStream_t st)
+{
+    const AmgLevel &L = S->amg->L[l];
+    if (l == 0)
+        l0_mul(S, x, y, st);
+    else
+        LAUNCH((k_amg_spmv<6, T>), nb(L.nn * L.bs), WG, st, L.nn, L.arow, L.acol, lv(L, T()).aval, x, y);
+}
+
 // x = p(M^-1 A) M^-1 b, degree-2 Chebyshev over the level's block Jacobi (x, b on the level).
-static void amg_smooth(fg_system *S, int l, const double *b, double *x, hipStream_t st)
+template <typename T>
+static void amg_smooth(fg_system *S, int l, const T *b, T *x, hipStream_t st)
 {
     AmgData *G = S->amg;
     AmgLevel &L = G->L[l];
+    const Lv<T> v = lv(L, T());
     const int64_t n = L.nn * L.bs;
     const double hi = l == 0 ? S->cheb_hi : L.rho, lo = hi / 30.0;
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
-    auto minv = [&](const double *v, double *out) {
+    auto minv = [&](const T *in, T *out) {
         if (l == 0)
-            bj_apply(S, v, out, st);
+            l0_minv(S, in, out, st);
         else
-            LAUNCH(k_amg_dapply, nb(n), WG, st, L.nn, L.dinv, v, 1.0, out);
+            LAUNCH((k_amg_dapply<T>), nb(n), WG, st, L.nn, v.dinv, in, (T)1, out);
     };
-    auto amul = [&](const double *v, double *out) {
-        if (l == 0)
-            spmv(S, FG_K, v, out, st);
-        else
-            LAUNCH((k_amg_spmv<6>), nb(n), WG, st, L.nn, L.arow, L.acol, L.aval, v, out);
-    };
-    double *d = L.d, *s = L.s, *w = L.w, *kd = L.t;
+    T *d = v.d, *s = v.s, *w = v.w, *kd = v.t;
     minv(b, d);
-    vscale(n, 1.0 / theta, d, st);
-    hipMemcpyAsync(x, d, n * sizeof(double), hipMemcpyDeviceToDevice, st);
-    hipMemcpyAsync(s, b, n * sizeof(double), hipMemcpyDeviceToDevice, st);
+    scale(n, 1.0 / theta, d, st);
+    hipMemcpyAsync(x, d, n * sizeof(T), hipMemcpyDeviceToDevice, st);
+    hipMemcpyAsync(s, b, n * sizeof(T), hipMemcpyDeviceToDevice, st);
     const double rho0 = 1.0 / sigma;
-    amul(d, kd);
-    vaxpby(n, -1.0, kd, 1.0, s, st);
+    amg_mul(S, l, d, kd, st);
+    axpby(n, -1.0, kd, 1.0, s, st);
     const double rho1 = 1.0 / (2.0 * sigma - rho0);
     minv(s, w);
-    vaxpby(n, 2.0 * rho1 / delta, w, rho1 * rho0, d, st);
-    vaxpby(n, 1.0, d, 1.0, x, st);
+    axpby(n, 2.0 * rho1 / delta, w, rho1 * rho0, d, st);
+    axpby(n, 1.0, d, 1.0, x, st);
 }
 
-static void amg_vcycle(fg_system *S, int l, const double *b, double *x, hipStream_t st)
+template <typename T>
+static void amg_vcycle(fg_system *S, int l, const T *b, T *x, hipStream_t st)
 {
     AmgData *G = S->amg;
     AmgLevel &L = G->L[l];
+    const Lv<T> v = lv(L, T());
     const int64_t n = L.nn * L.bs;
     if (l == G->nlev - 1) {
-        LAUNCH(k_amg_dense, nb(64 * n), WG, st, n, G->cinv, b, x);
+        LAUNCH((k_amg_dense<T>), nb(64 * n), WG, st, n, cinv_of(G, T()), b, x);
         return;
     }
-    AmgLevel &C = G->L[l + 1];
-    auto amul = [&](const double *v, double *out) {
-        if (l == 0)
-            spmv(S, FG_K, v, out, st);
-        else
-            LAUNCH((k_amg_spmv<6>), nb(n), WG, st, L.nn, L.arow, L.acol, L.aval, v, out);
-    };
+    const Lv<T> c = lv(G->L[l + 1], T());
     amg_smooth(S, l, b, x, st);                       // pre-smoothing from zero
-    amul(x, L.r);
-    vaxpby(n, 1.0, b, -1.0, L.r, st);                 // r = b - A x
+    amg_mul(S, l, (const T *)x, v.r, st);
+    axpby(n, 1.0, b, -1.0, v.r, st);                  // r = b - A x
     if (L.bs == 3)
-        LAUNCH((k_amg_restrict<3>), nb(64 * L.nc), WG, st, L.nc, L.rrow, L.rnode, L.rent, L.pval, L.r, C.b);
+        LAUNCH((k_amg_restrict<3, T>), nb(64 * L.nc), WG, st, L.nc, L.rrow, L.rnode, L.rent, v.pval, v.r, c.b);
     else
-        LAUNCH((k_amg_restrict<6>), nb(64 * L.nc), WG, st, L.nc, L.rrow, L.rnode, L.rent, L.pval, L.r, C.b);
-    amg_vcycle(S, l + 1, C.b, C.x, st);
+        LAUNCH((k_amg_restrict<6, T>), nb(64 * L.nc), WG, st, L.nc, L.rrow, L.rnode, L.rent, v.pval, v.r, c.b);
+    amg_vcycle(S, l + 1, (const T *)c.b, c.x, st);
     if (L.bs == 3)
-        LAUNCH((k_amg_prolong_add<3>), nb(n), WG, st, L.nn, L.prow, L.pcol, L.pval, C.x, x);
+        LAUNCH((k_amg_prolong_add<3, T>), nb(n), WG, st, L.nn, L.prow, L.pcol, v.pval, c.x, x);
     else
-        LAUNCH((k_amg_prolong_add<6>), nb(n), WG, st, L.nn, L.prow, L.pcol, L.pval, C.x, x);
-    amul(x, L.r);
-    vaxpby(n, 1.0, b, -1.0, L.r, st);
-    amg_smooth(S, l, L.r, L.e, st);                   // post-smoothing on the residual
-    vaxpby(n, 1.0, L.e, 1.0, x, st);
+        LAUNCH((k_amg_prolong_add<6, T>), nb(n), WG, st, L.nn, L.prow, L.pcol, v.pval, c.x, x);
+    amg_mul(S, l, (const T *)x, v.r, st);
+    axpby(n, 1.0, b, -1.0, v.r, st);
+    amg_smooth(S, l, (const T *)v.r, v.e, st);       // post-smoothing on the residual
+    axpby(n, 1.0, v.e, 1.0, x, st);
 }
 
 fg_status amg_aggregates(const fg_system *S, int level, int32_t *out)
@@ -1009,27 +1139,54 @@ void amg_levels(const fg_system *S, int *nlev, int64_t *nodes)
 }
 
 // PCG on K with the V-cycle (internal vectors; same recurrence and stop test as cg_run).
-fg_status amg_pcg(fg_system *S, const double *b, double *x, double tol, int64_t maxit, int64_t *iters, double *relres,
-                  hipStream_t st)
+// f32: the cycle runs in FP32 on r scaled to unit norm by the last residual norm, and
+// its result is scaled back; the CG stays FP64 and, since rounding makes that cycle
+// slightly non-symmetric, takes beta in the flexible form
+// r_{k+1}.(z_{k+1} - z_k) / r_k.z_k (Golub and Ye, SIAM J. Sci. Comput. 21, 1999).
+fg_status amg_pcg(fg_system *S, const double *b, double *x, double tol, int64_t maxit, bool f32, int64_t *iters,
+                  double *relres, hipStream_t st)
 {
     *iters = 0;
     *relres = 0;
     fg_status e = amg_ready(S, st);
     if (e) return e;
+    if (f32) {
+        e = amg_ready32(S, st);
+        if (e) return e;
+    }
+    AmgData *G = S->amg;
     const int64_t n = 3 * S->Npad;
-    double *r = S->amg->cr, *z = S->amg->cz, *p = S->amg->cp, *q = S->amg->cq;
+    double *r = G->cr, *z = G->cz, *p = G->cp, *q = G->cq, *z0 = G->cz0;
+    auto precond = [&](double rn) {
+        if (!f32) {
+            amg_vcycle(S, 0, (const double *)r, z, st);
+            return;
+        }
+        to_f32(n, 1.0 / rn, r, G->cr32, st);
+        amg_vcycle(S, 0, (const float *)G->cr32, G->cz32, st);
+        LAUNCH(k_amg_widen, nb(n), WG, st, n, rn, G->cz32, z);
+    };
     vfill(x, 0.0, n, st);
     hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, st);
-    amg_vcycle(S, 0, r, z, st);
-    hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, st);
-    double d2[2];
-    {
+    double bn, rho;
+    if (f32) {
+        const double *A[1] = {b};
+        vdots(S, n, 1, A, A, &bn, st);
+        bn = std::sqrt(bn);
+        if (!(bn > 0)) return std::isfinite(bn) ? FG_OK : FG_ERR_NAN;
+        precond(bn);
+        const double *R[1] = {r}, *Z[1] = {z};
+        vdots(S, n, 1, R, Z, &rho, st);
+    } else {
+        precond(1.0);
+        double d2[2];
         const double *A[2] = {b, r}, *B2[2] = {b, z};
         vdots(S, n, 2, A, B2, d2, st);
+        bn = std::sqrt(d2[0]);
+        rho = d2[1];
+        if (!(bn > 0)) return std::isfinite(bn) ? FG_OK : FG_ERR_NAN;
     }
-    const double bn = std::sqrt(d2[0]);
-    double rho = d2[1];
-    if (!(bn > 0)) return std::isfinite(bn) ? FG_OK : FG_ERR_NAN;
+    hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, st);
     int64_t it = 0;
     for (;;) {
         double rr;
@@ -1062,13 +1219,20 @@ fg_status amg_pcg(fg_system *S, const double *b, double *x, double tol, int64_t 
         const double al = rho / pq;
         vaxpby(n, al, p, 1.0, x, st);
         vaxpby(n, -al, q, 1.0, r, st);
-        amg_vcycle(S, 0, r, z, st);
-        double rho2;
-        {
+        if (f32) std::swap(z, z0);   // z0: the last preconditioned residual
+        precond(std::sqrt(rr));
+        double rho2, rz0 = 0.0;
+        if (f32) {
+            double d2[2];
+            const double *A[2] = {r, r}, *B2[2] = {z, z0};
+            vdots(S, n, 2, A, B2, d2, st);
+            rho2 = d2[0];
+            rz0 = d2[1];
+        } else {
             const double *A[1] = {r}, *B1[1] = {z};
             vdots(S, n, 1, A, B1, &rho2, st);
         }
-        const double be = rho2 / rho;
+        const double be = (rho2 - rz0) / rho;
         rho = rho2;
         vaxpby(n, 1.0, z, be, p, st);
         ++it;

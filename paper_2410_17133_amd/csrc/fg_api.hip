@@ -130,13 +130,25 @@ struct AdjointSolves {
 fg_status k_solve(fg_system *S, const double *rhs, double *out, const fg_pcg_opts &o, fg_pcg_info *info, hipStream_t st)
 {
     const int64_t n = 3 * S->Npad;
+    if (S->k_precond == 3 && !S->exact_tangent && S->ngroups == 1 &&
+        (o.precision == FG_F64 || o.precision == FG_MIXED)) {
+        // AMG-PCG in FP64; FG_MIXED runs its V-cycle in FP32
+        int64_t it = 0;
+        double rr = 0;
+        fg_status s = amg_pcg(S, rhs, out, o.tol, o.max_iter, o.precision == FG_MIXED, &it, &rr, st);
+        if (info) {
+            info->iters = it;
+            info->cycles = 1;
+            info->relres = rr;
+            info->status = s;
+        }
+        return s;
+    }
     if (o.precision == FG_F64 || o.precision == FG_F32) {
         int64_t it = 0;
         double rr = 0;
         fg_status s;
-        if (o.precision == FG_F64 && S->k_precond == 3 && !S->exact_tangent && S->ngroups == 1) {
-            s = amg_pcg(S, rhs, out, o.tol, o.max_iter, &it, &rr, st);
-        } else if (o.precision == FG_F64 && S->exact_tangent && S->ngroups == 1) {
+        if (o.precision == FG_F64 && S->exact_tangent && S->ngroups == 1) {
             s = bicgstab_exact(S, rhs, out, o.tol, o.max_iter, S->exact_tangent == 2, &it, &rr, st);
         } else if (o.precision == FG_F64 && S->k_precond == 2 && S->ngroups == 1) {
             s = cheb_cg(S, rhs, out, o.tol, o.max_iter, o.check_every, &it, &rr, st);

@@ -30,14 +30,17 @@ namespace fg {
 
 namespace {
 
-struct BjView {
-    const double *A;       // [Npad*6] symmetric 3x3 blocks of M^-1: xx yy zz yz xz xy
-    const double *B;       // [nfr*9] pair coupling blocks of M^-1, row-major
+template <typename T>
+struct BjViewT {
+    const T *A;            // [Npad*6] symmetric 3x3 blocks of M^-1: xx yy zz yz xz xy
+    const T *B;            // [nfr*9] pair coupling blocks of M^-1, row-major
     const int32_t *fslot;  // [Npad] fault-row index, -1 off the interface
     const int32_t *fpart;  // [nfr] partner row, -1 if none
 };
+typedef BjViewT<double> BjView;
 
-__device__ __forceinline__ double sym6(const double *a, int r, int c)
+template <typename T>
+__device__ __forceinline__ T sym6(const T *a, int r, int c)
 {
     if (r == c) return a[r];
     const int s = r + c;  // 1: xy, 2: xz, 3: yz
@@ -45,18 +48,19 @@ __device__ __forceinline__ double sym6(const double *a, int r, int c)
 }
 
 // w = M^-1 s on one unit: row u alone (nr = 1) or rows u, v of a pair (nr = 2).
-__device__ __forceinline__ void unit_apply(const BjView &m, int64_t u, int64_t v, int ku, int kv, const double (&s)[6],
-                                           int nr, double (&w)[6])
+template <typename T>
+__device__ __forceinline__ void unit_apply(const BjViewT<T> &m, int64_t u, int64_t v, int ku, int kv, const T (&s)[6],
+                                           int nr, T (&w)[6])
 {
     for (int h = 0; h < nr; ++h) {
         const int64_t row = h == 0 ? u : v;
         const int kk = h == 0 ? ku : kv;
-        const double *a = m.A + 6 * row;
-        const double *so = s + 3 * h, *sp = s + 3 * (1 - h);
+        const T *a = m.A + 6 * row;
+        const T *so = s + 3 * h, *sp = s + 3 * (1 - h);
         for (int c = 0; c < 3; ++c) {
-            double z = sym6(a, c, 0) * so[0] + sym6(a, c, 1) * so[1] + sym6(a, c, 2) * so[2];
+            T z = sym6(a, c, 0) * so[0] + sym6(a, c, 1) * so[1] + sym6(a, c, 2) * so[2];
             if (nr == 2) {
-                const double *b = m.B + 9 * kk + 3 * c;
+                const T *b = m.B + 9 * kk + 3 * c;
                 z += b[0] * sp[0] + b[1] * sp[1] + b[2] * sp[2];
             }
             w[3 * h + c] = z;
@@ -65,7 +69,8 @@ __device__ __forceinline__ void unit_apply(const BjView &m, int64_t u, int64_t v
 }
 
 // Unit of row u: false if u is the upper row of a pair (its lower row owns it).
-__device__ __forceinline__ bool unit_of(const BjView &m, int64_t u, int64_t &v, int &ku, int &kv, int &nr)
+template <typename T>
+__device__ __forceinline__ bool unit_of(const BjViewT<T> &m, int64_t u, int64_t &v, int &ku, int &kv, int &nr)
 {
     ku = m.fslot[u];
     v = ku >= 0 ? m.fpart[ku] : -1;
@@ -77,15 +82,16 @@ __device__ __forceinline__ bool unit_of(const BjView &m, int64_t u, int64_t &v, 
 
 __device__ __forceinline__ int64_t unit_dof(int64_t u, int64_t v, int e) { return 3 * (e < 3 ? u : v) + e % 3; }
 
-// out = M^-1 in (the Lanczos estimate).
-__global__ __launch_bounds__(WG) void k_ch_bj(int64_t Npad, BjView m, const double *__restrict__ in,
-                                              double *__restrict__ out)
+// out = M^-1 in (the Lanczos estimate, the AMG smoother of level 0; FP64 or FP32).
+template <typename T>
+__global__ __launch_bounds__(WG) void k_ch_bj(int64_t Npad, BjViewT<T> m, const T *__restrict__ in,
+                                              T *__restrict__ out)
 {
     for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < Npad; u += (int64_t)gridDim.x * blockDim.x) {
         int64_t v;
         int ku, kv, nr;
         if (!unit_of(m, u, v, ku, kv, nr)) continue;
-        double s[6] = {0, 0, 0, 0, 0, 0}, w[6];
+        T s[6] = {0, 0, 0, 0, 0, 0}, w[6];
         for (int e = 0; e < 3 * nr; ++e) s[e] = in[unit_dof(u, v, e)];
         unit_apply(m, u, v, ku, kv, s, nr, w);
         for (int e = 0; e < 3 * nr; ++e) out[unit_dof(u, v, e)] = w[e];
@@ -300,7 +306,7 @@ fg_status bj_lanczos(fg_system *S, int steps, std::vector<double> &a, std::vecto
     LAUNCH(k_ch_probe, (3 * S->N + WG - 1) / WG, WG, st, 3 * S->N, q);
     perm_in(S, 3, q, r, st);
     vmask(n, S->dir_u, r, st);
-    LAUNCH(k_ch_bj, grid_elems(S->Npad), WG, st, S->Npad, m, r, z);
+    LAUNCH(k_ch_bj<double>, grid_elems(S->Npad), WG, st, S->Npad, m, r, z);
     hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, st);
     double rho = 0;
     {
@@ -321,7 +327,7 @@ fg_status bj_lanczos(fg_system *S, int steps, std::vector<double> &a, std::vecto
         }
         const double alpha = rho / pq;
         vaxpby(n, -alpha, q, 1.0, r, st);
-        LAUNCH(k_ch_bj, grid_elems(S->Npad), WG, st, S->Npad, m, r, z);
+        LAUNCH(k_ch_bj<double>, grid_elems(S->Npad), WG, st, S->Npad, m, r, z);
         double rho2 = 0;
         {
             const double *A[1] = {r}, *B[1] = {z};
@@ -369,7 +375,13 @@ fg_status cheb_estimate(fg_system *S, hipStream_t st)
 
 void bj_apply(fg_system *S, const double *in, double *out, hipStream_t st)
 {
-    LAUNCH(k_ch_bj, grid_elems(S->Npad), WG, st, S->Npad, bj_view(S), in, out);
+    LAUNCH(k_ch_bj<double>, grid_elems(S->Npad), WG, st, S->Npad, bj_view(S), in, out);
+}
+
+void bj_apply32(fg_system *S, const float *in, float *out, hipStream_t st)
+{
+    const BjViewT<float> m{S->bjA32, S->bjB32, S->fslot, S->fpart};
+    LAUNCH(k_ch_bj<float>, grid_elems(S->Npad), WG, st, S->Npad, m, in, out);
 }
 
 fg_status cheb_interval_ready(fg_system *S, hipStream_t st)

@@ -75,15 +75,18 @@ fg_status cheb_interval_ready(fg_system *S, hipStream_t st);
 fg_status lanczos_bounds(fg_system *S, int steps, double *lo, double *hi, hipStream_t st);
 // Smoothed-aggregation AMG (fg_amg.hip): hierarchy for the current K (symbolic part
 // once per mesh, numeric part when K changed), PCG with its V-cycle on internal
-// vectors, and release.
+// vectors (f32: the cycle on FP32 copies of every level inside the FP64 CG), and
+// release.
 fg_status amg_ready(fg_system *S, hipStream_t st);
-fg_status amg_pcg(fg_system *S, const double *b, double *x, double tol, int64_t maxit, int64_t *iters, double *relres,
-                  hipStream_t st);
+fg_status amg_pcg(fg_system *S, const double *b, double *x, double tol, int64_t maxit, bool f32, int64_t *iters,
+                  double *relres, hipStream_t st);
 void amg_destroy(fg_system *S);
 void amg_levels(const fg_system *S, int *nlev, int64_t *nodes);  // nodes[6]
 fg_status amg_aggregates(const fg_system *S, int level, int32_t *out);  // host out, level's nodes
 // out = M^-1 in with the block-Jacobi data (bj_ready first).
 void bj_apply(fg_system *S, const double *in, double *out, hipStream_t st);
+// The same with the FP32 copy of the blocks (bj_ready32 first).
+void bj_apply32(fg_system *S, const float *in, float *out, hipStream_t st);
 
 // Length of S->bx: five BiCGStab work vectors and room for its device scalars.
 constexpr int64_t BX_TAIL = 16;

@@ -62,7 +62,47 @@ def test_amg_pcg_matches_oracle(n, dip, slip):
     assert 4 * info.iters < itb
 
 
-@pytest.mark.parametrize("cfg", ["cube8", "slip4"])
+@pytest.mark.parametrize("n,dip", [(12, 60.0), (16, 35.0)])
+def test_mixed_amg_reaches_the_oracle_solution(n, dip):
+    """FG_MIXED with the AMG preconditioner: FP64 CG whose V-cycle runs on FP32 copies
+    of the hierarchy.  Rounding the cycle perturbs the preconditioner, not the FP64
+    recurrence that decides the solution, so each solve to 1e-12 reaches the
+    oracle's FP64 AMG-PCG solution to 1e-9 (the bound of the FP64 cycle) with its
+    true residual (the oracle's product) within 1e-11, in at most 10% (+2) more
+    iterations.  A second right-hand side after a change of the tangent (a
+    displacement with slip points) checks that the FP32 copies follow K."""
+    from oracle import oracle as O
+    from paper_2410_17133_amd import fg
+    inst = I.make_instance(I.cube_config(n, dip_deg=dip, heterogeneous=True))
+    print(f"[case] mixed AMG {n}^3 dip {dip}", flush=True)
+    ctx = fg.Context(0)
+    S = fg.System.from_instance(ctx, inst)
+    S.assemble(inst.params, inst.E, inst.logk)
+    P = O.Problem(inst)
+    r = np.random.default_rng(60 + n)
+    U0 = np.zeros(3 * S.N)
+    U1 = r.normal(0.0, 2e-5 / n, 3 * S.N) * (1 - inst.dir_u)
+    S.tune("k_precond", 3)
+    try:
+        for k, U in enumerate((U0, U1)):
+            P.cohesive(U, np.zeros((P.nq, 2)))
+            S.cohesive_update(dev(U), dev(np.zeros(2 * S.nq)), dev(inst.t0.reshape(-1)))
+            hi0 = P.cheb_bounds(40, 1.1, 300)[1]
+            b = r.standard_normal(3 * S.N) * (1 - inst.dir_u)
+            xo, st, ito, _, _, _ = P.pcg_amg(b, hi0, tol=1e-12)
+            x, info = S.pcg_solve(fg.FG_K, dev(b), tol=1e-12, precision=fg.FG_MIXED)
+            x = x.cpu().numpy()
+            res = np.linalg.norm(b - P.spmv(O.K_TANGENT, x)) / np.linalg.norm(b)
+            print(f"[mixed amg] tangent {k}: iterations fp32 cycle {info.iters}, oracle fp64 cycle {ito}; "
+                  f"solution {relerr(x, xo):.1e}, true residual {res:.1e}", flush=True)
+            assert st == 0 and info.status == 0 and info.cycles == 1
+            assert info.iters <= 1.1 * ito + 2
+            assert relerr(x, xo) < 1e-9 and res <= 1e-11
+    finally:
+        S.tune("k_precond", 0)
+
+
+@pytest.mark.parametrize("cfg", ["cube8", "slip4", "cube8-mixed"])
 def test_step_with_amg_reaches_the_same_state(cfg):
     """A full implicit step (Newton, partitioned CG) whose FP64 K solves are
     preconditioned by the AMG V-cycle ends in the oracle's converged state; the
@@ -70,7 +110,7 @@ def test_step_with_amg_reaches_the_same_state(cfg):
     from oracle import oracle as O
     from paper_2410_17133_amd import fg
     import dataclasses
-    if cfg == "cube8":
+    if cfg.startswith("cube8"):
         inst = I.make_instance(I.cube_config(8))
     else:                                              # a higher injection rate: slip points in the step
         inst = I.make_instance(dataclasses.replace(I.cube_config(4), Q=4e-3))
@@ -87,7 +127,8 @@ def test_step_with_amg_reaches_the_same_state(cfg):
     try:
         U, Pp, die = dev(np.zeros(3 * N)), dev(np.zeros(N)), dev(np.zeros(2 * nq))
         trac, flag, info = S.step(U, Pp, die, dev(inst.t0.reshape(-1)), dev(inst.load), dev(inst.source),
-                                  newton_tol=1e-11, newton_max_iter=60, inner_k=fg.opts(tol=1e-13),
+                                  newton_tol=1e-11, newton_max_iter=60,
+                                  inner_k=fg.opts(tol=1e-13, precision=fg.FG_MIXED if "mixed" in cfg else fg.FG_F64),
                                   inner_p=fg.opts(tol=1e-13), outer_tol=1e-12)
     finally:
         S.tune("k_precond", 0)

@@ -97,6 +97,22 @@ def test_mixed_precision_solve_full_size(full):
           f"vs fp64 {relerr(xm, x64):.2e}", flush=True)
     assert im.status == 0 and res <= 1e-8
     assert relerr(xm, x64) < 1e-6
+    # the AMG preconditioner: FP64 CG with the V-cycle in FP32 against the FP64 cycle
+    S.tune("k_precond", 3)
+    try:
+        xa, ia = S.pcg_solve(fg.FG_K, dev(b), tol=1e-8)
+        xam, iam = S.pcg_solve(fg.FG_K, dev(b), tol=1e-8, precision=fg.FG_MIXED)
+    finally:
+        S.tune("k_precond", 0)
+    xa, xam = host(xa), host(xam)
+    res_a = np.linalg.norm(b - P.spmv(O.K_TANGENT, xa)) / np.linalg.norm(b)
+    res_am = np.linalg.norm(b - P.spmv(O.K_TANGENT, xam)) / np.linalg.norm(b)
+    print(f"[mixed full] AMG: fp64 cycle {ia.iters} iterations residual {res_a:.2e}; fp32 cycle {iam.iters} "
+          f"iterations residual {res_am:.2e}, vs fp64 point Jacobi {relerr(xam, x64):.2e}", flush=True)
+    assert ia.status == 0 and iam.status == 0 and iam.cycles == 1
+    assert res_a <= 1.01e-8 and res_am <= 1.01e-8
+    assert iam.iters <= 1.1 * ia.iters + 2
+    assert relerr(xam, x64) < 1e-6 and relerr(xa, x64) < 1e-6
 
 
 def test_converged_k_solve_full_size(full):
