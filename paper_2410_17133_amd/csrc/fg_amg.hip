@@ -57,17 +57,16 @@ struct AmgLevel {
     int64_t *rrow = nullptr;           // P^T: per aggregate, (node, P entry) in increasing node order
     int32_t *rnode = nullptr;
     int64_t *rent = nullptr;
+    double *rval = nullptr;            // [nrz bs 6] the P entries in P^T order (restriction)
     double *dinv = nullptr;            // [nn bs bs]
     double rho = 0;
-    // cycle vectors of the level: x, b (coarse levels), r residual, e post-smoothing
-    // correction, and the smoother's scratch d, s, w, t
-    double *x = nullptr, *b = nullptr, *r = nullptr, *e = nullptr, *t = nullptr, *d = nullptr, *s = nullptr,
-           *w = nullptr;
+    // cycle vectors of the level: x, b (coarse levels), r (A x, then the residual), and
+    // the smoother's d and t = A d
+    double *x = nullptr, *b = nullptr, *r = nullptr, *t = nullptr, *d = nullptr;
     // FP32 copies for the mixed-precision cycle (allocated on its first use): A and
     // dinv (coarse levels), P (every level but the coarsest), the cycle vectors
-    float *aval32 = nullptr, *dinv32 = nullptr, *pval32 = nullptr;
-    float *x32 = nullptr, *b32 = nullptr, *r32 = nullptr, *e32 = nullptr, *t32 = nullptr, *d32 = nullptr,
-          *s32 = nullptr, *w32 = nullptr;
+    float *aval32 = nullptr, *dinv32 = nullptr, *pval32 = nullptr, *rval32 = nullptr;
+    float *x32 = nullptr, *b32 = nullptr, *r32 = nullptr, *t32 = nullptr, *d32 = nullptr;
 };
 
 struct AmgData {
@@ -463,74 +462,152 @@ __global__ void k_amg_unit_empty(int64_t nc, const int64_t *__restrict__ crow, c
 
 // ------------------------------------------------------------ cycle kernels
 // T: double for the FP64 cycle, float for the FP32 cycle of the mixed-precision solve.
-template <int BS, typename T>
-__global__ void k_amg_spmv(int64_t nn, const int64_t *__restrict__ arow, const int32_t *__restrict__ acol,
-                           const T *__restrict__ aval, const T *__restrict__ x, T *y)
+//
+// y = A x with 6x6 blocks (the coarse levels): 8 H lanes per block row, lane group q
+// (H lanes) taking the row's blocks q, q + 8, ... (each block's 36 values contiguous,
+// so a group reads 8 consecutive blocks at once), lane h of the group rows 6h/H to
+// 6(h+1)/H - 1 of each (H = 2 for FP64 keeps a lane's share of a block in registers);
+// then a fixed-order xor reduction over the groups.
+template <typename T, int H>
+__global__ __launch_bounds__(WG) void k_amg_spmv6(int64_t nn, const int64_t *__restrict__ arow,
+                                                  const int32_t *__restrict__ acol, const T *__restrict__ aval,
+                                                  const T *__restrict__ x, T *__restrict__ y)
 {
-    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (g >= nn * BS) return;
-    const int64_t i = g / BS;
-    const int r = (int)(g - i * BS);
-    T s = 0;
-    for (int64_t o = arow[i]; o < arow[i + 1]; ++o) {
-        const T *m = aval + BS * BS * o + BS * r;
-        const T *xj = x + (int64_t)BS * acol[o];
-        for (int k = 0; k < BS; ++k) s += m[k] * xj[k];
+    constexpr int G = 8 * H, RL = 6 / H;
+    const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;   // uniform per G lanes
+    const int j = threadIdx.x & (G - 1);
+    const int h = j % H, q = j / H;
+    if (i >= nn) return;
+    T s[RL];
+    for (int r = 0; r < RL; ++r) s[r] = 0;
+    const int64_t o1 = arow[i + 1];
+    for (int64_t o = arow[i] + q; o < o1; o += 8) {
+        const T *m = aval + 36 * o + 6 * RL * h;
+        const T *xj = x + 6 * (int64_t)acol[o];
+        T xv[6];
+        for (int k = 0; k < 6; ++k) xv[k] = xj[k];
+        for (int r = 0; r < RL; ++r)
+            for (int k = 0; k < 6; ++k) s[r] += m[6 * r + k] * xv[k];
     }
-    y[g] = s;
+    T out = 0;
+    for (int r = 0; r < RL; ++r) {
+        for (int d = G / 2; d >= H; d >>= 1) s[r] += __shfl_xor(s[r], d, G);
+        if (r == q) out = s[r];
+    }
+    if (q < RL) y[6 * i + RL * h + q] = out;
 }
 
-// out = dinv x per node (6x6 blocks of the coarse levels), scaled by sc.
+// Degree-2 Chebyshev smoothing over the 6x6 diagonal blocks of a coarse level, one
+// kernel per step, a thread per scalar row.  step 0: d = D^-1 b / theta, then x = d
+// (acc: x += d).  step 1, on kd = A d: x += c2 D^-1 (b - kd) + c1 d.
 template <typename T>
-__global__ void k_amg_dapply(int64_t nn, const T *__restrict__ dinv, const T *__restrict__ x, T sc, T *out)
+__global__ void k_amg_dsmooth(int64_t nn, int step, int acc, const T *__restrict__ dinv, T inv_theta, T c1, T c2,
+                              const T *__restrict__ b, const T *__restrict__ kd, T *__restrict__ d, T *__restrict__ x)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= nn * 6) return;
+    const int64_t i = g / 6;
+    const int r = (int)(g - i * 6);
+    T w = 0;
+    for (int k = 0; k < 6; ++k) {
+        const T sk = step ? b[6 * i + k] - kd[6 * i + k] : b[6 * i + k];
+        w += dinv[36 * i + 6 * r + k] * sk;
+    }
+    if (step == 0) {
+        const T di = w * inv_theta;
+        d[g] = di;
+        x[g] = acc ? x[g] + di : di;
+    } else {
+        x[g] += c2 * w + c1 * d[g];
+    }
+}
+
+// The P entries in P^T order: rval(t) = pval(rent(t)), after every change of P.
+template <int BS>
+__global__ void k_amg_rfill(int64_t nrz, const int64_t *__restrict__ rent, const double *__restrict__ pval,
+                            double *__restrict__ rval)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= nrz * BS * 6) return;
+    const int64_t t = g / (BS * 6);
+    rval[g] = pval[BS * 6 * rent[t] + (g - t * BS * 6)];
+}
+
+// bc(I) = sum_{(i, e)} P_e^T r_i with the residual r = b - ax formed on the fly: LN
+// lanes per aggregate taking every LN-th entry of its P^T list (values stored in that
+// order, so the lanes read consecutive entries), then a fixed-order xor reduction;
+// lane c < 6 writes coarse DOF c.  A wavefront per aggregate (LN = 64): on level 0
+// (about 100 entries per aggregate) 16 lanes measured slower, each lane's entries
+// then being a dependent chain.
+template <int BS, typename T, int LN>
+__global__ __launch_bounds__(WG) void k_amg_restrict(int64_t nc, const int64_t *__restrict__ rrow,
+                                                     const int32_t *__restrict__ rnode, const T *__restrict__ rval,
+                                                     const T *__restrict__ b, const T *__restrict__ ax, T *bc)
+{
+    const int64_t I = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / LN;   // uniform per LN lanes
+    const int lane = threadIdx.x & (LN - 1);
+    if (I >= nc) return;
+    T s[6] = {0, 0, 0, 0, 0, 0};
+    const int64_t t1 = rrow[I + 1];
+    for (int64_t t = rrow[I] + lane; t < t1; t += LN) {
+        const T *p = rval + BS * 6 * t;
+        const T *bi = b + (int64_t)BS * rnode[t], *ai = ax + (int64_t)BS * rnode[t];
+        for (int k = 0; k < BS; ++k) {
+            const T rk = bi[k] - ai[k];
+            for (int c = 0; c < 6; ++c) s[c] += p[6 * k + c] * rk;
+        }
+    }
+    T out = 0;
+    for (int c = 0; c < 6; ++c) {
+        for (int o = LN / 2; o > 0; o >>= 1) s[c] += __shfl_xor(s[c], o, LN);
+        if (c == lane) out = s[c];
+    }
+    if (lane < 6) bc[6 * I + lane] = out;
+}
+
+// x_i += sum_{e in P row i} P_e xc(agg) on level 0 (3 rows per node): 4 lanes per node
+// taking every 4th entry of its P row (the node's entries contiguous, so the lanes
+// read consecutive entries), a fixed-order xor reduction, lane r < 3 updates row r.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_amg_prolong_add3(int64_t nn, const int64_t *__restrict__ prow,
+                                                         const int32_t *__restrict__ pcol, const T *__restrict__ pval,
+                                                         const T *__restrict__ xc, T *x)
+{
+    const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 2;   // uniform per 4 lanes
+    const int q = threadIdx.x & 3;
+    if (i >= nn) return;
+    T s[3] = {0, 0, 0};
+    const int64_t e1 = prow[i + 1];
+    for (int64_t e = prow[i] + q; e < e1; e += 4) {
+        const T *p = pval + 18 * e;
+        const T *xa = xc + 6 * (int64_t)pcol[e];
+        T xv[6];
+        for (int c = 0; c < 6; ++c) xv[c] = xa[c];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 6; ++c) s[r] += p[6 * r + c] * xv[c];
+    }
+    T out = 0;
+    for (int r = 0; r < 3; ++r) {
+        s[r] += __shfl_xor(s[r], 2, 4);
+        s[r] += __shfl_xor(s[r], 1, 4);
+        if (r == q) out = s[r];
+    }
+    if (q < 3) x[3 * i + q] += out;
+}
+
+// x_i += sum_{e in P row i} P_e xc(agg) on the coarse levels (6 rows per node): a
+// thread per scalar row.
+template <typename T>
+__global__ void k_amg_prolong_add6(int64_t nn, const int64_t *__restrict__ prow, const int32_t *__restrict__ pcol,
+                                   const T *__restrict__ pval, const T *__restrict__ xc, T *x)
 {
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (g >= nn * 6) return;
     const int64_t i = g / 6;
     const int r = (int)(g - i * 6);
     T s = 0;
-    for (int k = 0; k < 6; ++k) s += dinv[36 * i + 6 * r + k] * x[6 * i + k];
-    out[g] = sc * s;
-}
-
-// bc(I) = sum_{(i, e)} P_e^T r_i: one wavefront per aggregate, its lanes taking
-// every 64th entry of the aggregate's P^T list, then a fixed-order lane reduction.
-template <int BS, typename T>
-__global__ __launch_bounds__(WG) void k_amg_restrict(int64_t nc, const int64_t *__restrict__ rrow,
-                                                     const int32_t *__restrict__ rnode, const int64_t *__restrict__ rent,
-                                                     const T *__restrict__ pval, const T *__restrict__ r, T *bc)
-{
-    const int64_t I = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;   // uniform per wavefront
-    const int lane = threadIdx.x & 63;
-    if (I >= nc) return;
-    T s[6] = {0, 0, 0, 0, 0, 0};
-    const int64_t t1 = rrow[I + 1];
-    for (int64_t t = rrow[I] + lane; t < t1; t += 64) {
-        const T *p = pval + BS * 6 * rent[t];
-        const T *ri = r + (int64_t)BS * rnode[t];
-        for (int k = 0; k < BS; ++k) {
-            const T rk = ri[k];
-            for (int c = 0; c < 6; ++c) s[c] += p[6 * k + c] * rk;
-        }
-    }
-    for (int c = 0; c < 6; ++c)
-        for (int o = 32; o > 0; o >>= 1) s[c] += __shfl_down(s[c], o, 64);
-    if (lane == 0)
-        for (int c = 0; c < 6; ++c) bc[6 * I + c] = s[c];
-}
-
-// x_i += sum_{e in P row i} P_e xc(agg)
-template <int BS, typename T>
-__global__ void k_amg_prolong_add(int64_t nn, const int64_t *__restrict__ prow, const int32_t *__restrict__ pcol,
-                                  const T *__restrict__ pval, const T *__restrict__ xc, T *x)
-{
-    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (g >= nn * BS) return;
-    const int64_t i = g / BS;
-    const int r = (int)(g - i * BS);
-    T s = 0;
     for (int64_t e = prow[i]; e < prow[i + 1]; ++e) {
-        const T *p = pval + BS * 6 * e + 6 * r;
+        const T *p = pval + 36 * e + 6 * r;
         const T *xa = xc + 6 * (int64_t)pcol[e];
         for (int c = 0; c < 6; ++c) s += p[c] * xa[c];
     }
@@ -557,12 +634,6 @@ __global__ void k_amg_axpby32(int64_t n, float a, const float *__restrict__ x, f
     if (i < n) y[i] = a * x[i] + b * y[i];
 }
 
-__global__ void k_amg_scale32(int64_t n, float a, float *y)
-{
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) y[i] *= a;
-}
-
 // y = s x, FP32 to FP64 (the preconditioned residual of the mixed cycle).
 __global__ void k_amg_widen(int64_t n, double s, const float *__restrict__ x, double *__restrict__ y)
 {
@@ -575,8 +646,8 @@ inline int64_t nb(int64_t n) { return std::max<int64_t>((n + WG - 1) / WG, 1); }
 void free_level(AmgLevel &L)
 {
     void *p[] = {L.arow, L.acol, L.arid, L.aval, L.agg, L.q, L.prow, L.pcol, L.pval, L.wrow, L.wcol, L.wval,
-                 L.rrow, L.rnode, L.rent, L.dinv, L.x, L.b, L.r, L.e, L.t, L.d, L.s, L.w,
-                 L.aval32, L.dinv32, L.pval32, L.x32, L.b32, L.r32, L.e32, L.t32, L.d32, L.s32, L.w32};
+                 L.rrow, L.rnode, L.rent, L.rval, L.dinv, L.x, L.b, L.r, L.t, L.d,
+                 L.aval32, L.dinv32, L.pval32, L.rval32, L.x32, L.b32, L.r32, L.t32, L.d32};
     for (void *v : p)
         if (v) hipFree(v);
     L = AmgLevel{};
@@ -673,7 +744,7 @@ static fg_status amg_plan(fg_system *S)
         L.nn = rows;
         AMG_CK(dmal(&L.aval, L.nnzb * bs * bs));
         AMG_CK(dmal(&L.dinv, rows * bs * bs));
-        double **vec[] = {&L.x, &L.b, &L.r, &L.e, &L.t, &L.d, &L.s, &L.w};
+        double **vec[] = {&L.x, &L.b, &L.r, &L.t, &L.d};
         for (double **v : vec) AMG_CK(dmal(v, rows * bs));
         if (nn <= G->coarse_nodes || l == AMG_MAXLEV - 1) break;
         // aggregation on the level's node graph
@@ -778,6 +849,7 @@ static fg_status amg_plan(fg_system *S)
         AMG_CK(up(&L.rrow, rrow));
         AMG_CK(up(&L.rnode, rnode));
         AMG_CK(up(&L.rent, rent));
+        AMG_CK(dmal(&L.rval, L.nrz * bs * 6));
         // next level
         A_pat.swap(Cp);
         for (int64_t a = 0; a < na; ++a) {
@@ -858,6 +930,7 @@ static fg_status amg_numeric(fg_system *S, hipStream_t st)
         if (L.bs == 3) {
             LAUNCH((k_amg_prolong<3>), nb(L.nn), WG, st, L.nn, L.arow, L.acol, L.aval, L.agg, L.q, L.dinv, L.prow,
                    L.pcol, w, L.pval);
+            LAUNCH((k_amg_rfill<3>), nb(18 * L.nrz), WG, st, L.nrz, L.rent, L.pval, L.rval);
             LAUNCH((k_amg_ap<3>), nb(L.nn), WG, st, L.nn, L.arow, L.acol, L.aval, L.prow, L.pcol, L.pval, L.wrow,
                    L.wcol, L.wval);
             LAUNCH((k_amg_rap<3>), nb(C.nnzb), WG, st, C.nnzb, C.arid, C.acol, L.rrow, L.rnode, L.rent, L.pval,
@@ -865,6 +938,7 @@ static fg_status amg_numeric(fg_system *S, hipStream_t st)
         } else {
             LAUNCH((k_amg_prolong<6>), nb(L.nn), WG, st, L.nn, L.arow, L.acol, L.aval, L.agg, L.q, L.dinv, L.prow,
                    L.pcol, w, L.pval);
+            LAUNCH((k_amg_rfill<6>), nb(36 * L.nrz), WG, st, L.nrz, L.rent, L.pval, L.rval);
             LAUNCH((k_amg_ap<6>), nb(L.nn), WG, st, L.nn, L.arow, L.acol, L.aval, L.prow, L.pcol, L.pval, L.wrow,
                    L.wcol, L.wval);
             LAUNCH((k_amg_rap<6>), nb(C.nnzb), WG, st, C.nnzb, C.arid, C.acol, L.rrow, L.rnode, L.rent, L.pval,
@@ -952,7 +1026,7 @@ fg_status amg_ready(fg_system *S, hipStream_t st)
 static void free32(AmgData *G)
 {
     for (AmgLevel &L : G->L) {
-        float **p[] = {&L.aval32, &L.dinv32, &L.pval32, &L.x32, &L.b32, &L.r32, &L.e32, &L.t32, &L.d32, &L.s32, &L.w32};
+        float **p[] = {&L.aval32, &L.dinv32, &L.pval32, &L.rval32, &L.x32, &L.b32, &L.r32, &L.t32, &L.d32};
         for (float **v : p) {
             if (*v) hipFree(*v);
             *v = nullptr;
@@ -979,8 +1053,9 @@ static fg_status amg_ready32(fg_system *S, hipStream_t st)
             AmgLevel &L = G->L[l];
             const int64_t n = L.nn * L.bs;
             if (l > 0) ok = ok && !dmal(&L.aval32, L.nnzb * L.bs * L.bs) && !dmal(&L.dinv32, n * L.bs);
-            if (l < G->nlev - 1) ok = ok && !dmal(&L.pval32, L.npz * L.bs * 6);
-            float **vec[] = {&L.x32, &L.b32, &L.r32, &L.e32, &L.t32, &L.d32, &L.s32, &L.w32};
+            if (l < G->nlev - 1)
+                ok = ok && !dmal(&L.pval32, L.npz * L.bs * 6) && !dmal(&L.rval32, L.nrz * L.bs * 6);
+            float **vec[] = {&L.x32, &L.b32, &L.r32, &L.t32, &L.d32};
             for (float **v : vec) ok = ok && !dmal(v, n);
         }
         const int64_t n0 = 3 * S->Npad;
@@ -1001,7 +1076,10 @@ static fg_status amg_ready32(fg_system *S, hipStream_t st)
             to_f32(L.nnzb * L.bs * L.bs, 1.0, L.aval, L.aval32, st);
             to_f32(L.nn * L.bs * L.bs, 1.0, L.dinv, L.dinv32, st);
         }
-        if (l < G->nlev - 1) to_f32(L.npz * L.bs * 6, 1.0, L.pval, L.pval32, st);
+        if (l < G->nlev - 1) {
+            to_f32(L.npz * L.bs * 6, 1.0, L.pval, L.pval32, st);
+            to_f32(L.nrz * L.bs * 6, 1.0, L.rval, L.rval32, st);
+        }
     }
     to_f32(G->nco * G->nco, 1.0, G->cinv, G->cinv32, st);
     G->epoch32 = G->epoch;
@@ -1012,25 +1090,23 @@ static fg_status amg_ready32(fg_system *S, hipStream_t st)
 // One level's cycle arrays in the cycle's precision.
 template <typename T>
 struct Lv {
-    const T *aval, *dinv, *pval;
-    T *x, *b, *r, *e, *t, *d, *s, *w;
+    const T *aval, *dinv, *pval, *rval;
+    T *x, *b, *r, *t, *d;
 };
 static Lv<double> lv(const AmgLevel &L, double)
 {
-    return {L.aval, L.dinv, L.pval, L.x, L.b, L.r, L.e, L.t, L.d, L.s, L.w};
+    return {L.aval, L.dinv, L.pval, L.rval, L.x, L.b, L.r, L.t, L.d};
 }
 static Lv<float> lv(const AmgLevel &L, float)
 {
-    return {L.aval32, L.dinv32, L.pval32, L.x32, L.b32, L.r32, L.e32, L.t32, L.d32, L.s32, L.w32};
+    return {L.aval32, L.dinv32, L.pval32, L.rval32, L.x32, L.b32, L.r32, L.t32, L.d32};
 }
 static const double *cinv_of(const AmgData *G, double) { return G->cinv; }
 static const float *cinv_of(const AmgData *G, float) { return G->cinv32; }
 
-// Level 0 works on K itself: the library's product and block-Jacobi apply.
+// Level 0 works on K itself: the library's product and block-Jacobi smoothing.
 static void l0_mul(fg_system *S, const double *x, double *y, hipStream_t st) { spmv(S, FG_K, x, y, st); }
 static void l0_mul(fg_system *S, const float *x, float *y, hipStream_t st) { spmv_k32(S, x, y, st); }
-static void l0_minv(fg_system *S, const double *x, double *y, hipStream_t st) { bj_apply(S, x, y, st); }
-static void l0_minv(fg_system *S, const float *x, float *y, hipStream_t st) { bj_apply32(S, x, y, st); }
 static void axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t st)
 {
     vaxpby(n, a, x, b, y, st);
@@ -1039,8 +1115,6 @@ static void axpby(int64_t n, double a, const float *x, double b, float *y, hipSt
 {
     LAUNCH(k_amg_axpby32, nb(n), WG, st, n, (float)a, x, (float)b, y);
 }
-static void scale(int64_t n, double a, double *y, hipStream_t st) { vscale(n, a, y, st); }
-static void scale(int64_t n, double a, float *y, hipStream_t st) { LAUNCH(k_amg_scale32, nb(n), WG, st, n, (float)a, y); }
 
 // y = A_l x on level l.
 template <typename T>
@@ -1050,12 +1124,16 @@ static void amg_mul(fg_system *S, int l, const T *x, T *y, hipStream_t st)
     if (l == 0)
         l0_mul(S, x, y, st);
     else
-        LAUNCH((k_amg_spmv<6, T>), nb(L.nn * L.bs), WG, st, L.nn, L.arow, L.acol, lv(L, T()).aval, x, y);
+        LAUNCH((k_amg_spmv6<T, sizeof(T) == 8 ? 2 : 1>), nb((sizeof(T) == 8 ? 16 : 8) * L.nn), WG, st, L.nn, L.arow,
+               L.acol, lv(L, T()).aval, x, y);
 }
 
-// x = p(M^-1 A) M^-1 b, degree-2 Chebyshev over the level's block Jacobi (x, b on the level).
+// x = p(M^-1 A) M^-1 b (acc: x += p(M^-1 A) M^-1 b), degree-2 Chebyshev over the level's
+// block Jacobi on [hi/30, hi]: d0 = M^-1 b / theta, d1 = c1 d0 + c2 M^-1 (b - A d0),
+// x = d0 + d1 (level 0: the blocks of "k_precond" 1, hi as for the Chebyshev
+// preconditioner; below: 6x6 diagonal blocks, hi their Gershgorin bound).
 template <typename T>
-static void amg_smooth(fg_system *S, int l, const T *b, T *x, hipStream_t st)
+static void amg_smooth(fg_system *S, int l, const T *b, T *x, int acc, hipStream_t st)
 {
     AmgData *G = S->amg;
     AmgLevel &L = G->L[l];
@@ -1063,24 +1141,18 @@ static void amg_smooth(fg_system *S, int l, const T *b, T *x, hipStream_t st)
     const int64_t n = L.nn * L.bs;
     const double hi = l == 0 ? S->cheb_hi : L.rho, lo = hi / 30.0;
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
-    auto minv = [&](const T *in, T *out) {
+    const double rho0 = 1.0 / sigma, rho1 = 1.0 / (2.0 * sigma - rho0);
+    const double c1 = rho1 * rho0, c2 = 2.0 * rho1 / delta;
+    auto step = [&](int k) {
         if (l == 0)
-            l0_minv(S, in, out, st);
+            bj_smooth(S, k, acc, 1.0 / theta, c1, c2, b, v.t, v.d, x, st);
         else
-            LAUNCH((k_amg_dapply<T>), nb(n), WG, st, L.nn, v.dinv, in, (T)1, out);
+            LAUNCH((k_amg_dsmooth<T>), nb(n), WG, st, L.nn, k, acc, v.dinv, (T)(1.0 / theta), (T)c1, (T)c2, b, v.t,
+                   v.d, x);
     };
-    T *d = v.d, *s = v.s, *w = v.w, *kd = v.t;
-    minv(b, d);
-    scale(n, 1.0 / theta, d, st);
-    hipMemcpyAsync(x, d, n * sizeof(T), hipMemcpyDeviceToDevice, st);
-    hipMemcpyAsync(s, b, n * sizeof(T), hipMemcpyDeviceToDevice, st);
-    const double rho0 = 1.0 / sigma;
-    amg_mul(S, l, d, kd, st);
-    axpby(n, -1.0, kd, 1.0, s, st);
-    const double rho1 = 1.0 / (2.0 * sigma - rho0);
-    minv(s, w);
-    axpby(n, 2.0 * rho1 / delta, w, rho1 * rho0, d, st);
-    axpby(n, 1.0, d, 1.0, x, st);
+    step(0);
+    amg_mul(S, l, (const T *)v.d, v.t, st);
+    step(1);
 }
 
 template <typename T>
@@ -1095,22 +1167,20 @@ static void amg_vcycle(fg_system *S, int l, const T *b, T *x, hipStream_t st)
         return;
     }
     const Lv<T> c = lv(G->L[l + 1], T());
-    amg_smooth(S, l, b, x, st);                       // pre-smoothing from zero
-    amg_mul(S, l, (const T *)x, v.r, st);
-    axpby(n, 1.0, b, -1.0, v.r, st);                  // r = b - A x
+    amg_smooth(S, l, b, x, 0, st);                    // pre-smoothing from zero
+    amg_mul(S, l, (const T *)x, v.r, st);             // restriction of b - A x
     if (L.bs == 3)
-        LAUNCH((k_amg_restrict<3, T>), nb(64 * L.nc), WG, st, L.nc, L.rrow, L.rnode, L.rent, v.pval, v.r, c.b);
+        LAUNCH((k_amg_restrict<3, T, 64>), nb(64 * L.nc), WG, st, L.nc, L.rrow, L.rnode, v.rval, b, v.r, c.b);
     else
-        LAUNCH((k_amg_restrict<6, T>), nb(64 * L.nc), WG, st, L.nc, L.rrow, L.rnode, L.rent, v.pval, v.r, c.b);
+        LAUNCH((k_amg_restrict<6, T, 64>), nb(64 * L.nc), WG, st, L.nc, L.rrow, L.rnode, v.rval, b, v.r, c.b);
     amg_vcycle(S, l + 1, (const T *)c.b, c.x, st);
     if (L.bs == 3)
-        LAUNCH((k_amg_prolong_add<3, T>), nb(n), WG, st, L.nn, L.prow, L.pcol, v.pval, c.x, x);
+        LAUNCH((k_amg_prolong_add3<T>), nb(4 * L.nn), WG, st, L.nn, L.prow, L.pcol, v.pval, c.x, x);
     else
-        LAUNCH((k_amg_prolong_add<6, T>), nb(n), WG, st, L.nn, L.prow, L.pcol, v.pval, c.x, x);
+        LAUNCH((k_amg_prolong_add6<T>), nb(n), WG, st, L.nn, L.prow, L.pcol, v.pval, c.x, x);
     amg_mul(S, l, (const T *)x, v.r, st);
-    axpby(n, 1.0, b, -1.0, v.r, st);
-    amg_smooth(S, l, (const T *)v.r, v.e, st);       // post-smoothing on the residual
-    axpby(n, 1.0, v.e, 1.0, x, st);
+    axpby(n, 1.0, b, -1.0, v.r, st);                  // r = b - A x
+    amg_smooth(S, l, (const T *)v.r, x, 1, st);       // post-smoothing on the residual, added to x
 }
 
 fg_status amg_aggregates(const fg_system *S, int level, int32_t *out)

@@ -82,7 +82,7 @@ __device__ __forceinline__ bool unit_of(const BjViewT<T> &m, int64_t u, int64_t 
 
 __device__ __forceinline__ int64_t unit_dof(int64_t u, int64_t v, int e) { return 3 * (e < 3 ? u : v) + e % 3; }
 
-// out = M^-1 in (the Lanczos estimate, the AMG smoother of level 0; FP64 or FP32).
+// out = M^-1 in (the Lanczos estimate).
 template <typename T>
 __global__ __launch_bounds__(WG) void k_ch_bj(int64_t Npad, BjViewT<T> m, const T *__restrict__ in,
                                               T *__restrict__ out)
@@ -95,6 +95,37 @@ __global__ __launch_bounds__(WG) void k_ch_bj(int64_t Npad, BjViewT<T> m, const 
         for (int e = 0; e < 3 * nr; ++e) s[e] = in[unit_dof(u, v, e)];
         unit_apply(m, u, v, ku, kv, s, nr, w);
         for (int e = 0; e < 3 * nr; ++e) out[unit_dof(u, v, e)] = w[e];
+    }
+}
+
+// Degree-2 Chebyshev smoothing over block Jacobi, one kernel per step (level 0 of the
+// AMG cycle, FP64 or FP32).  step 0: d = M^-1 b / theta, then x = d (acc: x += d).
+// step 1, on kd = K d: x += c2 M^-1 (b - kd) + c1 d.  Each thread owns whole units.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_bj_smooth(int64_t Npad, int step, int acc, BjViewT<T> m, T inv_theta, T c1,
+                                                  T c2, const T *__restrict__ b, const T *__restrict__ kd,
+                                                  T *__restrict__ d, T *__restrict__ x)
+{
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < Npad; u += (int64_t)gridDim.x * blockDim.x) {
+        int64_t v;
+        int ku, kv, nr;
+        if (!unit_of(m, u, v, ku, kv, nr)) continue;
+        T s[6] = {0, 0, 0, 0, 0, 0}, w[6];
+        for (int e = 0; e < 3 * nr; ++e) {
+            const int64_t i = unit_dof(u, v, e);
+            s[e] = step ? b[i] - kd[i] : b[i];
+        }
+        unit_apply(m, u, v, ku, kv, s, nr, w);
+        for (int e = 0; e < 3 * nr; ++e) {
+            const int64_t i = unit_dof(u, v, e);
+            if (step == 0) {
+                const T di = w[e] * inv_theta;
+                d[i] = di;
+                x[i] = acc ? x[i] + di : di;
+            } else {
+                x[i] += c2 * w[e] + c1 * d[i];
+            }
+        }
     }
 }
 
@@ -378,10 +409,19 @@ void bj_apply(fg_system *S, const double *in, double *out, hipStream_t st)
     LAUNCH(k_ch_bj<double>, grid_elems(S->Npad), WG, st, S->Npad, bj_view(S), in, out);
 }
 
-void bj_apply32(fg_system *S, const float *in, float *out, hipStream_t st)
+void bj_smooth(fg_system *S, int step, int acc, double inv_theta, double c1, double c2, const double *b,
+               const double *kd, double *d, double *x, hipStream_t st)
+{
+    LAUNCH(k_bj_smooth<double>, grid_elems(S->Npad), WG, st, S->Npad, step, acc, bj_view(S), inv_theta, c1, c2, b, kd,
+           d, x);
+}
+
+void bj_smooth(fg_system *S, int step, int acc, double inv_theta, double c1, double c2, const float *b,
+               const float *kd, float *d, float *x, hipStream_t st)
 {
     const BjViewT<float> m{S->bjA32, S->bjB32, S->fslot, S->fpart};
-    LAUNCH(k_ch_bj<float>, grid_elems(S->Npad), WG, st, S->Npad, m, in, out);
+    LAUNCH(k_bj_smooth<float>, grid_elems(S->Npad), WG, st, S->Npad, step, acc, m, (float)inv_theta, (float)c1,
+           (float)c2, b, kd, d, x);
 }
 
 fg_status cheb_interval_ready(fg_system *S, hipStream_t st)

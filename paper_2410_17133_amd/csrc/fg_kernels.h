@@ -85,8 +85,14 @@ void amg_levels(const fg_system *S, int *nlev, int64_t *nodes);  // nodes[6]
 fg_status amg_aggregates(const fg_system *S, int level, int32_t *out);  // host out, level's nodes
 // out = M^-1 in with the block-Jacobi data (bj_ready first).
 void bj_apply(fg_system *S, const double *in, double *out, hipStream_t st);
-// The same with the FP32 copy of the blocks (bj_ready32 first).
-void bj_apply32(fg_system *S, const float *in, float *out, hipStream_t st);
+// One step of the AMG cycle's level-0 smoother (degree-2 Chebyshev over block Jacobi),
+// FP64 or FP32 (the FP32 copy of the blocks: bj_ready32 first).  step 0:
+// d = M^-1 b * inv_theta, x = d (acc: x += d); step 1, kd = K d:
+// x += c2 M^-1 (b - kd) + c1 d.
+void bj_smooth(fg_system *S, int step, int acc, double inv_theta, double c1, double c2, const double *b,
+               const double *kd, double *d, double *x, hipStream_t st);
+void bj_smooth(fg_system *S, int step, int acc, double inv_theta, double c1, double c2, const float *b,
+               const float *kd, float *d, float *x, hipStream_t st);
 
 // Length of S->bx: five BiCGStab work vectors and room for its device scalars.
 constexpr int64_t BX_TAIL = 16;
