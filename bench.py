@@ -492,7 +492,8 @@ def extra_adjoint(ctx, log):
 
 def extra_steps(ctx, log, nsteps=20):
     """The 20-step 64^3 trajectory (constant injection, the state U, P and inelastic slip
-    carried from step to step, inexact Newton as in the adjoint, block-Jacobi K solves),
+    carried from step to step, inexact Newton as in the adjoint, K solves by FP64 CG with the
+    AMG V-cycle in FP32),
     checkpointed, then the reverse sweep: the gradient of J = sum over the steps of the
     fault-slip and uplift objective w.r.t. ln k and E through the whole loop, slip state
     included."""
@@ -512,11 +513,12 @@ def extra_steps(ctx, log, nsteps=20):
     U, P, die = d(np.zeros(3 * S.N)), d(np.zeros(S.N)), d(np.zeros(2 * S.nq))
     t0, load, src = d(inst.t0.reshape(-1)), d(inst.load), d(inst.source)
     inner = fg.opts(tol=1e-4, check_every=64)
-    S.tune("k_precond", 1)
+    inner_k = fg.opts(tol=1e-4, check_every=64, precision=fg.FG_MIXED)
+    S.tune("k_precond", 3)
     steps, ck = [], []
     for k in range(nsteps):
         ts, (c, infos) = _timed(lambda: T.run(S, U, P, die, t0, load, src, 1, newton_tol=1e-8, newton_max_iter=60,
-                                              inner_k=inner, inner_p=inner, outer_tol=1e-2))
+                                              inner_k=inner_k, inner_p=inner, outer_tol=1e-2))
         ck += c
         info = infos[0]
         fl = S.cohesive_update(U, c[0][2], t0, write_tangent=False)[2].cpu().numpy()
@@ -539,16 +541,17 @@ def extra_steps(ctx, log, nsteps=20):
         return g, torch.zeros_like(Pn)
     # corrections solved loosely (outer 0.05, inner 1e-3); the defect tolerance sets the accuracy
     corr = fg.opts(tol=1e-3, check_every=64)
-    tr, (dE, dk, ainfos) = _timed(lambda: T.gradient(S, ck, t0, logk, grad_y, inner_k=corr, inner_p=corr,
+    corr_k = fg.opts(tol=1e-3, check_every=64, precision=fg.FG_MIXED)
+    tr, (dE, dk, ainfos) = _timed(lambda: T.gradient(S, ck, t0, logk, grad_y, inner_k=corr_k, inner_p=corr,
                                                      outer_tol=0.05, defect_tol=1e-8))
     S.tune("k_precond", 0)
     defect = [i.newton_iters for i in ainfos]
     log(f"reverse sweep over {nsteps} steps: {tr:.1f}s, defect iterations per step {defect}, "
         f"K iters {sum(i.inner_k_iters for i in ainfos)}")
     fwd = float(sum(s["s"] for s in steps))
-    return {"workload": f"cube64_dip60_hetero, {nsteps} consecutive 1 s steps (the 20-step trajectory); block-Jacobi "
-                        f"K solves; Newton 1e-8, outer 1e-2, inner 1e-4; reverse sweep: defect 1e-8, corrections "
-                        f"outer 0.05 inner 1e-3",
+    return {"workload": f"cube64_dip60_hetero, {nsteps} consecutive 1 s steps (the 20-step trajectory); K solves by "
+                        f"FP64 CG with the AMG V-cycle in FP32; Newton 1e-8, outer 1e-2, inner 1e-4; reverse sweep: "
+                        f"defect 1e-8, corrections outer 0.05 inner 1e-3",
             "steps": steps, "mean_step_s": float(np.mean([s["s"] for s in steps])), "forward_s": fwd,
             "reverse_s": tr, "reverse_defect_iters": defect, "gradients_per_s": 1.0 / tr,
             "forward_and_reverse_s": fwd + tr,

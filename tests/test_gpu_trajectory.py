@@ -160,3 +160,37 @@ def test_autograd_loop_gradient_equals_reverse_sweep(loop):
     J.backward()
     print(f"[autograd loop] dE {rel(host(E.grad), dE_o):.1e} dlnk {rel(host(logk.grad), dk_o):.1e}", flush=True)
     assert rel(host(E.grad), dE_o) < 1e-7 and rel(host(logk.grad), dk_o) < 1e-7
+
+
+def test_loop_with_mixed_amg_solves_matches_oracle(loop):
+    """The same 4-step loop and its reverse sweep with every K solve by the FP64 CG whose
+    AMG V-cycle runs in FP32 ("k_precond" 3 with FG_MIXED): states and gradient equal the
+    oracle's to the bounds of the point-Jacobi runs (1e-9, 1e-7), since the preconditioner
+    changes the iterations, not the solutions the tolerances fix; the AMG hierarchy's
+    values and their FP32 copies are rebuilt at every change of the tangent."""
+    inst, P, ck_o, S, ck, t0, fg, T = loop
+    uplift = I.uplift_nodes(inst, 8)
+    jg = objective(inst, uplift)
+    dE_o, dk_o = P.trajectory_gradient(ck_o, lambda n, U, Pp: (jg(U)[1], np.zeros(P.N)))
+    print("[mixed amg loop] oracle reverse sweep done", flush=True)
+    mk = fg.opts(tol=1e-14, max_iter=50000, precision=fg.FG_MIXED)
+    kw = tight(fg)
+    kw["inner_k"] = mk
+    S.tune("k_precond", 3)
+    try:
+        U, Pp, die = dev(np.zeros(3 * S.N)), dev(np.zeros(S.N)), dev(np.zeros(2 * S.nq))
+        ck2, infos = T.run(S, U, Pp, die, t0, dev(np.zeros(3 * S.N)), dev(inst.source), 4, **kw)
+        print(f"[mixed amg loop] forward loop done, K iterations {[i.inner_k_iters for i in infos]}", flush=True)
+        for n, ((Uo, Po, dpo, do), (Un, Pn, dp, d)) in enumerate(zip(ck_o, ck2)):
+            print(f"[mixed amg loop] step {n}: U {rel(host(Un), Uo):.1e} P {rel(host(Pn), Po):.1e}", flush=True)
+            assert rel(host(Un), Uo) < 1e-9 and rel(host(Pn), Po) < 1e-9
+            assert np.abs(host(d) - do.reshape(-1)).max() <= 1e-9 * max(np.abs(do).max(), 1e-300)
+        dE, dk, ainfos = T.gradient(S, ck2, t0, dev(inst.logk),
+                                    lambda n, Un, Pn: (dev(jg(host(Un))[1]), torch.zeros_like(Pn)),
+                                    inner_k=mk, inner_p=fg.opts(tol=1e-14, max_iter=50000), outer_tol=1e-13,
+                                    defect_tol=1e-12, max_defect_iters=100, log=lambda s: print(s, flush=True))
+    finally:
+        S.tune("k_precond", 0)
+    print(f"[mixed amg loop] dE {rel(host(dE), dE_o):.1e} dlnk {rel(host(dk), dk_o):.1e}", flush=True)
+    assert all(i.status == 0 for i in ainfos)
+    assert rel(host(dE), dE_o) < 1e-7 and rel(host(dk), dk_o) < 1e-7
