@@ -29,6 +29,7 @@
 #include <cmath>
 #include <cstring>
 #include <initializer_list>
+#include <thread>
 #include <vector>
 
 #include "fg_device.h"
@@ -91,6 +92,23 @@ namespace {
 
 // ------------------------------------------------------------ host symbolic set-up
 typedef std::vector<std::vector<int32_t>> Lists;
+
+// f(begin, end) over [0, n) split in contiguous ranges across up to 16 host threads
+// (one range below 4096 items); f writes only what its own items own.
+template <typename F>
+void par_for(int64_t n, F &&f)
+{
+    const unsigned hw = std::max(1u, std::min(std::thread::hardware_concurrency(), 16u));
+    const int64_t nt = std::min<int64_t>((int64_t)hw, (n + 4095) / 4096);
+    if (nt <= 1) {
+        f((int64_t)0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve((size_t)nt);
+    for (int64_t t = 0; t < nt; ++t) th.emplace_back([&f, n, nt, t] { f(n * t / nt, n * (t + 1) / nt); });
+    for (std::thread &x : th) x.join();
+}
 
 // The three aggregation passes (see the file comment); twin[i] the other lip of a
 // fault pair or -1 (level 0 only).  Returns the number of aggregates.
@@ -169,7 +187,8 @@ void tentative(int bs, int64_t nn, int64_t na, const std::vector<int32_t> &agg, 
     for (int64_t i = 0; i < nn; ++i) mem[agg[i]].push_back((int32_t)i);
     Q.assign(nn * bs * 6, 0.0);
     Bc.assign(na * 36, 0.0);
-    for (int64_t a = 0; a < na; ++a) {
+    par_for(na, [&](int64_t a0, int64_t a1) {
+    for (int64_t a = a0; a < a1; ++a) {
         const int64_t rows = (int64_t)mem[a].size() * bs;
         std::vector<double> M(rows * 6);
         for (size_t t = 0; t < mem[a].size(); ++t)
@@ -203,6 +222,7 @@ void tentative(int bs, int64_t nn, int64_t na, const std::vector<int32_t> &agg, 
                 for (int k = 0; k < 6; ++k) Q[((int64_t)mem[a][t] * bs + r) * 6 + k] = M[(t * bs + r) * 6 + k];
         std::memcpy(&Bc[a * 36], R, sizeof R);
     }
+    });
 }
 
 void sorted_union(std::vector<int32_t> &v)
@@ -233,14 +253,20 @@ fg_status dmal(T **p, int64_t n)
     return FG_OK;
 }
 
-// CSR of per-row sorted lists.
-void to_csr(const Lists &l, std::vector<int64_t> &row, std::vector<int32_t> &col)
+// CSR of per-row sorted lists; row r is list perm[r] (empty where perm[r] < 0), or
+// list r without perm.
+void to_csr(const Lists &l, std::vector<int64_t> &row, std::vector<int32_t> &col, int64_t nrows = -1,
+            const int32_t *perm = nullptr)
 {
-    row.assign(l.size() + 1, 0);
-    for (size_t i = 0; i < l.size(); ++i) row[i + 1] = row[i] + (int64_t)l[i].size();
-    col.clear();
-    col.reserve(row.back());
-    for (const auto &v : l) col.insert(col.end(), v.begin(), v.end());
+    if (nrows < 0) nrows = (int64_t)l.size();
+    auto src = [&](int64_t r) { return perm ? perm[r] : (int32_t)r; };
+    row.assign(nrows + 1, 0);
+    for (int64_t r = 0; r < nrows; ++r) row[r + 1] = row[r] + (src(r) >= 0 ? (int64_t)l[src(r)].size() : 0);
+    col.resize((size_t)row.back());
+    par_for(nrows, [&](int64_t r0, int64_t r1) {
+        for (int64_t r = r0; r < r1; ++r)
+            if (src(r) >= 0) std::copy(l[src(r)].begin(), l[src(r)].end(), col.begin() + row[r]);
+    });
 }
 
 // ------------------------------------------------------------ numeric kernels
@@ -682,32 +708,36 @@ static fg_status amg_plan(fg_system *S)
     std::vector<int32_t> twin(N, -1);
     std::vector<double> xyz(3 * N);
     std::vector<uint8_t> held(3 * N);
-    for (int64_t r = 0; r < Npad; ++r) {
-        const int32_t i = P.perm[r];
-        if (i < 0) continue;
-        const int64_t base = P.slice_ptr[r / SLICE] + r % SLICE;
-        for (int j = 0; j < P.rowlen[r]; ++j) {
-            const int32_t c = P.perm[P.col[base + (int64_t)j * SLICE]];
-            if (c != i && c >= 0) adj[i].push_back(c);
+    par_for(Npad, [&](int64_t r0, int64_t r1) {   // row r fills node perm[r] only
+        for (int64_t r = r0; r < r1; ++r) {
+            const int32_t i = P.perm[r];
+            if (i < 0) continue;
+            const int64_t base = P.slice_ptr[r / SLICE] + r % SLICE;
+            for (int j = 0; j < P.rowlen[r]; ++j) {
+                const int32_t c = P.perm[P.col[base + (int64_t)j * SLICE]];
+                if (c != i && c >= 0) adj[i].push_back(c);
+            }
+            sorted_union(adj[i]);
+            const int32_t k = P.fslot.empty() ? -1 : P.fslot[r];
+            if (k >= 0 && P.fpart[k] >= 0) twin[i] = P.perm[P.fpart[k]];
+            for (int c = 0; c < 3; ++c) {
+                xyz[3 * i + c] = P.xyz[3 * r + c];
+                held[3 * i + c] = P.dir_u[3 * r + c];
+            }
         }
-        sorted_union(adj[i]);
-        const int32_t k = P.fslot.empty() ? -1 : P.fslot[r];
-        if (k >= 0 && P.fpart[k] >= 0) twin[i] = P.perm[P.fpart[k]];
-        for (int c = 0; c < 3; ++c) {
-            xyz[3 * i + c] = P.xyz[3 * r + c];
-            held[3 * i + c] = P.dir_u[3 * r + c];
-        }
-    }
+    });
     for (int64_t i = 0; i < N; ++i)
         if (twin[i] >= 0 && twin[twin[i]] != i) twin[i] = -1;
     std::vector<double> B(N * 18, 0.0);
     int64_t nn = N;
     int bs = 3;
-    Lists A_pat = adj;   // per node, neighbours and itself, sorted (built below)
-    for (int64_t i = 0; i < N; ++i) {
-        A_pat[i].push_back((int32_t)i);
-        sorted_union(A_pat[i]);
-    }
+    Lists A_pat(N);   // per node, neighbours and itself, sorted
+    par_for(N, [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i) {
+            A_pat[i] = adj[i];
+            A_pat[i].insert(std::lower_bound(A_pat[i].begin(), A_pat[i].end(), (int32_t)i), (int32_t)i);
+        }
+    });
     fg_status st = FG_OK;
 #define AMG_CK(x)                         \
     do {                                  \
@@ -747,13 +777,16 @@ static fg_status amg_plan(fg_system *S)
         double **vec[] = {&L.x, &L.b, &L.r, &L.t, &L.d};
         for (double **v : vec) AMG_CK(dmal(v, rows * bs));
         if (nn <= G->coarse_nodes || l == AMG_MAXLEV - 1) break;
-        // aggregation on the level's node graph
-        Lists nb_l(nn);
-        for (int64_t i = 0; i < nn; ++i)
-            for (int32_t j : A_pat[i])
-                if (j != i) nb_l[i].push_back(j);
+        // aggregation on the level's node graph (level 0: adj, the neighbours without self)
+        Lists nb_l(l == 0 ? 0 : nn);
+        if (l > 0)
+            par_for(nn, [&](int64_t i0, int64_t i1) {
+                for (int64_t i = i0; i < i1; ++i)
+                    for (int32_t j : A_pat[i])
+                        if (j != i) nb_l[i].push_back(j);
+            });
         std::vector<int32_t> agg;
-        const int64_t na = aggregate(nn, nb_l, l == 0 ? &twin : nullptr, agg);
+        const int64_t na = aggregate(nn, l == 0 ? adj : nb_l, l == 0 ? &twin : nullptr, agg);
         L.nc = na;
         if (l == 0) {
             std::vector<double> cen(3 * na, 0.0);
@@ -774,43 +807,59 @@ static fg_status amg_plan(fg_system *S)
         }
         std::vector<double> Q, Bc;
         tentative(bs, nn, na, agg, B, Q, Bc);
-        // patterns of P, W = A P and A_c = P^T W (entries touched by the products)
+        // patterns of P, W = A P and A_c = P^T W (entries touched by the products): sorted
+        // unions, W's and A_c's by a per-thread marker over the aggregates
         Lists Pp(nn), Wp(nn), Cp(na);
-        for (int64_t i = 0; i < nn; ++i) {
-            for (int32_t j : A_pat[i]) Pp[i].push_back(agg[j]);
-            sorted_union(Pp[i]);
-        }
-        for (int64_t i = 0; i < nn; ++i) {
-            for (int32_t j : A_pat[i]) Wp[i].insert(Wp[i].end(), Pp[j].begin(), Pp[j].end());
-            sorted_union(Wp[i]);
-        }
+        par_for(nn, [&](int64_t i0, int64_t i1) {
+            for (int64_t i = i0; i < i1; ++i) {
+                for (int32_t j : A_pat[i]) Pp[i].push_back(agg[j]);
+                sorted_union(Pp[i]);
+            }
+        });
+        par_for(nn, [&](int64_t i0, int64_t i1) {
+            std::vector<int32_t> mark((size_t)na, -1);
+            for (int64_t i = i0; i < i1; ++i) {
+                for (int32_t j : A_pat[i])
+                    for (int32_t a : Pp[j])
+                        if (mark[a] != (int32_t)i) {
+                            mark[a] = (int32_t)i;
+                            Wp[i].push_back(a);
+                        }
+                std::sort(Wp[i].begin(), Wp[i].end());
+            }
+        });
         std::vector<std::vector<std::pair<int32_t, int64_t>>> Rl(na);   // (node, P entry), increasing node
         std::vector<int64_t> prow_c(nn + 1, 0);
         for (int64_t i = 0; i < nn; ++i) prow_c[i + 1] = prow_c[i] + (int64_t)Pp[i].size();
         for (int64_t i = 0; i < nn; ++i)
-            for (size_t t = 0; t < Pp[i].size(); ++t) {
-                Rl[Pp[i][t]].push_back({(int32_t)i, prow_c[i] + (int64_t)t});
-                Cp[Pp[i][t]].insert(Cp[Pp[i][t]].end(), Wp[i].begin(), Wp[i].end());
+            for (size_t t = 0; t < Pp[i].size(); ++t) Rl[Pp[i][t]].push_back({(int32_t)i, prow_c[i] + (int64_t)t});
+        par_for(na, [&](int64_t a0, int64_t a1) {
+            std::vector<int32_t> mark((size_t)na, -1);
+            for (int64_t a = a0; a < a1; ++a) {
+                for (const auto &pr : Rl[a])
+                    for (int32_t c : Wp[pr.first])
+                        if (mark[c] != (int32_t)a) {
+                            mark[c] = (int32_t)a;
+                            Cp[a].push_back(c);
+                        }
+                std::sort(Cp[a].begin(), Cp[a].end());
             }
-        for (auto &v : Cp) sorted_union(v);
+        });
         // to the device; level 0 rows go to internal order
         std::vector<int64_t> prow, wrow, rrow(na + 1, 0), rent;
         std::vector<int32_t> pcol, wcol, rnode, aggd;
         std::vector<double> qd;
         if (l == 0) {
-            Lists Pi(Npad), Wi(Npad);
             std::vector<int32_t> ag(Npad, -1);
             qd.assign(Npad * 18, 0.0);
             for (int64_t r = 0; r < Npad; ++r) {
                 const int32_t i = P.perm[r];
                 if (i < 0) continue;
-                Pi[r] = Pp[i];
-                Wi[r] = Wp[i];
                 ag[r] = agg[i];
                 std::memcpy(&qd[r * 18], &Q[(int64_t)i * 18], 18 * sizeof(double));
             }
-            to_csr(Pi, prow, pcol);
-            to_csr(Wi, wrow, wcol);
+            to_csr(Pp, prow, pcol, Npad, P.perm.data());
+            to_csr(Wp, wrow, wcol, Npad, P.perm.data());
             aggd = ag;
             // P^T lists: internal row and internal P entry, in increasing caller node order
             for (int64_t a = 0; a < na; ++a) {
