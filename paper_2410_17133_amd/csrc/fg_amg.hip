@@ -1306,13 +1306,13 @@ fg_status amg_pcg(fg_system *S, const double *b, double *x, double tol, int64_t 
         if (!(bn > 0)) return std::isfinite(bn) ? FG_OK : FG_ERR_NAN;
     }
     hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, st);
+    double rr;   // r.r, taken in the same reduction as r.z after every update
+    {
+        const double *A[1] = {r};
+        vdots(S, n, 1, A, A, &rr, st);
+    }
     int64_t it = 0;
     for (;;) {
-        double rr;
-        {
-            const double *A[1] = {r};
-            vdots(S, n, 1, A, A, &rr, st);
-        }
         const double rel = std::sqrt(rr) / bn;
         *relres = rel;
         if (!std::isfinite(rel)) {
@@ -1342,14 +1342,18 @@ fg_status amg_pcg(fg_system *S, const double *b, double *x, double tol, int64_t 
         precond(std::sqrt(rr));
         double rho2, rz0 = 0.0;
         if (f32) {
+            double d3[3];
+            const double *A[3] = {r, r, r}, *B3[3] = {z, r, z0};
+            vdots(S, n, 3, A, B3, d3, st);
+            rho2 = d3[0];
+            rr = d3[1];
+            rz0 = d3[2];
+        } else {
             double d2[2];
-            const double *A[2] = {r, r}, *B2[2] = {z, z0};
+            const double *A[2] = {r, r}, *B2[2] = {z, r};
             vdots(S, n, 2, A, B2, d2, st);
             rho2 = d2[0];
-            rz0 = d2[1];
-        } else {
-            const double *A[1] = {r}, *B1[1] = {z};
-            vdots(S, n, 1, A, B1, &rho2, st);
+            rr = d2[1];
         }
         const double be = (rho2 - rz0) / rho;
         rho = rho2;
