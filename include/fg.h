@@ -478,7 +478,9 @@ fg_status fg_group_stats(const fg_system *sys, int64_t *iters_h, double *relres_
  *               (BiCGStab, the transposed exact tangent) instead of the
  *               symmetric tangent: the same multipliers (the refinement runs on
  *               the true residual of the exact transposed system either way) in
- *               fewer corrections.  fg_pcg_solve always uses the symmetric
+ *               fewer corrections.  If a correction breaks down (the Schur
+ *               complement of K_t + N^T need not be positive definite at slip
+ *               points), it and the later ones use the symmetric tangent.  fg_pcg_solve always uses the symmetric
  *               tangent; mixed-precision K solves stay symmetric.
  *   "cheb_degree": degree of the Chebyshev polynomial, 1 to 16 (default 4;
  *               1 is block Jacobi scaled by 1/theta: same iterates).

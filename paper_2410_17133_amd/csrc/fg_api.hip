@@ -960,6 +960,18 @@ static fg_status adjoint_core(fg_system *S, const double *die_n, const double *t
     while (k < max_defect_iters) {
         fg_solve_info sk{};
         fg_status s = prevost(S, r1, r2, dmu, dlp, ok, op, outer_tol, 1000, &sk, st);
+        if (s == FG_ERR_BREAKDOWN && S->exact_tangent == 2) {
+            // with K_t + N^T the Schur complement's symmetric part can be indefinite at
+            // slip points (d.S d <= 0): redo this correction, and the later ones, with the
+            // symmetric tangent; the true residual above still carries N^T, so the fixed
+            // point is the same
+            S->exact_tangent = 0;
+            outer += sk.outer_iters;
+            kit += sk.inner_k_iters;
+            ait += sk.inner_a22_iters;
+            sk = fg_solve_info{};
+            s = prevost(S, r1, r2, dmu, dlp, ok, op, outer_tol, 1000, &sk, st);
+        }
         outer += sk.outer_iters;
         kit += sk.inner_k_iters;
         ait += sk.inner_a22_iters;
