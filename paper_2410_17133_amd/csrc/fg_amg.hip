@@ -106,7 +106,12 @@ void par_for(int64_t n, F &&f)
     }
     std::vector<std::thread> th;
     th.reserve((size_t)nt);
-    for (int64_t t = 0; t < nt; ++t) th.emplace_back([&f, n, nt, t] { f(n * t / nt, n * (t + 1) / nt); });
+    int64_t t = 0;
+    try {
+        for (; t < nt; ++t) th.emplace_back([&f, n, nt, t] { f(n * t / nt, n * (t + 1) / nt); });
+    } catch (...) {   // no thread to be had: the remaining ranges on this one
+        for (; t < nt; ++t) f(n * t / nt, n * (t + 1) / nt);
+    }
     for (std::thread &x : th) x.join();
 }
 
