@@ -160,21 +160,25 @@ def test_amg_on_a_mesh_below_the_coarsening_threshold_is_a_direct_solve():
     try:
         gl, gnodes = S.amg_levels()
         x, info = S.pcg_solve(fg.FG_K, dev(b), tol=1e-12)
+        # the FP32 cycle: the exact inverse rounded to FP32 inside the FP64 CG
+        xm, im = S.pcg_solve(fg.FG_K, dev(b), tol=1e-12, precision=fg.FG_MIXED)
     finally:
         S.tune("k_precond", 0)
-    x = x.cpu().numpy()
+    x, xm = x.cpu().numpy(), xm.cpu().numpy()
     print(f"[amg one level] levels gpu {gl} oracle {levels}; iterations gpu {info.iters} oracle {ito}; "
-          f"solution {relerr(x, xo):.1e}", flush=True)
+          f"solution {relerr(x, xo):.1e}; FP32 cycle {im.iters} iterations, solution {relerr(xm, xo):.1e}",
+          flush=True)
     assert gl == levels == 1 and list(gnodes) == list(nodes)
     assert info.status == 0 and st == 0 and info.iters <= 2 and abs(info.iters - ito) <= 1
     assert relerr(x, xo) < 1e-9
+    assert im.status == 0 and im.iters <= 8 and relerr(xm, xo) < 1e-9
 
 
 def test_amg_edge_cases():
     """A zero right-hand side (x = 0 at once), an iteration cap (FG_NOT_CONVERGED with
     the iterate so far, as the oracle's capped AMG-PCG), a new "amg_coarse" (the
     hierarchy rebuilt, as the oracle builds it with the same threshold) and
-    out-of-range knobs (rejected)."""
+    out-of-range knobs (rejected); the first three with the FP32 cycle too."""
     from oracle import oracle as O
     from paper_2410_17133_amd import fg
     inst = I.make_instance(I.cube_config(12, dip_deg=60.0, heterogeneous=True))
@@ -189,12 +193,15 @@ def test_amg_edge_cases():
     b = np.random.default_rng(3).standard_normal(3 * S.N) * (1 - inst.dir_u)
     S.tune("k_precond", 3)
     try:
-        x0, i0 = S.pcg_solve(fg.FG_K, dev(np.zeros(3 * S.N)), tol=1e-10)
-        assert i0.status == 0 and i0.iters == 0 and not x0.abs().max().item()
+        for prec in (fg.FG_F64, fg.FG_MIXED):
+            x0, i0 = S.pcg_solve(fg.FG_K, dev(np.zeros(3 * S.N)), tol=1e-10, precision=prec)
+            assert i0.status == 0 and i0.iters == 0 and not x0.abs().max().item()
         xc, ic = S.pcg_solve(fg.FG_K, dev(b), tol=1e-14, max_iter=7)
         xoc, stc, itc, _, _, _ = P.pcg_amg(b, hi0, tol=1e-14, maxit=7)
         assert ic.status == fg.FG_NOT_CONVERGED and ic.iters == itc == 7 and stc == 1
         assert relerr(xc.cpu().numpy(), xoc) < 1e-6
+        _, icm = S.pcg_solve(fg.FG_K, dev(b), tol=1e-14, max_iter=7, precision=fg.FG_MIXED)
+        assert icm.status == fg.FG_NOT_CONVERGED and icm.iters == 7
         levels_64 = S.amg_levels()
         S.tune("amg_coarse", 200)                   # coarsening stops one level earlier
         gl, gnodes = S.amg_levels()
@@ -202,6 +209,9 @@ def test_amg_edge_cases():
         assert gl == levels < levels_64[0] and list(gnodes) == list(nodes)
         x, info = S.pcg_solve(fg.FG_K, dev(b), tol=1e-12)
         assert info.status == 0 and abs(info.iters - ito) <= 1
+        xm, im = S.pcg_solve(fg.FG_K, dev(b), tol=1e-12, precision=fg.FG_MIXED)   # FP32 copies of the new hierarchy
+        assert im.status == 0 and im.iters <= 1.1 * ito + 2
+        assert relerr(xm.cpu().numpy(), x.cpu().numpy()) < 1e-9
         for bad in (0, 1001):
             with pytest.raises(fg.FgError):
                 S.tune("amg_coarse", bad)
