@@ -461,7 +461,10 @@ fg_status fg_group_stats(const fg_system *sys, int64_t *iters_h, double *relres_
  *               blocks of stage 1 on [hi/30, hi] with hi as for stage 2; below:
  *               6x6 blocks on [rho/30, rho]).  The patterns are built on the host
  *               once per mesh, the values on the GPU after every change of K;
- *               other solves behave as with 1.  FG_MIXED single-right-hand-side
+ *               the BiCGStab of fg_exact_solve and of the exact-tangent solves
+ *               (see "exact_tangent") is preconditioned by one FP64 V-cycle of
+ *               the same hierarchy (built on the symmetric tangent K_t); other
+ *               solves behave as with 1.  FG_MIXED single-right-hand-side
  *               K solves run the same FP64 CG with the V-cycle in FP32: every
  *               level's values rounded once per change of K (level 0: K's FP32
  *               copy and the FP32 blocks of stage 1), the cycle's input scaled

@@ -1237,6 +1237,10 @@ static void amg_vcycle(fg_system *S, int l, const T *b, T *x, hipStream_t st)
     amg_smooth(S, l, (const T *)v.r, x, 1, st);       // post-smoothing on the residual, added to x
 }
 
+// z = B r, one FP64 V-cycle on the hierarchy of the current K (after amg_ready); the
+// preconditioner of the exact-tangent BiCGStab (r, z internal vectors, not the AMG's).
+void amg_apply(fg_system *S, const double *r, double *z, hipStream_t st) { amg_vcycle(S, 0, r, z, st); }
+
 fg_status amg_aggregates(const fg_system *S, int level, int32_t *out)
 {
     const AmgData *G = S->amg;

@@ -7,7 +7,8 @@
 //   (N x)_a = +-sum_q w N_a(q) (-f k_n tau_q) (n . jump(x)(q))  on the + / - lip,
 // the transpose of the N^T product of the adjoint.  K_t + N is solved by BiCGStab
 // (van der Vorst, SIAM J. Sci. Stat. Comput. 13, 1992) with the K_t preconditioner
-// (point or block Jacobi) applied on the right.
+// (point or block Jacobi, or a V-cycle of the AMG hierarchy of K_t) applied on the
+// right.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -275,7 +276,9 @@ __global__ void k_dmul(int64_t n, const double *__restrict__ d, const double *__
 void precond(fg_system *S, const double *x, double *y, hipStream_t st)
 {
     const int64_t n = 3 * S->Npad;
-    if (S->k_precond)
+    if (S->k_precond == 3)
+        amg_apply(S, x, y, st);
+    else if (S->k_precond)
         bj_apply(S, x, y, st);
     else
         LAUNCH(k_dmul, grid_elems(n), WG, st, n, S->dinvK, x, y);
@@ -314,7 +317,10 @@ fg_status bicgstab_exact(fg_system *S, const double *b, double *x, double tol, i
     const int64_t n = 3 * S->Npad;
     *iters = 0;
     *relres = 0;
-    if (S->k_precond) {
+    if (S->k_precond == 3) {   // the V-cycle of the symmetric tangent (amg_ready checks the blocks)
+        const fg_status e = amg_ready(S, st);
+        if (e) return e;
+    } else if (S->k_precond) {
         bj_ready(S, st);
         if (S->bj_singular) {
             set_error("fg_exact_solve: a diagonal or fault-pair block of K is singular (block Jacobi)");
@@ -335,8 +341,11 @@ fg_status bicgstab_exact(fg_system *S, const double *b, double *x, double tol, i
     fg_status e = check_hip("fg_exact_solve init");
     if (e) return e;
     BiScalars h{};
+    // the kernels stop at the device's flag, the preconditioner does not: with the
+    // V-cycle (two per iteration) the flag is read after every iteration
+    const int batch = S->k_precond == 3 ? 1 : 16;
     for (int64_t k = 0;;) {
-        for (int j = 0; j < 16; ++j, ++k) {
+        for (int j = 0; j < batch; ++j, ++k) {
             const int par = (int)(k & 1);
             LAUNCH(k_bi_p, gv, WG, st, n, par, (int)(k == 0), tol, r, p, v, part, stride, gv, sc);
             precond(S, p, ph, st);

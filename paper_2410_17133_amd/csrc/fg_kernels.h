@@ -80,6 +80,7 @@ fg_status lanczos_bounds(fg_system *S, int steps, double *lo, double *hi, hipStr
 fg_status amg_ready(fg_system *S, hipStream_t st);
 fg_status amg_pcg(fg_system *S, const double *b, double *x, double tol, int64_t maxit, bool f32, int64_t *iters,
                   double *relres, hipStream_t st);
+void amg_apply(fg_system *S, const double *r, double *z, hipStream_t st);   // one FP64 V-cycle
 void amg_destroy(fg_system *S);
 void amg_levels(const fg_system *S, int *nlev, int64_t *nodes);  // nodes[6]
 fg_status amg_aggregates(const fg_system *S, int level, int32_t *out);  // host out, level's nodes

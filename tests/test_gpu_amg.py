@@ -102,11 +102,13 @@ def test_mixed_amg_reaches_the_oracle_solution(n, dip):
         S.tune("k_precond", 0)
 
 
-@pytest.mark.parametrize("cfg", ["cube8", "slip4", "cube8-mixed"])
+@pytest.mark.parametrize("cfg", ["cube8", "slip4", "cube8-mixed", "slip4-exact"])
 def test_step_with_amg_reaches_the_same_state(cfg):
     """A full implicit step (Newton, partitioned CG) whose FP64 K solves are
     preconditioned by the AMG V-cycle ends in the oracle's converged state; the
-    hierarchy's values are rebuilt at every change of the tangent."""
+    hierarchy's values are rebuilt at every change of the tangent.  -mixed: the
+    V-cycle in FP32; -exact: Newton on the exact tangent K_t + N, whose BiCGStab
+    solves take the V-cycle of K_t as preconditioner."""
     from oracle import oracle as O
     from paper_2410_17133_amd import fg
     import dataclasses
@@ -124,6 +126,7 @@ def test_step_with_amg_reaches_the_same_state(cfg):
     _, flag_o, _, st = P.step(Uo, Po, dieo, tol_newton=1e-11, max_newton=60, tol_outer=1e-12, tol_inner=1e-13)
     assert st == 0
     S.tune("k_precond", 3)
+    S.tune("exact_tangent", 1 if "exact" in cfg else 0)
     try:
         U, Pp, die = dev(np.zeros(3 * N)), dev(np.zeros(N)), dev(np.zeros(2 * nq))
         trac, flag, info = S.step(U, Pp, die, dev(inst.t0.reshape(-1)), dev(inst.load), dev(inst.source),
@@ -131,6 +134,7 @@ def test_step_with_amg_reaches_the_same_state(cfg):
                                   inner_k=fg.opts(tol=1e-13, precision=fg.FG_MIXED if "mixed" in cfg else fg.FG_F64),
                                   inner_p=fg.opts(tol=1e-13), outer_tol=1e-12)
     finally:
+        S.tune("exact_tangent", 0)
         S.tune("k_precond", 0)
     eu, ep = relerr(U.cpu().numpy(), Uo), relerr(Pp.cpu().numpy(), Po)
     print(f"[amg step] {cfg}: newton {info.newton_iters}, K iterations {info.inner_k_iters}, slip points "

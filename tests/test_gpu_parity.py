@@ -389,6 +389,16 @@ def test_exact_tangent_product_and_bicgstab_match_oracle(name):
     x2, i2 = S.exact_solve(dev(b), tol=1e-11)
     print(f"[exact] point Jacobi BiCGStab {i2.iters} iterations", flush=True)
     assert i2.status == 0 and relerr(host(x2), xo1) < 1e-8
+    # the AMG V-cycle of the symmetric tangent as BiCGStab's preconditioner
+    S.tune("k_precond", 3)
+    try:
+        x3, i3 = S.exact_solve(dev(b), tol=1e-11)
+    finally:
+        S.tune("k_precond", 0)
+    res3 = np.linalg.norm(b - P.spmv(O.K_TANGENT, host(x3)) - P.apply_N(host(x3))) / np.linalg.norm(b)
+    print(f"[exact] AMG BiCGStab {i3.iters} iterations, true residual {res3:.1e}", flush=True)
+    assert i3.status == 0 and res3 <= 1e-9 and relerr(host(x3), xo1) < 1e-8
+    assert 2 * i3.iters < i1.iters
     # the symmetric tangent's solution differs: N matters at these slip points
     xs, _ = S.pcg_solve(fg.FG_K, dev(b), tol=1e-11)
     assert relerr(host(xs), xo1) > 1e-6
