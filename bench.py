@@ -417,7 +417,7 @@ def extra_adjoint(ctx, log):
     for name, prec, kp, et in (("f64", fg.FG_F64, 0, 0), ("mixed", fg.FG_MIXED, 0, 0),
                                ("f64_block_jacobi", fg.FG_F64, 1, 0), ("mixed_block_jacobi", fg.FG_MIXED, 1, 0),
                                ("f64_block_jacobi_exact", fg.FG_F64, 1, 1), ("f64_amg", fg.FG_F64, 3, 0),
-                               ("mixed_amg", fg.FG_MIXED, 3, 0)):
+                               ("mixed_amg", fg.FG_MIXED, 3, 0), ("f64_amg_exact", fg.FG_F64, 3, 1)):
         # corrections solved loosely (outer 0.05, inner 1e-3); the defect tolerance sets the accuracy;
         # exact: the corrections solve with K_t + N^T (BiCGStab) instead of the symmetric tangent
         S.tune("k_precond", kp)
@@ -435,7 +435,8 @@ def extra_adjoint(ctx, log):
     bj = {name: {"s": res[name][0], "defect_iters": res[name][1].newton_iters, "k_iters": res[name][1].inner_k_iters,
                  "status": res[name][1].status,
                  "vs_f64_grad_rel_l2": (torch.linalg.norm(res[name][2] - g64) / torch.linalg.norm(g64)).item()}
-          for name in ("f64_block_jacobi", "mixed_block_jacobi", "f64_block_jacobi_exact", "f64_amg", "mixed_amg")}
+          for name in ("f64_block_jacobi", "mixed_block_jacobi", "f64_block_jacobi_exact", "f64_amg", "mixed_amg",
+                       "f64_amg_exact")}
     # the exact tangent K_t + N at the converged state (slip points present): BiCGStab to 1e-8
     # on b = dJ/dU, against CG on the symmetric tangent
     S.cohesive_update(U, die0, t0, write_tangent=True)
@@ -454,14 +455,14 @@ def extra_adjoint(ctx, log):
     # and AMG-preconditioned K solves (symmetric tangent; hierarchy values rebuilt at every change of K)
     fwd = {}
     inner32 = fg.opts(tol=1e-4, check_every=64, precision=fg.FG_MIXED)
-    for kp, et, ik in ((1, 0, inner), (1, 1, inner), (3, 0, inner), (3, 0, inner32)):
+    for kp, et, ik in ((1, 0, inner), (1, 1, inner), (3, 0, inner), (3, 0, inner32), (3, 1, inner)):
         S.tune("k_precond", kp)
         S.tune("exact_tangent", et)
         U2, P2, die2 = d(np.zeros(3 * S.N)), d(np.zeros(S.N)), d(np.zeros(2 * S.nq))
         t_f, (_, flag2, finfo2) = _timed(lambda: S.step(U2, P2, die2, t0, d(inst.load), d(inst.source),
                                                          newton_tol=1e-8, newton_max_iter=60, inner_k=ik,
                                                          inner_p=inner, outer_tol=1e-2))
-        name = ("amg_mixed_symmetric" if ik is inner32 else "amg_symmetric") if kp == 3 else \
+        name = ("amg_exact" if et else "amg_mixed_symmetric" if ik is inner32 else "amg_symmetric") if kp == 3 else \
             "exact" if et else "symmetric"
         log(f"forward step, {'AMG' if kp == 3 else 'block Jacobi'}, {name} tangent: {t_f:.2f}s newton {finfo2.newton_iters} cuts "
             f"{finfo2.step_cuts} K iters {finfo2.inner_k_iters} status {finfo2.status}")
