@@ -417,7 +417,8 @@ def extra_adjoint(ctx, log):
     for name, prec, kp, et in (("f64", fg.FG_F64, 0, 0), ("mixed", fg.FG_MIXED, 0, 0),
                                ("f64_block_jacobi", fg.FG_F64, 1, 0), ("mixed_block_jacobi", fg.FG_MIXED, 1, 0),
                                ("f64_block_jacobi_exact", fg.FG_F64, 1, 1), ("f64_amg", fg.FG_F64, 3, 0),
-                               ("mixed_amg", fg.FG_MIXED, 3, 0), ("f64_amg_exact", fg.FG_F64, 3, 1)):
+                               ("mixed_amg", fg.FG_MIXED, 3, 0), ("f64_amg_exact", fg.FG_F64, 3, 1),
+                               ("mixed_amg_exact", fg.FG_MIXED, 3, 1)):
         # corrections solved loosely (outer 0.05, inner 1e-3); the defect tolerance sets the accuracy;
         # exact: the corrections solve with K_t + N^T (BiCGStab) instead of the symmetric tangent
         S.tune("k_precond", kp)
@@ -436,7 +437,7 @@ def extra_adjoint(ctx, log):
                  "status": res[name][1].status,
                  "vs_f64_grad_rel_l2": (torch.linalg.norm(res[name][2] - g64) / torch.linalg.norm(g64)).item()}
           for name in ("f64_block_jacobi", "mixed_block_jacobi", "f64_block_jacobi_exact", "f64_amg", "mixed_amg",
-                       "f64_amg_exact")}
+                       "f64_amg_exact", "mixed_amg_exact")}
     # the exact tangent K_t + N at the converged state (slip points present): BiCGStab to 1e-8
     # on b = dJ/dU, against CG on the symmetric tangent
     S.cohesive_update(U, die0, t0, write_tangent=True)

@@ -71,8 +71,8 @@ typedef int fg_status;
                       tenfold, the FP32 solution is added to the FP64 one, b - K x is formed in FP64
                       and replaces the FP32 residual, and CG continues (reliable updates; per
                       column in the block solve, per group on batched systems).  With the AMG
-                      preconditioner ("k_precond" 3, see fg_tune): FP64 CG whose V-cycle runs in
-                      FP32 */
+                      preconditioner ("k_precond" 3, see fg_tune): FP64 CG (on the exact tangent:
+                      FP64 BiCGStab) whose V-cycle runs in FP32 */
 #define FG_MIXED_F32VAL 3  /* inner PCG on the FP32 matrix values with FP64 vectors and arithmetic,
                               FP64 residual and refinement (single right-hand side, unbatched) */
 
@@ -462,8 +462,9 @@ fg_status fg_group_stats(const fg_system *sys, int64_t *iters_h, double *relres_
  *               6x6 blocks on [rho/30, rho]).  The patterns are built on the host
  *               once per mesh, the values on the GPU after every change of K;
  *               the BiCGStab of fg_exact_solve and of the exact-tangent solves
- *               (see "exact_tangent") is preconditioned by one FP64 V-cycle of
- *               the same hierarchy (built on the symmetric tangent K_t); other
+ *               (see "exact_tangent") is preconditioned by one V-cycle of the
+ *               same hierarchy (built on the symmetric tangent K_t; FP32 under
+ *               FG_MIXED, its input scaled on the device by a power of two); other
  *               solves behave as with 1.  FG_MIXED single-right-hand-side
  *               K solves run the same FP64 CG with the V-cycle in FP32: every
  *               level's values rounded once per change of K (level 0: K's FP32
@@ -484,7 +485,9 @@ fg_status fg_group_stats(const fg_system *sys, int64_t *iters_h, double *relres_
  *               fewer corrections.  If a correction breaks down (the Schur
  *               complement of K_t + N^T need not be positive definite at slip
  *               points), it and the later ones use the symmetric tangent.  fg_pcg_solve always uses the symmetric
- *               tangent; mixed-precision K solves stay symmetric.
+ *               tangent; mixed-precision K solves stay symmetric, except with
+ *               "k_precond" 3, where FG_MIXED solves the exact tangent by FP64
+ *               BiCGStab with the V-cycle in FP32.
  *   "cheb_degree": degree of the Chebyshev polynomial, 1 to 16 (default 4;
  *               1 is block Jacobi scaled by 1/theta: same iterates).
  *   "cheb_ratio": hi / lo of the interval, 2 to 1000000 (default 300).

@@ -84,6 +84,7 @@ struct AmgData {
     // result, the previous preconditioned residual of the flexible CG
     float *cinv32 = nullptr, *cr32 = nullptr, *cz32 = nullptr;
     double *cz0 = nullptr;
+    double *sc32 = nullptr;            // [2] the device-side scale of amg_apply32 and its inverse
     int64_t epoch32 = -1;              // bj_epoch of the FP32 copies
     int64_t coarse_nodes = 64;
 };
@@ -665,6 +666,48 @@ __global__ void k_amg_axpby32(int64_t n, float a, const float *__restrict__ x, f
     if (i < n) y[i] = a * x[i] + b * y[i];
 }
 
+// Per-block max |x| (the scale of the FP32 cycle inside BiCGStab, formed on the device).
+__global__ __launch_bounds__(WG) void k_amg_absmax(int64_t n, const double *__restrict__ x, double *part)
+{
+    __shared__ double sh[WG];
+    double m = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        m = fmax(m, fabs(x[i]));
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = WG / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// sc[0] = 2^-e with 2^e <= max |x| < 2^(e+1) (1 for a zero, tiny or non-finite x), sc[1] = 1 / sc[0]:
+// powers of two, so scaling by them rounds nothing.
+__global__ void k_amg_scale_fin(int nparts, const double *__restrict__ part, double *sc)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double m = 0;
+    for (int i = 0; i < nparts; ++i) m = fmax(m, part[i]);
+    const bool ok = m > 0x1p-1000 && isfinite(m);
+    sc[0] = ok ? ldexp(1.0, -ilogb(m)) : 1.0;
+    sc[1] = ok ? ldexp(1.0, ilogb(m)) : 1.0;
+}
+
+__global__ void k_amg_narrow_sc(int64_t n, const double *__restrict__ sc, const double *__restrict__ x,
+                                float *__restrict__ y)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) y[i] = (float)(sc[0] * x[i]);
+}
+
+__global__ void k_amg_widen_sc(int64_t n, const double *__restrict__ sc, const float *__restrict__ x,
+                               double *__restrict__ y)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) y[i] = sc[1] * (double)x[i];
+}
+
 // y = s x, FP32 to FP64 (the preconditioned residual of the mixed cycle).
 __global__ void k_amg_widen(int64_t n, double s, const float *__restrict__ x, double *__restrict__ y)
 {
@@ -692,7 +735,7 @@ void amg_destroy(fg_system *S)
     for (AmgLevel &L : S->amg->L) free_level(L);
     if (S->amg->cinv) hipFree(S->amg->cinv);
     if (S->amg->part) hipFree(S->amg->part);
-    for (double *v : {S->amg->cr, S->amg->cz, S->amg->cp, S->amg->cq, S->amg->cz0})
+    for (double *v : {S->amg->cr, S->amg->cz, S->amg->cp, S->amg->cq, S->amg->cz0, S->amg->sc32})
         if (v) hipFree(v);
     for (float *v : {S->amg->cinv32, S->amg->cr32, S->amg->cz32})
         if (v) hipFree(v);
@@ -1090,8 +1133,10 @@ static void free32(AmgData *G)
         if (*v) hipFree(*v);
         *v = nullptr;
     }
-    if (G->cz0) hipFree(G->cz0);
-    G->cz0 = nullptr;
+    for (double **v : {&G->cz0, &G->sc32}) {
+        if (*v) hipFree(*v);
+        *v = nullptr;
+    }
     G->epoch32 = -1;
 }
 
@@ -1114,7 +1159,7 @@ static fg_status amg_ready32(fg_system *S, hipStream_t st)
         }
         const int64_t n0 = 3 * S->Npad;
         ok = ok && !dmal(&G->cinv32, G->nco * G->nco) && !dmal(&G->cr32, n0) && !dmal(&G->cz32, n0) &&
-             !dmal(&G->cz0, n0);
+             !dmal(&G->cz0, n0) && !dmal(&G->sc32, 2);
         if (!ok) {
             free32(G);
             set_error("AMG: device allocation for the FP32 cycle failed");
@@ -1240,6 +1285,26 @@ static void amg_vcycle(fg_system *S, int l, const T *b, T *x, hipStream_t st)
 // z = B r, one FP64 V-cycle on the hierarchy of the current K (after amg_ready); the
 // preconditioner of the exact-tangent BiCGStab (r, z internal vectors, not the AMG's).
 void amg_apply(fg_system *S, const double *r, double *z, hipStream_t st) { amg_vcycle(S, 0, r, z, st); }
+
+// The same with the V-cycle in FP32 (after amg_ready_f32): r scaled on the device by the
+// power of two below max |r| (no host synchronisation), the result scaled back.
+void amg_apply32(fg_system *S, const double *r, double *z, hipStream_t st)
+{
+    AmgData *G = S->amg;
+    const int64_t n = 3 * S->Npad;
+    const int nparts = (int)std::min<int64_t>(nb(n), 1024);
+    LAUNCH(k_amg_absmax, nparts, WG, st, n, r, G->part);
+    LAUNCH(k_amg_scale_fin, 1, 64, st, nparts, (const double *)G->part, G->sc32);
+    LAUNCH(k_amg_narrow_sc, nb(n), WG, st, n, (const double *)G->sc32, r, G->cr32);
+    amg_vcycle(S, 0, (const float *)G->cr32, G->cz32, st);
+    LAUNCH(k_amg_widen_sc, nb(n), WG, st, n, (const double *)G->sc32, (const float *)G->cz32, z);
+}
+
+fg_status amg_ready_f32(fg_system *S, hipStream_t st)
+{
+    const fg_status e = amg_ready(S, st);
+    return e ? e : amg_ready32(S, st);
+}
 
 fg_status amg_aggregates(const fg_system *S, int level, int32_t *out)
 {

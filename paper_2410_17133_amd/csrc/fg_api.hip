@@ -144,6 +144,19 @@ fg_status k_solve(fg_system *S, const double *rhs, double *out, const fg_pcg_opt
         }
         return s;
     }
+    if (S->k_precond == 3 && S->exact_tangent && S->ngroups == 1 && o.precision == FG_MIXED) {
+        // the exact tangent by FP64 BiCGStab with the V-cycle in FP32
+        int64_t it = 0;
+        double rr = 0;
+        fg_status s = bicgstab_exact(S, rhs, out, o.tol, o.max_iter, S->exact_tangent == 2, &it, &rr, st, true);
+        if (info) {
+            info->iters = it;
+            info->cycles = 1;
+            info->relres = rr;
+            info->status = s;
+        }
+        return s;
+    }
     if (o.precision == FG_F64 || o.precision == FG_F32) {
         int64_t it = 0;
         double rr = 0;

@@ -272,11 +272,14 @@ __global__ void k_dmul(int64_t n, const double *__restrict__ d, const double *__
         y[i] = d[i] * x[i];
 }
 
-// y = M^-1 x with the K_t preconditioner of the single-vector solves.
-void precond(fg_system *S, const double *x, double *y, hipStream_t st)
+// y = M^-1 x with the K_t preconditioner of the single-vector solves (f32: the V-cycle
+// in FP32).
+void precond(fg_system *S, const double *x, double *y, bool f32, hipStream_t st)
 {
     const int64_t n = 3 * S->Npad;
-    if (S->k_precond == 3)
+    if (S->k_precond == 3 && f32)
+        amg_apply32(S, x, y, st);
+    else if (S->k_precond == 3)
         amg_apply(S, x, y, st);
     else if (S->k_precond)
         bj_apply(S, x, y, st);
@@ -312,13 +315,13 @@ void spmv_exact(fg_system *S, const double *x, double *y, bool transposed, hipSt
 }
 
 fg_status bicgstab_exact(fg_system *S, const double *b, double *x, double tol, int64_t maxit, bool transposed,
-                         int64_t *iters, double *relres, hipStream_t st)
+                         int64_t *iters, double *relres, hipStream_t st, bool f32)
 {
     const int64_t n = 3 * S->Npad;
     *iters = 0;
     *relres = 0;
     if (S->k_precond == 3) {   // the V-cycle of the symmetric tangent (amg_ready checks the blocks)
-        const fg_status e = amg_ready(S, st);
+        const fg_status e = f32 ? amg_ready_f32(S, st) : amg_ready(S, st);
         if (e) return e;
     } else if (S->k_precond) {
         bj_ready(S, st);
@@ -348,11 +351,11 @@ fg_status bicgstab_exact(fg_system *S, const double *b, double *x, double tol, i
         for (int j = 0; j < batch; ++j, ++k) {
             const int par = (int)(k & 1);
             LAUNCH(k_bi_p, gv, WG, st, n, par, (int)(k == 0), tol, r, p, v, part, stride, gv, sc);
-            precond(S, p, ph, st);
+            precond(S, p, ph, f32, st);
             spmv_exact(S, ph, v, transposed, st);
             LAUNCH(k_bi_dot, gv, WG, st, n, rh, v, part, stride);
             LAUNCH(k_bi_s, gv, WG, st, n, par, r, v, s, part, stride, gv, sc);
-            precond(S, s, sh, st);
+            precond(S, s, sh, f32, st);
             spmv_exact(S, sh, t, transposed, st);
             LAUNCH(k_bi_dot2, gv, WG, st, n, t, s, part, stride);
             LAUNCH(k_bi_xr, gv, WG, st, n, x, r, ph, sh, s, t, rh, part, stride, gv, sc);

@@ -81,6 +81,8 @@ fg_status amg_ready(fg_system *S, hipStream_t st);
 fg_status amg_pcg(fg_system *S, const double *b, double *x, double tol, int64_t maxit, bool f32, int64_t *iters,
                   double *relres, hipStream_t st);
 void amg_apply(fg_system *S, const double *r, double *z, hipStream_t st);   // one FP64 V-cycle
+fg_status amg_ready_f32(fg_system *S, hipStream_t st);                      // hierarchy and its FP32 copies
+void amg_apply32(fg_system *S, const double *r, double *z, hipStream_t st); // one FP32 V-cycle
 void amg_destroy(fg_system *S);
 void amg_levels(const fg_system *S, int *nlev, int64_t *nodes);  // nodes[6]
 fg_status amg_aggregates(const fg_system *S, int level, int32_t *out);  // host out, level's nodes
@@ -105,8 +107,9 @@ inline int64_t bx_len(const fg_system *S) { return 15 * S->Npad + BX_TAIL; }
 void apply_N_add(fg_system *S, const double *x, double *y, hipStream_t st);
 void apply_NT_add(fg_system *S, const double *x, double *y, hipStream_t st);
 void spmv_exact(fg_system *S, const double *x, double *y, bool transposed, hipStream_t st);
+// f32 (with "k_precond" 3): the V-cycle preconditioner in FP32.
 fg_status bicgstab_exact(fg_system *S, const double *b, double *x, double tol, int64_t maxit, bool transposed,
-                         int64_t *iters, double *relres, hipStream_t st);
+                         int64_t *iters, double *relres, hipStream_t st, bool f32 = false);
 
 // float <-> double conversions with a scale: y = (T)(s * x)
 void to_f32(int64_t n, double s, const double *x, float *y, hipStream_t st);

@@ -84,12 +84,15 @@ def oracle_adjoint(case):
 @pytest.mark.parametrize("case,loose,exact", [("small_slip", False, False), ("small_slip", True, False),
                                               ("config1", False, False), ("config1", True, False),
                                               ("small_slip", True, True), ("config1", True, True),
-                                              ("dip60_hetero12", True, False), ("dip60_hetero12", True, True)])
+                                              ("dip60_hetero12", True, False), ("dip60_hetero12", True, True),
+                                              ("dip60_hetero12", True, "amg"), ("dip60_hetero12", True, "amg32")])
 def test_adjoint_matches_oracle_at_the_same_state(case, loose, exact):
     """loose: every defect correction solved to outer 0.05 / inner 1e-3 only; the
     refinement on the true residual must still reach the same multipliers.  exact:
     fg_tune exact_tangent 1, the corrections solve with K_t + N^T (BiCGStab) and need
-    no more of them than the symmetric corrections."""
+    no more of them than the symmetric corrections; "amg": that BiCGStab takes the AMG
+    V-cycle of K_t as preconditioner ("k_precond" 3), "amg32" the V-cycle in FP32
+    (FG_MIXED)."""
     from paper_2410_17133_amd import fg
     print(f"[case] adjoint parity {case}", flush=True)
     inst, U, Pp, gu, gp, lu_o, lp_o, dE_o, dk_o, stats = oracle_adjoint(case)
@@ -101,10 +104,15 @@ def test_adjoint_matches_oracle_at_the_same_state(case, loose, exact):
     if exact:
         ai_sym = S.adjoint(*args, multipliers=True, **kw)[4]
         S.tune("exact_tangent", 1)
+    if exact in ("amg", "amg32"):
+        S.tune("k_precond", 3)
+    if exact == "amg32":
+        kw["inner_k"] = fg.opts(tol=1e-3, precision=fg.FG_MIXED)
     try:
         dE, dk, lu, lp, ai = S.adjoint(*args, multipliers=True, **kw)
     finally:
         S.tune("exact_tangent", 0)
+        S.tune("k_precond", 0)
     print(f"[adjoint] loose={loose} exact={exact} defect iterations gpu {ai.newton_iters} (K iters "
           f"{ai.inner_k_iters}) oracle {stats[0]:.0f}", flush=True)
     if exact:
